@@ -1,0 +1,797 @@
+// FP64 CPU oracle for the 360Roam geometry-aware radiance-field hot path.
+//
+// TEST INFRASTRUCTURE ONLY. Nothing in the product path links, loads or calls
+// this file; only the tests, the smoke check and the CPU-baseline leg of the
+// benchmark do. It is plain and slow on purpose: loops in the order of the
+// paper's definitions, no blocking, no fusion, no reordering. It shares no
+// code with the HIP library.
+//
+// Paper: "360Roam: Real-Time Indoor Roaming Using Geometry-Aware 360°
+// Radiance Fields" (arXiv 2208.02705). Equation numbers below count the
+// paper's displayed equations in order: Eq.1 the two-stage MLP (Sec. 3.1),
+// Eq.2 pixel <-> sphere and Eq.3 sphere -> Cartesian (Sec. 3.2), Eq.4 colour
+// and depth compositing and Eq.5 the sample weights (Sec. 3.2), Eq.6 the
+// logit occupancy update (Sec. 4.1), Eq.7 the distillation loss (Sec. 4.2).
+//
+// Precision: the geometric front end (ray directions, voxel traversal,
+// sample positions) is a specified FP32 formula, evaluated here in float
+// with correctly rounded operations and no contraction (build with
+// -ffp-contract=off, no fast-math), so that sample -> voxel -> field
+// assignment can be compared bit for bit. Everything after the sample
+// position (encoding, MLP, compositing, loss, gradients) is FP64.
+//
+// Parity pins: every function below is checked by the CPU test-suite against
+// closed forms, invariants or brute force (see tests/test_oracle_pins.py).
+// The absolute values of rendered pixels are not printed in the paper, so
+// end-to-end pixel values are pinned only through those per-stage checks.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <thread>
+#include <vector>
+#include <algorithm>
+#include <limits>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Scene description (mirrors the ctypes structure in oracle/__init__.py)
+// ---------------------------------------------------------------------------
+struct OrcScene {
+    int32_t n[3];          // voxels per axis
+    float lo[3];           // grid lower corner (m)
+    float voxel;           // voxel edge (m); a power of two
+    float threshold;       // occupied where occ > threshold
+    const float* occ;      // [n2][n1][n0], x fastest
+    const int32_t* field;  // same layout, -1 = none
+    int32_t n_fields;
+    int32_t hidden;
+    int32_t L_xyz, L_dir;
+    float center[3];       // encoding centre
+    float half_extent;     // encoding half extent: xhat = (p - center) / half_extent
+    const float* weights;  // [n_fields][P] canonical FP32
+    float near_, far_;
+    int32_t max_samples;
+};
+
+const double PI = 3.14159265358979323846;
+
+// sin(pi r) in FP64 with the argument reduced exactly: r mod 2 is exact in
+// binary floating point, and the symmetric fold keeps |r| <= 1/2 so that
+// integer r gives exactly 0 and half-integers give exactly +-1.
+double sinpi_d(double r) {
+    double m = std::fmod(r, 2.0);        // exact, in (-2, 2)
+    if (m > 1.0) m -= 2.0;               // exact, now in [-1, 1]
+    if (m < -1.0) m += 2.0;
+    if (m > 0.5) m = 1.0 - m;            // sin(pi m) = sin(pi (1 - m))
+    else if (m < -0.5) m = -1.0 - m;     // sin(pi m) = sin(pi (-1 - m))
+    return std::sin(PI * m);
+}
+double cospi_d(double r) { return sinpi_d(r + 0.5); }  // r + 1/2 is exact here
+
+// ---------------------------------------------------------------------------
+// Ray generation (Sec. 3.2, Eq.2 and Eq.3)
+// ---------------------------------------------------------------------------
+// Eq.2 maps longitude phi and latitude theta to pixel (u, v); inverted at
+// the pixel centre (u + 1/2, v + 1/2):
+//   phi   = pi * a_phi,   a_phi   = ((2u + 1) - W) / W
+//   theta = pi * a_theta, a_theta = (H - (2v + 1)) / (2H)
+// each a correctly rounded FP32 division of exact integers. The sines and
+// cosines are evaluated in FP64 and rounded once to FP32.
+// Eq.3: d = (cos(theta) sin(phi), -sin(theta), cos(theta) cos(phi)),
+// camera frame x right, y down, z forward; FP32 products, not renormalised.
+void equirect_trig(int W, int H, int u, int v, float* sphi, float* cphi, float* sth, float* cth) {
+    float a_phi = (float)((2 * u + 1) - W) / (float)W;
+    float a_th = (float)(H - (2 * v + 1)) / (float)(2 * H);
+    *sphi = (float)sinpi_d((double)a_phi);
+    *cphi = (float)cospi_d((double)a_phi);
+    *sth = (float)sinpi_d((double)a_th);
+    *cth = (float)cospi_d((double)a_th);
+}
+
+// World direction d = R d_cam with the chain fma(R2, z, fma(R1, y, R0 * x)).
+void to_world(const float* c2w, const float dc[3], float o[3], float d[3]) {
+    for (int i = 0; i < 3; ++i) {
+        const float* r = c2w + 4 * i;
+        d[i] = std::fma(r[2], dc[2], std::fma(r[1], dc[1], r[0] * dc[0]));
+        o[i] = r[3];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Occupancy-grid sampling: voxel traversal in FP32 (Sec. 4.2 fine-tuning
+// "densely sample the occupied voxels", Sec. 5 ray casting over the labelled
+// occupancy map). One midpoint sample per occupied voxel segment, with the
+// segment length as its interval, the first max_samples in increasing t.
+// ---------------------------------------------------------------------------
+struct Seg { float t_mid, delta; int32_t voxel, field; };
+
+int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) {
+    const float INF = std::numeric_limits<float>::infinity();
+    float inv[3], hi[3];
+    bool active[3];
+    float t0 = s.near_, t1 = s.far_;
+    for (int a = 0; a < 3; ++a) {
+        hi[a] = s.lo[a] + (float)s.n[a] * s.voxel;
+        active[a] = d[a] != 0.0f;
+        if (active[a]) {
+            inv[a] = 1.0f / d[a];
+            float ta = (s.lo[a] - o[a]) * inv[a];
+            float tb = (hi[a] - o[a]) * inv[a];
+            t0 = std::max(t0, std::min(ta, tb));
+            t1 = std::min(t1, std::max(ta, tb));
+        } else {
+            inv[a] = 0.0f;
+            if (!(o[a] >= s.lo[a] && o[a] < hi[a])) return 0;
+        }
+    }
+    if (!(t0 < t1)) return 0;
+    const float inv_vox = 1.0f / s.voxel;   // exact: the voxel edge is a power of two
+    int idx[3];
+    for (int a = 0; a < 3; ++a) {
+        float p = std::fma(t0, d[a], o[a]);
+        float q = (p - s.lo[a]) * inv_vox;
+        float fq = std::floor(q);
+        int i = (int)fq;
+        if (q == fq && d[a] < 0.0f) i -= 1;   // on a plane moving down: the lower voxel
+        idx[a] = std::min(std::max(i, 0), s.n[a] - 1);
+    }
+    int count = 0;
+    float t_in = t0;
+    for (;;) {
+        float tn[3];
+        for (int a = 0; a < 3; ++a) {
+            if (active[a]) {
+                float plane = std::fma((float)(idx[a] + (d[a] > 0.0f ? 1 : 0)), s.voxel, s.lo[a]);
+                tn[a] = (plane - o[a]) * inv[a];
+            } else {
+                tn[a] = INF;
+            }
+        }
+        int am = 0;                           // ties go to the lowest axis
+        if (tn[1] < tn[am]) am = 1;
+        if (tn[2] < tn[am]) am = 2;
+        float t_out = std::min(tn[am], t1);
+        int64_t lin = idx[0] + (int64_t)s.n[0] * (idx[1] + (int64_t)s.n[1] * idx[2]);
+        if (t_out > t_in && s.occ[lin] > s.threshold && s.field[lin] >= 0) {
+            out[count].t_mid = (t_in + t_out) * 0.5f;
+            out[count].delta = t_out - t_in;
+            out[count].voxel = (int32_t)lin;
+            out[count].field = s.field[lin];
+            if (++count == s.max_samples) break;
+        }
+        if (!(tn[am] < t1)) break;
+        t_in = std::max(t_in, tn[am]);
+        idx[am] += d[am] > 0.0f ? 1 : -1;
+        if (idx[am] < 0 || idx[am] >= s.n[am]) break;
+    }
+    return count;
+}
+
+// Encoding input: p = fma(t_mid, d, o), xhat = (p - center) * (1 / half_extent)
+// in FP32, then widened exactly.
+void sample_position(const OrcScene& s, const float o[3], const float d[3], float t_mid, double xh[3]) {
+    const float inv_h = 1.0f / s.half_extent;
+    for (int a = 0; a < 3; ++a) {
+        float p = std::fma(t_mid, d[a], o[a]);
+        xh[a] = (double)((p - s.center[a]) * inv_h);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Positional encoding (Sec. 3.1, applied to each component separately):
+//   gamma_L(x) = [x, sin(2^0 pi x), cos(2^0 pi x), ..., sin(2^(L-1) pi x), cos(...)]
+// laid out as the three raw components, then for each frequency l the sines
+// of (x, y, z) followed by the cosines of (x, y, z). Width 3 + 6L.
+// ---------------------------------------------------------------------------
+void encode(const double x[3], int L, double* out) {
+    out[0] = x[0]; out[1] = x[1]; out[2] = x[2];
+    for (int l = 0; l < L; ++l) {
+        for (int c = 0; c < 3; ++c) {
+            double r = std::ldexp(x[c], l);   // 2^l x, exact
+            out[3 + 6 * l + c] = sinpi_d(r);
+            out[3 + 6 * l + 3 + c] = cospi_d(r);
+        }
+    }
+}
+
+double softplus(double z) { return std::max(z, 0.0) + std::log1p(std::exp(-std::fabs(z))); }
+double sigmoid(double z) { return 1.0 / (1.0 + std::exp(-z)); }
+double relu(double z) { return z > 0.0 ? z : 0.0; }
+
+// y[o] = b[o] + sum_i W[o][i] x[i]   (W row-major [out x in])
+void dense(const double* W, const double* b, int n_out, int n_in, const double* x, double* y) {
+    for (int o = 0; o < n_out; ++o) {
+        double acc = b[o];
+        for (int i = 0; i < n_in; ++i) acc += W[(size_t)o * n_in + i] * x[i];
+        y[o] = acc;
+    }
+}
+
+// Views of one local field's canonical parameter vector.
+struct LocalNet {
+    const double *W1, *b1, *W2, *b2, *ws, *bs, *Wf, *bf, *W3, *b3, *W4, *b4;
+    int h, dx, dd;
+};
+size_t local_params(int h, int dx, int dd) {
+    return (size_t)h * dx + h + (size_t)h * h + h + h + 1 + (size_t)h * h + h + (size_t)h * (h + dd) + h + 3 * (size_t)h + 3;
+}
+LocalNet local_view(const double* w, int h, int dx, int dd) {
+    LocalNet n; n.h = h; n.dx = dx; n.dd = dd;
+    const double* p = w;
+    n.W1 = p; p += (size_t)h * dx; n.b1 = p; p += h;
+    n.W2 = p; p += (size_t)h * h;  n.b2 = p; p += h;
+    n.ws = p; p += h;              n.bs = p; p += 1;
+    n.Wf = p; p += (size_t)h * h;  n.bf = p; p += h;
+    n.W3 = p; p += (size_t)h * (h + dd); n.b3 = p; p += h;
+    n.W4 = p; p += 3 * (size_t)h;  n.b4 = p;
+    return n;
+}
+
+// Activations of one local-field evaluation, kept for the backward pass.
+struct LocalAct {
+    std::vector<double> gx, gd, z1, h1, z2, h2, f, in3, z3, h3;
+    double zs, sigma, z4[3], rgb[3];
+};
+
+// Local field MLP (Eq.1, tiny form): h1 = relu(W1 gx + b1); h2 = relu(W2 h1 + b2);
+// sigma = softplus(ws h2 + bs); f = Wf h2 + bf (linear);
+// h3 = relu(W3 [f; gd] + b3); rgb = sigmoid(W4 h3 + b4).
+void local_forward(const LocalNet& n, const double xh[3], const double dir[3], int Lx, int Ld, LocalAct& a) {
+    const int h = n.h;
+    a.gx.assign(n.dx, 0.0); a.gd.assign(n.dd, 0.0);
+    encode(xh, Lx, a.gx.data());
+    encode(dir, Ld, a.gd.data());
+    a.z1.assign(h, 0.0); a.h1.assign(h, 0.0); a.z2.assign(h, 0.0); a.h2.assign(h, 0.0);
+    a.f.assign(h, 0.0); a.in3.assign(h + n.dd, 0.0); a.z3.assign(h, 0.0); a.h3.assign(h, 0.0);
+    dense(n.W1, n.b1, h, n.dx, a.gx.data(), a.z1.data());
+    for (int i = 0; i < h; ++i) a.h1[i] = relu(a.z1[i]);
+    dense(n.W2, n.b2, h, h, a.h1.data(), a.z2.data());
+    for (int i = 0; i < h; ++i) a.h2[i] = relu(a.z2[i]);
+    dense(n.ws, n.bs, 1, h, a.h2.data(), &a.zs);
+    a.sigma = softplus(a.zs);
+    dense(n.Wf, n.bf, h, h, a.h2.data(), a.f.data());
+    for (int i = 0; i < h; ++i) a.in3[i] = a.f[i];
+    for (int i = 0; i < n.dd; ++i) a.in3[h + i] = a.gd[i];
+    dense(n.W3, n.b3, h, h + n.dd, a.in3.data(), a.z3.data());
+    for (int i = 0; i < h; ++i) a.h3[i] = relu(a.z3[i]);
+    dense(n.W4, n.b4, 3, h, a.h3.data(), a.z4);
+    for (int c = 0; c < 3; ++c) a.rgb[c] = sigmoid(a.z4[c]);
+}
+
+// dW += g x^T, db += g; dx = W^T g (dx may be null)
+void dense_backward(const double* W, int n_out, int n_in, const double* x, const double* g,
+                    double* dW, double* db, double* dx) {
+    for (int o = 0; o < n_out; ++o) {
+        for (int i = 0; i < n_in; ++i) dW[(size_t)o * n_in + i] += g[o] * x[i];
+        db[o] += g[o];
+    }
+    if (dx) {
+        for (int i = 0; i < n_in; ++i) {
+            double acc = 0.0;
+            for (int o = 0; o < n_out; ++o) acc += W[(size_t)o * n_in + i] * g[o];
+            dx[i] = acc;
+        }
+    }
+}
+
+// Backward of local_forward given dL/dsigma and dL/drgb; accumulates into the
+// gradient view `gn` (same layout as the weights).
+void local_backward(const LocalNet& n, const LocalAct& a, double dsigma, const double drgb[3], const LocalNet& gn) {
+    const int h = n.h;
+    double dz4[3];
+    for (int c = 0; c < 3; ++c) dz4[c] = drgb[c] * a.rgb[c] * (1.0 - a.rgb[c]);
+    std::vector<double> dh3(h), dz3(h), din3(h + n.dd), dh2(h, 0.0), dz2(h), dh1(h), dz1(h), tmp(h);
+    dense_backward(n.W4, 3, h, a.h3.data(), dz4, (double*)gn.W4, (double*)gn.b4, dh3.data());
+    for (int i = 0; i < h; ++i) dz3[i] = a.z3[i] > 0.0 ? dh3[i] : 0.0;
+    dense_backward(n.W3, h, h + n.dd, a.in3.data(), dz3.data(), (double*)gn.W3, (double*)gn.b3, din3.data());
+    // f = Wf h2 + bf (linear): df = din3[0:h]
+    dense_backward(n.Wf, h, h, a.h2.data(), din3.data(), (double*)gn.Wf, (double*)gn.bf, tmp.data());
+    for (int i = 0; i < h; ++i) dh2[i] += tmp[i];
+    double dzs = dsigma * sigmoid(a.zs);   // softplus' = sigmoid
+    dense_backward(n.ws, 1, h, a.h2.data(), &dzs, (double*)gn.ws, (double*)gn.bs, tmp.data());
+    for (int i = 0; i < h; ++i) dh2[i] += tmp[i];
+    for (int i = 0; i < h; ++i) dz2[i] = a.z2[i] > 0.0 ? dh2[i] : 0.0;
+    dense_backward(n.W2, h, h, a.h1.data(), dz2.data(), (double*)gn.W2, (double*)gn.b2, dh1.data());
+    for (int i = 0; i < h; ++i) dz1[i] = a.z1[i] > 0.0 ? dh1[i] : 0.0;
+    dense_backward(n.W1, h, n.dx, a.gx.data(), dz1.data(), (double*)gn.W1, (double*)gn.b1, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// Compositing (Sec. 3.2, Eq.4 and Eq.5): with tau_k = sigma_k delta_k,
+//   w_i = exp(-sum_{k<i} tau_k) (1 - exp(-tau_i)),
+//   C = sum_i w_i c_i, D = sum_i w_i t_i, A = sum_i w_i.
+// No background colour is added.
+// ---------------------------------------------------------------------------
+void composite(int n, const double* sigma, const double* rgb /*[n][3]*/, const double* t_mid,
+               const double* delta, double C[3], double* D, double* A, double* w_out) {
+    C[0] = C[1] = C[2] = 0.0; *D = 0.0; *A = 0.0;
+    double S = 0.0;   // sum_{k<i} tau_k
+    for (int i = 0; i < n; ++i) {
+        double tau = sigma[i] * delta[i];
+        double w = std::exp(-S) * (-std::expm1(-tau));
+        if (w_out) w_out[i] = w;
+        for (int c = 0; c < 3; ++c) C[c] += w * rgb[3 * i + c];
+        *D += w * t_mid[i];
+        *A += w;
+        S += tau;
+    }
+}
+
+// Gradient of C w.r.t. sigma_i and c_i, from dL/dC = g:
+//   dL/dc_i = w_i g,
+//   dL/dsigma_i = delta_i [ T_{i+1} (c_i . g) - ((C - C_{<=i}) . g) ],
+// where T_{i+1} = exp(-sum_{k<=i} tau_k) and C_{<=i} = sum_{k<=i} w_k c_k.
+void composite_backward(int n, const double* sigma, const double* rgb, const double* delta,
+                        const double g[3], double* dsigma, double* drgb) {
+    std::vector<double> w(n);
+    double C[3] = {0, 0, 0};
+    double S = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double tau = sigma[i] * delta[i];
+        w[i] = std::exp(-S) * (-std::expm1(-tau));
+        for (int c = 0; c < 3; ++c) C[c] += w[i] * rgb[3 * i + c];
+        S += tau;
+    }
+    double Cle[3] = {0, 0, 0};
+    S = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double tau = sigma[i] * delta[i];
+        S += tau;
+        double T_next = std::exp(-S);
+        double cg = 0.0, rg = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            Cle[c] += w[i] * rgb[3 * i + c];
+            cg += rgb[3 * i + c] * g[c];
+            rg += (C[c] - Cle[c]) * g[c];
+            drgb[3 * i + c] = w[i] * g[c];
+        }
+        dsigma[i] = delta[i] * (T_next * cg - rg);
+    }
+}
+
+template <class F>
+void parallel_for(int64_t n, int nthreads, F fn) {
+    if (nthreads <= 1 || n < 2) { fn(0, n, 0); return; }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nthreads - 1) / nthreads;
+    for (int t = 0; t < nthreads; ++t) {
+        int64_t b = t * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back(fn, b, e, t);
+    }
+    for (auto& x : th) x.join();
+}
+
+std::vector<double> widen(const float* w, size_t n) {
+    std::vector<double> out(n);
+    for (size_t i = 0; i < n; ++i) out[i] = (double)w[i];
+    return out;
+}
+
+// Global omnidirectional field (360NeRF architecture table, Sec. 3.2): eight
+// position layers of width W with [h4 ; gx] at the fifth layer input, the
+// eighth without activation; sigma = relu(ws h8 + bs); f = relu(Wf h8 + bf);
+// h10 = relu(W10 [f ; gd] + b10); rgb = sigmoid(W11 h10 + b11).
+struct GlobalNet {
+    const double* W[8]; const double* b[8];
+    const double *ws, *bs, *Wf, *bf, *W10, *b10, *W11, *b11;
+    int w, c, dx, dd;
+};
+size_t global_params(int w, int c, int dx, int dd) {
+    return (size_t)w * dx + w + 3 * ((size_t)w * w + w) + (size_t)w * (w + dx) + w + 3 * ((size_t)w * w + w)
+           + w + 1 + (size_t)w * w + w + (size_t)c * (w + dd) + c + 3 * (size_t)c + 3;
+}
+GlobalNet global_view(const double* p, int w, int c, int dx, int dd) {
+    GlobalNet n; n.w = w; n.c = c; n.dx = dx; n.dd = dd;
+    for (int k = 0; k < 8; ++k) {
+        int in = (k == 0) ? dx : (k == 4 ? w + dx : w);
+        n.W[k] = p; p += (size_t)w * in; n.b[k] = p; p += w;
+    }
+    n.ws = p; p += w; n.bs = p; p += 1;
+    n.Wf = p; p += (size_t)w * w; n.bf = p; p += w;
+    n.W10 = p; p += (size_t)c * (w + dd); n.b10 = p; p += c;
+    n.W11 = p; p += 3 * (size_t)c; n.b11 = p;
+    return n;
+}
+struct GlobalAct {
+    std::vector<double> gx, gd, in[8], z[8], h[8], zf, f, in10, z10, h10;
+    double zs, sigma, z11[3], rgb[3];
+};
+void global_forward(const GlobalNet& n, const double xh[3], const double dir[3], int Lx, int Ld, GlobalAct& a) {
+    a.gx.assign(n.dx, 0.0); a.gd.assign(n.dd, 0.0);
+    encode(xh, Lx, a.gx.data());
+    encode(dir, Ld, a.gd.data());
+    for (int k = 0; k < 8; ++k) {
+        if (k == 0) a.in[k] = a.gx;
+        else if (k == 4) { a.in[k] = a.h[3]; a.in[k].insert(a.in[k].end(), a.gx.begin(), a.gx.end()); }
+        else a.in[k] = a.h[k - 1];
+        a.z[k].assign(n.w, 0.0);
+        dense(n.W[k], n.b[k], n.w, (int)a.in[k].size(), a.in[k].data(), a.z[k].data());
+        a.h[k].assign(n.w, 0.0);
+        for (int i = 0; i < n.w; ++i) a.h[k][i] = (k == 7) ? a.z[k][i] : relu(a.z[k][i]);
+    }
+    dense(n.ws, n.bs, 1, n.w, a.h[7].data(), &a.zs);
+    a.sigma = relu(a.zs);
+    a.zf.assign(n.w, 0.0); a.f.assign(n.w, 0.0);
+    dense(n.Wf, n.bf, n.w, n.w, a.h[7].data(), a.zf.data());
+    for (int i = 0; i < n.w; ++i) a.f[i] = relu(a.zf[i]);
+    a.in10 = a.f; a.in10.insert(a.in10.end(), a.gd.begin(), a.gd.end());
+    a.z10.assign(n.c, 0.0); a.h10.assign(n.c, 0.0);
+    dense(n.W10, n.b10, n.c, n.w + n.dd, a.in10.data(), a.z10.data());
+    for (int i = 0; i < n.c; ++i) a.h10[i] = relu(a.z10[i]);
+    dense(n.W11, n.b11, 3, n.c, a.h10.data(), a.z11);
+    for (int k = 0; k < 3; ++k) a.rgb[k] = sigmoid(a.z11[k]);
+}
+void global_backward(const GlobalNet& n, const GlobalAct& a, double dsigma, const double drgb[3], const GlobalNet& g) {
+    double dz11[3];
+    for (int k = 0; k < 3; ++k) dz11[k] = drgb[k] * a.rgb[k] * (1.0 - a.rgb[k]);
+    std::vector<double> dh10(n.c), dz10(n.c), din10(n.w + n.dd), dh8(n.w, 0.0), dzf(n.w), tmp(n.w + n.dx);
+    dense_backward(n.W11, 3, n.c, a.h10.data(), dz11, (double*)g.W11, (double*)g.b11, dh10.data());
+    for (int i = 0; i < n.c; ++i) dz10[i] = a.z10[i] > 0.0 ? dh10[i] : 0.0;
+    dense_backward(n.W10, n.c, n.w + n.dd, a.in10.data(), dz10.data(), (double*)g.W10, (double*)g.b10, din10.data());
+    for (int i = 0; i < n.w; ++i) dzf[i] = a.zf[i] > 0.0 ? din10[i] : 0.0;
+    dense_backward(n.Wf, n.w, n.w, a.h[7].data(), dzf.data(), (double*)g.Wf, (double*)g.bf, tmp.data());
+    for (int i = 0; i < n.w; ++i) dh8[i] += tmp[i];
+    double dzs = a.zs > 0.0 ? dsigma : 0.0;
+    dense_backward(n.ws, 1, n.w, a.h[7].data(), &dzs, (double*)g.ws, (double*)g.bs, tmp.data());
+    for (int i = 0; i < n.w; ++i) dh8[i] += tmp[i];
+    std::vector<double> dh = dh8, dz(n.w);
+    for (int k = 7; k >= 0; --k) {
+        for (int i = 0; i < n.w; ++i) dz[i] = (k == 7) ? dh[i] : (a.z[k][i] > 0.0 ? dh[i] : 0.0);
+        int in = (int)a.in[k].size();
+        std::vector<double> din(in);
+        dense_backward(n.W[k], n.w, in, a.in[k].data(), dz.data(), (double*)g.W[k], (double*)g.b[k],
+                       k > 0 ? din.data() : nullptr);
+        if (k > 0) for (int i = 0; i < n.w; ++i) dh[i] = din[i];   // the skip's gx part has no parameters upstream
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+// ---- Eq.2/Eq.3 ------------------------------------------------------------
+void orc_equirect_lut(int W, int H, float* sphi, float* cphi, float* sth, float* cth) {
+    for (int u = 0; u < W; ++u) {
+        float a, b, c, d;
+        equirect_trig(W, H, u, 0, &a, &b, &c, &d);
+        sphi[u] = a; cphi[u] = b;
+    }
+    for (int v = 0; v < H; ++v) {
+        float a, b, c, d;
+        equirect_trig(W, H, 0, v, &a, &b, &c, &d);
+        sth[v] = c; cth[v] = d;
+    }
+}
+
+// Rays for the given pixels (linear index v * W + u) of an equirect camera;
+// pix == nullptr means all W*H pixels in raster order. o, d are [3][N].
+void orc_equirect_rays(int W, int H, const float* c2w, const int64_t* pix, int64_t N, float* o, float* d) {
+    for (int64_t r = 0; r < N; ++r) {
+        int64_t p = pix ? pix[r] : r;
+        int u = (int)(p % W), v = (int)(p / W);
+        float sphi, cphi, sth, cth;
+        equirect_trig(W, H, u, v, &sphi, &cphi, &sth, &cth);
+        float dc[3] = {cth * sphi, -sth, cth * cphi};
+        float oo[3], dd[3];
+        to_world(c2w, dc, oo, dd);
+        for (int a = 0; a < 3; ++a) { o[a * N + r] = oo[a]; d[a * N + r] = dd[a]; }
+    }
+}
+
+// Pinhole rays (perspective viewports): x = ((u + 1/2) - W/2) / fx,
+// y = ((v + 1/2) - H/2) / fy, z = 1, normalised with a correctly rounded
+// sqrt of fma(x, x, fma(y, y, 1)); then to the world frame.
+void orc_pinhole_rays(int W, int H, float fx, float fy, const float* c2w, int64_t N0, int64_t N, float* o, float* d) {
+    for (int64_t r = 0; r < N; ++r) {
+        int64_t p = N0 + r;
+        int u = (int)(p % W), v = (int)(p / W);
+        float x = ((float)u + 0.5f - 0.5f * (float)W) / fx;
+        float y = ((float)v + 0.5f - 0.5f * (float)H) / fy;
+        float nrm = std::sqrt(std::fma(x, x, std::fma(y, y, 1.0f)));
+        float dc[3] = {x / nrm, y / nrm, 1.0f / nrm};
+        float oo[3], dd[3];
+        to_world(c2w, dc, oo, dd);
+        for (int a = 0; a < 3; ++a) { o[a * N + r] = oo[a]; d[a * N + r] = dd[a]; }
+    }
+}
+
+// ---- sampling -------------------------------------------------------------
+// Per-ray sample counts (counts[N]).
+void orc_count_samples(const OrcScene* s, int64_t N, const float* o, const float* d, int32_t* counts, int nthreads) {
+    parallel_for(N, nthreads, [&](int64_t b, int64_t e, int) {
+        std::vector<Seg> segs(s->max_samples);
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dd[3] = {d[r], d[N + r], d[2 * N + r]};
+            counts[r] = sample_ray(*s, oo, dd, segs.data());
+        }
+    });
+}
+
+// Sample lists in ray-major order at the given exclusive offsets.
+void orc_sample_rays(const OrcScene* s, int64_t N, const float* o, const float* d, const int64_t* offsets,
+                     float* t_mid, float* delta, int32_t* ray_id, int32_t* voxel, int32_t* field, int nthreads) {
+    parallel_for(N, nthreads, [&](int64_t b, int64_t e, int) {
+        std::vector<Seg> segs(s->max_samples);
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dd[3] = {d[r], d[N + r], d[2 * N + r]};
+            int n = sample_ray(*s, oo, dd, segs.data());
+            for (int k = 0; k < n; ++k) {
+                int64_t j = offsets[r] + k;
+                t_mid[j] = segs[k].t_mid; delta[j] = segs[k].delta;
+                ray_id[j] = (int32_t)r; voxel[j] = segs[k].voxel; field[j] = segs[k].field;
+            }
+        }
+    });
+}
+
+// ---- encoding / MLP / compositing building blocks (for pins) ---------------
+void orc_encode(const double* x, int L, double* out) { encode(x, L, out); }
+
+void orc_local_mlp(const float* w, int hidden, int Lx, int Ld, const double* xh, const double* dir,
+                   double* sigma, double* rgb) {
+    int dx = 3 + 6 * Lx, dd = 3 + 6 * Ld;
+    std::vector<double> wd = widen(w, local_params(hidden, dx, dd));
+    LocalNet n = local_view(wd.data(), hidden, dx, dd);
+    LocalAct a;
+    local_forward(n, xh, dir, Lx, Ld, a);
+    *sigma = a.sigma;
+    for (int c = 0; c < 3; ++c) rgb[c] = a.rgb[c];
+}
+
+void orc_composite(int n, const double* sigma, const double* rgb, const double* t_mid, const double* delta,
+                   double* C, double* D, double* A, double* w) {
+    composite(n, sigma, rgb, t_mid, delta, C, D, A, w);
+}
+
+void orc_composite_backward(int n, const double* sigma, const double* rgb, const double* delta, const double* g,
+                            double* dsigma, double* drgb) {
+    composite_backward(n, sigma, rgb, delta, g, dsigma, drgb);
+}
+
+// ---- full render: sampling -> encoding -> local MLP -> compositing --------
+// Per ray: rgb [3][N], depth [N], opacity [N]; optional per-sample sigma/rgb
+// in ray-major order at `offsets` (may be null).
+void orc_render_rays(const OrcScene* s, int64_t N, const float* o, const float* d, double* rgb, double* depth,
+                     double* opacity, int nthreads) {
+    const int dx = 3 + 6 * s->L_xyz, dd = 3 + 6 * s->L_dir;
+    const size_t P = local_params(s->hidden, dx, dd);
+    std::vector<double> wd = widen(s->weights, P * s->n_fields);
+    parallel_for(N, nthreads, [&](int64_t b, int64_t e, int) {
+        std::vector<Seg> segs(s->max_samples);
+        std::vector<double> sig(s->max_samples), col(3 * s->max_samples), tm(s->max_samples), de(s->max_samples);
+        LocalAct a;
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
+            int n = sample_ray(*s, oo, dv, segs.data());
+            double dir[3] = {dv[0], dv[1], dv[2]};
+            for (int k = 0; k < n; ++k) {
+                double xh[3];
+                sample_position(*s, oo, dv, segs[k].t_mid, xh);
+                LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
+                local_forward(net, xh, dir, s->L_xyz, s->L_dir, a);
+                sig[k] = a.sigma;
+                for (int c = 0; c < 3; ++c) col[3 * k + c] = a.rgb[c];
+                tm[k] = segs[k].t_mid; de[k] = segs[k].delta;
+            }
+            double C[3], D, A;
+            composite(n, sig.data(), col.data(), tm.data(), de.data(), C, &D, &A, nullptr);
+            for (int c = 0; c < 3; ++c) rgb[c * N + r] = C[c];
+            depth[r] = D; opacity[r] = A;
+        }
+    });
+}
+
+// Per-sample network outputs in ray-major order (offsets as from the counts).
+void orc_sample_outputs(const OrcScene* s, int64_t N, const float* o, const float* d, const int64_t* offsets,
+                        double* sigma, double* rgb /*[3][S]*/, int64_t S, int nthreads) {
+    const int dx = 3 + 6 * s->L_xyz, dd = 3 + 6 * s->L_dir;
+    const size_t P = local_params(s->hidden, dx, dd);
+    std::vector<double> wd = widen(s->weights, P * s->n_fields);
+    parallel_for(N, nthreads, [&](int64_t b, int64_t e, int) {
+        std::vector<Seg> segs(s->max_samples);
+        LocalAct a;
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
+            int n = sample_ray(*s, oo, dv, segs.data());
+            double dir[3] = {dv[0], dv[1], dv[2]};
+            for (int k = 0; k < n; ++k) {
+                double xh[3];
+                sample_position(*s, oo, dv, segs[k].t_mid, xh);
+                LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
+                local_forward(net, xh, dir, s->L_xyz, s->L_dir, a);
+                int64_t j = offsets[r] + k;
+                sigma[j] = a.sigma;
+                for (int c = 0; c < 3; ++c) rgb[c * S + j] = a.rgb[c];
+            }
+        }
+    });
+}
+
+// ---- training: L = 1/(3B) sum_rays sum_ch (C - C*)^2, gradient w.r.t. all
+// local-field weights (Sec. 4.2 fine-tuning with an L2 photometric loss).
+// grad is [n_fields][P] FP64 (overwritten). Returns the loss.
+double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float* d, const float* target /*[3][N]*/,
+                      double* grad, double* rgb_out /*[3][N] or null*/, int nthreads) {
+    const int dx = 3 + 6 * s->L_xyz, dd = 3 + 6 * s->L_dir;
+    const size_t P = local_params(s->hidden, dx, dd);
+    const size_t GP = P * s->n_fields;
+    std::vector<double> wd = widen(s->weights, GP);
+    int nt = std::max(1, nthreads);
+    std::vector<std::vector<double>> gth(nt, std::vector<double>(GP, 0.0));
+    std::vector<double> lth(nt, 0.0);
+    parallel_for(N, nt, [&](int64_t b, int64_t e, int t) {
+        std::vector<Seg> segs(s->max_samples);
+        std::vector<LocalAct> acts(s->max_samples);
+        std::vector<double> sig(s->max_samples), col(3 * s->max_samples), tm(s->max_samples), de(s->max_samples);
+        std::vector<double> dsig(s->max_samples), dcol(3 * s->max_samples);
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
+            int n = sample_ray(*s, oo, dv, segs.data());
+            double dir[3] = {dv[0], dv[1], dv[2]};
+            for (int k = 0; k < n; ++k) {
+                double xh[3];
+                sample_position(*s, oo, dv, segs[k].t_mid, xh);
+                LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
+                local_forward(net, xh, dir, s->L_xyz, s->L_dir, acts[k]);
+                sig[k] = acts[k].sigma;
+                for (int c = 0; c < 3; ++c) col[3 * k + c] = acts[k].rgb[c];
+                tm[k] = segs[k].t_mid; de[k] = segs[k].delta;
+            }
+            double C[3], D, A;
+            composite(n, sig.data(), col.data(), tm.data(), de.data(), C, &D, &A, nullptr);
+            double g[3];
+            for (int c = 0; c < 3; ++c) {
+                double diff = C[c] - (double)target[c * N + r];
+                lth[t] += diff * diff / (3.0 * N);
+                g[c] = 2.0 * diff / (3.0 * N);
+                if (rgb_out) rgb_out[c * N + r] = C[c];
+            }
+            composite_backward(n, sig.data(), col.data(), de.data(), g, dsig.data(), dcol.data());
+            for (int k = 0; k < n; ++k) {
+                LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
+                LocalNet gn = local_view(gth[t].data() + P * segs[k].field, s->hidden, dx, dd);
+                local_backward(net, acts[k], dsig[k], &dcol[3 * k], gn);
+            }
+        }
+    });
+    double loss = 0.0;
+    for (size_t i = 0; i < GP; ++i) grad[i] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        loss += lth[t];
+        for (size_t i = 0; i < GP; ++i) grad[i] += gth[t][i];
+    }
+    return loss;
+}
+
+// ---- global omnidirectional field ----------------------------------------
+// Sample placement uniform in inverse depth over [near, far] (Sec. 3.2:
+// sampling "in inverse distance"), FP32 spec:
+//   a = 1/near, b = 1/far, s_i = i / (N - 1), t_i = 1 / fma(s_i, b, (1 - s_i) a),
+// which gives 1/near and 1/far exactly at the two ends;
+//   delta_i = t_{i+1} - t_i, and delta_{N-1} = 0.
+void orc_invdepth_t(int n_samples, float near_, float far_, float* t, float* delta) {
+    float a = 1.0f / near_, b = 1.0f / far_;
+    for (int i = 0; i < n_samples; ++i) {
+        float si = (float)i / (float)(n_samples - 1);
+        t[i] = 1.0f / std::fma(si, b, (1.0f - si) * a);
+    }
+    for (int i = 0; i < n_samples; ++i) delta[i] = (i + 1 < n_samples) ? t[i + 1] - t[i] : 0.0f;
+}
+
+struct OrcGlobal {
+    int32_t width, color_width, L_xyz, L_dir, n_samples;
+    float near_, far_;
+    float center[3];
+    float half_extent;
+    const float* weights;
+    // occupancy grid for the density max: grid[n2][n1][n0]
+    int32_t n[3];
+    float lo[3];
+    float voxel;
+};
+
+// Forward + backward of the global field over N rays; returns the loss and
+// writes the gradient [P] (FP64), per-ray colour [3][N], depth, opacity, and
+// the per-voxel max of sample density into occ_max (FP64, initialised by the
+// caller).
+double orc_global_step(const OrcGlobal* g, int64_t N, const float* o, const float* d, const float* target,
+                       double* grad, double* rgb_out, double* depth_out, double* opacity_out,
+                       double* occ_max, int nthreads) {
+    const int dx = 3 + 6 * g->L_xyz, dd = 3 + 6 * g->L_dir, ns = g->n_samples;
+    const size_t P = global_params(g->width, g->color_width, dx, dd);
+    std::vector<double> wd = widen(g->weights, P);
+    GlobalNet net = global_view(wd.data(), g->width, g->color_width, dx, dd);
+    std::vector<float> tt(ns), dl(ns);
+    orc_invdepth_t(ns, g->near_, g->far_, tt.data(), dl.data());
+    int nt = std::max(1, nthreads);
+    std::vector<std::vector<double>> gth(nt, std::vector<double>(P, 0.0));
+    std::vector<double> lth(nt, 0.0);
+    const size_t ncell = (size_t)g->n[0] * g->n[1] * g->n[2];
+    std::vector<std::vector<double>> occ_th(nt, std::vector<double>(occ_max ? ncell : 0, 0.0));
+    const float inv_h = 1.0f / g->half_extent, inv_vox = 1.0f / g->voxel;
+    parallel_for(N, nt, [&](int64_t b, int64_t e, int t) {
+        std::vector<GlobalAct> acts(ns);
+        std::vector<double> sig(ns), col(3 * ns), tm(ns), de(ns), dsig(ns), dcol(3 * ns);
+        GlobalNet gn = global_view(gth[t].data(), g->width, g->color_width, dx, dd);
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
+            double dir[3] = {dv[0], dv[1], dv[2]};
+            for (int k = 0; k < ns; ++k) {
+                double xh[3];
+                int cell[3];
+                bool inside = true;
+                for (int a = 0; a < 3; ++a) {
+                    float p = std::fma(tt[k], dv[a], oo[a]);
+                    xh[a] = (double)((p - g->center[a]) * inv_h);
+                    float q = (p - g->lo[a]) * inv_vox;
+                    inside = inside && (q >= 0.0f) && (q < (float)g->n[a]);
+                    cell[a] = inside ? (int)std::floor(q) : 0;
+                }
+                global_forward(net, xh, dir, g->L_xyz, g->L_dir, acts[k]);
+                sig[k] = acts[k].sigma;
+                for (int c = 0; c < 3; ++c) col[3 * k + c] = acts[k].rgb[c];
+                tm[k] = tt[k]; de[k] = dl[k];
+                if (occ_max && inside) {
+                    size_t lin = cell[0] + (size_t)g->n[0] * (cell[1] + (size_t)g->n[1] * cell[2]);
+                    occ_th[t][lin] = std::max(occ_th[t][lin], sig[k]);
+                }
+            }
+            double C[3], D, A;
+            composite(ns, sig.data(), col.data(), tm.data(), de.data(), C, &D, &A, nullptr);
+            if (rgb_out) for (int c = 0; c < 3; ++c) rgb_out[c * N + r] = C[c];
+            if (depth_out) depth_out[r] = D;
+            if (opacity_out) opacity_out[r] = A;
+            double gC[3];
+            for (int c = 0; c < 3; ++c) {
+                double diff = C[c] - (double)target[c * N + r];
+                lth[t] += diff * diff / (3.0 * N);
+                gC[c] = 2.0 * diff / (3.0 * N);
+            }
+            composite_backward(ns, sig.data(), col.data(), de.data(), gC, dsig.data(), dcol.data());
+            for (int k = 0; k < ns; ++k) global_backward(net, acts[k], dsig[k], &dcol[3 * k], gn);
+        }
+    });
+    double loss = 0.0;
+    for (size_t i = 0; i < P; ++i) grad[i] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        loss += lth[t];
+        for (size_t i = 0; i < P; ++i) grad[i] += gth[t][i];
+        if (occ_max) for (size_t i = 0; i < ncell; ++i) occ_max[i] = std::max(occ_max[i], occ_th[t][i]);
+    }
+    return loss;
+}
+
+// Global field forward at explicit points (pins and per-sample checks).
+void orc_global_mlp(const float* w, int width, int color_width, int Lx, int Ld, const double* xh, const double* dir,
+                    double* sigma, double* rgb) {
+    int dx = 3 + 6 * Lx, dd = 3 + 6 * Ld;
+    std::vector<double> wd = widen(w, global_params(width, color_width, dx, dd));
+    GlobalNet n = global_view(wd.data(), width, color_width, dx, dd);
+    GlobalAct a;
+    global_forward(n, xh, dir, Lx, Ld, a);
+    *sigma = a.sigma;
+    for (int c = 0; c < 3; ++c) rgb[c] = a.rgb[c];
+}
+
+int64_t orc_local_params(int hidden, int Lx, int Ld) { return (int64_t)local_params(hidden, 3 + 6 * Lx, 3 + 6 * Ld); }
+int64_t orc_global_params(int width, int color_width, int Lx, int Ld) {
+    return (int64_t)global_params(width, color_width, 3 + 6 * Lx, 3 + 6 * Ld);
+}
+
+// ---- Adam (Sec. 6.1 training details: beta1 0.9, beta2 0.99) -------------
+// m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
+// w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), FP64.
+void orc_adam(int64_t n, double* w, const double* g, double* m, double* v, int64_t step, double lr, double b1,
+              double b2, double eps) {
+    double c1 = 1.0 - std::pow(b1, (double)step), c2 = 1.0 - std::pow(b2, (double)step);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (std::sqrt(v[i] / c2) + eps);
+    }
+}
+
+}  // extern "C"

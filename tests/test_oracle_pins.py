@@ -1,0 +1,561 @@
+"""Pins for the FP64 oracle: closed forms, invariants, brute force and
+numbers printed in the paper. None of these re-derive a value from the
+oracle's own code path; each is chosen so that a dropped term, a wrong sign
+or index, or a transposed operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------------------
+# Parameter counts printed in the paper (App. C, Sec. 6.2)
+# ---------------------------------------------------------------------------
+
+def test_param_counts_match_paper(orc):
+    g = golden("paper_constants.json")
+    assert orc.local_params(32) == g["tiny_mlp_params"]["value"]
+    assert synth.n_params(synth.local_mlp_layout(32)) == g["tiny_mlp_params"]["value"]
+    gp = orc.global_params(256, 128)
+    assert abs(gp - g["global_mlp_params_approx"]["value"]) <= g["global_mlp_params_approx"]["rel_tol"] * 596000
+    assert gp == synth.n_params(synth.global_mlp_layout())
+    n200 = 200 * orc.local_params(32)
+    assert abs(n200 - 1.2e6) <= 0.05 * 1.2e6
+    assert orc.local_params(64) == 18564
+
+
+# ---------------------------------------------------------------------------
+# Ray generation (Eq.2 / Eq.3)
+# ---------------------------------------------------------------------------
+
+def test_equirect_round_trip(orc):
+    W, H = 64, 32
+    o, d = orc.equirect_rays(W, H, synth.IDENTITY_C2W)
+    d64 = d.astype(np.float64)
+    phi = np.arctan2(d64[0], d64[2])
+    theta = -np.arcsin(np.clip(d64[1], -1, 1))
+    u = phi * W / (2 * np.pi) + W / 2 - 0.5          # Eq.2 forward, minus the pixel centre
+    v = -theta * H / np.pi + H / 2 - 0.5
+    uu, vv = np.meshgrid(np.arange(W), np.arange(H))
+    assert np.max(np.abs(u - uu.ravel())) < 1e-3
+    assert np.max(np.abs(v - vv.ravel())) < 1e-3
+    assert np.all(o == 0)
+
+
+def test_equirect_special_directions(orc):
+    W, H = 256, 128
+    o, d = orc.equirect_rays(W, H, synth.IDENTITY_C2W)
+    d = d.reshape(3, H, W).astype(np.float64)
+    # |d| = 1 to a few FP32 ulp (not renormalised)
+    nrm = np.sqrt((d ** 2).sum(0))
+    assert np.max(np.abs(nrm - 1)) < 4 * 2.0 ** -24 * 2
+    # top row points up (y down): d_y = -sin(theta_0), theta_0 = pi (H - 1) / (2H)
+    assert np.allclose(d[1, 0, :], -np.sin(np.pi * (H - 1) / (2 * H)), atol=1e-7)
+    assert np.allclose(d[1, H - 1, :], np.sin(np.pi * (H - 1) / (2 * H)), atol=1e-7)
+    # the two central columns straddle +z symmetrically
+    c0, c1 = W // 2 - 1, W // 2
+    assert np.allclose(d[0, :, c0], -d[0, :, c1]) and np.all(d[2, H // 2, c0:c1 + 1] > 0.99)
+    # column 0 looks backwards (phi near -pi)
+    assert np.all(d[2, H // 2, 0] < -0.99)
+
+
+def test_pinhole_directions(orc):
+    W, H = 64, 48
+    f = W / 2.0                                         # 90 degree horizontal field of view
+    o, d = orc.pinhole_rays(W, H, f, f, synth.c2w_at((1.0, 2.0, 3.0)))
+    d = d.reshape(3, H, W).astype(np.float64)
+    assert np.allclose(o[:, 0], [1, 2, 3])
+    # right-most column centre: x/z = ((W - 1/2) - W/2)/f
+    assert np.allclose(d[0, :, -1] / d[2, :, -1], (W - 0.5 - W / 2) / f, atol=1e-6)
+    assert np.allclose(np.sqrt((d ** 2).sum(0)), 1, atol=1e-6)
+    # quarter-turn yaw maps +z to +x (rotation entries 0/+-1: exact)
+    o2, d2 = orc.pinhole_rays(W, H, f, f, synth.c2w_yaw((0, 0, 0), 1))
+    o1, d1 = orc.pinhole_rays(W, H, f, f, synth.c2w_yaw((0, 0, 0), 0))
+    assert np.array_equal(d2[0], d1[2]) and np.array_equal(d2[2], -d1[0]) and np.array_equal(d2[1], d1[1])
+
+
+# ---------------------------------------------------------------------------
+# Voxel traversal (FP32 specification) against FP64 brute force
+# ---------------------------------------------------------------------------
+
+def brute_segments(scene, o, d, near=0.0, far=np.inf):
+    """All positive-length voxel segments by an FP64 slab test per voxel."""
+    n, lo, vs = scene.n, scene.lo, scene.voxel
+    o = o.astype(np.float64); d = d.astype(np.float64)
+    idx = np.arange(n)
+    k, j, i = np.meshgrid(idx, idx, idx, indexing="ij")
+    boxes_lo = [lo + i * vs, lo + j * vs, lo + k * vs]
+    tin = np.full(i.shape, -np.inf); tout = np.full(i.shape, np.inf)
+    for a in range(3):
+        blo, bhi = boxes_lo[a], boxes_lo[a] + vs
+        if d[a] != 0:
+            ta, tb = (blo - o[a]) / d[a], (bhi - o[a]) / d[a]
+            tin = np.maximum(tin, np.minimum(ta, tb)); tout = np.minimum(tout, np.maximum(ta, tb))
+        else:
+            inside = (o[a] >= blo) & (o[a] < bhi)
+            tin = np.where(inside, tin, np.inf)
+    tin = np.maximum(tin, near); tout = np.minimum(tout, far)
+    keep = (tout > tin) & scene.occupied & (scene.field_map >= 0)
+    lin = (i + n * (j + n * k))[keep]
+    a_in, a_out = tin[keep], tout[keep]
+    order = np.argsort(a_in)
+    return lin[order], a_in[order], a_out[order], tin, tout
+
+
+def test_dda_matches_brute_force(orc):
+    checked = 0
+    for n, seed in ((2, 1), (4, 2), (8, 3)):
+        sc = synth.tiny_scene(n, seed, p_occ=0.6, max_samples=64)
+        rng = np.random.default_rng(seed)
+        N = 300
+        o = rng.uniform(-5, 5, size=(3, N)).astype(np.float32)
+        d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0)
+        d = d.astype(np.float32)
+        smp = orc.sample_rays(sc, o, d)
+        for r in range(N):
+            lin, tin, tout, all_in, all_out = brute_segments(sc, o[:, r], d[:, r])
+            seglen = all_out - all_in
+            if np.any((seglen > 0) & (seglen < 1e-4)):
+                continue                                   # grazing an edge: tie region
+            a, b = smp["offsets"][r], smp["offsets"][r + 1]
+            assert np.array_equal(smp["voxel"][a:b], lin), (n, r)
+            tm = 0.5 * (tin + tout)
+            assert np.allclose(smp["t_mid"][a:b], tm, rtol=0, atol=4e-6 * max(1.0, np.max(np.abs(tm), initial=1)))
+            assert np.allclose(smp["delta"][a:b], tout - tin, rtol=0, atol=4e-6 * max(1.0, np.max(np.abs(tm), initial=1)))
+            assert np.all(smp["ray_id"][a:b] == r)
+            assert np.array_equal(smp["field"][a:b], sc.field_map.ravel()[lin])
+            checked += 1
+    assert checked > 700
+
+
+def test_dda_axis_aligned_full_voxels(orc):
+    sc = synth.tiny_scene(8, 5, p_occ=1.0)
+    o = np.array([[-3.9], [0.1], [0.2]], np.float32)
+    d = np.array([[1.0], [0.0], [0.0]], np.float32)
+    smp = orc.sample_rays(sc, o, d)
+    assert smp["counts"][0] == 8
+    # every full voxel has delta exactly one voxel edge; the first is partial
+    assert np.all(smp["delta"][1:] == np.float32(1.0))
+    assert smp["delta"][0] == np.float32(-3.0) - np.float32(-3.9)
+    assert list(smp["voxel"]) == [i + 8 * (4 + 8 * 4) for i in range(8)]
+
+
+def test_dda_full_grid_lengths_telescope(orc):
+    sc = synth.tiny_scene(8, 6, p_occ=1.0, max_samples=64)
+    rng = np.random.default_rng(7)
+    N = 200
+    o = rng.uniform(-3, 3, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    smp = orc.sample_rays(sc, o, d)
+    for r in range(N):
+        t1 = np.min(np.maximum((-4 - o[:, r].astype(np.float64)) / d[:, r], (4 - o[:, r].astype(np.float64)) / d[:, r]))
+        a, b = smp["offsets"][r], smp["offsets"][r + 1]
+        assert abs(smp["delta"][a:b].astype(np.float64).sum() - t1) < 1e-5
+
+
+def test_dda_corner_start_diagonal_tie(orc):
+    # camera exactly on the centre corner of an 8^3 grid of 1 m voxels, moving
+    # along the (-1,-1,-1) diagonal: only the diagonal voxels have positive
+    # length; ties across planes emit nothing.
+    sc = synth.tiny_scene(8, 8, p_occ=1.0)
+    o = np.zeros((3, 1), np.float32)
+    s = np.float32(-1 / np.sqrt(3))
+    d = np.array([[s], [s], [s]], np.float32)
+    smp = orc.sample_rays(sc, o, d)
+    assert [int(v) for v in smp["voxel"]] == [c + 8 * (c + 8 * c) for c in (3, 2, 1, 0)]
+    assert np.allclose(smp["delta"], np.sqrt(3), rtol=1e-6)
+    # the same along +x from the corner: voxel row (4.., 4, 4) -- floor picks the upper voxel
+    d = np.array([[1.0], [0.0], [0.0]], np.float32)
+    smp = orc.sample_rays(sc, o, d)
+    assert [int(v) for v in smp["voxel"]] == [i + 8 * (4 + 8 * 4) for i in range(4, 8)]
+    # and along -x: the lower voxel on the start plane
+    d = np.array([[-1.0], [0.0], [0.0]], np.float32)
+    smp = orc.sample_rays(sc, o, d)
+    assert [int(v) for v in smp["voxel"]] == [i + 8 * (4 + 8 * 4) for i in (3, 2, 1, 0)]
+
+
+def test_dda_near_far_and_cap(orc):
+    sc = synth.tiny_scene(8, 9, p_occ=0.7, max_samples=64)
+    rng = np.random.default_rng(10)
+    N = 100
+    o = rng.uniform(-2, 2, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    full = orc.sample_rays(sc, o, d)
+    capped = orc.sample_rays(sc, o, d, max_samples=3)
+    clipped = orc.sample_rays(sc, o, d, near=1.0, far=3.0)
+    for r in range(N):
+        a, b = full["offsets"][r], full["offsets"][r + 1]
+        ca, cb = capped["offsets"][r], capped["offsets"][r + 1]
+        assert cb - ca == min(3, b - a)
+        assert np.array_equal(capped["voxel"][ca:cb], full["voxel"][a:a + (cb - ca)])
+        ka, kb = clipped["offsets"][r], clipped["offsets"][r + 1]
+        tm, dl = clipped["t_mid"][ka:kb], clipped["delta"][ka:kb]
+        assert np.all(tm - dl / 2 >= 1.0 - 1e-6) and np.all(tm + dl / 2 <= 3.0 + 1e-6)
+
+
+def test_dda_counts_on_small_config(orc):
+    # strictly increasing t, positive deltas, segments do not overlap
+    sc = synth.scene_small()
+    o, d = orc.equirect_rays(256, 128, synth.IDENTITY_C2W)
+    smp = orc.sample_rays(sc, o, d)
+    assert smp["counts"].max() <= 32 and np.all(smp["delta"] > 0)
+    ends = smp["t_mid"] + smp["delta"] / 2
+    starts = smp["t_mid"] - smp["delta"] / 2
+    same = smp["ray_id"][1:] == smp["ray_id"][:-1]
+    assert np.all(starts[1:][same] >= ends[:-1][same] - 1e-6)
+    assert np.all(sc.occupied.ravel()[smp["voxel"]])
+
+
+# ---------------------------------------------------------------------------
+# Positional encoding
+# ---------------------------------------------------------------------------
+
+def test_encoding_layout_and_closed_values(orc):
+    assert len(orc.encode([0.1, 0.2, 0.3], 10)) == 63 and len(orc.encode([0.1, 0.2, 0.3], 4)) == 27
+    g = orc.encode([0.0, 0.5, 1.0], 10)
+    assert list(g[:3]) == [0.0, 0.5, 1.0]
+    for l in range(10):
+        s, c = g[3 + 6 * l: 6 + 6 * l], g[6 + 6 * l: 9 + 6 * l]
+        # x = 0: sin 0, cos 1
+        assert s[0] == 0.0 and c[0] == 1.0
+        # x = 1/2: sin(2^l pi / 2) and cos(2^l pi / 2)
+        assert s[1] == (1.0 if l == 0 else 0.0)
+        assert c[1] == (0.0 if l == 0 else (-1.0 if l == 1 else 1.0))
+        # x = 1: sin(2^l pi) = 0, cos = -1 for l = 0 else 1
+        assert s[2] == 0.0 and c[2] == (-1.0 if l == 0 else 1.0)
+
+
+def test_encoding_unit_circle_and_frequency(orc):
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        x = rng.uniform(-1.3, 1.3, 3)
+        g = orc.encode(x, 10)
+        for l in range(10):
+            s, c = g[3 + 6 * l: 6 + 6 * l], g[6 + 6 * l: 9 + 6 * l]
+            assert np.allclose(s ** 2 + c ** 2, 1.0, atol=1e-14)
+            assert np.allclose(s, np.sin(np.pi * 2.0 ** l * x), atol=1e-12)
+            assert np.allclose(c, np.cos(np.pi * 2.0 ** l * x), atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Local MLP
+# ---------------------------------------------------------------------------
+
+def _zeros_local(h):
+    lay = synth.local_mlp_layout(h)
+    w = np.zeros(synth.n_params(lay), np.float32)
+    return lay, w, synth.unpack(lay, w)
+
+
+def sp(z):
+    return max(z, 0) + math.log1p(math.exp(-abs(z)))
+
+
+def sg(z):
+    return 1 / (1 + math.exp(-z))
+
+
+def test_local_mlp_zero_weights(orc):
+    lay, w, t = _zeros_local(32)
+    t["bs"][0] = 0.37
+    t["b4"][:] = [-0.5, 0.25, 1.5]
+    t["b1"][:] = 3.0; t["b2"][:] = -1.0; t["b3"][:] = 2.0
+    sigma, rgb = orc.local_mlp(w, 32, [0.1, -0.2, 0.3], [0, 0, 1])
+    assert abs(sigma - sp(float(np.float32(0.37)))) < 1e-15
+    assert np.allclose(rgb, [sg(-0.5), sg(0.25), sg(1.5)], atol=1e-15)
+
+
+def test_local_mlp_routed_signal(orc):
+    """Hand-wired weights carry known signals through distinct indices of
+    every layer; a transposed matrix, a wrong offset or a wrong encoding
+    slot moves the signal and changes the closed-form result."""
+    h = 32
+    lay, w, t = _zeros_local(h)
+    x, y, z = 0.3, 0.1, 0.05
+    dvec = np.array([0.6, 0.0, 0.8])
+    # density path: raw x -> h1[5] -> h2[7] (x2) -> sigma
+    t["W1"][5, 0] = 1.0
+    t["W2"][7, 5] = 2.0
+    t["ws"][0, 7] = 1.5; t["bs"][0] = -0.25
+    # colour path: sin(4 pi y) (l=2, sine, component y) -> h1[2] -> h2[9] -> f[12] -> h3[6] -> red
+    t["W1"][2, 3 + 6 * 2 + 1] = 1.0
+    t["W2"][9, 2] = 1.0
+    t["Wf"][12, 9] = 1.0
+    t["W3"][6, 12] = 1.0
+    t["W4"][0, 6] = 1.0
+    # cos(4 pi z) -> h1[4] -> h2[10] -> f[13] -> h3[8], plus 0.5 cos(2 pi d_x) -> green
+    t["W1"][4, 3 + 6 * 2 + 3 + 2] = 1.0
+    t["W2"][10, 4] = 1.0
+    t["Wf"][13, 10] = 1.0; t["bf"][13] = 0.125
+    t["W3"][8, 13] = 1.0
+    t["W3"][8, h + 3 + 6 * 1 + 3 + 0] = 0.5
+    t["W4"][1, 8] = 1.0
+    # f[12] also reaches blue with a negative sign through h3[3] and the raw direction d_z
+    t["W3"][3, 12] = 1.0; t["W3"][3, h + 2] = -2.0; t["b3"][3] = 2.0
+    t["W4"][2, 3] = -1.0; t["b4"][2] = 0.5
+    sigma, rgb = orc.local_mlp(w, h, [x, y, z], dvec)
+    assert abs(sigma - sp(3 * x - 0.25)) < 1e-14
+    f12 = max(math.sin(4 * math.pi * y), 0)
+    assert abs(rgb[0] - sg(f12)) < 1e-14
+    h38 = max(max(math.cos(4 * math.pi * z), 0) + 0.125 + 0.5 * math.cos(2 * math.pi * 0.6), 0)
+    assert abs(rgb[1] - sg(h38)) < 1e-14
+    h33 = max(f12 - 2 * 0.8 + 2.0, 0)
+    assert abs(rgb[2] - sg(0.5 - h33)) < 1e-14
+
+
+def test_local_mlp_single_layer_against_matmul(orc):
+    """With identity-like downstream layers the red output is sigmoid of one
+    ReLU dense layer of the encoding, checked against numpy's matmul."""
+    h = 32
+    lay, w, t = _zeros_local(h)
+    rng = np.random.default_rng(3)
+    t["W1"][:] = rng.normal(size=t["W1"].shape).astype(np.float32) * 0.2
+    t["b1"][:] = rng.normal(size=h).astype(np.float32) * 0.1
+    for k in range(h):
+        t["W2"][k, k] = 1.0
+    t["Wf"][0, :] = 1.0 / h
+    t["W3"][0, 0] = 1.0
+    t["W4"][0, 0] = 1.0
+    xh = np.array([0.21, -0.43, 0.77])
+    sigma, rgb = orc.local_mlp(w, h, xh, [0, 1, 0])
+    # encoding by its definition, via numpy
+    enc = [*xh]
+    for l in range(10):
+        enc += list(np.sin(np.pi * 2.0 ** l * xh)) + list(np.cos(np.pi * 2.0 ** l * xh))
+    h1 = np.maximum(t["W1"].astype(np.float64) @ np.array(enc) + t["b1"], 0)
+    assert abs(rgb[0] - sg(max(h1.mean(), 0))) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Compositing (Eq.4 / Eq.5)
+# ---------------------------------------------------------------------------
+
+def test_composite_constant_density_closed_form(orc):
+    sigma0, n, L, t0 = 1.7, 13, 2.3, 0.4
+    dl = L / n
+    tm = t0 + (np.arange(n) + 0.5) * dl
+    col = np.tile([0.2, 0.5, 0.9], (n, 1))
+    C, D, A, w = orc.composite(np.full(n, sigma0), col, tm, np.full(n, dl))
+    assert abs(A - (1 - math.exp(-sigma0 * L))) < 1e-14
+    assert abs(w.sum() - A) < 1e-15
+    assert np.allclose(C, np.array([0.2, 0.5, 0.9]) * A, atol=1e-15)
+    r = math.exp(-sigma0 * dl)
+    Dc = (1 - r) * ((t0 + dl / 2) * (1 - r ** n) / (1 - r) + dl * (r - n * r ** n + (n - 1) * r ** (n + 1)) / (1 - r) ** 2)
+    assert abs(D - Dc) < 1e-13
+
+
+def test_composite_special_cases(orc):
+    C, D, A, w = orc.composite([0.8], [[0.1, 0.2, 0.3]], [2.0], [0.5])
+    a = 1 - math.exp(-0.4)
+    assert abs(A - a) < 1e-15 and abs(D - 2.0 * a) < 1e-15 and np.allclose(C, np.array([0.1, 0.2, 0.3]) * a)
+    C, D, A, w = orc.composite(np.zeros(5), np.ones((5, 3)), np.arange(5.0), np.ones(5))
+    assert A == 0 and D == 0 and np.all(C == 0)
+    C, D, A, w = orc.composite([], np.zeros((0, 3)), [], [])
+    assert A == 0
+    # an opaque first sample hides everything behind it; order matters
+    C, D, A, w = orc.composite([50.0, 1.0], [[1, 0, 0], [0, 1, 0]], [1.0, 2.0], [1.0, 1.0])
+    assert w[0] == 1 - math.exp(-50.0) and w[1] < 1e-20 and C[1] < 1e-20
+    rng = np.random.default_rng(1)
+    s = rng.uniform(0, 3, 40); dl = rng.uniform(0.01, 0.2, 40)
+    C, D, A, w = orc.composite(s, rng.uniform(0, 1, (40, 3)), np.cumsum(dl), dl)
+    T_final = math.exp(-(s * dl).sum())
+    assert abs(A - (1 - T_final)) < 1e-14 and A <= 1
+
+
+def test_composite_backward_finite_difference(orc):
+    rng = np.random.default_rng(2)
+    n = 9
+    s = rng.uniform(0.1, 4, n); col = rng.uniform(0, 1, (n, 3)); dl = rng.uniform(0.05, 0.4, n)
+    tm = np.cumsum(dl)
+    g = rng.normal(size=3)
+    ds, dc = orc.composite_backward(s, col, dl, g)
+
+    def L(s_, c_):
+        C, _, _, _ = orc.composite(s_, c_, tm, dl)
+        return float(C @ g)
+    for i in range(n):
+        e = 1e-6
+        sp_, sm_ = s.copy(), s.copy(); sp_[i] += e; sm_[i] -= e
+        assert abs((L(sp_, col) - L(sm_, col)) / (2 * e) - ds[i]) < 1e-8
+        for c in range(3):
+            cp, cm = col.copy(), col.copy(); cp[i, c] += e; cm[i, c] -= e
+            assert abs((L(s, cp) - L(s, cm)) / (2 * e) - dc[i, c]) < 1e-8
+    # one sample: dC/dsigma = delta exp(-sigma delta) c
+    ds1, _ = orc.composite_backward([0.7], [[0.3, 0.6, 0.9]], [0.25], [1.0, 0.0, 0.0])
+    assert abs(ds1[0] - 0.25 * math.exp(-0.7 * 0.25) * 0.3) < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Whole local path: batched oracle vs per-sample evaluation + naive compositing
+# ---------------------------------------------------------------------------
+
+def test_render_equals_per_sample_evaluation(orc):
+    sc = synth.tiny_scene(8, 11, p_occ=0.4, n_fields=3, hidden=32)
+    rng = np.random.default_rng(11)
+    N = 40
+    o = rng.uniform(-3, 3, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    rgb, depth, opac = orc.render_rays(sc, o, d)
+    smp = orc.sample_rays(sc, o, d)
+    sig_b, rgb_b = orc.sample_outputs(sc, o, d, smp["offsets"])
+    P = sc.n_params
+    for r in range(N):
+        a, b = smp["offsets"][r], smp["offsets"][r + 1]
+        sig, col = [], []
+        for j in range(a, b):
+            # encoding input by the FP32 specification: p = fma(t, d, o), xhat = p / 4
+            p = np.array([np.float32(np.float64(smp["t_mid"][j]) * np.float64(d[k, r]) + np.float64(o[k, r]))
+                          for k in range(3)], np.float32)
+            s1, c1 = orc.local_mlp(sc.weights[smp["field"][j]], 32, (p * np.float32(0.25)).astype(np.float64),
+                                   d[:, r].astype(np.float64))
+            sig.append(s1); col.append(c1)
+            assert abs(s1 - sig_b[j]) < 1e-12 and np.allclose(c1, rgb_b[:, j], atol=1e-12)
+        C, D, A, _ = orc.composite(sig, np.array(col).reshape(-1, 3), smp["t_mid"][a:b], smp["delta"][a:b])
+        assert np.allclose(C, rgb[:, r], atol=1e-12) and abs(D - depth[r]) < 1e-11 and abs(A - opac[r]) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Loss gradient of the local path: analytic vs central finite differences
+# ---------------------------------------------------------------------------
+
+def _fd_check(loss_fn, w, idx, grad, rel=1e-5):
+    bad = []
+    for i in idx:
+        base = w[i]
+        hstep = np.float32(max(abs(base), 1e-2) * 2e-4)
+        wp, wm = w.copy(), w.copy()
+        wp[i] = base + hstep; wm[i] = base - hstep
+        eff = np.float64(wp[i]) - np.float64(wm[i])
+        fd = (loss_fn(wp) - loss_fn(wm)) / eff
+        wp2, wm2 = w.copy(), w.copy()
+        wp2[i] = base + hstep / 2; wm2[i] = base - hstep / 2
+        fd2 = (loss_fn(wp2) - loss_fn(wm2)) / (np.float64(wp2[i]) - np.float64(wm2[i]))
+        if abs(fd - fd2) > 1e-3 * max(abs(fd), 1e-9):
+            continue                                   # a ReLU kink inside the stencil
+        if abs(fd - grad[i]) > rel * max(abs(fd), 1e-7) + 1e-12:
+            bad.append((i, fd, grad[i]))
+    return bad
+
+
+def test_train_grad_finite_difference(orc):
+    sc = synth.tiny_scene(4, 12, p_occ=0.5, n_fields=2, hidden=16)
+    rng = np.random.default_rng(12)
+    N = 12
+    o = rng.uniform(-1, 1, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    # give the fields some non-zero biases so that every layer carries gradient
+    w0 = sc.weights.copy()
+    w0 += rng.normal(size=w0.shape).astype(np.float32) * 0.05
+    target = rng.uniform(0, 1, (3, N)).astype(np.float32)
+    loss, grad, _ = orc.train_grad(sc, o, d, target, weights=w0)
+    flat = w0.ravel()
+
+    def loss_fn(wf):
+        l, _, _ = orc.train_grad(sc, o, d, target, weights=wf.reshape(w0.shape))
+        return l
+    idx = rng.choice(flat.size, 150, replace=False)
+    # include every bias group and the density head explicitly
+    lay = synth.local_mlp_layout(16)
+    off = 0
+    for name, shape in lay:
+        size = int(np.prod(shape))
+        idx = np.append(idx, [off, off + size - 1])
+        off += size
+    bad = _fd_check(loss_fn, flat, idx, grad.ravel())
+    assert not bad, bad[:5]
+    assert np.count_nonzero(grad) > 0.3 * grad.size
+
+
+# ---------------------------------------------------------------------------
+# Global omnidirectional field
+# ---------------------------------------------------------------------------
+
+def test_invdepth_samples(orc):
+    t, dl = orc.invdepth_t(128, 0.1, 20.0)
+    assert abs(t[0] - 0.1) < 1e-7 and abs(t[-1] - 20.0) < 4e-6
+    inv = 1.0 / t.astype(np.float64)
+    assert np.allclose(np.diff(inv), (1 / 20.0 - 1 / 0.1) / 127, rtol=1e-4)
+    assert np.all(np.diff(t) > 0) and dl[-1] == 0 and np.allclose(dl[:-1], np.diff(t))
+
+
+def test_global_mlp_zero_weights_and_skip(orc):
+    lay = synth.global_mlp_layout(16, color_width=8)
+    w = np.zeros(synth.n_params(lay), np.float32)
+    t = synth.unpack(lay, w)
+    t["bs"][0] = 0.5; t["b11"][:] = [0.1, -0.2, 0.3]
+    s, rgb = orc.global_mlp(w, [0.1, 0.2, 0.3], [0, 0, 1], width=16, color_width=8)
+    assert s == 0.5 and np.allclose(rgb, [sg(float(np.float32(v))) for v in (0.1, -0.2, 0.3)], atol=1e-15)
+    # the skip: encoded position re-enters at the fifth layer (its slot 16 + 2 = raw z)
+    t["W5"][3, 16 + 2] = 1.0
+    t["W6"][3, 3] = 1.0; t["W7"][3, 3] = 1.0; t["W8"][3, 3] = 1.0
+    t["ws"][0, 3] = 2.0
+    s, _ = orc.global_mlp(w, [0.1, 0.2, 0.3], [0, 0, 1], width=16, color_width=8)
+    assert abs(s - (0.5 + 2 * 0.3)) < 1e-15
+    # the layer-8 output has no activation: a negative value passes through to sigma's ReLU input
+    t["bs"][0] = 0.0; t["b8"][3] = -1.0
+    s, _ = orc.global_mlp(w, [0.1, 0.2, 0.3], [0, 0, 1], width=16, color_width=8)
+    assert abs(s - max(2 * (0.3 - 1.0), 0)) < 1e-15
+    t["ws"][0, 3] = -2.0
+    s, _ = orc.global_mlp(w, [0.1, 0.2, 0.3], [0, 0, 1], width=16, color_width=8)
+    assert abs(s - 1.4) < 1e-15
+
+
+def test_global_step_finite_difference_and_occupancy(orc):
+    width, cw = 16, 8
+    lay = synth.global_mlp_layout(width, color_width=cw)
+    rng = np.random.default_rng(13)
+    w = synth.xavier_weights(lay, 1, 13, synth.STREAM_WEIGHTS)[0]
+    w += rng.normal(size=w.shape).astype(np.float32) * 0.05
+    N, ns = 3, 16
+    o = rng.uniform(-1, 1, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    target = rng.uniform(0, 1, (3, N)).astype(np.float32)
+    kw = dict(n_samples=ns, width=width, color_width=cw, grid_n=8, voxel=1.0)
+    res = orc.global_step(w, o, d, target, **kw)
+
+    def loss_fn(wf):
+        return orc.global_step(wf, o, d, target, occupancy=False, **kw)["loss"]
+    idx = rng.choice(w.size, 120, replace=False)
+    bad = _fd_check(loss_fn, w, idx, res["grad"])
+    assert not bad, bad[:5]
+    # occupancy: max of per-sample density over the samples in each voxel,
+    # recomputed one sample at a time and independent of visiting order
+    t, dl = orc.invdepth_t(ns, 0.1, 20.0)
+    occ = np.zeros((8, 8, 8))
+    order = rng.permutation(N * ns)
+    for q in order:
+        r, k = divmod(int(q), ns)
+        p = np.array([np.float32(np.float64(t[k]) * d[a, r] + o[a, r]) for a in range(3)], np.float32)
+        s1, _ = orc.global_mlp(w, (p * np.float32(0.25)).astype(np.float64), d[:, r].astype(np.float64),
+                               width=width, color_width=cw)
+        qv = (p.astype(np.float32) - np.float32(-4.0)) * np.float32(1.0)
+        if np.all((qv >= 0) & (qv < 8)):
+            i = np.floor(qv).astype(int)
+            occ[i[2], i[1], i[0]] = max(occ[i[2], i[1], i[0]], s1)
+    assert np.allclose(occ, res["occ_max"], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Adam (Sec. 6.3)
+# ---------------------------------------------------------------------------
+
+def test_adam_first_step_is_signed_lr(orc):
+    g = np.array([0.3, -2.0, 1e-3, 0.0])
+    w = np.ones(4); m = np.zeros(4); v = np.zeros(4)
+    orc.adam(w, g, m, v, 1, 1e-3)
+    assert np.allclose(w, 1 - 1e-3 * np.sign(g) * np.abs(g) / (np.abs(g) + 1e-8), atol=1e-15)
+    # second step with the same gradient keeps the same magnitude (bias correction)
+    orc.adam(w, g, m, v, 2, 1e-3)
+    assert np.allclose(w[:3], 1 - 2e-3 * np.sign(g[:3]), atol=1e-9)
