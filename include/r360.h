@@ -1,0 +1,226 @@
+/*
+ * r360.h -- C ABI of the MI355X (gfx950) hot path of 360Roam's
+ * geometry-aware radiance fields (arXiv 2208.02705).
+ *
+ * The path: equirect (or pinhole) ray generation (Sec. 3.2, Eq.2/Eq.3) ->
+ * sampling of the occupied voxels of an occupancy grid along each ray
+ * (Sec. 4.2, Sec. 5) -> routing of each sample to the local radiance field
+ * that owns its voxel (Sec. 5, Alg.1 Stage II labels) -> positional encoding
+ * plus that field's tiny MLP (Sec. 3.1 Eq.1, App. C) -> alpha compositing
+ * (Sec. 3.2, Eq.4/Eq.5); and its backward pass for fine-tuning with an L2
+ * photometric loss and Adam (Sec. 4.2, Sec. 6.3).
+ *
+ * Conventions
+ *  - Every pointer argument is a DEVICE pointer unless its name ends in
+ *    _host. Arrays are caller-owned; the library never frees or reallocates
+ *    them. Ray and per-ray arrays are structure-of-arrays: o and d are [3][N]
+ *    (all x, then all y, then all z); rgb is [3][N].
+ *  - `stream` is a hipStream_t passed as void*; every call only enqueues work
+ *    on it (asynchronous), except where a _host output forces a wait.
+ *  - Transient memory is a caller-supplied workspace of at least
+ *    r360_workspace_bytes() bytes, 256-byte aligned. A render leaves its sample
+ *    lists in the workspace; r360_backward() reads them, so the same
+ *    workspace must be passed unchanged between the two.
+ *  - The library owns only the opaque objects it creates (scene, equirect
+ *    tables); their destroy calls free them.
+ *  - Every entry point returns r360_status. Argument checks run before any
+ *    launch; a failed check launches nothing. Launch failures return
+ *    R360_EHIP and r360_last_error() gives the runtime's text. Nothing aborts
+ *    across this boundary.
+ *  - Sizes: N * max_samples must stay below 2^31 per call (split larger ray
+ *    sets into chunks); max_samples is in [1, 256]; n_fields in [1, 32767].
+ *  - Calls that share a workspace or a scene must not overlap on different
+ *    streams.
+ */
+#ifndef R360_H
+#define R360_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    R360_OK = 0,
+    R360_EINVAL = -1,        /* bad argument (null pointer, size out of range, misaligned) */
+    R360_ENOMEM = -2,        /* device allocation failed (scene / table creation only) */
+    R360_EHIP = -3,          /* a HIP runtime call or launch failed */
+    R360_EUNSUPPORTED = -4,  /* valid but unsupported configuration (e.g. encoding length) */
+    R360_EWORKSPACE = -5     /* workspace smaller than r360_workspace_bytes() */
+} r360_status;
+
+typedef enum {
+    R360_FP32 = 0,           /* MLP layers on FP32 MFMA (v_mfma_f32_16x16x4f32) */
+    R360_BF16 = 1,           /* MLP layers on BF16 MFMA, FP32 accumulation */
+    R360_FP16 = 2,           /* MLP layers on FP16 MFMA, FP32 accumulation */
+    R360_FP64_GRADCHECK = 3  /* scalar FP64 kernels; only r360_gradcheck_* accept it */
+} r360_precision;
+
+/* Occupancy grid: n[0] x n[1] x n[2] voxels of edge `voxel` (a power of two)
+ * from corner lo; voxel (i, j, k) is element i + n0 (j + n1 k) (x fastest).
+ * A voxel is occupied where its probability is strictly larger than
+ * `threshold` (Sec. 4.1: "larger than the threshold"). */
+typedef struct {
+    int32_t n[3];
+    float lo[3];
+    float voxel;
+    float threshold;
+} r360_grid_desc;
+
+/* Local fields (App. C tiny network, widened per the config): per field
+ * h1 = relu(W1 g(x) + b1); h2 = relu(W2 h1 + b2); sigma = softplus(ws h2 + bs);
+ * f = Wf h2 + bf; h3 = relu(W3 [f ; g(d)] + b3); rgb = sigmoid(W4 h3 + b4),
+ * with g the positional encoding of Sec. 3.1 (identity term included, 3 + 6L
+ * wide). The encoding input is xhat = (p - center) * (1 / half_extent).
+ * Supported: hidden in {32, 64}, L_xyz = 10, L_dir = 4. */
+typedef struct {
+    int32_t n_fields;
+    int32_t hidden;
+    int32_t L_xyz;
+    int32_t L_dir;
+    float center[3];
+    float half_extent;
+} r360_mlp_desc;
+
+/* Per-call options. Samples lie in [near, far] along unit-length d;
+ * far may be +inf. At most max_samples occupied-voxel samples per ray,
+ * nearest first. `precision` is an r360_precision. */
+typedef struct {
+    float near_;
+    float far_;
+    int32_t max_samples;
+    int32_t precision;
+} r360_render_opts;
+
+typedef struct r360_scene r360_scene;
+typedef struct r360_equirect r360_equirect;
+
+/* Number of FP32 parameters of one local field in canonical order:
+ * W1[h x 63], b1[h], W2[h x h], b2[h], ws[1 x h], bs[1], Wf[h x h], bf[h],
+ * W3[h x (h + 27)], b3[h], W4[3 x h], b4[3]  (matrices row-major [out x in],
+ * W3's input order [f ; g(d)]). 6212 for h = 32 (App. C), 18564 for h = 64. */
+int64_t r360_field_params(int32_t hidden, int32_t L_xyz, int32_t L_dir);
+
+/* Create a scene on the current device: takes the occupancy decision and the
+ * voxel -> field labels (Sec. 5: each occupied voxel is labelled with its
+ * tiny MLP) from occ_prob [n2][n1][n0] and field_map (same layout, -1 = none)
+ * into a library-owned label grid, and packs `weights` ([n_fields][P] FP32,
+ * canonical order, device) into the per-precision MFMA fragment layouts.
+ * The inputs are read during the call (on `stream`) and may be freed after
+ * the stream has passed this point. Errors: EINVAL, EUNSUPPORTED, ENOMEM, EHIP. */
+r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob, const int32_t* field_map,
+                              const r360_mlp_desc* mlp, const float* weights, void* stream, r360_scene** out);
+
+/* Re-pack new FP32 canonical weights (e.g. after an optimizer step). */
+r360_status r360_scene_set_weights(r360_scene* scene, const float* weights, void* stream);
+
+/* Replace the occupancy decision and labels (same grid shape). */
+r360_status r360_scene_set_grid(r360_scene* scene, const float* occ_prob, const int32_t* field_map, void* stream);
+
+void r360_scene_destroy(r360_scene* scene);
+
+/* Per-resolution sine/cosine tables for equirect rays (Eq.2 inverted at
+ * pixel centres, Eq.3): phi = pi a_phi with a_phi = ((2u+1) - W)/W and
+ * theta = pi a_theta with a_theta = (H - (2v+1))/(2H), each a correctly
+ * rounded FP32 quotient; sin/cos are evaluated in FP64 on the host and
+ * rounded once to FP32, then uploaded (synchronous). */
+r360_status r360_equirect_create(int32_t W, int32_t H, r360_equirect** out);
+void r360_equirect_destroy(r360_equirect* eq);
+/* Copy the tables to host arrays (W, W, H, H floats) for inspection. */
+r360_status r360_equirect_tables(const r360_equirect* eq, float* sin_phi_host, float* cos_phi_host,
+                                 float* sin_theta_host, float* cos_theta_host);
+
+/* Ray directions for pixels of an equirect camera (Eq.3, camera frame
+ * x right, y down, z forward), rotated by the 3x4 row-major camera-to-world
+ * c2w_host (d = R d_cam as fma(R2, z, fma(R1, y, R0 x))); o = c2w translation.
+ * pix: N linear pixel indices v * W + u (int64), or NULL for all W*H pixels
+ * in raster order (then N must equal W*H). Outputs o, d: [3][N]. */
+r360_status r360_equirect_rays(const r360_equirect* eq, const float c2w_host[12], const int64_t* pix, int64_t N,
+                               float* o, float* d, void* stream);
+
+/* Workspace bytes for r360_render_* / r360_sample_rays / r360_backward over
+ * N rays with the given max_samples (the capacity is N * max_samples). */
+size_t r360_workspace_bytes(const r360_scene* scene, int64_t n_rays, int32_t max_samples);
+
+/* Occupied-voxel sampling only (Sec. 4.2 dense sampling of occupied voxels,
+ * Sec. 5 ray casting): per ray, traverse the voxels between
+ * t0 = max(near, box entry) and t1 = min(far, box exit) in FP32 and emit one
+ * sample per occupied voxel segment of positive length: t_mid = (t_in +
+ * t_out) / 2, delta = t_out - t_in, nearest max_samples first. Outputs in
+ * ray-major order; caller arrays hold N * max_samples entries; voxel may be
+ * NULL. ray_offset [N+1] (int32) gets the exclusive prefix of per-ray counts.
+ * If n_samples_host is not NULL the call waits for the stream and stores the
+ * total there. */
+r360_status r360_sample_rays(const r360_scene* scene, const float* o, const float* d, int64_t N,
+                             const r360_render_opts* opts, int64_t* n_samples_host, float* t_mid, float* delta,
+                             int32_t* ray_id, int32_t* field_id, int32_t* voxel, int32_t* ray_offset,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Full render of N rays: sampling, routing by field, encoding + field MLP in
+ * opts->precision, compositing (Eq.4/Eq.5 with log-space FP32 transmittance,
+ * no background). Outputs rgb [3][N], depth [N] (sum of w t_mid, not
+ * normalised), opacity [N] (sum of w = 1 - T_final). */
+r360_status r360_render_rays(const r360_scene* scene, const float* o, const float* d, int64_t N,
+                             const r360_render_opts* opts, float* rgb, float* depth, float* opacity,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* Render a whole equirect view (W*H rays from the table's resolution) from
+ * camera c2w_host. Outputs [3][H][W], [H][W], [H][W]. */
+r360_status r360_render_equirect(const r360_scene* scene, const r360_equirect* eq, const float c2w_host[12],
+                                 const r360_render_opts* opts, float* rgb, float* depth, float* opacity,
+                                 void* ws, size_t ws_bytes, void* stream);
+
+/* Render a pinhole viewport: d_cam = (x, y, 1)/|.| with x = ((u + 1/2) - W/2)/fx,
+ * y = ((v + 1/2) - H/2)/fy (correctly rounded sqrt of fma(x,x,fma(y,y,1))). */
+r360_status r360_render_pinhole(const r360_scene* scene, int32_t W, int32_t H, float fx, float fy,
+                                const float c2w_host[12], const r360_render_opts* opts, float* rgb, float* depth,
+                                float* opacity, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward of the most recent r360_render_rays on this workspace (same
+ * scene, rays and opts): from dL/dC (grad_rgb [3][N]) recompute per-ray
+ * transmittance and partial colours (nothing per-sample is kept from the
+ * compositing forward), then dL/dsigma_i = delta_i [T_{i+1} (c_i . g) -
+ * ((C - C_{<=i}) . g)] and dL/dc_i = w_i g, then the field MLPs' backward in
+ * opts->precision with FP32 accumulation. grad_weights [n_fields][P] (FP32,
+ * canonical order) is overwritten. */
+r360_status r360_backward(const r360_scene* scene, const float* o, const float* d, int64_t N,
+                          const r360_render_opts* opts, const float* grad_rgb, float* grad_weights,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* One fine-tuning step (Sec. 4.2, L2 photometric loss): render the N rays,
+ * loss = 1/(3N) sum (C - C*)^2 into loss[0] (device), its gradient w.r.t. all
+ * field weights into grad_weights (overwritten); rgb_out [3][N] may be NULL. */
+r360_status r360_train_step(const r360_scene* scene, const float* o, const float* d, int64_t N,
+                            const float* target_rgb, const r360_render_opts* opts, float* loss,
+                            float* grad_weights, float* rgb_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Adam (Sec. 6.3: beta1 0.9, beta2 0.99): m = b1 m + (1-b1) g;
+ * v = b2 v + (1-b2) g^2; w -= lr (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps).
+ * FP32 master weights, in place. step >= 1. */
+r360_status r360_adam_step(float* w, const float* g, float* m, float* v, int64_t n, int64_t step, float lr,
+                           float beta1, float beta2, float eps, void* stream);
+
+/* FP64 gradient-check forms (FP64 only here): the same sampling, then scalar
+ * FP64 encoding, field MLP and compositing over FP64 canonical weights
+ * weights64 [n_fields][P]. Forward writes rgb64 [3][N]; backward takes
+ * grad_rgb64 [3][N] and overwrites grad64 [n_fields][P]. The forward leaves
+ * its samples in ws for the backward, as r360_render_rays does. */
+r360_status r360_gradcheck_forward(const r360_scene* scene, const double* weights64, const float* o,
+                                   const float* d, int64_t N, const r360_render_opts* opts, double* rgb64,
+                                   void* ws, size_t ws_bytes, void* stream);
+r360_status r360_gradcheck_backward(const r360_scene* scene, const double* weights64, const float* o,
+                                    const float* d, int64_t N, const r360_render_opts* opts,
+                                    const double* grad_rgb64, double* grad64, void* ws, size_t ws_bytes,
+                                    void* stream);
+
+/* Status text; for R360_EHIP also the runtime's last error text. */
+const char* r360_status_string(int32_t status);
+const char* r360_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* R360_H */

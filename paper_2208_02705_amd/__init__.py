@@ -1,0 +1,13 @@
+"""MI355X (gfx950) hot path of 360Roam's geometry-aware radiance fields.
+
+Equirect/pinhole ray generation -> occupied-voxel sampling -> routing by
+field -> positional encoding + per-field MLP (MFMA) -> alpha compositing,
+plus the backward pass for fine-tuning; every step is a HIP kernel in
+libr360.so behind the C ABI of include/r360.h. This package only marshals
+arguments (ctypes) and provides torch.autograd wrappers. The shared library
+is loaded on first use and its absence is an error.
+"""
+from ._lib import R360Error, FP32, BF16, FP16, FP64_GRADCHECK, LIB_PATH  # noqa: F401
+from .render import (Scene, Equirect, EquirectRenderer, RenderFunction, GradcheckFunction,  # noqa: F401
+                     sample_rays, render_rays, render_equirect, render_pinhole, backward, train_step, adam_step,
+                     field_params, lr_at)

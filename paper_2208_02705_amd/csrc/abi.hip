@@ -1,0 +1,496 @@
+// Host side of the C ABI (include/r360.h): argument checks, object
+// lifetimes, workspace carve-up and the launch sequences of the hot path.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <vector>
+
+#include "r360_internal.h"
+
+namespace r360 {
+size_t pack_bytes16(int H);
+size_t pack_bytes32(int H);
+size_t bias_floats(int H);
+int route_waves(int F);
+}
+
+using namespace r360;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+r360_status hip_fail(const char* where, hipError_t e) {
+    std::snprintf(g_err, sizeof(g_err), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+    return R360_EHIP;
+}
+r360_status inval(const char* what) {
+    std::snprintf(g_err, sizeof(g_err), "invalid argument: %s", what);
+    return R360_EINVAL;
+}
+#define R360_TRY(where, expr)                         \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(where, e_); \
+    } while (0)
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool pow2(float v) {
+    if (!(v > 0.0f) || !std::isfinite(v)) return false;
+    int e;
+    return std::frexp(v, &e) == 0.5f;
+}
+
+int64_t field_params(int h, int Lx, int Ld) {
+    const int64_t dx = 3 + 6 * Lx, dd = 3 + 6 * Ld;
+    return h * dx + h + (int64_t)h * h + h + h + 1 + (int64_t)h * h + h + h * (h + dd) + h + 3 * (int64_t)h + 3;
+}
+
+r360_status check_opts(const r360_render_opts* o, bool allow_fp64) {
+    if (!o) return inval("opts is NULL");
+    if (o->max_samples < 1 || o->max_samples > 256) return inval("max_samples outside [1, 256]");
+    if (std::isnan(o->near_) || std::isnan(o->far_)) return inval("near/far is NaN");
+    if (o->precision < R360_FP32 || o->precision > R360_FP64_GRADCHECK) return inval("unknown precision");
+    if (o->precision == R360_FP64_GRADCHECK && !allow_fp64) {
+        std::snprintf(g_err, sizeof(g_err), "FP64 is only accepted by the gradient-check entry points");
+        return R360_EUNSUPPORTED;
+    }
+    return R360_OK;
+}
+
+}  // namespace
+
+namespace r360 {
+
+Workspace carve(void* base, int64_t N, int64_t cap, int F, int64_t P) {
+    Workspace w{};
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* q = p ? p + off : nullptr;
+        off += al(bytes);
+        return q;
+    };
+    w.ray_off = (int32_t*)take((N + 1) * 4);
+    w.o = (float*)take(3 * N * 4);
+    w.d = (float*)take(3 * N * 4);
+    w.t_mid = (float*)take(cap * 4);
+    w.delta = (float*)take(cap * 4);
+    w.ray = (int32_t*)take(cap * 4);
+    w.field = (int32_t*)take(cap * 4);
+    w.perm = (int32_t*)take(cap * 4);
+    w.sigma = (float*)take(cap * 4);
+    w.rgb = (float*)take(3 * cap * 4);
+    w.dsigma = (float*)take(cap * 4);
+    w.drgb = (float*)take(3 * cap * 4);
+    w.scan = (int32_t*)take(((N + SCAN_TILE - 1) / SCAN_TILE + 1) * 4);
+    w.hist = (int32_t*)take((size_t)F * route_waves(F) * 4);
+    w.field_start = (int32_t*)take((F + 1) * 4);
+    w.dw_part = (float*)take((size_t)DW_SLOTS * P * 4);
+    w.misc = (int32_t*)take(256 * 4);
+    w.loss_part = (float*)take(((N + 255) / 256) * 4);
+    w.ray_rgb = (float*)take(3 * N * 4);
+    w.ray_grad = (float*)take(3 * N * 4);
+    w.N = N;
+    w.cap = cap;
+    w.bytes = off;
+    return w;
+}
+
+DdaParams dda_params(const r360_scene* s, const r360_render_opts* o) {
+    DdaParams p;
+    p.labels = s->labels;
+    p.n0 = s->grid.n[0]; p.n1 = s->grid.n[1]; p.n2 = s->grid.n[2];
+    p.lo0 = s->grid.lo[0]; p.lo1 = s->grid.lo[1]; p.lo2 = s->grid.lo[2];
+    p.voxel = s->grid.voxel;
+    p.inv_voxel = 1.0f / s->grid.voxel;
+    p.near_ = o->near_;
+    p.far_ = o->far_;
+    p.max_samples = o->max_samples;
+    return p;
+}
+
+}  // namespace r360
+
+namespace {
+
+// Validates the common render arguments and carves the workspace.
+r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts, void* ws, size_t ws_bytes,
+                    bool allow_fp64, Workspace* w) {
+    if (!s) return inval("scene is NULL");
+    r360_status st = check_opts(opts, allow_fp64);
+    if (st != R360_OK) return st;
+    if (N <= 0) return inval("N must be positive");
+    const int64_t cap = N * (int64_t)opts->max_samples;
+    if (cap >= (int64_t(1) << 31)) return inval("N * max_samples must stay below 2^31; split the rays");
+    if (!ws) return inval("workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    *w = carve(ws, N, cap, s->mlp.n_fields, s->P);
+    if (ws_bytes < w->bytes) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, w->bytes);
+        return R360_EWORKSPACE;
+    }
+    return R360_OK;
+}
+
+r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
+                          float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st) {
+    w.ro = src.mode == RAYS_GIVEN ? src.o : w.o;
+    w.rd = src.mode == RAYS_GIVEN ? src.d : w.d;
+    const DdaParams p = dda_params(s, opts);
+    R360_TRY("sample", launch_sample(src, p, N, w, nullptr, st));
+    R360_TRY("route", launch_route(w, s->mlp.n_fields, st));
+    R360_TRY("mlp forward", launch_mlp_forward(s, w, opts->precision, st));
+    R360_TRY("composite", launch_composite(w, N, rgb, depth, opacity, st));
+    return R360_OK;
+}
+
+bool valid_c2w(const float* c) {
+    if (!c) return false;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(c[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t r360_field_params(int32_t hidden, int32_t L_xyz, int32_t L_dir) {
+    if (hidden <= 0 || L_xyz < 0 || L_dir < 0) return -1;
+    return field_params(hidden, L_xyz, L_dir);
+}
+
+r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob, const int32_t* field_map,
+                              const r360_mlp_desc* mlp, const float* weights, void* stream, r360_scene** out) {
+    if (!out) return inval("out is NULL");
+    *out = nullptr;
+    if (!grid || !mlp || !occ_prob || !field_map || !weights) return inval("NULL pointer");
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 1 || grid->n[a] > 4096) return inval("grid size outside [1, 4096]");
+        if (!std::isfinite(grid->lo[a])) return inval("grid corner not finite");
+    }
+    if (!pow2(grid->voxel)) return inval("voxel edge must be a positive power of two");
+    if (std::isnan(grid->threshold)) return inval("threshold is NaN");
+    if (mlp->n_fields < 1 || mlp->n_fields > 16384) return inval("n_fields outside [1, 16384]");
+    if (!(mlp->half_extent > 0.0f) || !std::isfinite(mlp->half_extent)) return inval("half_extent must be positive");
+    if (mlp->hidden != 32 && mlp->hidden != 64) {
+        std::snprintf(g_err, sizeof(g_err), "hidden width %d unsupported (32 or 64)", mlp->hidden);
+        return R360_EUNSUPPORTED;
+    }
+    if (mlp->L_xyz != LXYZ || mlp->L_dir != LDIR) {
+        std::snprintf(g_err, sizeof(g_err), "encoding lengths must be L_xyz = 10, L_dir = 4");
+        return R360_EUNSUPPORTED;
+    }
+    const int64_t nvox = (int64_t)grid->n[0] * grid->n[1] * grid->n[2];
+    r360_scene* s = new (std::nothrow) r360_scene();
+    if (!s) return R360_ENOMEM;
+    s->grid = *grid;
+    s->mlp = *mlp;
+    s->P = field_params(mlp->hidden, mlp->L_xyz, mlp->L_dir);
+    (void)hipGetDevice(&s->device);
+    const int F = mlp->n_fields, H = mlp->hidden;
+    bool ok = hipMalloc((void**)&s->labels, nvox * sizeof(int16_t)) == hipSuccess;
+    ok = ok && hipMalloc(&s->pack16_bf, F * pack_bytes16(H)) == hipSuccess;
+    ok = ok && hipMalloc(&s->pack16_h, F * pack_bytes16(H)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->pack32, F * pack_bytes32(H)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->bias, F * bias_floats(H) * sizeof(float)) == hipSuccess;
+    if (!ok) {
+        r360_scene_destroy(s);
+        return R360_ENOMEM;
+    }
+    hipError_t e = launch_labels(occ_prob, field_map, grid->threshold, nvox, F, s->labels, S(stream));
+    if (e == hipErrorInvalidValue) {
+        r360_scene_destroy(s);
+        return inval("field_map holds ids outside [-1, n_fields)");
+    }
+    if (e == hipSuccess) e = launch_repack(s, weights, S(stream));
+    if (e != hipSuccess) {
+        r360_scene_destroy(s);
+        return hip_fail("scene_create", e);
+    }
+    *out = s;
+    return R360_OK;
+}
+
+r360_status r360_scene_set_weights(r360_scene* s, const float* weights, void* stream) {
+    if (!s || !weights) return inval("NULL pointer");
+    R360_TRY("repack", launch_repack(s, weights, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_scene_set_grid(r360_scene* s, const float* occ_prob, const int32_t* field_map, void* stream) {
+    if (!s || !occ_prob || !field_map) return inval("NULL pointer");
+    const int64_t nvox = (int64_t)s->grid.n[0] * s->grid.n[1] * s->grid.n[2];
+    hipError_t e = launch_labels(occ_prob, field_map, s->grid.threshold, nvox, s->mlp.n_fields, s->labels, S(stream));
+    if (e == hipErrorInvalidValue) return inval("field_map holds ids outside [-1, n_fields)");
+    if (e != hipSuccess) return hip_fail("set_grid", e);
+    return R360_OK;
+}
+
+void r360_scene_destroy(r360_scene* s) {
+    if (!s) return;
+    (void)hipFree(s->labels);
+    (void)hipFree(s->pack16_bf);
+    (void)hipFree(s->pack16_h);
+    (void)hipFree(s->pack32);
+    (void)hipFree(s->bias);
+    delete s;
+}
+
+r360_status r360_equirect_create(int32_t W, int32_t H, r360_equirect** out) {
+    if (!out) return inval("out is NULL");
+    *out = nullptr;
+    if (W < 1 || H < 1 || W > (1 << 16) || H > (1 << 16)) return inval("W, H outside [1, 65536]");
+    // Eq.2 inverted at pixel centres; sin/cos in FP64 with the argument
+    // folded to |m| <= 1/2 first (m = a or 1 - a etc., exact), rounded once.
+    auto sinpi = [](double a) {
+        double m = std::fmod(a, 2.0);
+        if (m > 1.0) m -= 2.0;
+        if (m < -1.0) m += 2.0;
+        if (m > 0.5) m = 1.0 - m;
+        else if (m < -0.5) m = -1.0 - m;
+        return std::sin(3.14159265358979323846 * m);
+    };
+    std::vector<float> t(2 * (size_t)W + 2 * (size_t)H);
+    for (int u = 0; u < W; ++u) {
+        const float a = (float)((2 * u + 1) - W) / (float)W;
+        t[u] = (float)sinpi((double)a);
+        t[W + u] = (float)sinpi((double)a + 0.5);
+    }
+    for (int v = 0; v < H; ++v) {
+        const float a = (float)(H - (2 * v + 1)) / (float)(2 * H);
+        t[2 * W + v] = (float)sinpi((double)a);
+        t[2 * W + H + v] = (float)sinpi((double)a + 0.5);
+    }
+    r360_equirect* eq = new (std::nothrow) r360_equirect();
+    if (!eq) return R360_ENOMEM;
+    eq->W = W;
+    eq->H = H;
+    if (hipMalloc((void**)&eq->tables, t.size() * sizeof(float)) != hipSuccess) {
+        delete eq;
+        return R360_ENOMEM;
+    }
+    hipError_t e = hipMemcpy(eq->tables, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        r360_equirect_destroy(eq);
+        return hip_fail("equirect_create", e);
+    }
+    *out = eq;
+    return R360_OK;
+}
+
+void r360_equirect_destroy(r360_equirect* eq) {
+    if (!eq) return;
+    (void)hipFree(eq->tables);
+    delete eq;
+}
+
+r360_status r360_equirect_tables(const r360_equirect* eq, float* sp, float* cp, float* st, float* ct) {
+    if (!eq || !sp || !cp || !st || !ct) return inval("NULL pointer");
+    const int W = eq->W, H = eq->H;
+    R360_TRY("tables", hipMemcpy(sp, eq->tables, W * sizeof(float), hipMemcpyDeviceToHost));
+    R360_TRY("tables", hipMemcpy(cp, eq->tables + W, W * sizeof(float), hipMemcpyDeviceToHost));
+    R360_TRY("tables", hipMemcpy(st, eq->tables + 2 * W, H * sizeof(float), hipMemcpyDeviceToHost));
+    R360_TRY("tables", hipMemcpy(ct, eq->tables + 2 * W + H, H * sizeof(float), hipMemcpyDeviceToHost));
+    return R360_OK;
+}
+
+r360_status r360_equirect_rays(const r360_equirect* eq, const float c2w_host[12], const int64_t* pix, int64_t N,
+                               float* o, float* d, void* stream) {
+    if (!eq || !o || !d) return inval("NULL pointer");
+    if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
+    if (N <= 0) return inval("N must be positive");
+    if (!pix && N != (int64_t)eq->W * eq->H) return inval("without a pixel list N must be W*H");
+    RaySource src{};
+    src.mode = RAYS_EQUIRECT;
+    src.tables = eq->tables;
+    src.W = eq->W;
+    src.H = eq->H;
+    std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    src.pix = pix;
+    R360_TRY("equirect_rays", launch_rays(src, N, o, d, S(stream)));
+    return R360_OK;
+}
+
+size_t r360_workspace_bytes(const r360_scene* s, int64_t n_rays, int32_t max_samples) {
+    if (!s || n_rays <= 0 || max_samples < 1) return 0;
+    return carve(nullptr, n_rays, n_rays * (int64_t)max_samples, s->mlp.n_fields, s->P).bytes;
+}
+
+r360_status r360_sample_rays(const r360_scene* s, const float* o, const float* d, int64_t N,
+                             const r360_render_opts* opts, int64_t* n_samples_host, float* t_mid, float* delta,
+                             int32_t* ray_id, int32_t* field_id, int32_t* voxel, int32_t* ray_offset, void* ws,
+                             size_t ws_bytes, void* stream) {
+    if (!o || !d || !t_mid || !delta || !ray_id || !field_id || !ray_offset) return inval("NULL pointer");
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    w.ray_off = ray_offset;
+    w.t_mid = t_mid;
+    w.delta = delta;
+    w.ray = ray_id;
+    w.field = field_id;
+    RaySource src{};
+    src.mode = RAYS_GIVEN;
+    src.o = o;
+    src.d = d;
+    R360_TRY("sample", launch_sample(src, dda_params(s, opts), N, w, voxel, S(stream)));
+    if (n_samples_host) {
+        int32_t tot = 0;
+        R360_TRY("sample total", hipMemcpyAsync(&tot, ray_offset + N, sizeof(int32_t), hipMemcpyDeviceToHost, S(stream)));
+        R360_TRY("sample sync", hipStreamSynchronize(S(stream)));
+        *n_samples_host = tot;
+    }
+    return R360_OK;
+}
+
+r360_status r360_render_rays(const r360_scene* s, const float* o, const float* d, int64_t N,
+                             const r360_render_opts* opts, float* rgb, float* depth, float* opacity, void* ws,
+                             size_t ws_bytes, void* stream) {
+    if (!o || !d || !rgb || !depth || !opacity) return inval("NULL pointer");
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    RaySource src{};
+    src.mode = RAYS_GIVEN;
+    src.o = o;
+    src.d = d;
+    return render_common(s, src, N, opts, rgb, depth, opacity, w, S(stream));
+}
+
+r360_status r360_render_equirect(const r360_scene* s, const r360_equirect* eq, const float c2w_host[12],
+                                 const r360_render_opts* opts, float* rgb, float* depth, float* opacity, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    if (!eq || !rgb || !depth || !opacity) return inval("NULL pointer");
+    if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
+    const int64_t N = (int64_t)eq->W * eq->H;
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    RaySource src{};
+    src.mode = RAYS_EQUIRECT;
+    src.tables = eq->tables;
+    src.W = eq->W;
+    src.H = eq->H;
+    std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    return render_common(s, src, N, opts, rgb, depth, opacity, w, S(stream));
+}
+
+r360_status r360_render_pinhole(const r360_scene* s, int32_t W, int32_t H, float fx, float fy,
+                                const float c2w_host[12], const r360_render_opts* opts, float* rgb, float* depth,
+                                float* opacity, void* ws, size_t ws_bytes, void* stream) {
+    if (!rgb || !depth || !opacity) return inval("NULL pointer");
+    if (W < 1 || H < 1) return inval("W, H must be positive");
+    if (!(fx > 0.0f) || !(fy > 0.0f) || !std::isfinite(fx) || !std::isfinite(fy)) return inval("focal length");
+    if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
+    const int64_t N = (int64_t)W * H;
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    RaySource src{};
+    src.mode = RAYS_PINHOLE;
+    src.W = W;
+    src.H = H;
+    src.fx = fx;
+    src.fy = fy;
+    std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    return render_common(s, src, N, opts, rgb, depth, opacity, w, S(stream));
+}
+
+r360_status r360_backward(const r360_scene* s, const float* o, const float* d, int64_t N,
+                          const r360_render_opts* opts, const float* grad_rgb, float* grad_weights, void* ws,
+                          size_t ws_bytes, void* stream) {
+    if (!o || !d || !grad_rgb || !grad_weights) return inval("NULL pointer");
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    w.ro = o;
+    w.rd = d;
+    R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
+    R360_TRY("mlp backward", launch_mlp_backward(s, w, opts->precision, grad_weights, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_train_step(const r360_scene* s, const float* o, const float* d, int64_t N, const float* target,
+                            const r360_render_opts* opts, float* loss, float* grad_weights, float* rgb_out, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (!o || !d || !target || !loss || !grad_weights) return inval("NULL pointer");
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    float* rgb = rgb_out ? rgb_out : w.ray_rgb;
+    float* grad_rgb = w.ray_grad;
+    RaySource src{};
+    src.mode = RAYS_GIVEN;
+    src.o = o;
+    src.d = d;
+    st = render_common(s, src, N, opts, rgb, nullptr, nullptr, w, S(stream));
+    if (st != R360_OK) return st;
+    R360_TRY("loss", launch_loss_grad(w, N, rgb, target, loss, grad_rgb, S(stream)));
+    R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
+    R360_TRY("mlp backward", launch_mlp_backward(s, w, opts->precision, grad_weights, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_adam_step(float* w, const float* g, float* m, float* v, int64_t n, int64_t step, float lr,
+                           float b1, float b2, float eps, void* stream) {
+    if (!w || !g || !m || !v) return inval("NULL pointer");
+    if (n <= 0 || step < 1) return inval("n must be positive and step >= 1");
+    if (!(b1 >= 0.0f && b1 < 1.0f) || !(b2 >= 0.0f && b2 < 1.0f) || !(eps > 0.0f) || !std::isfinite(lr))
+        return inval("Adam hyper-parameters");
+    R360_TRY("adam", launch_adam(w, g, m, v, n, step, lr, b1, b2, eps, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_gradcheck_forward(const r360_scene* s, const double* w64, const float* o, const float* d, int64_t N,
+                                   const r360_render_opts* opts, double* rgb64, void* ws, size_t ws_bytes,
+                                   void* stream) {
+    if (!w64 || !o || !d || !rgb64) return inval("NULL pointer");
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, true, &w);
+    if (st != R360_OK) return st;
+    if (opts->precision != R360_FP64_GRADCHECK) return inval("precision must be R360_FP64_GRADCHECK");
+    w.ro = o;
+    w.rd = d;
+    RaySource src{};
+    src.mode = RAYS_GIVEN;
+    src.o = o;
+    src.d = d;
+    R360_TRY("sample", launch_sample(src, dda_params(s, opts), N, w, nullptr, S(stream)));
+    R360_TRY("gradcheck forward", launch_gradcheck_forward(s, w, w64, N, rgb64, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_gradcheck_backward(const r360_scene* s, const double* w64, const float* o, const float* d, int64_t N,
+                                    const r360_render_opts* opts, const double* grad_rgb64, double* grad64, void* ws,
+                                    size_t ws_bytes, void* stream) {
+    if (!w64 || !o || !d || !grad_rgb64 || !grad64) return inval("NULL pointer");
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, true, &w);
+    if (st != R360_OK) return st;
+    if (opts->precision != R360_FP64_GRADCHECK) return inval("precision must be R360_FP64_GRADCHECK");
+    w.ro = o;
+    w.rd = d;
+    R360_TRY("gradcheck backward", launch_gradcheck_backward(s, w, w64, N, grad_rgb64, grad64, S(stream)));
+    return R360_OK;
+}
+
+const char* r360_status_string(int32_t status) {
+    switch (status) {
+    case R360_OK: return "ok";
+    case R360_EINVAL: return "invalid argument";
+    case R360_ENOMEM: return "out of device memory";
+    case R360_EHIP: return "HIP runtime error";
+    case R360_EUNSUPPORTED: return "unsupported configuration";
+    case R360_EWORKSPACE: return "workspace too small";
+    default: return "unknown status";
+    }
+}
+
+const char* r360_last_error(void) { return g_err; }
+
+}  // extern "C"

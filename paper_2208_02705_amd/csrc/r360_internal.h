@@ -1,0 +1,277 @@
+// Internal declarations shared by the HIP translation units of libr360.
+// Device helpers (MFMA fragment types, the exact-argument sin/cos of pi x,
+// encoding slot tables) and the host-side launcher prototypes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "r360.h"
+
+namespace r360 {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+constexpr int WAVE = 64;
+constexpr int LXYZ = 10;                 // position encoding frequencies
+constexpr int LDIR = 4;                  // direction encoding frequencies
+constexpr int DXYZ = 3 + 6 * LXYZ;       // 63
+constexpr int DDIR = 3 + 6 * LDIR;       // 27
+
+// ---------------------------------------------------------------------------
+// Canonical parameter offsets of one local field (hidden width h):
+// W1[h x 63] b1 W2[h x h] b2 ws[1 x h] bs Wf[h x h] bf W3[h x (h+27)] b3 W4[3 x h] b4
+// ---------------------------------------------------------------------------
+struct FieldLayout {
+    int h;
+    __host__ __device__ constexpr int W1() const { return 0; }
+    __host__ __device__ constexpr int b1() const { return h * DXYZ; }
+    __host__ __device__ constexpr int W2() const { return b1() + h; }
+    __host__ __device__ constexpr int b2() const { return W2() + h * h; }
+    __host__ __device__ constexpr int ws() const { return b2() + h; }
+    __host__ __device__ constexpr int bs() const { return ws() + h; }
+    __host__ __device__ constexpr int Wf() const { return bs() + 1; }
+    __host__ __device__ constexpr int bf() const { return Wf() + h * h; }
+    __host__ __device__ constexpr int W3() const { return bf() + h; }
+    __host__ __device__ constexpr int b3() const { return W3() + h * (h + DDIR); }
+    __host__ __device__ constexpr int W4() const { return b3() + h; }
+    __host__ __device__ constexpr int b4() const { return W4() + 3 * h; }
+    __host__ __device__ constexpr int P() const { return b4() + 3; }
+};
+
+// ---------------------------------------------------------------------------
+// Encoding slots. Each lane group g (lanes 16g..16g+15 of a wave) evaluates
+// 16 position-encoding values and 8 direction-encoding values of its sample
+// with one uniform instruction stream; these tables say which canonical
+// encoding feature each (g, slot) holds. Canonical feature index:
+// 0..2 raw components, 3 + 6l + c = sin(2^l pi x_c), 6 + 6l + c = cos(...).
+// SLOT_BIAS carries a constant 1 (the layer bias); SLOT_ZERO is padding.
+// ---------------------------------------------------------------------------
+constexpr int SLOT_BIAS = -1;
+constexpr int SLOT_ZERO = -2;
+
+__host__ __device__ constexpr int pe_slot_feature(int g, int s) {
+    // g < 3: component g, frequency m = s/2 (sin even, cos odd), m = 0..7.
+    // g = 3: frequencies 8 and 9 of x, y, z plus the raw components and the bias.
+    return g < 3 ? ((s & 1) ? 6 + 6 * (s >> 1) + g : 3 + 6 * (s >> 1) + g)
+                 : (s == 0 ? 51 : s == 1 ? 54 : s == 2 ? 57 : s == 3 ? 60 : s == 4 ? 0 : s == 5 ? 1 :
+                    s == 6 ? 52 : s == 7 ? 55 : s == 8 ? 58 : s == 9 ? 61 : s == 10 ? 2 : s == 11 ? SLOT_BIAS :
+                    s == 12 ? 53 : s == 13 ? 56 : s == 14 ? 59 : 62);
+}
+__host__ __device__ constexpr int dir_slot_feature(int g, int s) {
+    return g < 3 ? ((s & 1) ? 6 + 6 * (s >> 1) + g : 3 + 6 * (s >> 1) + g)
+                 : (s < 3 ? s : s == 3 ? SLOT_BIAS : SLOT_ZERO);
+}
+
+// ---------------------------------------------------------------------------
+// sin(pi x) and cos(pi x) for an exactly known FP32 argument x.
+// x = n/2 + f with n = rint(2x) and |f| <= 1/4 (the subtraction is exact);
+// then truncated Taylor series of sin(pi f)/f and cos(pi f), whose first
+// omitted terms are below 2e-9 on |f| <= 1/4, and the quadrant n mod 4.
+// ---------------------------------------------------------------------------
+constexpr double PI_D = 3.14159265358979323846;
+constexpr double pw(double x, int k) { return k == 0 ? 1.0 : x * pw(x, k - 1); }
+constexpr double fact(int k) { return k <= 1 ? 1.0 : k * fact(k - 1); }
+constexpr float TS(int k) { return (float)(((k / 2) % 2 ? -1.0 : 1.0) * pw(PI_D, k) / fact(k)); }
+
+__device__ __forceinline__ void sincospi(float x, float& s, float& c) {
+    const float n = __builtin_rintf(x + x);
+    const float f = __builtin_fmaf(n, -0.5f, x);
+    const float f2 = f * f;
+    float ps = __builtin_fmaf(f2, TS(9), TS(7));
+    ps = __builtin_fmaf(f2, ps, TS(5));
+    ps = __builtin_fmaf(f2, ps, TS(3));
+    ps = __builtin_fmaf(f2, ps, TS(1));
+    ps = ps * f;
+    float pc = __builtin_fmaf(f2, TS(10), TS(8));
+    pc = __builtin_fmaf(f2, pc, TS(6));
+    pc = __builtin_fmaf(f2, pc, TS(4));
+    pc = __builtin_fmaf(f2, pc, TS(2));
+    pc = __builtin_fmaf(f2, pc, 1.0f);
+    const int q = (int)n & 3;
+    float sv = (q & 1) ? pc : ps;
+    float cv = (q & 1) ? ps : pc;
+    s = (q & 2) ? -sv : sv;
+    c = ((q + 1) & 2) ? -cv : cv;
+}
+
+// Angle doubling: (sin 2a, cos 2a) from (sin a, cos a).
+__device__ __forceinline__ void dbl(float s, float c, float& s2, float& c2) {
+    s2 = 2.0f * s * c;
+    c2 = (c - s) * (c + s);
+}
+
+// Position encoding values of lane group g in slot order (16 values).
+__device__ __forceinline__ void pe_position(int g, const float xh[3], float v[16]) {
+    const bool g3 = (g == 3);
+    const int cA = g3 ? 0 : g, cB = g3 ? 1 : g, cC = g3 ? 2 : g;
+    const float xA = cA == 0 ? xh[0] : cA == 1 ? xh[1] : xh[2];
+    const float xB = cB == 0 ? xh[0] : cB == 1 ? xh[1] : xh[2];
+    const float xC = cC == 0 ? xh[0] : cC == 1 ? xh[1] : xh[2];
+    float s, c;
+    sincospi(__builtin_ldexpf(xA, g3 ? 8 : 0), s, c);
+    v[0] = s; v[1] = c;
+    dbl(s, c, v[2], v[3]);
+    dbl(v[2], v[3], v[4], v[5]);
+    sincospi(__builtin_ldexpf(xB, g3 ? 8 : 3), s, c);
+    v[6] = s; v[7] = c;
+    dbl(s, c, v[8], v[9]);
+    dbl(v[8], v[9], v[10], v[11]);
+    sincospi(__builtin_ldexpf(xC, g3 ? 8 : 6), s, c);
+    v[12] = s; v[13] = c;
+    dbl(s, c, v[14], v[15]);
+    if (g3) { v[4] = xh[0]; v[5] = xh[1]; v[10] = xh[2]; v[11] = 1.0f; }
+}
+
+// Direction encoding values of lane group g in slot order (8 values).
+__device__ __forceinline__ void pe_direction(int g, const float d[3], float v[8]) {
+    const bool g3 = (g == 3);
+    const float x = g3 ? d[0] : (g == 0 ? d[0] : g == 1 ? d[1] : d[2]);
+    float s, c;
+    sincospi(x, s, c);
+    v[0] = s; v[1] = c;
+    dbl(v[0], v[1], v[2], v[3]);
+    dbl(v[2], v[3], v[4], v[5]);
+    dbl(v[4], v[5], v[6], v[7]);
+    if (g3) { v[0] = d[0]; v[1] = d[1]; v[2] = d[2]; v[3] = 1.0f; v[4] = v[5] = v[6] = v[7] = 0.0f; }
+}
+
+// ---------------------------------------------------------------------------
+// Packed weights. For each layer the A operand of every MFMA is stored in
+// the exact per-lane order the instruction consumes (see mlp.hip for the
+// index maps). Layers in order: L1 (encoding -> h), L2 (h -> h), HEAD
+// (h -> [f ; sigma], h + 16 rows), L3 ([f ; dir] -> h), L4 (h -> rgb, 16 rows).
+// ---------------------------------------------------------------------------
+template <int H>
+struct PackGeom {
+    static constexpr int NT = H / 16;                 // 16-row output tiles of a hidden layer
+    // 16-bit (K = 32 per MFMA)
+    static constexpr int KH16 = H / 32;               // k-steps over a hidden input
+    static constexpr int F_L1 = NT * 2;
+    static constexpr int F_L2 = NT * KH16;
+    static constexpr int F_HD = (NT + 1) * KH16;
+    static constexpr int F_L3 = NT * (KH16 + 1);
+    static constexpr int F_L4 = KH16;
+    static constexpr int FRAGS16 = F_L1 + F_L2 + F_HD + F_L3 + F_L4;
+    static constexpr int BYTES16 = FRAGS16 * WAVE * 16;
+    // FP32 (K = 4 per MFMA), stored as float4 groups of 4 consecutive k-steps
+    static constexpr int KH32 = H / 4;
+    static constexpr int S_L1 = NT * 16;
+    static constexpr int S_L2 = NT * KH32;
+    static constexpr int S_HD = (NT + 1) * KH32;
+    static constexpr int S_L3 = NT * (KH32 + 8);
+    static constexpr int S_L4 = KH32;
+    static constexpr int STEPS32 = S_L1 + S_L2 + S_HD + S_L3 + S_L4;
+    static constexpr int BYTES32 = STEPS32 * WAVE * 4;
+    // biases added through the accumulator (L2, HEAD, L4): 16 floats per tile
+    static constexpr int BIAS_TILES = NT + (NT + 1) + 1;
+    static constexpr int BIAS_FLOATS = BIAS_TILES * 16;
+};
+
+}  // namespace r360
+
+// ---------------------------------------------------------------------------
+// Opaque objects
+// ---------------------------------------------------------------------------
+struct r360_scene {
+    r360_grid_desc grid;
+    r360_mlp_desc mlp;
+    int64_t P;
+    int16_t* labels;         // [n2][n1][n0]: field id of occupied voxels, -1 elsewhere
+    void* pack16_bf;         // [F][FRAGS16][64][8] bf16
+    void* pack16_h;          // [F][FRAGS16][64][8] f16
+    float* pack32;           // [F][STEPS32/4][64][4] f32
+    float* bias;             // [F][BIAS_FLOATS]
+    int device;
+};
+
+struct r360_equirect {
+    int32_t W, H;
+    float* tables;           // device [sin_phi W | cos_phi W | sin_theta H | cos_theta H]
+};
+
+namespace r360 {
+
+// Workspace carve-up (all offsets 256-byte aligned).
+struct Workspace {
+    int32_t* ray_off;   // [N+1]   exclusive prefix of per-ray counts; ray_off[N] = total
+    float* o;           // [3][N]  generated rays (equirect / pinhole)
+    float* d;           // [3][N]
+    float* t_mid;       // [cap]
+    float* delta;       // [cap]
+    int32_t* ray;       // [cap]
+    int32_t* field;     // [cap]
+    int32_t* perm;      // [cap]   field-sorted position -> ray-major sample index
+    float* sigma;       // [cap]
+    float* rgb;         // [3][cap]
+    float* dsigma;      // [cap]   backward
+    float* drgb;        // [3][cap]
+    int32_t* scan;      // scan block sums
+    int32_t* hist;      // [F][ROUTE_WAVES]
+    int32_t* field_start;  // [F+1]
+    float* dw_part;     // [DW_SLOTS][P] per-slot gradient partials
+    int32_t* misc;      // small counters
+    float* loss_part;   // per-block loss partial sums
+    float* ray_rgb;     // [3][N] per-ray colour (train step)
+    float* ray_grad;    // [3][N] dL/dC (train step)
+    const float* ro;    // rays the downstream passes read: caller's or o/d above
+    const float* rd;
+    int64_t N, cap;
+    size_t bytes;
+};
+
+constexpr int ROUTE_BLOCKS = 1024;        // 4 waves each
+constexpr int ROUTE_WAVES = ROUTE_BLOCKS * 4;
+constexpr int SCAN_TILE = 4096;           // elements per scan block (1024 threads x 4)
+constexpr int DW_SLOTS = 512;             // backward work groups with private gradient partials
+
+Workspace carve(void* base, int64_t N, int64_t cap, int F, int64_t P);
+
+// launchers (return hipError_t of the launch)
+enum RayMode { RAYS_GIVEN = 0, RAYS_EQUIRECT = 1, RAYS_PINHOLE = 2 };
+struct RaySource {
+    int mode;
+    const float* o;       // RAYS_GIVEN
+    const float* d;
+    const float* tables;  // RAYS_EQUIRECT
+    int W, H;
+    float fx, fy;         // RAYS_PINHOLE
+    float c2w[12];
+    const int64_t* pix;   // optional pixel list (equirect)
+};
+struct DdaParams {
+    const int16_t* labels;
+    int n0, n1, n2;
+    float lo0, lo1, lo2;
+    float voxel, inv_voxel;
+    float near_, far_;
+    int max_samples;
+};
+DdaParams dda_params(const r360_scene* s, const r360_render_opts* opts);
+
+hipError_t launch_rays(const RaySource& src, int64_t N, float* o, float* d, hipStream_t st);
+hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w,
+                         int32_t* voxel_out, hipStream_t st);
+hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64_t nvox, int n_fields,
+                         int16_t* labels, hipStream_t st);
+hipError_t launch_route(const Workspace& w, int F, hipStream_t st);
+hipError_t launch_repack(r360_scene* s, const float* weights, hipStream_t st);
+hipError_t launch_mlp_forward(const r360_scene* s, const Workspace& w, int precision, hipStream_t st);
+hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
+                            hipStream_t st);
+hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, const float* target, float* loss,
+                            float* grad_rgb, hipStream_t st);
+hipError_t launch_composite_backward(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);
+hipError_t launch_mlp_backward(const r360_scene* s, const Workspace& w, int precision, float* grad_weights,
+                               hipStream_t st);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, int64_t step, float lr,
+                       float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_gradcheck_forward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,
+                                    double* rgb64, hipStream_t st);
+hipError_t launch_gradcheck_backward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,
+                                     const double* grad_rgb64, double* grad64, hipStream_t st);
+
+}  // namespace r360

@@ -1,0 +1,176 @@
+// Routing of samples to the local field that owns their voxel (Sec. 5:
+// each occupied voxel is labelled with its tiny MLP; the labels come from
+// Alg.1 Stage II). A stable counting sort by field id:
+//   1. every wave counts the field ids of a contiguous slice of the samples;
+//   2. per field, an exclusive scan over the waves' counts; then a scan over
+//      the fields gives each field's first sorted position;
+//   3. every wave walks its slice again and places each sample at
+//      field_start + (earlier waves' count) + (rank among equal ids so far),
+//      the rank within 64 lanes coming from ballots over the id bits.
+// The result perm[sorted position] = ray-major sample index keeps ray order
+// inside each field, so the sort is deterministic.
+#include "r360_internal.h"
+
+namespace r360 {
+
+namespace {
+
+__device__ __forceinline__ void slice(int S, int rw, int w, int& beg, int& end) {
+    const int per = (S + rw - 1) / rw;
+    beg = min(S, w * per);
+    end = min(S, beg + per);
+}
+
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_hist(const int32_t* __restrict__ field, const int32_t* __restrict__ total,
+                                                   int F, int rw, int32_t* __restrict__ hist) {
+    extern __shared__ int32_t lds[];
+    const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t* h = lds + wl * F;
+    for (int f = lane; f < F; f += 64) h[f] = 0;
+    const int w = blockIdx.x * WPB + wl;
+    int beg, end;
+    slice(*total, rw, w, beg, end);
+    for (int i = beg + lane; i < end; i += 64) atomicAdd(&h[field[i]], 1);
+    __syncthreads();
+    for (int f = lane; f < F; f += 64) hist[(int64_t)f * rw + w] = h[f];
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const int t = __shfl_up(v, s, 64);
+        if (lane >= s) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int block_excl_scan(int v, int* total) {
+    __shared__ int wsum[16];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        int x = lane < 16 ? wsum[lane] : 0;
+        x = wave_incl_scan(x);
+        if (lane < 16) wsum[lane] = x;
+    }
+    __syncthreads();
+    const int before = w > 0 ? wsum[w - 1] : 0;
+    *total = wsum[15];
+    __syncthreads();
+    return before + inc - v;
+}
+
+// One block per field: exclusive scan over the waves' counts (in place);
+// the field's total goes to cnt[f].
+__global__ __launch_bounds__(1024) void k_rows(int32_t* __restrict__ hist, int rw, int32_t* __restrict__ cnt) {
+    const int f = blockIdx.x;
+    int32_t* row = hist + (int64_t)f * rw;
+    int carry = 0;
+    for (int base = 0; base < rw; base += 4096) {
+        int v[4], s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = base + threadIdx.x * 4 + k;
+            v[k] = i < rw ? row[i] : 0;
+            s += v[k];
+        }
+        int tot;
+        int ex = carry + block_excl_scan(s, &tot);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = base + threadIdx.x * 4 + k;
+            if (i < rw) row[i] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) cnt[f] = carry;
+}
+
+// Exclusive scan over the fields' totals (in place); start[F] = total.
+__global__ __launch_bounds__(1024) void k_fields(int32_t* __restrict__ start, int F) {
+    int carry = 0;
+    for (int base = 0; base < F; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = i < F ? start[i] : 0;
+        int tot;
+        const int ex = block_excl_scan(v, &tot);
+        if (i < F) start[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) start[F] = carry;
+}
+
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict__ field, const int32_t* __restrict__ total,
+                                                      int F, int nbits, int rw, const int32_t* __restrict__ hist,
+                                                      const int32_t* __restrict__ start, int32_t* __restrict__ perm) {
+    extern __shared__ int32_t lds[];
+    const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t* run = lds + wl * F;
+    const int w = blockIdx.x * WPB + wl;
+    int beg, end;
+    slice(*total, rw, w, beg, end);
+    if (beg < end)
+        for (int f = lane; f < F; f += 64) run[f] = start[f] + hist[(int64_t)f * rw + w];
+    __syncthreads();
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int c = beg; c < end; c += 64) {
+        const int i = c + lane;
+        const bool valid = i < end;
+        const int f = valid ? field[i] : 0;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < nbits; ++b) {
+            const bool bit = (f >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        if (valid) {
+            const int rank = __popcll(peers & lt);
+            const int n = __popcll(peers);
+            const int pos = run[f] + rank;
+            perm[pos] = i;
+            if (rank == n - 1) run[f] = pos + 1;
+        }
+    }
+}
+
+}  // namespace
+
+int route_waves(int F) {
+    int rw = ROUTE_WAVES;
+    while (rw > 256 && (int64_t)rw * F > (4 << 20)) rw >>= 1;
+    return rw;
+}
+
+hipError_t launch_route(const Workspace& w, int F, hipStream_t st) {
+    const int rw = route_waves(F);
+    int nbits = 1;
+    while ((1 << nbits) < F) ++nbits;
+    const int32_t* total = w.ray_off + w.N;
+    if (F <= 4096) {
+        const size_t lds = 4 * F * sizeof(int32_t);
+        hipLaunchKernelGGL(k_hist<4>, dim3(rw / 4), dim3(256), lds, st, w.field, total, F, rw, w.hist);
+    } else {
+        const size_t lds = F * sizeof(int32_t);
+        hipLaunchKernelGGL(k_hist<1>, dim3(rw), dim3(64), lds, st, w.field, total, F, rw, w.hist);
+    }
+    hipLaunchKernelGGL(k_rows, dim3(F), dim3(1024), 0, st, w.hist, rw, w.field_start);
+    hipLaunchKernelGGL(k_fields, dim3(1), dim3(1024), 0, st, w.field_start, F);
+    if (F <= 4096) {
+        const size_t lds = 4 * F * sizeof(int32_t);
+        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, total, F, nbits, rw, w.hist,
+                           w.field_start, w.perm);
+    } else {
+        const size_t lds = F * sizeof(int32_t);
+        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, total, F, nbits, rw, w.hist,
+                           w.field_start, w.perm);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace r360
