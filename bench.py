@@ -1,0 +1,218 @@
+"""Benchmark of the r360 hot path on one MI355X.
+
+A step is one BF16 render of a 2048x1024 equirect view of the synthetic
+room scene (128^3 occupancy grid of walls/furniture boxes plus 2% salt,
+octree-split fields of hidden width 64, up to 64 samples per ray, near
+0.05 m, far 12 m): ray generation, occupied-voxel sampling, routing by
+field, encoding + field MLPs on BF16 MFMA, compositing. The same view in
+the FP32 path and a 65,536-ray forward+backward training step are timed
+beside it. Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s render at 2048x1024 equirect (BF16 vs FP32); train-step ms per 64K rays"
+W, H = 2048, 1024
+FLOP_PER_SAMPLE_FWD = 36608          # 2 x 18,304 MACs of the hidden-64 field MLP
+FLOP_PER_SAMPLE_TRAIN = 98304        # forward + dW + dX MACs x 2
+PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-train", action="store_true")
+    p.add_argument("--only", choices=["bf16", "fp32", "train"], default=None,
+                   help="time only one leg (for profiler runs)")
+    return p.parse_args()
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    import paper_2208_02705_amd as R
+
+    torch.cuda.set_device(0)
+    sc = synth.scene_room()
+    scene = R.Scene.from_synth(sc)
+    c2w = synth.IDENTITY_C2W
+    eq = R.Equirect(W, H)
+    o, d = eq.rays(c2w)
+    smp = R.sample_rays(scene, o, d, with_voxel=False)
+    S = int(smp["t_mid"].numel())
+    del smp
+    torch.cuda.synchronize()
+    out = {}
+
+    def leg(prec, steps, warmup):
+        r = R.EquirectRenderer(scene, W, H, precision=prec)
+        R.profile_read()
+        R.profile_enable(True)
+        sec = timed(lambda: r(c2w), steps, warmup)
+        prof = R.profile_read()
+        R.profile_enable(False)
+        del r
+        return sec, prof
+
+    legs = ["bf16", "fp32", "train"] if args.only is None else [args.only]
+    res = {}
+    if "bf16" in legs:
+        res["bf16"] = leg("bf16", args.steps, args.warmup)
+    if "fp32" in legs:
+        res["fp32"] = leg("fp32", max(3, args.steps // 5), max(1, args.warmup // 2))
+    train = None
+    if "train" in legs and not args.no_train:
+        try:
+            train = train_leg(R, sc, scene, args)
+        except R.R360Error as e:
+            train = {"error": str(e)}
+
+    main_prec = "bf16" if "bf16" in res else next(iter(res), None)
+    line = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+            "data": "synthetic (seeded room scene and Xavier-initialised fields; no dataset or trained weights)",
+            "config": {"workload": "equirect-2048x1024 render of the 128^3 room scene", "rays": W * H,
+                       "samples_per_frame": S, "n_fields": sc.n_fields, "hidden": sc.hidden,
+                       "max_samples": sc.max_samples, "near": sc.near, "far": sc.far}}
+    if main_prec is not None:
+        sec, prof = res[main_prec]
+        line["value"] = W * H / sec / 1e6
+        line["ms_per_step"] = sec * 1e3
+        line["dtype"] = main_prec
+        line["msamples_per_s"] = S / sec / 1e6
+        mlp_ms, mlp_n = prof["mlp_forward"]
+        avg = mlp_ms / max(mlp_n, 1)
+        achieved = S * FLOP_PER_SAMPLE_FWD / (avg * 1e-3) / 1e12
+        line["roofline"] = {"bound": "mfma", "kernel": f"field MLP forward ({main_prec})", "achieved": achieved,
+                            "peak": PEAK[main_prec], "unit": "TFLOP/s", "frac": achieved / PEAK[main_prec],
+                            "traffic": None, "avg_launch_ms": avg,
+                            "algorithmic_flop_per_launch": S * FLOP_PER_SAMPLE_FWD}
+        line["stages_ms"] = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
+        # HBM-bound stages against the 8 TB/s roofline (algorithmic bytes)
+        st = line["stages_ms"]
+        hb = {}
+        if "sample" in st:
+            b = 16 * S + 8 * W * H + 24 * W * H
+            hb["sample"] = {"GB/s": b / (st["sample"] * 1e-3) / 1e9, "bytes": b}
+        if "composite" in st:
+            b = 24 * S + 8 * W * H + 20 * W * H
+            hb["composite"] = {"GB/s": b / (st["composite"] * 1e-3) / 1e9, "bytes": b}
+        for v in hb.values():
+            v["frac"] = v["GB/s"] / HBM_PEAK_GBS
+        line["hbm_stages"] = hb
+    for prec, (sec, prof) in res.items():
+        line[f"{prec}_mrays_per_s"] = W * H / sec / 1e6
+        line[f"{prec}_ms_per_frame"] = sec * 1e3
+        m = prof["mlp_forward"]
+        line[f"{prec}_mlp_tflops"] = S * FLOP_PER_SAMPLE_FWD / (m[0] / max(m[1], 1) * 1e-3) / 1e12
+    if train is not None:
+        line["train_step"] = train
+    line["context"] = ("paper: 360Roam renders a 1520x760 panorama in 0.03 s on one RTX2080 Ti (about 38.5 Mrays/s, "
+                       "precision not stated) and runs in real time on a GTX1080; different hardware and scenes")
+    if not args.no_cpu_baseline and args.only is None:
+        line["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(line), flush=True)
+
+
+def train_leg(R, sc, scene, args):
+    """Forward + backward over a 65,536-ray batch from 20 cameras (BF16 MLPs,
+    FP32 master weights and accumulation), then one Adam step."""
+    import numpy as np
+    import torch
+    import synth
+    N = 65536
+    cams = synth.camera_centres(sc, 20)
+    cam, u, v = synth.ray_draws(N, 20, W, H)
+    eq = R.Equirect(W, H)
+    o = torch.empty(3, N, device="cuda")
+    d = torch.empty(3, N, device="cuda")
+    for k in range(20):
+        sel = np.nonzero(cam == k)[0]
+        if len(sel) == 0:
+            continue
+        pix = torch.from_numpy((v[sel].astype(np.int64) * W + u[sel])).cuda()
+        ok, dk = eq.rays(synth.c2w_at(cams[k]), pix)
+        idx = torch.from_numpy(sel).cuda()
+        o[:, idx] = ok
+        d[:, idx] = dk
+    # targets: a teacher field set rendered by the same path, plus N(0, 0.01^2)
+    teacher = R.Scene.from_synth(sc, weights=torch.from_numpy(synth.teacher_weights(sc)).cuda())
+    tgt, _, _ = R.render_rays(teacher, o, d, precision="fp32")
+    tgt = (tgt + torch.from_numpy(synth.noise(3 * N, 0.01).reshape(3, N).astype(np.float32)).cuda()).contiguous()
+    del teacher
+    w = torch.from_numpy(sc.weights).cuda()
+    m = torch.zeros_like(w); vv = torch.zeros_like(w)
+    grad = torch.empty_like(w); loss = torch.empty(1, device="cuda")
+    step = [0]
+
+    def fwd_bwd():
+        R.train_step(scene, o, d, tgt, precision="bf16", grad=grad, loss=loss)
+
+    def full():
+        fwd_bwd()
+        step[0] += 1
+        R.adam_step(w, grad, m, vv, step[0], R.lr_at(step[0], 1000))
+        scene.set_weights(w)
+
+    R.profile_read()
+    R.profile_enable(True)
+    sec = timed(fwd_bwd, max(5, args.steps // 2), 2)
+    prof = R.profile_read()
+    R.profile_enable(False)
+    sec_full = timed(full, max(5, args.steps // 2), 2)
+    smp = R.sample_rays(scene, o, d, with_voxel=False)
+    S = int(smp["t_mid"].numel())
+    st = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
+    return {"rays": N, "samples": S, "ms_fwd_bwd": sec * 1e3, "ms_with_adam": sec_full * 1e3,
+            "stages_ms": st, "tflops_fwd_bwd": S * FLOP_PER_SAMPLE_TRAIN / sec / 1e12, "loss": float(loss.item())}
+
+
+def cpu_baseline(sc):
+    """The FP64 oracle on the host cores: every 16th pixel of the same view."""
+    import numpy as np
+    import oracle
+    import synth
+    pix = np.arange(0, W * H, 16, dtype=np.int64)
+    o, d = oracle.equirect_rays(W, H, synth.IDENTITY_C2W, pix)
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    oracle.render_rays(sc, o, d, threads=threads)
+    el = time.perf_counter() - t0
+    return {"value": len(pix) / el / 1e6, "unit": "Mrays/s", "cores": threads, "kind": "oracle",
+            "sample": f"every 16th pixel of the 2048x1024 view ({len(pix)} rays), whole oracle path "
+                      f"(FP32 traversal, FP64 encoding/MLP/compositing), {el:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -215,6 +215,18 @@ r360_status r360_gradcheck_backward(const r360_scene* scene, const double* weigh
                                     const double* grad_rgb64, double* grad64, void* ws, size_t ws_bytes,
                                     void* stream);
 
+/* Optional per-stage timing for benchmarking: when enabled, every entry
+ * point records a HIP event pair around each stage of its launch sequence on
+ * the call's own stream. Stages: 0 sampling (count + scan + fill), 1 routing,
+ * 2 field-MLP forward, 3 compositing, 4 loss, 5 compositing backward,
+ * 6 field-MLP backward, 7 gradient reduction. */
+#define R360_NSTAGES 8
+r360_status r360_profile_enable(int32_t on);
+/* Waits for the recorded events and returns, per stage, the milliseconds and
+ * the number of timed launches since the previous read (arrays of
+ * R360_NSTAGES); then forgets them. */
+r360_status r360_profile_read(double* ms_host, int32_t* count_host);
+
 /* Status text; for R360_EHIP also the runtime's last error text. */
 const char* r360_status_string(int32_t status);
 const char* r360_last_error(void);

@@ -15,6 +15,9 @@ LIB_PATH = os.path.join(HERE, "libr360.so")
 R360_OK, R360_EINVAL, R360_ENOMEM, R360_EHIP, R360_EUNSUPPORTED, R360_EWORKSPACE = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16, FP64_GRADCHECK = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp64": FP64_GRADCHECK}
+NSTAGES = 8
+STAGES = ["sample", "route", "mlp_forward", "composite", "loss", "composite_backward", "mlp_backward",
+          "grad_reduce"]
 
 
 class GridDesc(C.Structure):
@@ -59,6 +62,8 @@ SIGNATURES = {
     "r360_adam_step": (i32, [vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, vp]),
     "r360_gradcheck_forward": (i32, [vp, vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, sz, vp]),
     "r360_gradcheck_backward": (i32, [vp, vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, sz, vp]),
+    "r360_profile_enable": (i32, [i32]),
+    "r360_profile_read": (i32, [vp, vp]),
     "r360_status_string": (C.c_char_p, [i32]),
     "r360_last_error": (C.c_char_p, []),
 }

@@ -13,6 +13,9 @@ size_t pack_bytes16(int H);
 size_t pack_bytes32(int H);
 size_t bias_floats(int H);
 int route_waves(int F);
+inline size_t packT_bytes16(int H) {
+    return (size_t)(H == 32 ? PackGeom<32>::FRAGS_T : PackGeom<64>::FRAGS_T) * WAVE * 16;
+}
 }
 
 using namespace r360;
@@ -36,6 +39,28 @@ r360_status inval(const char* what) {
     } while (0)
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Per-stage event timing (r360_profile_enable / r360_profile_read).
+struct StageEvents { int stage; hipEvent_t a, b; };
+bool g_prof = false;
+std::vector<StageEvents> g_events;
+
+struct StageTimer {
+    hipStream_t st;
+    StageEvents ev{-1, nullptr, nullptr};
+    StageTimer(int stage, hipStream_t s) : st(s) {
+        if (!g_prof) return;
+        ev.stage = stage;
+        if (hipEventCreate(&ev.a) != hipSuccess || hipEventCreate(&ev.b) != hipSuccess) { ev.stage = -1; return; }
+        (void)hipEventRecord(ev.a, st);
+    }
+    ~StageTimer() {
+        if (ev.stage < 0) return;
+        (void)hipEventRecord(ev.b, st);
+        g_events.push_back(ev);
+    }
+};
+#define R360_STAGE(k, st) StageTimer timer_##k(k, st)
 inline size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
 bool pow2(float v) {
@@ -141,10 +166,22 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
     w.ro = src.mode == RAYS_GIVEN ? src.o : w.o;
     w.rd = src.mode == RAYS_GIVEN ? src.d : w.d;
     const DdaParams p = dda_params(s, opts);
-    R360_TRY("sample", launch_sample(src, p, N, w, nullptr, st));
-    R360_TRY("route", launch_route(w, s->mlp.n_fields, st));
-    R360_TRY("mlp forward", launch_mlp_forward(s, w, opts->precision, st));
-    R360_TRY("composite", launch_composite(w, N, rgb, depth, opacity, st));
+    {
+        R360_STAGE(0, st);
+        R360_TRY("sample", launch_sample(src, p, N, w, nullptr, st));
+    }
+    {
+        R360_STAGE(1, st);
+        R360_TRY("route", launch_route(w, s->mlp.n_fields, st));
+    }
+    {
+        R360_STAGE(2, st);
+        R360_TRY("mlp forward", launch_mlp_forward(s, w, opts->precision, st));
+    }
+    {
+        R360_STAGE(3, st);
+        R360_TRY("composite", launch_composite(w, N, rgb, depth, opacity, st));
+    }
     return R360_OK;
 }
 
@@ -198,6 +235,10 @@ r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob,
     ok = ok && hipMalloc(&s->pack16_h, F * pack_bytes16(H)) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->pack32, F * pack_bytes32(H)) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->bias, F * bias_floats(H) * sizeof(float)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->pack16_f, F * pack_bytes16(H) * 2) == hipSuccess;
+    ok = ok && hipMalloc(&s->packT_bf, F * packT_bytes16(H)) == hipSuccess;
+    ok = ok && hipMalloc(&s->packT_h, F * packT_bytes16(H)) == hipSuccess;
+    ok = ok && hipMalloc((void**)&s->packT_f, F * packT_bytes16(H) * 2) == hipSuccess;
     if (!ok) {
         r360_scene_destroy(s);
         return R360_ENOMEM;
@@ -208,6 +249,7 @@ r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob,
         return inval("field_map holds ids outside [-1, n_fields)");
     }
     if (e == hipSuccess) e = launch_repack(s, weights, S(stream));
+    if (e == hipSuccess) e = launch_repack_bwd(s, weights, S(stream));
     if (e != hipSuccess) {
         r360_scene_destroy(s);
         return hip_fail("scene_create", e);
@@ -219,6 +261,7 @@ r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob,
 r360_status r360_scene_set_weights(r360_scene* s, const float* weights, void* stream) {
     if (!s || !weights) return inval("NULL pointer");
     R360_TRY("repack", launch_repack(s, weights, S(stream)));
+    R360_TRY("repack", launch_repack_bwd(s, weights, S(stream)));
     return R360_OK;
 }
 
@@ -238,6 +281,10 @@ void r360_scene_destroy(r360_scene* s) {
     (void)hipFree(s->pack16_h);
     (void)hipFree(s->pack32);
     (void)hipFree(s->bias);
+    (void)hipFree(s->pack16_f);
+    (void)hipFree(s->packT_bf);
+    (void)hipFree(s->packT_h);
+    (void)hipFree(s->packT_f);
     delete s;
 }
 
@@ -410,8 +457,14 @@ r360_status r360_backward(const r360_scene* s, const float* o, const float* d, i
     if (st != R360_OK) return st;
     w.ro = o;
     w.rd = d;
-    R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
-    R360_TRY("mlp backward", launch_mlp_backward(s, w, opts->precision, grad_weights, S(stream)));
+    {
+        R360_STAGE(5, S(stream));
+        R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
+    }
+    {
+        R360_STAGE(6, S(stream));
+        R360_TRY("mlp backward", launch_mlp_backward(s, w, opts->precision, grad_weights, S(stream)));
+    }
     return R360_OK;
 }
 
@@ -430,9 +483,18 @@ r360_status r360_train_step(const r360_scene* s, const float* o, const float* d,
     src.d = d;
     st = render_common(s, src, N, opts, rgb, nullptr, nullptr, w, S(stream));
     if (st != R360_OK) return st;
-    R360_TRY("loss", launch_loss_grad(w, N, rgb, target, loss, grad_rgb, S(stream)));
-    R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
-    R360_TRY("mlp backward", launch_mlp_backward(s, w, opts->precision, grad_weights, S(stream)));
+    {
+        R360_STAGE(4, S(stream));
+        R360_TRY("loss", launch_loss_grad(w, N, rgb, target, loss, grad_rgb, S(stream)));
+    }
+    {
+        R360_STAGE(5, S(stream));
+        R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
+    }
+    {
+        R360_STAGE(6, S(stream));
+        R360_TRY("mlp backward", launch_mlp_backward(s, w, opts->precision, grad_weights, S(stream)));
+    }
     return R360_OK;
 }
 
@@ -477,6 +539,28 @@ r360_status r360_gradcheck_backward(const r360_scene* s, const double* w64, cons
     w.rd = d;
     R360_TRY("gradcheck backward", launch_gradcheck_backward(s, w, w64, N, grad_rgb64, grad64, S(stream)));
     return R360_OK;
+}
+
+r360_status r360_profile_enable(int32_t on) {
+    g_prof = on != 0;
+    return R360_OK;
+}
+
+r360_status r360_profile_read(double* ms, int32_t* count) {
+    if (!ms || !count) return inval("NULL pointer");
+    for (int k = 0; k < R360_NSTAGES; ++k) { ms[k] = 0.0; count[k] = 0; }
+    r360_status st = R360_OK;
+    for (auto& e : g_events) {
+        float t = 0.0f;
+        hipError_t err = hipEventSynchronize(e.b);
+        if (err == hipSuccess) err = hipEventElapsedTime(&t, e.a, e.b);
+        if (err != hipSuccess && st == R360_OK) st = hip_fail("profile_read", err);
+        if (e.stage >= 0 && e.stage < R360_NSTAGES) { ms[e.stage] += t; count[e.stage] += 1; }
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    g_events.clear();
+    return st;
 }
 
 const char* r360_status_string(int32_t status) {

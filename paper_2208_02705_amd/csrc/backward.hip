@@ -1,17 +1,875 @@
-// Backward of the field MLPs and the FP64 gradient-check forms.
+// Backward of the per-field MLPs for fine-tuning (Sec. 4.2: all tiny
+// networks are fine-tuned with an L2 photometric loss), and the FP64
+// gradient-check forms.
+//
+// Inputs: the field-sorted samples of the preceding render (route.hip) and,
+// per sample, dL/dsigma and dL/drgb from the compositing backward.
+//
+// Per block of 8 waves and per chunk of 128 samples of one field:
+//  1. each wave recomputes the forward pass of its 16 samples on MFMA
+//     (activations are recomputed, never stored in memory);
+//  2. it runs the input-gradient chain dz4 -> dh3 -> dz3 -> df, dzs -> dh2 ->
+//     dz2 -> dh1 -> dz1 on MFMA with transposed weight fragments, where every
+//     accumulator layout feeds the next product directly (the same k-slot
+//     permutation as the forward pass);
+//  3. for each layer, the eight waves write their layer inputs x and output
+//     gradients dz for the 128 samples into an LDS panel, transposed so that
+//     samples run along k, and every wave accumulates its share of the
+//     16x16 tiles of dW = dz x^T (the bias gradient rides along as a row of
+//     ones in x).
+// The weight-gradient tiles stay in registers while the block stays on one
+// field. A field that lies entirely inside one block's slice is written to
+// the gradient directly; the pieces of fields shared by neighbouring blocks
+// go to two per-block partial slots and a reduction kernel adds them in block
+// order, so the result does not depend on scheduling.
+//
+// Precision: BF16 or FP16 MFMA operands with FP32 accumulation, or FP32
+// throughout (each K = 32 step then issues eight 16x16x4 FP32 MFMAs with the
+// same k-slot layout).
 #include "r360_internal.h"
 
 namespace r360 {
 
-hipError_t launch_mlp_backward(const r360_scene*, const Workspace&, int, float*, hipStream_t) {
-    return hipErrorNotSupported;
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) float f32x8;
+template <typename T> struct FragT;
+template <> struct FragT<__bf16> { typedef bf16x8 type; };
+template <> struct FragT<_Float16> { typedef f16x8 type; };
+template <> struct FragT<float> { typedef f32x8 type; };
+
+template <typename T>
+__device__ __forceinline__ f32x4 mma(typename FragT<T>::type a, typename FragT<T>::type b, f32x4 c) {
+    if constexpr (__is_same(T, __bf16)) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    } else if constexpr (__is_same(T, _Float16)) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], c, 0, 0, 0);
+        return c;
+    }
 }
-hipError_t launch_gradcheck_forward(const r360_scene*, const Workspace&, const double*, int64_t, double*, hipStream_t) {
-    return hipErrorNotSupported;
+
+template <typename T>
+__device__ __forceinline__ typename FragT<T>::type pack8(const float* v) {
+    typename FragT<T>::type r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r[e] = (T)v[e];
+    return r;
 }
-hipError_t launch_gradcheck_backward(const r360_scene*, const Workspace&, const double*, int64_t, const double*,
-                                     double*, hipStream_t) {
-    return hipErrorNotSupported;
+
+// Two accumulator tiles as one B operand (elements 0..3 from a, 4..7 from b).
+template <typename T, bool RELU>
+__device__ __forceinline__ typename FragT<T>::type hand(f32x4 a, f32x4 b) {
+    float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    if (RELU) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = v[e] > 0.0f ? v[e] : 0.0f;
+    }
+    return pack8<T>(v);
+}
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) {
+    int lo = 0, hi = F;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= pos) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+constexpr int BW = 8;                           // waves per backward block
+constexpr int BCH = 16 * BW;                    // samples per backward chunk
+__device__ __forceinline__ int slice_len(int S, int nb) { return (((S + nb - 1) / nb) + BCH - 1) / BCH * BCH; }
+
+// ---------------------------------------------------------------------------
+// Transposed fragments for the input-gradient chain. Fragment (ot, ks) of a
+// transposed layer: lane l, element e holds W[k][i] with i = 16 ot + l%16
+// (an input feature of the forward layer) and k = hidden_col16(ks, l/16, e)
+// (an output row of the forward layer, in the accumulator hand-off order).
+// ---------------------------------------------------------------------------
+template <int H>
+__device__ float packedT_source(const float* w, int fr, int lane, int e) {
+    using G = PackGeom<H>;
+    constexpr FieldLayout L{H};
+    const int g = lane >> 4;
+    int ly, ot, ks;
+    if (fr < G::T_L4) { ly = 4; ot = fr; ks = 0; }
+    else if ((fr -= G::T_L4) < G::T_L3) { ly = 3; ot = fr / G::KH16; ks = fr % G::KH16; }
+    else if ((fr -= G::T_L3) < G::T_HD) { ly = 2; ot = fr / G::KHD; ks = fr % G::KHD; }
+    else { fr -= G::T_HD; ly = 1; ot = fr / G::KH16; ks = fr % G::KH16; }
+    const int i = 16 * ot + (lane & 15);
+    const int k = hidden_col16(ks, g, e);
+    switch (ly) {
+    case 4: return k < 3 ? w[L.W4() + k * H + i] : 0.0f;
+    case 3: return w[L.W3() + k * (H + DDIR) + i];
+    case 2: return k < H ? w[L.Wf() + k * H + i] : (k == H ? w[L.ws() + i] : 0.0f);
+    default: return w[L.W2() + k * H + i];
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(256) void k_repack_bwd(const float* __restrict__ weights, int F,
+                                                    float* __restrict__ p16f, __bf16* __restrict__ tbf,
+                                                    _Float16* __restrict__ th, float* __restrict__ tf) {
+    using G = PackGeom<H>;
+    constexpr FieldLayout L{H};
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nf = (int64_t)F * G::FRAGS16 * WAVE * 8;
+    const int64_t nt = (int64_t)F * G::FRAGS_T * WAVE * 8;
+    const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
+    const int64_t fr_all = i >> 9;
+    if (i < nf) {
+        const int f = (int)(fr_all / G::FRAGS16), fr = (int)(fr_all % G::FRAGS16);
+        p16f[i] = packed_source16<H>(weights + (int64_t)f * L.P(), fr, lane, e);
+    }
+    if (i < nt) {
+        const int f = (int)(fr_all / G::FRAGS_T), fr = (int)(fr_all % G::FRAGS_T);
+        const float v = packedT_source<H>(weights + (int64_t)f * L.P(), fr, lane, e);
+        tbf[i] = (__bf16)v;
+        th[i] = (_Float16)v;
+        tf[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight-gradient tiles: canonical parameter index of tile element
+// (out row, in column) of each layer, or -1 for padding.
+// ---------------------------------------------------------------------------
+template <int H>
+__device__ __forceinline__ int dw_index(int ly, int out, int in) {
+    constexpr FieldLayout L{H};
+    switch (ly) {
+    case LY_L1: {
+        const int feat = pe_slot_feature(in >> 4, in & 15);
+        return feat == SLOT_BIAS ? L.b1() + out : L.W1() + out * DXYZ + feat;
+    }
+    case LY_L2:
+        return in < H ? L.W2() + out * H + in : (in == H ? L.b2() + out : -1);
+    case LY_HD:
+        if (out < H) return in < H ? L.Wf() + out * H + in : (in == H ? L.bf() + out : -1);
+        if (out == H) return in < H ? L.ws() + in : (in == H ? L.bs() : -1);
+        return -1;
+    case LY_L3: {
+        if (in < H) return L.W3() + out * (H + DDIR) + in;
+        const int q = in - H;
+        const int feat = dir_slot_feature(q >> 3, q & 7);
+        if (feat == SLOT_ZERO) return -1;
+        return feat == SLOT_BIAS ? L.b3() + out : L.W3() + out * (H + DDIR) + H + feat;
+    }
+    default:
+        if (out >= 3) return -1;
+        return in < H ? L.W4() + out * H + in : (in == H ? L.b4() + out : -1);
+    }
+}
+
+struct BwdArgs {
+    const int32_t* total;
+    const int32_t* field_start;
+    const int32_t* perm;
+    const float* t_mid;
+    const int32_t* ray;
+    const float* o;
+    const float* d;
+    const float* dsigma;
+    const float* drgb;          // [3][cap]
+    int64_t N, cap;
+    int F;
+    int P;
+    float c0, c1, c2, inv_h;
+    const void* pack;           // forward fragments in the K = 32 layout, element type T
+    const void* packT;          // transposed fragments
+    const float* bias;
+    float* grad;                // [F][P]
+    float* part;                // [2 * gridDim][P]
+};
+
+template <int H>
+struct BwdGeom {
+    using G = PackGeom<H>;
+    static constexpr int NT = G::NT, KH = G::KH16, KHD = G::KHD;
+    // weight-gradient tiles per layer (out tiles x in tiles)
+    static constexpr int OT[5] = {NT, NT, NT + 1, NT, 1};
+    static constexpr int IT[5] = {4, NT + 1, NT + 1, NT + 2, NT + 1};
+    static constexpr int TILES(int ly) { return OT[ly] * IT[ly]; }
+    static constexpr int PER_WAVE(int ly) { return (TILES(ly) + BW - 1) / BW; }
+    static constexpr int ROWS = 2 * H + 32;        // largest x + dz panel (L3 / HEAD)
+    static constexpr int PSTRIDE = BCH + 8;        // samples per panel row, padded
+};
+
+// One layer's weight-gradient stage: the panel holds x rows [0, XR) and dz
+// rows [XR, XR + 16 OT) for the chunk's samples; wave wv accumulates tiles
+// k = wv, wv + BW, ... of the OT x IT tile grid.
+template <typename T, int NACC>
+__device__ __forceinline__ void dw_stage(const T* panel, int pstride, int XR, int OT, int IT, int wv, int lane,
+                                         f32x4* acc) {
+    using F8 = typename FragT<T>::type;
+    const int g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+        const int k = wv + BW * q;
+        if (k < OT * IT) {
+            const int ot = k / IT, it = k % IT;
+#pragma unroll
+            for (int ks = 0; ks < BCH / 32; ++ks) {
+                const F8 A = *reinterpret_cast<const F8*>(panel + (XR + 16 * ot + l16) * pstride + 32 * ks + 8 * g);
+                const F8 B = *reinterpret_cast<const F8*>(panel + (16 * it + l16) * pstride + 32 * ks + 8 * g);
+                acc[q] = mma<T>(A, B, acc[q]);
+            }
+        }
+    }
+}
+
+template <int H, int NACC>
+__device__ __forceinline__ void dw_flush(int ly, int OT, int IT, int wv, int lane, f32x4* acc, float* dst) {
+    const int g = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int q = 0; q < NACC; ++q) {
+        const int k = wv + BW * q;
+        if (k < OT * IT) {
+            const int ot = k / IT, it = k % IT;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int idx = dw_index<H>(ly, 16 * ot + 4 * g + r, 16 * it + l16);
+                if (idx >= 0) dst[idx] = acc[q][r];
+            }
+        }
+        acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+template <int H, typename T>
+__global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
+    using BG = BwdGeom<H>;
+    using G = PackGeom<H>;
+    using F8 = typename FragT<T>::type;
+    constexpr int NT = BG::NT, KH = BG::KH, KHD = BG::KHD, PS = BG::PSTRIDE;
+    constexpr int N1 = BG::PER_WAVE(0), N2 = BG::PER_WAVE(1), NH = BG::PER_WAVE(2), N3 = BG::PER_WAVE(3),
+                  N4 = BG::PER_WAVE(4);
+    extern __shared__ __attribute__((aligned(32))) char smem_raw[];
+    T* panel = reinterpret_cast<T*>(smem_raw);
+    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15, wv = threadIdx.x >> 6;
+    const int col = 16 * wv + j;                     // this lane's sample column in the panel
+    const int nb = gridDim.x;
+    const int b = xcd_block(blockIdx.x, nb);
+    const int S = *a.total;
+    const int per = slice_len(S, nb);
+    const int beg = min(S, b * per), end = min(S, beg + per);
+    if (beg >= end) return;
+    const int first = find_field(a.field_start, a.F, beg);
+    const int last = find_field(a.field_start, a.F, end - 1);
+    const F8* pk = reinterpret_cast<const F8*>(a.pack);
+    const F8* pt = reinterpret_cast<const F8*>(a.packT);
+    const float cc[3] = {a.c0, a.c1, a.c2};
+
+    f32x4 w1[N1], w2[N2], wh[NH], w3[N3], w4[N4];
+    auto zero = [](f32x4* v, int n) { for (int q = 0; q < n; ++q) v[q] = f32x4{0.f, 0.f, 0.f, 0.f}; };
+    zero(w1, N1); zero(w2, N2); zero(wh, NH); zero(w3, N3); zero(w4, N4);
+
+    for (int pos = beg; pos < end;) {
+        const int f = find_field(a.field_start, a.F, pos);
+        const int fend = min(end, a.field_start[f + 1]);
+        const F8* P = pk + (int64_t)f * G::FRAGS16 * WAVE + lane;
+        const F8* PT = pt + (int64_t)f * G::FRAGS_T * WAVE + lane;
+        const f32x4* bias = reinterpret_cast<const f32x4*>(a.bias + (int64_t)f * G::BIAS_FLOATS) + g;
+        for (int c = pos; c < fend; c += BCH) {
+            // Keep the weight fragments out of registers across chunks: the
+            // compiler would otherwise hoist all ~70 per-field fragment loads
+            // out of this loop and spill. They are re-read from L1/L2 instead.
+            const F8* Pc = P;
+            const F8* PTc = PT;
+            asm volatile("" : "+v"(Pc));
+            asm volatile("" : "+v"(PTc));
+            const int sp = c + col;
+            const bool valid = sp < fend;
+            const int orig = a.perm[valid ? sp : c];
+            const float t = a.t_mid[orig];
+            const int64_t r = a.ray[orig];
+            const float dv[3] = {a.d[r], a.d[a.N + r], a.d[2 * a.N + r]};
+            float xh[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xh[k] = (__builtin_fmaf(t, dv[k], a.o[k * a.N + r]) - cc[k]) * a.inv_h;
+
+            // ---- forward recompute ----
+            F8 x0, x1;
+            {
+                float pe[16];
+                pe_position(g, xh, pe);
+                x0 = pack8<T>(pe);
+                x1 = pack8<T>(pe + 8);
+            }
+            f32x4 acc[NT + 1];
+            const F8* q = Pc;
+#pragma unroll
+            for (int ot = 0; ot < NT; ++ot) {
+                acc[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+                acc[ot] = mma<T>(q[(2 * ot) * WAVE], x0, acc[ot]);
+                acc[ot] = mma<T>(q[(2 * ot + 1) * WAVE], x1, acc[ot]);
+            }
+            q += G::F_L1 * WAVE;
+            F8 h1[KH], h2[KH], fb[KH], h3[KH];
+#pragma unroll
+            for (int ks = 0; ks < KH; ++ks) h1[ks] = hand<T, true>(acc[2 * ks], acc[2 * ks + 1]);
+#pragma unroll
+            for (int ot = 0; ot < NT; ++ot) {
+                acc[ot] = bias[ot * 4];
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) acc[ot] = mma<T>(q[(ot * KH + ks) * WAVE], h1[ks], acc[ot]);
+            }
+            q += G::F_L2 * WAVE;
+#pragma unroll
+            for (int ks = 0; ks < KH; ++ks) h2[ks] = hand<T, true>(acc[2 * ks], acc[2 * ks + 1]);
+#pragma unroll
+            for (int ot = 0; ot < NT + 1; ++ot) {
+                acc[ot] = bias[(NT + ot) * 4];
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) acc[ot] = mma<T>(q[(ot * KH + ks) * WAVE], h2[ks], acc[ot]);
+            }
+            q += G::F_HD * WAVE;
+            const float zs = acc[NT][0];
+#pragma unroll
+            for (int ks = 0; ks < KH; ++ks) fb[ks] = hand<T, false>(acc[2 * ks], acc[2 * ks + 1]);
+            F8 xd;
+            {
+                float dpe[8];
+                pe_direction(g, dv, dpe);
+                xd = pack8<T>(dpe);
+            }
+#pragma unroll
+            for (int ot = 0; ot < NT; ++ot) {
+                acc[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) acc[ot] = mma<T>(q[(ot * (KH + 1) + ks) * WAVE], fb[ks], acc[ot]);
+                acc[ot] = mma<T>(q[(ot * (KH + 1) + KH) * WAVE], xd, acc[ot]);
+            }
+            q += G::F_L3 * WAVE;
+#pragma unroll
+            for (int ks = 0; ks < KH; ++ks) h3[ks] = hand<T, true>(acc[2 * ks], acc[2 * ks + 1]);
+            f32x4 o4 = bias[(2 * NT + 1) * 4];
+#pragma unroll
+            for (int ks = 0; ks < KH; ++ks) o4 = mma<T>(q[ks * WAVE], h3[ks], o4);
+
+            // ---- output gradients (lane group 0 holds rows 0..3 of each tile) ----
+            float dzs = 0.0f;
+            f32x4 dz4 = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (g == 0 && valid) {
+                dzs = a.dsigma[orig] * sigmoidf_(zs);                 // softplus' = sigmoid
+#pragma unroll
+                for (int cch = 0; cch < 3; ++cch) {
+                    const float s = sigmoidf_(o4[cch]);
+                    dz4[cch] = a.drgb[cch * a.cap + orig] * s * (1.0f - s);
+                }
+            }
+
+            // Panel writers: hidden features from hand-off fragments, C-layout tiles.
+            auto put_hidden = [&](int row0, const F8* hb) {
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) panel[(row0 + hidden_col16(ks, g, e)) * PS + col] = hb[ks][e];
+            };
+            auto put_ones = [&](int row0) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) panel[(row0 + 4 * g + rr) * PS + col] = (T)((4 * g + rr) == 0 ? 1.0f : 0.0f);
+            };
+            auto put_tiles = [&](int row0, const f32x4* tl, int ntl) {
+                for (int tt = 0; tt < ntl; ++tt)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) panel[(row0 + 16 * tt + 4 * g + rr) * PS + col] = (T)tl[tt][rr];
+            };
+            auto mask = [&](f32x4* dz, const F8* hb) {   // dz *= [h > 0]
+#pragma unroll
+                for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+                        if (!((float)hb[tt >> 1][4 * (tt & 1) + rr] > 0.0f)) dz[tt][rr] = 0.0f;
+            };
+
+            // ---- L4: dW4 and dh3 = W4^T dz4 ----
+            put_hidden(0, h3);
+            put_ones(H);
+            put_tiles(H + 16, &dz4, 1);
+            __syncthreads();
+            dw_stage<T, N4>(panel, PS, H + 16, 1, NT + 1, wv, lane, w4);
+            __syncthreads();
+            f32x4 dz[NT + 1];
+            {
+                const F8 bz = hand<T, false>(dz4, f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                for (int ot = 0; ot < NT; ++ot) dz[ot] = mma<T>(PTc[ot * WAVE], bz, f32x4{0.f, 0.f, 0.f, 0.f});
+            }
+            mask(dz, h3);
+            // ---- L3: dW3 over [f ; g(d)] and df = W3_f^T dz3 ----
+            put_hidden(0, fb);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) panel[(H + 8 * g + e) * PS + col] = xd[e];
+            put_tiles(H + 32, dz, NT);
+            __syncthreads();
+            dw_stage<T, N3>(panel, PS, H + 32, NT, NT + 2, wv, lane, w3);
+            __syncthreads();
+            f32x4 df[NT + 1];
+            {
+                F8 bz[KH];
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) bz[ks] = hand<T, false>(dz[2 * ks], dz[2 * ks + 1]);
+                const F8* q3 = PTc + G::T_L4 * WAVE;
+#pragma unroll
+                for (int ot = 0; ot < NT; ++ot) {
+                    df[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < KH; ++ks) df[ot] = mma<T>(q3[(ot * KH + ks) * WAVE], bz[ks], df[ot]);
+                }
+            }
+            df[NT] = f32x4{dzs, 0.f, 0.f, 0.f};           // the sigma row H sits in tile NT, row 0
+            // ---- HEAD: d[Wf ; ws] and dh2 = [Wf ; ws]^T [df ; dzs] ----
+            put_hidden(0, h2);
+            put_ones(H);
+            put_tiles(H + 16, df, NT + 1);
+            __syncthreads();
+            dw_stage<T, NH>(panel, PS, H + 16, NT + 1, NT + 1, wv, lane, wh);
+            __syncthreads();
+            {
+                F8 bz[KHD];
+#pragma unroll
+                for (int ks = 0; ks < KHD; ++ks) {
+                    const f32x4 t0 = df[2 * ks];
+                    const f32x4 t1 = (2 * ks + 1 <= NT) ? df[(2 * ks + 1 <= NT) ? 2 * ks + 1 : 0] : f32x4{0.f, 0.f, 0.f, 0.f};
+                    bz[ks] = hand<T, false>(t0, t1);
+                }
+                const F8* qh = PTc + (G::T_L4 + G::T_L3) * WAVE;
+#pragma unroll
+                for (int ot = 0; ot < NT; ++ot) {
+                    dz[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < KHD; ++ks) dz[ot] = mma<T>(qh[(ot * KHD + ks) * WAVE], bz[ks], dz[ot]);
+                }
+            }
+            mask(dz, h2);
+            // ---- L2: dW2 and dh1 = W2^T dz2 ----
+            put_hidden(0, h1);
+            put_ones(H);
+            put_tiles(H + 16, dz, NT);
+            __syncthreads();
+            dw_stage<T, N2>(panel, PS, H + 16, NT, NT + 1, wv, lane, w2);
+            __syncthreads();
+            {
+                F8 bz[KH];
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) bz[ks] = hand<T, false>(dz[2 * ks], dz[2 * ks + 1]);
+                const F8* q2 = PTc + (G::T_L4 + G::T_L3 + G::T_HD) * WAVE;
+                f32x4 t1[NT];
+#pragma unroll
+                for (int ot = 0; ot < NT; ++ot) {
+                    t1[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int ks = 0; ks < KH; ++ks) t1[ot] = mma<T>(q2[(ot * KH + ks) * WAVE], bz[ks], t1[ot]);
+                }
+#pragma unroll
+                for (int ot = 0; ot < NT; ++ot) dz[ot] = t1[ot];
+            }
+            mask(dz, h1);
+            // ---- L1: dW1 over the encoding slots ----
+#pragma unroll
+            for (int s2 = 0; s2 < 8; ++s2) {
+                panel[(16 * g + s2) * PS + col] = x0[s2];
+                panel[(16 * g + 8 + s2) * PS + col] = x1[s2];
+            }
+            put_tiles(64, dz, NT);
+            __syncthreads();
+            dw_stage<T, N1>(panel, PS, 64, NT, 4, wv, lane, w1);
+            __syncthreads();
+        }
+        // flush this field's tiles
+        float* dst;
+        if (f == first) dst = a.part + (int64_t)(2 * b) * a.P;
+        else if (f == last) dst = a.part + (int64_t)(2 * b + 1) * a.P;
+        else dst = a.grad + (int64_t)f * a.P;
+        dw_flush<H, N1>(LY_L1, NT, 4, wv, lane, w1, dst);
+        dw_flush<H, N2>(LY_L2, NT, NT + 1, wv, lane, w2, dst);
+        dw_flush<H, NH>(LY_HD, NT + 1, NT + 1, wv, lane, wh, dst);
+        dw_flush<H, N3>(LY_L3, NT, NT + 2, wv, lane, w3, dst);
+        dw_flush<H, N4>(LY_L4, 1, NT + 1, wv, lane, w4, dst);
+        pos = fend;
+    }
+}
+
+// Adds the partial slots of fields shared by several blocks, in block order.
+__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, float* __restrict__ grad,
+                                                   const int32_t* __restrict__ start, const int32_t* __restrict__ total,
+                                                   int F, int P, int nb) {
+    const int f = blockIdx.y;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= P) return;
+    const int S = *total;
+    const int per = slice_len(S, nb);
+    const int fs = start[f], fe = start[f + 1];
+    if (fe <= fs) { grad[(int64_t)f * P + p] = 0.0f; return; }
+    const int b0 = fs / per, b1 = (fe - 1) / per;
+    if (b0 == b1) {
+        const int beg = b0 * per, end = min(S, beg + per);
+        if (f != find_field(start, F, beg) && f != find_field(start, F, end - 1)) return;   // written directly
+    }
+    float acc = 0.0f;
+    for (int b = b0; b <= b1; ++b) {
+        const int slot = (f == find_field(start, F, b * per)) ? 2 * b : 2 * b + 1;
+        acc += part[(int64_t)slot * P + p];
+    }
+    grad[(int64_t)f * P + p] = acc;
+}
+
+template <typename K>
+int resident(K kernel, size_t lds) {
+    int dev = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * BW, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    hipDeviceProp_t prop;
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    int nb = per_cu * cus;
+    nb = nb > DW_SLOTS / 2 ? DW_SLOTS / 2 : nb;
+    nb &= ~7;
+    return nb < 8 ? 8 : nb;
+}
+
+template <int H, typename T>
+hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack, const void* packT, float* grad,
+                      hipStream_t st) {
+    using BG = BwdGeom<H>;
+    BwdArgs a;
+    a.total = w.ray_off + w.N;
+    a.field_start = w.field_start;
+    a.perm = w.perm;
+    a.t_mid = w.t_mid;
+    a.ray = w.ray;
+    a.o = w.ro; a.d = w.rd;
+    a.dsigma = w.dsigma; a.drgb = w.drgb;
+    a.N = w.N; a.cap = w.cap;
+    a.F = s->mlp.n_fields;
+    a.P = (int)s->P;
+    a.c0 = s->mlp.center[0]; a.c1 = s->mlp.center[1]; a.c2 = s->mlp.center[2];
+    a.inv_h = 1.0f / s->mlp.half_extent;
+    a.pack = pack; a.packT = packT;
+    a.bias = s->bias;
+    a.grad = grad;
+    a.part = w.dw_part;
+    const size_t lds = (size_t)BG::ROWS * BG::PSTRIDE * sizeof(T);
+    static int nb = 0;
+    if (!nb) nb = resident(k_bwd<H, T>, lds);
+    hipLaunchKernelGGL((k_bwd<H, T>), dim3(nb), dim3(64 * BW), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dw_reduce, dim3((a.P + 255) / 256, a.F), dim3(256), 0, st, w.dw_part, grad, w.field_start,
+                       a.total, a.F, a.P, nb);
+    return hipGetLastError();
+}
+
+template <int H>
+hipError_t bwd_h(const r360_scene* s, const Workspace& w, int precision, float* grad, hipStream_t st) {
+    if (precision == R360_BF16) return bwd_launch<H, __bf16>(s, w, s->pack16_bf, s->packT_bf, grad, st);
+    if (precision == R360_FP16) return bwd_launch<H, _Float16>(s, w, s->pack16_h, s->packT_h, grad, st);
+    return bwd_launch<H, float>(s, w, s->pack16_f, s->packT_f, grad, st);
+}
+
+template <int H>
+hipError_t repack_bwd_h(r360_scene* s, const float* weights, hipStream_t st) {
+    using G = PackGeom<H>;
+    const int F = s->mlp.n_fields;
+    const int64_t n = (int64_t)F * (G::FRAGS16 > G::FRAGS_T ? G::FRAGS16 : G::FRAGS_T) * WAVE * 8;
+    hipLaunchKernelGGL(k_repack_bwd<H>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, weights, F, s->pack16_f,
+                       (__bf16*)s->packT_bf, (_Float16*)s->packT_h, s->packT_f);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 gradient-check forms: one block per ray, one thread per neuron,
+// activations in LDS, plain FP64 arithmetic; weight gradients with FP64
+// atomics. Small inputs only.
+// ---------------------------------------------------------------------------
+struct GcArgs {
+    const int32_t* off;
+    const float* t_mid;
+    const float* delta;
+    const int32_t* field;
+    const float* o;
+    const float* d;
+    int64_t N;
+    float c0, c1, c2, inv_h;
+    const double* w;
+    int P;
+    const double* grad_rgb;    // [3][N] (backward)
+    double* out;               // forward: rgb [3][N]; backward: grad [F][P]
+};
+
+constexpr int GC_MAXS = 256;
+
+template <int H>
+struct GcNet {
+    double gx[DXYZ], gd[DDIR], z1[H], h1[H], z2[H], h2[H], in3[H + DDIR], z3[H], h3[H], z4[3], zs;
+    double dz4[3], dh3[H], dz3[H], din3[H + DDIR], dh2[H], dz2[H], dh1[H], dz1[H], dzs;
+};
+
+__device__ double enc_value(const double* x, int k) {
+    if (k < 3) return x[k];
+    const int l = (k - 3) / 6, m = (k - 3) % 6;
+    const double r = ldexp(x[m % 3], l);
+    return m < 3 ? sinpi(r) : cospi(r);
+}
+
+// Forward of one sample by the block's threads (tid < H active for layers).
+template <int H>
+__device__ void gc_forward(GcNet<H>& n, const double* w, const double xh[3], const double dd[3], int tid) {
+    constexpr FieldLayout L{H};
+    for (int k = tid; k < DXYZ; k += 64) n.gx[k] = enc_value(xh, k);
+    for (int k = tid; k < DDIR; k += 64) n.gd[k] = enc_value(dd, k);
+    __syncthreads();
+    if (tid < H) {
+        double acc = w[L.b1() + tid];
+        for (int i = 0; i < DXYZ; ++i) acc += w[L.W1() + tid * DXYZ + i] * n.gx[i];
+        n.z1[tid] = acc; n.h1[tid] = acc > 0.0 ? acc : 0.0;
+    }
+    __syncthreads();
+    if (tid < H) {
+        double acc = w[L.b2() + tid];
+        for (int i = 0; i < H; ++i) acc += w[L.W2() + tid * H + i] * n.h1[i];
+        n.z2[tid] = acc; n.h2[tid] = acc > 0.0 ? acc : 0.0;
+    }
+    __syncthreads();
+    if (tid < H) {
+        double acc = w[L.bf() + tid];
+        for (int i = 0; i < H; ++i) acc += w[L.Wf() + tid * H + i] * n.h2[i];
+        n.in3[tid] = acc;
+    }
+    if (tid == 0) {
+        double acc = w[L.bs()];
+        for (int i = 0; i < H; ++i) acc += w[L.ws() + i] * n.h2[i];
+        n.zs = acc;
+    }
+    for (int k = tid; k < DDIR; k += 64) n.in3[H + k] = n.gd[k];
+    __syncthreads();
+    if (tid < H) {
+        double acc = w[L.b3() + tid];
+        for (int i = 0; i < H + DDIR; ++i) acc += w[L.W3() + tid * (H + DDIR) + i] * n.in3[i];
+        n.z3[tid] = acc; n.h3[tid] = acc > 0.0 ? acc : 0.0;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double acc = w[L.b4() + tid];
+        for (int i = 0; i < H; ++i) acc += w[L.W4() + tid * H + i] * n.h3[i];
+        n.z4[tid] = acc;
+    }
+    __syncthreads();
+}
+
+__device__ double softplus_d(double z) { return fmax(z, 0.0) + log1p(exp(-fabs(z))); }
+__device__ double sigmoid_d(double z) { return 1.0 / (1.0 + exp(-z)); }
+
+template <int H>
+__device__ void gc_inputs(const GcArgs& a, int64_t r, int j, double xh[3], double dd[3]) {
+    const float t = a.t_mid[j];
+    const float cc[3] = {a.c0, a.c1, a.c2};
+    for (int k = 0; k < 3; ++k) {
+        const float dk = a.d[k * a.N + r];
+        const float p = __builtin_fmaf(t, dk, a.o[k * a.N + r]);
+        xh[k] = (double)((p - cc[k]) * a.inv_h);
+        dd[k] = (double)dk;
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(64) void k_gc_forward(GcArgs a) {
+    __shared__ GcNet<H> n;
+    __shared__ double sig[GC_MAXS], col[GC_MAXS][3];
+    const int64_t r = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int s0 = a.off[r], s1 = a.off[r + 1];
+    for (int j = s0; j < s1; ++j) {
+        double xh[3], dd[3];
+        gc_inputs<H>(a, r, j, xh, dd);
+        gc_forward<H>(n, a.w + (int64_t)a.field[j] * a.P, xh, dd, tid);
+        if (tid == 0) {
+            sig[j - s0] = softplus_d(n.zs);
+            for (int c = 0; c < 3; ++c) col[j - s0][c] = sigmoid_d(n.z4[c]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double C[3] = {0, 0, 0}, S = 0.0;
+        for (int k = 0; k < s1 - s0; ++k) {
+            const double tau = sig[k] * (double)a.delta[s0 + k];
+            const double wgt = exp(-S) * (-expm1(-tau));
+            for (int c = 0; c < 3; ++c) C[c] += wgt * col[k][c];
+            S += tau;
+        }
+        for (int c = 0; c < 3; ++c) a.out[c * a.N + r] = C[c];
+    }
+}
+
+template <int H>
+__global__ __launch_bounds__(64) void k_gc_backward(GcArgs a) {
+    constexpr FieldLayout L{H};
+    __shared__ GcNet<H> n;
+    __shared__ double sig[GC_MAXS], col[GC_MAXS][3], dsig[GC_MAXS], dcol[GC_MAXS][3];
+    const int64_t r = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int s0 = a.off[r], s1 = a.off[r + 1];
+    for (int j = s0; j < s1; ++j) {
+        double xh[3], dd[3];
+        gc_inputs<H>(a, r, j, xh, dd);
+        gc_forward<H>(n, a.w + (int64_t)a.field[j] * a.P, xh, dd, tid);
+        if (tid == 0) {
+            sig[j - s0] = softplus_d(n.zs);
+            for (int c = 0; c < 3; ++c) col[j - s0][c] = sigmoid_d(n.z4[c]);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        // dL/dc_i = w_i g; dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - ((C - C_{<=i}) . g)]
+        const double g[3] = {a.grad_rgb[r], a.grad_rgb[a.N + r], a.grad_rgb[2 * a.N + r]};
+        const int n_s = s1 - s0;
+        double C[3] = {0, 0, 0}, S = 0.0;
+        for (int k = 0; k < n_s; ++k) {
+            const double tau = sig[k] * (double)a.delta[s0 + k];
+            const double wgt = exp(-S) * (-expm1(-tau));
+            for (int c = 0; c < 3; ++c) C[c] += wgt * col[k][c];
+            S += tau;
+        }
+        double Cle[3] = {0, 0, 0};
+        S = 0.0;
+        for (int k = 0; k < n_s; ++k) {
+            const double tau = sig[k] * (double)a.delta[s0 + k];
+            const double wgt = exp(-S) * (-expm1(-tau));
+            S += tau;
+            double cg = 0.0, rg = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                Cle[c] += wgt * col[k][c];
+                cg += col[k][c] * g[c];
+                rg += (C[c] - Cle[c]) * g[c];
+                dcol[k][c] = wgt * g[c];
+            }
+            dsig[k] = (double)a.delta[s0 + k] * (exp(-S) * cg - rg);
+        }
+    }
+    __syncthreads();
+    for (int j = s0; j < s1; ++j) {
+        const int k = j - s0;
+        double xh[3], dd[3];
+        gc_inputs<H>(a, r, j, xh, dd);
+        const double* w = a.w + (int64_t)a.field[j] * a.P;
+        double* gw = a.out + (int64_t)a.field[j] * a.P;
+        gc_forward<H>(n, w, xh, dd, tid);
+        if (tid < 3) {
+            const double s = sigmoid_d(n.z4[tid]);
+            n.dz4[tid] = dcol[k][tid] * s * (1.0 - s);
+        }
+        if (tid == 0) n.dzs = dsig[k] * sigmoid_d(n.zs);
+        __syncthreads();
+        if (tid < H) {
+            double acc = 0.0;
+            for (int o = 0; o < 3; ++o) {
+                acc += w[L.W4() + o * H + tid] * n.dz4[o];
+                atomicAdd(&gw[L.W4() + o * H + tid], n.dz4[o] * n.h3[tid]);
+            }
+            n.dh3[tid] = acc;
+            n.dz3[tid] = n.z3[tid] > 0.0 ? acc : 0.0;
+        }
+        if (tid < 3) atomicAdd(&gw[L.b4() + tid], n.dz4[tid]);
+        __syncthreads();
+        for (int i = tid; i < H + DDIR; i += 64) {
+            double acc = 0.0;
+            for (int o = 0; o < H; ++o) {
+                acc += w[L.W3() + o * (H + DDIR) + i] * n.dz3[o];
+                atomicAdd(&gw[L.W3() + o * (H + DDIR) + i], n.dz3[o] * n.in3[i]);
+            }
+            n.din3[i] = acc;
+        }
+        if (tid < H) atomicAdd(&gw[L.b3() + tid], n.dz3[tid]);
+        __syncthreads();
+        if (tid < H) {
+            double acc = w[L.ws() + tid] * n.dzs;
+            atomicAdd(&gw[L.ws() + tid], n.dzs * n.h2[tid]);
+            for (int o = 0; o < H; ++o) {
+                acc += w[L.Wf() + o * H + tid] * n.din3[o];
+                atomicAdd(&gw[L.Wf() + o * H + tid], n.din3[o] * n.h2[tid]);
+            }
+            n.dh2[tid] = acc;
+            n.dz2[tid] = n.z2[tid] > 0.0 ? acc : 0.0;
+            atomicAdd(&gw[L.bf() + tid], n.din3[tid]);
+        }
+        if (tid == 0) atomicAdd(&gw[L.bs()], n.dzs);
+        __syncthreads();
+        if (tid < H) {
+            double acc = 0.0;
+            for (int o = 0; o < H; ++o) {
+                acc += w[L.W2() + o * H + tid] * n.dz2[o];
+                atomicAdd(&gw[L.W2() + o * H + tid], n.dz2[o] * n.h1[tid]);
+            }
+            n.dh1[tid] = acc;
+            n.dz1[tid] = n.z1[tid] > 0.0 ? acc : 0.0;
+            atomicAdd(&gw[L.b2() + tid], n.dz2[tid]);
+        }
+        __syncthreads();
+        for (int i = tid; i < DXYZ; i += 64)
+            for (int o = 0; o < H; ++o) atomicAdd(&gw[L.W1() + o * DXYZ + i], n.dz1[o] * n.gx[i]);
+        if (tid < H) atomicAdd(&gw[L.b1() + tid], n.dz1[tid]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_zero_f64(double* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+GcArgs gc_args(const r360_scene* s, const Workspace& w, const double* w64) {
+    GcArgs a;
+    a.off = w.ray_off;
+    a.t_mid = w.t_mid;
+    a.delta = w.delta;
+    a.field = w.field;
+    a.o = w.ro; a.d = w.rd;
+    a.N = w.N;
+    a.c0 = s->mlp.center[0]; a.c1 = s->mlp.center[1]; a.c2 = s->mlp.center[2];
+    a.inv_h = 1.0f / s->mlp.half_extent;
+    a.w = w64;
+    a.P = (int)s->P;
+    a.grad_rgb = nullptr;
+    a.out = nullptr;
+    return a;
+}
+
+}  // namespace
+
+hipError_t launch_repack_bwd(r360_scene* s, const float* weights, hipStream_t st) {
+    return s->mlp.hidden == 32 ? repack_bwd_h<32>(s, weights, st) : repack_bwd_h<64>(s, weights, st);
+}
+
+hipError_t launch_mlp_backward(const r360_scene* s, const Workspace& w, int precision, float* grad, hipStream_t st) {
+    return s->mlp.hidden == 32 ? bwd_h<32>(s, w, precision, grad, st) : bwd_h<64>(s, w, precision, grad, st);
+}
+
+hipError_t launch_gradcheck_forward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,
+                                    double* rgb64, hipStream_t st) {
+    GcArgs a = gc_args(s, w, w64);
+    a.out = rgb64;
+    if (s->mlp.hidden == 32) hipLaunchKernelGGL(k_gc_forward<32>, dim3((unsigned)N), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL(k_gc_forward<64>, dim3((unsigned)N), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gradcheck_backward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,
+                                     const double* grad_rgb64, double* grad64, hipStream_t st) {
+    GcArgs a = gc_args(s, w, w64);
+    a.grad_rgb = grad_rgb64;
+    a.out = grad64;
+    const int64_t n = (int64_t)s->mlp.n_fields * s->P;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, grad64, n);
+    if (s->mlp.hidden == 32) hipLaunchKernelGGL(k_gc_backward<32>, dim3((unsigned)N), dim3(64), 0, st, a);
+    else hipLaunchKernelGGL(k_gc_backward<64>, dim3((unsigned)N), dim3(64), 0, st, a);
+    return hipGetLastError();
 }
 
 }  // namespace r360

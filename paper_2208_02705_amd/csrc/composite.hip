@@ -11,25 +11,61 @@ namespace r360 {
 
 namespace {
 
+// Each wave owns 64 consecutive rays, whose samples are one contiguous
+// range. The range is staged through LDS in chunks with coalesced loads;
+// each lane then walks its own ray's samples from LDS. (Walking them straight
+// from global memory would make every load instruction touch ~20 cache lines
+// and thrash L1.)
+constexpr int CCH = 512;                      // samples per staged chunk and wave
+
+struct Stage6 { float s[CCH], dl[CCH], t[CCH], r[CCH], g[CCH], b[CCH]; };
+
+__device__ __forceinline__ void stage_chunk(Stage6& L, int base, int end, int lane, int64_t cap,
+                                            const float* __restrict__ sigma, const float* __restrict__ rgb,
+                                            const float* __restrict__ t_mid, const float* __restrict__ delta) {
+    for (int k = lane; k < CCH && base + k < end; k += 64) {
+        const int i = base + k;
+        L.s[k] = sigma[i];
+        L.dl[k] = delta[i];
+        L.t[k] = t_mid ? t_mid[i] : 0.0f;
+        L.r[k] = rgb[i];
+        L.g[k] = rgb[cap + i];
+        L.b[k] = rgb[2 * cap + i];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ off, int64_t N, int64_t cap,
                                                    const float* __restrict__ sigma, const float* __restrict__ rgb,
                                                    const float* __restrict__ t_mid, const float* __restrict__ delta,
                                                    float* __restrict__ out_rgb, float* __restrict__ depth,
                                                    float* __restrict__ opacity) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    const int a = off[r], b = off[r + 1];
+    __shared__ Stage6 lds[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    Stage6& L = lds[wv];
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+    if (r0 >= N) return;
+    const int64_t r = r0 + lane;
+    const bool live = r < N;
+    const int wa = off[r0], wb = off[min(r0 + 64, N)];
+    const int a = live ? off[r] : 0, b = live ? off[r + 1] : 0;
     float logT = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f, A = 0.0f;
-    for (int i = a; i < b; ++i) {
-        const float tau = sigma[i] * delta[i];
-        const float w = expf(logT) * -expm1f(-tau);
-        c0 += w * rgb[i];
-        c1 += w * rgb[cap + i];
-        c2 += w * rgb[2 * cap + i];
-        D += w * t_mid[i];
-        A += w;
-        logT -= tau;
+    for (int base = wa; base < wb; base += CCH) {
+        stage_chunk(L, base, wb, lane, cap, sigma, rgb, t_mid, delta);
+        __builtin_amdgcn_wave_barrier();
+        const int lo = max(a, base) - base, hi = min(b, base + CCH) - base;
+        for (int k = lo; k < hi; ++k) {
+            const float tau = L.s[k] * L.dl[k];
+            const float w = expf(logT) * -expm1f(-tau);
+            c0 += w * L.r[k];
+            c1 += w * L.g[k];
+            c2 += w * L.b[k];
+            D += w * L.t[k];
+            A += w;
+            logT -= tau;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
+    if (!live) return;
     if (out_rgb) { out_rgb[r] = c0; out_rgb[N + r] = c1; out_rgb[2 * N + r] = c2; }
     if (depth) depth[r] = D;
     if (opacity) opacity[r] = A;
@@ -76,34 +112,61 @@ __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ pa
 // Backward of compositing. Pass 1 recomputes C; pass 2 repeats the same
 // accumulation so that C - C_{<=i} is a difference of identical partial sums:
 //   dL/dc_i = w_i g,  dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - ((C - C_{<=i}) . g)].
+// Both passes stage the wave's sample range through LDS as the forward does;
+// pass 2 writes the per-sample gradients back through LDS, coalesced.
 __global__ __launch_bounds__(256) void k_composite_bwd(const int32_t* __restrict__ off, int64_t N, int64_t cap,
                                                        const float* __restrict__ sigma, const float* __restrict__ rgb,
                                                        const float* __restrict__ delta, const float* __restrict__ grad,
                                                        float* __restrict__ dsigma, float* __restrict__ drgb) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    const int a = off[r], b = off[r + 1];
-    const float g0 = grad[r], g1 = grad[N + r], g2 = grad[2 * N + r];
+    __shared__ Stage6 lds[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    Stage6& L = lds[wv];
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+    if (r0 >= N) return;
+    const int64_t r = r0 + lane;
+    const bool live = r < N;
+    const int wa = off[r0], wb = off[min(r0 + 64, N)];
+    const int a = live ? off[r] : 0, b = live ? off[r + 1] : 0;
+    const float g0 = live ? grad[r] : 0.0f, g1 = live ? grad[N + r] : 0.0f, g2 = live ? grad[2 * N + r] : 0.0f;
     float logT = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    for (int i = a; i < b; ++i) {
-        const float tau = sigma[i] * delta[i];
-        const float w = expf(logT) * -expm1f(-tau);
-        C0 += w * rgb[i]; C1 += w * rgb[cap + i]; C2 += w * rgb[2 * cap + i];
-        logT -= tau;
+    for (int base = wa; base < wb; base += CCH) {
+        stage_chunk(L, base, wb, lane, cap, sigma, rgb, nullptr, delta);
+        __builtin_amdgcn_wave_barrier();
+        const int lo = max(a, base) - base, hi = min(b, base + CCH) - base;
+        for (int k = lo; k < hi; ++k) {
+            const float tau = L.s[k] * L.dl[k];
+            const float w = expf(logT) * -expm1f(-tau);
+            C0 += w * L.r[k]; C1 += w * L.g[k]; C2 += w * L.b[k];
+            logT -= tau;
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
     logT = 0.0f;
-    for (int i = a; i < b; ++i) {
-        const float tau = sigma[i] * delta[i];
-        const float w = expf(logT) * -expm1f(-tau);
-        const float r0 = rgb[i], r1 = rgb[cap + i], r2 = rgb[2 * cap + i];
-        P0 += w * r0; P1 += w * r1; P2 += w * r2;
-        logT -= tau;
-        const float Tn = expf(logT);
-        const float cg = r0 * g0 + r1 * g1 + r2 * g2;
-        const float rg = (C0 - P0) * g0 + (C1 - P1) * g1 + (C2 - P2) * g2;
-        dsigma[i] = delta[i] * (Tn * cg - rg);
-        drgb[i] = w * g0; drgb[cap + i] = w * g1; drgb[2 * cap + i] = w * g2;
+    for (int base = wa; base < wb; base += CCH) {
+        stage_chunk(L, base, wb, lane, cap, sigma, rgb, nullptr, delta);
+        __builtin_amdgcn_wave_barrier();
+        const int lo = max(a, base) - base, hi = min(b, base + CCH) - base;
+        for (int k = lo; k < hi; ++k) {
+            const float tau = L.s[k] * L.dl[k];
+            const float w = expf(logT) * -expm1f(-tau);
+            const float q0 = L.r[k], q1 = L.g[k], q2 = L.b[k];
+            P0 += w * q0; P1 += w * q1; P2 += w * q2;
+            logT -= tau;
+            const float Tn = expf(logT);
+            const float cg = q0 * g0 + q1 * g1 + q2 * g2;
+            const float rg = (C0 - P0) * g0 + (C1 - P1) * g1 + (C2 - P2) * g2;
+            // results overwrite the staged inputs of this sample (read above)
+            L.s[k] = L.dl[k] * (Tn * cg - rg);
+            L.r[k] = w * g0; L.g[k] = w * g1; L.b[k] = w * g2;
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int k = lane; k < CCH && base + k < wb; k += 64) {
+            const int i = base + k;
+            dsigma[i] = L.s[k];
+            drgb[i] = L.r[k]; drgb[cap + i] = L.g[k]; drgb[2 * cap + i] = L.b[k];
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -124,8 +187,10 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+inline unsigned nwblk(int64_t n) { return (unsigned)((n + 255) / 256); }   // 4 waves x 64 rays per block
+
 hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity, hipStream_t st) {
-    hipLaunchKernelGGL(k_composite, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.sigma, w.rgb, w.t_mid,
+    hipLaunchKernelGGL(k_composite, dim3(nwblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.sigma, w.rgb, w.t_mid,
                        w.delta, rgb, depth, opacity);
     return hipGetLastError();
 }
@@ -139,7 +204,7 @@ hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, con
 }
 
 hipError_t launch_composite_backward(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st) {
-    hipLaunchKernelGGL(k_composite_bwd, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.sigma, w.rgb,
+    hipLaunchKernelGGL(k_composite_bwd, dim3(nwblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.sigma, w.rgb,
                        w.delta, grad_rgb, w.dsigma, w.drgb);
     return hipGetLastError();
 }

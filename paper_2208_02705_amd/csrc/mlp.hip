@@ -32,61 +32,8 @@ namespace r360 {
 
 namespace {
 
-// Column of the previous layer's output that k slot (ks, e) of lane group g
-// carries, for a hidden-width input. 16-bit: k-step ks covers the two 16-row
-// tiles 2ks and 2ks+1; element e < 4 comes from tile 2ks, row 4g + e.
-__host__ __device__ constexpr int hidden_col16(int ks, int g, int e) { return 16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3); }
-// FP32: k-step ks is register ks%4 of tile ks/4.
+// FP32 forward: k-step ks is register ks%4 of tile ks/4.
 __host__ __device__ constexpr int hidden_col32(int ks, int g) { return 16 * (ks >> 2) + 4 * g + (ks & 3); }
-
-enum Layer { LY_L1 = 0, LY_L2, LY_HD, LY_L3, LY_L4 };
-
-// Canonical weight (or 0) for output row `row` of layer `ly` and the input
-// described either as a hidden column (col >= 0) or an encoding feature.
-template <int H>
-__device__ float canon_weight(const float* w, int ly, int row, bool is_enc, int feat_or_col) {
-    constexpr FieldLayout L{H};
-    switch (ly) {
-    case LY_L1:
-        if (feat_or_col == SLOT_ZERO) return 0.0f;
-        return feat_or_col == SLOT_BIAS ? w[L.b1() + row] : w[L.W1() + row * DXYZ + feat_or_col];
-    case LY_L2:
-        return w[L.W2() + row * H + feat_or_col];
-    case LY_HD:
-        if (row < H) return w[L.Wf() + row * H + feat_or_col];
-        if (row == H) return w[L.ws() + feat_or_col];
-        return 0.0f;
-    case LY_L3:
-        if (!is_enc) return w[L.W3() + row * (H + DDIR) + feat_or_col];
-        if (feat_or_col == SLOT_ZERO) return 0.0f;
-        return feat_or_col == SLOT_BIAS ? w[L.b3() + row] : w[L.W3() + row * (H + DDIR) + H + feat_or_col];
-    default:
-        return row < 3 ? w[L.W4() + row * H + feat_or_col] : 0.0f;
-    }
-}
-
-// Layer, output tile and k-step of 16-bit fragment `fr`.
-template <int H>
-__device__ void frag16(int fr, int& ly, int& ot, int& ks, int& nks) {
-    using G = PackGeom<H>;
-    if (fr < G::F_L1) { ly = LY_L1; nks = 2; }
-    else if ((fr -= G::F_L1) < G::F_L2) { ly = LY_L2; nks = G::KH16; }
-    else if ((fr -= G::F_L2) < G::F_HD) { ly = LY_HD; nks = G::KH16; }
-    else if ((fr -= G::F_HD) < G::F_L3) { ly = LY_L3; nks = G::KH16 + 1; }
-    else { fr -= G::F_L3; ly = LY_L4; nks = G::KH16; }
-    ot = fr / nks;
-    ks = fr % nks;
-}
-
-template <int H>
-__device__ float packed_source16(const float* w, int fr, int lane, int e) {
-    int ly, ot, ks, nks;
-    frag16<H>(fr, ly, ot, ks, nks);
-    const int g = lane >> 4, row = 16 * ot + (lane & 15);
-    if (ly == LY_L1) return canon_weight<H>(w, ly, row, true, pe_slot_feature(g, 8 * ks + e));
-    if (ly == LY_L3 && ks == PackGeom<H>::KH16) return canon_weight<H>(w, ly, row, true, dir_slot_feature(g, e));
-    return canon_weight<H>(w, ly, row, false, hidden_col16(ks, g, e));
-}
 
 template <int H>
 __device__ void step32(int st, int& ly, int& ot, int& ks) {
@@ -213,16 +160,36 @@ __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) 
 
 __device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
-// Encoding inputs of sample `orig`: xhat (FP32 spec) and d.
-__device__ __forceinline__ void sample_inputs(const FwdArgs& a, int orig, float xh[3], float dv[3]) {
-    const float t = a.t_mid[orig];
-    const int64_t r = a.ray[orig];
-    const float o[3] = {a.o[r], a.o[a.N + r], a.o[2 * a.N + r]};
-    dv[0] = a.d[r]; dv[1] = a.d[a.N + r]; dv[2] = a.d[2 * a.N + r];
+// Per-sample inputs, gathered in three dependent steps (sorted position ->
+// sample index -> ray); the chunk loops issue the steps for the next chunk
+// while the current one computes.
+struct SampleIn {
+    int orig;
+    float t;
+    int64_t ray;
+    float o[3], d[3];
+};
+
+__device__ __forceinline__ void fetch_index(const FwdArgs& a, int pos, int fend, int j, SampleIn& s) {
+    const int jp = pos + j;
+    s.orig = a.perm[jp < fend ? jp : pos];
+}
+__device__ __forceinline__ void fetch_sample(const FwdArgs& a, SampleIn& s) {
+    s.t = a.t_mid[s.orig];
+    s.ray = a.ray[s.orig];
+}
+__device__ __forceinline__ void fetch_ray(const FwdArgs& a, SampleIn& s) {
+    const int64_t r = s.ray;
+    s.o[0] = a.o[r]; s.o[1] = a.o[a.N + r]; s.o[2] = a.o[2 * a.N + r];
+    s.d[0] = a.d[r]; s.d[1] = a.d[a.N + r]; s.d[2] = a.d[2 * a.N + r];
+}
+
+// Encoding input xhat = (fma(t, d, o) - center) / half_extent (FP32 spec).
+__device__ __forceinline__ void sample_xhat(const FwdArgs& a, const SampleIn& s, float xh[3]) {
     const float cc[3] = {a.c0, a.c1, a.c2};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float p = __builtin_fmaf(t, dv[k], o[k]);
+        const float p = __builtin_fmaf(s.t, s.d[k], s.o[k]);
         xh[k] = (p - cc[k]) * a.inv_h;
     }
 }
@@ -269,12 +236,19 @@ __global__ __launch_bounds__(256) void k_fwd16(FwdArgs a) {
             for (int ks = 0; ks < KH; ++ks) w4[ks] = p[(k++) * WAVE];
         }
         const f32x4* bias = reinterpret_cast<const f32x4*>(a.bias + (int64_t)f * G::BIAS_FLOATS) + g;
+        SampleIn nx;
+        fetch_index(a, pos, fend, j, nx);
+        fetch_sample(a, nx);
+        fetch_ray(a, nx);
         for (; pos < fend; pos += 16) {
-            const int jp = pos + j;
-            const bool valid = jp < fend;
-            const int orig = a.perm[valid ? jp : pos];
-            float xh[3], dv[3];
-            sample_inputs(a, orig, xh, dv);
+            const SampleIn cur = nx;
+            const bool valid = pos + j < fend;
+            const int orig = cur.orig;
+            const bool more = pos + 16 < fend;
+            if (more) fetch_index(a, pos + 16, fend, j, nx);
+            float xh[3];
+            sample_xhat(a, cur, xh);
+            const float dv[3] = {cur.d[0], cur.d[1], cur.d[2]};
             float pe[16];
             pe_position(g, xh, pe);
             const V8 x0 = to8<T>(pe), x1 = to8<T>(pe + 8);
@@ -289,6 +263,7 @@ __global__ __launch_bounds__(256) void k_fwd16(FwdArgs a) {
             V8 hb[KH];
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) hb[ks] = handoff<T, true>(acc[2 * ks], acc[2 * ks + 1]);
+            if (more) fetch_sample(a, nx);
             // L2
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
@@ -308,6 +283,7 @@ __global__ __launch_bounds__(256) void k_fwd16(FwdArgs a) {
             const float zs = acc[NT][0];
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) hb[ks] = handoff<T, false>(acc[2 * ks], acc[2 * ks + 1]);
+            if (more) fetch_ray(a, nx);
             float dpe[8];
             pe_direction(g, dv, dpe);
             const V8 xd = to8<T>(dpe);
@@ -357,12 +333,25 @@ __global__ __launch_bounds__(256) void k_fwd32(FwdArgs a) {
         for (int i = threadIdx.x; i < (G::STEPS32 / 4) * WAVE; i += 256) lw[i] = src[i];
         for (int i = threadIdx.x; i < G::BIAS_FLOATS; i += 256) lbias[i] = a.bias[(int64_t)f * G::BIAS_FLOATS + i];
         __syncthreads();
+        SampleIn nx;
+        if (pos + 16 * wv < fend) {
+            fetch_index(a, pos + 16 * wv, fend, j, nx);
+            fetch_sample(a, nx);
+            fetch_ray(a, nx);
+        }
         for (int c = pos + 16 * wv; c < fend; c += 64) {
-            const int jp = c + j;
-            const bool valid = jp < fend;
-            const int orig = a.perm[valid ? jp : c];
-            float xh[3], dv[3];
-            sample_inputs(a, orig, xh, dv);
+            const SampleIn cur = nx;
+            const bool valid = c + j < fend;
+            const int orig = cur.orig;
+            const bool more = c + 64 < fend;
+            if (more) {
+                fetch_index(a, c + 64, fend, j, nx);
+                fetch_sample(a, nx);
+                fetch_ray(a, nx);
+            }
+            float xh[3];
+            sample_xhat(a, cur, xh);
+            const float dv[3] = {cur.d[0], cur.d[1], cur.d[2]};
             float pe[16];
             pe_position(g, xh, pe);
             const float4* p = lw + lane;

@@ -76,20 +76,23 @@ constexpr double PI_D = 3.14159265358979323846;
 constexpr double pw(double x, int k) { return k == 0 ? 1.0 : x * pw(x, k - 1); }
 constexpr double fact(int k) { return k <= 1 ? 1.0 : k * fact(k - 1); }
 constexpr float TS(int k) { return (float)(((k / 2) % 2 ? -1.0 : 1.0) * pw(PI_D, k) / fact(k)); }
+// evaluated at compile time (constexpr variables), never at run time
+constexpr float kS1 = TS(1), kS3 = TS(3), kS5 = TS(5), kS7 = TS(7), kS9 = TS(9);
+constexpr float kC2 = TS(2), kC4 = TS(4), kC6 = TS(6), kC8 = TS(8), kC10 = TS(10);
 
 __device__ __forceinline__ void sincospi(float x, float& s, float& c) {
     const float n = __builtin_rintf(x + x);
     const float f = __builtin_fmaf(n, -0.5f, x);
     const float f2 = f * f;
-    float ps = __builtin_fmaf(f2, TS(9), TS(7));
-    ps = __builtin_fmaf(f2, ps, TS(5));
-    ps = __builtin_fmaf(f2, ps, TS(3));
-    ps = __builtin_fmaf(f2, ps, TS(1));
+    float ps = __builtin_fmaf(f2, kS9, kS7);
+    ps = __builtin_fmaf(f2, ps, kS5);
+    ps = __builtin_fmaf(f2, ps, kS3);
+    ps = __builtin_fmaf(f2, ps, kS1);
     ps = ps * f;
-    float pc = __builtin_fmaf(f2, TS(10), TS(8));
-    pc = __builtin_fmaf(f2, pc, TS(6));
-    pc = __builtin_fmaf(f2, pc, TS(4));
-    pc = __builtin_fmaf(f2, pc, TS(2));
+    float pc = __builtin_fmaf(f2, kC10, kC8);
+    pc = __builtin_fmaf(f2, pc, kC6);
+    pc = __builtin_fmaf(f2, pc, kC4);
+    pc = __builtin_fmaf(f2, pc, kC2);
     pc = __builtin_fmaf(f2, pc, 1.0f);
     const int q = (int)n & 3;
     float sv = (q & 1) ? pc : ps;
@@ -169,7 +172,71 @@ struct PackGeom {
     // biases added through the accumulator (L2, HEAD, L4): 16 floats per tile
     static constexpr int BIAS_TILES = NT + (NT + 1) + 1;
     static constexpr int BIAS_FLOATS = BIAS_TILES * 16;
+    // backward: transposed A fragments (K = 32 per k-step) for the input
+    // gradients: W4^T (k over the 16 padded rgb rows + 16 zero rows), W3^T
+    // restricted to the feature inputs, [Wf ; ws]^T (k over the H + 16 head
+    // rows, padded to whole k-steps) and W2^T
+    static constexpr int KHD = (NT + 2) / 2;          // k-steps over the head's NT+1 tiles
+    static constexpr int T_L4 = NT;
+    static constexpr int T_L3 = NT * KH16;
+    static constexpr int T_HD = NT * KHD;
+    static constexpr int T_L2 = NT * KH16;
+    static constexpr int FRAGS_T = T_L4 + T_L3 + T_HD + T_L2;
 };
+
+// Column of the previous layer's output that k slot (ks, e) of lane group g
+// carries, for a hidden-width input. 16-bit: k-step ks covers the two 16-row
+// tiles 2ks and 2ks+1; element e < 4 comes from tile 2ks, row 4g + e.
+__host__ __device__ constexpr int hidden_col16(int ks, int g, int e) { return 16 * (2 * ks + (e >> 2)) + 4 * g + (e & 3); }
+
+enum Layer { LY_L1 = 0, LY_L2, LY_HD, LY_L3, LY_L4 };
+
+// Canonical weight (or 0) for output row `row` of layer `ly` and the input
+// described either as a hidden column (col >= 0) or an encoding feature.
+template <int H>
+__device__ float canon_weight(const float* w, int ly, int row, bool is_enc, int feat_or_col) {
+    constexpr FieldLayout L{H};
+    switch (ly) {
+    case LY_L1:
+        if (feat_or_col == SLOT_ZERO) return 0.0f;
+        return feat_or_col == SLOT_BIAS ? w[L.b1() + row] : w[L.W1() + row * DXYZ + feat_or_col];
+    case LY_L2:
+        return w[L.W2() + row * H + feat_or_col];
+    case LY_HD:
+        if (row < H) return w[L.Wf() + row * H + feat_or_col];
+        if (row == H) return w[L.ws() + feat_or_col];
+        return 0.0f;
+    case LY_L3:
+        if (!is_enc) return w[L.W3() + row * (H + DDIR) + feat_or_col];
+        if (feat_or_col == SLOT_ZERO) return 0.0f;
+        return feat_or_col == SLOT_BIAS ? w[L.b3() + row] : w[L.W3() + row * (H + DDIR) + H + feat_or_col];
+    default:
+        return row < 3 ? w[L.W4() + row * H + feat_or_col] : 0.0f;
+    }
+}
+
+// Layer, output tile and k-step of 16-bit fragment `fr`.
+template <int H>
+__device__ void frag16(int fr, int& ly, int& ot, int& ks, int& nks) {
+    using G = PackGeom<H>;
+    if (fr < G::F_L1) { ly = LY_L1; nks = 2; }
+    else if ((fr -= G::F_L1) < G::F_L2) { ly = LY_L2; nks = G::KH16; }
+    else if ((fr -= G::F_L2) < G::F_HD) { ly = LY_HD; nks = G::KH16; }
+    else if ((fr -= G::F_HD) < G::F_L3) { ly = LY_L3; nks = G::KH16 + 1; }
+    else { fr -= G::F_L3; ly = LY_L4; nks = G::KH16; }
+    ot = fr / nks;
+    ks = fr % nks;
+}
+
+template <int H>
+__device__ float packed_source16(const float* w, int fr, int lane, int e) {
+    int ly, ot, ks, nks;
+    frag16<H>(fr, ly, ot, ks, nks);
+    const int g = lane >> 4, row = 16 * ot + (lane & 15);
+    if (ly == LY_L1) return canon_weight<H>(w, ly, row, true, pe_slot_feature(g, 8 * ks + e));
+    if (ly == LY_L3 && ks == PackGeom<H>::KH16) return canon_weight<H>(w, ly, row, true, dir_slot_feature(g, e));
+    return canon_weight<H>(w, ly, row, false, hidden_col16(ks, g, e));
+}
 
 }  // namespace r360
 
@@ -185,6 +252,10 @@ struct r360_scene {
     void* pack16_h;          // [F][FRAGS16][64][8] f16
     float* pack32;           // [F][STEPS32/4][64][4] f32
     float* bias;             // [F][BIAS_FLOATS]
+    float* pack16_f;         // [F][FRAGS16][64][8] f32: the 16-bit fragment layout in FP32 (backward)
+    void* packT_bf;          // [F][FRAGS_T][64][8] bf16 transposed fragments (backward)
+    void* packT_h;           // [F][FRAGS_T][64][8] f16
+    float* packT_f;          // [F][FRAGS_T][64][8] f32
     int device;
 };
 
@@ -226,7 +297,7 @@ struct Workspace {
 constexpr int ROUTE_BLOCKS = 1024;        // 4 waves each
 constexpr int ROUTE_WAVES = ROUTE_BLOCKS * 4;
 constexpr int SCAN_TILE = 4096;           // elements per scan block (1024 threads x 4)
-constexpr int DW_SLOTS = 512;             // backward work groups with private gradient partials
+constexpr int DW_SLOTS = 1024;            // two gradient partial slots per backward block
 
 Workspace carve(void* base, int64_t N, int64_t cap, int F, int64_t P);
 
@@ -259,6 +330,7 @@ hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64
                          int16_t* labels, hipStream_t st);
 hipError_t launch_route(const Workspace& w, int F, hipStream_t st);
 hipError_t launch_repack(r360_scene* s, const float* weights, hipStream_t st);
+hipError_t launch_repack_bwd(r360_scene* s, const float* weights, hipStream_t st);
 hipError_t launch_mlp_forward(const r360_scene* s, const Workspace& w, int precision, hipStream_t st);
 hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
                             hipStream_t st);

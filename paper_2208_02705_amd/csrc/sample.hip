@@ -63,9 +63,30 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 // counts. Per step only the crossed axis's next-plane distance changes; the
 // others are reused (their plane index did not change, so the recomputation
 // would give the same bits).
-template <bool FILL>
-__device__ int traverse(const DdaParams& P, const float o[3], const float d[3], int64_t base, int32_t ray_id,
-                        float* t_mid, float* delta, int32_t* ray, int32_t* field, int32_t* voxel_out) {
+// Where emitted samples go: nowhere (count pass), straight to the global
+// arrays, or to the wave's LDS window (packed lane << 16 | field).
+struct CountSink {
+    __device__ void emit(int, float, float, int, int64_t) {}
+};
+struct GlobalSink {
+    int64_t base; int32_t ray_id;
+    float *t_mid, *delta; int32_t *ray, *field, *voxel;
+    __device__ void emit(int k, float tm, float dl, int lab, int64_t lin) {
+        const int64_t j = base + k;
+        t_mid[j] = tm; delta[j] = dl; ray[j] = ray_id; field[j] = lab;
+        if (voxel) voxel[j] = (int32_t)lin;
+    }
+};
+struct LdsSink {
+    int pos; int lane;
+    float *t_mid, *delta; int32_t* tag;
+    __device__ void emit(int k, float tm, float dl, int lab, int64_t) {
+        t_mid[pos + k] = tm; delta[pos + k] = dl; tag[pos + k] = (lane << 16) | lab;
+    }
+};
+
+template <class Sink>
+__device__ int traverse(const DdaParams& P, const float o[3], const float d[3], Sink& sink) {
     const float INF = __builtin_inff();
     const int n[3] = {P.n0, P.n1, P.n2};
     const float lo[3] = {P.lo0, P.lo1, P.lo2};
@@ -117,14 +138,7 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         const float t_out = mn(tna, t1);
         const int lab = P.labels[lin];
         if (t_out > t_in && lab >= 0) {
-            if constexpr (FILL) {
-                const int64_t j = base + count;
-                t_mid[j] = (t_in + t_out) * 0.5f;
-                delta[j] = t_out - t_in;
-                ray[j] = ray_id;
-                field[j] = lab;
-                if (voxel_out) voxel_out[j] = (int32_t)lin;
-            }
+            sink.emit(count, (t_in + t_out) * 0.5f, t_out - t_in, lab, lin);
             if (++count == P.max_samples) break;
         }
         if (!(tna < t1)) break;
@@ -162,20 +176,51 @@ __global__ __launch_bounds__(256) void k_count(RaySource src, DdaParams P, int64
 #pragma unroll
         for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
     }
-    cnt[r] = traverse<false>(P, o, d, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
+    CountSink sink;
+    cnt[r] = traverse(P, o, d, sink);
 }
 
-// Pass 2: the same traversal writes the samples at the ray's offset.
+// Pass 2: the same traversal writes the samples at the ray's offset. The 64
+// rays of a wave own one contiguous output range; when it fits the wave's LDS
+// window the samples are emitted there and copied out with coalesced stores,
+// otherwise (and when voxel ids are requested) they go straight to memory.
+constexpr int FILL_WIN = 1024;
+
 __global__ __launch_bounds__(256) void k_fill(DdaParams P, int64_t N, const float* __restrict__ o_in,
                                               const float* __restrict__ d_in, const int32_t* __restrict__ off,
                                               float* __restrict__ t_mid, float* __restrict__ delta,
                                               int32_t* __restrict__ ray, int32_t* __restrict__ field,
                                               int32_t* __restrict__ voxel) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    const float o[3] = {o_in[r], o_in[N + r], o_in[2 * N + r]};
-    const float d[3] = {d_in[r], d_in[N + r], d_in[2 * N + r]};
-    traverse<true>(P, o, d, off[r], (int32_t)r, t_mid, delta, ray, field, voxel);
+    __shared__ float l_t[4][FILL_WIN], l_d[4][FILL_WIN];
+    __shared__ int32_t l_tag[4][FILL_WIN];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+    if (r0 >= N) return;
+    const int64_t r = r0 + lane;
+    const bool live = r < N;
+    const int wa = off[r0], wb = off[min(r0 + 64, N)];
+    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 0.f};
+    if (live) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) { o[a] = o_in[a * N + r]; d[a] = d_in[a * N + r]; }
+    }
+    if (wb - wa <= FILL_WIN && voxel == nullptr) {
+        if (live) {
+            LdsSink sink{off[r] - wa, lane, l_t[wv], l_d[wv], l_tag[wv]};
+            traverse(P, o, d, sink);
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int k = lane; k < wb - wa; k += 64) {
+            const int tag = l_tag[wv][k];
+            t_mid[wa + k] = l_t[wv][k];
+            delta[wa + k] = l_d[wv][k];
+            ray[wa + k] = (int32_t)(r0 + (tag >> 16));
+            field[wa + k] = tag & 0xFFFF;
+        }
+    } else if (live) {
+        GlobalSink sink{off[r], (int32_t)r, t_mid, delta, ray, field, voxel};
+        traverse(P, o, d, sink);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -303,8 +348,8 @@ hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, co
     if (e != hipSuccess) return e;
     const float* o = src.mode == RAYS_GIVEN ? src.o : w.o;
     const float* d = src.mode == RAYS_GIVEN ? src.d : w.d;
-    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(256), 0, st, p, N, o, d, w.ray_off, w.t_mid, w.delta, w.ray, w.field,
-                       voxel_out);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(N, 256)), dim3(256), 0, st, p, N, o, d, w.ray_off, w.t_mid, w.delta,
+                       w.ray, w.field, voxel_out);
     return hipGetLastError();
 }
 

@@ -276,6 +276,19 @@ def adam_step(w, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float
                                _stream()))
 
 
+def profile_enable(on: bool = True):
+    """Per-stage HIP-event timing inside the library (see r360_profile_enable)."""
+    check(lib().r360_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """{stage: (milliseconds, launches)} since the previous read."""
+    ms = (C.c_double * _lib.NSTAGES)()
+    cnt = (C.c_int32 * _lib.NSTAGES)()
+    check(lib().r360_profile_read(ms, cnt))
+    return {name: (ms[k], cnt[k]) for k, name in enumerate(_lib.STAGES)}
+
+
 def lr_at(step: int, total: int, lr0: float = 1e-3, lr1: float = 5e-5) -> float:
     """Exponential decay from lr0 to lr1 over `total` steps (Sec. 6.3)."""
     return lr0 * (lr1 / lr0) ** (min(step, total) / max(total, 1))

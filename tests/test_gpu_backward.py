@@ -1,0 +1,154 @@
+"""GPU backward path (compositing backward + field-MLP backward) against the
+FP64 oracle's analytic gradient, FP64 finite differences (GPU FP64
+gradient-check forms under torch.autograd.gradcheck), determinism, Adam.
+
+Gradient tolerances are stated relative to the largest gradient entry of
+the batch (entries of tiny magnitude carry no relative meaning):
+FP32 path 2e-4, BF16/FP16 paths 3e-2; see the design doc for the derivation.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FP32_GRAD = 2e-4
+X16_GRAD = 3e-2
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2208_02705_amd import render
+    return render
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rays(N, seed, lim=3.0):
+    rng = np.random.default_rng(seed)
+    o = rng.uniform(-lim, lim, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0)
+    return o, d.astype(np.float32), rng.uniform(0, 1, (3, N)).astype(np.float32)
+
+
+def _perturbed(sc, seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    return (sc.weights + rng.normal(size=sc.weights.shape).astype(np.float32) * scale).astype(np.float32)
+
+
+def _rel_err(g, ref):
+    return float(np.abs(g - ref).max() / np.abs(ref).max())
+
+
+@pytest.mark.parametrize("hidden", [32, 64])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_train_step_matches_oracle_gradient(R, orc, hidden, prec):
+    sc = synth.tiny_scene(8, 40 + hidden, p_occ=0.5, n_fields=5, hidden=hidden, max_samples=24)
+    w = _perturbed(sc, 1)
+    scene = R.Scene.from_synth(sc, weights=_t(w))
+    o, d, tgt = _rays(3000, 41)
+    loss, grad = R.train_step(scene, _t(o), _t(d), _t(tgt), precision=prec)
+    l_ref, g_ref, _ = orc.train_grad(sc, o, d, tgt, weights=w)
+    tol = FP32_GRAD if prec == "fp32" else X16_GRAD
+    assert abs(float(_np(loss)[0]) - l_ref) <= (1e-5 if prec == "fp32" else 1e-2) * l_ref
+    err = _rel_err(_np(grad), g_ref)
+    print(f"{prec} h{hidden}: max|dg|/max|g| = {err:.3g}")
+    assert err <= tol, err
+
+
+def test_train_step_headline_batch(R, orc):
+    """65,536 rays from 20 camera centres in the room scene, BF16 MLPs; the
+    full-batch gradient against the oracle's."""
+    import torch
+    sc = synth.scene_room()
+    scene = R.Scene.from_synth(sc)
+    W, H, N = 2048, 1024, 65536
+    cams = synth.camera_centres(sc, 20)
+    cam, u, v = synth.ray_draws(N, 20, W, H)
+    o = np.empty((3, N), np.float32); d = np.empty((3, N), np.float32)
+    for k in range(20):
+        sel = np.nonzero(cam == k)[0]
+        ok, dk = orc.equirect_rays(W, H, synth.c2w_at(cams[k]), v[sel].astype(np.int64) * W + u[sel])
+        o[:, sel] = ok; d[:, sel] = dk
+    tgt = np.random.default_rng(5).uniform(0, 1, (3, N)).astype(np.float32)
+    loss, grad = R.train_step(scene, _t(o), _t(d), _t(tgt), precision="bf16")
+    l_ref, g_ref, _ = orc.train_grad(sc, o, d, tgt)
+    err = _rel_err(_np(grad), g_ref)
+    print(f"headline batch bf16: loss {float(_np(loss)[0]):.6g} vs {l_ref:.6g}, grad rel err {err:.3g}")
+    assert abs(float(_np(loss)[0]) - l_ref) <= 1e-2 * l_ref
+    assert err <= X16_GRAD, err
+    loss32, grad32 = R.train_step(scene, _t(o), _t(d), _t(tgt), precision="fp32")
+    assert _rel_err(_np(grad32), g_ref) <= FP32_GRAD
+
+
+def test_backward_deterministic(R):
+    sc = synth.tiny_scene(8, 44, p_occ=0.5, n_fields=7, hidden=64, max_samples=32)
+    scene = R.Scene.from_synth(sc)
+    o, d, tgt = _rays(5000, 44)
+    g1 = _np(R.train_step(scene, _t(o), _t(d), _t(tgt), precision="bf16")[1])
+    g2 = _np(R.train_step(scene, _t(o), _t(d), _t(tgt), precision="bf16")[1])
+    assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+def test_autograd_function_matches_train_step(R, orc):
+    import torch
+    sc = synth.tiny_scene(8, 45, p_occ=0.5, n_fields=3, hidden=32, max_samples=16)
+    scene = R.Scene.from_synth(sc)
+    o, d, tgt = _rays(700, 45)
+    w = torch.from_numpy(sc.weights).cuda().requires_grad_(True)
+    rgb = R.RenderFunction.apply(w, scene, _t(o), _t(d), "fp32")
+    loss = ((rgb - _t(tgt)) ** 2).mean()
+    loss.backward()
+    _, g_ref, _ = orc.train_grad(sc, o, d, tgt)
+    assert _rel_err(_np(w.grad), g_ref) <= FP32_GRAD
+
+
+def test_fp64_gradcheck_against_finite_differences(R, orc):
+    """torch.autograd.gradcheck of the FP64 GPU forms (central differences of
+    the FP64 forward vs the FP64 analytic backward), on a 16-ray subset."""
+    import torch
+    sc = synth.tiny_scene(4, 46, p_occ=0.6, n_fields=2, hidden=32, max_samples=8)
+    scene = R.Scene.from_synth(sc)
+    o, d, _ = _rays(16, 46, lim=1.0)
+    w64 = torch.from_numpy(sc.weights.astype(np.float64) + np.random.default_rng(46).normal(
+        size=sc.weights.shape) * 0.05).cuda().requires_grad_(True)
+    to, td = _t(o), _t(d)
+
+    def f(w):
+        return R.GradcheckFunction.apply(w, scene, to, td)
+    assert torch.autograd.gradcheck(f, (w64,), eps=1e-7, atol=1e-6, rtol=1e-4, fast_mode=True, nondet_tol=1e-12)
+    # and the FP64 GPU gradient against the oracle's analytic gradient
+    rgb = f(w64)
+    g = torch.rand(3, 16, dtype=torch.float64, device="cuda")
+    (rgb * g).sum().backward()
+    # the oracle's loss is (1/3N) sum (C - C*)^2: choose C* so that its
+    # gradient 2 (C - C*)/(3N) equals g
+    C = _np(rgb.detach())
+    target = (C - _np(g) * (3 * 16) / 2).astype(np.float32)
+    _, g_ref, _ = orc.train_grad(sc, o, d, target, weights=w64.detach().cpu().numpy().astype(np.float32))
+    # the oracle sees FP32-rounded weights and targets: compare loosely
+    assert _rel_err(_np(w64.grad), g_ref) <= 1e-4
+
+
+def test_adam_matches_oracle(R, orc):
+    rng = np.random.default_rng(7)
+    n = 10000
+    w = rng.normal(size=n); g = rng.normal(size=n); m = np.zeros(n); v = np.zeros(n)
+    tw, tg, tm, tv = (_t(a.astype(np.float32)) for a in (w, g, m, v))
+    for step in (1, 2, 3):
+        R.adam_step(tw, tg, tm, tv, step, 1e-3)
+        orc.adam(w, g, m, v, step, 1e-3)
+    assert np.allclose(_np(tw), w, rtol=0, atol=1e-6)
