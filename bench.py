@@ -38,7 +38,20 @@ def parse():
     p.add_argument("--no-train", action="store_true")
     p.add_argument("--only", choices=["bf16", "fp32", "train"], default=None,
                    help="time only one leg (for profiler runs)")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run a plain device-to-device copy of MIB mebibytes (to calibrate HBM byte counters)")
     return p.parse_args()
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4}))
 
 
 def timed(fn, steps, warmup):
@@ -55,6 +68,9 @@ def timed(fn, steps, warmup):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1", "n_gpus": args.gpus}))
         sys.exit(2)

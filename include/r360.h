@@ -28,7 +28,7 @@
  *    R360_EHIP and r360_last_error() gives the runtime's text. Nothing aborts
  *    across this boundary.
  *  - Sizes: N * max_samples must stay below 2^31 per call (split larger ray
- *    sets into chunks); max_samples is in [1, 256]; n_fields in [1, 32767].
+ *    sets into chunks); max_samples is in [1, 256]; n_fields in [1, 16384].
  *  - Calls that share a workspace or a scene must not overlap on different
  *    streams.
  */
@@ -214,6 +214,46 @@ r360_status r360_gradcheck_backward(const r360_scene* scene, const double* weigh
                                     const float* d, int64_t N, const r360_render_opts* opts,
                                     const double* grad_rgb64, double* grad64, void* ws, size_t ws_bytes,
                                     void* stream);
+
+/* Global omnidirectional field stage (Sec. 3.2 360NeRF; architecture table
+ * of App. C), the density source of Sec. 4.1's occupancy estimation:
+ * n_samples samples per ray uniform in inverse depth over [near, far]
+ * (t_k = 1 / fma(s_k, 1/far, (1 - s_k)/near), s_k = k/(n_samples - 1);
+ * delta_k = t_{k+1} - t_k, the last 0), xhat = (fma(t, d, o) - center) /
+ * half_extent, encoding L = 10 / 4, eight ReLU layers of `width` with the
+ * encoding concatenated again at the fifth (the eighth linear), sigma =
+ * relu(ws h8 + bs), f = relu(Wf h8 + bf), colour sigmoid(W11 relu(W10 [f ;
+ * g(d)] + b10) + b11), compositing as Eq.4/Eq.5. Weights: FP32 canonical
+ * order W1 b1 ... W8 b8 ws bs Wf bf W10 b10 W11 b11 (W5 input [h4 ; g(x)]).
+ * The occupancy grid (grid_n, grid_lo, voxel) receives the per-sample max of
+ * sigma over the samples inside each cell. */
+typedef struct {
+    int32_t width;          /* 256 in the paper's table */
+    int32_t color_width;    /* 128 */
+    int32_t n_samples;      /* samples per ray, >= 2 */
+    float near_, far_;
+    float center[3];
+    float half_extent;
+    int32_t grid_n[3];
+    float grid_lo[3];
+    float voxel;
+} r360_global_desc;
+
+/* Canonical parameter count (595,844 at width 256, colour width 128). */
+int64_t r360_global_params(int32_t width, int32_t color_width);
+size_t r360_global_workspace_bytes(const r360_global_desc* desc, int64_t n_rays);
+
+/* Forward (BF16 MFMA GEMMs, FP32 accumulation) over N rays [3][N]; writes
+ * rgb_out [3][N] and depth_out [N] if not NULL; folds max(sigma) into
+ * occ_grid [n2][n1][n0] (FP32, caller-initialised; NULL skips). With
+ * target_rgb [3][N] also the loss (loss[0], L = 1/(3N) sum (C - C*)^2) and
+ * its gradient w.r.t. all weights, grad [P] FP32 (overwritten). Sizes: width
+ * and color_width multiples of 32; N * n_samples a multiple of 2048 when a
+ * target is given. */
+r360_status r360_global_field_step(const r360_global_desc* desc, const float* weights, const float* o,
+                                   const float* d, int64_t N, const float* target_rgb, float* loss, float* grad,
+                                   float* rgb_out, float* depth_out, float* occ_grid, void* ws, size_t ws_bytes,
+                                   void* stream);
 
 /* Optional per-stage timing for benchmarking: when enabled, every entry
  * point records a HIP event pair around each stage of its launch sequence on

@@ -27,13 +27,27 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-pthread"]
 
 
-def build(force: bool = True) -> str:
-    """Compile oracle.cpp with g++ (no contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", *CXXFLAGS, _SRC, "-o", tmp])
-        os.replace(tmp, _LIB)
-    return _LIB
+def build(force: bool = True, out: Optional[str] = None, plant: int = 0) -> str:
+    """Compile oracle.cpp with g++ (no contraction, no fast-math). `plant`
+    (tests only) builds a copy with a deliberate mistake into `out`."""
+    target = out or _LIB
+    if force or not os.path.exists(target):
+        tmp = target + ".tmp"
+        extra = [f"-DORC_PLANT={plant}"] if plant else []
+        subprocess.check_call(["g++", *CXXFLAGS, *extra, _SRC, "-o", tmp])
+        os.replace(tmp, target)
+    return target
+
+
+def use_library(path: Optional[str]):
+    """Point this module at another build of the oracle (tests only); None
+    restores the default build."""
+    global _lib, _LIB_OVERRIDE
+    _LIB_OVERRIDE = path
+    _lib = None
+
+
+_LIB_OVERRIDE: Optional[str] = None
 
 
 class OrcScene(C.Structure):
@@ -56,9 +70,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = _LIB_OVERRIDE or _LIB
+        if not os.path.exists(path):
             build()
-        L = C.CDLL(_LIB)
+        L = C.CDLL(path)
         vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
         sig = {
             "orc_equirect_lut": (None, [C.c_int, C.c_int, vp, vp, vp, vp]),

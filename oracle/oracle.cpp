@@ -33,6 +33,12 @@
 #include <algorithm>
 #include <limits>
 
+// Test-only switch: the mutation tests rebuild this file with ORC_PLANT = k
+// to plant a known mistake and check that the pins catch it. 0 = none.
+#ifndef ORC_PLANT
+#define ORC_PLANT 0
+#endif
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -111,7 +117,7 @@ int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) 
     const float INF = std::numeric_limits<float>::infinity();
     float inv[3], hi[3];
     bool active[3];
-    float t0 = s.near_, t1 = s.far_;
+    float t0 = s.near_, t1 = ORC_PLANT == 9 ? INF : s.far_;
     for (int a = 0; a < 3; ++a) {
         hi[a] = s.lo[a] + (float)s.n[a] * s.voxel;
         active[a] = d[a] != 0.0f;
@@ -155,7 +161,7 @@ int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) 
         float t_out = std::min(tn[am], t1);
         int64_t lin = idx[0] + (int64_t)s.n[0] * (idx[1] + (int64_t)s.n[1] * idx[2]);
         if (t_out > t_in && s.occ[lin] > s.threshold && s.field[lin] >= 0) {
-            out[count].t_mid = (t_in + t_out) * 0.5f;
+            out[count].t_mid = ORC_PLANT == 8 ? t_out : (t_in + t_out) * 0.5f;
             out[count].delta = t_out - t_in;
             out[count].voxel = (int32_t)lin;
             out[count].field = s.field[lin];
@@ -189,8 +195,8 @@ void encode(const double x[3], int L, double* out) {
     out[0] = x[0]; out[1] = x[1]; out[2] = x[2];
     for (int l = 0; l < L; ++l) {
         for (int c = 0; c < 3; ++c) {
-            double r = std::ldexp(x[c], l);   // 2^l x, exact
-            out[3 + 6 * l + c] = sinpi_d(r);
+            double r = std::ldexp(x[c], ORC_PLANT == 4 ? l + 1 : l);   // 2^l x, exact
+            out[3 + 6 * l + c] = ORC_PLANT == 3 ? cospi_d(r) : sinpi_d(r);
             out[3 + 6 * l + 3 + c] = cospi_d(r);
         }
     }
@@ -204,7 +210,8 @@ double relu(double z) { return z > 0.0 ? z : 0.0; }
 void dense(const double* W, const double* b, int n_out, int n_in, const double* x, double* y) {
     for (int o = 0; o < n_out; ++o) {
         double acc = b[o];
-        for (int i = 0; i < n_in; ++i) acc += W[(size_t)o * n_in + i] * x[i];
+        for (int i = 0; i < n_in; ++i)
+            acc += (ORC_PLANT == 5 && n_out == n_in ? W[(size_t)i * n_in + o] : W[(size_t)o * n_in + i]) * x[i];
         y[o] = acc;
     }
 }
@@ -248,9 +255,9 @@ void local_forward(const LocalNet& n, const double xh[3], const double dir[3], i
     dense(n.W1, n.b1, h, n.dx, a.gx.data(), a.z1.data());
     for (int i = 0; i < h; ++i) a.h1[i] = relu(a.z1[i]);
     dense(n.W2, n.b2, h, h, a.h1.data(), a.z2.data());
-    for (int i = 0; i < h; ++i) a.h2[i] = relu(a.z2[i]);
+    for (int i = 0; i < h; ++i) a.h2[i] = ORC_PLANT == 6 ? a.z2[i] : relu(a.z2[i]);
     dense(n.ws, n.bs, 1, h, a.h2.data(), &a.zs);
-    a.sigma = softplus(a.zs);
+    a.sigma = ORC_PLANT == 7 ? relu(a.zs) : softplus(a.zs);
     dense(n.Wf, n.bf, h, h, a.h2.data(), a.f.data());
     for (int i = 0; i < h; ++i) a.in3[i] = a.f[i];
     for (int i = 0; i < n.dd; ++i) a.in3[h + i] = a.gd[i];
@@ -310,7 +317,7 @@ void composite(int n, const double* sigma, const double* rgb /*[n][3]*/, const d
     double S = 0.0;   // sum_{k<i} tau_k
     for (int i = 0; i < n; ++i) {
         double tau = sigma[i] * delta[i];
-        double w = std::exp(-S) * (-std::expm1(-tau));
+        double w = (ORC_PLANT == 1 ? 1.0 : std::exp(ORC_PLANT == 2 ? -(S + tau) : -S)) * (-std::expm1(-tau));
         if (w_out) w_out[i] = w;
         for (int c = 0; c < 3; ++c) C[c] += w * rgb[3 * i + c];
         *D += w * t_mid[i];
@@ -347,7 +354,7 @@ void composite_backward(int n, const double* sigma, const double* rgb, const dou
             rg += (C[c] - Cle[c]) * g[c];
             drgb[3 * i + c] = w[i] * g[c];
         }
-        dsigma[i] = delta[i] * (T_next * cg - rg);
+        dsigma[i] = delta[i] * (T_next * cg + (ORC_PLANT == 10 ? rg : -rg));
     }
 }
 
@@ -405,7 +412,11 @@ void global_forward(const GlobalNet& n, const double xh[3], const double dir[3],
     encode(dir, Ld, a.gd.data());
     for (int k = 0; k < 8; ++k) {
         if (k == 0) a.in[k] = a.gx;
-        else if (k == 4) { a.in[k] = a.h[3]; a.in[k].insert(a.in[k].end(), a.gx.begin(), a.gx.end()); }
+        else if (k == 4) {
+            a.in[k] = a.h[3];
+            a.in[k].insert(a.in[k].end(), a.gx.begin(), a.gx.end());
+            if (ORC_PLANT == 12) for (int i = n.w; i < n.w + n.dx; ++i) a.in[k][i] = 0.0;
+        }
         else a.in[k] = a.h[k - 1];
         a.z[k].assign(n.w, 0.0);
         dense(n.W[k], n.b[k], n.w, (int)a.in[k].size(), a.in[k].data(), a.z[k].data());
@@ -474,7 +485,7 @@ void orc_equirect_rays(int W, int H, const float* c2w, const int64_t* pix, int64
         int u = (int)(p % W), v = (int)(p / W);
         float sphi, cphi, sth, cth;
         equirect_trig(W, H, u, v, &sphi, &cphi, &sth, &cth);
-        float dc[3] = {cth * sphi, -sth, cth * cphi};
+        float dc[3] = {cth * sphi, ORC_PLANT == 11 ? sth : -sth, cth * cphi};
         float oo[3], dd[3];
         to_world(c2w, dc, oo, dd);
         for (int a = 0; a < 3; ++a) { o[a * N + r] = oo[a]; d[a * N + r] = dd[a]; }

@@ -33,6 +33,12 @@ class RenderOpts(C.Structure):
     _fields_ = [("near_", C.c_float), ("far_", C.c_float), ("max_samples", C.c_int32), ("precision", C.c_int32)]
 
 
+class GlobalDesc(C.Structure):
+    _fields_ = [("width", C.c_int32), ("color_width", C.c_int32), ("n_samples", C.c_int32), ("near_", C.c_float),
+                ("far_", C.c_float), ("center", C.c_float * 3), ("half_extent", C.c_float),
+                ("grid_n", C.c_int32 * 3), ("grid_lo", C.c_float * 3), ("voxel", C.c_float)]
+
+
 class R360Error(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"r360 status {status}: {msg}")
@@ -62,6 +68,9 @@ SIGNATURES = {
     "r360_adam_step": (i32, [vp, vp, vp, vp, i64, i64, f32, f32, f32, f32, vp]),
     "r360_gradcheck_forward": (i32, [vp, vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, sz, vp]),
     "r360_gradcheck_backward": (i32, [vp, vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, sz, vp]),
+    "r360_global_params": (i64, [i32, i32]),
+    "r360_global_workspace_bytes": (sz, [C.POINTER(GlobalDesc), i64]),
+    "r360_global_field_step": (i32, [C.POINTER(GlobalDesc), vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
     "r360_profile_enable": (i32, [i32]),
     "r360_profile_read": (i32, [vp, vp]),
     "r360_status_string": (C.c_char_p, [i32]),

@@ -10,7 +10,6 @@
 
 namespace r360 {
 size_t pack_bytes16(int H);
-size_t pack_bytes32(int H);
 size_t bias_floats(int H);
 int route_waves(int F);
 inline size_t packT_bytes16(int H) {
@@ -233,7 +232,6 @@ r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob,
     bool ok = hipMalloc((void**)&s->labels, nvox * sizeof(int16_t)) == hipSuccess;
     ok = ok && hipMalloc(&s->pack16_bf, F * pack_bytes16(H)) == hipSuccess;
     ok = ok && hipMalloc(&s->pack16_h, F * pack_bytes16(H)) == hipSuccess;
-    ok = ok && hipMalloc((void**)&s->pack32, F * pack_bytes32(H)) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->bias, F * bias_floats(H) * sizeof(float)) == hipSuccess;
     ok = ok && hipMalloc((void**)&s->pack16_f, F * pack_bytes16(H) * 2) == hipSuccess;
     ok = ok && hipMalloc(&s->packT_bf, F * packT_bytes16(H)) == hipSuccess;
@@ -279,7 +277,6 @@ void r360_scene_destroy(r360_scene* s) {
     (void)hipFree(s->labels);
     (void)hipFree(s->pack16_bf);
     (void)hipFree(s->pack16_h);
-    (void)hipFree(s->pack32);
     (void)hipFree(s->bias);
     (void)hipFree(s->pack16_f);
     (void)hipFree(s->packT_bf);
@@ -538,6 +535,52 @@ r360_status r360_gradcheck_backward(const r360_scene* s, const double* w64, cons
     w.ro = o;
     w.rd = d;
     R360_TRY("gradcheck backward", launch_gradcheck_backward(s, w, w64, N, grad_rgb64, grad64, S(stream)));
+    return R360_OK;
+}
+
+int64_t r360_global_params(int32_t width, int32_t color_width) {
+    if (width < 32 || color_width < 32 || width % 32 || color_width % 32) return -1;
+    return global_params(width, color_width);
+}
+
+static r360_status check_global(const r360_global_desc* g) {
+    if (!g) return inval("desc is NULL");
+    if (g->width < 32 || g->width % 32 || g->width > 4096 || g->color_width < 32 || g->color_width % 32 ||
+        g->color_width > 4096) {
+        std::snprintf(g_err, sizeof(g_err), "width and color_width must be positive multiples of 32");
+        return R360_EUNSUPPORTED;
+    }
+    if (g->n_samples < 2 || g->n_samples > 4096) return inval("n_samples outside [2, 4096]");
+    if (!(g->near_ > 0.0f) || !(g->far_ > g->near_) || !std::isfinite(g->far_)) return inval("need 0 < near < far < inf");
+    if (!(g->half_extent > 0.0f) || !pow2(g->voxel)) return inval("half_extent > 0 and a power-of-two voxel");
+    for (int a = 0; a < 3; ++a)
+        if (g->grid_n[a] < 1 || g->grid_n[a] > 4096) return inval("grid size outside [1, 4096]");
+    return R360_OK;
+}
+
+size_t r360_global_workspace_bytes(const r360_global_desc* g, int64_t n_rays) {
+    if (check_global(g) != R360_OK || n_rays <= 0) return 0;
+    return global_workspace_bytes(g->width, g->color_width, n_rays, g->n_samples);
+}
+
+r360_status r360_global_field_step(const r360_global_desc* g, const float* weights, const float* o, const float* d,
+                                   int64_t N, const float* target, float* loss, float* grad, float* rgb_out,
+                                   float* depth_out, float* occ, void* ws, size_t ws_bytes, void* stream) {
+    r360_status st = check_global(g);
+    if (st != R360_OK) return st;
+    if (!weights || !o || !d || !ws) return inval("NULL pointer");
+    if (N <= 0 || N * (int64_t)g->n_samples >= (int64_t(1) << 31)) return inval("N * n_samples outside [1, 2^31)");
+    if (target && (!loss || !grad)) return inval("a target needs loss and grad outputs");
+    if (target && (N * (int64_t)g->n_samples) % 2048) return inval("with a target, N * n_samples must be a multiple of 2048");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    const size_t need = global_workspace_bytes(g->width, g->color_width, N, g->n_samples);
+    if (ws_bytes < need) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return R360_EWORKSPACE;
+    }
+    R360_STAGE(7, S(stream));
+    R360_TRY("global field", launch_global_step(g, weights, o, d, N, target, loss, grad, rgb_out, depth_out, occ, ws,
+                                                S(stream), target ? 3 : 1));
     return R360_OK;
 }
 

@@ -32,44 +32,6 @@ namespace r360 {
 
 namespace {
 
-typedef __attribute__((ext_vector_type(8))) float f32x8;
-template <typename T> struct FragT;
-template <> struct FragT<__bf16> { typedef bf16x8 type; };
-template <> struct FragT<_Float16> { typedef f16x8 type; };
-template <> struct FragT<float> { typedef f32x8 type; };
-
-template <typename T>
-__device__ __forceinline__ f32x4 mma(typename FragT<T>::type a, typename FragT<T>::type b, f32x4 c) {
-    if constexpr (__is_same(T, __bf16)) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    } else if constexpr (__is_same(T, _Float16)) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], c, 0, 0, 0);
-        return c;
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ typename FragT<T>::type pack8(const float* v) {
-    typename FragT<T>::type r;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = (T)v[e];
-    return r;
-}
-
-// Two accumulator tiles as one B operand (elements 0..3 from a, 4..7 from b).
-template <typename T, bool RELU>
-__device__ __forceinline__ typename FragT<T>::type hand(f32x4 a, f32x4 b) {
-    float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-    if (RELU) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = v[e] > 0.0f ? v[e] : 0.0f;
-    }
-    return pack8<T>(v);
-}
-
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
 
 __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) {
@@ -114,19 +76,14 @@ __device__ float packedT_source(const float* w, int fr, int lane, int e) {
 
 template <int H>
 __global__ __launch_bounds__(256) void k_repack_bwd(const float* __restrict__ weights, int F,
-                                                    float* __restrict__ p16f, __bf16* __restrict__ tbf,
-                                                    _Float16* __restrict__ th, float* __restrict__ tf) {
+                                                    __bf16* __restrict__ tbf, _Float16* __restrict__ th,
+                                                    float* __restrict__ tf) {
     using G = PackGeom<H>;
     constexpr FieldLayout L{H};
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nf = (int64_t)F * G::FRAGS16 * WAVE * 8;
     const int64_t nt = (int64_t)F * G::FRAGS_T * WAVE * 8;
     const int e = (int)(i & 7), lane = (int)((i >> 3) & 63);
     const int64_t fr_all = i >> 9;
-    if (i < nf) {
-        const int f = (int)(fr_all / G::FRAGS16), fr = (int)(fr_all % G::FRAGS16);
-        p16f[i] = packed_source16<H>(weights + (int64_t)f * L.P(), fr, lane, e);
-    }
     if (i < nt) {
         const int f = (int)(fr_all / G::FRAGS_T), fr = (int)(fr_all % G::FRAGS_T);
         const float v = packedT_source<H>(weights + (int64_t)f * L.P(), fr, lane, e);
@@ -578,8 +535,8 @@ template <int H>
 hipError_t repack_bwd_h(r360_scene* s, const float* weights, hipStream_t st) {
     using G = PackGeom<H>;
     const int F = s->mlp.n_fields;
-    const int64_t n = (int64_t)F * (G::FRAGS16 > G::FRAGS_T ? G::FRAGS16 : G::FRAGS_T) * WAVE * 8;
-    hipLaunchKernelGGL(k_repack_bwd<H>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, weights, F, s->pack16_f,
+    const int64_t n = (int64_t)F * G::FRAGS_T * WAVE * 8;
+    hipLaunchKernelGGL(k_repack_bwd<H>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, weights, F,
                        (__bf16*)s->packT_bf, (_Float16*)s->packT_h, s->packT_f);
     return hipGetLastError();
 }

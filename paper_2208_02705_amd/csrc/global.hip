@@ -1,0 +1,625 @@
+// Global omnidirectional field stage (360NeRF, Sec. 3.2 and the 360NeRF
+// architecture table of App. C): rays sampled uniformly in inverse depth,
+// positional encoding, an 8 x 256 MLP with the encoding concatenated again
+// at the fifth layer input, a density head and a feature layer, the colour
+// branch on [feature ; encoded direction], compositing (Eq.4/Eq.5), L2 loss
+// and the full backward pass; the per-sample densities are max-reduced into
+// an occupancy grid (the density source of Sec. 4.1's occupancy estimation).
+//
+// Every layer is one BF16 MFMA GEMM over all M = rays x samples rows with
+// FP32 accumulation, activations kept in HBM as BF16 for the backward pass
+// (≈2.7 GB at 4,096 rays x 128 samples). The GEMM stages 128 x 128 x 32
+// tiles of both operands through LDS; an operand whose contraction index is
+// not contiguous in memory (the weight gradients, which contract over the
+// samples) is transposed while it is staged. Epilogues apply bias and
+// activation, write straight into the next layer's (concatenated) input,
+// mask the input gradients with the ReLU pattern of the forward activations,
+// or emit per-slice FP32 weight-gradient partials (and the bias gradients as
+// column sums of the staged output-gradient tile). The partials are reduced
+// in slice order, so the gradient is deterministic.
+#include <algorithm>
+#include <utility>
+
+#include "r360_internal.h"
+
+namespace r360 {
+
+namespace {
+
+typedef __bf16 bf16;
+
+// ---------------------------------------------------------------------------
+// Layer matrices. All layers are stored as BF16 [N][K] (row = output, K
+// contiguous) and as their transposes [K][NC] (NC = N padded to a multiple
+// of 32), with biases either folded into a constant-1 input column (L1, L5,
+// L10) or kept as FP32 vectors added in the epilogue.
+// ---------------------------------------------------------------------------
+enum GLayer { G1 = 0, G2, G3, G4, G5, G6, G7, G8, GH, G10, G11, NGL };
+
+struct GLayerGeom {
+    int N, K, NC;         // rows, padded contraction width, padded rows for the transpose
+    int bias_col;         // input column holding the constant 1 (folded bias), or -1
+    int64_t w_off, t_off; // offsets (elements) of W and W^T in the bf16 arena
+    int64_t b_off;        // offset (floats) of the epilogue bias, or -1
+    int64_t g_off;        // offset (floats) of this layer's gradient partial [N][K]
+    int64_t gb_off;       // offset (floats) of its bias-gradient partial [N], or -1
+};
+
+struct GNet {
+    int w, c;             // width 256, colour width 128
+    GLayerGeom L[NGL];
+    int64_t w_elems, b_elems, g_elems;   // arena sizes
+    int64_t P;            // canonical parameter count
+};
+
+constexpr int GDX = DXYZ;   // 63
+constexpr int GDD = DDIR;   // 27
+
+inline int up32(int x) { return (x + 31) & ~31; }
+
+GNet make_net(int w, int c) {
+    GNet n{};
+    n.w = w; n.c = c;
+    auto set = [&](int i, int N, int K, int bias_col, bool epi_bias) {
+        GLayerGeom& g = n.L[i];
+        g.N = N; g.K = K; g.NC = up32(N); g.bias_col = bias_col;
+        g.w_off = n.w_elems; n.w_elems += (int64_t)N * K;
+        g.t_off = n.w_elems; n.w_elems += (int64_t)K * g.NC;
+        g.b_off = epi_bias ? n.b_elems : -1; if (epi_bias) n.b_elems += N;
+        g.g_off = n.g_elems; n.g_elems += (int64_t)N * K;
+        g.gb_off = epi_bias ? n.g_elems : -1; if (epi_bias) n.g_elems += N;
+    };
+    set(G1, w, 64, GDX, false);                        // [gx (63) | 1]
+    set(G2, w, w, -1, true); set(G3, w, w, -1, true); set(G4, w, w, -1, true);
+    set(G5, w, w + 64, w + GDX, false);                // [h4 | gx | 1]
+    set(G6, w, w, -1, true); set(G7, w, w, -1, true); set(G8, w, w, -1, true);
+    set(GH, w + 1, w, -1, true);                       // rows [f (w) ; sigma]
+    set(G10, c, up32(w + GDD + 1), w + GDD, false);    // [f | gd (27) | 1 | 0..]
+    set(G11, 3, c, -1, true);
+    n.P = (int64_t)w * GDX + w + 3 * ((int64_t)w * w + w) + (int64_t)w * (w + GDX) + w + 3 * ((int64_t)w * w + w)
+          + w + 1 + (int64_t)w * w + w + (int64_t)c * (w + GDD) + c + 3 * (int64_t)c + 3;
+    return n;
+}
+
+// Canonical parameter p -> (layer, row, column or -1 for an epilogue bias).
+// Canonical order: W1 b1 W2 b2 ... W8 b8 ws bs Wf bf W10 b10 W11 b11.
+__host__ __device__ inline void canon_to_layer(int w, int c, int64_t p, int& ly, int& row, int& col) {
+    const int64_t in0 = GDX, in4 = w + GDX;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t in = (k == 0) ? in0 : (k == 4 ? in4 : w);
+        if (p < (int64_t)w * in) {
+            ly = k; row = (int)(p / in); col = (int)(p % in);
+            return;
+        }
+        p -= (int64_t)w * in;
+        if (p < w) {                          // bias
+            ly = k; row = (int)p;
+            col = (k == 0) ? GDX : (k == 4 ? w + GDX : -1);
+            return;
+        }
+        p -= w;
+    }
+    if (p < w) { ly = GH; row = w; col = (int)p; return; }          // ws
+    p -= w;
+    if (p < 1) { ly = GH; row = w; col = -1; return; }              // bs
+    p -= 1;
+    if (p < (int64_t)w * w) { ly = GH; row = (int)(p / w); col = (int)(p % w); return; }   // Wf
+    p -= (int64_t)w * w;
+    if (p < w) { ly = GH; row = (int)p; col = -1; return; }         // bf
+    p -= w;
+    if (p < (int64_t)c * (w + GDD)) { ly = G10; row = (int)(p / (w + GDD)); col = (int)(p % (w + GDD)); return; }
+    p -= (int64_t)c * (w + GDD);
+    if (p < c) { ly = G10; row = (int)p; col = w + GDD; return; }   // b10 (folded)
+    p -= c;
+    if (p < 3 * (int64_t)c) { ly = G11; row = (int)(p / c); col = (int)(p % c); return; }
+    p -= 3 * (int64_t)c;
+    ly = G11; row = (int)p; col = -1;                                 // b11
+}
+
+struct GNetDev {
+    int w, c;
+    int64_t P;
+    GLayerGeom L[NGL];
+};
+
+// FP32 canonical weights -> BF16 layer matrices, their transposes and the
+// FP32 epilogue biases (one thread per canonical parameter).
+__global__ void k_gnet_pack(GNetDev n, const float* __restrict__ wc, bf16* __restrict__ arena, float* __restrict__ bias) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n.P) return;
+    int ly, row, col;
+    canon_to_layer(n.w, n.c, p, ly, row, col);
+    const GLayerGeom& g = n.L[ly];
+    const float v = wc[p];
+    if (col < 0) {
+        bias[g.b_off + row] = v;
+    } else {
+        arena[g.w_off + (int64_t)row * g.K + col] = (bf16)v;
+        arena[g.t_off + (int64_t)col * g.NC + row] = (bf16)v;
+    }
+}
+
+// Weight gradient: canonical parameter <- sum over slices of its partial.
+__global__ void k_gnet_grad(GNetDev n, const float* __restrict__ part, int64_t part_stride, int slices,
+                            float* __restrict__ grad) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n.P) return;
+    int ly, row, col;
+    canon_to_layer(n.w, n.c, p, ly, row, col);
+    const GLayerGeom& g = n.L[ly];
+    const int64_t off = col < 0 ? g.gb_off + row : g.g_off + (int64_t)row * g.K + col;
+    float s = 0.0f;
+    for (int k = 0; k < slices; ++k) s += part[(int64_t)k * part_stride + off];
+    grad[p] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Samples and encodings: sample k of ray r is row m = 128 r + k (ray-major).
+// t_k = 1 / fma(s_k, 1/far, (1 - s_k) / near) with s_k = k / (S - 1) (uniform
+// in inverse depth, exact at both ends), delta_k = t_{k+1} - t_k, delta_last
+// = 0; p = fma(t, d, o); xhat = (p - center) / half_extent.
+// ---------------------------------------------------------------------------
+struct GSampleArgs {
+    const float* o; const float* d;
+    int64_t N; int S;
+    float a_near, b_far;       // 1/near, 1/far
+    float c0, c1, c2, inv_h;
+    float lo0, lo1, lo2, inv_vox;
+    int g0, g1, g2;            // occupancy grid size
+    bf16* x5;                  // [M][w + 64]: cols w.. = gx | 1
+    bf16* x10;                 // [M][K10]:   cols w.. = gd | 1 | 0
+    int w, k10;
+    float* t; float* delta;    // [M]
+    int32_t* voxel;            // [M] linear cell or -1
+    int32_t* ray_off;          // [N+1]
+};
+
+__device__ inline float inv_depth_t(const GSampleArgs& a, int k) {
+    const float s = (float)k / (float)(a.S - 1);
+    return 1.0f / __builtin_fmaf(s, a.b_far, (1.0f - s) * a.a_near);
+}
+
+__global__ __launch_bounds__(256) void k_gsamples(GSampleArgs a) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t M = a.N * a.S;
+    if (m <= a.N) a.ray_off[m] = (int32_t)(m * a.S);
+    if (m >= M) return;
+    const int64_t r = m / a.S;
+    const int k = (int)(m % a.S);
+    const float t = inv_depth_t(a, k);
+    a.t[m] = t;
+    a.delta[m] = (k + 1 < a.S) ? inv_depth_t(a, k + 1) - t : 0.0f;
+    const float o[3] = {a.o[r], a.o[a.N + r], a.o[2 * a.N + r]};
+    const float d[3] = {a.d[r], a.d[a.N + r], a.d[2 * a.N + r]};
+    const float cc[3] = {a.c0, a.c1, a.c2};
+    const float lo[3] = {a.lo0, a.lo1, a.lo2};
+    const int gn[3] = {a.g0, a.g1, a.g2};
+    float xh[3];
+    int cell[3];
+    bool inside = true;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const float p = __builtin_fmaf(t, d[q], o[q]);
+        xh[q] = (p - cc[q]) * a.inv_h;
+        const float u = (p - lo[q]) * a.inv_vox;
+        inside = inside && (u >= 0.0f) && (u < (float)gn[q]);
+        cell[q] = inside ? (int)__builtin_floorf(u) : 0;
+    }
+    a.voxel[m] = inside ? cell[0] + gn[0] * (cell[1] + gn[1] * cell[2]) : -1;
+    bf16* x = a.x5 + m * (a.w + 64) + a.w;
+    x[0] = (bf16)xh[0]; x[1] = (bf16)xh[1]; x[2] = (bf16)xh[2];
+    for (int l = 0; l < LXYZ; ++l) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float s, cth;
+            sincospi(__builtin_ldexpf(xh[q], l), s, cth);
+            x[3 + 6 * l + q] = (bf16)s;
+            x[6 + 6 * l + q] = (bf16)cth;
+        }
+    }
+    x[GDX] = (bf16)1.0f;
+    bf16* y = a.x10 + m * a.k10 + a.w;
+    y[0] = (bf16)d[0]; y[1] = (bf16)d[1]; y[2] = (bf16)d[2];
+    for (int l = 0; l < LDIR; ++l) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float s, cth;
+            sincospi(__builtin_ldexpf(d[q], l), s, cth);
+            y[3 + 6 * l + q] = (bf16)s;
+            y[6 + 6 * l + q] = (bf16)cth;
+        }
+    }
+    y[GDD] = (bf16)1.0f;
+    for (int q = GDD + 1; q < a.k10 - a.w; ++q) y[q] = (bf16)0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[r][c] = sum_k A(r, k) B(c, k), r < R, c < C, k < Kc (a multiple of
+// 32, or a slice of it). Operand element (row, k) sits at p[row * sr + k * sk].
+// ---------------------------------------------------------------------------
+enum Epi { EPI_FWD = 0, EPI_RGB, EPI_DX, EPI_DW };
+
+struct GemmArgs {
+    const bf16* A; int64_t a_sr, a_sk;
+    const bf16* B; int64_t b_sr, b_sk;
+    int R, C, Kc;              // rows, columns, contraction length (per slice for EPI_DW)
+    // EPI_FWD: out[r * ldo + c] = act(acc + bias[c]) for c < n_out; column c == sig_col
+    // goes to sig[r] (ReLU) instead
+    const float* bias;
+    bool relu;
+    bf16* out; int64_t ldo;
+    int n_out;
+    int sig_col; float* sig;
+    // EPI_RGB: rgb[c * R + r] = sigmoid(acc + bias[c]) for c < 3
+    float* rgb;
+    // EPI_DX: out[r * ldo + c] = acc * [mask[r * ldm + c] > 0] (mask may be null)
+    const bf16* mask; int64_t ldm;
+    // EPI_DW: part[slice * pstride + r * ldp + c] = acc; colsum part[slice * pstride + boff + r]
+    float* part; int64_t pstride, ldp, boff;   // boff < 0: no bias gradient
+};
+
+constexpr int GT = 128;         // tile rows / columns
+constexpr int GK = 32;          // contraction step
+constexpr int GPAD = 40;        // LDS row stride (elements), 80 bytes
+
+typedef __attribute__((ext_vector_type(4))) unsigned u4;
+
+// Loads this thread's two 16-byte pieces of a 128 x 32 operand tile.
+// K-contiguous operands: piece = 8 consecutive k of one row. Row-contiguous
+// operands: piece = 8 consecutive rows at one k.
+__device__ __forceinline__ void tile_load(const bf16* p, int64_t sr, int64_t sk, int rows, int r0, int k0, int kmax,
+                                          int tid, u4 v[2]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int piece = tid + 256 * q;          // 512 pieces
+        u4 val = {0u, 0u, 0u, 0u};
+        if (sk == 1) {
+            const int row = r0 + (piece >> 2), k = k0 + 8 * (piece & 3);
+            if (row < rows && k < kmax) val = *reinterpret_cast<const u4*>(p + row * sr + k);
+        } else {
+            const int k = k0 + (piece >> 4), row = r0 + 8 * (piece & 15);
+            if (k < kmax && row < rows) {
+                if (row + 8 <= rows) {
+                    val = *reinterpret_cast<const u4*>(p + row + k * sk);
+                } else {
+                    bf16 tmp[8];
+                    for (int e = 0; e < 8; ++e) tmp[e] = row + e < rows ? p[row + e + k * sk] : (bf16)0.0f;
+                    val = __builtin_bit_cast(u4, tmp);
+                }
+            }
+        }
+        v[q] = val;
+    }
+}
+
+__device__ __forceinline__ void tile_store(bf16* lds, bool kcontig, int tid, const u4 v[2]) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int piece = tid + 256 * q;
+        if (kcontig) {
+            *reinterpret_cast<u4*>(lds + (piece >> 2) * GPAD + 8 * (piece & 3)) = v[q];
+        } else {
+            const int k = piece >> 4, row = 8 * (piece & 15);
+            const bf16* e8 = reinterpret_cast<const bf16*>(&v[q]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) lds[(row + e) * GPAD + k] = e8[e];
+        }
+    }
+}
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) bf16 la[GT * GPAD], lb[GT * GPAD];
+    __shared__ float colsum[GT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
+    const int slice = blockIdx.z;
+    const int kbeg = slice * g.Kc, kend = kbeg + g.Kc;
+    const bool a_kc = g.a_sk == 1, b_kc = g.b_sk == 1;
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float csum = 0.0f;                            // EPI_DW: column sum of A rows (bias gradient)
+    u4 va[2], vb[2];
+    tile_load(g.A, g.a_sr, g.a_sk, g.R, r0, kbeg, kend, tid, va);
+    tile_load(g.B, g.b_sr, g.b_sk, g.C, c0, kbeg, kend, tid, vb);
+    for (int k0 = kbeg; k0 < kend; k0 += GK) {
+        __syncthreads();
+        tile_store(la, a_kc, tid, va);
+        tile_store(lb, b_kc, tid, vb);
+        __syncthreads();
+        if (k0 + GK < kend) {
+            tile_load(g.A, g.a_sr, g.a_sk, g.R, r0, k0 + GK, kend, tid, va);
+            tile_load(g.B, g.b_sr, g.b_sk, g.C, c0, k0 + GK, kend, tid, vb);
+        }
+        if constexpr (EPI == EPI_DW) {
+            if (g.boff >= 0 && tid < GT) {
+#pragma unroll 8
+                for (int k = 0; k < GK; ++k) csum += (float)la[tid * GPAD + k];
+            }
+        }
+        bf16x8 fa[4], fb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            fa[i] = *reinterpret_cast<const bf16x8*>(la + (64 * wm + 16 * i + (lane & 15)) * GPAD + 8 * (lane >> 4));
+            fb[i] = *reinterpret_cast<const bf16x8*>(lb + (64 * wn + 16 * i + (lane & 15)) * GPAD + 8 * (lane >> 4));
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    // epilogue: lane holds rows 16 i + 4 (lane / 16) + q, column 16 j + lane % 16 of its 64 x 64 quarter
+    const int g4 = lane >> 4, l16 = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = c0 + 64 * wn + 16 * j + l16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = r0 + 64 * wm + 16 * i + 4 * g4 + q;
+                if (r >= g.R || c >= g.C) continue;
+                float v = acc[i][j][q];
+                if constexpr (EPI == EPI_FWD) {
+                    if (g.bias) v += g.bias[c];
+                    if (g.relu) v = v > 0.0f ? v : 0.0f;
+                    if (c == g.sig_col) g.sig[r] = v;
+                    else if (c < g.n_out) g.out[(int64_t)r * g.ldo + c] = (bf16)v;
+                } else if constexpr (EPI == EPI_RGB) {
+                    if (c < 3) g.rgb[(int64_t)c * g.R + r] = 1.0f / (1.0f + expf(-(v + g.bias[c])));
+                } else if constexpr (EPI == EPI_DX) {
+                    if (g.mask && !((float)g.mask[(int64_t)r * g.ldm + c] > 0.0f)) v = 0.0f;
+                    g.out[(int64_t)r * g.ldo + c] = (bf16)v;
+                } else {
+                    g.part[(int64_t)slice * g.pstride + (int64_t)r * g.ldp + c] = v;
+                }
+            }
+        }
+    }
+    if constexpr (EPI == EPI_DW) {
+        if (g.boff >= 0 && blockIdx.y == 0) {
+            if (tid < GT) colsum[tid] = csum;
+            __syncthreads();
+            if (tid < GT && r0 + tid < g.R) g.part[(int64_t)slice * g.pstride + g.boff + r0 + tid] = colsum[tid];
+        }
+    }
+}
+
+// dZ11 = drgb * s (1 - s) in the first 3 of 32 columns; dZhead column w = dsigma * [sigma > 0].
+__global__ void k_gout_grads(int64_t M, const float* __restrict__ rgb, const float* __restrict__ drgb,
+                             bf16* __restrict__ dz11, const float* __restrict__ sig, const float* __restrict__ dsig,
+                             bf16* __restrict__ dzh, int ldh, int w) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    for (int c = 0; c < 32; ++c) {
+        float v = 0.0f;
+        if (c < 3) {
+            const float s = rgb[c * M + m];
+            v = drgb[c * M + m] * s * (1.0f - s);
+        }
+        dz11[m * 32 + c] = (bf16)v;
+    }
+    dzh[m * ldh + w] = (bf16)(sig[m] > 0.0f ? dsig[m] : 0.0f);
+    for (int c = w + 1; c < ldh; ++c) dzh[m * ldh + c] = (bf16)0.0f;
+}
+
+// Per-sample density max into the occupancy grid (float bits as unsigned:
+// order-preserving for non-negative values; -0 is stored as +0).
+__global__ void k_gocc(int64_t M, const float* __restrict__ sig, const int32_t* __restrict__ voxel,
+                       unsigned* __restrict__ grid) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int v = voxel[m];
+    if (v < 0) return;
+    const float s = sig[m] > 0.0f ? sig[m] : 0.0f;
+    atomicMax(grid + v, __float_as_uint(s));
+}
+
+GNetDev dev_net(const GNet& n) {
+    GNetDev d;
+    d.w = n.w; d.c = n.c; d.P = n.P;
+    for (int i = 0; i < NGL; ++i) d.L[i] = n.L[i];
+    return d;
+}
+
+}  // namespace
+
+// Workspace of the global stage.
+struct GlobalWs {
+    bf16 *arena, *x5, *h[9], *x10, *h10, *dza, *dzb, *dz11;   // h[1..3], h[5..8]
+    float *bias, *sig, *rgb, *t, *delta, *dsig, *drgb, *part, *ray_rgb, *ray_grad, *loss_part;
+    int32_t *voxel, *ray_off;
+    size_t bytes;
+};
+
+constexpr int G_SLICES = 64;
+
+static GlobalWs gcarve(void* base, const GNet& n, int64_t Nr, int S) {
+    GlobalWs g{};
+    const int64_t M = Nr * S;
+    char* p = static_cast<char*>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* q = p ? p + off : nullptr;
+        off += (bytes + 255) & ~size_t(255);
+        return q;
+    };
+    const int w = n.w;
+    g.arena = (bf16*)take(n.w_elems * 2);
+    g.bias = (float*)take(n.b_elems * 4);
+    g.x5 = (bf16*)take(M * (w + 64) * 2);
+    for (int k : {1, 2, 3, 5, 6, 7, 8}) g.h[k] = (bf16*)take(M * w * 2);
+    g.x10 = (bf16*)take(M * n.L[G10].K * 2);
+    g.h10 = (bf16*)take(M * n.c * 2);
+    g.dza = (bf16*)take(M * (w + 64) * 2);
+    g.dzb = (bf16*)take(M * (w + 64) * 2);
+    g.dz11 = (bf16*)take(M * 32 * 2);
+    g.sig = (float*)take(M * 4);
+    g.rgb = (float*)take(3 * M * 4);
+    g.t = (float*)take(M * 4);
+    g.delta = (float*)take(M * 4);
+    g.dsig = (float*)take(M * 4);
+    g.drgb = (float*)take(3 * M * 4);
+    g.voxel = (int32_t*)take(M * 4);
+    g.ray_off = (int32_t*)take((Nr + 1) * 4);
+    g.part = (float*)take((size_t)G_SLICES * n.g_elems * 4);
+    g.ray_rgb = (float*)take(3 * Nr * 4);
+    g.ray_grad = (float*)take(3 * Nr * 4);
+    g.loss_part = (float*)take(((Nr + 255) / 256) * 4);
+    g.bytes = off;
+    return g;
+}
+
+size_t global_workspace_bytes(int w, int c, int64_t Nr, int S) { return gcarve(nullptr, make_net(w, c), Nr, S).bytes; }
+int64_t global_params(int w, int c) { return make_net(w, c).P; }
+
+static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
+    dim3 grid((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices);
+    switch (epi) {
+    case EPI_FWD: hipLaunchKernelGGL(k_gemm<EPI_FWD>, grid, dim3(256), 0, st, a); break;
+    case EPI_RGB: hipLaunchKernelGGL(k_gemm<EPI_RGB>, grid, dim3(256), 0, st, a); break;
+    case EPI_DX: hipLaunchKernelGGL(k_gemm<EPI_DX>, grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL(k_gemm<EPI_DW>, grid, dim3(256), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_global_step(const r360_global_desc* desc, const float* weights, const float* o, const float* d,
+                              int64_t Nr, const float* target, float* loss, float* grad, float* rgb_out,
+                              float* depth_out, float* occ, void* ws, hipStream_t st, int stage_mask) {
+    const GNet n = make_net(desc->width, desc->color_width);
+    const GNetDev nd = dev_net(n);
+    const int S = desc->n_samples, w = n.w, c = n.c;
+    const int64_t M = Nr * S;
+    GlobalWs g = gcarve(ws, n, Nr, S);
+    const unsigned nbP = (unsigned)((n.P + 255) / 256);
+    hipLaunchKernelGGL(k_gnet_pack, dim3(nbP), dim3(256), 0, st, nd, weights, g.arena, g.bias);
+    // samples and encodings
+    GSampleArgs sa;
+    sa.o = o; sa.d = d; sa.N = Nr; sa.S = S;
+    sa.a_near = 1.0f / desc->near_; sa.b_far = 1.0f / desc->far_;
+    sa.c0 = desc->center[0]; sa.c1 = desc->center[1]; sa.c2 = desc->center[2];
+    sa.inv_h = 1.0f / desc->half_extent;
+    sa.lo0 = desc->grid_lo[0]; sa.lo1 = desc->grid_lo[1]; sa.lo2 = desc->grid_lo[2];
+    sa.inv_vox = 1.0f / desc->voxel;
+    sa.g0 = desc->grid_n[0]; sa.g1 = desc->grid_n[1]; sa.g2 = desc->grid_n[2];
+    sa.x5 = g.x5; sa.x10 = g.x10; sa.w = w; sa.k10 = n.L[G10].K;
+    sa.t = g.t; sa.delta = g.delta; sa.voxel = g.voxel; sa.ray_off = g.ray_off;
+    hipLaunchKernelGGL(k_gsamples, dim3((unsigned)((std::max<int64_t>(M, Nr + 1) + 255) / 256)), dim3(256), 0, st, sa);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    const bf16* W = g.arena;
+    auto Wm = [&](int ly) { return W + n.L[ly].w_off; };
+    auto Wt = [&](int ly) { return W + n.L[ly].t_off; };
+    auto Bv = [&](int ly) { return n.L[ly].b_off >= 0 ? g.bias + n.L[ly].b_off : nullptr; };
+    const int64_t ld5 = w + 64, ld10 = n.L[G10].K;
+    // forward: layer(A input [M x K] with row stride lda) -> out
+    auto fwd = [&](int ly, const bf16* A, int64_t lda, bf16* out, int64_t ldo, bool relu) {
+        GemmArgs a{};
+        a.A = A; a.a_sr = lda; a.a_sk = 1;
+        a.B = Wm(ly); a.b_sr = n.L[ly].K; a.b_sk = 1;
+        a.R = (int)M; a.C = n.L[ly].N; a.Kc = n.L[ly].K;
+        a.bias = Bv(ly); a.relu = relu; a.out = out; a.ldo = ldo; a.n_out = n.L[ly].N; a.sig_col = -1;
+        return gemm(EPI_FWD, a, 1, st);
+    };
+    if ((e = fwd(G1, g.x5 + w, ld5, g.h[1], w, true)) != hipSuccess) return e;
+    if ((e = fwd(G2, g.h[1], w, g.h[2], w, true)) != hipSuccess) return e;
+    if ((e = fwd(G3, g.h[2], w, g.h[3], w, true)) != hipSuccess) return e;
+    if ((e = fwd(G4, g.h[3], w, g.x5, ld5, true)) != hipSuccess) return e;
+    if ((e = fwd(G5, g.x5, ld5, g.h[5], w, true)) != hipSuccess) return e;
+    if ((e = fwd(G6, g.h[5], w, g.h[6], w, true)) != hipSuccess) return e;
+    if ((e = fwd(G7, g.h[6], w, g.h[7], w, true)) != hipSuccess) return e;
+    if ((e = fwd(G8, g.h[7], w, g.h[8], w, false)) != hipSuccess) return e;
+    {   // head: relu(Wf h8 + bf) -> x10[:, :w]; relu(ws h8 + bs) -> sigma
+        GemmArgs a{};
+        a.A = g.h[8]; a.a_sr = w; a.a_sk = 1;
+        a.B = Wm(GH); a.b_sr = w; a.b_sk = 1;
+        a.R = (int)M; a.C = w + 1; a.Kc = w;
+        a.bias = Bv(GH); a.relu = true; a.out = g.x10; a.ldo = ld10; a.n_out = w; a.sig_col = w; a.sig = g.sig;
+        if ((e = gemm(EPI_FWD, a, 1, st)) != hipSuccess) return e;
+    }
+    if ((e = fwd(G10, g.x10, ld10, g.h10, c, true)) != hipSuccess) return e;
+    {
+        GemmArgs a{};
+        a.A = g.h10; a.a_sr = c; a.a_sk = 1;
+        a.B = Wm(G11); a.b_sr = c; a.b_sk = 1;
+        a.R = (int)M; a.C = 3; a.Kc = c;
+        a.bias = Bv(G11); a.rgb = g.rgb;
+        if ((e = gemm(EPI_RGB, a, 1, st)) != hipSuccess) return e;
+    }
+    if (occ) hipLaunchKernelGGL(k_gocc, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, g.sig, g.voxel,
+                                reinterpret_cast<unsigned*>(occ));
+    // compositing, loss and its backward reuse the local path's kernels
+    Workspace lw{};
+    lw.ray_off = g.ray_off; lw.sigma = g.sig; lw.rgb = g.rgb; lw.t_mid = g.t; lw.delta = g.delta;
+    lw.dsigma = g.dsig; lw.drgb = g.drgb; lw.loss_part = g.loss_part; lw.N = Nr; lw.cap = M;
+    float* ray_rgb = rgb_out ? rgb_out : g.ray_rgb;
+    if ((e = launch_composite(lw, Nr, ray_rgb, depth_out, nullptr, st)) != hipSuccess) return e;
+    if (!(stage_mask & 2)) return hipSuccess;      // forward only
+    if ((e = launch_loss_grad(lw, Nr, ray_rgb, target, loss, g.ray_grad, st)) != hipSuccess) return e;
+    if ((e = launch_composite_backward(lw, Nr, g.ray_grad, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gout_grads, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, g.rgb, g.drgb, g.dz11,
+                       g.sig, g.dsig, g.dzb, (int)up32(w + 1), w);
+
+    const int64_t kslice = M / G_SLICES;          // M is a multiple of 128 * 64 below
+    // input gradient: dX[M x K'] = dZ [M x NC] . W^T -> masked by act (if any)
+    auto dx = [&](int ly, const bf16* dz, int64_t ldz, bf16* out, int64_t ldo, int ncols, const bf16* act,
+                  int64_t ldact) {
+        GemmArgs a{};
+        a.A = dz; a.a_sr = ldz; a.a_sk = 1;
+        a.B = Wt(ly); a.b_sr = n.L[ly].NC; a.b_sk = 1;
+        a.R = (int)M; a.C = ncols; a.Kc = n.L[ly].NC;
+        a.out = out; a.ldo = ldo; a.mask = act; a.ldm = ldact;
+        return gemm(EPI_DX, a, 1, st);
+    };
+    // weight gradient partials: dW[N x K] = dZ^T [N x M] . X [M x K], sliced over M
+    auto dw = [&](int ly, const bf16* dz, int64_t ldz, const bf16* x, int64_t ldx) {
+        GemmArgs a{};
+        a.A = dz; a.a_sr = 1; a.a_sk = ldz;
+        a.B = x; a.b_sr = 1; a.b_sk = ldx;
+        a.R = n.L[ly].N; a.C = n.L[ly].K; a.Kc = (int)kslice;
+        a.part = g.part + n.L[ly].g_off; a.pstride = n.g_elems; a.ldp = n.L[ly].K;
+        a.boff = n.L[ly].gb_off >= 0 ? n.L[ly].gb_off - n.L[ly].g_off : -1;
+        return gemm(EPI_DW, a, G_SLICES, st);
+    };
+    const int ldh = up32(w + 1);
+    // L11
+    if ((e = dw(G11, g.dz11, 32, g.h10, c)) != hipSuccess) return e;
+    if ((e = dx(G11, g.dz11, 32, g.dza, c, c, g.h10, c)) != hipSuccess) return e;              // dz10
+    // L10 (feature part of the input only) -> dZf into dzb[:, :w]
+    if ((e = dw(G10, g.dza, c, g.x10, ld10)) != hipSuccess) return e;
+    if ((e = dx(G10, g.dza, c, g.dzb, ldh, w, g.x10, ld10)) != hipSuccess) return e;
+    // head -> dz8 (layer 8 is linear)
+    if ((e = dw(GH, g.dzb, ldh, g.h[8], w)) != hipSuccess) return e;
+    if ((e = dx(GH, g.dzb, ldh, g.dza, w, w, nullptr, 0)) != hipSuccess) return e;
+    // layers 8..6
+    bf16* cur = g.dza; bf16* nxt = g.dzb;
+    const int back[3] = {G8, G7, G6};
+    const bf16* inputs[3] = {g.h[7], g.h[6], g.h[5]};
+    for (int q = 0; q < 3; ++q) {
+        if ((e = dw(back[q], cur, w, inputs[q], w)) != hipSuccess) return e;
+        if ((e = dx(back[q], cur, w, nxt, w, w, inputs[q], w)) != hipSuccess) return e;
+        std::swap(cur, nxt);
+    }
+    // layer 5: input [h4 | gx | 1]; only the h4 part propagates
+    if ((e = dw(G5, cur, w, g.x5, ld5)) != hipSuccess) return e;
+    if ((e = dx(G5, cur, w, nxt, w, w, g.x5, ld5)) != hipSuccess) return e;
+    std::swap(cur, nxt);
+    const int back2[3] = {G4, G3, G2};
+    const bf16* inputs2[3] = {g.h[3], g.h[2], g.h[1]};
+    for (int q = 0; q < 3; ++q) {
+        if ((e = dw(back2[q], cur, w, inputs2[q], w)) != hipSuccess) return e;
+        if ((e = dx(back2[q], cur, w, nxt, w, w, inputs2[q], w)) != hipSuccess) return e;
+        std::swap(cur, nxt);
+    }
+    if ((e = dw(G1, cur, w, g.x5 + w, ld5)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_gnet_grad, dim3(nbP), dim3(256), 0, st, nd, g.part, n.g_elems, G_SLICES, grad);
+    return hipGetLastError();
+}
+
+}  // namespace r360

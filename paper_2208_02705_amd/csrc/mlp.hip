@@ -18,54 +18,31 @@
 // Layer biases ride along as an encoding slot holding 1 (L1, L3) or as the
 // accumulator's initial value (L2, HEAD, L4).
 //
-// Work split: samples arrive sorted by field (route.hip). 16-bit forms: each
-// wave takes a contiguous slice of the sorted samples and keeps the current
-// field's A fragments in registers, reloading them only when the slice
-// crosses into the next field. FP32 form: a block takes a contiguous slice;
-// its four waves share the field's FP32 fragments staged in LDS.
+// Work split: samples arrive sorted by field (route.hip). A block of four
+// waves takes a contiguous slice of the sorted samples; for every field in
+// its slice it stages that field's A fragments in LDS once, and each wave
+// then processes chunks of 64 samples as four independent 16-column tiles,
+// so every fragment read from LDS feeds four MFMAs and the four dependency
+// chains keep the matrix unit busy while the encoding runs on the VALU.
 // Block indices are remapped so that the blocks resident on one XCD (blocks
 // are dealt round-robin over the 8 XCDs) take neighbouring slices, which
-// mostly share a field and so its weights in that XCD's L2.
+// mostly share fields and so their weights in that XCD's L2.
+//
+// Precision: BF16 or FP16 operands with FP32 accumulation, or FP32 (each
+// K = 32 step as eight 16x16x4 FP32 MFMAs over the same fragment layout).
 #include "r360_internal.h"
 
 namespace r360 {
 
 namespace {
 
-// FP32 forward: k-step ks is register ks%4 of tile ks/4.
-__host__ __device__ constexpr int hidden_col32(int ks, int g) { return 16 * (ks >> 2) + 4 * g + (ks & 3); }
-
-template <int H>
-__device__ void step32(int st, int& ly, int& ot, int& ks) {
-    using G = PackGeom<H>;
-    int nks;
-    if (st < G::S_L1) { ly = LY_L1; nks = 16; }
-    else if ((st -= G::S_L1) < G::S_L2) { ly = LY_L2; nks = G::KH32; }
-    else if ((st -= G::S_L2) < G::S_HD) { ly = LY_HD; nks = G::KH32; }
-    else if ((st -= G::S_HD) < G::S_L3) { ly = LY_L3; nks = G::KH32 + 8; }
-    else { st -= G::S_L3; ly = LY_L4; nks = G::KH32; }
-    ot = st / nks;
-    ks = st % nks;
-}
-
-template <int H>
-__device__ float packed_source32(const float* w, int st, int lane) {
-    int ly, ot, ks;
-    step32<H>(st, ly, ot, ks);
-    const int g = lane >> 4, row = 16 * ot + (lane & 15);
-    if (ly == LY_L1) return canon_weight<H>(w, ly, row, true, pe_slot_feature(g, ks));
-    if (ly == LY_L3 && ks >= PackGeom<H>::KH32) return canon_weight<H>(w, ly, row, true, dir_slot_feature(g, ks - PackGeom<H>::KH32));
-    return canon_weight<H>(w, ly, row, false, hidden_col32(ks, g));
-}
-
 template <int H>
 __global__ __launch_bounds__(256) void k_repack(const float* __restrict__ weights, int F, __bf16* __restrict__ pbf,
-                                                _Float16* __restrict__ ph, float* __restrict__ p32,
+                                                _Float16* __restrict__ ph, float* __restrict__ pf,
                                                 float* __restrict__ bias) {
     using G = PackGeom<H>;
     constexpr FieldLayout L{H};
     const int64_t n16 = (int64_t)F * G::FRAGS16 * WAVE * 8;
-    const int64_t n32 = (int64_t)F * G::STEPS32 * WAVE;
     const int64_t nb = (int64_t)F * G::BIAS_FLOATS;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) {
@@ -75,13 +52,7 @@ __global__ __launch_bounds__(256) void k_repack(const float* __restrict__ weight
         const float v = packed_source16<H>(weights + (int64_t)f * L.P(), fr, lane, e);
         pbf[i] = (__bf16)v;
         ph[i] = (_Float16)v;
-    }
-    if (i < n32) {
-        // stored as float4 groups of 4 consecutive k-steps: [F][STEPS32/4][64][4]
-        const int e = (int)(i & 3), lane = (int)((i >> 2) & 63);
-        const int64_t grp_all = i >> 8;
-        const int f = (int)(grp_all / (G::STEPS32 / 4)), grp = (int)(grp_all % (G::STEPS32 / 4));
-        p32[i] = packed_source32<H>(weights + (int64_t)f * L.P(), grp * 4 + e, lane);
+        pf[i] = v;
     }
     if (i < nb) {
         const int f = (int)(i / G::BIAS_FLOATS), k = (int)(i % G::BIAS_FLOATS);
@@ -100,37 +71,10 @@ __global__ __launch_bounds__(256) void k_repack(const float* __restrict__ weight
 // ---------------------------------------------------------------------------
 // Forward
 // ---------------------------------------------------------------------------
-template <typename T> struct V8of;
-template <> struct V8of<__bf16> { typedef bf16x8 type; };
-template <> struct V8of<_Float16> { typedef f16x8 type; };
-
-template <typename T>
-__device__ __forceinline__ f32x4 mfma16(typename V8of<T>::type a, typename V8of<T>::type b, f32x4 c) {
-    if constexpr (sizeof(T) == 2 && __is_same(T, __bf16)) return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-    else return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
-}
-
-template <typename T>
-__device__ __forceinline__ typename V8of<T>::type to8(const float* v) {
-    typename V8of<T>::type r;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r[e] = (T)v[e];
-    return r;
-}
-
-// ReLU (optional) of two accumulator tiles into one 16-bit B operand.
-template <typename T, bool RELU>
-__device__ __forceinline__ typename V8of<T>::type handoff(f32x4 a, f32x4 b) {
-    float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-    if (RELU) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = v[e] > 0.0f ? v[e] : 0.0f;
-    }
-    return to8<T>(v);
-}
-
-__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
+// Output activations with the hardware exp/log/reciprocal (relative error
+// ~1e-7, far inside every tolerance of the path).
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + __logf(1.0f + __expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 struct FwdArgs {
     const int32_t* total;        // ray_off + N
@@ -143,7 +87,7 @@ struct FwdArgs {
     int64_t N, cap;
     int F;
     float c0, c1, c2, inv_h;
-    const void* pack;            // 16-bit fragments or FP32 groups
+    const void* pack;            // [F][FRAGS16][64] fragments of the chosen element type
     const float* bias;
     float* sigma;
     float* rgb;                  // [3][cap]
@@ -160,299 +104,155 @@ __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) 
 
 __device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
-// Per-sample inputs, gathered in three dependent steps (sorted position ->
-// sample index -> ray); the chunk loops issue the steps for the next chunk
-// while the current one computes.
-struct SampleIn {
-    int orig;
-    float t;
-    int64_t ray;
-    float o[3], d[3];
-};
-
-__device__ __forceinline__ void fetch_index(const FwdArgs& a, int pos, int fend, int j, SampleIn& s) {
-    const int jp = pos + j;
-    s.orig = a.perm[jp < fend ? jp : pos];
-}
-__device__ __forceinline__ void fetch_sample(const FwdArgs& a, SampleIn& s) {
-    s.t = a.t_mid[s.orig];
-    s.ray = a.ray[s.orig];
-}
-__device__ __forceinline__ void fetch_ray(const FwdArgs& a, SampleIn& s) {
-    const int64_t r = s.ray;
-    s.o[0] = a.o[r]; s.o[1] = a.o[a.N + r]; s.o[2] = a.o[2 * a.N + r];
-    s.d[0] = a.d[r]; s.d[1] = a.d[a.N + r]; s.d[2] = a.d[2 * a.N + r];
-}
-
-// Encoding input xhat = (fma(t, d, o) - center) / half_extent (FP32 spec).
-__device__ __forceinline__ void sample_xhat(const FwdArgs& a, const SampleIn& s, float xh[3]) {
-    const float cc[3] = {a.c0, a.c1, a.c2};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const float p = __builtin_fmaf(s.t, s.d[k], s.o[k]);
-        xh[k] = (p - cc[k]) * a.inv_h;
-    }
-}
+constexpr int NTILE = 4;               // 16-sample column tiles per wave chunk
+constexpr int FCH = 16 * NTILE;        // samples per wave chunk
+constexpr int FWD_WAVES = 4;
 
 template <int H, typename T>
-__global__ __launch_bounds__(256) void k_fwd16(FwdArgs a) {
+__global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
     using G = PackGeom<H>;
-    using V8 = typename V8of<T>::type;
-    constexpr int NT = G::NT, KH = G::KH16;
-    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
-    const int nw = gridDim.x * 4;
-    const int w = xcd_block(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    const int S = *a.total;
-    const int per = (((S + nw - 1) / nw) + 15) & ~15;
-    const int beg = min(S, w * per), end = min(S, beg + per);
-
-    V8 w1[NT][2], w2[NT][KH], wh[NT + 1][KH], w3[NT][KH + 1], w4[KH];
-    const V8* pk = reinterpret_cast<const V8*>(a.pack);
-    int cur = -1;
-    for (int pos = beg; pos < end;) {
-        const int f = find_field(a.field_start, a.F, pos);
-        const int fend = min(end, a.field_start[f + 1]);
-        if (f != cur) {
-            cur = f;
-            const V8* p = pk + (int64_t)f * G::FRAGS16 * WAVE + lane;
-            int k = 0;
-#pragma unroll
-            for (int ot = 0; ot < NT; ++ot)
-#pragma unroll
-                for (int ks = 0; ks < 2; ++ks) w1[ot][ks] = p[(k++) * WAVE];
-#pragma unroll
-            for (int ot = 0; ot < NT; ++ot)
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) w2[ot][ks] = p[(k++) * WAVE];
-#pragma unroll
-            for (int ot = 0; ot < NT + 1; ++ot)
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) wh[ot][ks] = p[(k++) * WAVE];
-#pragma unroll
-            for (int ot = 0; ot < NT; ++ot)
-#pragma unroll
-                for (int ks = 0; ks < KH + 1; ++ks) w3[ot][ks] = p[(k++) * WAVE];
-#pragma unroll
-            for (int ks = 0; ks < KH; ++ks) w4[ks] = p[(k++) * WAVE];
-        }
-        const f32x4* bias = reinterpret_cast<const f32x4*>(a.bias + (int64_t)f * G::BIAS_FLOATS) + g;
-        SampleIn nx;
-        fetch_index(a, pos, fend, j, nx);
-        fetch_sample(a, nx);
-        fetch_ray(a, nx);
-        for (; pos < fend; pos += 16) {
-            const SampleIn cur = nx;
-            const bool valid = pos + j < fend;
-            const int orig = cur.orig;
-            const bool more = pos + 16 < fend;
-            if (more) fetch_index(a, pos + 16, fend, j, nx);
-            float xh[3];
-            sample_xhat(a, cur, xh);
-            const float dv[3] = {cur.d[0], cur.d[1], cur.d[2]};
-            float pe[16];
-            pe_position(g, xh, pe);
-            const V8 x0 = to8<T>(pe), x1 = to8<T>(pe + 8);
-            // L1
-            f32x4 acc[NT + 1];
-#pragma unroll
-            for (int ot = 0; ot < NT; ++ot) {
-                acc[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
-                acc[ot] = mfma16<T>(w1[ot][0], x0, acc[ot]);
-                acc[ot] = mfma16<T>(w1[ot][1], x1, acc[ot]);
-            }
-            V8 hb[KH];
-#pragma unroll
-            for (int ks = 0; ks < KH; ++ks) hb[ks] = handoff<T, true>(acc[2 * ks], acc[2 * ks + 1]);
-            if (more) fetch_sample(a, nx);
-            // L2
-#pragma unroll
-            for (int ot = 0; ot < NT; ++ot) {
-                acc[ot] = bias[ot * 4];
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) acc[ot] = mfma16<T>(w2[ot][ks], hb[ks], acc[ot]);
-            }
-#pragma unroll
-            for (int ks = 0; ks < KH; ++ks) hb[ks] = handoff<T, true>(acc[2 * ks], acc[2 * ks + 1]);
-            // HEAD: [f ; sigma]
-#pragma unroll
-            for (int ot = 0; ot < NT + 1; ++ot) {
-                acc[ot] = bias[(NT + ot) * 4];
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) acc[ot] = mfma16<T>(wh[ot][ks], hb[ks], acc[ot]);
-            }
-            const float zs = acc[NT][0];
-#pragma unroll
-            for (int ks = 0; ks < KH; ++ks) hb[ks] = handoff<T, false>(acc[2 * ks], acc[2 * ks + 1]);
-            if (more) fetch_ray(a, nx);
-            float dpe[8];
-            pe_direction(g, dv, dpe);
-            const V8 xd = to8<T>(dpe);
-            // L3 on [f ; g(d)]
-#pragma unroll
-            for (int ot = 0; ot < NT; ++ot) {
-                acc[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) acc[ot] = mfma16<T>(w3[ot][ks], hb[ks], acc[ot]);
-                acc[ot] = mfma16<T>(w3[ot][KH], xd, acc[ot]);
-            }
-#pragma unroll
-            for (int ks = 0; ks < KH; ++ks) hb[ks] = handoff<T, true>(acc[2 * ks], acc[2 * ks + 1]);
-            // L4
-            f32x4 o4 = bias[(2 * NT + 1) * 4];
-#pragma unroll
-            for (int ks = 0; ks < KH; ++ks) o4 = mfma16<T>(w4[ks], hb[ks], o4);
-            if (g == 0 && valid) {
-                a.sigma[orig] = softplusf(zs);
-                a.rgb[orig] = sigmoidf(o4[0]);
-                a.rgb[a.cap + orig] = sigmoidf(o4[1]);
-                a.rgb[2 * a.cap + orig] = sigmoidf(o4[2]);
-            }
-        }
-    }
-}
-
-// FP32 form: block-wide slices; the field's fragments are staged in LDS.
-template <int H>
-__global__ __launch_bounds__(256) void k_fwd32(FwdArgs a) {
-    using G = PackGeom<H>;
-    constexpr int NT = G::NT, KH = G::KH32;
-    extern __shared__ float4 lw[];                         // [STEPS32/4][64] float4, then bias
-    float* lbias = reinterpret_cast<float*>(lw + (G::STEPS32 / 4) * WAVE);
+    using F8 = typename FragT<T>::type;
+    constexpr int NT = G::NT, KH = G::KH16, FR = G::FRAGS16;
+    extern __shared__ __attribute__((aligned(32))) char smem[];
+    F8* lw = reinterpret_cast<F8*>(smem);                                          // [FR][64]
+    float* lb = reinterpret_cast<float*>(smem + (size_t)FR * WAVE * sizeof(F8));   // [BIAS_FLOATS]
     const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15, wv = threadIdx.x >> 6;
     const int nb = gridDim.x;
     const int b = xcd_block(blockIdx.x, nb);
     const int S = *a.total;
-    const int per = (((S + nb - 1) / nb) + 63) & ~63;
+    constexpr int BCHK = FWD_WAVES * FCH;
+    const int per = (((S + nb - 1) / nb) + BCHK - 1) / BCHK * BCHK;
     const int beg = min(S, b * per), end = min(S, beg + per);
-    const float4* pk = reinterpret_cast<const float4*>(a.pack);
+    const F8* pk = reinterpret_cast<const F8*>(a.pack);
+    const float cc[3] = {a.c0, a.c1, a.c2};
     for (int pos = beg; pos < end;) {
         const int f = find_field(a.field_start, a.F, pos);
         const int fend = min(end, a.field_start[f + 1]);
+        __syncthreads();                               // the previous field's fragments are no longer read
+        const F8* src = pk + (int64_t)f * FR * WAVE;
+        for (int i = threadIdx.x; i < FR * WAVE; i += 64 * FWD_WAVES) lw[i] = src[i];
+        for (int i = threadIdx.x; i < G::BIAS_FLOATS; i += 64 * FWD_WAVES) lb[i] = a.bias[(int64_t)f * G::BIAS_FLOATS + i];
         __syncthreads();
-        const float4* src = pk + (int64_t)f * (G::STEPS32 / 4) * WAVE;
-        for (int i = threadIdx.x; i < (G::STEPS32 / 4) * WAVE; i += 256) lw[i] = src[i];
-        for (int i = threadIdx.x; i < G::BIAS_FLOATS; i += 256) lbias[i] = a.bias[(int64_t)f * G::BIAS_FLOATS + i];
-        __syncthreads();
-        SampleIn nx;
-        if (pos + 16 * wv < fend) {
-            fetch_index(a, pos + 16 * wv, fend, j, nx);
-            fetch_sample(a, nx);
-            fetch_ray(a, nx);
-        }
-        for (int c = pos + 16 * wv; c < fend; c += 64) {
-            const SampleIn cur = nx;
-            const bool valid = c + j < fend;
-            const int orig = cur.orig;
-            const bool more = c + 64 < fend;
-            if (more) {
-                fetch_index(a, c + 64, fend, j, nx);
-                fetch_sample(a, nx);
-                fetch_ray(a, nx);
+        const F8* W = lw + lane;
+        const f32x4* bias = reinterpret_cast<const f32x4*>(lb) + g;
+        for (int c = pos + FCH * wv; c < fend; c += BCHK) {
+            int orig[NTILE];
+            bool valid[NTILE];
+            float dv[NTILE][3];
+            F8 x0[NTILE], x1[NTILE];
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n) {
+                const int sp = c + 16 * n + j;
+                valid[n] = sp < fend;
+                orig[n] = a.perm[valid[n] ? sp : c];
             }
-            float xh[3];
-            sample_xhat(a, cur, xh);
-            const float dv[3] = {cur.d[0], cur.d[1], cur.d[2]};
-            float pe[16];
-            pe_position(g, xh, pe);
-            const float4* p = lw + lane;
-            f32x4 acc[NT + 1];
-            // L1: 16 k-steps
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n) {
+                const float t = a.t_mid[orig[n]];
+                const int64_t r = a.ray[orig[n]];
+                float xh[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    dv[n][k] = a.d[k * a.N + r];
+                    xh[k] = (__builtin_fmaf(t, dv[n][k], a.o[k * a.N + r]) - cc[k]) * a.inv_h;
+                }
+                float pe[16];
+                pe_position<__is_same(T, float)>(g, xh, pe);
+                x0[n] = pack8<T>(pe);
+                x1[n] = pack8<T>(pe + 8);
+            }
+            f32x4 acc[NTILE][NT + 1];
+            F8 hb[NTILE][KH];
+            // L1: encoding -> h (bias in the encoding's constant slot)
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
-                acc[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const F8 A0 = W[(2 * ot) * WAVE], A1 = W[(2 * ot + 1) * WAVE];
 #pragma unroll
-                for (int kg = 0; kg < 4; ++kg) {
-                    const float4 w4v = p[(ot * 4 + kg) * WAVE];
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.x, pe[4 * kg + 0], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.y, pe[4 * kg + 1], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.z, pe[4 * kg + 2], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.w, pe[4 * kg + 3], acc[ot], 0, 0, 0);
+                for (int n = 0; n < NTILE; ++n) {
+                    acc[n][ot] = mma<T>(A0, x0[n], f32x4{0.f, 0.f, 0.f, 0.f});
+                    acc[n][ot] = mma<T>(A1, x1[n], acc[n][ot]);
                 }
             }
-            p += G::S_L1 / 4 * WAVE;
-            f32x4 h[NT];
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int n = 0; n < NTILE; ++n)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) h[t][r] = acc[t][r] > 0.0f ? acc[t][r] : 0.0f;
-            const float4* lb = reinterpret_cast<const float4*>(lbias) + g;
-            // L2
+                for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            // L2: h -> h
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
-                const float4 bb = lb[ot * 4];
-                acc[ot] = f32x4{bb.x, bb.y, bb.z, bb.w};
+                const f32x4 bb = bias[ot * 4];
 #pragma unroll
-                for (int kg = 0; kg < KH / 4; ++kg) {
-                    const float4 w4v = p[(ot * (KH / 4) + kg) * WAVE];
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.x, h[kg][0], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.y, h[kg][1], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.z, h[kg][2], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.w, h[kg][3], acc[ot], 0, 0, 0);
+                for (int ks = 0; ks < KH; ++ks) {
+                    const F8 A = W[(G::F_L1 + ot * KH + ks) * WAVE];
+#pragma unroll
+                    for (int n = 0; n < NTILE; ++n) acc[n][ot] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][ot]);
                 }
             }
-            p += G::S_L2 / 4 * WAVE;
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int n = 0; n < NTILE; ++n)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) h[t][r] = acc[t][r] > 0.0f ? acc[t][r] : 0.0f;
-            // HEAD
+                for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            // HEAD: h -> [f ; sigma]
 #pragma unroll
             for (int ot = 0; ot < NT + 1; ++ot) {
-                const float4 bb = lb[(NT + ot) * 4];
-                acc[ot] = f32x4{bb.x, bb.y, bb.z, bb.w};
+                const f32x4 bb = bias[(NT + ot) * 4];
 #pragma unroll
-                for (int kg = 0; kg < KH / 4; ++kg) {
-                    const float4 w4v = p[(ot * (KH / 4) + kg) * WAVE];
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.x, h[kg][0], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.y, h[kg][1], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.z, h[kg][2], acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.w, h[kg][3], acc[ot], 0, 0, 0);
+                for (int ks = 0; ks < KH; ++ks) {
+                    const F8 A = W[(G::F_L1 + G::F_L2 + ot * KH + ks) * WAVE];
+#pragma unroll
+                    for (int n = 0; n < NTILE; ++n) acc[n][ot] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][ot]);
                 }
             }
-            p += G::S_HD / 4 * WAVE;
-            const float zs = acc[NT][0];
+            float zs[NTILE];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) h[t] = acc[t];
-            float dpe[8];
-            pe_direction(g, dv, dpe);
-            // L3 on [f ; g(d)]
+            for (int n = 0; n < NTILE; ++n) {
+                zs[n] = acc[n][NT][0];
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, false>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            }
+            // L3: [f ; g(d)] -> h (bias in the direction encoding's constant slot)
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n) {
+                float dpe[8];
+                pe_direction<__is_same(T, float)>(g, dv[n], dpe);
+                x0[n] = pack8<T>(dpe);
+            }
+            constexpr int O3 = G::F_L1 + G::F_L2 + G::F_HD;
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
-                acc[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int kg = 0; kg < KH / 4 + 2; ++kg) {
-                    const float4 w4v = p[(ot * (KH / 4 + 2) + kg) * WAVE];
-                    const float b0 = kg < KH / 4 ? h[kg < KH / 4 ? kg : 0][0] : dpe[4 * (kg - KH / 4) + 0];
-                    const float b1 = kg < KH / 4 ? h[kg < KH / 4 ? kg : 0][1] : dpe[4 * (kg - KH / 4) + 1];
-                    const float b2 = kg < KH / 4 ? h[kg < KH / 4 ? kg : 0][2] : dpe[4 * (kg - KH / 4) + 2];
-                    const float b3 = kg < KH / 4 ? h[kg < KH / 4 ? kg : 0][3] : dpe[4 * (kg - KH / 4) + 3];
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.x, b0, acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.y, b1, acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.z, b2, acc[ot], 0, 0, 0);
-                    acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.w, b3, acc[ot], 0, 0, 0);
+                for (int n = 0; n < NTILE; ++n) acc[n][ot] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < KH + 1; ++ks) {
+                    const F8 A = W[(O3 + ot * (KH + 1) + ks) * WAVE];
+#pragma unroll
+                    for (int n = 0; n < NTILE; ++n) acc[n][ot] = mma<T>(A, ks < KH ? hb[n][ks < KH ? ks : 0] : x0[n], acc[n][ot]);
                 }
             }
-            p += G::S_L3 / 4 * WAVE;
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int n = 0; n < NTILE; ++n)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) h[t][r] = acc[t][r] > 0.0f ? acc[t][r] : 0.0f;
-            // L4
-            const float4 bb = lb[(2 * NT + 1) * 4];
-            f32x4 o4 = f32x4{bb.x, bb.y, bb.z, bb.w};
+                for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            // L4: h -> rgb
+            constexpr int O4 = O3 + G::F_L3;
+            {
+                const f32x4 bb = bias[(2 * NT + 1) * 4];
 #pragma unroll
-            for (int kg = 0; kg < KH / 4; ++kg) {
-                const float4 w4v = p[kg * WAVE];
-                o4 = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.x, h[kg][0], o4, 0, 0, 0);
-                o4 = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.y, h[kg][1], o4, 0, 0, 0);
-                o4 = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.z, h[kg][2], o4, 0, 0, 0);
-                o4 = __builtin_amdgcn_mfma_f32_16x16x4f32(w4v.w, h[kg][3], o4, 0, 0, 0);
+                for (int ks = 0; ks < KH; ++ks) {
+                    const F8 A = W[(O4 + ks) * WAVE];
+#pragma unroll
+                    for (int n = 0; n < NTILE; ++n) acc[n][0] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][0]);
+                }
             }
-            if (g == 0 && valid) {
-                a.sigma[orig] = softplusf(zs);
-                a.rgb[orig] = sigmoidf(o4[0]);
-                a.rgb[a.cap + orig] = sigmoidf(o4[1]);
-                a.rgb[2 * a.cap + orig] = sigmoidf(o4[2]);
+            if (g == 0) {
+#pragma unroll
+                for (int n = 0; n < NTILE; ++n) {
+                    if (!valid[n]) continue;
+                    a.sigma[orig[n]] = softplusf(zs[n]);
+                    a.rgb[orig[n]] = sigmoidf(acc[n][0][0]);
+                    a.rgb[a.cap + orig[n]] = sigmoidf(acc[n][0][1]);
+                    a.rgb[2 * a.cap + orig[n]] = sigmoidf(acc[n][0][2]);
+                }
             }
         }
         pos = fend;
@@ -464,12 +264,22 @@ int resident_blocks(K kernel, size_t lds) {
     int dev = 0;
     (void)hipGetDevice(&dev);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * FWD_WAVES, lds) != hipSuccess || per_cu < 1) per_cu = 1;
     hipDeviceProp_t prop;
     int cus = 256;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
     int nb = per_cu * cus;
     return (nb + 7) & ~7;
+}
+
+template <int H, typename T>
+hipError_t fwd_launch(const FwdArgs& a, hipStream_t st) {
+    using G = PackGeom<H>;
+    const size_t lds = (size_t)G::FRAGS16 * WAVE * sizeof(typename FragT<T>::type) + G::BIAS_FLOATS * sizeof(float);
+    static int nb = 0;
+    if (!nb) nb = resident_blocks(k_fwd<H, T>, lds);
+    hipLaunchKernelGGL((k_fwd<H, T>), dim3(nb), dim3(64 * FWD_WAVES), lds, st, a);
+    return hipGetLastError();
 }
 
 template <int H>
@@ -487,41 +297,25 @@ hipError_t fwd_h(const r360_scene* s, const Workspace& w, int precision, hipStre
     a.inv_h = 1.0f / s->mlp.half_extent;
     a.bias = s->bias;
     a.sigma = w.sigma; a.rgb = w.rgb;
-    if (precision == R360_FP32) {
-        a.pack = s->pack32;
-        const size_t lds = (size_t)PackGeom<H>::BYTES32 + PackGeom<H>::BIAS_FLOATS * 4;
-        static int nb = 0;
-        if (!nb) nb = resident_blocks(k_fwd32<H>, lds);
-        hipLaunchKernelGGL(k_fwd32<H>, dim3(nb), dim3(256), lds, st, a);
-    } else if (precision == R360_BF16) {
-        a.pack = s->pack16_bf;
-        static int nb = 0;
-        if (!nb) nb = resident_blocks(k_fwd16<H, __bf16>, 0);
-        hipLaunchKernelGGL((k_fwd16<H, __bf16>), dim3(nb), dim3(256), 0, st, a);
-    } else {
-        a.pack = s->pack16_h;
-        static int nb = 0;
-        if (!nb) nb = resident_blocks(k_fwd16<H, _Float16>, 0);
-        hipLaunchKernelGGL((k_fwd16<H, _Float16>), dim3(nb), dim3(256), 0, st, a);
-    }
-    return hipGetLastError();
+    if (precision == R360_BF16) { a.pack = s->pack16_bf; return fwd_launch<H, __bf16>(a, st); }
+    if (precision == R360_FP16) { a.pack = s->pack16_h; return fwd_launch<H, _Float16>(a, st); }
+    a.pack = s->pack16_f;
+    return fwd_launch<H, float>(a, st);
 }
 
 template <int H>
 hipError_t repack_h(r360_scene* s, const float* weights, hipStream_t st) {
     using G = PackGeom<H>;
     const int F = s->mlp.n_fields;
-    const int64_t n = std::max<int64_t>((int64_t)F * G::FRAGS16 * WAVE * 8,
-                                        std::max<int64_t>((int64_t)F * G::STEPS32 * WAVE, (int64_t)F * G::BIAS_FLOATS));
+    const int64_t n = std::max<int64_t>((int64_t)F * G::FRAGS16 * WAVE * 8, (int64_t)F * G::BIAS_FLOATS);
     hipLaunchKernelGGL(k_repack<H>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, weights, F,
-                       (__bf16*)s->pack16_bf, (_Float16*)s->pack16_h, s->pack32, s->bias);
+                       (__bf16*)s->pack16_bf, (_Float16*)s->pack16_h, s->pack16_f, s->bias);
     return hipGetLastError();
 }
 
 }  // namespace
 
 size_t pack_bytes16(int H) { return H == 32 ? PackGeom<32>::BYTES16 : PackGeom<64>::BYTES16; }
-size_t pack_bytes32(int H) { return H == 32 ? PackGeom<32>::BYTES32 : PackGeom<64>::BYTES32; }
 size_t bias_floats(int H) { return H == 32 ? PackGeom<32>::BIAS_FLOATS : PackGeom<64>::BIAS_FLOATS; }
 
 hipError_t launch_repack(r360_scene* s, const float* weights, hipStream_t st) {

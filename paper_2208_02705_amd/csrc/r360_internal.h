@@ -107,39 +107,141 @@ __device__ __forceinline__ void dbl(float s, float c, float& s2, float& c2) {
     c2 = (c - s) * (c + s);
 }
 
-// Position encoding values of lane group g in slot order (16 values).
+// (sin pi a, cos pi a) for a = 2^l x. EXACT: the reduced polynomial above.
+// Otherwise the hardware sine/cosine of the exactly reduced argument in
+// revolutions (a/2 minus the nearest integer), accurate to about 2^-20
+// absolute: used only where the result is rounded to 8 or 11 bits next.
+template <bool EXACT>
+__device__ __forceinline__ void sincos_oct(float x, int l, float& s, float& c) {
+    if constexpr (EXACT) {
+        sincospi(__builtin_ldexpf(x, l), s, c);
+    } else {
+        float r = __builtin_ldexpf(x, l - 1);
+        r = r - __builtin_rintf(r);
+        s = __builtin_amdgcn_sinf(r);
+        c = __builtin_amdgcn_cosf(r);
+    }
+}
+
+// x[c] for a lane-dependent c in {0, 1, 2}, branch-free and exact (the
+// weights are 0 or 1).
+__device__ __forceinline__ float sel3(int c, const float x[3]) {
+    const float w1 = (float)(c == 1), w2 = (float)(c == 2), w0 = 1.0f - w1 - w2;
+    return __builtin_fmaf(w2, x[2], __builtin_fmaf(w1, x[1], w0 * x[0]));
+}
+
+// Position encoding values of lane group g in slot order (16 values): three
+// chains of octaves (exact evaluation, then angle doubling) per lane; lane
+// group 3 replaces its two spare pairs by the raw components and the bias 1.
+template <bool EXACT = true>
 __device__ __forceinline__ void pe_position(int g, const float xh[3], float v[16]) {
     const bool g3 = (g == 3);
-    const int cA = g3 ? 0 : g, cB = g3 ? 1 : g, cC = g3 ? 2 : g;
-    const float xA = cA == 0 ? xh[0] : cA == 1 ? xh[1] : xh[2];
-    const float xB = cB == 0 ? xh[0] : cB == 1 ? xh[1] : xh[2];
-    const float xC = cC == 0 ? xh[0] : cC == 1 ? xh[1] : xh[2];
     float s, c;
-    sincospi(__builtin_ldexpf(xA, g3 ? 8 : 0), s, c);
+    sincos_oct<EXACT>(sel3(g3 ? 0 : g, xh), g3 ? 8 : 0, s, c);
     v[0] = s; v[1] = c;
     dbl(s, c, v[2], v[3]);
     dbl(v[2], v[3], v[4], v[5]);
-    sincospi(__builtin_ldexpf(xB, g3 ? 8 : 3), s, c);
+    sincos_oct<EXACT>(sel3(g3 ? 1 : g, xh), g3 ? 8 : 3, s, c);
     v[6] = s; v[7] = c;
     dbl(s, c, v[8], v[9]);
     dbl(v[8], v[9], v[10], v[11]);
-    sincospi(__builtin_ldexpf(xC, g3 ? 8 : 6), s, c);
+    sincos_oct<EXACT>(sel3(g3 ? 2 : g, xh), g3 ? 8 : 6, s, c);
     v[12] = s; v[13] = c;
     dbl(s, c, v[14], v[15]);
-    if (g3) { v[4] = xh[0]; v[5] = xh[1]; v[10] = xh[2]; v[11] = 1.0f; }
+    v[4] = g3 ? xh[0] : v[4];
+    v[5] = g3 ? xh[1] : v[5];
+    v[10] = g3 ? xh[2] : v[10];
+    v[11] = g3 ? 1.0f : v[11];
 }
 
 // Direction encoding values of lane group g in slot order (8 values).
+template <bool EXACT = true>
 __device__ __forceinline__ void pe_direction(int g, const float d[3], float v[8]) {
     const bool g3 = (g == 3);
-    const float x = g3 ? d[0] : (g == 0 ? d[0] : g == 1 ? d[1] : d[2]);
     float s, c;
-    sincospi(x, s, c);
+    sincos_oct<EXACT>(sel3(g3 ? 0 : g, d), 0, s, c);
     v[0] = s; v[1] = c;
     dbl(v[0], v[1], v[2], v[3]);
     dbl(v[2], v[3], v[4], v[5]);
     dbl(v[4], v[5], v[6], v[7]);
-    if (g3) { v[0] = d[0]; v[1] = d[1]; v[2] = d[2]; v[3] = 1.0f; v[4] = v[5] = v[6] = v[7] = 0.0f; }
+    v[0] = g3 ? d[0] : v[0];
+    v[1] = g3 ? d[1] : v[1];
+    v[2] = g3 ? d[2] : v[2];
+    v[3] = g3 ? 1.0f : v[3];
+#pragma unroll
+    for (int e = 4; e < 8; ++e) v[e] = g3 ? 0.0f : v[e];
+}
+
+// ---------------------------------------------------------------------------
+// MFMA fragments. A K = 32 step is one 16x16x32 BF16/FP16 MFMA, or eight
+// 16x16x4 FP32 MFMAs that use element e of every lane in the e-th
+// instruction; both pair lane (16g + i, element e) of A with lane
+// (16g + j, element e) of B, so one fragment layout serves all three types.
+// ---------------------------------------------------------------------------
+typedef __attribute__((ext_vector_type(8))) float f32x8;
+template <typename T> struct FragT;
+template <> struct FragT<__bf16> { typedef bf16x8 type; };
+template <> struct FragT<_Float16> { typedef f16x8 type; };
+template <> struct FragT<float> { typedef f32x8 type; };
+
+template <typename T>
+__device__ __forceinline__ f32x4 mma(typename FragT<T>::type a, typename FragT<T>::type b, f32x4 c) {
+    if constexpr (__is_same(T, __bf16)) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    } else if constexpr (__is_same(T, _Float16)) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], c, 0, 0, 0);
+        return c;
+    }
+}
+
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+template <typename T>
+__device__ __forceinline__ typename FragT<T>::type pack8(const float* v) {
+    const f32x8 x = {v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]};
+    if constexpr (__is_same(T, float)) {
+        return x;
+    } else if constexpr (__is_same(T, __bf16)) {
+        // one round-to-nearest-even pair conversion per two values
+        u32x4 r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const f32x2 pr = {v[2 * k], v[2 * k + 1]};
+            r[k] = __builtin_bit_cast(unsigned, __builtin_convertvector(pr, bf16x2));
+        }
+        return __builtin_bit_cast(bf16x8, r);
+    } else {
+        return __builtin_convertvector(x, typename FragT<T>::type);
+    }
+}
+
+// Two accumulator tiles as one B operand (elements 0..3 from a, 4..7 from b).
+// For 16-bit types the ReLU is applied after rounding, on the bit patterns:
+// a BF16/FP16 value with the sign bit set is a negative int16, so a packed
+// integer max with 0 zeroes exactly the negative values (and -0).
+typedef __attribute__((ext_vector_type(8))) short i16x8;
+template <typename T, bool RELU>
+__device__ __forceinline__ typename FragT<T>::type hand(f32x4 a, f32x4 b) {
+    float v[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    if constexpr (__is_same(T, float)) {
+        if (RELU) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = __builtin_fmaxf(v[e], 0.0f);
+        }
+        return pack8<T>(v);
+    } else {
+        typename FragT<T>::type r = pack8<T>(v);
+        if (RELU) {
+            i16x8 q = __builtin_bit_cast(i16x8, r);
+            q = __builtin_elementwise_max(q, (i16x8)0);
+            r = __builtin_bit_cast(typename FragT<T>::type, q);
+        }
+        return r;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -160,15 +262,6 @@ struct PackGeom {
     static constexpr int F_L4 = KH16;
     static constexpr int FRAGS16 = F_L1 + F_L2 + F_HD + F_L3 + F_L4;
     static constexpr int BYTES16 = FRAGS16 * WAVE * 16;
-    // FP32 (K = 4 per MFMA), stored as float4 groups of 4 consecutive k-steps
-    static constexpr int KH32 = H / 4;
-    static constexpr int S_L1 = NT * 16;
-    static constexpr int S_L2 = NT * KH32;
-    static constexpr int S_HD = (NT + 1) * KH32;
-    static constexpr int S_L3 = NT * (KH32 + 8);
-    static constexpr int S_L4 = KH32;
-    static constexpr int STEPS32 = S_L1 + S_L2 + S_HD + S_L3 + S_L4;
-    static constexpr int BYTES32 = STEPS32 * WAVE * 4;
     // biases added through the accumulator (L2, HEAD, L4): 16 floats per tile
     static constexpr int BIAS_TILES = NT + (NT + 1) + 1;
     static constexpr int BIAS_FLOATS = BIAS_TILES * 16;
@@ -250,9 +343,8 @@ struct r360_scene {
     int16_t* labels;         // [n2][n1][n0]: field id of occupied voxels, -1 elsewhere
     void* pack16_bf;         // [F][FRAGS16][64][8] bf16
     void* pack16_h;          // [F][FRAGS16][64][8] f16
-    float* pack32;           // [F][STEPS32/4][64][4] f32
     float* bias;             // [F][BIAS_FLOATS]
-    float* pack16_f;         // [F][FRAGS16][64][8] f32: the 16-bit fragment layout in FP32 (backward)
+    float* pack16_f;         // [F][FRAGS16][64][8] f32: the same fragment layout in FP32
     void* packT_bf;          // [F][FRAGS_T][64][8] bf16 transposed fragments (backward)
     void* packT_h;           // [F][FRAGS_T][64][8] f16
     float* packT_f;          // [F][FRAGS_T][64][8] f32
@@ -341,6 +433,11 @@ hipError_t launch_mlp_backward(const r360_scene* s, const Workspace& w, int prec
                                hipStream_t st);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, int64_t step, float lr,
                        float b1, float b2, float eps, hipStream_t st);
+hipError_t launch_global_step(const r360_global_desc* desc, const float* weights, const float* o, const float* d,
+                              int64_t Nr, const float* target, float* loss, float* grad, float* rgb_out,
+                              float* depth_out, float* occ, void* ws, hipStream_t st, int stage_mask);
+size_t global_workspace_bytes(int w, int c, int64_t Nr, int S);
+int64_t global_params(int w, int c);
 hipError_t launch_gradcheck_forward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,
                                     double* rgb64, hipStream_t st);
 hipError_t launch_gradcheck_backward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,

@@ -77,11 +77,18 @@ struct GlobalSink {
         if (voxel) voxel[j] = (int32_t)lin;
     }
 };
-struct LdsSink {
-    int pos; int lane;
-    float *t_mid, *delta; int32_t* tag;
-    __device__ void emit(int k, float tm, float dl, int lab, int64_t) {
-        t_mid[pos + k] = tm; delta[pos + k] = dl; tag[pos + k] = (lane << 16) | lab;
+// Samples whose wave-local position falls inside the window go to LDS, the
+// rest straight to memory.
+struct WindowSink {
+    int pos; int lane; int win;
+    float *l_t, *l_d; int32_t* l_tag;
+    GlobalSink far_;
+    __device__ void emit(int k, float tm, float dl, int lab, int64_t lin) {
+        if (pos + k < win) {
+            l_t[pos + k] = tm; l_d[pos + k] = dl; l_tag[pos + k] = (lane << 16) | lab;
+        } else {
+            far_.emit(k, tm, dl, lab, lin);
+        }
     }
 };
 
@@ -181,10 +188,12 @@ __global__ __launch_bounds__(256) void k_count(RaySource src, DdaParams P, int64
 }
 
 // Pass 2: the same traversal writes the samples at the ray's offset. The 64
-// rays of a wave own one contiguous output range; when it fits the wave's LDS
-// window the samples are emitted there and copied out with coalesced stores,
-// otherwise (and when voxel ids are requested) they go straight to memory.
-constexpr int FILL_WIN = 1024;
+// rays of a wave own one contiguous output range; its first FILL_WIN samples
+// are emitted into the wave's LDS window and copied out with coalesced
+// stores, the rest (and everything when voxel ids are requested) go straight
+// to memory. The window is kept small so that the traversal,
+// which waits on one label load per step, keeps enough waves resident (9 KB per wave).
+constexpr int FILL_WIN = 768;
 
 __global__ __launch_bounds__(256) void k_fill(DdaParams P, int64_t N, const float* __restrict__ o_in,
                                               const float* __restrict__ d_in, const int32_t* __restrict__ off,
@@ -204,13 +213,15 @@ __global__ __launch_bounds__(256) void k_fill(DdaParams P, int64_t N, const floa
 #pragma unroll
         for (int a = 0; a < 3; ++a) { o[a] = o_in[a * N + r]; d[a] = d_in[a * N + r]; }
     }
-    if (wb - wa <= FILL_WIN && voxel == nullptr) {
+    if (voxel == nullptr) {
         if (live) {
-            LdsSink sink{off[r] - wa, lane, l_t[wv], l_d[wv], l_tag[wv]};
+            WindowSink sink{off[r] - wa, lane, FILL_WIN, l_t[wv], l_d[wv], l_tag[wv],
+                            GlobalSink{off[r], (int32_t)r, t_mid, delta, ray, field, nullptr}};
             traverse(P, o, d, sink);
         }
         __builtin_amdgcn_wave_barrier();
-        for (int k = lane; k < wb - wa; k += 64) {
+        const int nwin = min(wb - wa, FILL_WIN);
+        for (int k = lane; k < nwin; k += 64) {
             const int tag = l_tag[wv][k];
             t_mid[wa + k] = l_t[wv][k];
             delta[wa + k] = l_d[wv][k];

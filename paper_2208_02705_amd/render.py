@@ -276,6 +276,60 @@ def adam_step(w, g, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float
                                _stream()))
 
 
+class GlobalField:
+    """The global omnidirectional field stage (8 x width MLP with the encoding
+    re-entering at the fifth layer) on BF16 MFMA GEMMs: forward, loss,
+    backward and the per-cell density max into an occupancy grid."""
+
+    def __init__(self, width: int = 256, color_width: int = 128, n_samples: int = 128, near: float = 0.1,
+                 far: float = 20.0, center=(0.0, 0.0, 0.0), half_extent: float = 4.0, grid_n: int = 128,
+                 grid_lo: float = -4.0, voxel: float = 0.0625):
+        g = _lib.GlobalDesc()
+        g.width, g.color_width, g.n_samples = width, color_width, n_samples
+        g.near_, g.far_ = near, far
+        g.center[:] = list(center)
+        g.half_extent = half_extent
+        g.grid_n[:] = [grid_n] * 3
+        g.grid_lo[:] = [grid_lo] * 3
+        g.voxel = voxel
+        self.desc = g
+        self.P = int(lib().r360_global_params(width, color_width))
+        self._ws = None
+
+    def workspace(self, n_rays: int, device) -> torch.Tensor:
+        need = int(lib().r360_global_workspace_bytes(C.byref(self.desc), n_rays))
+        if need == 0:
+            raise ValueError("invalid global-field description")
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device)
+        return self._ws
+
+    def step(self, weights: torch.Tensor, o: torch.Tensor, d: torch.Tensor, target: Optional[torch.Tensor] = None,
+             occ: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
+        """Returns dict(rgb [3, N], depth [N], loss [1] or None, grad [P] or None)."""
+        weights = _dev(weights, torch.float32, "weights")
+        o = _dev(o, torch.float32, "o"); d = _dev(d, torch.float32, "d")
+        N = o.shape[1]
+        dev = o.device
+        ws = self.workspace(N, dev)
+        rgb = torch.empty(3, N, dtype=torch.float32, device=dev)
+        depth = torch.empty(N, dtype=torch.float32, device=dev)
+        loss = None
+        if target is not None:
+            target = _dev(target, torch.float32, "target")
+            loss = torch.empty(1, dtype=torch.float32, device=dev)
+            grad = torch.empty(self.P, dtype=torch.float32, device=dev) if grad is None else grad
+        else:
+            grad = None
+        if occ is not None:
+            occ = _dev(occ, torch.float32, "occ")
+        check(lib().r360_global_field_step(C.byref(self.desc), _ptr(weights), _ptr(o), _ptr(d), N, _ptr(target),
+                                           _ptr(loss), _ptr(grad), _ptr(rgb), _ptr(depth), _ptr(occ), _ptr(ws),
+                                           ws.numel(), _stream()))
+        return dict(rgb=rgb, depth=depth, loss=loss, grad=grad)
+
+
 def profile_enable(on: bool = True):
     """Per-stage HIP-event timing inside the library (see r360_profile_enable)."""
     check(lib().r360_profile_enable(1 if on else 0))
