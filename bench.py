@@ -4,9 +4,12 @@ A step is one BF16 render of a 2048x1024 equirect view of the synthetic
 room scene (128^3 occupancy grid of walls/furniture boxes plus 2% salt,
 octree-split fields of hidden width 64, up to 64 samples per ray, near
 0.05 m, far 12 m): ray generation, occupied-voxel sampling, routing by
-field, encoding + field MLPs on BF16 MFMA, compositing. The same view in
-the FP32 path and a 65,536-ray forward+backward training step are timed
-beside it. Prints one JSON line.
+field, encoding + field MLPs on BF16 MFMA, compositing. Timed beside it:
+the same view in the FP32 path; a 65,536-ray forward+backward training
+step; the large uneven scene (256^3 grid, 512 Zipf-sized fields) rendered as
+one 4096x2048 equirect view plus four 1920x1080 viewports in BF16, FP16 and
+FP32; and the global 8x256 field's training step over 4,096 rays x 128
+samples. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -25,6 +28,9 @@ METRIC = "Mrays/s render at 2048x1024 equirect (BF16 vs FP32); train-step ms per
 W, H = 2048, 1024
 FLOP_PER_SAMPLE_FWD = 36608          # 2 x 18,304 MACs of the hidden-64 field MLP
 FLOP_PER_SAMPLE_TRAIN = 98304        # forward + dW + dX MACs x 2
+# global 8x256 field, per sample and training step: forward 593,408 MACs,
+# weight gradients the same, input gradients 557,696 MACs (none into the encoding)
+FLOP_PER_SAMPLE_GLOBAL = 2 * (593408 + 593408 + 557696)
 PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0
 
@@ -36,7 +42,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-train", action="store_true")
-    p.add_argument("--only", choices=["bf16", "fp32", "train"], default=None,
+    p.add_argument("--no-large", action="store_true")
+    p.add_argument("--no-global", action="store_true")
+    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global"], default=None,
                    help="time only one leg (for profiler runs)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB mebibytes (to calibrate HBM byte counters)")
@@ -101,7 +109,7 @@ def main():
         del r
         return sec, prof
 
-    legs = ["bf16", "fp32", "train"] if args.only is None else [args.only]
+    legs = ["bf16", "fp32", "train", "large", "global"] if args.only is None else [args.only]
     res = {}
     if "bf16" in legs:
         res["bf16"] = leg("bf16", args.steps, args.warmup)
@@ -113,6 +121,13 @@ def main():
             train = train_leg(R, sc, scene, args)
         except R.R360Error as e:
             train = {"error": str(e)}
+
+    large = None
+    if "large" in legs and not args.no_large:
+        large = large_leg(R, args)
+    glob = None
+    if "global" in legs and not args.no_global:
+        glob = global_leg(R, args)
 
     main_prec = "bf16" if "bf16" in res else next(iter(res), None)
     line = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -154,6 +169,10 @@ def main():
         line[f"{prec}_mlp_tflops"] = S * FLOP_PER_SAMPLE_FWD / (m[0] / max(m[1], 1) * 1e-3) / 1e12
     if train is not None:
         line["train_step"] = train
+    if large is not None:
+        line["large_uneven"] = large
+    if glob is not None:
+        line["global_field"] = glob
     line["context"] = ("paper: 360Roam renders a 1520x760 panorama in 0.03 s on one RTX2080 Ti (about 38.5 Mrays/s, "
                        "precision not stated) and runs in real time on a GTX1080; different hardware and scenes")
     if not args.no_cpu_baseline and args.only is None:
@@ -212,6 +231,87 @@ def train_leg(R, sc, scene, args):
     st = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
     return {"rays": N, "samples": S, "ms_fwd_bwd": sec * 1e3, "ms_with_adam": sec_full * 1e3,
             "stages_ms": st, "tflops_fwd_bwd": S * FLOP_PER_SAMPLE_TRAIN / sec / 1e12, "loss": float(loss.item())}
+
+
+def large_leg(R, args):
+    """Large uneven scene (256^3 grid, 512 Zipf(1.2)-sized fields, hidden 64,
+    up to 96 samples): one 4096x2048 equirect view plus four 1920x1080 90-degree
+    viewports (the four quarter-turn yaws) per sequence, in BF16, FP16 and FP32."""
+    import torch
+    import synth
+    sc = synth.scene_large()
+    scene = R.Scene.from_synth(sc)
+    EW, EH, PW, PH = 4096, 2048, 1920, 1080
+    rays = EW * EH + 4 * PW * PH
+    out = {"rays_per_sequence": rays, "n_fields": sc.n_fields, "max_samples": sc.max_samples}
+    steps = max(3, args.steps // 10)
+    for prec in ("bf16", "fp16", "fp32"):
+        eqr = R.EquirectRenderer(scene, EW, EH, precision=prec)
+        phs = [R.PinholeRenderer(scene, PW, PH, PW / 2, PW / 2, precision=prec) for _ in range(4)]
+        yaws = [synth.c2w_yaw((0.0, 0.0, 0.0), q) for q in range(4)]
+
+        def seq():
+            eqr(synth.IDENTITY_C2W)
+            for r, c in zip(phs, yaws):
+                r(c)
+        R.profile_read()
+        R.profile_enable(True)
+        sec = timed(seq, steps, 1)
+        prof = R.profile_read()
+        R.profile_enable(False)
+        # five launches per sequence; the profile also holds the warm-up sequence
+        out[prec] = {"mrays_per_s": rays / sec / 1e6, "ms_per_sequence": sec * 1e3,
+                     "stages_ms_per_sequence": {k: v[0] / (v[1] / 5) for k, v in prof.items() if v[1]}}
+        del eqr, phs
+    smp = R.sample_rays(scene, *R.Equirect(EW, EH).rays(synth.IDENTITY_C2W), with_voxel=False)
+    out["equirect_samples"] = int(smp["t_mid"].numel())
+    del smp, scene
+    torch.cuda.empty_cache()
+    return out
+
+
+def global_leg(R, args):
+    """Global 8x256 field stage: 4,096 rays x 128 inverse-depth samples,
+    forward + L2 loss + backward + per-cell density max (BF16 MFMA GEMMs,
+    FP32 accumulation)."""
+    import numpy as np
+    import torch
+    import synth
+    N = 4096
+    sc = synth.scene_room(with_weights=False)
+    cams = synth.camera_centres(sc, 20)
+    cam, u, v = synth.ray_draws(N, 20, W, H)
+    eq = R.Equirect(W, H)
+    o = torch.empty(3, N, device="cuda"); d = torch.empty(3, N, device="cuda")
+    for k in range(20):
+        sel = np.nonzero(cam == k)[0]
+        if len(sel) == 0:
+            continue
+        ok, dk = eq.rays(synth.c2w_at(cams[k]), torch.from_numpy(v[sel].astype(np.int64) * W + u[sel]).cuda())
+        idx = torch.from_numpy(sel).cuda()
+        o[:, idx] = ok; d[:, idx] = dk
+    gf = R.GlobalField()
+    w = torch.from_numpy(synth.xavier_weights(synth.global_mlp_layout(), 1, synth.MASTER_SEED,
+                                              synth.STREAM_WEIGHTS)[0]).cuda()
+    tgt = torch.from_numpy(synth.uniform(synth.MASTER_SEED, synth.STREAM_NOISE,
+                                         np.arange(3 * N, dtype=np.uint64)).reshape(3, N).astype(np.float32)).cuda()
+    occ = torch.zeros(128, 128, 128, device="cuda")
+    grad = torch.empty(gf.P, device="cuda")
+
+    def step():
+        gf.step(w, o, d, target=tgt, occ=occ, grad=grad)
+    R.profile_read()
+    R.profile_enable(True)
+    steps = max(5, args.steps // 5)
+    sec = timed(step, steps, 2)
+    prof = R.profile_read()
+    R.profile_enable(False)
+    S = N * gf.desc.n_samples
+    tf = S * FLOP_PER_SAMPLE_GLOBAL / sec / 1e12
+    return {"rays": N, "samples": S, "params": gf.P, "ms_per_step": sec * 1e3,
+            "msamples_per_s": S / sec / 1e6, "tflops": tf, "frac_bf16_peak": tf / PEAK["bf16"],
+            "flop_per_sample": FLOP_PER_SAMPLE_GLOBAL,
+            "stages_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
 
 
 def cpu_baseline(sc):

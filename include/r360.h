@@ -257,9 +257,10 @@ r360_status r360_global_field_step(const r360_global_desc* desc, const float* we
 
 /* Optional per-stage timing for benchmarking: when enabled, every entry
  * point records a HIP event pair around each stage of its launch sequence on
- * the call's own stream. Stages: 0 sampling (count + scan + fill), 1 routing,
+ * the call's own stream. Stages: 0 sampling (traversal + scan + compaction), 1 routing,
  * 2 field-MLP forward, 3 compositing, 4 loss, 5 compositing backward,
- * 6 field-MLP backward, 7 gradient reduction. */
+ * 6 field-MLP backward (with the per-field gradient reduction), 7 the whole
+ * global-field step. */
 #define R360_NSTAGES 8
 r360_status r360_profile_enable(int32_t on);
 /* Waits for the recorded events and returns, per stage, the milliseconds and

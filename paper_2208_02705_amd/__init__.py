@@ -8,6 +8,6 @@ arguments (ctypes) and provides torch.autograd wrappers. The shared library
 is loaded on first use and its absence is an error.
 """
 from ._lib import R360Error, FP32, BF16, FP16, FP64_GRADCHECK, LIB_PATH  # noqa: F401
-from .render import (Scene, Equirect, EquirectRenderer, RenderFunction, GradcheckFunction,  # noqa: F401
+from .render import (Scene, Equirect, EquirectRenderer, PinholeRenderer, RenderFunction, GradcheckFunction,  # noqa: F401
                      sample_rays, render_rays, render_equirect, render_pinhole, backward, train_step, adam_step,
                      field_params, lr_at, profile_enable, profile_read, GlobalField)

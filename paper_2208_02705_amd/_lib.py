@@ -17,7 +17,7 @@ FP32, BF16, FP16, FP64_GRADCHECK = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp64": FP64_GRADCHECK}
 NSTAGES = 8
 STAGES = ["sample", "route", "mlp_forward", "composite", "loss", "composite_backward", "mlp_backward",
-          "grad_reduce"]
+          "global_field"]
 
 
 class GridDesc(C.Structure):

@@ -27,6 +27,7 @@ namespace r360 {
 namespace {
 
 typedef __bf16 bf16;
+typedef unsigned u32;
 
 // ---------------------------------------------------------------------------
 // Layer matrices. All layers are stored as BF16 [N][K] (row = output, K
@@ -121,6 +122,13 @@ struct GNetDev {
     int64_t P;
     GLayerGeom L[NGL];
 };
+
+// Zero fill of the BF16 arena: the padding of every layer matrix (columns
+// past K's real inputs, rows past N in the transposes) must hold 0, since
+// the GEMMs contract over it against zero activations and 0 * NaN is NaN.
+__global__ void k_gzero(u32* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
 
 // FP32 canonical weights -> BF16 layer matrices, their transposes and the
 // FP32 epilogue biases (one thread per canonical parameter).
@@ -497,6 +505,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     const int64_t M = Nr * S;
     GlobalWs g = gcarve(ws, n, Nr, S);
     const unsigned nbP = (unsigned)((n.P + 255) / 256);
+    hipLaunchKernelGGL(k_gzero, dim3(256), dim3(256), 0, st, reinterpret_cast<u32*>(g.arena), (n.w_elems + 1) / 2);
     hipLaunchKernelGGL(k_gnet_pack, dim3(nbP), dim3(256), 0, st, nd, weights, g.arena, g.bias);
     // samples and encodings
     GSampleArgs sa;

@@ -6,9 +6,12 @@
 // occupied voxel segment of positive length (Sec. 4.2 dense sampling of the
 // occupied voxels; Sec. 5 ray casting over the labelled occupancy map).
 //
-// Two passes over the rays (count, then fill at scanned offsets) keep each
-// ray's samples contiguous and in t order, so compositing reads one
-// contiguous run per ray and the whole result is deterministic.
+// One traversal per ray writes sample k of ray r to slot k*N + r of
+// staging arrays (neighbouring lanes write neighbouring addresses, so every
+// store is coalesced) and its count; after an exclusive scan of the counts a
+// compaction pass moves each ray's samples to one contiguous run in t order
+// at its offset, so compositing reads one run per ray and the whole result
+// is deterministic.
 //
 // Bit-exact contract: this file is compiled without floating-point
 // contraction; every operation below is a correctly rounded FP32 add, mul,
@@ -59,36 +62,23 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 }
 
 // Voxel traversal. Emits (t_mid, delta, voxel, field) for the first
-// max_samples occupied segments; returns the count. With FILL false only
+// max_samples occupied segments; returns the count. With a CountSink only
 // counts. Per step only the crossed axis's next-plane distance changes; the
 // others are reused (their plane index did not change, so the recomputation
 // would give the same bits).
-// Where emitted samples go: nowhere (count pass), straight to the global
-// arrays, or to the wave's LDS window (packed lane << 16 | field).
 struct CountSink {
     __device__ void emit(int, float, float, int, int64_t) {}
 };
-struct GlobalSink {
-    int64_t base; int32_t ray_id;
-    float *t_mid, *delta; int32_t *ray, *field, *voxel;
-    __device__ void emit(int k, float tm, float dl, int lab, int64_t lin) {
-        const int64_t j = base + k;
-        t_mid[j] = tm; delta[j] = dl; ray[j] = ray_id; field[j] = lab;
-        if (voxel) voxel[j] = (int32_t)lin;
-    }
-};
-// Samples whose wave-local position falls inside the window go to LDS, the
-// rest straight to memory.
-struct WindowSink {
-    int pos; int lane; int win;
-    float *l_t, *l_d; int32_t* l_tag;
-    GlobalSink far_;
-    __device__ void emit(int k, float tm, float dl, int lab, int64_t lin) {
-        if (pos + k < win) {
-            l_t[pos + k] = tm; l_d[pos + k] = dl; l_tag[pos + k] = (lane << 16) | lab;
-        } else {
-            far_.emit(k, tm, dl, lab, lin);
-        }
+// Sample k of ray r goes to slot k*N + r (k < max_samples, so the slot stays
+// below N * max_samples < 2^31).
+struct SlotSink {
+    int N, r;
+    float *t, *dl;
+    int32_t *fld, *vox;
+    __device__ void emit(int k, float tm, float d, int lab, int64_t lin) {
+        const int j = k * N + r;
+        t[j] = tm; dl[j] = d; fld[j] = lab;
+        if (vox) vox[j] = (int32_t)lin;
     }
 };
 
@@ -170,11 +160,15 @@ __global__ __launch_bounds__(256) void k_rays(RaySource src, int64_t N, float* _
     for (int a = 0; a < 3; ++a) { o[a * N + r] = oo[a]; d[a * N + r] = dd[a]; }
 }
 
-// Pass 1: per-ray sample counts into ray_off[r]; generated rays are stored
-// for the later passes.
+// Pass 1: traversal. Per-ray sample counts go to ray_off[r], the samples to
+// the staging slots; generated rays are stored for the later passes.
+struct Staging {
+    float* t; float* dl; int32_t* fld; int32_t* vox;
+};
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_count(RaySource src, DdaParams P, int64_t N, int32_t* __restrict__ cnt,
-                                               float* __restrict__ o_ws, float* __restrict__ d_ws) {
+__global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64_t N, int32_t* __restrict__ cnt,
+                                               float* __restrict__ o_ws, float* __restrict__ d_ws, Staging sg) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
     float o[3], d[3];
@@ -183,54 +177,57 @@ __global__ __launch_bounds__(256) void k_count(RaySource src, DdaParams P, int64
 #pragma unroll
         for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
     }
-    CountSink sink;
+    SlotSink sink{(int)N, (int)r, sg.t, sg.dl, sg.fld, sg.vox};
     cnt[r] = traverse(P, o, d, sink);
 }
 
-// Pass 2: the same traversal writes the samples at the ray's offset. The 64
-// rays of a wave own one contiguous output range; its first FILL_WIN samples
-// are emitted into the wave's LDS window and copied out with coalesced
-// stores, the rest (and everything when voxel ids are requested) go straight
-// to memory. The window is kept small so that the traversal,
-// which waits on one label load per step, keeps enough waves resident (9 KB per wave).
-constexpr int FILL_WIN = 768;
+// Pass 2 (after the scan): compaction. The 64 rays of a wave own one
+// contiguous output range; it is assembled window by window in LDS (each
+// lane reads its own staging slots, coalesced across the wave) and written
+// out with coalesced stores.
+constexpr int CWIN = 512;
 
-__global__ __launch_bounds__(256) void k_fill(DdaParams P, int64_t N, const float* __restrict__ o_in,
-                                              const float* __restrict__ d_in, const int32_t* __restrict__ off,
-                                              float* __restrict__ t_mid, float* __restrict__ delta,
-                                              int32_t* __restrict__ ray, int32_t* __restrict__ field,
-                                              int32_t* __restrict__ voxel) {
-    __shared__ float l_t[4][FILL_WIN], l_d[4][FILL_WIN];
-    __shared__ int32_t l_tag[4][FILL_WIN];
+__global__ __launch_bounds__(256) void k_compact(int64_t N, const int32_t* __restrict__ off, Staging sg,
+                                                 float* __restrict__ t_mid, float* __restrict__ delta,
+                                                 int32_t* __restrict__ ray, int32_t* __restrict__ field,
+                                                 int32_t* __restrict__ voxel) {
+    __shared__ float l_t[4][CWIN], l_d[4][CWIN];
+    __shared__ int32_t l_g[4][CWIN], l_v[4][CWIN];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
     if (r0 >= N) return;
     const int64_t r = r0 + lane;
     const bool live = r < N;
     const int wa = off[r0], wb = off[min(r0 + 64, N)];
-    float o[3] = {0.f, 0.f, 0.f}, d[3] = {0.f, 0.f, 0.f};
-    if (live) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) { o[a] = o_in[a * N + r]; d[a] = d_in[a * N + r]; }
-    }
-    if (voxel == nullptr) {
-        if (live) {
-            WindowSink sink{off[r] - wa, lane, FILL_WIN, l_t[wv], l_d[wv], l_tag[wv],
-                            GlobalSink{off[r], (int32_t)r, t_mid, delta, ray, field, nullptr}};
-            traverse(P, o, d, sink);
+    const int mine = live ? off[r] - wa : 0;
+    const int cnt = live ? off[r + 1] - off[r] : 0;
+    const bool with_vox = voxel != nullptr;
+    for (int base = 0; base < wb - wa; base += CWIN) {
+        const int k0 = max(0, base - mine), k1 = min(cnt, base + CWIN - mine);
+        for (int k = k0; k < k1; ++k) {
+            const int j = k * (int)N + (int)r;
+            const int q = mine + k - base;
+            l_t[wv][q] = sg.t[j];
+            l_d[wv][q] = sg.dl[j];
+            l_g[wv][q] = (lane << 16) | sg.fld[j];
+            if (with_vox) l_v[wv][q] = sg.vox[j];
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const int nwin = min(wb - wa, FILL_WIN);
-        for (int k = lane; k < nwin; k += 64) {
-            const int tag = l_tag[wv][k];
-            t_mid[wa + k] = l_t[wv][k];
-            delta[wa + k] = l_d[wv][k];
-            ray[wa + k] = (int32_t)(r0 + (tag >> 16));
-            field[wa + k] = tag & 0xFFFF;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int nwin = min(wb - wa - base, CWIN);
+        const int at = wa + base;
+        for (int q = lane; q < nwin; q += 64) {
+            const int tag = l_g[wv][q];
+            t_mid[at + q] = l_t[wv][q];
+            delta[at + q] = l_d[wv][q];
+            ray[at + q] = (int32_t)(r0 + (tag >> 16));
+            field[at + q] = tag & 0xFFFF;
+            if (with_vox) voxel[at + q] = l_v[wv][q];
         }
-    } else if (live) {
-        GlobalSink sink{off[r], (int32_t)r, t_mid, delta, ray, field, voxel};
-        traverse(P, o, d, sink);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -343,12 +340,15 @@ hipError_t launch_rays(const RaySource& src, int64_t N, float* o, float* d, hipS
 hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w,
                          int32_t* voxel_out, hipStream_t st) {
     const unsigned nb = blocks_for(N, 256);
+    // staging slots live in the sigma/rgb arrays, which are not needed until the field MLPs run
+    const Staging sg{w.sigma, w.rgb, reinterpret_cast<int32_t*>(w.rgb + w.cap),
+                     voxel_out ? reinterpret_cast<int32_t*>(w.rgb + 2 * w.cap) : nullptr};
     if (src.mode == RAYS_EQUIRECT)
-        hipLaunchKernelGGL(k_count<RAYS_EQUIRECT>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d);
+        hipLaunchKernelGGL(k_trace<RAYS_EQUIRECT>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
     else if (src.mode == RAYS_PINHOLE)
-        hipLaunchKernelGGL(k_count<RAYS_PINHOLE>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d);
+        hipLaunchKernelGGL(k_trace<RAYS_PINHOLE>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
     else
-        hipLaunchKernelGGL(k_count<RAYS_GIVEN>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d);
+        hipLaunchKernelGGL(k_trace<RAYS_GIVEN>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned ns = blocks_for(N, SCAN_TILE);
@@ -357,10 +357,8 @@ hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, co
     hipLaunchKernelGGL(k_scan_down, dim3(ns), dim3(1024), 0, st, w.ray_off, N, w.scan);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const float* o = src.mode == RAYS_GIVEN ? src.o : w.o;
-    const float* d = src.mode == RAYS_GIVEN ? src.d : w.d;
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(N, 256)), dim3(256), 0, st, p, N, o, d, w.ray_off, w.t_mid, w.delta,
-                       w.ray, w.field, voxel_out);
+    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, st, N, w.ray_off, sg, w.t_mid, w.delta, w.ray, w.field,
+                       voxel_out);
     return hipGetLastError();
 }
 

@@ -225,17 +225,30 @@ def render_equirect(scene: Scene, W: int, H: int, c2w, **kw):
     return rgb.clone(), depth.clone(), opac.clone()
 
 
-def render_pinhole(scene: Scene, W: int, H: int, fx: float, fy: float, c2w, *, precision="bf16", near=None,
-                   far=None, max_samples=None):
-    opts = _opts(scene, near, far, max_samples, precision)
-    ws = scene.workspace(W * H, opts.max_samples)
-    dev = scene.device
-    rgb = torch.empty(3, H, W, dtype=torch.float32, device=dev)
-    depth = torch.empty(H, W, dtype=torch.float32, device=dev)
-    opac = torch.empty(H, W, dtype=torch.float32, device=dev)
-    check(lib().r360_render_pinhole(scene._h, W, H, fx, fy, _lib.c2w_arg(c2w), C.byref(opts), _ptr(rgb),
-                                    _ptr(depth), _ptr(opac), _ptr(ws), ws.numel(), _stream()))
-    return rgb, depth, opac
+class PinholeRenderer:
+    """Renders W x H perspective viewports (focal lengths fx, fy in pixels);
+    owns the output buffers and shares the scene's workspace."""
+
+    def __init__(self, scene: Scene, W: int, H: int, fx: float, fy: float, *, precision="bf16", near=None,
+                 far=None, max_samples=None):
+        self.scene, self.W, self.H, self.fx, self.fy = scene, W, H, fx, fy
+        self.opts = _opts(scene, near, far, max_samples, precision)
+        self.ws = scene.workspace(W * H, self.opts.max_samples)
+        dev = scene.device
+        self.rgb = torch.empty(3, H, W, dtype=torch.float32, device=dev)
+        self.depth = torch.empty(H, W, dtype=torch.float32, device=dev)
+        self.opacity = torch.empty(H, W, dtype=torch.float32, device=dev)
+
+    def __call__(self, c2w):
+        check(lib().r360_render_pinhole(self.scene._h, self.W, self.H, self.fx, self.fy, _lib.c2w_arg(c2w),
+                                        C.byref(self.opts), _ptr(self.rgb), _ptr(self.depth), _ptr(self.opacity),
+                                        _ptr(self.ws), self.ws.numel(), _stream()))
+        return self.rgb, self.depth, self.opacity
+
+
+def render_pinhole(scene: Scene, W: int, H: int, fx: float, fy: float, c2w, **kw):
+    r = PinholeRenderer(scene, W, H, fx, fy, **kw)
+    return r(c2w)
 
 
 def backward(scene: Scene, o, d, grad_rgb, *, precision="fp32", near=None, far=None, max_samples=None,

@@ -92,8 +92,7 @@ def _compare_samples(mine, ref):
 
 
 def _both_paths(R, scene, o, d, ref, **kw):
-    # with voxel ids the samples are written straight to memory; without,
-    # through the per-wave LDS window (the path renders take)
+    # with and without voxel ids (renders request none)
     _compare_samples(R.sample_rays(scene, _t(o), _t(d), **kw), ref)
     _compare_samples(R.sample_rays(scene, _t(o), _t(d), with_voxel=False, **kw), ref)
 
@@ -102,6 +101,18 @@ def test_sampling_bitexact_small_config(R, orc, small):
     sc, scene = small
     o, d = orc.equirect_rays(256, 128, synth.IDENTITY_C2W)
     _both_paths(R, scene, o, d, orc.sample_rays(sc, o, d))
+
+
+def test_sampling_bitexact_dense_grid_many_windows(R, orc):
+    """A fully occupied 32^3 grid: ~50 samples per ray, so a wave's 64 rays
+    own several thousand samples and the compaction runs over many windows;
+    the ray count leaves a ragged last wave."""
+    sc = synth.tiny_scene(32, 61, p_occ=1.0, n_fields=5, max_samples=64)
+    scene = R.Scene.from_synth(sc)
+    o, d = _random_rays(1000, 61, lo=-3.9, hi=3.9)
+    ref = orc.sample_rays(sc, o, d)
+    assert np.diff(ref["offsets"]).max() > 40
+    _both_paths(R, scene, o, d, ref)
 
 
 def test_sampling_bitexact_headline_config(R, orc, room):
@@ -186,6 +197,40 @@ def test_render_headline_full_size_sampled(R, orc, room, prec):
     else:
         _check_x16(mine, ref_rgb)
         _check_x16(_np(op).reshape(-1)[pix], ref_op)
+
+
+@pytest.fixture(scope="module")
+def large(R):
+    sc = synth.scene_large()
+    return sc, R.Scene.from_synth(sc)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_render_large_uneven_sampled(R, orc, large, prec):
+    """The large uneven scene (256^3 grid, 512 Zipf-sized fields, up to 96
+    samples) in the launch sequence the benchmark times: one 4096x2048
+    equirect view, then four 1920x1080 90-degree viewports; sampled pixels of
+    each against the oracle."""
+    import torch
+    sc, scene = large
+    er = R.EquirectRenderer(scene, 4096, 2048, precision=prec)
+    rgb, _, op = er(synth.IDENTITY_C2W)
+    pix = np.arange(0, 4096 * 2048, 1021, dtype=np.int64)
+    o, d = orc.equirect_rays(4096, 2048, synth.IDENTITY_C2W, pix)
+    ref_rgb, _, ref_op = orc.render_rays(sc, o, d)
+    check = _check_fp32 if prec == "fp32" else _check_x16
+    check(_np(rgb).reshape(3, -1)[:, pix], ref_rgb)
+    check(_np(op).reshape(-1)[pix], ref_op)
+    for q in range(4):
+        c2w = synth.c2w_yaw((0.0, 0.0, 0.0), q)
+        pr = R.PinholeRenderer(scene, 1920, 1080, 960.0, 960.0, precision=prec)
+        rgb, _, _ = pr(c2w)
+        pix = np.arange(q, 1920 * 1080, 2039, dtype=np.int64)
+        o, d = orc.pinhole_rays(1920, 1080, 960.0, 960.0, c2w)
+        ref_rgb, _, _ = orc.render_rays(sc, o[:, pix], d[:, pix])
+        check(_np(rgb).reshape(3, -1)[:, pix], ref_rgb)
+        del pr
+    torch.cuda.synchronize()
 
 
 def test_render_pinhole_viewport(R, orc, room):
