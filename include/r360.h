@@ -59,9 +59,9 @@ typedef enum {
 } r360_precision;
 
 /* Occupancy grid: n[0] x n[1] x n[2] voxels of edge `voxel` (a power of two)
- * from corner lo; voxel (i, j, k) is element i + n0 (j + n1 k) (x fastest).
- * A voxel is occupied where its probability is strictly larger than
- * `threshold` (Sec. 4.1: "larger than the threshold"). */
+ * from corner lo; voxel (i, j, k) is element i + n0 (j + n1 k) (x fastest);
+ * each n[a] in [1, 4096] and fewer than 2^31 voxels in all. A voxel is
+ * occupied where its probability is strictly above `threshold` (Sec. 4.1). */
 typedef struct {
     int32_t n[3];
     float lo[3];

@@ -106,9 +106,9 @@ void to_world(const float* c2w, const float dc[3], float o[3], float d[3]) {
 }
 
 // ---------------------------------------------------------------------------
-// Occupancy-grid sampling: voxel traversal in FP32 (Sec. 4.2 fine-tuning
-// "densely sample the occupied voxels", Sec. 5 ray casting over the labelled
-// occupancy map). One midpoint sample per occupied voxel segment, with the
+// Occupancy-grid sampling: voxel traversal in FP32 (Sec. 4.2: fine-tuning
+// samples densely inside the occupied voxels; Sec. 5: rays are cast over the
+// labelled occupancy map). One midpoint sample per occupied voxel segment, with the
 // segment length as its interval, the first max_samples in increasing t.
 // ---------------------------------------------------------------------------
 struct Seg { float t_mid, delta; int32_t voxel, field; };
@@ -678,8 +678,8 @@ double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float*
 }
 
 // ---- global omnidirectional field ----------------------------------------
-// Sample placement uniform in inverse depth over [near, far] (Sec. 3.2:
-// sampling "in inverse distance"), FP32 spec:
+// Sample placement uniform in inverse depth over [near, far] (Sec. 3.2
+// places the global field's samples evenly in inverse distance), FP32 spec:
 //   a = 1/near, b = 1/far, s_i = i / (N - 1), t_i = 1 / fma(s_i, b, (1 - s_i) a),
 // which gives 1/near and 1/far exactly at the two ends;
 //   delta_i = t_{i+1} - t_i, and delta_{N-1} = 0.

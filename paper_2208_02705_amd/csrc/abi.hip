@@ -210,6 +210,7 @@ r360_status r360_scene_create(const r360_grid_desc* grid, const float* occ_prob,
         if (!std::isfinite(grid->lo[a])) return inval("grid corner not finite");
     }
     if (!pow2(grid->voxel)) return inval("voxel edge must be a positive power of two");
+    if ((int64_t)grid->n[0] * grid->n[1] * grid->n[2] >= (int64_t(1) << 31)) return inval("grid has 2^31 voxels or more");
     if (std::isnan(grid->threshold)) return inval("threshold is NaN");
     if (mlp->n_fields < 1 || mlp->n_fields > 16384) return inval("n_fields outside [1, 16384]");
     if (!(mlp->half_extent > 0.0f) || !std::isfinite(mlp->half_extent)) return inval("half_extent must be positive");
@@ -555,6 +556,7 @@ static r360_status check_global(const r360_global_desc* g) {
     if (!(g->half_extent > 0.0f) || !pow2(g->voxel)) return inval("half_extent > 0 and a power-of-two voxel");
     for (int a = 0; a < 3; ++a)
         if (g->grid_n[a] < 1 || g->grid_n[a] > 4096) return inval("grid size outside [1, 4096]");
+    if ((int64_t)g->grid_n[0] * g->grid_n[1] * g->grid_n[2] >= (int64_t(1) << 31)) return inval("grid has 2^31 voxels or more");
     return R360_OK;
 }
 

@@ -169,6 +169,7 @@ __device__ __forceinline__ void dw_stage(const T* panel, int pstride, int XR, in
 #pragma unroll
     for (int q = 0; q < NACC; ++q) {
         const int k = wv + BW * q;
+        __builtin_amdgcn_sched_barrier(0);
         if (k < OT * IT) {
             const int ot = k / IT, it = k % IT;
 #pragma unroll
@@ -183,6 +184,10 @@ __device__ __forceinline__ void dw_stage(const T* panel, int pstride, int XR, in
 
 template <int H, int NACC>
 __device__ __forceinline__ void dw_flush(int ly, int OT, int IT, int wv, int lane, f32x4* acc, float* dst) {
+    // opaque copies: the flush indices are recomputed here, once per field,
+    // instead of being hoisted out of the field loop into live registers
+    asm volatile("" : "+v"(lane));
+    asm volatile("" : "+v"(wv));
     const int g = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int q = 0; q < NACC; ++q) {
@@ -237,6 +242,8 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             // Keep the weight fragments out of registers across chunks: the
             // compiler would otherwise hoist all ~70 per-field fragment loads
             // out of this loop and spill. They are re-read from L1/L2 instead.
+            // The scheduling barriers below likewise keep each phase's loads
+            // within that phase.
             const F8* Pc = P;
             const F8* PTc = PT;
             asm volatile("" : "+v"(Pc));
@@ -251,6 +258,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) xh[k] = (__builtin_fmaf(t, dv[k], a.o[k * a.N + r]) - cc[k]) * a.inv_h;
 
+            __builtin_amdgcn_sched_barrier(0);
             // ---- forward recompute ----
             F8 x0, x1;
             {
@@ -267,6 +275,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 acc[ot] = mma<T>(q[(2 * ot) * WAVE], x0, acc[ot]);
                 acc[ot] = mma<T>(q[(2 * ot + 1) * WAVE], x1, acc[ot]);
             }
+            __builtin_amdgcn_sched_barrier(0);
             q += G::F_L1 * WAVE;
             F8 h1[KH], h2[KH], fb[KH], h3[KH];
 #pragma unroll
@@ -277,6 +286,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) acc[ot] = mma<T>(q[(ot * KH + ks) * WAVE], h1[ks], acc[ot]);
             }
+            __builtin_amdgcn_sched_barrier(0);
             q += G::F_L2 * WAVE;
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) h2[ks] = hand<T, true>(acc[2 * ks], acc[2 * ks + 1]);
@@ -286,6 +296,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) acc[ot] = mma<T>(q[(ot * KH + ks) * WAVE], h2[ks], acc[ot]);
             }
+            __builtin_amdgcn_sched_barrier(0);
             q += G::F_HD * WAVE;
             const float zs = acc[NT][0];
 #pragma unroll
@@ -303,6 +314,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 for (int ks = 0; ks < KH; ++ks) acc[ot] = mma<T>(q[(ot * (KH + 1) + ks) * WAVE], fb[ks], acc[ot]);
                 acc[ot] = mma<T>(q[(ot * (KH + 1) + KH) * WAVE], xd, acc[ot]);
             }
+            __builtin_amdgcn_sched_barrier(0);
             q += G::F_L3 * WAVE;
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) h3[ks] = hand<T, true>(acc[2 * ks], acc[2 * ks + 1]);
@@ -310,6 +322,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) o4 = mma<T>(q[ks * WAVE], h3[ks], o4);
 
+            __builtin_amdgcn_sched_barrier(0);
             // ---- output gradients (lane group 0 holds rows 0..3 of each tile) ----
             float dzs = 0.0f;
             f32x4 dz4 = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -346,6 +359,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                         if (!((float)hb[tt >> 1][4 * (tt & 1) + rr] > 0.0f)) dz[tt][rr] = 0.0f;
             };
 
+            __builtin_amdgcn_sched_barrier(0);
             // ---- L4: dW4 and dh3 = W4^T dz4 ----
             put_hidden(0, h3);
             put_ones(H);
@@ -360,6 +374,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 for (int ot = 0; ot < NT; ++ot) dz[ot] = mma<T>(PTc[ot * WAVE], bz, f32x4{0.f, 0.f, 0.f, 0.f});
             }
             mask(dz, h3);
+            __builtin_amdgcn_sched_barrier(0);
             // ---- L3: dW3 over [f ; g(d)] and df = W3_f^T dz3 ----
             put_hidden(0, fb);
 #pragma unroll
@@ -382,6 +397,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 }
             }
             df[NT] = f32x4{dzs, 0.f, 0.f, 0.f};           // the sigma row H sits in tile NT, row 0
+            __builtin_amdgcn_sched_barrier(0);
             // ---- HEAD: d[Wf ; ws] and dh2 = [Wf ; ws]^T [df ; dzs] ----
             put_hidden(0, h2);
             put_ones(H);
@@ -406,6 +422,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 }
             }
             mask(dz, h2);
+            __builtin_amdgcn_sched_barrier(0);
             // ---- L2: dW2 and dh1 = W2^T dz2 ----
             put_hidden(0, h1);
             put_ones(H);
@@ -429,6 +446,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 for (int ot = 0; ot < NT; ++ot) dz[ot] = t1[ot];
             }
             mask(dz, h1);
+            __builtin_amdgcn_sched_barrier(0);
             // ---- L1: dW1 over the encoding slots ----
 #pragma unroll
             for (int s2 = 0; s2 < 8; ++s2) {

@@ -20,17 +20,31 @@ constexpr int CCH = 512;                      // samples per staged chunk and wa
 
 struct Stage6 { float s[CCH], dl[CCH], t[CCH], r[CCH], g[CCH], b[CCH]; };
 
+// All loads of a chunk are issued before any LDS store, so the wave waits
+// for memory once per chunk rather than once per 64 samples.
 __device__ __forceinline__ void stage_chunk(Stage6& L, int base, int end, int lane, int64_t cap,
                                             const float* __restrict__ sigma, const float* __restrict__ rgb,
                                             const float* __restrict__ t_mid, const float* __restrict__ delta) {
-    for (int k = lane; k < CCH && base + k < end; k += 64) {
-        const int i = base + k;
-        L.s[k] = sigma[i];
-        L.dl[k] = delta[i];
-        L.t[k] = t_mid ? t_mid[i] : 0.0f;
-        L.r[k] = rgb[i];
-        L.g[k] = rgb[cap + i];
-        L.b[k] = rgb[2 * cap + i];
+    constexpr int IT = CCH / 64;
+    float v[IT][6];
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+        const int i0 = base + lane + 64 * u;
+        const int i = i0 < end ? i0 : base;           // base < end: an in-range stand-in
+        v[u][0] = sigma[i];
+        v[u][1] = delta[i];
+        v[u][2] = t_mid ? t_mid[i] : 0.0f;
+        v[u][3] = rgb[i];
+        v[u][4] = rgb[cap + i];
+        v[u][5] = rgb[2 * cap + i];
+    }
+#pragma unroll
+    for (int u = 0; u < IT; ++u) {
+        const int k = lane + 64 * u;
+        if (base + k < end) {
+            L.s[k] = v[u][0]; L.dl[k] = v[u][1]; L.t[k] = v[u][2];
+            L.r[k] = v[u][3]; L.g[k] = v[u][4]; L.b[k] = v[u][5];
+        }
     }
 }
 

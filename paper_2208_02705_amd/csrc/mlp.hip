@@ -30,6 +30,12 @@
 //
 // Precision: BF16 or FP16 operands with FP32 accumulation, or FP32 (each
 // K = 32 step as eight 16x16x4 FP32 MFMAs over the same fragment layout).
+//
+// Scheduling barriers separate the layers: without them the compiler hoists
+// the LDS reads of every weight fragment of the network to the top of the
+// chunk, which needs more than 256 registers and spills to scratch (the
+// spill traffic then saturates HBM); with them each layer holds only its
+// own fragments and the kernel runs three waves per SIMD without spills.
 #include "r360_internal.h"
 
 namespace r360 {
@@ -163,6 +169,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             }
             f32x4 acc[NTILE][NT + 1];
             F8 hb[NTILE][KH];
+            __builtin_amdgcn_sched_barrier(0);
             // L1: encoding -> h (bias in the encoding's constant slot)
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
@@ -177,6 +184,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            __builtin_amdgcn_sched_barrier(0);
             // L2: h -> h
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
@@ -192,6 +200,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            __builtin_amdgcn_sched_barrier(0);
             // HEAD: h -> [f ; sigma]
 #pragma unroll
             for (int ot = 0; ot < NT + 1; ++ot) {
@@ -210,6 +219,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, false>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             }
+            __builtin_amdgcn_sched_barrier(0);
             // L3: [f ; g(d)] -> h (bias in the direction encoding's constant slot)
 #pragma unroll
             for (int n = 0; n < NTILE; ++n) {
@@ -233,6 +243,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
+            __builtin_amdgcn_sched_barrier(0);
             // L4: h -> rgb
             constexpr int O4 = O3 + G::F_L3;
             {

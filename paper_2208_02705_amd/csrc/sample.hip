@@ -67,7 +67,7 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 // others are reused (their plane index did not change, so the recomputation
 // would give the same bits).
 struct CountSink {
-    __device__ void emit(int, float, float, int, int64_t) {}
+    __device__ void emit(int, float, float, int, int) {}
 };
 // Sample k of ray r goes to slot k*N + r (k < max_samples, so the slot stays
 // below N * max_samples < 2^31).
@@ -75,7 +75,7 @@ struct SlotSink {
     int N, r;
     float *t, *dl;
     int32_t *fld, *vox;
-    __device__ void emit(int k, float tm, float d, int lab, int64_t lin) {
+    __device__ void emit(int k, float tm, float d, int lab, int lin) {
         const int j = k * N + r;
         t[j] = tm; dl[j] = d; fld[j] = lab;
         if (vox) vox[j] = (int32_t)lin;
@@ -109,44 +109,92 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         }
     }
     if (!(t0 < t1)) return 0;
-    int idx[3], step[3];
-    float tn[3];
+    // Per axis: pk = index of the next plane to cross (as an exact float),
+    // sf = +-1, tn = its distance, ds = signed step of the linear index.
+    // Kept in scalars (not arrays): the per-step selection among the axes
+    // must stay register selects.
+    float pk0, pk1, pk2, sf0, sf1, sf2, tn0, tn1, tn2;
+    int ds0, ds1, ds2;
+    int lin = 0;
+    {
+        float pk[3], sf[3], tn[3];
+        int ds[3];
+        const int stride[3] = {1, P.n0, P.n0 * P.n1};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float p = __builtin_fmaf(t0, d[a], o[a]);
-        const float q = (p - lo[a]) * P.inv_voxel;
-        const float fq = __builtin_floorf(q);
-        int i = (int)fq;
-        if (q == fq && d[a] < 0.0f) i -= 1;
-        idx[a] = i < 0 ? 0 : (i > n[a] - 1 ? n[a] - 1 : i);
-        step[a] = d[a] > 0.0f ? 1 : -1;
-        tn[a] = act[a] ? (__builtin_fmaf((float)(idx[a] + (d[a] > 0.0f ? 1 : 0)), P.voxel, lo[a]) - o[a]) * inv[a]
-                       : INF;
+        for (int a = 0; a < 3; ++a) {
+            const float p = __builtin_fmaf(t0, d[a], o[a]);
+            const float q = (p - lo[a]) * P.inv_voxel;
+            const float fq = __builtin_floorf(q);
+            int i = (int)fq;
+            if (q == fq && d[a] < 0.0f) i -= 1;
+            i = i < 0 ? 0 : (i > n[a] - 1 ? n[a] - 1 : i);
+            lin += i * stride[a];
+            const bool up = d[a] > 0.0f;
+            pk[a] = (float)(i + (up ? 1 : 0));
+            sf[a] = up ? 1.0f : -1.0f;
+            ds[a] = up ? stride[a] : -stride[a];
+            tn[a] = act[a] ? (__builtin_fmaf(pk[a], P.voxel, lo[a]) - o[a]) * inv[a] : INF;
+        }
+        pk0 = pk[0]; pk1 = pk[1]; pk2 = pk[2];
+        sf0 = sf[0]; sf1 = sf[1]; sf2 = sf[2];
+        tn0 = tn[0]; tn1 = tn[1]; tn2 = tn[2];
+        ds0 = ds[0]; ds1 = ds[1]; ds2 = ds[2];
     }
-    const int64_t sx = 1, sy = P.n0, sz = (int64_t)P.n0 * P.n1;
-    int64_t lin = idx[0] + sy * idx[1] + sz * idx[2];
+    const float o0 = o[0], o1 = o[1], o2 = o[2];
+    const float lo0 = lo[0], lo1 = lo[1], lo2 = lo[2];
+    const float iv0 = inv[0], iv1 = inv[1], iv2 = inv[2];
+    const unsigned nvox = (unsigned)P.n0 * (unsigned)P.n1 * (unsigned)P.n2;
+    // labels read as unsigned 16-bit words: free labels (-1) become 0xFFFF,
+    // field ids stay as they are
+    const uint16_t* labels = reinterpret_cast<const uint16_t*>(P.labels);
     int count = 0;
     float t_in = t0;
-    for (;;) {
-        int am = 0;
-        if (tn[1] < tn[am]) am = 1;
-        if (tn[2] < tn[am]) am = 2;
-        const float tna = tn[am];
-        const float t_out = mn(tna, t1);
-        const int lab = P.labels[lin];
-        if (t_out > t_in && lab >= 0) {
-            sink.emit(count, (t_in + t_out) * 0.5f, t_out - t_in, lab, lin);
-            if (++count == P.max_samples) break;
-        }
-        if (!(tna < t1)) break;
-        t_in = mx(t_in, tna);
-        const int ni = idx[am] + step[am];
-        if (ni < 0 || ni >= n[am]) break;
-        idx[am] = ni;
-        const int64_t stride = am == 0 ? sx : (am == 1 ? sy : sz);
-        lin += step[am] > 0 ? stride : -stride;
-        tn[am] = (__builtin_fmaf((float)(ni + (d[am] > 0.0f ? 1 : 0)), P.voxel, lo[am]) - o[am]) * inv[am];
+    // One traversal step (R360_DDA_STEP): handles the current voxel (label
+    // `cur`) and requests the label of the next one into `nxt`; leaves the
+    // loop when the walk ends. The loop alternates the two label registers,
+    // so the value just requested is not copied (which would wait for the
+    // load) within the step. (A macro, not a lambda: captured references
+    // would turn the per-axis selects into loads through selected pointers.)
+#define R360_DDA_STEP(cur, nxt)                                                      \
+    {                                                                                \
+        const bool c1 = tn1 < tn0; /* nearest plane, ties to the lowest axis */      \
+        const float m01 = c1 ? tn1 : tn0;                                            \
+        const bool c2 = tn2 < m01;                                                   \
+        const float tna = c2 ? tn2 : m01;                                            \
+        const float t_out = mn(tna, t1);                                             \
+        const float pka = c2 ? pk2 : (c1 ? pk1 : pk0);                               \
+        const float sfa = c2 ? sf2 : (c1 ? sf1 : sf0);                               \
+        const float loa = c2 ? lo2 : (c1 ? lo1 : lo0);                               \
+        const float oa = c2 ? o2 : (c1 ? o1 : o0);                                   \
+        const float ia = c2 ? iv2 : (c1 ? iv1 : iv0);                                \
+        const int lin_next = lin + (c2 ? ds2 : (c1 ? ds1 : ds0));                    \
+        const bool more = tna < t1 && (unsigned)lin_next < nvox;                     \
+        nxt = labels[more ? lin_next : lin];                                         \
+        __builtin_amdgcn_sched_barrier(0);                                           \
+        if (t_out > t_in && cur < 0x8000) {                                          \
+            sink.emit(count, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin);    \
+            if (++count == P.max_samples) break;                                     \
+        }                                                                            \
+        if (!more) break;                                                            \
+        t_in = mx(t_in, tna);                                                        \
+        const float pkn = pka + sfa;                                                 \
+        const float tnn = (__builtin_fmaf(pkn, P.voxel, loa) - oa) * ia;             \
+        const bool x0 = !c1 && !c2, x1 = c1 && !c2;                                  \
+        pk0 = x0 ? pkn : pk0; tn0 = x0 ? tnn : tn0;                                  \
+        pk1 = x1 ? pkn : pk1; tn1 = x1 ? tnn : tn1;                                  \
+        pk2 = c2 ? pkn : pk2; tn2 = c2 ? tnn : tn2;                                  \
+        lin = lin_next;                                                              \
     }
+    // Leaving the grid means crossing one of its boundary planes, whose
+    // distance is that axis's box exit (the plane position is computed with
+    // one rounding either way), which is >= t1: the walk ends on tna >= t1
+    // first. The index test in `more` only guards the load.
+    uint16_t la = labels[lin], lb = 0;
+    for (;;) {
+        R360_DDA_STEP(la, lb)
+        R360_DDA_STEP(lb, la)
+    }
+#undef R360_DDA_STEP
     return count;
 }
 
@@ -182,10 +230,13 @@ __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64
 }
 
 // Pass 2 (after the scan): compaction. The 64 rays of a wave own one
-// contiguous output range; it is assembled window by window in LDS (each
-// lane reads its own staging slots, coalesced across the wave) and written
-// out with coalesced stores.
+// contiguous output range, assembled window by window in LDS: each lane
+// copies its own ray's staging slots (slot k*N + r: lanes at the same k read
+// neighbouring addresses) into the window, eight samples per batch so that
+// the wave waits for memory once per batch; the window is then written out
+// with coalesced stores.
 constexpr int CWIN = 512;
+constexpr int CBATCH = 8;
 
 __global__ __launch_bounds__(256) void k_compact(int64_t N, const int32_t* __restrict__ off, Staging sg,
                                                  float* __restrict__ t_mid, float* __restrict__ delta,
@@ -202,15 +253,30 @@ __global__ __launch_bounds__(256) void k_compact(int64_t N, const int32_t* __res
     const int mine = live ? off[r] - wa : 0;
     const int cnt = live ? off[r + 1] - off[r] : 0;
     const bool with_vox = voxel != nullptr;
+    const int Ni = (int)N, ri = (int)r;
     for (int base = 0; base < wb - wa; base += CWIN) {
         const int k0 = max(0, base - mine), k1 = min(cnt, base + CWIN - mine);
-        for (int k = k0; k < k1; ++k) {
-            const int j = k * (int)N + (int)r;
-            const int q = mine + k - base;
-            l_t[wv][q] = sg.t[j];
-            l_d[wv][q] = sg.dl[j];
-            l_g[wv][q] = (lane << 16) | sg.fld[j];
-            if (with_vox) l_v[wv][q] = sg.vox[j];
+        for (int k = k0; k < k1; k += CBATCH) {
+            float tv[CBATCH], dv[CBATCH];
+            int32_t fv[CBATCH], vv[CBATCH];
+#pragma unroll
+            for (int u = 0; u < CBATCH; ++u) {
+                const int j = min(k + u, k1 - 1) * Ni + ri;   // past k1: repeat the last slot
+                tv[u] = sg.t[j];
+                dv[u] = sg.dl[j];
+                fv[u] = sg.fld[j];
+                vv[u] = with_vox ? sg.vox[j] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < CBATCH; ++u) {
+                if (k + u < k1) {
+                    const int q = mine + k + u - base;
+                    l_t[wv][q] = tv[u];
+                    l_d[wv][q] = dv[u];
+                    l_g[wv][q] = (lane << 16) | fv[u];
+                    l_v[wv][q] = vv[u];
+                }
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
