@@ -89,8 +89,11 @@ r360_status check_opts(const r360_render_opts* o, bool allow_fp64) {
 
 namespace r360 {
 
-Workspace carve(void* base, int64_t N, int64_t cap, int F, int64_t P) {
+int64_t sample_cap(int64_t N, int max_samples) { return (N + 63) / 64 * 64 * (int64_t)max_samples; }
+
+Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P) {
     Workspace w{};
+    const int64_t cap = sample_cap(N, max_samples);
     char* p = static_cast<char*>(base);
     size_t off = 0;
     auto take = [&](size_t bytes) -> char* {
@@ -148,11 +151,11 @@ r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts
     r360_status st = check_opts(opts, allow_fp64);
     if (st != R360_OK) return st;
     if (N <= 0) return inval("N must be positive");
-    const int64_t cap = N * (int64_t)opts->max_samples;
-    if (cap >= (int64_t(1) << 31)) return inval("N * max_samples must stay below 2^31; split the rays");
+    if (sample_cap(N, opts->max_samples) >= (int64_t(1) << 31))
+        return inval("N * max_samples must stay below 2^31; split the rays");
     if (!ws) return inval("workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
-    *w = carve(ws, N, cap, s->mlp.n_fields, s->P);
+    *w = carve(ws, N, opts->max_samples, s->mlp.n_fields, s->P);
     if (ws_bytes < w->bytes) {
         std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, w->bytes);
         return R360_EWORKSPACE;
@@ -363,7 +366,7 @@ r360_status r360_equirect_rays(const r360_equirect* eq, const float c2w_host[12]
 
 size_t r360_workspace_bytes(const r360_scene* s, int64_t n_rays, int32_t max_samples) {
     if (!s || n_rays <= 0 || max_samples < 1) return 0;
-    return carve(nullptr, n_rays, n_rays * (int64_t)max_samples, s->mlp.n_fields, s->P).bytes;
+    return carve(nullptr, n_rays, max_samples, s->mlp.n_fields, s->P).bytes;
 }
 
 r360_status r360_sample_rays(const r360_scene* s, const float* o, const float* d, int64_t N,

@@ -391,7 +391,11 @@ constexpr int ROUTE_WAVES = ROUTE_BLOCKS * 4;
 constexpr int SCAN_TILE = 4096;           // elements per scan block (1024 threads x 4)
 constexpr int DW_SLOTS = 1024;            // two gradient partial slots per backward block
 
-Workspace carve(void* base, int64_t N, int64_t cap, int F, int64_t P);
+// Per-sample array length: N rounded up to whole waves of 64 rays, times
+// max_samples (the traversal stages sample k of ray r at slot
+// (r - r % 64) * max_samples + 64 k + r % 64).
+int64_t sample_cap(int64_t N, int max_samples);
+Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P);
 
 // launchers (return hipError_t of the launch)
 enum RayMode { RAYS_GIVEN = 0, RAYS_EQUIRECT = 1, RAYS_PINHOLE = 2 };

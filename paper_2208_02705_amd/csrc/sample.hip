@@ -69,14 +69,17 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 struct CountSink {
     __device__ void emit(int, float, float, int, int) {}
 };
-// Sample k of ray r goes to slot k*N + r (k < max_samples, so the slot stays
-// below N * max_samples < 2^31).
+// Sample k of ray r goes to slot base + 64 k, base = (r - r % 64) *
+// max_samples + r % 64: each wave of 64 rays stages into one contiguous
+// block of 64 * max_samples slots, and lanes at the same k write
+// neighbouring addresses (k < max_samples, so slots stay below the
+// workspace's sample capacity < 2^31).
 struct SlotSink {
-    int N, r;
+    int base;
     float *t, *dl;
     int32_t *fld, *vox;
     __device__ void emit(int k, float tm, float d, int lab, int lin) {
-        const int j = k * N + r;
+        const int j = base + 64 * k;
         t[j] = tm; dl[j] = d; fld[j] = lab;
         if (vox) vox[j] = (int32_t)lin;
     }
@@ -225,20 +228,20 @@ __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64
 #pragma unroll
         for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
     }
-    SlotSink sink{(int)N, (int)r, sg.t, sg.dl, sg.fld, sg.vox};
+    SlotSink sink{(int)(r & ~int64_t(63)) * P.max_samples + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox};
     cnt[r] = traverse(P, o, d, sink);
 }
 
 // Pass 2 (after the scan): compaction. The 64 rays of a wave own one
 // contiguous output range, assembled window by window in LDS: each lane
-// copies its own ray's staging slots (slot k*N + r: lanes at the same k read
-// neighbouring addresses) into the window, eight samples per batch so that
+// copies its own ray's staging slots (lanes at the same k read neighbouring
+// addresses of the wave's staging block) into the window, eight samples per batch so that
 // the wave waits for memory once per batch; the window is then written out
 // with coalesced stores.
 constexpr int CWIN = 512;
 constexpr int CBATCH = 8;
 
-__global__ __launch_bounds__(256) void k_compact(int64_t N, const int32_t* __restrict__ off, Staging sg,
+__global__ __launch_bounds__(256) void k_compact(int64_t N, int max_samples, const int32_t* __restrict__ off, Staging sg,
                                                  float* __restrict__ t_mid, float* __restrict__ delta,
                                                  int32_t* __restrict__ ray, int32_t* __restrict__ field,
                                                  int32_t* __restrict__ voxel) {
@@ -253,7 +256,7 @@ __global__ __launch_bounds__(256) void k_compact(int64_t N, const int32_t* __res
     const int mine = live ? off[r] - wa : 0;
     const int cnt = live ? off[r + 1] - off[r] : 0;
     const bool with_vox = voxel != nullptr;
-    const int Ni = (int)N, ri = (int)r;
+    const int sbase = (int)r0 * max_samples + lane;
     for (int base = 0; base < wb - wa; base += CWIN) {
         const int k0 = max(0, base - mine), k1 = min(cnt, base + CWIN - mine);
         for (int k = k0; k < k1; k += CBATCH) {
@@ -261,7 +264,7 @@ __global__ __launch_bounds__(256) void k_compact(int64_t N, const int32_t* __res
             int32_t fv[CBATCH], vv[CBATCH];
 #pragma unroll
             for (int u = 0; u < CBATCH; ++u) {
-                const int j = min(k + u, k1 - 1) * Ni + ri;   // past k1: repeat the last slot
+                const int j = sbase + 64 * min(k + u, k1 - 1);   // past k1: repeat the last slot
                 tv[u] = sg.t[j];
                 dv[u] = sg.dl[j];
                 fv[u] = sg.fld[j];
@@ -423,8 +426,8 @@ hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, co
     hipLaunchKernelGGL(k_scan_down, dim3(ns), dim3(1024), 0, st, w.ray_off, N, w.scan);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, st, N, w.ray_off, sg, w.t_mid, w.delta, w.ray, w.field,
-                       voxel_out);
+    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(256), 0, st, N, p.max_samples, w.ray_off, sg, w.t_mid, w.delta, w.ray,
+                       w.field, voxel_out);
     return hipGetLastError();
 }
 
