@@ -5,84 +5,171 @@
 // tau_i = sigma_i delta_i the transmittance is kept as the FP32 prefix sum
 // logT_i = -sum_{k<i} tau_k, alpha_i = -expm1(-tau_i), w_i = exp(logT_i) alpha_i,
 // C = sum w_i c_i, D = sum w_i t_i, A = sum w_i. No background colour.
+#include <climits>
+
 #include "r360_internal.h"
 
 namespace r360 {
 
 namespace {
 
-// Each wave owns 64 consecutive rays, whose samples are one contiguous
-// range. The range is staged through LDS in chunks with coalesced loads;
-// each lane then walks its own ray's samples from LDS. (Walking them straight
-// from global memory would make every load instruction touch ~20 cache lines
-// and thrash L1.)
-constexpr int CCH = 512;                      // samples per staged chunk and wave
+// Sample-parallel compositing. Each wave owns `rpw` consecutive rays, whose
+// samples form one contiguous range, and walks that range 64 samples at a
+// time with one sample per lane (coalesced loads of every per-sample array,
+// all lanes busy whatever the rays' lengths). Within a chunk the per-ray
+// prefix of tau and the per-ray sums are segmented wave scans; a ray that
+// continues into the next chunk carries its partial sums. The summation
+// order is fixed, so results are deterministic.
 
-struct Stage6 { float s[CCH], dl[CCH], t[CCH], r[CCH], g[CCH], b[CCH]; };
+// Wave-level data movement with DPP (no LDS traffic): row_shr:d within rows
+// of 16 lanes, row_bcast:15 / row_bcast:31 across rows, wave_shr:1 and
+// wave_shl:1 by one lane. Lanes without a source (or outside row_mask) get
+// `old`.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dppf(float old, float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v),
+                                                                 CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dppi(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, 0xf, false);
+}
+constexpr int DPP_ROW_SHR = 0x110, DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138, DPP_BCAST15 = 0x142,
+              DPP_BCAST31 = 0x143;
 
-// All loads of a chunk are issued before any LDS store, so the wave waits
-// for memory once per chunk rather than once per 64 samples.
-__device__ __forceinline__ void stage_chunk(Stage6& L, int base, int end, int lane, int64_t cap,
-                                            const float* __restrict__ sigma, const float* __restrict__ rgb,
-                                            const float* __restrict__ t_mid, const float* __restrict__ delta) {
-    constexpr int IT = CCH / 64;
-    float v[IT][6];
-#pragma unroll
-    for (int u = 0; u < IT; ++u) {
-        const int i0 = base + lane + 64 * u;
-        const int i = i0 < end ? i0 : base;           // base < end: an in-range stand-in
-        v[u][0] = sigma[i];
-        v[u][1] = delta[i];
-        v[u][2] = t_mid ? t_mid[i] : 0.0f;
-        v[u][3] = rgb[i];
-        v[u][4] = rgb[cap + i];
-        v[u][5] = rgb[2 * cap + i];
-    }
-#pragma unroll
-    for (int u = 0; u < IT; ++u) {
-        const int k = lane + 64 * u;
-        if (base + k < end) {
-            L.s[k] = v[u][0]; L.dl[k] = v[u][1]; L.t[k] = v[u][2];
-            L.r[k] = v[u][3]; L.g[k] = v[u][4]; L.b[k] = v[u][5];
-        }
+// Inclusive sum over the lanes of this lane's segment up to this lane
+// (`seg` = first lane of the segment): in-row Kogge-Stone steps, then the
+// row totals of rows 0 and 2 into rows 1 and 3, then that of rows 0-1 into
+// rows 2-3, each added only where it lies in the lane's segment.
+__device__ __forceinline__ float seg_scan(float v, int lane, int seg) {
+    float t;
+    t = dppf<DPP_ROW_SHR + 1>(0.0f, v); if (lane - 1 >= seg) v += t;
+    t = dppf<DPP_ROW_SHR + 2>(0.0f, v); if (lane - 2 >= seg) v += t;
+    t = dppf<DPP_ROW_SHR + 4>(0.0f, v); if (lane - 4 >= seg) v += t;
+    t = dppf<DPP_ROW_SHR + 8>(0.0f, v); if (lane - 8 >= seg) v += t;
+    t = dppf<DPP_BCAST15, 0xa>(0.0f, v); if (seg < (lane & ~15)) v += t;
+    t = dppf<DPP_BCAST31, 0xc>(0.0f, v); if (seg < 32) v += t;
+    return v;
+}
+
+// Inclusive max over lanes 0..lane (values >= 0).
+__device__ __forceinline__ int max_scan(int v) {
+    v = max(v, dppi<DPP_ROW_SHR + 1>(0, v));
+    v = max(v, dppi<DPP_ROW_SHR + 2>(0, v));
+    v = max(v, dppi<DPP_ROW_SHR + 4>(0, v));
+    v = max(v, dppi<DPP_ROW_SHR + 8>(0, v));
+    v = max(v, dppi<DPP_BCAST15, 0xa>(0, v));
+    v = max(v, dppi<DPP_BCAST31, 0xc>(0, v));
+    return v;
+}
+
+__device__ __forceinline__ float lane63(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+// Segment bookkeeping of one chunk: ray id per lane (INT_MAX past the
+// range), segment start, whether the lane's segment continues the carried
+// ray, whether the lane holds its ray's last sample. `next_first` is the ray
+// of the sample after the chunk (INT_MAX if none).
+struct ChunkSeg {
+    int ray, seg;
+    bool valid, cont, ends;
+};
+
+__device__ __forceinline__ ChunkSeg chunk_seg(int ray, bool valid, int next_first, int lane, int c_ray) {
+    ChunkSeg c;
+    c.valid = valid;
+    c.ray = ray;
+    // lane 0 compares with the carried ray, lane 63 with the next chunk's first
+    const int prev = dppi<DPP_WAVE_SHR1>(c_ray, c.ray);
+    const bool head = c.ray != prev;
+    c.seg = max_scan(head ? lane : 0);
+    c.cont = c.seg == 0 && __builtin_amdgcn_readlane(c.ray, 0) == c_ray;
+    const int nxt = dppi<DPP_WAVE_SHL1>(next_first, c.ray);
+    c.ends = c.valid && nxt != c.ray;
+    return c;
+}
+
+// Per-lane inputs of one 64-sample chunk; a wave loads CPB chunks at once so
+// that several chunks' loads are in flight together.
+constexpr int CPB = 4;
+struct ChunkIn {
+    int ray;
+    bool valid;
+    float sg, dl, q0, q1, q2, tm;
+};
+
+__device__ __forceinline__ ChunkIn load_chunk(const int32_t* __restrict__ ray, const float* __restrict__ sigma,
+                                              const float* __restrict__ rgb, const float* __restrict__ t_mid,
+                                              const float* __restrict__ delta, int64_t cap, int s, int sb) {
+    ChunkIn c;
+    c.valid = s < sb;
+    const int i = c.valid ? s : sb - 1;     // in-range stand-in
+    c.ray = c.valid ? ray[i] : INT_MAX;
+    c.sg = sigma[i];
+    c.dl = delta[i];
+    c.q0 = rgb[i]; c.q1 = rgb[cap + i]; c.q2 = rgb[2 * cap + i];
+    c.tm = t_mid ? t_mid[i] : 0.0f;
+    return c;
+}
+
+__device__ __forceinline__ void zero_empty_rays(const int32_t* __restrict__ off, int64_t N, int64_t r0, int64_t r1,
+                                                int lane, float* out_rgb, float* depth, float* opacity) {
+    for (int64_t r = r0 + lane; r < r1; r += 64) {
+        if (off[r] != off[r + 1]) continue;
+        if (out_rgb) { out_rgb[r] = 0.0f; out_rgb[N + r] = 0.0f; out_rgb[2 * N + r] = 0.0f; }
+        if (depth) depth[r] = 0.0f;
+        if (opacity) opacity[r] = 0.0f;
     }
 }
 
-__global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ off, int64_t N, int64_t cap,
-                                                   const float* __restrict__ sigma, const float* __restrict__ rgb,
-                                                   const float* __restrict__ t_mid, const float* __restrict__ delta,
-                                                   float* __restrict__ out_rgb, float* __restrict__ depth,
-                                                   float* __restrict__ opacity) {
-    __shared__ Stage6 lds[4];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    Stage6& L = lds[wv];
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+__global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ off, const int32_t* __restrict__ ray,
+                                                   int64_t N, int64_t cap, int rpw, const float* __restrict__ sigma,
+                                                   const float* __restrict__ rgb, const float* __restrict__ t_mid,
+                                                   const float* __restrict__ delta, float* __restrict__ out_rgb,
+                                                   float* __restrict__ depth, float* __restrict__ opacity) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * rpw;
     if (r0 >= N) return;
-    const int64_t r = r0 + lane;
-    const bool live = r < N;
-    const int wa = off[r0], wb = off[min(r0 + 64, N)];
-    const int a = live ? off[r] : 0, b = live ? off[r + 1] : 0;
-    float logT = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f, A = 0.0f;
-    for (int base = wa; base < wb; base += CCH) {
-        stage_chunk(L, base, wb, lane, cap, sigma, rgb, t_mid, delta);
-        __builtin_amdgcn_wave_barrier();
-        const int lo = max(a, base) - base, hi = min(b, base + CCH) - base;
-        for (int k = lo; k < hi; ++k) {
-            const float tau = L.s[k] * L.dl[k];
-            const float w = expf(logT) * -expm1f(-tau);
-            c0 += w * L.r[k];
-            c1 += w * L.g[k];
-            c2 += w * L.b[k];
-            D += w * L.t[k];
-            A += w;
-            logT -= tau;
+    const int64_t r1 = min(r0 + rpw, N);
+    zero_empty_rays(off, N, r0, r1, lane, out_rgb, depth, opacity);
+    const int sa = off[r0], sb = off[r1];
+    // carried partial sums of a ray that continues from the previous chunk
+    int c_ray = -1;
+    float cS = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, cD = 0.0f, cA = 0.0f;
+    for (int blk = sa; blk < sb; blk += 64 * CPB) {
+        ChunkIn in[CPB];
+#pragma unroll
+        for (int u = 0; u < CPB; ++u) in[u] = load_chunk(ray, sigma, rgb, t_mid, delta, cap, blk + 64 * u + lane, sb);
+        const int after = blk + 64 * CPB < sb ? ray[blk + 64 * CPB] : INT_MAX;
+#pragma unroll
+        for (int u = 0; u < CPB; ++u) {
+            if (blk + 64 * u >= sb) break;
+            const int next_first = u + 1 < CPB ? __builtin_amdgcn_readlane(in[u + 1 < CPB ? u + 1 : u].ray, 0) : after;
+            const ChunkSeg cs = chunk_seg(in[u].ray, in[u].valid, next_first, lane, c_ray);
+            const float tau = cs.valid ? in[u].sg * in[u].dl : 0.0f;
+            // S = sum of tau over the ray's earlier samples (log-space transmittance)
+            const float incl = seg_scan(tau, lane, cs.seg);
+            float S = dppf<DPP_WAVE_SHR1>(0.0f, incl);
+            if (lane == cs.seg) S = 0.0f;
+            if (cs.cont) S += cS;
+            const float w = cs.valid ? expf(-S) * -expm1f(-tau) : 0.0f;
+            float a0 = seg_scan(w * in[u].q0, lane, cs.seg), a1 = seg_scan(w * in[u].q1, lane, cs.seg);
+            float a2 = seg_scan(w * in[u].q2, lane, cs.seg), aD = seg_scan(w * in[u].tm, lane, cs.seg);
+            float aA = seg_scan(w, lane, cs.seg);
+            if (cs.cont) { a0 += c0; a1 += c1; a2 += c2; aD += cD; aA += cA; }
+            if (cs.ends) {
+                if (out_rgb) { out_rgb[cs.ray] = a0; out_rgb[N + cs.ray] = a1; out_rgb[2 * N + cs.ray] = a2; }
+                if (depth) depth[cs.ray] = aD;
+                if (opacity) opacity[cs.ray] = aA;
+            }
+            // lane 63's ray continues into the next chunk unless it ended here
+            const bool open = __builtin_amdgcn_readlane(cs.valid && !cs.ends ? 1 : 0, 63) != 0;
+            c_ray = open ? __builtin_amdgcn_readlane(cs.ray, 63) : -1;
+            cS = lane63(S + tau);
+            c0 = lane63(a0); c1 = lane63(a1); c2 = lane63(a2); cD = lane63(aD); cA = lane63(aA);
         }
-        __builtin_amdgcn_wave_barrier();
     }
-    if (!live) return;
-    if (out_rgb) { out_rgb[r] = c0; out_rgb[N + r] = c1; out_rgb[2 * N + r] = c2; }
-    if (depth) depth[r] = D;
-    if (opacity) opacity[r] = A;
 }
 
 // Loss L = 1/(3N) sum (C - C*)^2: per-block partial sums (fixed order), and
@@ -123,64 +210,70 @@ __global__ __launch_bounds__(256) void k_loss_final(const float* __restrict__ pa
     if (threadIdx.x == 0) *loss = red[0] / (3.0f * (float)N);
 }
 
-// Backward of compositing. Pass 1 recomputes C; pass 2 repeats the same
-// accumulation so that C - C_{<=i} is a difference of identical partial sums:
-//   dL/dc_i = w_i g,  dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - ((C - C_{<=i}) . g)].
-// Both passes stage the wave's sample range through LDS as the forward does;
-// pass 2 writes the per-sample gradients back through LDS, coalesced.
-__global__ __launch_bounds__(256) void k_composite_bwd(const int32_t* __restrict__ off, int64_t N, int64_t cap,
-                                                       const float* __restrict__ sigma, const float* __restrict__ rgb,
-                                                       const float* __restrict__ delta, const float* __restrict__ grad,
-                                                       float* __restrict__ dsigma, float* __restrict__ drgb) {
-    __shared__ Stage6 lds[4];
+// Backward of compositing, sample-parallel like the forward. With
+// u_i = w_i (c_i . g) and g = dL/dC of the sample's ray:
+//   dL/dc_i = w_i g,  dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - sum_{j>i} u_j].
+// Pass 1 sums u per ray (kept in LDS); pass 2 repeats the same scans, so the
+// tail sum is the ray total minus an identically computed inclusive prefix
+// (exactly 0 at the ray's last sample).
+__global__ __launch_bounds__(256) void k_composite_bwd(const int32_t* __restrict__ off, const int32_t* __restrict__ ray,
+                                                       int64_t N, int64_t cap, int rpw, const float* __restrict__ sigma,
+                                                       const float* __restrict__ rgb, const float* __restrict__ delta,
+                                                       const float* __restrict__ grad, float* __restrict__ dsigma,
+                                                       float* __restrict__ drgb) {
+    __shared__ float u_tot[4][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    Stage6& L = lds[wv];
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * 64;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wv) * rpw;
     if (r0 >= N) return;
-    const int64_t r = r0 + lane;
-    const bool live = r < N;
-    const int wa = off[r0], wb = off[min(r0 + 64, N)];
-    const int a = live ? off[r] : 0, b = live ? off[r + 1] : 0;
-    const float g0 = live ? grad[r] : 0.0f, g1 = live ? grad[N + r] : 0.0f, g2 = live ? grad[2 * N + r] : 0.0f;
-    float logT = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    for (int base = wa; base < wb; base += CCH) {
-        stage_chunk(L, base, wb, lane, cap, sigma, rgb, nullptr, delta);
-        __builtin_amdgcn_wave_barrier();
-        const int lo = max(a, base) - base, hi = min(b, base + CCH) - base;
-        for (int k = lo; k < hi; ++k) {
-            const float tau = L.s[k] * L.dl[k];
-            const float w = expf(logT) * -expm1f(-tau);
-            C0 += w * L.r[k]; C1 += w * L.g[k]; C2 += w * L.b[k];
-            logT -= tau;
+    const int64_t r1 = min(r0 + rpw, N);
+    const int sa = off[r0], sb = off[r1];
+    const int rb = (int)r0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int c_ray = -1;
+        float cS = 0.0f, cU = 0.0f;
+        for (int blk = sa; blk < sb; blk += 64 * CPB) {
+            ChunkIn in[CPB];
+#pragma unroll
+            for (int u = 0; u < CPB; ++u) in[u] = load_chunk(ray, sigma, rgb, nullptr, delta, cap, blk + 64 * u + lane, sb);
+            const int after = blk + 64 * CPB < sb ? ray[blk + 64 * CPB] : INT_MAX;
+#pragma unroll
+            for (int u = 0; u < CPB; ++u) {
+                if (blk + 64 * u >= sb) break;
+                const int next_first = u + 1 < CPB ? __builtin_amdgcn_readlane(in[u + 1 < CPB ? u + 1 : u].ray, 0) : after;
+                const ChunkSeg cs = chunk_seg(in[u].ray, in[u].valid, next_first, lane, c_ray);
+                const int ry = cs.valid ? cs.ray : rb;
+                const float dl = in[u].dl;
+                const float tau = cs.valid ? in[u].sg * dl : 0.0f;
+                const float q0 = in[u].q0, q1 = in[u].q1, q2 = in[u].q2;
+                const float g0 = grad[ry], g1 = grad[N + ry], g2 = grad[2 * N + ry];
+                const float incl = seg_scan(tau, lane, cs.seg);
+                float S = dppf<DPP_WAVE_SHR1>(0.0f, incl);
+                if (lane == cs.seg) S = 0.0f;
+                if (cs.cont) S += cS;
+                const float w = cs.valid ? expf(-S) * -expm1f(-tau) : 0.0f;
+                const float cg = q0 * g0 + q1 * g1 + q2 * g2;
+                float U = seg_scan(w * cg, lane, cs.seg);
+                if (cs.cont) U += cU;
+                const int s = blk + 64 * u + lane;
+                if (pass == 0) {
+                    if (cs.ends) u_tot[wv][cs.ray - rb] = U;
+                } else if (cs.valid) {
+                    const float tail = u_tot[wv][cs.ray - rb] - U;
+                    const float Tn = expf(-(S + tau));
+                    dsigma[s] = dl * (Tn * cg - tail);
+                    drgb[s] = w * g0;
+                    drgb[cap + s] = w * g1;
+                    drgb[2 * cap + s] = w * g2;
+                }
+                const bool open = __builtin_amdgcn_readlane(cs.valid && !cs.ends ? 1 : 0, 63) != 0;
+                c_ray = open ? __builtin_amdgcn_readlane(cs.ray, 63) : -1;
+                cS = lane63(S + tau);
+                cU = lane63(U);
+            }
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
-    }
-    float P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-    logT = 0.0f;
-    for (int base = wa; base < wb; base += CCH) {
-        stage_chunk(L, base, wb, lane, cap, sigma, rgb, nullptr, delta);
-        __builtin_amdgcn_wave_barrier();
-        const int lo = max(a, base) - base, hi = min(b, base + CCH) - base;
-        for (int k = lo; k < hi; ++k) {
-            const float tau = L.s[k] * L.dl[k];
-            const float w = expf(logT) * -expm1f(-tau);
-            const float q0 = L.r[k], q1 = L.g[k], q2 = L.b[k];
-            P0 += w * q0; P1 += w * q1; P2 += w * q2;
-            logT -= tau;
-            const float Tn = expf(logT);
-            const float cg = q0 * g0 + q1 * g1 + q2 * g2;
-            const float rg = (C0 - P0) * g0 + (C1 - P1) * g1 + (C2 - P2) * g2;
-            // results overwrite the staged inputs of this sample (read above)
-            L.s[k] = L.dl[k] * (Tn * cg - rg);
-            L.r[k] = w * g0; L.g[k] = w * g1; L.b[k] = w * g2;
-        }
-        __builtin_amdgcn_wave_barrier();
-        for (int k = lane; k < CCH && base + k < wb; k += 64) {
-            const int i = base + k;
-            dsigma[i] = L.s[k];
-            drgb[i] = L.r[k]; drgb[cap + i] = L.g[k]; drgb[2 * cap + i] = L.b[k];
-        }
-        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
@@ -201,11 +294,19 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-inline unsigned nwblk(int64_t n) { return (unsigned)((n + 255) / 256); }   // 4 waves x 64 rays per block
+// Rays per wave: 64 when there are enough rays, fewer (down to 1) so that
+// small batches of long rays still spread over at least 8192 waves.
+inline int rays_per_wave(int64_t N) {
+    int rpw = 64;
+    while (rpw > 1 && (N + rpw - 1) / rpw < 8192) rpw >>= 1;
+    return rpw;
+}
+inline unsigned wave_blocks(int64_t N, int rpw) { return (unsigned)(((N + rpw - 1) / rpw + 3) / 4); }
 
 hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity, hipStream_t st) {
-    hipLaunchKernelGGL(k_composite, dim3(nwblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.sigma, w.rgb, w.t_mid,
-                       w.delta, rgb, depth, opacity);
+    const int rpw = rays_per_wave(N);
+    hipLaunchKernelGGL(k_composite, dim3(wave_blocks(N, rpw)), dim3(256), 0, st, w.ray_off, w.ray, N, w.cap, rpw,
+                       w.sigma, w.rgb, w.t_mid, w.delta, rgb, depth, opacity);
     return hipGetLastError();
 }
 
@@ -218,8 +319,9 @@ hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, con
 }
 
 hipError_t launch_composite_backward(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st) {
-    hipLaunchKernelGGL(k_composite_bwd, dim3(nwblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.sigma, w.rgb,
-                       w.delta, grad_rgb, w.dsigma, w.drgb);
+    const int rpw = rays_per_wave(N);
+    hipLaunchKernelGGL(k_composite_bwd, dim3(wave_blocks(N, rpw)), dim3(256), 0, st, w.ray_off, w.ray, N, w.cap, rpw,
+                       w.sigma, w.rgb, w.delta, grad_rgb, w.dsigma, w.drgb);
     return hipGetLastError();
 }
 

@@ -179,6 +179,7 @@ struct GSampleArgs {
     int w, k10;
     float* t; float* delta;    // [M]
     int32_t* voxel;            // [M] linear cell or -1
+    int32_t* ray;              // [M] ray of each sample
     int32_t* ray_off;          // [N+1]
 };
 
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(256) void k_gsamples(GSampleArgs a) {
     const int k = (int)(m % a.S);
     const float t = inv_depth_t(a, k);
     a.t[m] = t;
+    a.ray[m] = (int32_t)r;
     a.delta[m] = (k + 1 < a.S) ? inv_depth_t(a, k + 1) - t : 0.0f;
     const float o[3] = {a.o[r], a.o[a.N + r], a.o[2 * a.N + r]};
     const float d[3] = {a.d[r], a.d[a.N + r], a.d[2 * a.N + r]};
@@ -440,7 +442,7 @@ GNetDev dev_net(const GNet& n) {
 struct GlobalWs {
     bf16 *arena, *x5, *h[9], *x10, *h10, *dza, *dzb, *dz11;   // h[1..3], h[5..8]
     float *bias, *sig, *rgb, *t, *delta, *dsig, *drgb, *part, *ray_rgb, *ray_grad, *loss_part;
-    int32_t *voxel, *ray_off;
+    int32_t *voxel, *ray, *ray_off;
     size_t bytes;
 };
 
@@ -473,6 +475,7 @@ static GlobalWs gcarve(void* base, const GNet& n, int64_t Nr, int S) {
     g.dsig = (float*)take(M * 4);
     g.drgb = (float*)take(3 * M * 4);
     g.voxel = (int32_t*)take(M * 4);
+    g.ray = (int32_t*)take(M * 4);
     g.ray_off = (int32_t*)take((Nr + 1) * 4);
     g.part = (float*)take((size_t)G_SLICES * n.g_elems * 4);
     g.ray_rgb = (float*)take(3 * Nr * 4);
@@ -517,7 +520,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     sa.inv_vox = 1.0f / desc->voxel;
     sa.g0 = desc->grid_n[0]; sa.g1 = desc->grid_n[1]; sa.g2 = desc->grid_n[2];
     sa.x5 = g.x5; sa.x10 = g.x10; sa.w = w; sa.k10 = n.L[G10].K;
-    sa.t = g.t; sa.delta = g.delta; sa.voxel = g.voxel; sa.ray_off = g.ray_off;
+    sa.t = g.t; sa.delta = g.delta; sa.voxel = g.voxel; sa.ray = g.ray; sa.ray_off = g.ray_off;
     hipLaunchKernelGGL(k_gsamples, dim3((unsigned)((std::max<int64_t>(M, Nr + 1) + 255) / 256)), dim3(256), 0, st, sa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -565,7 +568,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
                                 reinterpret_cast<unsigned*>(occ));
     // compositing, loss and its backward reuse the local path's kernels
     Workspace lw{};
-    lw.ray_off = g.ray_off; lw.sigma = g.sig; lw.rgb = g.rgb; lw.t_mid = g.t; lw.delta = g.delta;
+    lw.ray_off = g.ray_off; lw.ray = g.ray; lw.sigma = g.sig; lw.rgb = g.rgb; lw.t_mid = g.t; lw.delta = g.delta;
     lw.dsigma = g.dsig; lw.drgb = g.drgb; lw.loss_part = g.loss_part; lw.N = Nr; lw.cap = M;
     float* ray_rgb = rgb_out ? rgb_out : g.ray_rgb;
     if ((e = launch_composite(lw, Nr, ray_rgb, depth_out, nullptr, st)) != hipSuccess) return e;

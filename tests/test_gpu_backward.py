@@ -94,6 +94,30 @@ def test_train_step_headline_batch(R, orc):
     assert _rel_err(_np(grad32), g_ref) <= FP32_GRAD
 
 
+def test_chunk_aligned_rays_forward_and_backward(R, orc):
+    """36,000 rays along +x through a fully occupied 32^3 grid: every ray has
+    exactly 32 samples, so with several rays per wave a ray ends exactly at a
+    64-sample chunk boundary and the next one starts the following chunk
+    (the compositing carry must not leak from one ray into the next)."""
+    sc = synth.tiny_scene(32, 77, p_occ=1.0, n_fields=3, hidden=32, max_samples=32)
+    scene = R.Scene.from_synth(sc)
+    N = 36000
+    rng = np.random.default_rng(77)
+    o = np.empty((3, N), np.float32)
+    o[0] = -4.5
+    o[1:] = rng.uniform(-3.9, 3.9, size=(2, N)).astype(np.float32)
+    d = np.zeros((3, N), np.float32); d[0] = 1.0
+    tgt = rng.uniform(0, 1, (3, N)).astype(np.float32)
+    ref_rgb, _, ref_op = orc.render_rays(sc, o, d)
+    rgb, _, op = R.render_rays(scene, _t(o), _t(d), precision="fp32")
+    assert np.all(np.abs(_np(rgb) - ref_rgb) <= 1e-4 * np.abs(ref_rgb) + 1e-6)
+    assert np.all(np.abs(_np(op) - ref_op) <= 1e-4 * np.abs(ref_op) + 1e-6)
+    loss, grad = R.train_step(scene, _t(o), _t(d), _t(tgt), precision="fp32")
+    l_ref, g_ref, _ = orc.train_grad(sc, o, d, tgt)
+    assert abs(float(_np(loss)[0]) - l_ref) <= 1e-4 * l_ref
+    assert _rel_err(_np(grad), g_ref) <= FP32_GRAD
+
+
 def test_backward_deterministic(R):
     sc = synth.tiny_scene(8, 44, p_occ=0.5, n_fields=7, hidden=64, max_samples=32)
     scene = R.Scene.from_synth(sc)
