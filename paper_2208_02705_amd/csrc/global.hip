@@ -244,14 +244,18 @@ __global__ __launch_bounds__(256) void k_gsamples(GSampleArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// GEMM: C[r][c] = sum_k A(r, k) B(c, k), r < R, c < C, k < Kc (a multiple of
-// 32, or a slice of it). Operand element (row, k) sits at p[row * sr + k * sk].
+// GEMMs. Row GEMM (forward layers and input gradients):
+//   out[r][c] = epi(sum_k A[r][k] B[c][k]), r < R, c < C, k < Kc (multiple of 32),
+// both operands K-contiguous (element (row, k) at p[row * sr + k]).
+// Weight-gradient GEMM: part[slice][n][k'] = sum_m A[m][n] B[m][k'] over the
+// slice's samples m, both operands sample-major (element (m, col) at
+// p[m * sr + col]).
 // ---------------------------------------------------------------------------
 enum Epi { EPI_FWD = 0, EPI_RGB, EPI_DX, EPI_DW };
 
 struct GemmArgs {
-    const bf16* A; int64_t a_sr, a_sk;
-    const bf16* B; int64_t b_sr, b_sk;
+    const bf16* A; int64_t a_sr;
+    const bf16* B; int64_t b_sr;
     int R, C, Kc;              // rows, columns, contraction length (per slice for EPI_DW)
     // EPI_FWD: out[r * ldo + c] = act(acc + bias[c]) for c < n_out; column c == sig_col
     // goes to sig[r] (ReLU) instead
@@ -264,111 +268,91 @@ struct GemmArgs {
     float* rgb;
     // EPI_DX: out[r * ldo + c] = acc * [mask[r * ldm + c] > 0] (mask may be null)
     const bf16* mask; int64_t ldm;
-    // EPI_DW: part[slice * pstride + r * ldp + c] = acc; colsum part[slice * pstride + boff + r]
+    // EPI_DW: total samples M; readable columns of A and B (multiples of 8);
+    // part[slice * pstride + r * ldp + c] = acc; row sums at part[slice * pstride + boff + r]
+    int64_t Mtot; int a_lim, b_lim;
     float* part; int64_t pstride, ldp, boff;   // boff < 0: no bias gradient
 };
 
-constexpr int GT = 128;         // tile rows / columns
-constexpr int GK = 32;          // contraction step
-constexpr int GPAD = 40;        // LDS row stride (elements), 80 bytes
+constexpr int GT = 128;         // tile rows
+constexpr int GK = 32;          // contraction step of the row GEMM
+constexpr int GPAD = 40;        // LDS row stride (elements) of 32-wide k slabs: 80 bytes
 
 typedef __attribute__((ext_vector_type(4))) unsigned u4;
 
-// Loads this thread's two 16-byte pieces of a 128 x 32 operand tile.
-// K-contiguous operands: piece = 8 consecutive k of one row. Row-contiguous
-// operands: piece = 8 consecutive rows at one k.
-__device__ __forceinline__ void tile_load(const bf16* p, int64_t sr, int64_t sk, int rows, int r0, int k0, int kmax,
-                                          int tid, u4 v[2]) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int piece = tid + 256 * q;          // 512 pieces
-        u4 val = {0u, 0u, 0u, 0u};
-        if (sk == 1) {
-            const int row = r0 + (piece >> 2), k = k0 + 8 * (piece & 3);
-            if (row < rows && k < kmax) val = *reinterpret_cast<const u4*>(p + row * sr + k);
-        } else {
-            const int k = k0 + (piece >> 4), row = r0 + 8 * (piece & 15);
-            if (k < kmax && row < rows) {
-                if (row + 8 <= rows) {
-                    val = *reinterpret_cast<const u4*>(p + row + k * sk);
-                } else {
-                    bf16 tmp[8];
-                    for (int e = 0; e < 8; ++e) tmp[e] = row + e < rows ? p[row + e + k * sk] : (bf16)0.0f;
-                    val = __builtin_bit_cast(u4, tmp);
-                }
-            }
-        }
-        v[q] = val;
-    }
-}
-
-__device__ __forceinline__ void tile_store(bf16* lds, bool kcontig, int tid, const u4 v[2]) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int piece = tid + 256 * q;
-        if (kcontig) {
-            *reinterpret_cast<u4*>(lds + (piece >> 2) * GPAD + 8 * (piece & 3)) = v[q];
-        } else {
-            const int k = piece >> 4, row = 8 * (piece & 15);
-            const bf16* e8 = reinterpret_cast<const bf16*>(&v[q]);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) lds[(row + e) * GPAD + k] = e8[e];
-        }
-    }
-}
-
-template <int EPI>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) bf16 la[GT * GPAD], lb[GT * GPAD];
-    __shared__ float colsum[GT];
+// Row GEMM, tile GT x BN, four waves of 64 x BN/2. Operand slabs are double
+// buffered in LDS: the global loads of step k+1 are issued before the MFMAs
+// of step k and stored to the other buffer after them, one barrier per step.
+template <int EPI, int BN>
+__global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
+    constexpr int WN = BN / 2, TJ = WN / 16, BQ = BN / 64;
+    __shared__ __attribute__((aligned(16))) bf16 la[2][GT * GPAD];
+    __shared__ __attribute__((aligned(16))) bf16 lb[2][BN * GPAD];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv >> 1, wn = wv & 1;
-    const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
-    const int slice = blockIdx.z;
-    const int kbeg = slice * g.Kc, kend = kbeg + g.Kc;
-    const bool a_kc = g.a_sk == 1, b_kc = g.b_sk == 1;
-    f32x4 acc[4][4];
+    const int r0 = blockIdx.x * GT, c0 = blockIdx.y * BN;
+    f32x4 acc[4][TJ];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float csum = 0.0f;                            // EPI_DW: column sum of A rows (bias gradient)
-    u4 va[2], vb[2];
-    tile_load(g.A, g.a_sr, g.a_sk, g.R, r0, kbeg, kend, tid, va);
-    tile_load(g.B, g.b_sr, g.b_sk, g.C, c0, kbeg, kend, tid, vb);
-    for (int k0 = kbeg; k0 < kend; k0 += GK) {
-        __syncthreads();
-        tile_store(la, a_kc, tid, va);
-        tile_store(lb, b_kc, tid, vb);
-        __syncthreads();
-        if (k0 + GK < kend) {
-            tile_load(g.A, g.a_sr, g.a_sk, g.R, r0, k0 + GK, kend, tid, va);
-            tile_load(g.B, g.b_sr, g.b_sk, g.C, c0, k0 + GK, kend, tid, vb);
-        }
-        if constexpr (EPI == EPI_DW) {
-            if (g.boff >= 0 && tid < GT) {
-#pragma unroll 8
-                for (int k = 0; k < GK; ++k) csum += (float)la[tid * GPAD + k];
-            }
-        }
-        bf16x8 fa[4], fb[4];
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    u4 va[2], vb[BQ];
+    // piece p of a slab: row p / 4, k offset 8 (p % 4)
+#define R360_GLOAD(k0)                                                                                   \
+    {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                                  \
+            const int p = tid + 256 * q, row = r0 + (p >> 2);                                            \
+            va[q] = row < g.R ? *reinterpret_cast<const u4*>(g.A + row * g.a_sr + (k0) + 8 * (p & 3))    \
+                              : u4{0u, 0u, 0u, 0u};                                                      \
+        }                                                                                                \
+        _Pragma("unroll") for (int q = 0; q < BQ; ++q) {                                                 \
+            const int p = tid + 256 * q, row = c0 + (p >> 2);                                            \
+            vb[q] = row < g.C ? *reinterpret_cast<const u4*>(g.B + row * g.b_sr + (k0) + 8 * (p & 3))    \
+                              : u4{0u, 0u, 0u, 0u};                                                      \
+        }                                                                                                \
+    }
+#define R360_LSTORE(buf)                                                                                 \
+    {                                                                                                    \
+        _Pragma("unroll") for (int q = 0; q < 2; ++q) {                                                  \
+            const int p = tid + 256 * q;                                                                 \
+            *reinterpret_cast<u4*>(&la[buf][(p >> 2) * GPAD + 8 * (p & 3)]) = va[q];                     \
+        }                                                                                                \
+        _Pragma("unroll") for (int q = 0; q < BQ; ++q) {                                                 \
+            const int p = tid + 256 * q;                                                                 \
+            *reinterpret_cast<u4*>(&lb[buf][(p >> 2) * GPAD + 8 * (p & 3)]) = vb[q];                     \
+        }                                                                                                \
+    }
+    R360_GLOAD(0)
+    R360_LSTORE(0)
+    __syncthreads();
+    const int nk = g.Kc / GK;
+    for (int it = 0; it < nk; ++it) {
+        const int cur = it & 1;
+        const bool more = it + 1 < nk;
+        if (more) R360_GLOAD((it + 1) * GK)
+        bf16x8 fa[4], fb[TJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            fa[i] = *reinterpret_cast<const bf16x8*>(la + (64 * wm + 16 * i + (lane & 15)) * GPAD + 8 * (lane >> 4));
-            fb[i] = *reinterpret_cast<const bf16x8*>(lb + (64 * wn + 16 * i + (lane & 15)) * GPAD + 8 * (lane >> 4));
-        }
+        for (int i = 0; i < 4; ++i)
+            fa[i] = *reinterpret_cast<const bf16x8*>(&la[cur][(64 * wm + 16 * i + (lane & 15)) * GPAD + 8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+            fb[j] = *reinterpret_cast<const bf16x8*>(&lb[cur][(WN * wn + 16 * j + (lane & 15)) * GPAD + 8 * (lane >> 4)]);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        if (more) R360_LSTORE(cur ^ 1)
+        __syncthreads();
     }
-    // epilogue: lane holds rows 16 i + 4 (lane / 16) + q, column 16 j + lane % 16 of its 64 x 64 quarter
+#undef R360_GLOAD
+#undef R360_LSTORE
+    // epilogue: lane holds rows 16 i + 4 (lane / 16) + q, column 16 j + lane % 16 of its 64 x WN part
     const int g4 = lane >> 4, l16 = lane & 15;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = c0 + 64 * wn + 16 * j + l16;
+        for (int j = 0; j < TJ; ++j) {
+            const int c = c0 + WN * wn + 16 * j + l16;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + 64 * wm + 16 * i + 4 * g4 + q;
@@ -381,20 +365,113 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                     else if (c < g.n_out) g.out[(int64_t)r * g.ldo + c] = (bf16)v;
                 } else if constexpr (EPI == EPI_RGB) {
                     if (c < 3) g.rgb[(int64_t)c * g.R + r] = 1.0f / (1.0f + expf(-(v + g.bias[c])));
-                } else if constexpr (EPI == EPI_DX) {
+                } else {
                     if (g.mask && !((float)g.mask[(int64_t)r * g.ldm + c] > 0.0f)) v = 0.0f;
                     g.out[(int64_t)r * g.ldo + c] = (bf16)v;
-                } else {
-                    g.part[(int64_t)slice * g.pstride + (int64_t)r * g.ldp + c] = v;
                 }
             }
         }
     }
-    if constexpr (EPI == EPI_DW) {
-        if (g.boff >= 0 && blockIdx.y == 0) {
-            if (tid < GT) colsum[tid] = csum;
-            __syncthreads();
-            if (tid < GT && r0 + tid < g.R) g.part[(int64_t)slice * g.pstride + g.boff + r0 + tid] = colsum[tid];
+}
+
+// Weight-gradient GEMM, tile GT x GT over one slice of the samples, DK
+// samples per step. Threads 0..127 load an 8 (samples) x 8 (columns) block
+// of A, threads 128..255 one of B, and transpose it in registers so that each
+// LDS row (one output row n, or one input column k') holds DK consecutive
+// samples: the MFMA fragments are then plain 16-byte LDS reads. The next
+// step's blocks are loaded while this step's MFMAs run. Bias gradients (row
+// sums of A over the samples) come from extra MFMAs against a ones fragment.
+constexpr int DK = 64;
+constexpr int DPAD = DK + 8;    // 144-byte LDS rows
+
+__device__ __forceinline__ void transpose8(const u4 in[8], u4 out[8]) {
+    // in[q] = 8 columns of sample row q (two 16-bit columns per dword);
+    // out[e] = 8 samples of column e (two consecutive samples per dword)
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const unsigned lo = in[2 * p][d], hi = in[2 * p + 1][d];
+            out[2 * d][p] = (lo & 0xFFFFu) | (hi << 16);
+            out[2 * d + 1][p] = (lo >> 16) | (hi & 0xFFFF0000u);
+        }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_dw(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) bf16 la[GT * DPAD], lb[GT * DPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
+    const int slice = blockIdx.z;
+    const int64_t mbeg = (int64_t)slice * g.Kc;
+    const int64_t mend = min(mbeg + g.Kc, g.Mtot);
+    // this thread's 8 x 8 block: samples 8 mb .. 8 mb + 7 of the step, columns 8 cb .. 8 cb + 7
+    const bool isA = tid < 128;
+    const int blk = tid & 127, mb = blk >> 4, cb = blk & 15;
+    const bf16* src = isA ? g.A : g.B;
+    const int64_t sr = isA ? g.a_sr : g.b_sr;
+    const int col = (isA ? r0 : c0) + 8 * cb;
+    const bool col_ok = col < (isA ? g.a_lim : g.b_lim);
+    bf16* dst = (isA ? la : lb) + 8 * cb * DPAD + 8 * mb;
+    const bool do_bias = g.boff >= 0 && blockIdx.y == 0 && wn == 0;
+    f32x4 acc[4][4], accb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    bf16x8 ones;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = (bf16)1.0f;
+    u4 v[8];
+#define R360_DWLOAD(m0)                                                                                  \
+    _Pragma("unroll") for (int q = 0; q < 8; ++q) {                                                      \
+        const int64_t m = (m0) + 8 * mb + q;                                                             \
+        v[q] = (col_ok && m < mend) ? *reinterpret_cast<const u4*>(src + m * sr + col) : u4{0u, 0u, 0u, 0u}; \
+    }
+    R360_DWLOAD(mbeg)
+    for (int64_t m0 = mbeg; m0 < mend; m0 += DK) {
+        u4 t[8];
+        transpose8(v, t);
+        __syncthreads();                       // the previous step's fragments have been read
+#pragma unroll
+        for (int e = 0; e < 8; ++e) *reinterpret_cast<u4*>(dst + e * DPAD) = t[e];
+        __syncthreads();
+        if (m0 + DK < mend) R360_DWLOAD(m0 + DK)
+#pragma unroll
+        for (int ks = 0; ks < DK / 32; ++ks) {
+            bf16x8 fa[4], fb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                fa[i] = *reinterpret_cast<const bf16x8*>(&la[(64 * wm + 16 * i + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
+                fb[i] = *reinterpret_cast<const bf16x8*>(&lb[(64 * wn + 16 * i + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+            if (do_bias) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], ones, accb[i], 0, 0, 0);
+            }
+        }
+    }
+#undef R360_DWLOAD
+    const int g4 = lane >> 4, l16 = lane & 15;
+    float* part = g.part + (int64_t)slice * g.pstride;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = r0 + 64 * wm + 16 * i + 4 * g4 + q;
+            if (r >= g.R) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = c0 + 64 * wn + 16 * j + l16;
+                if (c < g.C) part[(int64_t)r * g.ldp + c] = acc[i][j][q];
+            }
+            if (do_bias && l16 == 0) part[g.boff + r] = accb[i][q];
         }
     }
 }
@@ -446,7 +523,7 @@ struct GlobalWs {
     size_t bytes;
 };
 
-constexpr int G_SLICES = 64;
+constexpr int G_SLICES = 128;     // sample slices of the weight-gradient GEMMs
 
 static GlobalWs gcarve(void* base, const GNet& n, int64_t Nr, int S) {
     GlobalWs g{};
@@ -489,12 +566,23 @@ size_t global_workspace_bytes(int w, int c, int64_t Nr, int S) { return gcarve(n
 int64_t global_params(int w, int c) { return make_net(w, c).P; }
 
 static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
-    dim3 grid((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices);
+    if (epi == EPI_DW) {
+        hipLaunchKernelGGL(k_gemm_dw, dim3((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices), dim3(256), 0, st, a);
+        return hipGetLastError();
+    }
+    // full-width tiles for 256 output columns (each input row is read once); 128 otherwise
+    const bool wide = a.C > 128 && a.C <= 256;
+    const dim3 grid((a.R + GT - 1) / GT, wide ? 1 : (a.C + 127) / 128);
     switch (epi) {
-    case EPI_FWD: hipLaunchKernelGGL(k_gemm<EPI_FWD>, grid, dim3(256), 0, st, a); break;
-    case EPI_RGB: hipLaunchKernelGGL(k_gemm<EPI_RGB>, grid, dim3(256), 0, st, a); break;
-    case EPI_DX: hipLaunchKernelGGL(k_gemm<EPI_DX>, grid, dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL(k_gemm<EPI_DW>, grid, dim3(256), 0, st, a); break;
+    case EPI_FWD:
+        if (wide) hipLaunchKernelGGL((k_gemm<EPI_FWD, 256>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gemm<EPI_FWD, 128>), grid, dim3(256), 0, st, a);
+        break;
+    case EPI_RGB: hipLaunchKernelGGL((k_gemm<EPI_RGB, 128>), grid, dim3(256), 0, st, a); break;
+    default:
+        if (wide) hipLaunchKernelGGL((k_gemm<EPI_DX, 256>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_gemm<EPI_DX, 128>), grid, dim3(256), 0, st, a);
+        break;
     }
     return hipGetLastError();
 }
@@ -533,8 +621,8 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     // forward: layer(A input [M x K] with row stride lda) -> out
     auto fwd = [&](int ly, const bf16* A, int64_t lda, bf16* out, int64_t ldo, bool relu) {
         GemmArgs a{};
-        a.A = A; a.a_sr = lda; a.a_sk = 1;
-        a.B = Wm(ly); a.b_sr = n.L[ly].K; a.b_sk = 1;
+        a.A = A; a.a_sr = lda; 
+        a.B = Wm(ly); a.b_sr = n.L[ly].K;
         a.R = (int)M; a.C = n.L[ly].N; a.Kc = n.L[ly].K;
         a.bias = Bv(ly); a.relu = relu; a.out = out; a.ldo = ldo; a.n_out = n.L[ly].N; a.sig_col = -1;
         return gemm(EPI_FWD, a, 1, st);
@@ -549,8 +637,8 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     if ((e = fwd(G8, g.h[7], w, g.h[8], w, false)) != hipSuccess) return e;
     {   // head: relu(Wf h8 + bf) -> x10[:, :w]; relu(ws h8 + bs) -> sigma
         GemmArgs a{};
-        a.A = g.h[8]; a.a_sr = w; a.a_sk = 1;
-        a.B = Wm(GH); a.b_sr = w; a.b_sk = 1;
+        a.A = g.h[8]; a.a_sr = w; 
+        a.B = Wm(GH); a.b_sr = w;
         a.R = (int)M; a.C = w + 1; a.Kc = w;
         a.bias = Bv(GH); a.relu = true; a.out = g.x10; a.ldo = ld10; a.n_out = w; a.sig_col = w; a.sig = g.sig;
         if ((e = gemm(EPI_FWD, a, 1, st)) != hipSuccess) return e;
@@ -558,8 +646,8 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     if ((e = fwd(G10, g.x10, ld10, g.h10, c, true)) != hipSuccess) return e;
     {
         GemmArgs a{};
-        a.A = g.h10; a.a_sr = c; a.a_sk = 1;
-        a.B = Wm(G11); a.b_sr = c; a.b_sk = 1;
+        a.A = g.h10; a.a_sr = c; 
+        a.B = Wm(G11); a.b_sr = c;
         a.R = (int)M; a.C = 3; a.Kc = c;
         a.bias = Bv(G11); a.rgb = g.rgb;
         if ((e = gemm(EPI_RGB, a, 1, st)) != hipSuccess) return e;
@@ -578,13 +666,14 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     hipLaunchKernelGGL(k_gout_grads, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, g.rgb, g.drgb, g.dz11,
                        g.sig, g.dsig, g.dzb, (int)up32(w + 1), w);
 
-    const int64_t kslice = M / G_SLICES;          // M is a multiple of 128 * 64 below
+    // samples per slice: a multiple of the GEMM's step; the last slice is clipped to M
+    const int64_t kslice = ((M + G_SLICES - 1) / G_SLICES + DK - 1) / DK * DK;
     // input gradient: dX[M x K'] = dZ [M x NC] . W^T -> masked by act (if any)
     auto dx = [&](int ly, const bf16* dz, int64_t ldz, bf16* out, int64_t ldo, int ncols, const bf16* act,
                   int64_t ldact) {
         GemmArgs a{};
-        a.A = dz; a.a_sr = ldz; a.a_sk = 1;
-        a.B = Wt(ly); a.b_sr = n.L[ly].NC; a.b_sk = 1;
+        a.A = dz; a.a_sr = ldz; 
+        a.B = Wt(ly); a.b_sr = n.L[ly].NC;
         a.R = (int)M; a.C = ncols; a.Kc = n.L[ly].NC;
         a.out = out; a.ldo = ldo; a.mask = act; a.ldm = ldact;
         return gemm(EPI_DX, a, 1, st);
@@ -592,9 +681,9 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     // weight gradient partials: dW[N x K] = dZ^T [N x M] . X [M x K], sliced over M
     auto dw = [&](int ly, const bf16* dz, int64_t ldz, const bf16* x, int64_t ldx) {
         GemmArgs a{};
-        a.A = dz; a.a_sr = 1; a.a_sk = ldz;
-        a.B = x; a.b_sr = 1; a.b_sk = ldx;
-        a.R = n.L[ly].N; a.C = n.L[ly].K; a.Kc = (int)kslice;
+        a.A = dz; a.a_sr = ldz; a.a_lim = (int)std::min<int64_t>(ldz, up32(n.L[ly].N));
+        a.B = x; a.b_sr = ldx; a.b_lim = n.L[ly].K;
+        a.R = n.L[ly].N; a.C = n.L[ly].K; a.Kc = (int)kslice; a.Mtot = M;
         a.part = g.part + n.L[ly].g_off; a.pstride = n.g_elems; a.ldp = n.L[ly].K;
         a.boff = n.L[ly].gb_off >= 0 ? n.L[ly].gb_off - n.L[ly].g_off : -1;
         return gemm(EPI_DW, a, G_SLICES, st);
