@@ -286,8 +286,13 @@ typedef __attribute__((ext_vector_type(4))) unsigned u4;
 template <int EPI, int BN>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
     constexpr int WN = BN / 2, TJ = WN / 16, BQ = BN / 64;
-    __shared__ __attribute__((aligned(16))) bf16 la[2][GT * GPAD];
-    __shared__ __attribute__((aligned(16))) bf16 lb[2][BN * GPAD];
+    constexpr int SP = 64 + 8;                                   // epilogue staging row stride (elements)
+    constexpr int OPER = 2 * GT * GPAD + 2 * BN * GPAD, STAGE = 4 * 64 * SP;
+    // one LDS buffer: double-buffered operand slabs during the K loop, then
+    // the epilogue's staging area
+    __shared__ __attribute__((aligned(16))) bf16 smem[OPER > STAGE ? OPER : STAGE];
+    bf16 (*la)[GT * GPAD] = reinterpret_cast<bf16 (*)[GT * GPAD]>(smem);
+    bf16 (*lb)[BN * GPAD] = reinterpret_cast<bf16 (*)[BN * GPAD]>(smem + 2 * GT * GPAD);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int wm = wv >> 1, wn = wv & 1;
     const int r0 = blockIdx.x * GT, c0 = blockIdx.y * BN;
@@ -346,30 +351,83 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
     }
 #undef R360_GLOAD
 #undef R360_LSTORE
-    // epilogue: lane holds rows 16 i + 4 (lane / 16) + q, column 16 j + lane % 16 of its 64 x WN part
+    // Epilogue. Lane holds rows 16 i + 4 (lane / 16) + q, column 16 j + lane % 16
+    // of its wave's 64 x WN part. BF16 outputs go through LDS (the operand
+    // buffers are free now), 64 columns at a time per wave, and leave as
+    // 16-byte row pieces; the input-gradient mask is read the same way.
     const int g4 = lane >> 4, l16 = lane & 15;
+    if constexpr (EPI == EPI_RGB) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) {
-            const int c = c0 + WN * wn + 16 * j + l16;
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int r = r0 + 64 * wm + 16 * i + 4 * g4 + q;
-                if (r >= g.R || c >= g.C) continue;
-                float v = acc[i][j][q];
-                if constexpr (EPI == EPI_FWD) {
-                    if (g.bias) v += g.bias[c];
-                    if (g.relu) v = v > 0.0f ? v : 0.0f;
-                    if (c == g.sig_col) g.sig[r] = v;
-                    else if (c < g.n_out) g.out[(int64_t)r * g.ldo + c] = (bf16)v;
-                } else if constexpr (EPI == EPI_RGB) {
-                    if (c < 3) g.rgb[(int64_t)c * g.R + r] = 1.0f / (1.0f + expf(-(v + g.bias[c])));
+                const int c = c0 + WN * wn + l16;
+                if (r < g.R && c < 3) g.rgb[(int64_t)c * g.R + r] = 1.0f / (1.0f + expf(-(acc[i][0][q] + g.bias[c])));
+            }
+        return;
+    } else {
+        bf16* stg = smem + wv * 64 * SP;
+        const int rw = r0 + 64 * wm;                                 // first row of this wave
+#pragma unroll
+        for (int h = 0; h < WN / 64; ++h) {
+            const int cw = c0 + WN * wn + 64 * h;                    // first column of this half
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int j = 4 * h + jj;
+                    const int c = cw + 16 * jj + l16;
+                    float bsum = 0.0f;
+                    if constexpr (EPI == EPI_FWD) bsum = (g.bias && c < g.C) ? g.bias[c] : 0.0f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float v = acc[i][j][q] + bsum;
+                        if constexpr (EPI == EPI_FWD) {
+                            if (g.relu) v = v > 0.0f ? v : 0.0f;
+                            const int r = rw + 16 * i + 4 * g4 + q;
+                            if (c == g.sig_col && r < g.R) g.sig[r] = v;
+                        }
+                        stg[(16 * i + 4 * g4 + q) * SP + 16 * jj + l16] = (bf16)v;
+                    }
+                }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int ncols = EPI == EPI_FWD ? min(g.C, g.n_out) : g.C;   // columns that go to `out`
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int ch = lane + 64 * t;                        // 512 pieces of 8 columns
+                const int rr = ch >> 3, cc = 8 * (ch & 7);
+                const int r = rw + rr, c = cw + cc;
+                if (r >= g.R || c >= ncols) continue;
+                u4 val = *reinterpret_cast<const u4*>(&stg[rr * SP + cc]);
+                if constexpr (EPI == EPI_DX) {
+                    if (g.mask) {
+                        // keep the gradient where the forward activation is > 0 (ReLU)
+                        const u4 m = *reinterpret_cast<const u4*>(g.mask + (int64_t)r * g.ldm + c);
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) {
+                            const unsigned lo = m[d] & 0xFFFFu, hi = m[d] >> 16;
+                            const unsigned keep = ((lo != 0u && !(lo & 0x8000u)) ? 0xFFFFu : 0u) |
+                                                  ((hi != 0u && !(hi & 0x8000u)) ? 0xFFFF0000u : 0u);
+                            val[d] &= keep;
+                        }
+                    }
+                }
+                bf16* dst = g.out + (int64_t)r * g.ldo + c;
+                if (c + 8 <= ncols) {
+                    *reinterpret_cast<u4*>(dst) = val;
                 } else {
-                    if (g.mask && !((float)g.mask[(int64_t)r * g.ldm + c] > 0.0f)) v = 0.0f;
-                    g.out[(int64_t)r * g.ldo + c] = (bf16)v;
+                    const bf16x8 e8 = __builtin_bit_cast(bf16x8, val);
+#pragma unroll
+                    for (int e = 0; e < 8; ++e)
+                        if (c + e < ncols) dst[e] = e8[e];
                 }
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
 }
