@@ -35,6 +35,31 @@ PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, M
 HBM_PEAK_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_headline_bf16.md")
+TRAFFIC_SOURCES = ["paper_2208_02705_amd/csrc/mlp.hip", "paper_2208_02705_amd/csrc/r360_internal.h"]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the BF16 field-MLP forward from the committed
+    FETCH_SIZE / WRITE_SIZE profile, or None when the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        vals = {}
+        for line in open(TRAFFIC_FILE):
+            if " = " in line and line.split(" = ")[0] in ("traffic_bytes_per_launch", "source_hash"):
+                k, v = line.strip().split(" = ")
+                vals[k] = v
+        h = hashlib.sha256()
+        for f in TRAFFIC_SOURCES:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != vals.get("source_hash"):
+            return None
+        return float(vals["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -147,8 +172,10 @@ def main():
         achieved = S * FLOP_PER_SAMPLE_FWD / (avg * 1e-3) / 1e12
         line["roofline"] = {"bound": "mfma", "kernel": f"field MLP forward ({main_prec})", "achieved": achieved,
                             "peak": PEAK[main_prec], "unit": "TFLOP/s", "frac": achieved / PEAK[main_prec],
-                            "traffic": None, "avg_launch_ms": avg,
-                            "algorithmic_flop_per_launch": S * FLOP_PER_SAMPLE_FWD}
+                            "traffic": measured_traffic() if main_prec == "bf16" else None,
+                            "traffic_unit": "bytes per launch (FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                            "avg_launch_ms": avg, "algorithmic_flop_per_launch": S * FLOP_PER_SAMPLE_FWD,
+                            "algorithmic_bytes_per_launch": 52 * S}
         line["stages_ms"] = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
         # HBM-bound stages against the 8 TB/s roofline (algorithmic bytes)
         st = line["stages_ms"]
