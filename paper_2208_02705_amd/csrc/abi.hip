@@ -150,7 +150,7 @@ r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts
     if (!s) return inval("scene is NULL");
     r360_status st = check_opts(opts, allow_fp64);
     if (st != R360_OK) return st;
-    if (N <= 0) return inval("N must be positive");
+    if (N <= 0 || N > (int64_t(1) << 30)) return inval("N must be in [1, 2^30]");
     if (sample_cap(N, opts->max_samples) >= (int64_t(1) << 31))
         return inval("N * max_samples must stay below 2^31; split the rays");
     if (!ws) return inval("workspace is NULL");

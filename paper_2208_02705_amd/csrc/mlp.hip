@@ -68,8 +68,8 @@ __global__ __launch_bounds__(256) void k_repack(const float* __restrict__ weight
         if (tile < G::NT) b = w[L.b2() + 16 * tile + v];
         else if (tile < 2 * G::NT + 1) {
             const int row = 16 * (tile - G::NT) + v;
-            b = row < H ? w[L.bf() + row] : (row == H ? w[L.bs()] : 0.0f);
-        } else b = v < 3 ? w[L.b4() + v] : 0.0f;
+            b = row < H ? w[L.bf() + row] : (((row - H) & 3) == 0 ? w[L.bs()] : 0.0f);
+        } else b = (v & 3) < 3 ? w[L.b4() + (v & 3)] : 0.0f;
         bias[i] = b;
     }
 }
@@ -141,29 +141,50 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
         __syncthreads();
         const F8* W = lw + lane;
         const f32x4* bias = reinterpret_cast<const f32x4*>(lb) + g;
-        for (int c = pos + FCH * wv; c < fend; c += BCHK) {
-            int orig[NTILE];
-            bool valid[NTILE];
-            float dv[NTILE][3];
+        // Gathered inputs of a chunk: the sample behind each column (orig),
+        // its position input xh and direction dv. The next chunk's are
+        // loaded while this chunk's layers run: permutation entries before
+        // L1, t and ray before L2, the ray's o and d before L3 (each level
+        // needs the previous one), so the loads have a layer of MFMA work to
+        // arrive in.
+        int c = pos + FCH * wv;
+        // (no early exit here: every wave must reach the advance of pos and the
+        // barriers of the next field segment)
+        int orig[NTILE];
+        float xh[NTILE][3], dv[NTILE][3];
+        const int c0 = c < fend ? c : pos;             // an in-range stand-in when the wave has no chunk
+#pragma unroll
+        for (int n = 0; n < NTILE; ++n) {
+            const int sp = c0 + 16 * n + j;
+            orig[n] = a.perm[sp < fend ? sp : c0];
+        }
+#pragma unroll
+        for (int n = 0; n < NTILE; ++n) {
+            const unsigned u = (unsigned)orig[n];
+            const float t = a.t_mid[u];
+            const unsigned r = (unsigned)a.ray[u];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                dv[n][k] = a.d[k * (unsigned)a.N + r];
+                xh[n][k] = (__builtin_fmaf(t, dv[n][k], a.o[k * (unsigned)a.N + r]) - cc[k]) * a.inv_h;
+            }
+        }
+        for (; c < fend; c += BCHK) {   // no iterations when this wave has no chunk here
+            const int cn = c + BCHK;
+            const bool has_next = cn < fend;
+            int orig_n[NTILE];
+            float t_n[NTILE];
+            unsigned r_n[NTILE];
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n) {
+                const int sp = cn + 16 * n + j;
+                orig_n[n] = a.perm[has_next ? (sp < fend ? sp : cn) : c];
+            }
             F8 x0[NTILE], x1[NTILE];
 #pragma unroll
             for (int n = 0; n < NTILE; ++n) {
-                const int sp = c + 16 * n + j;
-                valid[n] = sp < fend;
-                orig[n] = a.perm[valid[n] ? sp : c];
-            }
-#pragma unroll
-            for (int n = 0; n < NTILE; ++n) {
-                const float t = a.t_mid[orig[n]];
-                const int64_t r = a.ray[orig[n]];
-                float xh[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    dv[n][k] = a.d[k * a.N + r];
-                    xh[k] = (__builtin_fmaf(t, dv[n][k], a.o[k * a.N + r]) - cc[k]) * a.inv_h;
-                }
                 float pe[16];
-                pe_position<__is_same(T, float)>(g, xh, pe);
+                pe_position<__is_same(T, float)>(g, xh[n], pe);
                 x0[n] = pack8<T>(pe);
                 x1[n] = pack8<T>(pe + 8);
             }
@@ -185,6 +206,12 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n) {
+                const unsigned u = (unsigned)orig_n[n];
+                t_n[n] = a.t_mid[u];
+                r_n[n] = (unsigned)a.ray[u];
+            }
             // L2: h -> h
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
@@ -201,7 +228,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             __builtin_amdgcn_sched_barrier(0);
-            // HEAD: h -> [f ; sigma]
+            // HEAD: h -> [f ; sigma] (sigma replicated in rows H, H+4, H+8, H+12)
 #pragma unroll
             for (int ot = 0; ot < NT + 1; ++ot) {
                 const f32x4 bb = bias[(NT + ot) * 4];
@@ -220,6 +247,14 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, false>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             }
             __builtin_amdgcn_sched_barrier(0);
+            float o_n[NTILE][3], d_n[NTILE][3];
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    o_n[n][k] = a.o[k * (unsigned)a.N + r_n[n]];
+                    d_n[n][k] = a.d[k * (unsigned)a.N + r_n[n]];
+                }
             // L3: [f ; g(d)] -> h (bias in the direction encoding's constant slot)
 #pragma unroll
             for (int n = 0; n < NTILE; ++n) {
@@ -244,7 +279,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             __builtin_amdgcn_sched_barrier(0);
-            // L4: h -> rgb
+            // L4: h -> rgb (rows 4g .. 4g+2 of every lane group g)
             constexpr int O4 = O3 + G::F_L3;
             {
                 const f32x4 bb = bias[(2 * NT + 1) * 4];
@@ -255,14 +290,34 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                     for (int n = 0; n < NTILE; ++n) acc[n][0] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][0]);
                 }
             }
-            if (g == 0) {
+            // Outputs: the sigma and rgb rows are replicated in every lane
+            // group, so lane group g finishes tile g (NTILE == 4 groups).
+            {
+                static_assert(NTILE == 4, "one output tile per lane group");
+                float z = zs[0], q0 = acc[0][0][0], q1 = acc[0][0][1], q2 = acc[0][0][2];
+                int og = orig[0];
 #pragma unroll
-                for (int n = 0; n < NTILE; ++n) {
-                    if (!valid[n]) continue;
-                    a.sigma[orig[n]] = softplusf(zs[n]);
-                    a.rgb[orig[n]] = sigmoidf(acc[n][0][0]);
-                    a.rgb[a.cap + orig[n]] = sigmoidf(acc[n][0][1]);
-                    a.rgb[2 * a.cap + orig[n]] = sigmoidf(acc[n][0][2]);
+                for (int n = 1; n < NTILE; ++n) {
+                    if (g == n) {
+                        z = zs[n]; q0 = acc[n][0][0]; q1 = acc[n][0][1]; q2 = acc[n][0][2]; og = orig[n];
+                    }
+                }
+                if (c + 16 * g + j < fend) {
+                    const unsigned u = (unsigned)og;
+                    a.sigma[u] = softplusf(z);
+                    a.rgb[u] = sigmoidf(q0);
+                    a.rgb[(unsigned)a.cap + u] = sigmoidf(q1);
+                    a.rgb[2 * (unsigned)a.cap + u] = sigmoidf(q2);
+                }
+            }
+            // the next chunk's position inputs
+#pragma unroll
+            for (int n = 0; n < NTILE; ++n) {
+                orig[n] = orig_n[n];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    dv[n][k] = d_n[n][k];
+                    xh[n][k] = (__builtin_fmaf(t_n[n], d_n[n][k], o_n[n][k]) - cc[k]) * a.inv_h;
                 }
             }
         }

@@ -296,15 +296,17 @@ __device__ float canon_weight(const float* w, int ly, int row, bool is_enc, int 
     case LY_L2:
         return w[L.W2() + row * H + feat_or_col];
     case LY_HD:
+        // the density row is repeated at H, H+4, H+8, H+12 so that every lane
+        // group of the accumulator holds it (the forward pass reads it there)
         if (row < H) return w[L.Wf() + row * H + feat_or_col];
-        if (row == H) return w[L.ws() + feat_or_col];
+        if (((row - H) & 3) == 0) return w[L.ws() + feat_or_col];
         return 0.0f;
     case LY_L3:
         if (!is_enc) return w[L.W3() + row * (H + DDIR) + feat_or_col];
         if (feat_or_col == SLOT_ZERO) return 0.0f;
         return feat_or_col == SLOT_BIAS ? w[L.b3() + row] : w[L.W3() + row * (H + DDIR) + H + feat_or_col];
-    default:
-        return row < 3 ? w[L.W4() + row * H + feat_or_col] : 0.0f;
+    default:   // rgb rows repeated at 4g .. 4g+2 for every lane group g
+        return (row & 3) < 3 ? w[L.W4() + (row & 3) * H + feat_or_col] : 0.0f;
     }
 }
 
