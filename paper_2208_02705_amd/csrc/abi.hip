@@ -123,6 +123,7 @@ Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P) {
     w.ray_grad = (float*)take(3 * N * 4);
     w.N = N;
     w.cap = cap;
+    w.slots = slot_map(max_samples);
     w.bytes = off;
     return w;
 }
@@ -170,7 +171,7 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
     const DdaParams p = dda_params(s, opts);
     {
         R360_STAGE(0, st);
-        R360_TRY("sample", launch_sample(src, p, N, w, nullptr, st));
+        R360_TRY("sample", launch_trace(src, p, N, w, st));
     }
     {
         R360_STAGE(1, st);
@@ -182,7 +183,7 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
     }
     {
         R360_STAGE(3, st);
-        R360_TRY("composite", launch_composite(w, N, rgb, depth, opacity, st));
+        R360_TRY("composite", launch_composite_slots(w, N, rgb, depth, opacity, st));
     }
     return R360_OK;
 }
@@ -460,7 +461,7 @@ r360_status r360_backward(const r360_scene* s, const float* o, const float* d, i
     w.rd = d;
     {
         R360_STAGE(5, S(stream));
-        R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
+        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, S(stream)));
     }
     {
         R360_STAGE(6, S(stream));
@@ -490,7 +491,7 @@ r360_status r360_train_step(const r360_scene* s, const float* o, const float* d,
     }
     {
         R360_STAGE(5, S(stream));
-        R360_TRY("composite backward", launch_composite_backward(w, N, grad_rgb, S(stream)));
+        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, S(stream)));
     }
     {
         R360_STAGE(6, S(stream));

@@ -125,11 +125,11 @@ __device__ __forceinline__ int dw_index(int ly, int out, int in) {
 }
 
 struct BwdArgs {
-    const int32_t* total;
+    const int32_t* total;       // field_start + F: number of samples
     const int32_t* field_start;
-    const int32_t* perm;
-    const float* t_mid;
-    const int32_t* ray;
+    const int32_t* perm;        // sorted position -> slot
+    const float* t_mid;         // slot layout
+    SlotMap slots;
     const float* o;
     const float* d;
     const float* dsigma;
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             const bool valid = sp < fend;
             const int orig = a.perm[valid ? sp : c];
             const float t = a.t_mid[orig];
-            const int64_t r = a.ray[orig];
+            const int64_t r = ray_of_slot((unsigned)orig, a.slots);
             const float dv[3] = {a.d[r], a.d[a.N + r], a.d[2 * a.N + r]};
             float xh[3];
 #pragma unroll
@@ -515,11 +515,11 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
                       hipStream_t st) {
     using BG = BwdGeom<H>;
     BwdArgs a;
-    a.total = w.ray_off + w.N;
+    a.total = w.field_start + s->mlp.n_fields;
     a.field_start = w.field_start;
     a.perm = w.perm;
     a.t_mid = w.t_mid;
-    a.ray = w.ray;
+    a.slots = w.slots;
     a.o = w.ro; a.d = w.rd;
     a.dsigma = w.dsigma; a.drgb = w.drgb;
     a.N = w.N; a.cap = w.cap;

@@ -172,6 +172,95 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
     }
 }
 
+// Compositing over the slot layout: one lane per ray (64 rays per wave),
+// walking its samples in t order; the lanes of a wave read sample k of their
+// rays from one contiguous 256-byte run, so every load is coalesced. Loads
+// are issued four samples at a time. The sums run in sample order, as in the
+// definition.
+constexpr int CB = 4;
+
+__global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restrict__ cnt, int64_t N, int64_t cap,
+                                                         int smax, const float* __restrict__ sigma,
+                                                         const float* __restrict__ rgb, const float* __restrict__ t_mid,
+                                                         const float* __restrict__ delta, float* __restrict__ out_rgb,
+                                                         float* __restrict__ depth, float* __restrict__ opacity) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int c = cnt[r];
+    const int64_t base = (r & ~int64_t(63)) * smax + (r & 63);
+    float S = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f, A = 0.0f;
+    for (int k = 0; k < c; k += CB) {
+        float sg[CB], dl[CB], tm[CB], q0[CB], q1[CB], q2[CB];
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            const int64_t i = base + 64 * (int64_t)min(k + u, c - 1);
+            sg[u] = sigma[i]; dl[u] = delta[i]; tm[u] = t_mid[i];
+            q0[u] = rgb[i]; q1[u] = rgb[cap + i]; q2[u] = rgb[2 * cap + i];
+        }
+#pragma unroll
+        for (int u = 0; u < CB; ++u) {
+            if (k + u < c) {
+                const float tau = sg[u] * dl[u];
+                const float w = expf(-S) * -expm1f(-tau);
+                c0 += w * q0[u]; c1 += w * q1[u]; c2 += w * q2[u];
+                D += w * tm[u];
+                A += w;
+                S += tau;
+            }
+        }
+    }
+    if (out_rgb) { out_rgb[r] = c0; out_rgb[N + r] = c1; out_rgb[2 * N + r] = c2; }
+    if (depth) depth[r] = D;
+    if (opacity) opacity[r] = A;
+}
+
+// Backward over the slot layout, one lane per ray: pass 1 recomputes C,
+// pass 2 repeats the same accumulation so that C - C_{<=i} is a difference of
+// identically computed partial sums (exactly 0 after the last sample):
+//   dL/dc_i = w_i g,  dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - ((C - C_{<=i}) . g)].
+__global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __restrict__ cnt, int64_t N, int64_t cap,
+                                                             int smax, const float* __restrict__ sigma,
+                                                             const float* __restrict__ rgb,
+                                                             const float* __restrict__ delta,
+                                                             const float* __restrict__ grad, float* __restrict__ dsigma,
+                                                             float* __restrict__ drgb) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const int c = cnt[r];
+    const int64_t base = (r & ~int64_t(63)) * smax + (r & 63);
+    const float g0 = grad[r], g1 = grad[N + r], g2 = grad[2 * N + r];
+    float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    for (int pass = 0; pass < 2; ++pass) {
+        float S = 0.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
+        for (int k = 0; k < c; k += CB) {
+            float sg[CB], dl[CB], q0[CB], q1[CB], q2[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const int64_t i = base + 64 * (int64_t)min(k + u, c - 1);
+                sg[u] = sigma[i]; dl[u] = delta[i];
+                q0[u] = rgb[i]; q1[u] = rgb[cap + i]; q2[u] = rgb[2 * cap + i];
+            }
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                if (k + u < c) {
+                    const float tau = sg[u] * dl[u];
+                    const float w = expf(-S) * -expm1f(-tau);
+                    P0 += w * q0[u]; P1 += w * q1[u]; P2 += w * q2[u];
+                    S += tau;
+                    if (pass == 1) {
+                        const int64_t i = base + 64 * (int64_t)(k + u);
+                        const float cg = q0[u] * g0 + q1[u] * g1 + q2[u] * g2;
+                        const float rg = (C0 - P0) * g0 + (C1 - P1) * g1 + (C2 - P2) * g2;
+                        dsigma[i] = dl[u] * (expf(-S) * cg - rg);
+                        drgb[i] = w * g0; drgb[cap + i] = w * g1; drgb[2 * cap + i] = w * g2;
+                    }
+                }
+            }
+        }
+        C0 = P0; C1 = P1; C2 = P2;
+    }
+}
+
 // Loss L = 1/(3N) sum (C - C*)^2: per-block partial sums (fixed order), and
 // dL/dC = 2 (C - C*) / (3N) per ray and channel.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, const float* __restrict__ target, int64_t N,
@@ -307,6 +396,19 @@ hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* de
     const int rpw = rays_per_wave(N);
     hipLaunchKernelGGL(k_composite, dim3(wave_blocks(N, rpw)), dim3(256), 0, st, w.ray_off, w.ray, N, w.cap, rpw,
                        w.sigma, w.rgb, w.t_mid, w.delta, rgb, depth, opacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
+                                  hipStream_t st) {
+    hipLaunchKernelGGL(k_composite_slots, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.slots.smax, w.sigma,
+                       w.rgb, w.t_mid, w.delta, rgb, depth, opacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st) {
+    hipLaunchKernelGGL(k_composite_bwd_slots, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.slots.smax,
+                       w.sigma, w.rgb, w.delta, grad_rgb, w.dsigma, w.drgb);
     return hipGetLastError();
 }
 

@@ -83,11 +83,10 @@ __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + __
 __device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 struct FwdArgs {
-    const int32_t* total;        // ray_off + N
-    const int32_t* field_start;  // [F+1]
-    const int32_t* perm;
-    const float* t_mid;
-    const int32_t* ray;
+    const int32_t* field_start;  // [F+1], field_start[F] = number of samples
+    const int32_t* perm;         // sorted position -> slot
+    const float* t_mid;          // [cap] slot layout
+    SlotMap slots;
     const float* o;              // [3][N]
     const float* d;
     int64_t N, cap;
@@ -125,7 +124,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
     const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15, wv = threadIdx.x >> 6;
     const int nb = gridDim.x;
     const int b = xcd_block(blockIdx.x, nb);
-    const int S = *a.total;
+    const int S = a.field_start[a.F];
     constexpr int BCHK = FWD_WAVES * FCH;
     const int per = (((S + nb - 1) / nb) + BCHK - 1) / BCHK * BCHK;
     const int beg = min(S, b * per), end = min(S, beg + per);
@@ -162,7 +161,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
         for (int n = 0; n < NTILE; ++n) {
             const unsigned u = (unsigned)orig[n];
             const float t = a.t_mid[u];
-            const unsigned r = (unsigned)a.ray[u];
+            const unsigned r = ray_of_slot(u, a.slots);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 dv[n][k] = a.d[k * (unsigned)a.N + r];
@@ -210,7 +209,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             for (int n = 0; n < NTILE; ++n) {
                 const unsigned u = (unsigned)orig_n[n];
                 t_n[n] = a.t_mid[u];
-                r_n[n] = (unsigned)a.ray[u];
+                r_n[n] = ray_of_slot(u, a.slots);
             }
             // L2: h -> h
 #pragma unroll
@@ -351,11 +350,10 @@ hipError_t fwd_launch(const FwdArgs& a, hipStream_t st) {
 template <int H>
 hipError_t fwd_h(const r360_scene* s, const Workspace& w, int precision, hipStream_t st) {
     FwdArgs a;
-    a.total = w.ray_off + w.N;
     a.field_start = w.field_start;
     a.perm = w.perm;
     a.t_mid = w.t_mid;
-    a.ray = w.ray;
+    a.slots = w.slots;
     a.o = w.ro; a.d = w.rd;
     a.N = w.N; a.cap = w.cap;
     a.F = s->mlp.n_fields;

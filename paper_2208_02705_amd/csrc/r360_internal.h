@@ -361,8 +361,25 @@ struct r360_equirect {
 namespace r360 {
 
 // Workspace carve-up (all offsets 256-byte aligned).
+// Sample layouts. Renders and training keep the traversal's slot layout:
+// sample k of ray r at slot (r - r % 64) * S + 64 k + r % 64 (S =
+// max_samples), per-ray counts in ray_off[0..N) and no prefix sum; the ray
+// of a slot follows from its index (ray_of_slot). The sampling entry point
+// and the FP64 gradient check use the compact layout: ray r's samples at
+// ray_off[r] .. ray_off[r+1] (exclusive prefix, ray_off[N] = total).
+struct SlotMap {
+    int smax;            // S
+    uint64_t magic;      // ceil(2^40 / S): (slot / 64) / S by a multiply (exact for slot < 2^31, S <= 256)
+};
+inline SlotMap slot_map(int smax) { return SlotMap{smax, ((uint64_t(1) << 40) + smax - 1) / smax}; }
+__device__ __forceinline__ unsigned ray_of_slot(unsigned slot, const SlotMap& m) {
+    const unsigned q = slot >> 6;                                   // block * S + k
+    const unsigned blk = (unsigned)(((uint64_t)q * m.magic) >> 40);
+    return (blk << 6) | (slot & 63u);
+}
+
 struct Workspace {
-    int32_t* ray_off;   // [N+1]   exclusive prefix of per-ray counts; ray_off[N] = total
+    int32_t* ray_off;   // [N+1]   per-ray counts (slot layout) or their exclusive prefix (compact layout)
     float* o;           // [3][N]  generated rays (equirect / pinhole)
     float* d;           // [3][N]
     float* t_mid;       // [cap]
@@ -385,10 +402,11 @@ struct Workspace {
     const float* ro;    // rays the downstream passes read: caller's or o/d above
     const float* rd;
     int64_t N, cap;
+    SlotMap slots;      // slot layout geometry (max_samples)
     size_t bytes;
 };
 
-constexpr int ROUTE_BLOCKS = 1024;        // 4 waves each
+constexpr int ROUTE_BLOCKS = 2048;        // 4 waves each
 constexpr int ROUTE_WAVES = ROUTE_BLOCKS * 4;
 constexpr int SCAN_TILE = 4096;           // elements per scan block (1024 threads x 4)
 constexpr int DW_SLOTS = 1024;            // two gradient partial slots per backward block
@@ -422,16 +440,24 @@ struct DdaParams {
 DdaParams dda_params(const r360_scene* s, const r360_render_opts* opts);
 
 hipError_t launch_rays(const RaySource& src, int64_t N, float* o, float* d, hipStream_t st);
+// Compact layout into w.t_mid/delta/ray/field (+ voxel ids), offsets in w.ray_off.
 hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w,
                          int32_t* voxel_out, hipStream_t st);
+// Slot layout into w.t_mid/delta/field, per-ray counts in w.ray_off.
+hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, hipStream_t st);
 hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64_t nvox, int n_fields,
                          int16_t* labels, hipStream_t st);
 hipError_t launch_route(const Workspace& w, int F, hipStream_t st);
 hipError_t launch_repack(r360_scene* s, const float* weights, hipStream_t st);
 hipError_t launch_repack_bwd(r360_scene* s, const float* weights, hipStream_t st);
 hipError_t launch_mlp_forward(const r360_scene* s, const Workspace& w, int precision, hipStream_t st);
+// Compositing over the compact layout with ray ids (w.ray_off offsets, w.ray) ...
 hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
                             hipStream_t st);
+// ... and over the slot layout (w.ray_off counts).
+hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
+                                  hipStream_t st);
+hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);
 hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, const float* target, float* loss,
                             float* grad_rgb, hipStream_t st);
 hipError_t launch_composite_backward(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);

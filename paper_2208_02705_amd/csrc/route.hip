@@ -1,37 +1,73 @@
 // Routing of samples to the local field that owns their voxel (Sec. 5:
 // each occupied voxel is labelled with its tiny MLP; the labels come from
-// Alg.1 Stage II). A stable counting sort by field id:
-//   1. every wave counts the field ids of a contiguous slice of the samples;
+// Alg.1 Stage II). A stable counting sort by field id over the samples in
+// slot layout (sample k of ray r at slot (r - r % 64) S + 64 k + r % 64):
+//   1. every wave takes a contiguous run of 64-ray blocks and counts the
+//      field ids of their samples (block by block, k by k, lane = ray);
 //   2. per field, an exclusive scan over the waves' counts; then a scan over
-//      the fields gives each field's first sorted position;
-//   3. every wave walks its slice again and places each sample at
-//      field_start + (earlier waves' count) + (rank among equal ids so far),
-//      the rank within 64 lanes coming from ballots over the id bits.
-// The result perm[sorted position] = ray-major sample index keeps ray order
-// inside each field, so the sort is deterministic.
+//      the fields gives each field's first sorted position (start[F] = total);
+//   3. every wave walks its blocks again in the same order and places each
+//      sample at field_start + (earlier waves' count) + (rank among equal ids
+//      so far), the rank within 64 lanes coming from ballots over the id bits.
+// perm[sorted position] = slot; the order inside each field is the fixed
+// walk order, so the sort is deterministic.
 #include "r360_internal.h"
 
 namespace r360 {
 
 namespace {
 
-__device__ __forceinline__ void slice(int S, int rw, int w, int& beg, int& end) {
-    const int per = (S + rw - 1) / rw;
-    beg = min(S, w * per);
-    end = min(S, beg + per);
+// The 64-ray blocks [beg, end) of route wave w.
+__device__ __forceinline__ void blocks_of(int64_t N, int rw, int w, int& beg, int& end) {
+    const int nblk = (int)((N + 63) / 64);
+    const int per = (nblk + rw - 1) / rw;
+    beg = min(nblk, w * per);
+    end = min(nblk, beg + per);
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int s = 32; s > 0; s >>= 1) v = max(v, __shfl_xor(v, s, 64));
+    return v;
+}
+
+// Field ids of sample levels k0 .. k0+RB-1 of this lane's ray in block blk
+// (-1 past the ray's count); the loads are issued together.
+constexpr int RB = 8;
+__device__ __forceinline__ void load_levels(const int32_t* __restrict__ field, int slot0, int k0, int c, int fv[RB]) {
+#pragma unroll
+    for (int u = 0; u < RB; ++u) {
+        const int k = k0 + u < c ? k0 + u : (c > 0 ? c - 1 : 0);
+        const int v = field[slot0 + 64 * k];
+        fv[u] = k0 + u < c ? v : -1;
+    }
 }
 
 template <int WPB>
-__global__ __launch_bounds__(WPB * 64) void k_hist(const int32_t* __restrict__ field, const int32_t* __restrict__ total,
-                                                   int F, int rw, int32_t* __restrict__ hist) {
+__global__ __launch_bounds__(WPB * 64) void k_hist(const int32_t* __restrict__ field, const int32_t* __restrict__ cnt,
+                                                   int64_t N, int smax, int F, int rw, int32_t* __restrict__ hist) {
     extern __shared__ int32_t lds[];
     const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t* h = lds + wl * F;
     for (int f = lane; f < F; f += 64) h[f] = 0;
     const int w = blockIdx.x * WPB + wl;
     int beg, end;
-    slice(*total, rw, w, beg, end);
-    for (int i = beg + lane; i < end; i += 64) atomicAdd(&h[field[i]], 1);
+    blocks_of(N, rw, w, beg, end);
+    int c_next = 0;
+    if (beg < end) { const int64_t r = (int64_t)beg * 64 + lane; c_next = r < N ? cnt[r] : 0; }
+    for (int blk = beg; blk < end; ++blk) {
+        const int c = c_next;
+        if (blk + 1 < end) { const int64_t r = (int64_t)(blk + 1) * 64 + lane; c_next = r < N ? cnt[r] : 0; }
+        const int kmax = wave_max(c);
+        const int slot0 = blk * 64 * smax + lane;
+        for (int k0 = 0; k0 < kmax; k0 += RB) {
+            int fv[RB];
+            load_levels(field, slot0, k0, c, fv);
+#pragma unroll
+            for (int u = 0; u < RB; ++u)
+                if (fv[u] >= 0) atomicAdd(&h[fv[u]], 1);
+        }
+    }
     __syncthreads();
     for (int f = lane; f < F; f += 64) hist[(int64_t)f * rw + w] = h[f];
 }
@@ -106,35 +142,52 @@ __global__ __launch_bounds__(1024) void k_fields(int32_t* __restrict__ start, in
 }
 
 template <int WPB>
-__global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict__ field, const int32_t* __restrict__ total,
-                                                      int F, int nbits, int rw, const int32_t* __restrict__ hist,
-                                                      const int32_t* __restrict__ start, int32_t* __restrict__ perm) {
+__global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict__ field, const int32_t* __restrict__ cnt,
+                                                      int64_t N, int smax, int F, int nbits, int rw,
+                                                      const int32_t* __restrict__ hist, const int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ perm) {
     extern __shared__ int32_t lds[];
     const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t* run = lds + wl * F;
     const int w = blockIdx.x * WPB + wl;
     int beg, end;
-    slice(*total, rw, w, beg, end);
+    blocks_of(N, rw, w, beg, end);
     if (beg < end)
         for (int f = lane; f < F; f += 64) run[f] = start[f] + hist[(int64_t)f * rw + w];
     __syncthreads();
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int c = beg; c < end; c += 64) {
-        const int i = c + lane;
-        const bool valid = i < end;
-        const int f = valid ? field[i] : 0;
-        uint64_t peers = __ballot(valid);
-        for (int b = 0; b < nbits; ++b) {
-            const bool bit = (f >> b) & 1;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
-        }
-        if (valid) {
-            const int rank = __popcll(peers & lt);
-            const int n = __popcll(peers);
-            const int pos = run[f] + rank;
-            perm[pos] = i;
-            if (rank == n - 1) run[f] = pos + 1;
+    int c_next = 0;
+    if (beg < end) { const int64_t r = (int64_t)beg * 64 + lane; c_next = r < N ? cnt[r] : 0; }
+    for (int blk = beg; blk < end; ++blk) {
+        const int c = c_next;
+        if (blk + 1 < end) { const int64_t r = (int64_t)(blk + 1) * 64 + lane; c_next = r < N ? cnt[r] : 0; }
+        const int kmax = wave_max(c);
+        const int slot0 = blk * 64 * smax + lane;
+        for (int k0 = 0; k0 < kmax; k0 += RB) {
+            int fv[RB];
+            load_levels(field, slot0, k0, c, fv);
+#pragma unroll
+            for (int u = 0; u < RB; ++u) {
+                if (k0 + u >= kmax) break;                  // wave-uniform
+                const bool valid = fv[u] >= 0;
+                const int f = valid ? fv[u] : 0;
+                uint64_t peers = __ballot(valid);
+                for (int bt = 0; bt < nbits; ++bt) {
+                    const bool bit = (f >> bt) & 1;
+                    const uint64_t m = __ballot(bit);
+                    peers &= bit ? m : ~m;
+                }
+                if (valid) {
+                    const int rank = __popcll(peers & lt);
+                    const int n = __popcll(peers);
+                    const int pos = run[f] + rank;
+                    perm[pos] = slot0 + 64 * (k0 + u);
+                    if (rank == n - 1) run[f] = pos + 1;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
         }
     }
 }
@@ -151,24 +204,25 @@ hipError_t launch_route(const Workspace& w, int F, hipStream_t st) {
     const int rw = route_waves(F);
     int nbits = 1;
     while ((1 << nbits) < F) ++nbits;
-    const int32_t* total = w.ray_off + w.N;
+    const int64_t N = w.N;
+    const int smax = w.slots.smax;
     if (F <= 4096) {
         const size_t lds = 4 * F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_hist<4>, dim3(rw / 4), dim3(256), lds, st, w.field, total, F, rw, w.hist);
+        hipLaunchKernelGGL(k_hist<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw, w.hist);
     } else {
         const size_t lds = F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_hist<1>, dim3(rw), dim3(64), lds, st, w.field, total, F, rw, w.hist);
+        hipLaunchKernelGGL(k_hist<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, rw, w.hist);
     }
     hipLaunchKernelGGL(k_rows, dim3(F), dim3(1024), 0, st, w.hist, rw, w.field_start);
     hipLaunchKernelGGL(k_fields, dim3(1), dim3(1024), 0, st, w.field_start, F);
     if (F <= 4096) {
         const size_t lds = 4 * F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, total, F, nbits, rw, w.hist,
-                           w.field_start, w.perm);
+        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, nbits, rw,
+                           w.hist, w.field_start, w.perm);
     } else {
         const size_t lds = F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, total, F, nbits, rw, w.hist,
-                           w.field_start, w.perm);
+        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, nbits, rw,
+                           w.hist, w.field_start, w.perm);
     }
     return hipGetLastError();
 }

@@ -431,6 +431,18 @@ hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, co
     return hipGetLastError();
 }
 
+hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, hipStream_t st) {
+    const unsigned nb = blocks_for(N, 256);
+    const Staging sg{w.t_mid, w.delta, w.field, nullptr};
+    if (src.mode == RAYS_EQUIRECT)
+        hipLaunchKernelGGL(k_trace<RAYS_EQUIRECT>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+    else if (src.mode == RAYS_PINHOLE)
+        hipLaunchKernelGGL(k_trace<RAYS_PINHOLE>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+    else
+        hipLaunchKernelGGL(k_trace<RAYS_GIVEN>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+    return hipGetLastError();
+}
+
 hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64_t nvox, int n_fields,
                          int16_t* labels, hipStream_t st) {
     int32_t* bad = nullptr;
