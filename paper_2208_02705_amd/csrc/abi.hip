@@ -152,8 +152,8 @@ r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts
     r360_status st = check_opts(opts, allow_fp64);
     if (st != R360_OK) return st;
     if (N <= 0 || N > (int64_t(1) << 30)) return inval("N must be in [1, 2^30]");
-    if (sample_cap(N, opts->max_samples) >= (int64_t(1) << 31))
-        return inval("N * max_samples must stay below 2^31; split the rays");
+    if (sample_cap(N, opts->max_samples) >= (int64_t(1) << 30))
+        return inval("N * max_samples must stay below 2^30; split the rays");
     if (!ws) return inval("workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
     *w = carve(ws, N, opts->max_samples, s->mlp.n_fields, s->P);

@@ -87,15 +87,17 @@ struct FwdArgs {
     const int32_t* perm;         // sorted position -> slot
     const float* t_mid;          // [cap] slot layout
     SlotMap slots;
-    const float* o;              // [3][N]
-    const float* d;
+    const float* o[3];           // per component, [N] each
+    const float* d[3];
     int64_t N, cap;
     int F;
     float c0, c1, c2, inv_h;
     const void* pack;            // [F][FRAGS16][64] fragments of the chosen element type
     const float* bias;
     float* sigma;
-    float* rgb;                  // [3][cap]
+    float* rgb0;                 // the three colour planes of rgb [3][cap]
+    float* rgb1;
+    float* rgb2;
 };
 
 __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) {
@@ -155,17 +157,17 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
         for (int n = 0; n < NTILE; ++n) {
             const int sp = c0 + 16 * n + j;
-            orig[n] = a.perm[sp < fend ? sp : c0];
+            orig[n] = ld32(a.perm, (unsigned)(sp < fend ? sp : c0));
         }
 #pragma unroll
         for (int n = 0; n < NTILE; ++n) {
             const unsigned u = (unsigned)orig[n];
-            const float t = a.t_mid[u];
+            const float t = ld32(a.t_mid, u);
             const unsigned r = ray_of_slot(u, a.slots);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                dv[n][k] = a.d[k * (unsigned)a.N + r];
-                xh[n][k] = (__builtin_fmaf(t, dv[n][k], a.o[k * (unsigned)a.N + r]) - cc[k]) * a.inv_h;
+                dv[n][k] = ld32(a.d[k], r);
+                xh[n][k] = (__builtin_fmaf(t, dv[n][k], ld32(a.o[k], r)) - cc[k]) * a.inv_h;
             }
         }
         for (; c < fend; c += BCHK) {   // no iterations when this wave has no chunk here
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
             for (int n = 0; n < NTILE; ++n) {
                 const int sp = cn + 16 * n + j;
-                orig_n[n] = a.perm[has_next ? (sp < fend ? sp : cn) : c];
+                orig_n[n] = ld32(a.perm, (unsigned)(has_next ? (sp < fend ? sp : cn) : c));
             }
             F8 x0[NTILE], x1[NTILE];
 #pragma unroll
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
             for (int n = 0; n < NTILE; ++n) {
                 const unsigned u = (unsigned)orig_n[n];
-                t_n[n] = a.t_mid[u];
+                t_n[n] = ld32(a.t_mid, u);
                 r_n[n] = ray_of_slot(u, a.slots);
             }
             // L2: h -> h
@@ -251,8 +253,8 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    o_n[n][k] = a.o[k * (unsigned)a.N + r_n[n]];
-                    d_n[n][k] = a.d[k * (unsigned)a.N + r_n[n]];
+                    o_n[n][k] = ld32(a.o[k], r_n[n]);
+                    d_n[n][k] = ld32(a.d[k], r_n[n]);
                 }
             // L3: [f ; g(d)] -> h (bias in the direction encoding's constant slot)
 #pragma unroll
@@ -303,10 +305,10 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                 }
                 if (c + 16 * g + j < fend) {
                     const unsigned u = (unsigned)og;
-                    a.sigma[u] = softplusf(z);
-                    a.rgb[u] = sigmoidf(q0);
-                    a.rgb[(unsigned)a.cap + u] = sigmoidf(q1);
-                    a.rgb[2 * (unsigned)a.cap + u] = sigmoidf(q2);
+                    st32(a.sigma, u, softplusf(z));
+                    st32(a.rgb0, u, sigmoidf(q0));
+                    st32(a.rgb1, u, sigmoidf(q1));
+                    st32(a.rgb2, u, sigmoidf(q2));
                 }
             }
             // the next chunk's position inputs
@@ -354,13 +356,13 @@ hipError_t fwd_h(const r360_scene* s, const Workspace& w, int precision, hipStre
     a.perm = w.perm;
     a.t_mid = w.t_mid;
     a.slots = w.slots;
-    a.o = w.ro; a.d = w.rd;
+    for (int k = 0; k < 3; ++k) { a.o[k] = w.ro + k * w.N; a.d[k] = w.rd + k * w.N; }
     a.N = w.N; a.cap = w.cap;
     a.F = s->mlp.n_fields;
     a.c0 = s->mlp.center[0]; a.c1 = s->mlp.center[1]; a.c2 = s->mlp.center[2];
     a.inv_h = 1.0f / s->mlp.half_extent;
     a.bias = s->bias;
-    a.sigma = w.sigma; a.rgb = w.rgb;
+    a.sigma = w.sigma; a.rgb0 = w.rgb; a.rgb1 = w.rgb + w.cap; a.rgb2 = w.rgb + 2 * w.cap;
     if (precision == R360_BF16) { a.pack = s->pack16_bf; return fwd_launch<H, __bf16>(a, st); }
     if (precision == R360_FP16) { a.pack = s->pack16_h; return fwd_launch<H, _Float16>(a, st); }
     a.pack = s->pack16_f;

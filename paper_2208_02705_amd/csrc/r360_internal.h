@@ -378,6 +378,19 @@ __device__ __forceinline__ unsigned ray_of_slot(unsigned slot, const SlotMap& m)
     return (blk << 6) | (slot & 63u);
 }
 
+// Element idx of an array through a 32-bit byte offset, so the load or store
+// addresses as (scalar base + vector offset) instead of 64-bit vector
+// arithmetic. Valid for arrays below 4 GiB: sample arrays hold fewer than
+// 2^30 entries and ray arrays are passed per component.
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, unsigned idx) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void st32(T* base, unsigned idx, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T)) = v;
+}
+
 struct Workspace {
     int32_t* ray_off;   // [N+1]   per-ray counts (slot layout) or their exclusive prefix (compact layout)
     float* o;           // [3][N]  generated rays (equirect / pinhole)
