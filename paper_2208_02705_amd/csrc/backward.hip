@@ -130,10 +130,10 @@ struct BwdArgs {
     const int32_t* perm;        // sorted position -> slot
     const float* t_mid;         // slot layout
     SlotMap slots;
-    const float* o;
-    const float* d;
+    const float* o[3];          // per component, [N] each
+    const float* d[3];
     const float* dsigma;
-    const float* drgb;          // [3][cap]
+    const float* drgb[3];       // colour planes of [3][cap]
     int64_t N, cap;
     int F;
     int P;
@@ -238,6 +238,25 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
         const F8* P = pk + (int64_t)f * G::FRAGS16 * WAVE + lane;
         const F8* PT = pt + (int64_t)f * G::FRAGS_T * WAVE + lane;
         const f32x4* bias = reinterpret_cast<const f32x4*>(a.bias + (int64_t)f * G::BIAS_FLOATS) + g;
+        // Gathered inputs of this lane's sample in the current chunk; the next
+        // chunk's are loaded while this chunk is processed (permutation entry
+        // first, then t, then o, d and the output gradients).
+        int orig;
+        float xh[3], dv[3], gsig, grgb[3];
+        {
+            const int sp = pos + col;
+            orig = ld32(a.perm, (unsigned)(sp < fend ? sp : pos));
+            const unsigned u = (unsigned)orig;
+            const float t = ld32(a.t_mid, u);
+            const unsigned r = ray_of_slot(u, a.slots);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                dv[k] = ld32(a.d[k], r);
+                xh[k] = (__builtin_fmaf(t, dv[k], ld32(a.o[k], r)) - cc[k]) * a.inv_h;
+                grgb[k] = ld32(a.drgb[k], u);
+            }
+            gsig = ld32(a.dsigma, u);
+        }
         for (int c = pos; c < fend; c += BCH) {
             // Keep the weight fragments out of registers across chunks: the
             // compiler would otherwise hoist all ~70 per-field fragment loads
@@ -248,15 +267,10 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             const F8* PTc = PT;
             asm volatile("" : "+v"(Pc));
             asm volatile("" : "+v"(PTc));
-            const int sp = c + col;
-            const bool valid = sp < fend;
-            const int orig = a.perm[valid ? sp : c];
-            const float t = a.t_mid[orig];
-            const int64_t r = ray_of_slot((unsigned)orig, a.slots);
-            const float dv[3] = {a.d[r], a.d[a.N + r], a.d[2 * a.N + r]};
-            float xh[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) xh[k] = (__builtin_fmaf(t, dv[k], a.o[k * a.N + r]) - cc[k]) * a.inv_h;
+            const bool valid = c + col < fend;
+            const int cn = c + BCH;
+            const int spn = cn + col;
+            const int orig_n = ld32(a.perm, (unsigned)(cn < fend ? (spn < fend ? spn : cn) : c));
 
             __builtin_amdgcn_sched_barrier(0);
             // ---- forward recompute ----
@@ -277,6 +291,9 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             }
             __builtin_amdgcn_sched_barrier(0);
             q += G::F_L1 * WAVE;
+            const unsigned un = (unsigned)orig_n;
+            const float t_n = ld32(a.t_mid, un);
+            const unsigned r_n = ray_of_slot(un, a.slots);
             F8 h1[KH], h2[KH], fb[KH], h3[KH];
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) h1[ks] = hand<T, true>(acc[2 * ks], acc[2 * ks + 1]);
@@ -298,6 +315,14 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             }
             __builtin_amdgcn_sched_barrier(0);
             q += G::F_HD * WAVE;
+            float o_n[3], d_n[3], grgb_n[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                o_n[k] = ld32(a.o[k], r_n);
+                d_n[k] = ld32(a.d[k], r_n);
+                grgb_n[k] = ld32(a.drgb[k], un);
+            }
+            const float gsig_n = ld32(a.dsigma, un);
             const float zs = acc[NT][0];
 #pragma unroll
             for (int ks = 0; ks < KH; ++ks) fb[ks] = hand<T, false>(acc[2 * ks], acc[2 * ks + 1]);
@@ -327,11 +352,11 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             float dzs = 0.0f;
             f32x4 dz4 = f32x4{0.f, 0.f, 0.f, 0.f};
             if (g == 0 && valid) {
-                dzs = a.dsigma[orig] * sigmoidf_(zs);                 // softplus' = sigmoid
+                dzs = gsig * sigmoidf_(zs);                           // softplus' = sigmoid
 #pragma unroll
                 for (int cch = 0; cch < 3; ++cch) {
                     const float s = sigmoidf_(o4[cch]);
-                    dz4[cch] = a.drgb[cch * a.cap + orig] * s * (1.0f - s);
+                    dz4[cch] = grgb[cch] * s * (1.0f - s);
                 }
             }
 
@@ -457,6 +482,15 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             __syncthreads();
             dw_stage<T, N1>(panel, PS, 64, NT, 4, wv, lane, w1);
             __syncthreads();
+            // the next chunk's inputs
+            orig = orig_n;
+            gsig = gsig_n;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                dv[k] = d_n[k];
+                grgb[k] = grgb_n[k];
+                xh[k] = (__builtin_fmaf(t_n, d_n[k], o_n[k]) - cc[k]) * a.inv_h;
+            }
         }
         // flush this field's tiles
         float* dst;
@@ -520,8 +554,10 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     a.perm = w.perm;
     a.t_mid = w.t_mid;
     a.slots = w.slots;
-    a.o = w.ro; a.d = w.rd;
-    a.dsigma = w.dsigma; a.drgb = w.drgb;
+    for (int k = 0; k < 3; ++k) {
+        a.o[k] = w.ro + k * w.N; a.d[k] = w.rd + k * w.N; a.drgb[k] = w.drgb + k * w.cap;
+    }
+    a.dsigma = w.dsigma;
     a.N = w.N; a.cap = w.cap;
     a.F = s->mlp.n_fields;
     a.P = (int)s->P;

@@ -31,6 +31,10 @@
 // Precision: BF16 or FP16 operands with FP32 accumulation, or FP32 (each
 // K = 32 step as eight 16x16x4 FP32 MFMAs over the same fragment layout).
 //
+// Each layer's MFMA loop runs at raised wave priority (s_setprio 1) and the
+// conversions at normal priority, so that a wave entering its MFMA phase
+// issues ahead of waves doing vector work and the two units overlap more.
+//
 // Scheduling barriers separate the layers: without them the compiler hoists
 // the LDS reads of every weight fragment of the network to the top of the
 // chunk, which needs more than 256 registers and spills to scratch (the
@@ -193,6 +197,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             F8 hb[NTILE][KH];
             __builtin_amdgcn_sched_barrier(0);
             // L1: encoding -> h (bias in the encoding's constant slot)
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
                 const F8 A0 = W[(2 * ot) * WAVE], A1 = W[(2 * ot + 1) * WAVE];
@@ -202,6 +207,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                     acc[n][ot] = mma<T>(A1, x1[n], acc[n][ot]);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
@@ -214,6 +220,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                 r_n[n] = ray_of_slot(u, a.slots);
             }
             // L2: h -> h
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
                 const f32x4 bb = bias[ot * 4];
@@ -224,12 +231,14 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                     for (int n = 0; n < NTILE; ++n) acc[n][ot] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][ot]);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             __builtin_amdgcn_sched_barrier(0);
             // HEAD: h -> [f ; sigma] (sigma replicated in rows H, H+4, H+8, H+12)
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ot = 0; ot < NT + 1; ++ot) {
                 const f32x4 bb = bias[(NT + ot) * 4];
@@ -240,6 +249,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                     for (int n = 0; n < NTILE; ++n) acc[n][ot] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][ot]);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             float zs[NTILE];
 #pragma unroll
             for (int n = 0; n < NTILE; ++n) {
@@ -264,6 +274,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                 x0[n] = pack8<T>(dpe);
             }
             constexpr int O3 = G::F_L1 + G::F_L2 + G::F_HD;
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int ot = 0; ot < NT; ++ot) {
 #pragma unroll
@@ -275,12 +286,14 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                     for (int n = 0; n < NTILE; ++n) acc[n][ot] = mma<T>(A, ks < KH ? hb[n][ks < KH ? ks : 0] : x0[n], acc[n][ot]);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int n = 0; n < NTILE; ++n)
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks) hb[n][ks] = hand<T, true>(acc[n][2 * ks], acc[n][2 * ks + 1]);
             __builtin_amdgcn_sched_barrier(0);
             // L4: h -> rgb (rows 4g .. 4g+2 of every lane group g)
+            __builtin_amdgcn_s_setprio(1);
             constexpr int O4 = O3 + G::F_L3;
             {
                 const f32x4 bb = bias[(2 * NT + 1) * 4];
@@ -291,6 +304,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                     for (int n = 0; n < NTILE; ++n) acc[n][0] = mma<T>(A, hb[n][ks], ks == 0 ? bb : acc[n][0]);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             // Outputs: the sigma and rgb rows are replicated in every lane
             // group, so lane group g finishes tile g (NTILE == 4 groups).
             {
