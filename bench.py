@@ -175,7 +175,7 @@ def main():
                             "traffic": measured_traffic() if main_prec == "bf16" else None,
                             "traffic_unit": "bytes per launch (FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
                             "avg_launch_ms": avg, "algorithmic_flop_per_launch": S * FLOP_PER_SAMPLE_FWD,
-                            "algorithmic_bytes_per_launch": 52 * S}
+                            "algorithmic_bytes_per_launch": 24 * S + 24 * W * H}
         line["stages_ms"] = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
         # HBM-bound stages against the 8 TB/s roofline (algorithmic bytes)
         st = line["stages_ms"]
