@@ -213,7 +213,19 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     constexpr int N1 = BG::PER_WAVE(0), N2 = BG::PER_WAVE(1), NH = BG::PER_WAVE(2), N3 = BG::PER_WAVE(3),
                   N4 = BG::PER_WAVE(4);
     extern __shared__ __attribute__((aligned(32))) char smem_raw[];
-    T* panel = reinterpret_cast<T*>(smem_raw);
+    // Two panels, used by alternate stages: a stage's panel is written while
+    // slower waves may still read the other one, so each stage needs a
+    // single barrier (after its panel is written; every wave has finished
+    // the stage before the previous one by then, which used this buffer).
+    // (FP32 panels are twice as large and do not fit twice in LDS: there the
+    // single panel is kept and the stage ends with a second barrier.)
+    constexpr bool DB = sizeof(T) == 2;
+    T* const panels = reinterpret_cast<T*>(smem_raw);
+    T* panel = panels;
+    auto flip = [&]() {
+        if constexpr (DB) panel = (panel == panels) ? panels + BG::ROWS * BG::PSTRIDE : panels;
+        else __syncthreads();
+    };
     const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15, wv = threadIdx.x >> 6;
     const int col = 16 * wv + j;                     // this lane's sample column in the panel
     const int nb = gridDim.x;
@@ -391,7 +403,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             put_tiles(H + 16, &dz4, 1);
             __syncthreads();
             dw_stage<T, N4>(panel, PS, H + 16, 1, NT + 1, wv, lane, w4);
-            __syncthreads();
+            flip();
             f32x4 dz[NT + 1];
             {
                 const F8 bz = hand<T, false>(dz4, f32x4{0.f, 0.f, 0.f, 0.f});
@@ -407,7 +419,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             put_tiles(H + 32, dz, NT);
             __syncthreads();
             dw_stage<T, N3>(panel, PS, H + 32, NT, NT + 2, wv, lane, w3);
-            __syncthreads();
+            flip();
             f32x4 df[NT + 1];
             {
                 F8 bz[KH];
@@ -429,7 +441,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             put_tiles(H + 16, df, NT + 1);
             __syncthreads();
             dw_stage<T, NH>(panel, PS, H + 16, NT + 1, NT + 1, wv, lane, wh);
-            __syncthreads();
+            flip();
             {
                 F8 bz[KHD];
 #pragma unroll
@@ -454,7 +466,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             put_tiles(H + 16, dz, NT);
             __syncthreads();
             dw_stage<T, N2>(panel, PS, H + 16, NT, NT + 1, wv, lane, w2);
-            __syncthreads();
+            flip();
             {
                 F8 bz[KH];
 #pragma unroll
@@ -481,7 +493,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             put_tiles(64, dz, NT);
             __syncthreads();
             dw_stage<T, N1>(panel, PS, 64, NT, 4, wv, lane, w1);
-            __syncthreads();
+            flip();
             // the next chunk's inputs
             orig = orig_n;
             gsig = gsig_n;
@@ -567,7 +579,7 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     a.bias = s->bias;
     a.grad = grad;
     a.part = w.dw_part;
-    const size_t lds = (size_t)BG::ROWS * BG::PSTRIDE * sizeof(T);
+    const size_t lds = (size_t)(sizeof(T) == 2 ? 2 : 1) * BG::ROWS * BG::PSTRIDE * sizeof(T);
     static int nb = 0;
     if (!nb) nb = resident(k_bwd<H, T>, lds);
     hipLaunchKernelGGL((k_bwd<H, T>), dim3(nb), dim3(64 * BW), lds, st, a);
