@@ -455,29 +455,36 @@ __device__ __forceinline__ void transpose8(const u4 in[8], u4 out[8]) {
         }
 }
 
-__global__ __launch_bounds__(256) void k_gemm_dw(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) bf16 la[GT * DPAD], lb[GT * DPAD];
+// TILE x TILE output tile: TILE = 128 with four waves of 64 x 64, or
+// TILE = 256 with eight waves of 64 x 128 (then each sample row of the
+// operands is read once per slice for a 256 x 256 layer).
+template <int TILE>
+__global__ __launch_bounds__(2 * TILE) void k_gemm_dw(GemmArgs g) {
+    constexpr int WM = TILE / 64, NW = 2 * TILE / 64, WNC = NW / WM, WCW = TILE / WNC, TJ = WCW / 16;
+    extern __shared__ __attribute__((aligned(16))) char dw_smem[];
+    bf16* la = reinterpret_cast<bf16*>(dw_smem);
+    bf16* lb = la + TILE * DPAD;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int wm = wv >> 1, wn = wv & 1;
-    const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
+    const int wm = wv % WM, wn = wv / WM;
+    const int r0 = blockIdx.x * TILE, c0 = blockIdx.y * TILE;
     const int slice = blockIdx.z;
     const int64_t mbeg = (int64_t)slice * g.Kc;
     const int64_t mend = min(mbeg + g.Kc, g.Mtot);
     // this thread's 8 x 8 block: samples 8 mb .. 8 mb + 7 of the step, columns 8 cb .. 8 cb + 7
-    const bool isA = tid < 128;
-    const int blk = tid & 127, mb = blk >> 4, cb = blk & 15;
+    const bool isA = tid < TILE;
+    const int blk = tid % TILE, mb = blk / (TILE / 8), cb = blk % (TILE / 8);
     const bf16* src = isA ? g.A : g.B;
     const int64_t sr = isA ? g.a_sr : g.b_sr;
     const int col = (isA ? r0 : c0) + 8 * cb;
     const bool col_ok = col < (isA ? g.a_lim : g.b_lim);
     bf16* dst = (isA ? la : lb) + 8 * cb * DPAD + 8 * mb;
     const bool do_bias = g.boff >= 0 && blockIdx.y == 0 && wn == 0;
-    f32x4 acc[4][4], accb[4];
+    f32x4 acc[4][TJ], accb[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         accb[i] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
     bf16x8 ones;
 #pragma unroll
@@ -499,16 +506,17 @@ __global__ __launch_bounds__(256) void k_gemm_dw(GemmArgs g) {
         if (m0 + DK < mend) R360_DWLOAD(m0 + DK)
 #pragma unroll
         for (int ks = 0; ks < DK / 32; ++ks) {
-            bf16x8 fa[4], fb[4];
+            bf16x8 fa[4], fb[TJ];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < 4; ++i)
                 fa[i] = *reinterpret_cast<const bf16x8*>(&la[(64 * wm + 16 * i + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
-                fb[i] = *reinterpret_cast<const bf16x8*>(&lb[(64 * wn + 16 * i + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
-            }
+#pragma unroll
+            for (int j = 0; j < TJ; ++j)
+                fb[j] = *reinterpret_cast<const bf16x8*>(&lb[(WCW * wn + 16 * j + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
             if (do_bias) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) accb[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], ones, accb[i], 0, 0, 0);
@@ -525,8 +533,8 @@ __global__ __launch_bounds__(256) void k_gemm_dw(GemmArgs g) {
             const int r = r0 + 64 * wm + 16 * i + 4 * g4 + q;
             if (r >= g.R) continue;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = c0 + 64 * wn + 16 * j + l16;
+            for (int j = 0; j < TJ; ++j) {
+                const int c = c0 + WCW * wn + 16 * j + l16;
                 if (c < g.C) part[(int64_t)r * g.ldp + c] = acc[i][j][q];
             }
             if (do_bias && l16 == 0) part[g.boff + r] = accb[i][q];
@@ -581,7 +589,7 @@ struct GlobalWs {
     size_t bytes;
 };
 
-constexpr int G_SLICES = 128;     // sample slices of the weight-gradient GEMMs
+constexpr int G_SLICES = 256;     // sample slices of the weight-gradient GEMMs
 
 static GlobalWs gcarve(void* base, const GNet& n, int64_t Nr, int S) {
     GlobalWs g{};
@@ -625,7 +633,21 @@ int64_t global_params(int w, int c) { return make_net(w, c).P; }
 
 static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
     if (epi == EPI_DW) {
-        hipLaunchKernelGGL(k_gemm_dw, dim3((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices), dim3(256), 0, st, a);
+        // 256 x 256 tiles for layers that fill them exactly (each operand row read once per slice)
+        const size_t lds256 = (size_t)2 * 256 * DPAD * sizeof(bf16), lds128 = (size_t)2 * 128 * DPAD * sizeof(bf16);
+        if (a.R % 256 == 0 && a.C % 256 == 0) {
+            static bool attr = false;       // more than 64 KB of dynamic LDS must be allowed explicitly
+            if (!attr) {
+                const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_dw<256>),
+                                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds256);
+                if (e != hipSuccess) return e;
+                attr = true;
+            }
+            hipLaunchKernelGGL(k_gemm_dw<256>, dim3(a.R / 256, a.C / 256, slices), dim3(512), lds256, st, a);
+        }
+        else
+            hipLaunchKernelGGL(k_gemm_dw<128>, dim3((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices), dim3(256), lds128,
+                               st, a);
         return hipGetLastError();
     }
     // full-width tiles for 256 output columns (each input row is read once); 128 otherwise
