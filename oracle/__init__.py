@@ -64,6 +64,12 @@ class OrcGlobal(C.Structure):
                 ("voxel", C.c_float)]
 
 
+class OrcOcc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_float * 3), ("voxel", C.c_float), ("near_", C.c_float),
+                ("far_", C.c_float), ("l_hit", C.c_float), ("l_miss", C.c_float), ("l_min", C.c_float),
+                ("l_max", C.c_float), ("min_opacity", C.c_float)]
+
+
 _lib = None
 
 
@@ -94,6 +100,9 @@ def lib():
             "orc_local_params": (i64, [C.c_int, C.c_int, C.c_int]),
             "orc_global_params": (i64, [C.c_int, C.c_int, C.c_int, C.c_int]),
             "orc_adam": (None, [i64, vp, vp, vp, vp, i64, f64, f64, f64, f64]),
+            "orc_depth_stats": (None, [i64, C.c_int, vp, vp, vp, vp, vp, vp]),
+            "orc_occupancy_update": (None, [vp, vp, vp, i64, vp, vp, vp, vp, vp, C.c_int]),
+            "orc_global_measure": (None, [vp, i64, vp, vp, vp, vp, vp, C.c_int]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -300,13 +309,8 @@ def invdepth_t(n_samples: int, near: float, far: float):
     return t, delta
 
 
-def global_step(weights, o, d, target, n_samples=128, near=0.1, far=20.0, width=256, color_width=128,
-                L_xyz=10, L_dir=4, center=(0.0, 0.0, 0.0), half_extent=4.0, grid_n=128, grid_lo=-4.0,
-                voxel=0.0625, occupancy=True, threads: Optional[int] = None):
-    """Global field forward + backward; returns dict(loss, grad, rgb, depth, opacity, occ_max)."""
-    w = _c(weights, np.float32)
-    o = _c(o, np.float32); d = _c(d, np.float32); target = _c(target, np.float32)
-    N = o.shape[1]
+def _global_desc(w, n_samples, near, far, width, color_width, L_xyz, L_dir, center, half_extent, grid_n, grid_lo,
+                 voxel):
     g = OrcGlobal()
     g.width, g.color_width, g.L_xyz, g.L_dir, g.n_samples = width, color_width, L_xyz, L_dir, n_samples
     g.near_, g.far_ = near, far
@@ -316,6 +320,18 @@ def global_step(weights, o, d, target, n_samples=128, near=0.1, far=20.0, width=
     g.n[:] = [grid_n] * 3
     g.lo[:] = [grid_lo] * 3
     g.voxel = voxel
+    return g
+
+
+def global_step(weights, o, d, target, n_samples=128, near=0.1, far=20.0, width=256, color_width=128,
+                L_xyz=10, L_dir=4, center=(0.0, 0.0, 0.0), half_extent=4.0, grid_n=128, grid_lo=-4.0,
+                voxel=0.0625, occupancy=True, threads: Optional[int] = None):
+    """Global field forward + backward; returns dict(loss, grad, rgb, depth, opacity, occ_max)."""
+    w = _c(weights, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32); target = _c(target, np.float32)
+    N = o.shape[1]
+    g = _global_desc(w, n_samples, near, far, width, color_width, L_xyz, L_dir, center, half_extent, grid_n, grid_lo,
+                     voxel)
     grad = np.empty(len(w), np.float64)
     rgb = np.empty((3, N)); depth = np.empty(N); opac = np.empty(N)
     occ = np.zeros(grid_n ** 3, np.float64) if occupancy else None
@@ -330,3 +346,54 @@ def adam(w, g, m, v, step, lr, b1=0.9, b2=0.99, eps=1e-8):
     for a in (w, g, m, v):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     lib().orc_adam(len(w), _p(w), _p(g), _p(m), _p(v), step, lr, b1, b2, eps)
+
+
+# ---- Stage I occupancy (Sec. 4.1, Alg.1) ------------------------------------
+def logit(p: float) -> float:
+    return float(np.log(p / (1.0 - p)))
+
+
+def depth_stats(t, delta, sigma):
+    """Per-ray (depth, uncertainty, opacity) FP64 from dense [N, S] samples."""
+    t = _c(t, np.float32); delta = _c(delta, np.float32); sigma = _c(sigma, np.float32)
+    N, S = t.shape
+    D = np.empty(N); U = np.empty(N); A = np.empty(N)
+    lib().orc_depth_stats(N, S, _p(t), _p(delta), _p(sigma), _p(D), _p(U), _p(A))
+    return D, U, A
+
+
+def occ_desc(n, lo, voxel, near=0.0, far=float("inf"), p_hit=0.7, p_miss=0.4, l_min=-2.0, l_max=3.5,
+             min_opacity=0.5) -> OrcOcc:
+    g = OrcOcc()
+    g.n[:] = list(n) if np.ndim(n) else [n] * 3
+    g.lo[:] = list(lo) if np.ndim(lo) else [lo] * 3
+    g.voxel = voxel
+    g.near_, g.far_ = near, far
+    g.l_hit, g.l_miss = logit(p_hit), logit(p_miss)
+    g.l_min, g.l_max, g.min_opacity = l_min, l_max, min_opacity
+    return g
+
+
+def occupancy_update(desc: OrcOcc, logit_grid: np.ndarray, o, d, depth, uncert, opacity,
+                     threads: Optional[int] = None) -> np.ndarray:
+    """One pose's update of the FP32 logit grid [n2, n1, n0] in place; returns the probability grid."""
+    assert logit_grid.dtype == np.float32 and logit_grid.flags.c_contiguous
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    depth = _c(depth, np.float32); uncert = _c(uncert, np.float32); opacity = _c(opacity, np.float32)
+    N = o.shape[1]
+    prob = np.empty_like(logit_grid)
+    lib().orc_occupancy_update(C.byref(desc), _p(logit_grid), _p(prob), N, _p(o), _p(d), _p(depth), _p(uncert),
+                               _p(opacity), threads or default_threads())
+    return prob
+
+
+def global_measure(weights, o, d, n_samples=128, near=0.1, far=20.0, width=256, color_width=128, L_xyz=10, L_dir=4,
+                   center=(0.0, 0.0, 0.0), half_extent=4.0, threads: Optional[int] = None):
+    """Stage I measurement of the global field: per-ray (depth, uncertainty, opacity), FP64."""
+    w = _c(weights, np.float32)
+    o = _c(o, np.float32); d = _c(d, np.float32)
+    N = o.shape[1]
+    g = _global_desc(w, n_samples, near, far, width, color_width, L_xyz, L_dir, center, half_extent, 1, 0.0, 1.0)
+    D = np.empty(N); U = np.empty(N); A = np.empty(N)
+    lib().orc_global_measure(C.byref(g), N, _p(o), _p(d), _p(D), _p(U), _p(A), threads or default_threads())
+    return D, U, A

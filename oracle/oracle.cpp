@@ -113,43 +113,49 @@ void to_world(const float* c2w, const float dc[3], float o[3], float d[3]) {
 // ---------------------------------------------------------------------------
 struct Seg { float t_mid, delta; int32_t voxel, field; };
 
-int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) {
+// The FP32 voxel walk shared by the sampler and the occupancy update: visits
+// the voxels the ray crosses between t0 = max(near, box entry) and t1 =
+// min(far, box exit) in increasing t and calls fn(lin, t_in, t_out) for every
+// segment of positive length (zero-length edge and corner touches are
+// skipped); fn returns false to stop the walk.
+template <class F>
+void walk_ray(const int32_t n[3], const float lo[3], float voxel, float near_, float far_, const float o[3],
+              const float d[3], F fn) {
     const float INF = std::numeric_limits<float>::infinity();
     float inv[3], hi[3];
     bool active[3];
-    float t0 = s.near_, t1 = ORC_PLANT == 9 ? INF : s.far_;
+    float t0 = near_, t1 = far_;
     for (int a = 0; a < 3; ++a) {
-        hi[a] = s.lo[a] + (float)s.n[a] * s.voxel;
+        hi[a] = lo[a] + (float)n[a] * voxel;
         active[a] = d[a] != 0.0f;
         if (active[a]) {
             inv[a] = 1.0f / d[a];
-            float ta = (s.lo[a] - o[a]) * inv[a];
+            float ta = (lo[a] - o[a]) * inv[a];
             float tb = (hi[a] - o[a]) * inv[a];
             t0 = std::max(t0, std::min(ta, tb));
             t1 = std::min(t1, std::max(ta, tb));
         } else {
             inv[a] = 0.0f;
-            if (!(o[a] >= s.lo[a] && o[a] < hi[a])) return 0;
+            if (!(o[a] >= lo[a] && o[a] < hi[a])) return;
         }
     }
-    if (!(t0 < t1)) return 0;
-    const float inv_vox = 1.0f / s.voxel;   // exact: the voxel edge is a power of two
+    if (!(t0 < t1)) return;
+    const float inv_vox = 1.0f / voxel;   // exact: the voxel edge is a power of two
     int idx[3];
     for (int a = 0; a < 3; ++a) {
         float p = std::fma(t0, d[a], o[a]);
-        float q = (p - s.lo[a]) * inv_vox;
+        float q = (p - lo[a]) * inv_vox;
         float fq = std::floor(q);
         int i = (int)fq;
         if (q == fq && d[a] < 0.0f) i -= 1;   // on a plane moving down: the lower voxel
-        idx[a] = std::min(std::max(i, 0), s.n[a] - 1);
+        idx[a] = std::min(std::max(i, 0), n[a] - 1);
     }
-    int count = 0;
     float t_in = t0;
     for (;;) {
         float tn[3];
         for (int a = 0; a < 3; ++a) {
             if (active[a]) {
-                float plane = std::fma((float)(idx[a] + (d[a] > 0.0f ? 1 : 0)), s.voxel, s.lo[a]);
+                float plane = std::fma((float)(idx[a] + (d[a] > 0.0f ? 1 : 0)), voxel, lo[a]);
                 tn[a] = (plane - o[a]) * inv[a];
             } else {
                 tn[a] = INF;
@@ -159,19 +165,28 @@ int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) 
         if (tn[1] < tn[am]) am = 1;
         if (tn[2] < tn[am]) am = 2;
         float t_out = std::min(tn[am], t1);
-        int64_t lin = idx[0] + (int64_t)s.n[0] * (idx[1] + (int64_t)s.n[1] * idx[2]);
-        if (t_out > t_in && s.occ[lin] > s.threshold && s.field[lin] >= 0) {
+        int64_t lin = idx[0] + (int64_t)n[0] * (idx[1] + (int64_t)n[1] * idx[2]);
+        if (t_out > t_in && !fn(lin, t_in, t_out)) break;
+        if (!(tn[am] < t1)) break;
+        t_in = std::max(t_in, tn[am]);
+        idx[am] += d[am] > 0.0f ? 1 : -1;
+        if (idx[am] < 0 || idx[am] >= n[am]) break;
+    }
+}
+
+int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) {
+    const float far_ = ORC_PLANT == 9 ? std::numeric_limits<float>::infinity() : s.far_;
+    int count = 0;
+    walk_ray(s.n, s.lo, s.voxel, s.near_, far_, o, d, [&](int64_t lin, float t_in, float t_out) {
+        if (s.occ[lin] > s.threshold && s.field[lin] >= 0) {
             out[count].t_mid = ORC_PLANT == 8 ? t_out : (t_in + t_out) * 0.5f;
             out[count].delta = t_out - t_in;
             out[count].voxel = (int32_t)lin;
             out[count].field = s.field[lin];
-            if (++count == s.max_samples) break;
+            if (++count == s.max_samples) return false;
         }
-        if (!(tn[am] < t1)) break;
-        t_in = std::max(t_in, tn[am]);
-        idx[am] += d[am] > 0.0f ? 1 : -1;
-        if (idx[am] < 0 || idx[am] >= s.n[am]) break;
-    }
+        return true;
+    });
     return count;
 }
 
@@ -357,6 +372,52 @@ void composite_backward(int n, const double* sigma, const double* rgb, const dou
         dsigma[i] = delta[i] * (T_next * cg + (ORC_PLANT == 10 ? rg : -rg));
     }
 }
+
+// ---------------------------------------------------------------------------
+// Stage I of Alg.1 (Sec. 4.1): the measurement a ray of the global field
+// gives. With the Eq.5 weights w_i of its samples: opacity A = sum w_i;
+// normalised weights v_i = w_i / A; depth D = sum v_i t_i (the Eq.4 depth
+// over normalised weights); uncertainty U = sqrt(sum v_i (t_i - D)^2), the
+// spread of the normalised weights about D. A ray with A = 0 gives D = U = 0.
+// ---------------------------------------------------------------------------
+void depth_stats(int n, const double* sigma, const double* t, const double* delta, double* D, double* U, double* A) {
+    std::vector<double> w(n), rgb(3 * (size_t)n, 0.0);
+    double C[3], Dw;
+    composite(n, sigma, rgb.data(), t, delta, C, &Dw, A, w.data());
+    *D = 0.0; *U = 0.0;
+    if (!(*A > 0.0)) return;
+    const double inv = ORC_PLANT == 16 ? 1.0 : 1.0 / *A;
+    for (int i = 0; i < n; ++i) *D += w[i] * inv * t[i];
+    double var = 0.0;
+    for (int i = 0; i < n; ++i) var += w[i] * inv * (t[i] - *D) * (t[i] - *D);
+    *U = std::sqrt(var);
+}
+
+// Stage I update for one sampling position (one pose): the logit form of
+// Eq.6, logit(p | z_1:t) = logit(p | z_1:t-1) + logit(p | z_t), with an
+// inverse sensor model read in the OctoMap manner the paper adopts:
+//  - a ray is a measurement when A >= min_opacity and D, U are finite, U >= 0;
+//  - walking its voxels (the sampler's FP32 walk, every voxel), a segment
+//    that ends at or before D - U is free space (logit l_miss < 0); the voxel
+//    whose segment [t_in, t_out) holds D is the hit, and the walk stops
+//    there; voxels inside the uncertainty band get nothing;
+//  - the hit's measurement logit shrinks with the ray's uncertainty:
+//    h = l_hit / (1 + U / voxel), all FP32 (the measurement probability
+//    follows the global field's own estimate);
+//  - per pose every voxel takes at most one measurement: the largest hit
+//    logit of the rays that end in it, otherwise l_miss if a ray passed
+//    through it freely;
+//  - the sum is clamped to [l_min, l_max] (Sec. 4.1: -2 and 3.5, i.e.
+//    probability 0.12 to 0.97); voxels without a measurement keep their value.
+// prob (optional) receives 1 / (1 + exp(-l)) for every voxel.
+struct OrcOcc {
+    int32_t n[3];
+    float lo[3];
+    float voxel;
+    float near_, far_;
+    float l_hit, l_miss, l_min, l_max;
+    float min_opacity;
+};
 
 template <class F>
 void parallel_for(int64_t n, int nthreads, F fn) {
@@ -790,6 +851,90 @@ void orc_global_mlp(const float* w, int width, int color_width, int Lx, int Ld, 
 int64_t orc_local_params(int hidden, int Lx, int Ld) { return (int64_t)local_params(hidden, 3 + 6 * Lx, 3 + 6 * Ld); }
 int64_t orc_global_params(int width, int color_width, int Lx, int Ld) {
     return (int64_t)global_params(width, color_width, 3 + 6 * Lx, 3 + 6 * Ld);
+}
+
+// ---- Stage I occupancy (Sec. 4.1, Alg.1) -----------------------------------
+// Per-ray measurement from dense samples [N][S] (FP32 inputs, FP64 result).
+void orc_depth_stats(int64_t N, int S, const float* t, const float* delta, const float* sigma, double* D, double* U,
+                     double* A) {
+    std::vector<double> sg(S), tt(S), dl(S);
+    for (int64_t r = 0; r < N; ++r) {
+        for (int k = 0; k < S; ++k) {
+            sg[k] = sigma[r * S + k]; tt[k] = t[r * S + k]; dl[k] = delta[r * S + k];
+        }
+        depth_stats(S, sg.data(), tt.data(), dl.data(), &D[r], &U[r], &A[r]);
+    }
+}
+
+// One pose's update of the logit grid [n2][n1][n0] (in place) from N rays.
+void orc_occupancy_update(const OrcOcc* g, float* logit, float* prob, int64_t N, const float* o, const float* d,
+                          const float* depth, const float* uncert, const float* opacity, int nthreads) {
+    const size_t ncell = (size_t)g->n[0] * g->n[1] * g->n[2];
+    const float inv_vox = 1.0f / g->voxel;
+    int nt = std::max(1, nthreads);
+    std::vector<std::vector<float>> hit(nt, std::vector<float>(ncell, 0.0f));
+    std::vector<std::vector<uint8_t>> miss(nt, std::vector<uint8_t>(ncell, 0));
+    parallel_for(N, nt, [&](int64_t b, int64_t e, int th) {
+        for (int64_t r = b; r < e; ++r) {
+            const float Dr = depth[r], Ur = uncert[r], Ar = opacity[r];
+            if (!(Ar >= g->min_opacity) || !std::isfinite(Dr) || !std::isfinite(Ur) || !(Ur >= 0.0f)) continue;
+            const float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
+            bool bad = false;
+            for (int a = 0; a < 3; ++a) bad = bad || !(oo[a] == oo[a]) || !(dv[a] == dv[a]);
+            if (bad) continue;
+            const float edge = ORC_PLANT == 14 ? Dr : Dr - Ur;
+            const float h = ORC_PLANT == 17 ? g->l_hit : g->l_hit / (1.0f + Ur * inv_vox);
+            walk_ray(g->n, g->lo, g->voxel, g->near_, g->far_, oo, dv, [&](int64_t lin, float t_in, float t_out) {
+                if (t_out <= edge) { miss[th][lin] = 1; return true; }
+                if (Dr < t_out) {
+                    if (t_in <= Dr) hit[th][lin] = std::max(hit[th][lin], h);
+                    return false;
+                }
+                return true;
+            });
+        }
+    });
+    for (size_t v = 0; v < ncell; ++v) {
+        float hv = 0.0f;
+        bool mv = false;
+        for (int t = 0; t < nt; ++t) { hv = std::max(hv, hit[t][v]); mv = mv || miss[t][v]; }
+        float l = logit[v];
+        const bool use_hit = ORC_PLANT == 15 ? (hv > 0.0f && !mv) : hv > 0.0f;
+        if (use_hit || mv) {
+            l = use_hit ? l + hv : l + g->l_miss;
+            if (ORC_PLANT != 13) l = std::min(std::max(l, g->l_min), g->l_max);
+            logit[v] = l;
+        }
+        if (prob) prob[v] = (float)(1.0 / (1.0 + std::exp(-(double)l)));
+    }
+}
+
+// Stage I measurement by the global field: its forward over the inverse-depth
+// samples of each ray, then the per-ray depth, uncertainty and opacity.
+void orc_global_measure(const OrcGlobal* g, int64_t N, const float* o, const float* d, double* depth,
+                        double* uncert, double* opacity, int nthreads) {
+    const int dx = 3 + 6 * g->L_xyz, dd = 3 + 6 * g->L_dir, ns = g->n_samples;
+    const size_t P = global_params(g->width, g->color_width, dx, dd);
+    std::vector<double> wd = widen(g->weights, P);
+    GlobalNet net = global_view(wd.data(), g->width, g->color_width, dx, dd);
+    std::vector<float> tt(ns), dl(ns);
+    orc_invdepth_t(ns, g->near_, g->far_, tt.data(), dl.data());
+    const float inv_h = 1.0f / g->half_extent;
+    parallel_for(N, std::max(1, nthreads), [&](int64_t b, int64_t e, int) {
+        GlobalAct act;
+        std::vector<double> sig(ns), tm(ns), de(ns);
+        for (int64_t r = b; r < e; ++r) {
+            float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
+            double dir[3] = {dv[0], dv[1], dv[2]};
+            for (int k = 0; k < ns; ++k) {
+                double xh[3];
+                for (int a = 0; a < 3; ++a) xh[a] = (double)((std::fma(tt[k], dv[a], oo[a]) - g->center[a]) * inv_h);
+                global_forward(net, xh, dir, g->L_xyz, g->L_dir, act);
+                sig[k] = act.sigma; tm[k] = tt[k]; de[k] = dl[k];
+            }
+            depth_stats(ns, sig.data(), tm.data(), de.data(), &depth[r], &uncert[r], &opacity[r]);
+        }
+    });
 }
 
 // ---- Adam (Sec. 6.1 training details: beta1 0.9, beta2 0.99) -------------

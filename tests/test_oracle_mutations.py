@@ -23,6 +23,11 @@ PLANTS = {
     10: "compositing backward: wrong sign of the remaining-colour term",
     11: "equirect rays: latitude sign flipped",
     12: "global field: encoding missing from the fifth-layer input",
+    13: "occupancy: logit sum not clamped to the paper's range",
+    14: "occupancy: free space runs up to the depth, ignoring the uncertainty band",
+    15: "occupancy: a free pass overrides a hit in the same pose",
+    16: "depth statistics: weights not normalised by the opacity",
+    17: "occupancy: hit logit not weakened by the uncertainty",
 }
 
 

@@ -559,3 +559,208 @@ def test_adam_first_step_is_signed_lr(orc):
     # second step with the same gradient keeps the same magnitude (bias correction)
     orc.adam(w, g, m, v, 2, 1e-3)
     assert np.allclose(w[:3], 1 - 2e-3 * np.sign(g[:3]), atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Stage I probabilistic occupancy (Sec. 4.1, Eq.6, Alg.1)
+# ---------------------------------------------------------------------------
+
+def _sig(l):
+    return 1.0 / (1.0 + math.exp(-l))
+
+
+def test_occupancy_logit_range_matches_paper(orc):
+    g = golden("paper_constants.json")["logit_range"]
+    assert round(_sig(g["hi"]), 2) == g["p_hi"] and round(_sig(g["lo"]), 2) == g["p_lo"]
+    assert abs(orc.logit(0.97) - 3.476) < 5e-4 and abs(orc.logit(0.12) - (-1.992)) < 5e-4
+    desc = orc.occ_desc(8, -4.0, 1.0)
+    o = np.array([[-3.9], [0.5], [0.5]], np.float32)
+    d = np.array([[1.0], [0.0], [0.0]], np.float32)
+    one = lambda v: np.array([v], np.float32)
+    L = np.zeros((8, 8, 8), np.float32)
+    # repeated sharp hits (one pose each) saturate at the upper bound; the
+    # voxel counts as occupied (p > 0.97) from the first pose whose sum
+    # passes logit(0.97): ceil(3.476 / logit(0.7)) = 5
+    first = None
+    for k in range(1, 9):
+        p = orc.occupancy_update(desc, L, o, d, one(4.4), one(0.0), one(1.0))
+        if first is None and p[4, 4, 4] > g["p_hi"]:
+            first = k
+    assert first == math.ceil(math.log(0.97 / 0.03) / math.log(0.7 / 0.3)) == 5
+    assert L[4, 4, 4] == np.float32(g["hi"]) and round(float(p[4, 4, 4]), 2) == g["p_hi"]
+    # the free voxels in front saturate at the lower bound
+    assert np.all(L[4, 4, :4] == np.float32(g["lo"])) and np.all(np.round(p[4, 4, :4], 2) == g["p_lo"])
+    assert np.all(L[4, 4, 5:] == 0) and np.count_nonzero(L) == 5
+
+
+def test_depth_stats_closed_forms(orc):
+    t = np.array([[1.0, 2.0, 3.0, 4.0]], np.float32)
+    dl = np.array([[1.0, 1.0, 1.0, 0.0]], np.float32)
+    # an opaque third sample takes all the weight
+    D, U, A = orc.depth_stats(t, dl, np.array([[0, 0, 1e4, 0]], np.float32))
+    assert abs(D[0] - 3.0) < 1e-12 and U[0] < 1e-6 and abs(A[0] - 1.0) < 1e-12
+    # tau_0 = ln 2 gives w_0 = 1/2; an opaque second sample takes the other half
+    D, U, A = orc.depth_stats(t, dl, np.array([[math.log(2.0), 1e4, 0, 0]], np.float32))
+    assert abs(A[0] - 1.0) < 1e-7 and abs(D[0] - 1.5) < 1e-7 and abs(U[0] - 0.5) < 1e-7
+    # half opacity: normalised weights put the depth at the sample itself
+    D, U, A = orc.depth_stats(t[:, :1], dl[:, :1], np.array([[math.log(2.0)]], np.float32))
+    assert abs(A[0] - 0.5) < 1e-7 and abs(D[0] - 1.0) < 1e-12 and U[0] == 0.0
+    # nothing visible: zero depth and spread
+    D, U, A = orc.depth_stats(t, dl, np.zeros((1, 4), np.float32))
+    assert D[0] == 0 and U[0] == 0 and A[0] == 0
+    # constant density on evenly spaced samples: the weights are geometric,
+    # P(i) = (1 - q) q^i with q = exp(-tau), so D = t_0 + dt q / (1 - q) and
+    # U = dt sqrt(q) / (1 - q) (the mean and spread of that distribution)
+    n, t0, dt, tau = 400, 0.5, 0.125, 0.25
+    tt = (t0 + dt * np.arange(n)).astype(np.float32)[None]
+    D, U, A = orc.depth_stats(tt, np.full((1, n), dt, np.float32), np.full((1, n), tau / dt, np.float32))
+    q = math.exp(-tau)
+    assert abs(A[0] - 1.0) < 1e-12
+    assert abs(D[0] - (t0 + dt * q / (1 - q))) < 1e-9
+    assert abs(U[0] - dt * math.sqrt(q) / (1 - q)) < 1e-9
+
+
+def test_occupancy_axis_ray_band_and_confidence(orc):
+    desc = orc.occ_desc(8, -4.0, 1.0)
+    lh, lm = np.float32(orc.logit(0.7)), np.float32(orc.logit(0.4))
+    o = np.array([[-3.9], [0.5], [0.5]], np.float32)
+    d = np.array([[1.0], [0.0], [0.0]], np.float32)
+    one = lambda v: np.array([v], np.float32)
+
+    def row(D, U, A=1.0, oo=o, dd=d):
+        L = np.zeros((8, 8, 8), np.float32)
+        orc.occupancy_update(desc, L, oo, dd, one(D), one(U), one(A))
+        return L
+
+    # sharp depth at x = 0.5 (voxel 4): voxels 0..3 free, 4 hit, the rest untouched
+    L = row(4.4, 0.0)
+    assert np.array_equal(L[4, 4], np.array([lm] * 4 + [lh, 0, 0, 0], np.float32))
+    assert np.count_nonzero(L) == 5
+    # uncertainty 1.6 (1.6 voxels): free only up to D - U = 2.8 (voxels 0, 1);
+    # 2 and 3 lie in the band; the hit logit is l_hit / (1 + 1.6)
+    L = row(4.4, 1.6)
+    h = np.float32(lh / (np.float32(1.0) + np.float32(1.6)))
+    assert np.array_equal(L[4, 4], np.array([lm, lm, 0, 0, h, 0, 0, 0], np.float32))
+    # below the opacity floor: no measurement
+    assert np.count_nonzero(row(4.4, 0.0, A=0.4)) == 0
+    # a surface beyond the box: every crossed voxel is free, none is hit
+    L = row(20.0, 0.0)
+    assert np.array_equal(L[4, 4], np.full(8, lm, np.float32)) and np.count_nonzero(L) == 8
+    # a depth before the start of the walk: nothing
+    o2 = np.array([[-1.5], [0.5], [0.5]], np.float32)
+    assert np.count_nonzero(row(-1.0, 0.0, oo=o2)) == 0
+    # a ray along -z from inside: the same rule in the other direction
+    o3 = np.array([[0.5], [0.5], [3.5]], np.float32)
+    d3 = np.array([[0.0], [0.0], [-1.0]], np.float32)
+    L = row(5.2, 0.0, oo=o3, dd=d3)          # z = -1.7: voxel 2
+    assert np.array_equal(L[:, 4, 4], np.array([0, 0, lh] + [lm] * 5, np.float32))
+
+
+def test_occupancy_one_measurement_per_voxel_per_pose(orc):
+    desc = orc.occ_desc(8, -4.0, 1.0)
+    lh, lm = np.float32(orc.logit(0.7)), np.float32(orc.logit(0.4))
+    o = np.array([[-3.9, -3.9, -3.9], [0.5, 0.5, 0.5], [0.5, 0.5, 0.5]], np.float32)
+    d = np.array([[1.0] * 3, [0.0] * 3, [0.0] * 3], np.float32)
+    # ray 0 ends in voxel 4 sharply, ray 1 ends there with U = 1 voxel, ray 2
+    # passes through voxel 4 freely and ends in voxel 6
+    D = np.array([4.4, 4.4, 6.4], np.float32)
+    U = np.array([0.0, 1.0, 0.0], np.float32)
+    A = np.ones(3, np.float32)
+    for perm in ([0, 1, 2], [2, 1, 0], [1, 2, 0]):
+        L = np.zeros((8, 8, 8), np.float32)
+        orc.occupancy_update(desc, L, o[:, perm], d[:, perm], D[perm], U[perm], A[perm])
+        # voxel 4: the strongest hit, never the miss; voxel 5 free; voxel 6 hit
+        assert np.array_equal(L[4, 4], np.array([lm] * 4 + [lh, lm, lh, 0], np.float32)), perm
+
+
+def _all_segments(n, lo, vs, o, d):
+    """Entry and exit distance of the ray through every voxel, FP64 slab test."""
+    sc = type("G", (), {})()
+    sc.n, sc.lo, sc.voxel = n, lo, vs
+    sc.occupied = np.ones((n, n, n), bool)
+    sc.field_map = np.zeros((n, n, n), np.int32)
+    _, _, _, tin, tout = brute_segments(sc, o, d)
+    return tin, tout
+
+
+def test_occupancy_matches_brute_force(orc):
+    n, lo, vs = 6, -1.5, 0.5
+    desc = orc.occ_desc(n, lo, vs)
+    lh, lm = orc.logit(0.7), orc.logit(0.4)
+    rng = np.random.default_rng(11)
+    checked = 0
+    for r in range(300):
+        o = rng.uniform(-1.4, 1.4, size=3).astype(np.float32)
+        dv = rng.normal(size=3); dv /= np.linalg.norm(dv)
+        dv = dv.astype(np.float32)
+        D = np.float32(rng.uniform(0.2, 3.0)); U = np.float32(rng.uniform(0.0, 0.6))
+        tin, tout = _all_segments(n, lo, vs, o, dv)
+        tin = np.maximum(tin, 0.0)
+        e = float(np.float32(D - U))
+        pos = tout > tin
+        margins = np.concatenate([np.abs(tout[pos] - e), np.abs(tin[pos] - D), np.abs(tout[pos] - D),
+                                  (tout - tin)[pos]])
+        if np.min(margins) < 1e-4:
+            continue
+        L = np.zeros((n, n, n), np.float32)
+        orc.occupancy_update(desc, L, o[:, None], dv[:, None], np.array([D]), np.array([U]), np.array([1.0]))
+        want = np.zeros((n, n, n))
+        hit = pos & (tin <= D) & (D < tout)
+        free = pos & (tout <= e)
+        want[free] = lm
+        want[hit] = lh / (1.0 + float(U) / vs)
+        assert hit.sum() <= 1
+        assert np.allclose(L, want, rtol=0, atol=1e-6), r
+        checked += 1
+    assert checked > 200
+
+
+def test_occupancy_invariants_over_poses(orc):
+    n = 16
+    desc = orc.occ_desc(n, -4.0, 0.5)
+    rng = np.random.default_rng(5)
+    L = np.zeros((n, n, n), np.float32)
+    walked = np.zeros((n, n, n), bool)
+    for pose in range(8):
+        N = 1500
+        c = rng.uniform(-3, 3, size=3)
+        o = np.repeat(c[:, None], N, axis=1).astype(np.float32)
+        dv = rng.normal(size=(3, N)); dv /= np.linalg.norm(dv, axis=0)
+        dv = dv.astype(np.float32)
+        D = rng.uniform(0.5, 6.0, N).astype(np.float32)
+        U = rng.uniform(0.0, 1.0, N).astype(np.float32)
+        A = rng.uniform(0.0, 1.0, N).astype(np.float32)
+        before = L.copy()
+        p = orc.occupancy_update(desc, L, o, dv, D, U, A)
+        assert L.min() >= -2.0 and L.max() <= 3.5
+        walked |= L != before
+        # probability is the logistic of the logit
+        assert np.allclose(np.log(p / (1 - p)), L, rtol=0, atol=2e-6)
+    # voxels no ray reached keep their initial value
+    assert np.all(L[~walked] == 0)
+    assert 0 < walked.sum() < n ** 3
+
+
+def test_global_measure_opaque_first_sample(orc):
+    lay = synth.global_mlp_layout(16, color_width=8)
+    w = np.zeros(synth.n_params(lay), np.float32)
+    t = synth.unpack(lay, w)
+    o = np.zeros((3, 4), np.float32)
+    d = np.array([[1, 0, 0, 0.6], [0, 1, 0, 0.8], [0, 0, 1, 0]], np.float32)
+    # a huge constant density puts all the weight on the first sample (t = near)
+    t["bs"][0] = 1e5
+    D, U, A = orc.global_measure(w, o, d, n_samples=16, width=16, color_width=8)
+    assert np.allclose(D, 0.1, atol=1e-7) and np.all(U < 1e-6) and np.allclose(A, 1.0)
+    # zero density: no measurement
+    t["bs"][0] = 0.0
+    D, U, A = orc.global_measure(w, o, d, n_samples=16, width=16, color_width=8)
+    assert np.all(A == 0) and np.all(D == 0) and np.all(U == 0)
+    # a constant density c along the ray: against the compositing of the step
+    t["bs"][0] = 0.3
+    ts, dl = orc.invdepth_t(16, 0.1, 20.0)
+    D, U, A = orc.global_measure(w, o, d, n_samples=16, width=16, color_width=8)
+    tau = 0.3 * dl.astype(np.float64)
+    S = np.concatenate([[0.0], np.cumsum(tau)[:-1]])
+    wts = np.exp(-S) * (1 - np.exp(-tau))
+    assert np.allclose(A, 1 - np.exp(-tau.sum()), rtol=1e-12)
+    assert np.allclose(D, (wts * ts).sum() / wts.sum(), rtol=1e-12)
