@@ -255,13 +255,69 @@ r360_status r360_global_field_step(const r360_global_desc* desc, const float* we
                                    float* rgb_out, float* depth_out, float* occ_grid, void* ws, size_t ws_bytes,
                                    void* stream);
 
+/* Stage I of Alg.1 (Sec. 4.1): progressive probabilistic occupancy.
+ *
+ * Measurement of one ray from its samples' Eq.5 weights w_i: opacity A =
+ * sum w_i, depth D = sum w_i t_i / A (the Eq.4 depth over normalised
+ * weights), uncertainty U = sqrt(sum w_i (t_i - D)^2 / A); A = 0 gives D =
+ * U = 0.
+ *
+ * Update for one sampling position (the logit form of Eq.6, one measurement
+ * per voxel per call): each ray with A >= min_opacity and finite D, U >= 0
+ * walks its voxels with the sampler's FP32 traversal over [max(near, box
+ * entry), min(far, box exit)]. A voxel segment of positive length ending at
+ * or before D - U is a free pass; the voxel whose segment [t_in, t_out)
+ * holds D is the hit, with logit l_hit / (1 + U / voxel), and ends the walk.
+ * Per voxel: l += the largest hit logit of the rays ending in it, else
+ * l_miss if a ray passed freely, then clamp to [l_min, l_max] (Sec. 4.1:
+ * -2 and 3.5); voxels without a measurement keep their value. Deterministic
+ * (independent of ray order). */
+typedef struct {
+    int32_t n[3];           /* voxels per axis, each in [1, 4096], < 2^31 in total */
+    float lo[3];            /* grid lower corner */
+    float voxel;            /* voxel edge, a power of two */
+    float near_, far_;      /* ray clip, 0 <= near < far (far may be +inf) */
+    float l_hit;            /* > 0: logit of a sharp hit (logit(0.7) by default) */
+    float l_miss;           /* < 0: logit of a free pass (logit(0.4) by default) */
+    float l_min, l_max;     /* clamp, l_min < l_max (-2 and 3.5 in the paper) */
+    float min_opacity;      /* rays below this opacity measure nothing */
+} r360_occ_desc;
+
+/* Per-ray depth, uncertainty and opacity ([N] each, device, written) from
+ * dense samples t, delta, sigma ([N][S] ray-major, device, read). N >= 1,
+ * N <= 2^31, S >= 1. */
+r360_status r360_depth_uncertainty(const float* t, const float* delta, const float* sigma, int64_t N, int32_t S,
+                                   float* depth, float* uncert, float* opacity, void* stream);
+
+/* Device workspace (bytes, 256-byte aligned base) of one update: 5 bytes per
+ * voxel, rounded up; 0 for an invalid description. */
+size_t r360_occupancy_workspace_bytes(const r360_occ_desc* desc);
+
+/* One pose's update of the FP32 logit grid logit [n2][n1][n0] (device, read
+ * and written in place) from N rays o, d [3][N] and their measurement depth,
+ * uncert, opacity [N] (device). prob [n2][n1][n0] (device, may be NULL)
+ * receives 1 / (1 + exp(-l)) for every voxel, ready for r360_scene_create
+ * with threshold 0.97. Caller-owned memory throughout; the workspace holds
+ * the per-voxel marks and is overwritten. */
+r360_status r360_occupancy_update(const r360_occ_desc* desc, float* logit, float* prob, const float* o,
+                                  const float* d, int64_t N, const float* depth, const float* uncert,
+                                  const float* opacity, void* ws, size_t ws_bytes, void* stream);
+
+/* The global field's Stage I measurement: its forward over N rays (as
+ * r360_global_field_step without a target) followed by the per-ray depth,
+ * uncertainty and opacity above ([N] each, device). Workspace as
+ * r360_global_workspace_bytes. */
+r360_status r360_global_field_measure(const r360_global_desc* desc, const float* weights, const float* o,
+                                      const float* d, int64_t N, float* depth, float* uncert, float* opacity,
+                                      void* ws, size_t ws_bytes, void* stream);
+
 /* Optional per-stage timing for benchmarking: when enabled, every entry
  * point records a HIP event pair around each stage of its launch sequence on
  * the call's own stream. Stages: 0 sampling (traversal + scan + compaction), 1 routing,
  * 2 field-MLP forward, 3 compositing, 4 loss, 5 compositing backward,
  * 6 field-MLP backward (with the per-field gradient reduction), 7 the whole
- * global-field step. */
-#define R360_NSTAGES 8
+ * global-field step, 8 the occupancy update (and depth statistics). */
+#define R360_NSTAGES 9
 r360_status r360_profile_enable(int32_t on);
 /* Waits for the recorded events and returns, per stage, the milliseconds and
  * the number of timed launches since the previous read (arrays of

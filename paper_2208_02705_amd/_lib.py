@@ -15,9 +15,9 @@ LIB_PATH = os.path.join(HERE, "libr360.so")
 R360_OK, R360_EINVAL, R360_ENOMEM, R360_EHIP, R360_EUNSUPPORTED, R360_EWORKSPACE = 0, -1, -2, -3, -4, -5
 FP32, BF16, FP16, FP64_GRADCHECK = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp16": FP16, "fp64": FP64_GRADCHECK}
-NSTAGES = 8
+NSTAGES = 9
 STAGES = ["sample", "route", "mlp_forward", "composite", "loss", "composite_backward", "mlp_backward",
-          "global_field"]
+          "global_field", "occupancy"]
 
 
 class GridDesc(C.Structure):
@@ -37,6 +37,12 @@ class GlobalDesc(C.Structure):
     _fields_ = [("width", C.c_int32), ("color_width", C.c_int32), ("n_samples", C.c_int32), ("near_", C.c_float),
                 ("far_", C.c_float), ("center", C.c_float * 3), ("half_extent", C.c_float),
                 ("grid_n", C.c_int32 * 3), ("grid_lo", C.c_float * 3), ("voxel", C.c_float)]
+
+
+class OccDesc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_float * 3), ("voxel", C.c_float), ("near_", C.c_float),
+                ("far_", C.c_float), ("l_hit", C.c_float), ("l_miss", C.c_float), ("l_min", C.c_float),
+                ("l_max", C.c_float), ("min_opacity", C.c_float)]
 
 
 class R360Error(RuntimeError):
@@ -71,6 +77,10 @@ SIGNATURES = {
     "r360_global_params": (i64, [i32, i32]),
     "r360_global_workspace_bytes": (sz, [C.POINTER(GlobalDesc), i64]),
     "r360_global_field_step": (i32, [C.POINTER(GlobalDesc), vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+    "r360_depth_uncertainty": (i32, [vp, vp, vp, i64, i32, vp, vp, vp, vp]),
+    "r360_occupancy_workspace_bytes": (sz, [C.POINTER(OccDesc)]),
+    "r360_occupancy_update": (i32, [C.POINTER(OccDesc), vp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
+    "r360_global_field_measure": (i32, [C.POINTER(GlobalDesc), vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
     "r360_profile_enable": (i32, [i32]),
     "r360_profile_read": (i32, [vp, vp]),
     "r360_status_string": (C.c_char_p, [i32]),

@@ -2,8 +2,8 @@
 
 Each translation unit under csrc/ is compiled separately (in parallel) and
 linked into paper_2208_02705_amd/libr360.so. The sampling units (local
-traversal, global inverse-depth samples) are compiled without floating-point
-contraction: their FP32 formulas are specified operation by operation and
+traversal, global inverse-depth samples) and the occupancy update (its voxel
+walk) are compiled without floating-point contraction: their FP32 formulas are specified operation by operation and
 must not be fused.
 """
 from __future__ import annotations
@@ -20,8 +20,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libr360.so")
 ARCH = os.environ.get("R360_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["abi.hip", "sample.hip", "route.hip", "mlp.hip", "composite.hip", "backward.hip", "global.hip"]
-NO_CONTRACT = {"sample.hip", "global.hip"}
+SOURCES = ["abi.hip", "sample.hip", "route.hip", "mlp.hip", "composite.hip", "backward.hip", "global.hip",
+           "occupancy.hip"]
+NO_CONTRACT = {"sample.hip", "global.hip", "occupancy.hip"}
 
 COMMON = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

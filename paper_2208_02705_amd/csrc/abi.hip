@@ -590,6 +590,76 @@ r360_status r360_global_field_step(const r360_global_desc* g, const float* weigh
     return R360_OK;
 }
 
+static r360_status check_occ(const r360_occ_desc* g) {
+    if (!g) return inval("desc is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (g->n[a] < 1 || g->n[a] > 4096) return inval("grid size outside [1, 4096]");
+    if ((int64_t)g->n[0] * g->n[1] * g->n[2] >= (int64_t(1) << 31)) return inval("grid has 2^31 voxels or more");
+    if (!pow2(g->voxel)) return inval("voxel edge must be a positive power of two");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(g->lo[a])) return inval("grid corner must be finite");
+    if (!(g->near_ >= 0.0f) || !std::isfinite(g->near_) || !(g->far_ > g->near_)) return inval("need 0 <= near < far");
+    if (!(g->l_hit > 0.0f) || !std::isfinite(g->l_hit)) return inval("l_hit must be positive and finite");
+    if (!(g->l_miss < 0.0f) || !std::isfinite(g->l_miss)) return inval("l_miss must be negative and finite");
+    if (!(g->l_min < g->l_max) || !std::isfinite(g->l_min) || !std::isfinite(g->l_max)) return inval("need l_min < l_max, finite");
+    if (!(g->min_opacity >= 0.0f) || !(g->min_opacity <= 1.0f)) return inval("min_opacity outside [0, 1]");
+    return R360_OK;
+}
+
+r360_status r360_depth_uncertainty(const float* t, const float* delta, const float* sigma, int64_t N,
+                                   int32_t per_ray, float* depth, float* uncert, float* opacity, void* stream) {
+    if (!t || !delta || !sigma || !depth || !uncert || !opacity) return inval("NULL pointer");
+    if (N < 1 || N > (int64_t(1) << 31) || per_ray < 1) return inval("need 1 <= N <= 2^31 and S >= 1");
+    R360_STAGE(8, S(stream));
+    R360_TRY("depth statistics",
+             launch_depth_stats(t, delta, sigma, N, per_ray, depth, uncert, opacity, S(stream)));
+    return R360_OK;
+}
+
+size_t r360_occupancy_workspace_bytes(const r360_occ_desc* g) {
+    if (check_occ(g) != R360_OK) return 0;
+    return occupancy_workspace_bytes((int64_t)g->n[0] * g->n[1] * g->n[2]);
+}
+
+r360_status r360_occupancy_update(const r360_occ_desc* g, float* logit, float* prob, const float* o, const float* d,
+                                  int64_t N, const float* depth, const float* uncert, const float* opacity, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    r360_status st = check_occ(g);
+    if (st != R360_OK) return st;
+    if (!logit || !o || !d || !depth || !uncert || !opacity || !ws) return inval("NULL pointer");
+    if (N < 1 || N > (int64_t(1) << 31)) return inval("N outside [1, 2^31]");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    const size_t need = occupancy_workspace_bytes((int64_t)g->n[0] * g->n[1] * g->n[2]);
+    if (ws_bytes < need) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return R360_EWORKSPACE;
+    }
+    R360_STAGE(8, S(stream));
+    R360_TRY("occupancy update",
+             launch_occupancy_update(g, logit, prob, o, d, N, depth, uncert, opacity, ws, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_global_field_measure(const r360_global_desc* g, const float* weights, const float* o, const float* d,
+                                      int64_t N, float* depth, float* uncert, float* opacity, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    r360_status st = check_global(g);
+    if (st != R360_OK) return st;
+    if (!weights || !o || !d || !depth || !uncert || !opacity || !ws) return inval("NULL pointer");
+    if (N <= 0 || N * (int64_t)g->n_samples >= (int64_t(1) << 31)) return inval("N * n_samples outside [1, 2^31)");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    const size_t need = global_workspace_bytes(g->width, g->color_width, N, g->n_samples);
+    if (ws_bytes < need) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return R360_EWORKSPACE;
+    }
+    const GlobalMeasure meas{depth, uncert, opacity};
+    R360_STAGE(7, S(stream));
+    R360_TRY("global field measure", launch_global_step(g, weights, o, d, N, nullptr, nullptr, nullptr, nullptr,
+                                                        nullptr, nullptr, ws, S(stream), 1, &meas));
+    return R360_OK;
+}
+
 r360_status r360_profile_enable(int32_t on) {
     g_prof = on != 0;
     return R360_OK;

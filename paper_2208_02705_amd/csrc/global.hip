@@ -669,7 +669,8 @@ static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
 
 hipError_t launch_global_step(const r360_global_desc* desc, const float* weights, const float* o, const float* d,
                               int64_t Nr, const float* target, float* loss, float* grad, float* rgb_out,
-                              float* depth_out, float* occ, void* ws, hipStream_t st, int stage_mask) {
+                              float* depth_out, float* occ, void* ws, hipStream_t st, int stage_mask,
+                              const GlobalMeasure* meas) {
     const GNet n = make_net(desc->width, desc->color_width);
     const GNetDev nd = dev_net(n);
     const int S = desc->n_samples, w = n.w, c = n.c;
@@ -740,6 +741,9 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     lw.dsigma = g.dsig; lw.drgb = g.drgb; lw.loss_part = g.loss_part; lw.N = Nr; lw.cap = M;
     float* ray_rgb = rgb_out ? rgb_out : g.ray_rgb;
     if ((e = launch_composite(lw, Nr, ray_rgb, depth_out, nullptr, st)) != hipSuccess) return e;
+    if (meas && (e = launch_depth_stats(g.t, g.delta, g.sig, Nr, S, meas->depth, meas->uncert, meas->opacity, st)) !=
+                    hipSuccess)
+        return e;
     if (!(stage_mask & 2)) return hipSuccess;      // forward only
     if ((e = launch_loss_grad(lw, Nr, ray_rgb, target, loss, g.ray_grad, st)) != hipSuccess) return e;
     if ((e = launch_composite_backward(lw, Nr, g.ray_grad, st)) != hipSuccess) return e;

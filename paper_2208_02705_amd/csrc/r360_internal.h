@@ -478,11 +478,25 @@ hipError_t launch_mlp_backward(const r360_scene* s, const Workspace& w, int prec
                                hipStream_t st);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, int64_t step, float lr,
                        float b1, float b2, float eps, hipStream_t st);
+// Optional per-ray Stage I measurement of the global forward (depth over
+// normalised weights, uncertainty, opacity).
+struct GlobalMeasure {
+    float *depth, *uncert, *opacity;
+};
 hipError_t launch_global_step(const r360_global_desc* desc, const float* weights, const float* o, const float* d,
                               int64_t Nr, const float* target, float* loss, float* grad, float* rgb_out,
-                              float* depth_out, float* occ, void* ws, hipStream_t st, int stage_mask);
+                              float* depth_out, float* occ, void* ws, hipStream_t st, int stage_mask,
+                              const GlobalMeasure* meas = nullptr);
 size_t global_workspace_bytes(int w, int c, int64_t Nr, int S);
 int64_t global_params(int w, int c);
+// Stage I occupancy: per-ray depth statistics over dense [N][S] samples, and
+// one pose's logit-grid update (workspace: occupancy_workspace_bytes).
+hipError_t launch_depth_stats(const float* t, const float* delta, const float* sigma, int64_t N, int S,
+                              float* depth, float* uncert, float* opacity, hipStream_t st);
+size_t occupancy_workspace_bytes(int64_t nvox);
+hipError_t launch_occupancy_update(const r360_occ_desc* g, float* logit, float* prob, const float* o, const float* d,
+                                   int64_t N, const float* depth, const float* uncert, const float* opacity,
+                                   void* ws, hipStream_t st);
 hipError_t launch_gradcheck_forward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,
                                     double* rgb64, hipStream_t st);
 hipError_t launch_gradcheck_backward(const r360_scene* s, const Workspace& w, const double* w64, int64_t N,

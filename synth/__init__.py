@@ -415,3 +415,16 @@ def random_unit_dirs(n: int, seed: int, stream: int = STREAM_RAYS) -> np.ndarray
     g = normal(seed, stream, np.arange(3 * n, dtype=np.uint64)).reshape(n, 3)
     g /= np.linalg.norm(g, axis=1, keepdims=True)
     return np.ascontiguousarray(g.T.astype(np.float32))
+
+
+def occupancy_measurements(n: int, seed: int, d_lo: float = 0.2, d_hi: float = 8.0, u_max: float = 0.5,
+                           p_valid: float = 0.8):
+    """Synthetic per-ray (depth, uncertainty, opacity) for the Stage I update
+    (input draws only): depth U[d_lo, d_hi), uncertainty U[0, u_max), and an
+    opacity of 1 for a fraction p_valid of the rays, else U[0, 1/2)."""
+    idx = np.arange(4 * n, dtype=np.uint64)
+    u = uniform(seed, STREAM_NOISE, idx).reshape(4, n)
+    depth = (d_lo + (d_hi - d_lo) * u[0]).astype(np.float32)
+    uncert = (u_max * u[1]).astype(np.float32)
+    opacity = np.where(u[2] < p_valid, 1.0, 0.5 * u[3]).astype(np.float32)
+    return depth, uncert, opacity

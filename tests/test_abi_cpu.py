@@ -84,3 +84,25 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_occupancy_arguments_rejected(L):
+    from paper_2208_02705_amd import _lib
+    assert L.r360_occupancy_workspace_bytes(None) == 0
+    g = _lib.OccDesc()
+    g.n[:] = [8, 8, 8]; g.lo[:] = [-4.0] * 3; g.voxel = 1.0
+    g.near_, g.far_ = 0.0, float("inf")
+    g.l_hit, g.l_miss, g.l_min, g.l_max, g.min_opacity = 0.85, -0.4, -2.0, 3.5, 0.5
+    assert L.r360_occupancy_workspace_bytes(C.byref(g)) == 2048 + 512
+    for field, bad in (("voxel", 0.3), ("l_hit", -1.0), ("l_miss", 0.2), ("min_opacity", 2.0), ("far_", 0.0)):
+        h = _lib.OccDesc.from_buffer_copy(g)
+        setattr(h, field, bad)
+        assert L.r360_occupancy_workspace_bytes(C.byref(h)) == 0, field
+        assert L.r360_occupancy_update(C.byref(h), None, None, None, None, 1, None, None, None, None, 0,
+                                       None) == _lib.R360_EINVAL
+    assert L.r360_occupancy_update(C.byref(g), None, None, None, None, 1, None, None, None, None, 0,
+                                   None) == _lib.R360_EINVAL
+    assert L.r360_depth_uncertainty(None, None, None, 4, 4, None, None, None, None) == _lib.R360_EINVAL
+    gd = _lib.GlobalDesc()
+    assert L.r360_global_field_measure(C.byref(gd), None, None, None, 4, None, None, None, None, 0,
+                                       None) == _lib.R360_EUNSUPPORTED
