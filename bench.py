@@ -69,7 +69,8 @@ def parse():
     p.add_argument("--no-train", action="store_true")
     p.add_argument("--no-large", action="store_true")
     p.add_argument("--no-global", action="store_true")
-    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global"], default=None,
+    p.add_argument("--no-occupancy", action="store_true")
+    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy"], default=None,
                    help="time only one leg (for profiler runs)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB mebibytes (to calibrate HBM byte counters)")
@@ -134,7 +135,7 @@ def main():
         del r
         return sec, prof
 
-    legs = ["bf16", "fp32", "train", "large", "global"] if args.only is None else [args.only]
+    legs = ["bf16", "fp32", "train", "large", "global", "occupancy"] if args.only is None else [args.only]
     res = {}
     if "bf16" in legs:
         res["bf16"] = leg("bf16", args.steps, args.warmup)
@@ -153,6 +154,9 @@ def main():
     glob = None
     if "global" in legs and not args.no_global:
         glob = global_leg(R, args)
+    occl = None
+    if "occupancy" in legs and not args.no_occupancy:
+        occl = occupancy_leg(R, scene, args)
 
     main_prec = "bf16" if "bf16" in res else next(iter(res), None)
     line = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -200,6 +204,8 @@ def main():
         line["large_uneven"] = large
     if glob is not None:
         line["global_field"] = glob
+    if occl is not None:
+        line["occupancy_update"] = occl
     line["context"] = ("paper: 360Roam renders a 1520x760 panorama in 0.03 s on one RTX2080 Ti (about 38.5 Mrays/s, "
                        "precision not stated) and runs in real time on a GTX1080; different hardware and scenes")
     if not args.no_cpu_baseline and args.only is None:
@@ -339,6 +345,43 @@ def global_leg(R, args):
             "msamples_per_s": S / sec / 1e6, "tflops": tf, "frac_bf16_peak": tf / PEAK["bf16"],
             "flop_per_sample": FLOP_PER_SAMPLE_GLOBAL,
             "stages_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
+
+
+def occupancy_leg(R, scene, args):
+    """Stage I update for one sampling position: the 2048 x 1024 panorama
+    from the room scene's centre into the 128^3 logit grid. Each ray that
+    meets the scene measures a surface at the BF16 render's depth over its
+    opacity (the normalised depth), with a spread of half a voxel and full
+    opacity, as a trained global field would give; the timed call clears the
+    marks, walks every ray and applies the clamped logit sums with the
+    probability grid."""
+    import torch
+    import synth
+    r = R.EquirectRenderer(scene, W, H, precision="bf16")
+    _, depth, opac = r(synth.IDENTITY_C2W)
+    hit = opac > 0
+    depth = torch.where(hit, depth / opac.clamp_min(1e-12), torch.zeros_like(depth)).reshape(-1).contiguous()
+    opac = hit.to(torch.float32).reshape(-1).contiguous()
+    uncert = torch.full_like(depth, 0.5 * 0.0625)
+    eq = R.Equirect(W, H)
+    o, d = eq.rays(synth.IDENTITY_C2W)
+    del r
+    om = R.OccupancyMap(128, -4.0, 0.0625)
+
+    def pose():
+        om.update(o, d, depth, uncert, opac)
+    R.profile_read()
+    R.profile_enable(True)
+    steps = max(10, args.steps // 2)
+    sec = timed(pose, steps, 3)
+    prof = R.profile_read()
+    R.profile_enable(False)
+    nvox = 128 ** 3
+    ms = prof["occupancy"][0] / max(prof["occupancy"][1], 1)
+    return {"rays": W * H, "grid": [128, 128, 128], "ms_per_pose": sec * 1e3, "mrays_per_s": W * H / sec / 1e6,
+            "library_ms_per_pose": ms, "measuring_rays": int((opac >= 0.5).sum().item()),
+            "occupied_after": int(om.occupied().sum().item()),
+            "voxel_pass_bytes": 5 * nvox + 17 * nvox}
 
 
 def cpu_baseline(sc):
