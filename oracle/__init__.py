@@ -103,6 +103,8 @@ def lib():
             "orc_depth_stats": (None, [i64, C.c_int, vp, vp, vp, vp, vp, vp]),
             "orc_occupancy_update": (None, [vp, vp, vp, i64, vp, vp, vp, vp, vp, C.c_int]),
             "orc_global_measure": (None, [vp, i64, vp, vp, vp, vp, vp, C.c_int]),
+            "orc_assign_fields": (i64, [vp, vp, f32, i32, vp]),
+            "orc_assign_uniform": (i32, [vp, vp, f32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -397,3 +399,23 @@ def global_measure(weights, o, d, n_samples=128, near=0.1, far=20.0, width=256, 
     D = np.empty(N); U = np.empty(N); A = np.empty(N)
     lib().orc_global_measure(C.byref(g), N, _p(o), _p(d), _p(D), _p(U), _p(A), threads or default_threads())
     return D, U, A
+
+
+# ---- Stage II field assignment (Sec. 4.2, Alg.1) ----------------------------
+def assign_fields(occ: np.ndarray, threshold: float, n_fields: int):
+    """(field_map int32 [n2, n1, n0], S) by Alg.1 Stage II."""
+    occ = _c(occ, np.float32)
+    n = (C.c_int32 * 3)(occ.shape[2], occ.shape[1], occ.shape[0])
+    fmap = np.empty(occ.shape, np.int32)
+    S = lib().orc_assign_fields(n, _p(occ), threshold, n_fields, _p(fmap))
+    return fmap, int(S)
+
+
+def assign_uniform(occ: np.ndarray, threshold: float, blocks):
+    """(field_map, n_fields) for the uniform decomposition into blocks (b0, b1, b2)."""
+    occ = _c(occ, np.float32)
+    n = (C.c_int32 * 3)(occ.shape[2], occ.shape[1], occ.shape[0])
+    b = (C.c_int32 * 3)(*blocks)
+    fmap = np.empty(occ.shape, np.int32)
+    nf = lib().orc_assign_uniform(n, _p(occ), threshold, b, _p(fmap))
+    return fmap, int(nf)

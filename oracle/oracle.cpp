@@ -937,6 +937,79 @@ void orc_global_measure(const OrcGlobal* g, int64_t N, const float* o, const flo
     });
 }
 
+// ---- Stage II of Alg.1 (Sec. 4.2): adaptive field assignment ---------------
+// S voxels are occupied (occ > thr); field k (0-based, k < n) receives
+// s_k = floor(S / n) + (k < S mod n ? 1 : 0) of them, so sizes differ by at
+// most one. For k = 0, 1, ...: the anchor is the unassigned occupied voxel of
+// smallest linear index (the minimum coordinate, z then y then x); the field
+// takes the s_k unassigned occupied voxels nearest to the anchor by squared
+// Euclidean distance between voxel indices, ties to the smaller linear index
+// (the anchor itself, at distance 0, first). Unoccupied voxels get -1.
+// Returns S.
+int64_t orc_assign_fields(const int32_t* n, const float* occ, float thr, int32_t n_fields, int32_t* field_map) {
+    const int64_t nvox = (int64_t)n[0] * n[1] * n[2];
+    std::vector<int64_t> occl;
+    for (int64_t v = 0; v < nvox; ++v) {
+        field_map[v] = -1;
+        if (occ[v] > thr) occl.push_back(v);
+    }
+    const int64_t S = (int64_t)occl.size();
+    if (n_fields < 1) return S;
+    const int64_t base = S / n_fields, rem = S % n_fields;
+    std::vector<char> done(S, 0);
+    struct Cand { int64_t d2, lin, i; };
+    std::vector<Cand> cand;
+    for (int32_t k = 0; k < n_fields; ++k) {
+        const int64_t sk = ORC_PLANT == 20 ? (k + 1 < n_fields ? base : S - base * (n_fields - 1))
+                                           : base + (k < rem ? 1 : 0);
+        if (sk == 0) continue;
+        int64_t a = -1;
+        for (int64_t i = 0; i < S; ++i)
+            if (!done[i] && (a < 0 || ORC_PLANT == 18)) a = i;   // smallest index (plant: largest)
+        const int64_t al = occl[a];
+        const int64_t ax = al % n[0], ay = (al / n[0]) % n[1], az = al / ((int64_t)n[0] * n[1]);
+        cand.clear();
+        for (int64_t i = 0; i < S; ++i) {
+            if (done[i]) continue;
+            const int64_t l = occl[i];
+            const int64_t dx = l % n[0] - ax, dy = (l / n[0]) % n[1] - ay, dz = l / ((int64_t)n[0] * n[1]) - az;
+            const int64_t d2 = ORC_PLANT == 19 ? std::llabs(dx) + std::llabs(dy) + std::llabs(dz)
+                                               : dx * dx + dy * dy + dz * dz;
+            cand.push_back({d2, l, i});
+        }
+        const int64_t take = std::min<int64_t>(sk, (int64_t)cand.size());
+        std::partial_sort(cand.begin(), cand.begin() + take, cand.end(), [](const Cand& x, const Cand& y) {
+            return x.d2 != y.d2 ? x.d2 < y.d2 : x.lin < y.lin;
+        });
+        for (int64_t j = 0; j < take; ++j) {
+            field_map[cand[j].lin] = k;
+            done[cand[j].i] = 1;
+        }
+    }
+    return S;
+}
+
+// The uniform decomposition (the 360Roam-u variant of Sec. 6): b[a] blocks
+// per axis, voxel index i in block floor(i * b[a] / n[a]); the fields are the
+// blocks that hold an occupied voxel, numbered in linear block order (x
+// fastest). Returns the number of fields.
+int32_t orc_assign_uniform(const int32_t* n, const float* occ, float thr, const int32_t* b, int32_t* field_map) {
+    const int64_t nvox = (int64_t)n[0] * n[1] * n[2];
+    const int64_t nb = (int64_t)b[0] * b[1] * b[2];
+    std::vector<int64_t> blk(nvox);
+    std::vector<int32_t> id(nb, -1);
+    for (int64_t v = 0; v < nvox; ++v) {
+        const int64_t x = v % n[0], y = (v / n[0]) % n[1], z = v / ((int64_t)n[0] * n[1]);
+        blk[v] = x * b[0] / n[0] + b[0] * (y * b[1] / n[1] + b[1] * (z * b[2] / n[2]));
+        if (occ[v] > thr) id[blk[v]] = 0;
+    }
+    int32_t count = 0;
+    for (int64_t q = 0; q < nb; ++q)
+        if (id[q] == 0) id[q] = count++;
+    for (int64_t v = 0; v < nvox; ++v) field_map[v] = occ[v] > thr ? id[blk[v]] : -1;
+    return count;
+}
+
 // ---- Adam (Sec. 6.1 training details: beta1 0.9, beta2 0.99) -------------
 // m = b1 m + (1 - b1) g; v = b2 v + (1 - b2) g^2;
 // w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps), FP64.

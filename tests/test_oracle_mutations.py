@@ -28,6 +28,9 @@ PLANTS = {
     15: "occupancy: a free pass overrides a hit in the same pose",
     16: "depth statistics: weights not normalised by the opacity",
     17: "occupancy: hit logit not weakened by the uncertainty",
+    18: "assignment: anchor at the largest free index",
+    19: "assignment: nearest by grid steps instead of Euclidean distance",
+    20: "assignment: the remainder voxels all go to the last field",
 }
 
 

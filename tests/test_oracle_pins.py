@@ -764,3 +764,99 @@ def test_global_measure_opaque_first_sample(orc):
     wts = np.exp(-S) * (1 - np.exp(-tau))
     assert np.allclose(A, 1 - np.exp(-tau.sum()), rtol=1e-12)
     assert np.allclose(D, (wts * ts).sum() / wts.sum(), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Stage II adaptive field assignment (Sec. 4.2, Alg.1) and the uniform variant
+# ---------------------------------------------------------------------------
+
+def _brute_assign(occ, thr, n):
+    """Alg.1 Stage II over index triples in plain Python (tiny grids only)."""
+    nz, ny, nx = occ.shape
+    free = [(z, y, x) for z in range(nz) for y in range(ny) for x in range(nx) if occ[z, y, x] > thr]
+    S = len(free)
+    out = np.full(occ.shape, -1, np.int32)
+    for k in range(n):
+        sk = S // n + (1 if k < S % n else 0)
+        if sk == 0:
+            continue
+        a = min(free)                       # (z, y, x) order is the linear order
+        free.sort(key=lambda v: (sum((p - q) ** 2 for p, q in zip(v, a)), v))
+        for v in free[:sk]:
+            out[v] = k
+        free = free[sk:]
+    return out
+
+
+def test_assign_line_of_voxels(orc):
+    occ = np.ones((1, 1, 10), np.float32)
+    fmap, S = orc.assign_fields(occ, 0.5, 3)
+    # sizes 4, 3, 3 (the first S mod n fields take the extra voxel); each
+    # anchor is the leftmost free voxel, its nearest free voxels lie to its right
+    assert S == 10 and fmap.ravel().tolist() == [0, 0, 0, 0, 1, 1, 1, 2, 2, 2]
+    fmap, _ = orc.assign_fields(occ, 0.5, 12)
+    assert fmap.ravel().tolist() == list(range(10))          # more fields than voxels: ten singletons
+
+
+def test_assign_euclidean_nearest_and_clusters(orc):
+    occ = np.zeros((1, 4, 4), np.float32)
+    occ[0, 0, 0] = occ[0, 2, 2] = occ[0, 0, 3] = 1.0
+    fmap, _ = orc.assign_fields(occ, 0.5, 2)
+    # from the anchor (0,0,0): (2,2) is at squared distance 8, (0,3) at 9, so
+    # (2,2) joins the anchor (by grid steps the order would be the other way)
+    assert fmap[0, 0, 0] == 0 and fmap[0, 2, 2] == 0 and fmap[0, 0, 3] == 1
+    occ = np.zeros((8, 8, 8), np.float32)
+    occ[:2, :2, :2] = 1.0
+    occ[6:, 6:, 6:] = 1.0
+    fmap, S = orc.assign_fields(occ, 0.5, 2)
+    assert S == 16 and np.all(fmap[:2, :2, :2] == 0) and np.all(fmap[6:, 6:, 6:] == 1)
+    assert np.all(fmap[occ == 0] == -1)
+
+
+def test_assign_matches_brute_force(orc):
+    for seed, shape, p, n in ((1, (3, 4, 5), 0.5, 4), (2, (6, 6, 6), 0.3, 7), (3, (5, 2, 7), 0.8, 3),
+                              (4, (4, 4, 4), 0.05, 9)):
+        occ = np.random.default_rng(seed).uniform(size=shape).astype(np.float32)
+        fmap, S = orc.assign_fields(occ, 1 - p, n)
+        assert S == int((occ > 1 - p).sum())
+        assert np.array_equal(fmap, _brute_assign(occ, 1 - p, n)), seed
+
+
+def test_assign_sizes_and_nearest_property(orc):
+    occ = np.random.default_rng(7).uniform(size=(10, 12, 9)).astype(np.float32)
+    n = 13
+    fmap, S = orc.assign_fields(occ, 0.6, n)
+    sizes = np.bincount(fmap[fmap >= 0], minlength=n)
+    assert sizes.sum() == S and set(sizes.tolist()) <= {S // n, S // n + 1}
+    assert np.all(sizes[: S % n] == S // n + 1)
+    z, y, x = np.nonzero(fmap >= 0)
+    lin = x + 9 * (y + 12 * z)
+    lab = fmap[z, y, x]
+    for k in range(n):
+        mine = lab == k
+        later = lab > k
+        a = lin[mine].min()
+        assert not np.any(lin[later] < a)                 # the anchor is the smallest free index
+        az, ay, ax = a // (9 * 12), (a // 9) % 12, a % 9
+        d2 = (x - ax) ** 2 + (y - ay) ** 2 + (z - az) ** 2
+        worst = max(zip(d2[mine], lin[mine]))
+        assert all((dd, ll) > worst for dd, ll in zip(d2[later], lin[later]))   # nobody later was nearer
+
+
+def test_assign_uniform_blocks(orc):
+    occ = np.ones((4, 4, 4), np.float32)
+    fmap, nf = orc.assign_uniform(occ, 0.5, (2, 2, 2))
+    z, y, x = np.indices((4, 4, 4))
+    assert nf == 8 and np.array_equal(fmap, x // 2 + 2 * (y // 2) + 4 * (z // 2))
+    # only non-empty blocks become fields, numbered in block order
+    occ = np.zeros((4, 4, 4), np.float32)
+    occ[3, 0, 3] = 1.0          # block (1, 0, 1) = 5
+    occ[0, 3, 1] = 1.0          # block (0, 1, 0) = 2
+    fmap, nf = orc.assign_uniform(occ, 0.5, (2, 2, 2))
+    assert nf == 2 and fmap[0, 3, 1] == 0 and fmap[3, 0, 3] == 1 and (fmap >= 0).sum() == 2
+    # a side of 5 cut into 2 blocks: indices 0..2 and 3..4 (floor(i * 2 / 5))
+    occ = np.ones((1, 1, 5), np.float32)
+    fmap, nf = orc.assign_uniform(occ, 0.5, (2, 1, 1))
+    assert nf == 2 and fmap.ravel().tolist() == [0, 0, 0, 1, 1]
+    fmap, nf = orc.assign_uniform(np.ones((3, 3, 3), np.float32), 0.5, (1, 1, 1))
+    assert nf == 1 and np.all(fmap == 0)
