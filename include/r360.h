@@ -311,6 +311,32 @@ r360_status r360_global_field_measure(const r360_global_desc* desc, const float*
                                       const float* d, int64_t N, float* depth, float* uncert, float* opacity,
                                       void* ws, size_t ws_bytes, void* stream);
 
+/* Stage II of Alg.1 (Sec. 4.2): adaptive field assignment. Occupied voxels
+ * are those with occ > threshold (FP32 compare), S of them; field k (0 <= k <
+ * n_fields) receives floor(S / n_fields) + (k < S mod n_fields) voxels. For k
+ * = 0, 1, ...: the anchor is the unassigned occupied voxel of smallest linear
+ * index (x + n0 (y + n1 z): the minimum coordinate, z then y then x); the
+ * field takes the unassigned occupied voxels nearest to the anchor (squared
+ * distance between voxel indices, ties to the smaller linear index), the
+ * anchor first. Writes field_map [n2][n1][n0] (device, int32, -1 for
+ * unoccupied voxels), usable directly by r360_scene_create. Synchronises
+ * the stream once (to size the loop by S); S is returned in
+ * n_occupied_host (may be NULL). Deterministic. */
+size_t r360_assign_workspace_bytes(const int32_t n[3]);
+r360_status r360_assign_fields(const int32_t n[3], const float* occ, float threshold, int32_t n_fields,
+                               int32_t* field_map, int64_t* n_occupied_host, void* ws, size_t ws_bytes,
+                               void* stream);
+
+/* The uniform decomposition (the 360Roam-u variant of Sec. 6): blocks[a]
+ * blocks per axis (1 <= blocks[a] <= n[a]), voxel index i in block
+ * floor(i * blocks[a] / n[a]); the fields are the blocks holding an occupied
+ * voxel, numbered in linear block order (x fastest). Writes field_map as
+ * above and the number of fields to n_fields_host (synchronises once). */
+size_t r360_assign_uniform_workspace_bytes(const int32_t blocks[3]);
+r360_status r360_assign_uniform(const int32_t n[3], const float* occ, float threshold, const int32_t blocks[3],
+                                int32_t* field_map, int32_t* n_fields_host, void* ws, size_t ws_bytes,
+                                void* stream);
+
 /* Optional per-stage timing for benchmarking: when enabled, every entry
  * point records a HIP event pair around each stage of its launch sequence on
  * the call's own stream. Stages: 0 sampling (traversal + scan + compaction), 1 routing,

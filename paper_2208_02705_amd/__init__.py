@@ -2,8 +2,8 @@
 
 Equirect/pinhole ray generation -> occupied-voxel sampling -> routing by
 field -> positional encoding + per-field MLP (MFMA) -> alpha compositing,
-plus the backward pass for fine-tuning, the global field and Stage I
-occupancy estimation; every step is a HIP kernel in
+plus the backward pass for fine-tuning, the global field, Stage I
+occupancy estimation and Stage II field assignment; every step is a HIP kernel in
 libr360.so behind the C ABI of include/r360.h. This package only marshals
 arguments (ctypes) and provides torch.autograd wrappers. The shared library
 is loaded on first use and its absence is an error.
@@ -13,3 +13,4 @@ from .render import (Scene, Equirect, EquirectRenderer, PinholeRenderer, RenderF
                      sample_rays, render_rays, render_equirect, render_pinhole, backward, train_step, adam_step,
                      field_params, lr_at, profile_enable, profile_read, GlobalField)
 from .occupancy import OccupancyMap, depth_uncertainty, global_measure  # noqa: F401
+from .assign import assign_fields, assign_uniform  # noqa: F401

@@ -81,6 +81,10 @@ SIGNATURES = {
     "r360_occupancy_workspace_bytes": (sz, [C.POINTER(OccDesc)]),
     "r360_occupancy_update": (i32, [C.POINTER(OccDesc), vp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
     "r360_global_field_measure": (i32, [C.POINTER(GlobalDesc), vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
+    "r360_assign_workspace_bytes": (sz, [vp]),
+    "r360_assign_fields": (i32, [vp, vp, f32, i32, vp, C.POINTER(i64), vp, sz, vp]),
+    "r360_assign_uniform_workspace_bytes": (sz, [vp]),
+    "r360_assign_uniform": (i32, [vp, vp, f32, vp, vp, C.POINTER(i32), vp, sz, vp]),
     "r360_profile_enable": (i32, [i32]),
     "r360_profile_read": (i32, [vp, vp]),
     "r360_status_string": (C.c_char_p, [i32]),

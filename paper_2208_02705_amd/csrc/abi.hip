@@ -660,6 +660,65 @@ r360_status r360_global_field_measure(const r360_global_desc* g, const float* we
     return R360_OK;
 }
 
+static r360_status check_dims(const int32_t* n) {
+    if (!n) return inval("grid size is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (n[a] < 1 || n[a] > 4096) return inval("grid size outside [1, 4096]");
+    if ((int64_t)n[0] * n[1] * n[2] >= (int64_t(1) << 31)) return inval("grid has 2^31 voxels or more");
+    return R360_OK;
+}
+
+size_t r360_assign_workspace_bytes(const int32_t n[3]) {
+    if (check_dims(n) != R360_OK) return 0;
+    return assign_workspace_bytes((int64_t)n[0] * n[1] * n[2]);
+}
+
+r360_status r360_assign_fields(const int32_t n[3], const float* occ, float threshold, int32_t n_fields,
+                               int32_t* field_map, int64_t* n_occupied_host, void* ws, size_t ws_bytes,
+                               void* stream) {
+    r360_status st = check_dims(n);
+    if (st != R360_OK) return st;
+    if (!occ || !field_map || !ws) return inval("NULL pointer");
+    if (n_fields < 1) return inval("n_fields must be >= 1");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    const size_t need = assign_workspace_bytes((int64_t)n[0] * n[1] * n[2]);
+    if (ws_bytes < need) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return R360_EWORKSPACE;
+    }
+    int64_t n_occ = 0;
+    R360_TRY("field assignment",
+             launch_assign_fields(n, occ, threshold, n_fields, field_map, &n_occ, ws, S(stream)));
+    if (n_occupied_host) *n_occupied_host = n_occ;
+    return R360_OK;
+}
+
+size_t r360_assign_uniform_workspace_bytes(const int32_t b[3]) {
+    if (!b || b[0] < 1 || b[1] < 1 || b[2] < 1 || (int64_t)b[0] * b[1] * b[2] > (int64_t(1) << 24)) return 0;
+    return uniform_workspace_bytes((int64_t)b[0] * b[1] * b[2]);
+}
+
+r360_status r360_assign_uniform(const int32_t n[3], const float* occ, float threshold, const int32_t b[3],
+                                int32_t* field_map, int32_t* n_fields_host, void* ws, size_t ws_bytes,
+                                void* stream) {
+    r360_status st = check_dims(n);
+    if (st != R360_OK) return st;
+    if (!occ || !field_map || !ws || !b) return inval("NULL pointer");
+    for (int a = 0; a < 3; ++a)
+        if (b[a] < 1 || b[a] > n[a]) return inval("blocks per axis outside [1, n]");
+    if ((int64_t)b[0] * b[1] * b[2] > (int64_t(1) << 24)) return inval("more than 2^24 blocks");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    const size_t need = uniform_workspace_bytes((int64_t)b[0] * b[1] * b[2]);
+    if (ws_bytes < need) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return R360_EWORKSPACE;
+    }
+    int32_t count = 0;
+    R360_TRY("uniform assignment", launch_assign_uniform(n, occ, threshold, b, field_map, &count, ws, S(stream)));
+    if (n_fields_host) *n_fields_host = count;
+    return R360_OK;
+}
+
 r360_status r360_profile_enable(int32_t on) {
     g_prof = on != 0;
     return R360_OK;

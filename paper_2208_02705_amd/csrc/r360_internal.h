@@ -494,6 +494,14 @@ int64_t global_params(int w, int c);
 hipError_t launch_depth_stats(const float* t, const float* delta, const float* sigma, int64_t N, int S,
                               float* depth, float* uncert, float* opacity, hipStream_t st);
 size_t occupancy_workspace_bytes(int64_t nvox);
+// Stage II field assignment (synchronises the stream once to read the
+// number of occupied voxels) and the uniform block decomposition.
+size_t assign_workspace_bytes(int64_t nvox);
+size_t uniform_workspace_bytes(int64_t nblocks);
+hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr, int32_t n_fields, int32_t* fmap,
+                                int64_t* S_out, void* ws, hipStream_t st);
+hipError_t launch_assign_uniform(const int32_t n[3], const float* occ, float thr, const int32_t b[3], int32_t* fmap,
+                                 int32_t* count_out, void* ws, hipStream_t st);
 hipError_t launch_occupancy_update(const r360_occ_desc* g, float* logit, float* prob, const float* o, const float* d,
                                    int64_t N, const float* depth, const float* uncert, const float* opacity,
                                    void* ws, hipStream_t st);

@@ -106,3 +106,18 @@ def test_occupancy_arguments_rejected(L):
     gd = _lib.GlobalDesc()
     assert L.r360_global_field_measure(C.byref(gd), None, None, None, 4, None, None, None, None, 0,
                                        None) == _lib.R360_EUNSUPPORTED
+
+
+def test_assignment_arguments_rejected(L):
+    from paper_2208_02705_amd import _lib
+    n = (C.c_int32 * 3)(8, 8, 8)
+    assert L.r360_assign_workspace_bytes(None) == 0
+    assert L.r360_assign_workspace_bytes((C.c_int32 * 3)(0, 8, 8)) == 0
+    assert L.r360_assign_workspace_bytes(n) > 512 * 13
+    S = C.c_int64(0)
+    assert L.r360_assign_fields(n, None, 0.5, 4, None, C.byref(S), None, 0, None) == _lib.R360_EINVAL
+    b = (C.c_int32 * 3)(2, 2, 2)
+    assert L.r360_assign_uniform_workspace_bytes(b) > 0
+    assert L.r360_assign_uniform_workspace_bytes((C.c_int32 * 3)(0, 1, 1)) == 0
+    nf = C.c_int32(0)
+    assert L.r360_assign_uniform(n, None, 0.5, b, None, C.byref(nf), None, 0, None) == _lib.R360_EINVAL
