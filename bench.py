@@ -70,7 +70,8 @@ def parse():
     p.add_argument("--no-large", action="store_true")
     p.add_argument("--no-global", action="store_true")
     p.add_argument("--no-occupancy", action="store_true")
-    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy"], default=None,
+    p.add_argument("--no-assign", action="store_true")
+    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy", "assign"], default=None,
                    help="time only one leg (for profiler runs)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB mebibytes (to calibrate HBM byte counters)")
@@ -135,7 +136,7 @@ def main():
         del r
         return sec, prof
 
-    legs = ["bf16", "fp32", "train", "large", "global", "occupancy"] if args.only is None else [args.only]
+    legs = ["bf16", "fp32", "train", "large", "global", "occupancy", "assign"] if args.only is None else [args.only]
     res = {}
     if "bf16" in legs:
         res["bf16"] = leg("bf16", args.steps, args.warmup)
@@ -157,6 +158,9 @@ def main():
     occl = None
     if "occupancy" in legs and not args.no_occupancy:
         occl = occupancy_leg(R, scene, args)
+    asg = None
+    if "assign" in legs and not args.no_assign:
+        asg = assign_leg(R, sc, args)
 
     main_prec = "bf16" if "bf16" in res else next(iter(res), None)
     line = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -206,6 +210,8 @@ def main():
         line["global_field"] = glob
     if occl is not None:
         line["occupancy_update"] = occl
+    if asg is not None:
+        line["field_assignment"] = asg
     line["context"] = ("paper: 360Roam renders a 1520x760 panorama in 0.03 s on one RTX2080 Ti (about 38.5 Mrays/s, "
                        "precision not stated) and runs in real time on a GTX1080; different hardware and scenes")
     if not args.no_cpu_baseline and args.only is None:
@@ -382,6 +388,22 @@ def occupancy_leg(R, scene, args):
             "library_ms_per_pose": ms, "measuring_rays": int((opac >= 0.5).sum().item()),
             "occupied_after": int(om.occupied().sum().item()),
             "voxel_pass_bytes": 5 * nvox + 17 * nvox}
+
+
+def assign_leg(R, sc, args):
+    """Stage II assignment (one call: compaction, then one radix select per
+    field): the headline scene's 128^3 occupancy into 141 fields, and the
+    large scene's 256^3 occupancy into 512 fields."""
+    import torch
+    import synth
+    out = {}
+    for name, s, n in (("room_128cube_141_fields", sc, 141), ("large_256cube_512_fields", synth.scene_large(), 512)):
+        occ = torch.from_numpy(s.occ).cuda()
+        steps = max(3, args.steps // 10)
+        sec = timed(lambda: R.assign_fields(occ, s.threshold, n), steps, 1)
+        _, S = R.assign_fields(occ, s.threshold, n)
+        out[name] = {"occupied": S, "fields": n, "ms": sec * 1e3, "mvoxels_per_s": S / sec / 1e6}
+    return out
 
 
 def cpu_baseline(sc):
