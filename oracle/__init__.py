@@ -104,6 +104,8 @@ def lib():
             "orc_occupancy_update": (None, [vp, vp, vp, i64, vp, vp, vp, vp, vp, C.c_int]),
             "orc_global_measure": (None, [vp, i64, vp, vp, vp, vp, vp, C.c_int]),
             "orc_assign_fields": (i64, [vp, vp, f32, i32, vp]),
+            "orc_distill": (f64, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
+            "orc_global_points": (None, [vp, i64, vp, vp, vp, vp, C.c_int]),
             "orc_assign_uniform": (i32, [vp, vp, f32, vp, vp]),
         }
         for name, (res, args) in sig.items():
@@ -419,3 +421,30 @@ def assign_uniform(occ: np.ndarray, threshold: float, blocks):
     fmap = np.empty(occ.shape, np.int32)
     nf = lib().orc_assign_uniform(n, _p(occ), threshold, b, _p(fmap))
     return fmap, int(nf)
+
+
+# ---- distillation (Sec. 4.2, Eq.7) -----------------------------------------
+def distill(scene, x, d, field, target_sigma, target_rgb, weights: Optional[np.ndarray] = None,
+            threads: Optional[int] = None):
+    """(loss, grad [n_fields, P] FP64, sigma [M], rgb [3, M]) of the Eq.7 loss summed over fields."""
+    h = SceneHandle(scene, weights=weights)
+    x = _c(x, np.float32); d = _c(d, np.float32); field = _c(field, np.int32)
+    ts = _c(target_sigma, np.float32); tr = _c(target_rgb, np.float32)
+    M = x.shape[1]
+    grad = np.empty(h.weights.shape, np.float64)
+    sig = np.empty(M); rgb = np.empty((3, M))
+    loss = lib().orc_distill(h.ptr, M, _p(x), _p(d), _p(field), _p(ts), _p(tr), _p(grad), _p(sig), _p(rgb),
+                             threads or default_threads())
+    return float(loss), grad, sig, rgb
+
+
+def global_points(weights, x, d, width=256, color_width=128, L_xyz=10, L_dir=4, center=(0.0, 0.0, 0.0),
+                  half_extent=4.0, threads: Optional[int] = None):
+    """The global field's (sigma [M], rgb [3, M]) FP64 at points x with directions d ([3, M] each)."""
+    w = _c(weights, np.float32)
+    x = _c(x, np.float32); d = _c(d, np.float32)
+    M = x.shape[1]
+    g = _global_desc(w, 2, 0.1, 20.0, width, color_width, L_xyz, L_dir, center, half_extent, 1, 0.0, 1.0)
+    sig = np.empty(M); rgb = np.empty((3, M))
+    lib().orc_global_points(C.byref(g), M, _p(x), _p(d), _p(sig), _p(rgb), threads or default_threads())
+    return sig, rgb

@@ -738,6 +738,64 @@ double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float*
     return loss;
 }
 
+// ---- distillation (Sec. 4.2, Eq.7): each local field is fitted to the global
+// field at points inside its own region. With point i (position x_i, view
+// direction d_i) owned by field k(i), local outputs sigma^k_i, c^k_i and the
+// global field's targets sigma_i, c_i:
+//   L = sum_k (1/I_k) sum_{i of field k} [(sigma^k_i - sigma_i)^2 + |c^k_i - c_i|^2],
+// I_k the number of points of field k (points with a field id outside
+// [0, n_fields) are ignored). The local field sees the point through the
+// renderer's own sample position with t = 0: p = fma(0, d, x) = x. Returns
+// L; grad [n_fields][P] (FP64, overwritten); sigma/rgb outputs optional.
+double orc_distill(const OrcScene* s, int64_t M, const float* x, const float* dir, const int32_t* field,
+                   const float* tsig, const float* trgb /*[3][M]*/, double* grad, double* sig_out,
+                   double* rgb_out /*[3][M]*/, int nthreads) {
+    const int dx = 3 + 6 * s->L_xyz, dd = 3 + 6 * s->L_dir;
+    const size_t P = local_params(s->hidden, dx, dd);
+    const size_t GP = P * s->n_fields;
+    std::vector<double> wd = widen(s->weights, GP);
+    std::vector<int64_t> I(s->n_fields, 0);
+    for (int64_t i = 0; i < M; ++i)
+        if (field[i] >= 0 && field[i] < s->n_fields) ++I[field[i]];
+    int nt = std::max(1, nthreads);
+    std::vector<std::vector<double>> gth(nt, std::vector<double>(GP, 0.0));
+    std::vector<double> lth(nt, 0.0);
+    parallel_for(M, nt, [&](int64_t b, int64_t e, int t) {
+        LocalAct a;
+        for (int64_t i = b; i < e; ++i) {
+            const int k = field[i];
+            if (k < 0 || k >= s->n_fields) continue;
+            float oo[3] = {x[i], x[M + i], x[2 * M + i]}, dv[3] = {dir[i], dir[M + i], dir[2 * M + i]};
+            double xh[3], dd3[3] = {dv[0], dv[1], dv[2]};
+            sample_position(*s, oo, dv, 0.0f, xh);
+            LocalNet net = local_view(wd.data() + P * k, s->hidden, dx, dd);
+            local_forward(net, xh, dd3, s->L_xyz, s->L_dir, a);
+            const double inv = ORC_PLANT == 21 ? 1.0 / (double)M : 1.0 / (double)I[k];
+            const double ds = a.sigma - (double)tsig[i];
+            double dsig = 2.0 * ds * inv, drgb[3];
+            double l = ds * ds;
+            for (int c = 0; c < 3; ++c) {
+                const double dc = a.rgb[c] - (double)trgb[c * M + i];
+                l += dc * dc;
+                drgb[c] = 2.0 * dc * inv;
+            }
+            if (ORC_PLANT == 22) dsig = 0.0;
+            lth[t] += l * inv;
+            LocalNet gn = local_view(gth[t].data() + P * k, s->hidden, dx, dd);
+            local_backward(net, a, dsig, drgb, gn);
+            if (sig_out) sig_out[i] = a.sigma;
+            if (rgb_out) for (int c = 0; c < 3; ++c) rgb_out[c * M + i] = a.rgb[c];
+        }
+    });
+    double loss = 0.0;
+    for (size_t q = 0; q < GP; ++q) grad[q] = 0.0;
+    for (int t = 0; t < nt; ++t) {
+        loss += lth[t];
+        for (size_t q = 0; q < GP; ++q) grad[q] += gth[t][q];
+    }
+    return loss;
+}
+
 // ---- global omnidirectional field ----------------------------------------
 // Sample placement uniform in inverse depth over [near, far] (Sec. 3.2
 // places the global field's samples evenly in inverse distance), FP32 spec:
@@ -834,6 +892,30 @@ double orc_global_step(const OrcGlobal* g, int64_t N, const float* o, const floa
         if (occ_max) for (size_t i = 0; i < ncell; ++i) occ_max[i] = std::max(occ_max[i], occ_th[t][i]);
     }
     return loss;
+}
+
+// The distillation targets: the global field's density and colour at given
+// points (position x, direction d): the global step's sample position with
+// t = 0, xhat = (fma(0, d, x) - center) / half_extent, FP64 network.
+void orc_global_points(const OrcGlobal* g, int64_t M, const float* x, const float* dir, double* sig,
+                       double* rgb /*[3][M]*/, int nthreads) {
+    const int dx = 3 + 6 * g->L_xyz, dd = 3 + 6 * g->L_dir;
+    const size_t P = global_params(g->width, g->color_width, dx, dd);
+    std::vector<double> wd = widen(g->weights, P);
+    GlobalNet net = global_view(wd.data(), g->width, g->color_width, dx, dd);
+    const float inv_h = 1.0f / g->half_extent;
+    parallel_for(M, std::max(1, nthreads), [&](int64_t b, int64_t e, int) {
+        GlobalAct a;
+        for (int64_t i = b; i < e; ++i) {
+            float dv[3] = {dir[i], dir[M + i], dir[2 * M + i]};
+            double xh[3], d3[3] = {dv[0], dv[1], dv[2]};
+            for (int c = 0; c < 3; ++c)
+                xh[c] = (double)((std::fma(0.0f, dv[c], x[c * M + i]) - g->center[c]) * inv_h);
+            global_forward(net, xh, d3, g->L_xyz, g->L_dir, a);
+            sig[i] = a.sigma;
+            for (int c = 0; c < 3; ++c) rgb[c * M + i] = a.rgb[c];
+        }
+    });
 }
 
 // Global field forward at explicit points (pins and per-sample checks).

@@ -31,6 +31,8 @@ PLANTS = {
     18: "assignment: anchor at the largest free index",
     19: "assignment: nearest by grid steps instead of Euclidean distance",
     20: "assignment: the remainder voxels all go to the last field",
+    21: "distillation: each field's term averaged over all points instead of its own",
+    22: "distillation: density term left out of the gradient",
 }
 
 

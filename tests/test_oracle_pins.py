@@ -860,3 +860,89 @@ def test_assign_uniform_blocks(orc):
     assert nf == 2 and fmap.ravel().tolist() == [0, 0, 0, 1, 1]
     fmap, nf = orc.assign_uniform(np.ones((3, 3, 3), np.float32), 0.5, (1, 1, 1))
     assert nf == 1 and np.all(fmap == 0)
+
+
+# ---------------------------------------------------------------------------
+# Distillation of the global field into the local fields (Sec. 4.2, Eq.7)
+# ---------------------------------------------------------------------------
+
+def _distill_points(M, n_fields, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-3.5, 3.5, size=(3, M)).astype(np.float32)
+    d = rng.normal(size=(3, M)); d /= np.linalg.norm(d, axis=0)
+    field = rng.integers(0, n_fields, M).astype(np.int32)
+    ts = rng.uniform(0, 3, M).astype(np.float32)
+    tr = rng.uniform(0, 1, (3, M)).astype(np.float32)
+    return x, d.astype(np.float32), field, ts, tr
+
+
+def test_distill_constant_fields_closed_form(orc):
+    """Zero weights leave sigma = softplus(b_s) and c = sigmoid(b_4) per field,
+    so Eq.7 and its bias gradients are closed forms; each field's term is
+    averaged over its own points."""
+    sc = synth.tiny_scene(4, 3, p_occ=0.5, n_fields=2, hidden=8)
+    lay = synth.local_mlp_layout(8)
+    w = np.zeros((2, synth.n_params(lay)), np.float32)
+    bs = [0.3, -1.2]
+    b4 = [[0.1, -0.4, 0.7], [-0.2, 0.5, 0.0]]
+    for k in range(2):
+        t = synth.unpack(lay, w[k])
+        t["bs"][0] = bs[k]; t["b4"][:] = b4[k]
+    x, d, field, ts, tr = _distill_points(11, 2, 4)
+    field[:3] = 0; field[3:] = 1                       # I_0 = 3, I_1 = 8
+    loss, grad, sig, rgb = orc.distill(sc, x, d, field, ts, tr, weights=w)
+    ts, tr = ts.astype(np.float64), tr.astype(np.float64)
+    want, g_bs, g_b4 = 0.0, [0.0, 0.0], [[0.0] * 3, [0.0] * 3]
+    for k, I in ((0, 3), (1, 8)):
+        s = sp(float(np.float32(bs[k])))
+        c = [1 / (1 + math.exp(-float(np.float32(v)))) for v in b4[k]]
+        for i in np.nonzero(field == k)[0]:
+            want += ((s - ts[i]) ** 2 + sum((c[q] - tr[q, i]) ** 2 for q in range(3))) / I
+            g_bs[k] += 2 * (s - ts[i]) / I / (1 + math.exp(-float(np.float32(bs[k]))))
+            for q in range(3):
+                g_b4[k][q] += 2 * (c[q] - tr[q, i]) / I * c[q] * (1 - c[q])
+    assert abs(loss - want) < 1e-12 * max(1, want)
+    for k in range(2):
+        gk = synth.unpack(lay, grad[k].copy())
+        assert abs(gk["bs"][0] - g_bs[k]) < 1e-12
+        assert np.allclose(gk["b4"], g_b4[k], rtol=0, atol=1e-12)
+        assert np.all(gk["W1"] == 0) and np.all(gk["W3"] == 0)    # zero weights pass no gradient further back
+    assert np.allclose(sig[:3], sp(float(np.float32(bs[0])))) and np.allclose(sig[3:], sp(float(np.float32(bs[1]))))
+
+
+def test_distill_finite_difference_and_ignored_points(orc):
+    sc = synth.tiny_scene(4, 6, p_occ=0.5, n_fields=3, hidden=16)
+    rng = np.random.default_rng(6)
+    w0 = sc.weights + rng.normal(size=sc.weights.shape).astype(np.float32) * 0.05
+    x, d, field, ts, tr = _distill_points(40, 3, 7)
+    loss, grad, _, _ = orc.distill(sc, x, d, field, ts, tr, weights=w0)
+    flat = w0.ravel()
+
+    def loss_fn(wf):
+        return orc.distill(sc, x, d, field, ts, tr, weights=wf.reshape(w0.shape))[0]
+    idx = rng.choice(flat.size, 120, replace=False)
+    bad = _fd_check(loss_fn, flat, idx, grad.ravel())
+    assert not bad, bad[:5]
+    # points whose field id is out of range take no part
+    f2 = np.concatenate([field, np.array([-1, 3], np.int32)])
+    x2 = np.concatenate([x, x[:, :2]], axis=1); d2 = np.concatenate([d, d[:, :2]], axis=1)
+    l2, g2, _, _ = orc.distill(sc, x2, d2, f2, np.concatenate([ts, ts[:2]]), np.concatenate([tr, tr[:, :2]], axis=1),
+                               weights=w0)
+    assert abs(l2 - loss) <= 1e-13 * loss and np.allclose(g2, grad, rtol=1e-12, atol=1e-15)
+
+
+def test_global_points_constant_field(orc):
+    lay = synth.global_mlp_layout(16, color_width=8)
+    w = np.zeros(synth.n_params(lay), np.float32)
+    t = synth.unpack(lay, w)
+    t["bs"][0] = 0.75; t["b11"][:] = [0.2, -0.1, 0.4]
+    x, d, _, _, _ = _distill_points(5, 1, 8)
+    sig, rgb = orc.global_points(w, x, d, width=16, color_width=8)
+    assert np.all(sig == np.float64(np.float32(0.75)))
+    assert np.allclose(rgb.T, [sg(float(np.float32(v))) for v in (0.2, -0.1, 0.4)], atol=1e-15)
+    # the raw position reaches the density through the first layer's identity slot
+    t["W1"][0, 2] = 1.0; t["W2"][0, 0] = 1.0; t["W3"][0, 0] = 1.0; t["W4"][0, 0] = 1.0
+    t["W5"][0, 0] = 1.0; t["W6"][0, 0] = 1.0; t["W7"][0, 0] = 1.0; t["W8"][0, 0] = 1.0; t["ws"][0, 0] = 1.0
+    sig, _ = orc.global_points(w, x, d, width=16, color_width=8)
+    z = x[2].astype(np.float64) / 4.0
+    assert np.allclose(sig, 0.75 + np.maximum(z, 0.0), atol=1e-7)
