@@ -311,6 +311,31 @@ r360_status r360_global_field_measure(const r360_global_desc* desc, const float*
                                       const float* d, int64_t N, float* depth, float* uncert, float* opacity,
                                       void* ws, size_t ws_bytes, void* stream);
 
+/* Distillation (Sec. 4.2, Eq.7). The global field's density and colour at
+ * M given points x [3][M] with view directions dir [3][M] (device), written
+ * to sigma [M] and rgb [3][M] (device): the global forward of
+ * r360_global_field_step with one sample per point at the point itself
+ * (desc's near, far and n_samples are not used). Workspace:
+ * r360_global_points_workspace_bytes. */
+size_t r360_global_points_workspace_bytes(const r360_global_desc* desc, int64_t M);
+r360_status r360_global_field_points(const r360_global_desc* desc, const float* weights, const float* x,
+                                     const float* dir, int64_t M, float* sigma, float* rgb, void* ws,
+                                     size_t ws_bytes, void* stream);
+
+/* One distillation step of the local fields: with point i (x, dir [3][M]
+ * device) owned by field[i] (int32 [M], device; ids outside [0, n_fields)
+ * take no part) and its targets target_sigma [M], target_rgb [3][M] (the
+ * global field's values), L = sum_k (1/I_k) sum_{i of field k} [(sigma^k_i -
+ * target_sigma_i)^2 + |c^k_i - target_rgb_i|^2], I_k the points of field k.
+ * Writes loss[0] and grad_weights [n_fields][P] FP32 (overwritten), on the
+ * scene's current weights at opts->precision (FP32, BF16 or FP16; near, far
+ * and max_samples are not used). Workspace: r360_workspace_bytes(scene, M,
+ * 1). 1 <= M <= 2^30. */
+r360_status r360_distill_step(const r360_scene* scene, const float* x, const float* dir, const int32_t* field,
+                              int64_t M, const float* target_sigma, const float* target_rgb,
+                              const r360_render_opts* opts, float* loss, float* grad_weights, void* ws,
+                              size_t ws_bytes, void* stream);
+
 /* Stage II of Alg.1 (Sec. 4.2): adaptive field assignment. Occupied voxels
  * are those with occ > threshold (FP32 compare), S of them; field k (0 <= k <
  * n_fields) receives floor(S / n_fields) + (k < S mod n_fields) voxels. For k

@@ -3,7 +3,8 @@
 Equirect/pinhole ray generation -> occupied-voxel sampling -> routing by
 field -> positional encoding + per-field MLP (MFMA) -> alpha compositing,
 plus the backward pass for fine-tuning, the global field, Stage I
-occupancy estimation and Stage II field assignment; every step is a HIP kernel in
+occupancy estimation, Stage II field assignment and the distillation of
+the global field into the local ones; every step is a HIP kernel in
 libr360.so behind the C ABI of include/r360.h. This package only marshals
 arguments (ctypes) and provides torch.autograd wrappers. The shared library
 is loaded on first use and its absence is an error.
@@ -14,3 +15,4 @@ from .render import (Scene, Equirect, EquirectRenderer, PinholeRenderer, RenderF
                      field_params, lr_at, profile_enable, profile_read, GlobalField)
 from .occupancy import OccupancyMap, depth_uncertainty, global_measure  # noqa: F401
 from .assign import assign_fields, assign_uniform  # noqa: F401
+from .distill import global_points, distill_step  # noqa: F401

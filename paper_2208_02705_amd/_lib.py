@@ -81,6 +81,9 @@ SIGNATURES = {
     "r360_occupancy_workspace_bytes": (sz, [C.POINTER(OccDesc)]),
     "r360_occupancy_update": (i32, [C.POINTER(OccDesc), vp, vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
     "r360_global_field_measure": (i32, [C.POINTER(GlobalDesc), vp, vp, vp, i64, vp, vp, vp, vp, sz, vp]),
+    "r360_global_points_workspace_bytes": (sz, [C.POINTER(GlobalDesc), i64]),
+    "r360_global_field_points": (i32, [C.POINTER(GlobalDesc), vp, vp, vp, i64, vp, vp, vp, sz, vp]),
+    "r360_distill_step": (i32, [vp, vp, vp, vp, i64, vp, vp, C.POINTER(RenderOpts), vp, vp, vp, sz, vp]),
     "r360_assign_workspace_bytes": (sz, [vp]),
     "r360_assign_fields": (i32, [vp, vp, f32, i32, vp, C.POINTER(i64), vp, sz, vp]),
     "r360_assign_uniform_workspace_bytes": (sz, [vp]),

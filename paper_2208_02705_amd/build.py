@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libr360.so")
 ARCH = os.environ.get("R360_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.hip", "sample.hip", "route.hip", "mlp.hip", "composite.hip", "backward.hip", "global.hip",
-           "occupancy.hip", "assign.hip"]
+           "occupancy.hip", "assign.hip", "distill.hip"]
 NO_CONTRACT = {"sample.hip", "global.hip", "occupancy.hip"}
 
 COMMON = [

@@ -660,6 +660,72 @@ r360_status r360_global_field_measure(const r360_global_desc* g, const float* we
     return R360_OK;
 }
 
+size_t r360_global_points_workspace_bytes(const r360_global_desc* g, int64_t M) {
+    if (check_global(g) != R360_OK || M <= 0) return 0;
+    return global_workspace_bytes(g->width, g->color_width, M, 1);
+}
+
+r360_status r360_global_field_points(const r360_global_desc* g, const float* weights, const float* x,
+                                     const float* dir, int64_t M, float* sigma, float* rgb, void* ws, size_t ws_bytes,
+                                     void* stream) {
+    r360_status st = check_global(g);
+    if (st != R360_OK) return st;
+    if (!weights || !x || !dir || !sigma || !rgb || !ws) return inval("NULL pointer");
+    if (M <= 0 || M >= (int64_t(1) << 31)) return inval("M outside [1, 2^31)");
+    if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
+    const size_t need = global_workspace_bytes(g->width, g->color_width, M, 1);
+    if (ws_bytes < need) {
+        std::snprintf(g_err, sizeof(g_err), "workspace has %zu bytes, needs %zu", ws_bytes, need);
+        return R360_EWORKSPACE;
+    }
+    r360_global_desc one = *g;
+    one.n_samples = 1;
+    GlobalMeasure pts;
+    pts.points = true;
+    pts.point_sigma = sigma;
+    pts.point_rgb = rgb;
+    R360_STAGE(7, S(stream));
+    R360_TRY("global field points", launch_global_step(&one, weights, x, dir, M, nullptr, nullptr, nullptr, nullptr,
+                                                       nullptr, nullptr, ws, S(stream), 1, &pts));
+    return R360_OK;
+}
+
+r360_status r360_distill_step(const r360_scene* s, const float* x, const float* dir, const int32_t* field,
+                              int64_t M, const float* tsig, const float* trgb, const r360_render_opts* opts,
+                              float* loss, float* grad_weights, void* ws, size_t ws_bytes, void* stream) {
+    if (!x || !dir || !field || !tsig || !trgb || !loss || !grad_weights || !opts) return inval("NULL pointer");
+    r360_render_opts one = *opts;
+    one.max_samples = 1;
+    one.near_ = 0.0f;
+    one.far_ = 1.0f;
+    Workspace w;
+    r360_status st = prepare(s, M, &one, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    w.ro = x;
+    w.rd = dir;
+    {
+        R360_STAGE(0, S(stream));
+        R360_TRY("distill points", launch_distill_points(w, M, field, s->mlp.n_fields, S(stream)));
+    }
+    {
+        R360_STAGE(1, S(stream));
+        R360_TRY("route", launch_route(w, s->mlp.n_fields, S(stream)));
+    }
+    {
+        R360_STAGE(2, S(stream));
+        R360_TRY("mlp forward", launch_mlp_forward(s, w, one.precision, S(stream)));
+    }
+    {
+        R360_STAGE(4, S(stream));
+        R360_TRY("distill loss", launch_distill_loss(w, M, tsig, trgb, loss, S(stream)));
+    }
+    {
+        R360_STAGE(6, S(stream));
+        R360_TRY("mlp backward", launch_mlp_backward(s, w, one.precision, grad_weights, S(stream)));
+    }
+    return R360_OK;
+}
+
 static r360_status check_dims(const int32_t* n) {
     if (!n) return inval("grid size is NULL");
     for (int a = 0; a < 3; ++a)

@@ -181,6 +181,7 @@ struct GSampleArgs {
     int32_t* voxel;            // [M] linear cell or -1
     int32_t* ray;              // [M] ray of each sample
     int32_t* ray_off;          // [N+1]
+    int points;                // one sample per ray at t = 0 (the origin itself)
 };
 
 __device__ inline float inv_depth_t(const GSampleArgs& a, int k) {
@@ -195,10 +196,10 @@ __global__ __launch_bounds__(256) void k_gsamples(GSampleArgs a) {
     if (m >= M) return;
     const int64_t r = m / a.S;
     const int k = (int)(m % a.S);
-    const float t = inv_depth_t(a, k);
+    const float t = a.points ? 0.0f : inv_depth_t(a, k);
     a.t[m] = t;
     a.ray[m] = (int32_t)r;
-    a.delta[m] = (k + 1 < a.S) ? inv_depth_t(a, k + 1) - t : 0.0f;
+    a.delta[m] = (!a.points && k + 1 < a.S) ? inv_depth_t(a, k + 1) - t : 0.0f;
     const float o[3] = {a.o[r], a.o[a.N + r], a.o[2 * a.N + r]};
     const float d[3] = {a.d[r], a.d[a.N + r], a.d[2 * a.N + r]};
     const float cc[3] = {a.c0, a.c1, a.c2};
@@ -690,6 +691,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     sa.g0 = desc->grid_n[0]; sa.g1 = desc->grid_n[1]; sa.g2 = desc->grid_n[2];
     sa.x5 = g.x5; sa.x10 = g.x10; sa.w = w; sa.k10 = n.L[G10].K;
     sa.t = g.t; sa.delta = g.delta; sa.voxel = g.voxel; sa.ray = g.ray; sa.ray_off = g.ray_off;
+    sa.points = (meas && meas->points) ? 1 : 0;
     hipLaunchKernelGGL(k_gsamples, dim3((unsigned)((std::max<int64_t>(M, Nr + 1) + 255) / 256)), dim3(256), 0, st, sa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -733,6 +735,11 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
         a.bias = Bv(G11); a.rgb = g.rgb;
         if ((e = gemm(EPI_RGB, a, 1, st)) != hipSuccess) return e;
     }
+    if (meas && meas->points) {
+        if ((e = hipMemcpyAsync(meas->point_sigma, g.sig, M * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+            return e;
+        return hipMemcpyAsync(meas->point_rgb, g.rgb, 3 * M * sizeof(float), hipMemcpyDeviceToDevice, st);
+    }
     if (occ) hipLaunchKernelGGL(k_gocc, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, g.sig, g.voxel,
                                 reinterpret_cast<unsigned*>(occ));
     // compositing, loss and its backward reuse the local path's kernels
@@ -741,8 +748,8 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     lw.dsigma = g.dsig; lw.drgb = g.drgb; lw.loss_part = g.loss_part; lw.N = Nr; lw.cap = M;
     float* ray_rgb = rgb_out ? rgb_out : g.ray_rgb;
     if ((e = launch_composite(lw, Nr, ray_rgb, depth_out, nullptr, st)) != hipSuccess) return e;
-    if (meas && (e = launch_depth_stats(g.t, g.delta, g.sig, Nr, S, meas->depth, meas->uncert, meas->opacity, st)) !=
-                    hipSuccess)
+    if (meas && meas->depth &&
+        (e = launch_depth_stats(g.t, g.delta, g.sig, Nr, S, meas->depth, meas->uncert, meas->opacity, st)) != hipSuccess)
         return e;
     if (!(stage_mask & 2)) return hipSuccess;      // forward only
     if ((e = launch_loss_grad(lw, Nr, ray_rgb, target, loss, g.ray_grad, st)) != hipSuccess) return e;

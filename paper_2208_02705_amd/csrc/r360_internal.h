@@ -478,10 +478,17 @@ hipError_t launch_mlp_backward(const r360_scene* s, const Workspace& w, int prec
                                hipStream_t st);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, int64_t step, float lr,
                        float b1, float b2, float eps, hipStream_t st);
-// Optional per-ray Stage I measurement of the global forward (depth over
-// normalised weights, uncertainty, opacity).
+// Optional extras of the global forward: the per-ray Stage I measurement
+// (depth over normalised weights, uncertainty, opacity), or the points mode
+// (one sample per "ray" at t = 0, i.e. at the ray origin, whose density and
+// colour are copied out and nothing is composited).
 struct GlobalMeasure {
-    float *depth, *uncert, *opacity;
+    float* depth = nullptr;
+    float* uncert = nullptr;
+    float* opacity = nullptr;
+    bool points = false;
+    float* point_sigma = nullptr;   // [M]
+    float* point_rgb = nullptr;     // [3][M]
 };
 hipError_t launch_global_step(const r360_global_desc* desc, const float* weights, const float* o, const float* d,
                               int64_t Nr, const float* target, float* loss, float* grad, float* rgb_out,
@@ -494,6 +501,11 @@ int64_t global_params(int w, int c);
 hipError_t launch_depth_stats(const float* t, const float* delta, const float* sigma, int64_t N, int S,
                               float* depth, float* uncert, float* opacity, hipStream_t st);
 size_t occupancy_workspace_bytes(int64_t nvox);
+// Distillation (Eq.7): points as one-sample rays in the one-slot layout, and
+// the per-field averaged squared error with its per-sample gradients.
+hipError_t launch_distill_points(const Workspace& w, int64_t M, const int32_t* field, int F, hipStream_t st);
+hipError_t launch_distill_loss(const Workspace& w, int64_t M, const float* tsig, const float* trgb, float* loss,
+                               hipStream_t st);
 // Stage II field assignment (synchronises the stream once to read the
 // number of occupied voxels) and the uniform block decomposition.
 size_t assign_workspace_bytes(int64_t nvox);

@@ -428,3 +428,24 @@ def occupancy_measurements(n: int, seed: int, d_lo: float = 0.2, d_hi: float = 8
     uncert = (u_max * u[1]).astype(np.float32)
     opacity = np.where(u[2] < p_valid, 1.0, 0.5 * u[3]).astype(np.float32)
     return depth, uncert, opacity
+
+
+def field_points(scene: Scene, per_field: int, seed: int):
+    """Distillation points (input draws only): per field, per_field voxels of
+    that field chosen uniformly with replacement, a uniform position inside
+    each, and a uniform unit view direction. Returns x [3, M], d [3, M],
+    field [M] (int32), grouped by field."""
+    fm = scene.field_map.reshape(-1)
+    order = np.argsort(fm, kind="stable")
+    counts = np.bincount(fm[fm >= 0], minlength=scene.n_fields)
+    starts = np.concatenate([[0], np.cumsum(counts)]) + int((fm < 0).sum())
+    M = per_field * scene.n_fields
+    u = uniform(seed, STREAM_RAYS, np.arange(4 * M, dtype=np.uint64)).reshape(4, M)
+    field = np.repeat(np.arange(scene.n_fields, dtype=np.int32), per_field)
+    pick = starts[field] + np.minimum((u[0] * counts[field]).astype(np.int64), counts[field] - 1)
+    lin = order[pick]
+    n = scene.n
+    ijk = np.stack([lin % n, (lin // n) % n, lin // (n * n)]).astype(np.float64)
+    x = (scene.lo + (ijk + u[1:4]) * scene.voxel).astype(np.float32)
+    d = random_unit_dirs(M, seed + 1)
+    return np.ascontiguousarray(x), d, field
