@@ -31,6 +31,7 @@ FLOP_PER_SAMPLE_TRAIN = 98304        # forward + dW + dX MACs x 2
 # global 8x256 field, per sample and training step: forward 593,408 MACs,
 # weight gradients the same, input gradients 557,696 MACs (none into the encoding)
 FLOP_PER_SAMPLE_GLOBAL = 2 * (593408 + 593408 + 557696)
+FLOP_PER_SAMPLE_GLOBAL_FWD = 2 * 593408
 PEAK = {"bf16": 2500.0, "fp16": 2500.0, "fp32": 157.3}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0
 
@@ -71,7 +72,9 @@ def parse():
     p.add_argument("--no-global", action="store_true")
     p.add_argument("--no-occupancy", action="store_true")
     p.add_argument("--no-assign", action="store_true")
-    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy", "assign"], default=None,
+    p.add_argument("--no-distill", action="store_true")
+    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill"],
+                   default=None,
                    help="time only one leg (for profiler runs)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run a plain device-to-device copy of MIB mebibytes (to calibrate HBM byte counters)")
@@ -136,7 +139,8 @@ def main():
         del r
         return sec, prof
 
-    legs = ["bf16", "fp32", "train", "large", "global", "occupancy", "assign"] if args.only is None else [args.only]
+    legs = (["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill"] if args.only is None
+            else [args.only])
     res = {}
     if "bf16" in legs:
         res["bf16"] = leg("bf16", args.steps, args.warmup)
@@ -161,6 +165,9 @@ def main():
     asg = None
     if "assign" in legs and not args.no_assign:
         asg = assign_leg(R, sc, args)
+    dst = None
+    if "distill" in legs and not args.no_distill:
+        dst = distill_leg(R, sc, scene, args)
 
     main_prec = "bf16" if "bf16" in res else next(iter(res), None)
     line = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -212,6 +219,8 @@ def main():
         line["occupancy_update"] = occl
     if asg is not None:
         line["field_assignment"] = asg
+    if dst is not None:
+        line["distillation"] = dst
     line["context"] = ("paper: 360Roam renders a 1520x760 panorama in 0.03 s on one RTX2080 Ti (about 38.5 Mrays/s, "
                        "precision not stated) and runs in real time on a GTX1080; different hardware and scenes")
     if not args.no_cpu_baseline and args.only is None:
@@ -404,6 +413,39 @@ def assign_leg(R, sc, args):
         _, S = R.assign_fields(occ, s.threshold, n)
         out[name] = {"occupied": S, "fields": n, "ms": sec * 1e3, "mvoxels_per_s": S / sec / 1e6}
     return out
+
+
+def distill_leg(R, sc, scene, args):
+    """Distillation (Eq.7) on the headline scene: 2,048 points in each of its
+    141 fields (288,768 points); the global field's targets at those points
+    (BF16 GEMM chain), then one BF16 step of the local fields (forward, loss,
+    backward with the per-field gradient reduction)."""
+    import torch
+    import synth
+    x, d, field = synth.field_points(sc, 2048, synth.MASTER_SEED)
+    x, d, field = (torch.from_numpy(a).cuda() for a in (x, d, field))
+    M = x.shape[1]
+    gf = R.GlobalField()
+    gw = torch.from_numpy(synth.xavier_weights(synth.global_mlp_layout(), 1, synth.MASTER_SEED,
+                                               synth.STREAM_WEIGHTS)[0]).cuda()
+    steps = max(5, args.steps // 5)
+    box = {}
+
+    def targets():
+        box["t"] = R.global_points(gf, gw, x, d)
+    sec_t = timed(targets, steps, 2)
+    ts, tr = box["t"]
+    grad = torch.empty(scene.n_fields, scene.P, device="cuda")
+    R.profile_read()
+    R.profile_enable(True)
+    sec = timed(lambda: R.distill_step(scene, x, d, field, ts, tr, precision="bf16", grad=grad), steps, 2)
+    prof = R.profile_read()
+    R.profile_enable(False)
+    return {"points": M, "fields": scene.n_fields, "ms_targets": sec_t * 1e3,
+            "targets_tflops": M * FLOP_PER_SAMPLE_GLOBAL_FWD / sec_t / 1e12,
+            "ms_step": sec * 1e3, "mpoints_per_s": M / sec / 1e6,
+            "step_tflops": M * FLOP_PER_SAMPLE_TRAIN / sec / 1e12,
+            "stages_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
 
 
 def cpu_baseline(sc):
