@@ -221,6 +221,12 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     // single panel is kept and the stage ends with a second barrier.)
     constexpr bool DB = sizeof(T) == 2;
     T* const panels = reinterpret_cast<T*>(smem_raw);
+    // 16-bit types also keep the current field's forward and transposed
+    // weight fragments in LDS (72 KB at H = 64, beside the two panels): every
+    // layer of every chunk then reads them at LDS latency instead of going
+    // back to L2. FP32 fragments are twice as large and are read from memory.
+    constexpr bool WL = sizeof(T) == 2;
+    F8* const wlds = reinterpret_cast<F8*>(smem_raw + (DB ? 2 : 1) * BG::ROWS * BG::PSTRIDE * sizeof(T));
     T* panel = panels;
     auto flip = [&]() {
         if constexpr (DB) panel = (panel == panels) ? panels + BG::ROWS * BG::PSTRIDE : panels;
@@ -249,6 +255,14 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
         const int fend = min(end, a.field_start[f + 1]);
         const F8* P = pk + (int64_t)f * G::FRAGS16 * WAVE + lane;
         const F8* PT = pt + (int64_t)f * G::FRAGS_T * WAVE + lane;
+        if constexpr (WL) {
+            __syncthreads();                      // every wave is done with the previous field's fragments
+            const F8* srcP = pk + (int64_t)f * G::FRAGS16 * WAVE;
+            const F8* srcT = pt + (int64_t)f * G::FRAGS_T * WAVE;
+            for (int i = threadIdx.x; i < G::FRAGS16 * WAVE; i += 64 * BW) wlds[i] = srcP[i];
+            for (int i = threadIdx.x; i < G::FRAGS_T * WAVE; i += 64 * BW) wlds[G::FRAGS16 * WAVE + i] = srcT[i];
+            __syncthreads();
+        }
         const f32x4* bias = reinterpret_cast<const f32x4*>(a.bias + (int64_t)f * G::BIAS_FLOATS) + g;
         // Gathered inputs of this lane's sample in the current chunk; the next
         // chunk's are loaded while this chunk is processed (permutation entry
@@ -275,10 +289,21 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             // out of this loop and spill. They are re-read from L1/L2 instead.
             // The scheduling barriers below likewise keep each phase's loads
             // within that phase.
-            const F8* Pc = P;
-            const F8* PTc = PT;
-            asm volatile("" : "+v"(Pc));
-            asm volatile("" : "+v"(PTc));
+            const F8* Pc;
+            const F8* PTc;
+            if constexpr (WL) {
+                // an opaque lane offset (not an opaque pointer), so the reads
+                // stay LDS reads
+                int lo = lane;
+                asm volatile("" : "+v"(lo));
+                Pc = wlds + lo;
+                PTc = wlds + G::FRAGS16 * WAVE + lo;
+            } else {
+                Pc = P;
+                PTc = PT;
+                asm volatile("" : "+v"(Pc));
+                asm volatile("" : "+v"(PTc));
+            }
             const bool valid = c + col < fend;
             const int cn = c + BCH;
             const int spn = cn + col;
@@ -579,9 +604,17 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     a.bias = s->bias;
     a.grad = grad;
     a.part = w.dw_part;
-    const size_t lds = (size_t)(sizeof(T) == 2 ? 2 : 1) * BG::ROWS * BG::PSTRIDE * sizeof(T);
+    using G = PackGeom<H>;
+    const size_t lds = (size_t)(sizeof(T) == 2 ? 2 : 1) * BG::ROWS * BG::PSTRIDE * sizeof(T) +
+                       (sizeof(T) == 2 ? (size_t)(G::FRAGS16 + G::FRAGS_T) * WAVE * 16 : 0);
     static int nb = 0;
-    if (!nb) nb = resident(k_bwd<H, T>, lds);
+    if (!nb) {
+        // more than 64 KB of dynamic LDS must be allowed explicitly
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bwd<H, T>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        nb = resident(k_bwd<H, T>, lds);
+    }
     hipLaunchKernelGGL((k_bwd<H, T>), dim3(nb), dim3(64 * BW), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
