@@ -433,6 +433,185 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
     }
 }
 
+// Weight-resident row GEMM for the forward and input-gradient layers whose
+// B (C <= 272 rows of Kc) fits in LDS: out[r][c] = sum_k A[r][k] B[c][k].
+// One block per CU stages B in LDS once (rows padded to whole 16-row tiles
+// with zeros, row stride Kc + 8 elements so that the 16 rows a fragment read
+// touches fall in distinct banks); each wave then walks 16-row tiles of A on
+// its own, with no block barrier: the tile's operand fragments come straight
+// from memory (lane group q reads the 16-byte piece 8q of each 32-wide k
+// step of its row) and the next tile's are loaded while the current one is
+// computed. The product is formed transposed, out^T = B A^T, so a lane ends
+// with four consecutive output columns of one row; pairs of lane groups
+// swap halves so that each stores eight (16 bytes). Four output tiles are
+// accumulated at a time, so consecutive MFMAs are independent.
+constexpr int RW_WAVES = 16;
+
+// Epilogue of two output tiles (a, b: the accumulators of tiles ta and ta+1
+// for row r). A lane of an even group keeps its four columns of tile ta and
+// takes the next four from its partner group (lane + 16); a lane of an odd
+// group does the same for tile ta+1. Each lane then owns eight consecutive
+// columns (16 bytes) and a row receives 64 contiguous bytes per store.
+template <int EPI>
+__device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, int g4, f32x4 a, f32x4 b,
+                                             int ncols) {
+    const bool odd = g4 & 1;
+    f32x4 send = odd ? a : b, got;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) got[q] = __shfl_xor(send[q], 16, WAVE);
+    float x[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        x[q] = odd ? got[q] : a[q];
+        x[4 + q] = odd ? b[q] : got[q];
+    }
+    const int c0 = 16 * (ta + (odd ? 1 : 0)) + 4 * (g4 & 2);   // first of the lane's eight columns
+    if (r >= g.R) return;
+    if constexpr (EPI == EPI_FWD) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int c = c0 + q;
+            float y = x[q];                                         // the bias is in the accumulator
+            if (g.relu) y = y > 0.0f ? y : 0.0f;
+            if (c == g.sig_col) g.sig[r] = y;
+            x[q] = y;
+        }
+    }
+    if (c0 >= ncols) return;
+    bf16x8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (bf16)x[q];
+    const bool whole = c0 + 8 <= ncols;
+    if constexpr (EPI == EPI_DX) {
+        if (g.mask) {
+            // keep the gradient where the forward activation is > 0 (ReLU)
+            const bf16* mp = g.mask + (int64_t)r * g.ldm + c0;
+            bf16x8 m;
+            if (whole) {
+                m = *reinterpret_cast<const bf16x8*>(mp);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) m[q] = c0 + q < ncols ? mp[q] : (bf16)0.0f;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (!((float)m[q] > 0.0f)) o[q] = (bf16)0.0f;
+        }
+    }
+    bf16* dst = g.out + (int64_t)r * g.ldo + c0;
+    if (whole) {
+        *reinterpret_cast<bf16x8*>(dst) = o;
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (c0 + q < ncols) dst[q] = o[q];
+    }
+}
+
+template <int EPI, int KS>
+__global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) {
+    extern __shared__ __attribute__((aligned(16))) char rw_raw[];
+    bf16* const wsm = reinterpret_cast<bf16*>(rw_raw);
+    constexpr int KP = 32 * KS + 8;                        // LDS row stride (elements)
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    {
+        constexpr int PQ = 4 * KS;                         // 16-byte pieces per row
+        for (int i = tid; i < 16 * CT * PQ; i += 64 * RW_WAVES) {
+            const int c = i / PQ, pq = i % PQ;
+            const u4 v = c < g.C ? *reinterpret_cast<const u4*>(g.B + (int64_t)c * g.b_sr + 8 * pq) : u4{0u, 0u, 0u, 0u};
+            *reinterpret_cast<u4*>(wsm + c * KP + 8 * pq) = v;
+        }
+    }
+    // the forward bias (zero past C) after the weights: each accumulator
+    // starts from its four rows' biases
+    float* const bsm = reinterpret_cast<float*>(wsm + 16 * CT * KP);
+    if constexpr (EPI == EPI_FWD)
+        for (int c = tid; c < 16 * CT; c += 64 * RW_WAVES) bsm[c] = (g.bias && c < g.C) ? g.bias[c] : 0.0f;
+    __syncthreads();
+    const int l16 = lane & 15, g4 = lane >> 4;
+    const int ntile = (g.R + 15) / 16;
+    const int stride = gridDim.x * RW_WAVES;
+    const int ncols = EPI == EPI_FWD ? min(g.C, g.n_out) : g.C;
+    const bf16* wl = wsm + l16 * KP + 8 * g4;              // this lane's fragment origin
+    bf16x8 xa[KS], xb[KS];
+    auto load = [&](bf16x8* x, int tile) {
+        const int row = tile * 16 + l16;
+        const bf16* src = g.A + (int64_t)row * g.a_sr + 8 * g4;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+            x[ks] = row < g.R ? *reinterpret_cast<const bf16x8*>(src + 32 * ks) : bf16x8{};
+    };
+    auto tile_mm = [&](const bf16x8* x, int tile) {
+        const int r = tile * 16 + l16;
+        for (int ot0 = 0; ot0 < CT; ot0 += 4) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ot = ot0 + j < CT ? ot0 + j : CT - 1;
+                if constexpr (EPI == EPI_FWD) acc[j] = *reinterpret_cast<const f32x4*>(bsm + 16 * ot + 4 * g4);
+                else acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ot = ot0 + j < CT ? ot0 + j : CT - 1;   // past the last tile: recompute it, unused
+                    const bf16x8 w = *reinterpret_cast<const bf16x8*>(wl + 16 * ot * KP + 32 * ks);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x[ks], acc[j], 0, 0, 0);
+                }
+            // tiles past CT were computed from a repeated fragment: their
+            // columns lie beyond C and are neither stored nor read
+            rw_epilogue2<EPI>(g, r, ot0, g4, acc[0], acc[1], ncols);
+            if (ot0 + 2 < CT) rw_epilogue2<EPI>(g, r, ot0 + 2, g4, acc[2], acc[3], ncols);
+        }
+    };
+    int t = blockIdx.x * RW_WAVES + wv;
+    if (t < ntile) load(xa, t);
+    // two tiles per round with the fragment buffers alternating, so the
+    // loads in flight are never copied
+    for (; t < ntile; t += 2 * stride) {
+        const int t1 = t + stride;
+        if (t1 < ntile) load(xb, t1);
+        tile_mm(xa, t);
+        if (t1 >= ntile) break;
+        const int t2 = t1 + stride;
+        if (t2 < ntile) load(xa, t2);
+        tile_mm(xb, t1);
+    }
+}
+
+template <int EPI, int KS>
+static hipError_t rowmm_launch(const GemmArgs& a, int CT, size_t lds, hipStream_t st) {
+    static bool attr = false;      // more than 64 KB of dynamic LDS must be allowed explicitly
+    if (!attr) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rowmm<EPI, KS>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const int ntile = (a.R + 15) / 16;
+    const int blocks = std::max(1, std::min(256, (ntile + RW_WAVES - 1) / RW_WAVES));
+    hipLaunchKernelGGL((k_rowmm<EPI, KS>), dim3(blocks), dim3(64 * RW_WAVES), lds, st, a, CT);
+    return hipGetLastError();
+}
+
+// The weight-resident kernel when B fits: returns false if it does not apply.
+template <int EPI>
+static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
+    if (a.Kc % 32 || a.C > 272 || a.R < 1) return false;
+    const int KS = a.Kc / 32, CT = (a.C + 15) / 16;
+    const size_t lds = (size_t)16 * CT * (a.Kc + 8) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
+    if (lds > (size_t)150 * 1024) return false;
+    switch (KS) {
+    case 1: *err = rowmm_launch<EPI, 1>(a, CT, lds, st); return true;
+    case 2: *err = rowmm_launch<EPI, 2>(a, CT, lds, st); return true;
+    case 4: *err = rowmm_launch<EPI, 4>(a, CT, lds, st); return true;
+    case 8: *err = rowmm_launch<EPI, 8>(a, CT, lds, st); return true;
+    case 9: *err = rowmm_launch<EPI, 9>(a, CT, lds, st); return true;
+    default: return false;
+    }
+}
+
 // Weight-gradient GEMM, tile GT x GT over one slice of the samples, DK
 // samples per step. Threads 0..127 load an 8 (samples) x 8 (columns) block
 // of A, threads 128..255 one of B, and transpose it in registers so that each
@@ -650,6 +829,11 @@ static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
             hipLaunchKernelGGL(k_gemm_dw<128>, dim3((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices), dim3(256), lds128,
                                st, a);
         return hipGetLastError();
+    }
+    {
+        hipError_t e = hipSuccess;
+        if (epi == EPI_FWD && rowmm<EPI_FWD>(a, st, &e)) return e;
+        if (epi == EPI_DX && rowmm<EPI_DX>(a, st, &e)) return e;
     }
     // full-width tiles for 256 output columns (each input row is read once); 128 otherwise
     const bool wide = a.C > 128 && a.C <= 256;
