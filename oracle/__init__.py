@@ -54,7 +54,8 @@ class OrcScene(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_float * 3), ("voxel", C.c_float), ("threshold", C.c_float),
                 ("occ", C.c_void_p), ("field", C.c_void_p), ("n_fields", C.c_int32), ("hidden", C.c_int32),
                 ("L_xyz", C.c_int32), ("L_dir", C.c_int32), ("center", C.c_float * 3), ("half_extent", C.c_float),
-                ("weights", C.c_void_p), ("near_", C.c_float), ("far_", C.c_float), ("max_samples", C.c_int32)]
+                ("weights", C.c_void_p), ("near_", C.c_float), ("far_", C.c_float), ("max_samples", C.c_int32),
+                ("samples_per_voxel", C.c_int32)]
 
 
 class OrcGlobal(C.Structure):
@@ -152,6 +153,7 @@ class SceneHandle:
         s.near_ = scene.near if near is None else near
         s.far_ = scene.far if far is None else far
         s.max_samples = scene.max_samples if max_samples is None else max_samples
+        s.samples_per_voxel = getattr(scene, "samples_per_voxel", 1)
         self.s = s
 
     @property

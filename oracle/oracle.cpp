@@ -59,6 +59,7 @@ struct OrcScene {
     const float* weights;  // [n_fields][P] canonical FP32
     float near_, far_;
     int32_t max_samples;
+    int32_t samples_per_voxel; // k >= 1 samples per occupied segment (0 reads as 1)
 };
 
 const double PI = 3.14159265358979323846;
@@ -174,16 +175,27 @@ void walk_ray(const int32_t n[3], const float lo[3], float voxel, float near_, f
     }
 }
 
+// With k samples per occupied segment, the segment is cut at b_j = fma(j,
+// (t_out - t_in) / k, t_in) for 0 < j < k (b_0 = t_in, b_k = t_out) and each
+// piece gives its midpoint (b_j + b_j+1) / 2 with interval b_j+1 - b_j; k = 1
+// is the single midpoint sample.
 int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) {
     const float far_ = ORC_PLANT == 9 ? std::numeric_limits<float>::infinity() : s.far_;
+    const int k = s.samples_per_voxel > 1 ? s.samples_per_voxel : 1;
     int count = 0;
     walk_ray(s.n, s.lo, s.voxel, s.near_, far_, o, d, [&](int64_t lin, float t_in, float t_out) {
         if (s.occ[lin] > s.threshold && s.field[lin] >= 0) {
-            out[count].t_mid = ORC_PLANT == 8 ? t_out : (t_in + t_out) * 0.5f;
-            out[count].delta = t_out - t_in;
-            out[count].voxel = (int32_t)lin;
-            out[count].field = s.field[lin];
-            if (++count == s.max_samples) return false;
+            const float piece = (t_out - t_in) / (float)k;
+            float b0 = t_in;
+            for (int j = 0; j < k; ++j) {
+                const float b1 = j + 1 == k ? t_out : std::fma((float)(j + 1), piece, t_in);
+                out[count].t_mid = ORC_PLANT == 8 ? b1 : (ORC_PLANT == 23 && k > 1 ? b0 : (b0 + b1) * 0.5f);
+                out[count].delta = b1 - b0;
+                out[count].voxel = (int32_t)lin;
+                out[count].field = s.field[lin];
+                b0 = b1;
+                if (++count == s.max_samples) return false;
+            }
         }
         return true;
     });

@@ -177,6 +177,7 @@ class Scene:
     near: float = 0.0
     far: float = float("inf")
     max_samples: int = 32
+    samples_per_voxel: int = 1  # samples per occupied voxel segment
     name: str = ""
     meta: dict = dc_field(default_factory=dict)
 

@@ -33,6 +33,7 @@ PLANTS = {
     20: "assignment: the remainder voxels all go to the last field",
     21: "distillation: each field's term averaged over all points instead of its own",
     22: "distillation: density term left out of the gradient",
+    23: "samples per voxel: pieces sampled at their start instead of their middle",
 }
 
 

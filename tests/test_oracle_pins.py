@@ -946,3 +946,53 @@ def test_global_points_constant_field(orc):
     sig, _ = orc.global_points(w, x, d, width=16, color_width=8)
     z = x[2].astype(np.float64) / 4.0
     assert np.allclose(sig, 0.75 + np.maximum(z, 0.0), atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# Several samples per occupied voxel (a renderer variant of Sec. 4.2's dense
+# sampling of the occupied voxels)
+# ---------------------------------------------------------------------------
+
+def test_samples_per_voxel_axis_ray(orc):
+    sc = synth.tiny_scene(8, 5, p_occ=1.0, max_samples=64)
+    sc.samples_per_voxel = 4
+    o = np.array([[-3.9], [0.1], [0.2]], np.float32)
+    d = np.array([[1.0], [0.0], [0.0]], np.float32)
+    smp = orc.sample_rays(sc, o, d)
+    assert smp["counts"][0] == 32
+    # full voxels [t, t + 1) of unit length: quarter pieces, midpoints at
+    # t + 1/8, 3/8, 5/8, 7/8 exactly
+    t_mid, dl = smp["t_mid"][4:].reshape(7, 4), smp["delta"][4:].reshape(7, 4)
+    t_in = np.float32(0.9) + np.arange(7, dtype=np.float32)
+    assert np.all(dl == np.float32(0.25))
+    for q, frac in enumerate((0.125, 0.375, 0.625, 0.875)):
+        assert np.allclose(t_mid[:, q], t_in + frac, rtol=0, atol=2e-7)
+    assert list(smp["voxel"][::4]) == [i + 8 * (4 + 8 * 4) for i in range(8)]
+    # one sample per voxel is the midpoint rule, unchanged
+    sc.samples_per_voxel = 1
+    one = orc.sample_rays(sc, o, d)
+    assert np.array_equal(one["t_mid"], orc.sample_rays(synth.tiny_scene(8, 5, p_occ=1.0, max_samples=64), o, d)["t_mid"])
+
+
+def test_samples_per_voxel_lengths_and_cap(orc):
+    sc = synth.tiny_scene(8, 7, p_occ=0.5, max_samples=256)
+    rng = np.random.default_rng(7)
+    N = 200
+    o = rng.uniform(-3.5, 3.5, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    base = orc.sample_rays(sc, o, d)
+    sc.samples_per_voxel = 3
+    three = orc.sample_rays(sc, o, d)
+    assert np.array_equal(three["counts"], 3 * base["counts"])
+    # the pieces of each voxel tile its segment: lengths add up, midpoints
+    # increase inside it
+    dl = three["delta"].reshape(-1, 3).astype(np.float64)
+    assert np.allclose(dl.sum(axis=1), base["delta"], rtol=1e-6, atol=1e-7)
+    tm = three["t_mid"].reshape(-1, 3)
+    assert np.all(np.diff(tm, axis=1) > 0)
+    lo = base["t_mid"] - 0.5 * base["delta"]; hi = base["t_mid"] + 0.5 * base["delta"]
+    assert np.all((tm >= lo[:, None] - 1e-6) & (tm <= hi[:, None] + 1e-6))
+    # the cap counts pieces: a voxel may be cut off part-way
+    sc.max_samples = 5
+    capped = orc.sample_rays(sc, o, d)
+    assert np.array_equal(capped["counts"], np.minimum(three["counts"], 5))
