@@ -86,12 +86,18 @@ typedef struct {
 
 /* Per-call options. Samples lie in [near, far] along unit-length d;
  * far may be +inf. At most max_samples occupied-voxel samples per ray,
- * nearest first. `precision` is an r360_precision. */
+ * nearest first. `precision` is an r360_precision. samples_per_voxel k in
+ * [0, 64] (0 reads as 1): each occupied segment [t_in, t_out) is cut at
+ * b_j = fma(j, (t_out - t_in) / k, t_in), 0 < j < k (b_0 = t_in, b_k =
+ * t_out), and every piece gives a sample t_mid = (b_j + b_j+1) / 2, delta =
+ * b_j+1 - b_j (FP32, as written); k = 1 is the single midpoint sample. The
+ * pieces count against max_samples. */
 typedef struct {
     float near_;
     float far_;
     int32_t max_samples;
     int32_t precision;
+    int32_t samples_per_voxel;
 } r360_render_opts;
 
 typedef struct r360_scene r360_scene;
@@ -148,7 +154,8 @@ size_t r360_workspace_bytes(const r360_scene* scene, int64_t n_rays, int32_t max
  * Sec. 5 ray casting): per ray, traverse the voxels between
  * t0 = max(near, box entry) and t1 = min(far, box exit) in FP32 and emit one
  * sample per occupied voxel segment of positive length: t_mid = (t_in +
- * t_out) / 2, delta = t_out - t_in, nearest max_samples first. Outputs in
+ * t_out) / 2, delta = t_out - t_in (or samples_per_voxel pieces of it),
+ * nearest max_samples first. Outputs in
  * ray-major order; caller arrays hold N * max_samples entries; voxel may be
  * NULL. ray_offset [N+1] (int32) gets the exclusive prefix of per-ray counts.
  * If n_samples_host is not NULL the call waits for the stream and stores the

@@ -76,6 +76,7 @@ int64_t field_params(int h, int Lx, int Ld) {
 r360_status check_opts(const r360_render_opts* o, bool allow_fp64) {
     if (!o) return inval("opts is NULL");
     if (o->max_samples < 1 || o->max_samples > 256) return inval("max_samples outside [1, 256]");
+    if (o->samples_per_voxel < 0 || o->samples_per_voxel > 64) return inval("samples_per_voxel outside [0, 64]");
     if (std::isnan(o->near_) || std::isnan(o->far_)) return inval("near/far is NaN");
     if (o->precision < R360_FP32 || o->precision > R360_FP64_GRADCHECK) return inval("unknown precision");
     if (o->precision == R360_FP64_GRADCHECK && !allow_fp64) {
@@ -138,6 +139,7 @@ DdaParams dda_params(const r360_scene* s, const r360_render_opts* o) {
     p.near_ = o->near_;
     p.far_ = o->far_;
     p.max_samples = o->max_samples;
+    p.spv = o->samples_per_voxel > 1 ? o->samples_per_voxel : 1;
     return p;
 }
 

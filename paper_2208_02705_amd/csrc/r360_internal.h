@@ -449,6 +449,7 @@ struct DdaParams {
     float voxel, inv_voxel;
     float near_, far_;
     int max_samples;
+    int spv;              // samples per occupied segment (>= 1)
 };
 DdaParams dda_params(const r360_scene* s, const r360_render_opts* opts);
 

@@ -85,7 +85,9 @@ struct SlotSink {
     }
 };
 
-template <class Sink>
+// MULTI: several samples per occupied segment (P.spv > 1); the single-sample
+// form is a separate instantiation with the plain midpoint emission.
+template <class Sink, bool MULTI>
 __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], Sink& sink) {
     const float INF = __builtin_inff();
     const int n[3] = {P.n0, P.n1, P.n2};
@@ -175,8 +177,23 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         nxt = labels[more ? lin_next : lin];                                         \
         __builtin_amdgcn_sched_barrier(0);                                           \
         if (t_out > t_in && cur < 0x8000) {                                          \
-            sink.emit(count, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin);    \
-            if (++count == P.max_samples) break;                                     \
+            if constexpr (!MULTI) {                                                  \
+                sink.emit(count, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin);\
+                if (++count == P.max_samples) break;                                 \
+            } else {                                                                 \
+                /* P.spv pieces cut at fma(j, length / k, t_in) */                   \
+                const float piece = (t_out - t_in) / (float)P.spv;                   \
+                float b0 = t_in;                                                     \
+                bool full = false;                                                   \
+                for (int q = 0; q < P.spv; ++q) {                                    \
+                    const float b1 = q + 1 == P.spv ? t_out                          \
+                                                    : __builtin_fmaf((float)(q + 1), piece, t_in); \
+                    sink.emit(count, (b0 + b1) * 0.5f, b1 - b0, (int)cur, lin);      \
+                    b0 = b1;                                                         \
+                    if (++count == P.max_samples) { full = true; break; }            \
+                }                                                                    \
+                if (full) break;                                                     \
+            }                                                                        \
         }                                                                            \
         if (!more) break;                                                            \
         t_in = mx(t_in, tna);                                                        \
@@ -217,7 +234,7 @@ struct Staging {
     float* t; float* dl; int32_t* fld; int32_t* vox;
 };
 
-template <int MODE>
+template <int MODE, bool MULTI>
 __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64_t N, int32_t* __restrict__ cnt,
                                                float* __restrict__ o_ws, float* __restrict__ d_ws, Staging sg) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -229,7 +246,7 @@ __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64
         for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
     }
     SlotSink sink{(int)(r & ~int64_t(63)) * P.max_samples + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox};
-    cnt[r] = traverse(P, o, d, sink);
+    cnt[r] = traverse<SlotSink, MULTI>(P, o, d, sink);
 }
 
 // Pass 2 (after the scan): compaction. The 64 rays of a wave own one
@@ -406,19 +423,34 @@ hipError_t launch_rays(const RaySource& src, int64_t N, float* o, float* d, hipS
     return hipGetLastError();
 }
 
+// The traversal kernel for the ray source and the samples-per-voxel form.
+static hipError_t trace_any(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, const Staging& sg,
+                     unsigned nb, hipStream_t st) {
+    if (p.spv > 1) {
+        if (src.mode == RAYS_EQUIRECT)
+            hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, true>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+        else if (src.mode == RAYS_PINHOLE)
+            hipLaunchKernelGGL((k_trace<RAYS_PINHOLE, true>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+        else
+            hipLaunchKernelGGL((k_trace<RAYS_GIVEN, true>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+    } else {
+        if (src.mode == RAYS_EQUIRECT)
+            hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, false>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+        else if (src.mode == RAYS_PINHOLE)
+            hipLaunchKernelGGL((k_trace<RAYS_PINHOLE, false>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+        else
+            hipLaunchKernelGGL((k_trace<RAYS_GIVEN, false>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w,
                          int32_t* voxel_out, hipStream_t st) {
     const unsigned nb = blocks_for(N, 256);
     // staging slots live in the sigma/rgb arrays, which are not needed until the field MLPs run
     const Staging sg{w.sigma, w.rgb, reinterpret_cast<int32_t*>(w.rgb + w.cap),
                      voxel_out ? reinterpret_cast<int32_t*>(w.rgb + 2 * w.cap) : nullptr};
-    if (src.mode == RAYS_EQUIRECT)
-        hipLaunchKernelGGL(k_trace<RAYS_EQUIRECT>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
-    else if (src.mode == RAYS_PINHOLE)
-        hipLaunchKernelGGL(k_trace<RAYS_PINHOLE>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
-    else
-        hipLaunchKernelGGL(k_trace<RAYS_GIVEN>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
-    hipError_t e = hipGetLastError();
+    hipError_t e = trace_any(src, p, N, w, sg, nb, st);
     if (e != hipSuccess) return e;
     const unsigned ns = blocks_for(N, SCAN_TILE);
     hipLaunchKernelGGL(k_scan_reduce, dim3(ns), dim3(1024), 0, st, w.ray_off, N, w.scan);
@@ -434,13 +466,7 @@ hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, co
 hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, hipStream_t st) {
     const unsigned nb = blocks_for(N, 256);
     const Staging sg{w.t_mid, w.delta, w.field, nullptr};
-    if (src.mode == RAYS_EQUIRECT)
-        hipLaunchKernelGGL(k_trace<RAYS_EQUIRECT>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
-    else if (src.mode == RAYS_PINHOLE)
-        hipLaunchKernelGGL(k_trace<RAYS_PINHOLE>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
-    else
-        hipLaunchKernelGGL(k_trace<RAYS_GIVEN>, dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
-    return hipGetLastError();
+    return trace_any(src, p, N, w, sg, nb, st);
 }
 
 hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64_t nvox, int n_fields,

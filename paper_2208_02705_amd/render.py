@@ -42,9 +42,10 @@ def precision_code(p) -> int:
     return _lib.PRECISIONS[p] if isinstance(p, str) else int(p)
 
 
-def make_opts(near: float, far: float, max_samples: int, precision) -> _lib.RenderOpts:
+def make_opts(near: float, far: float, max_samples: int, precision, samples_per_voxel: int = 1) -> _lib.RenderOpts:
     o = _lib.RenderOpts()
     o.near_, o.far_, o.max_samples, o.precision = near, far, max_samples, precision_code(precision)
+    o.samples_per_voxel = samples_per_voxel
     return o
 
 
@@ -82,6 +83,7 @@ class Scene:
         self.grid, self.mlp = g, m
         self.n_fields, self.hidden, self.P = n_fields, hidden, weights.shape[1]
         self.device = occ.device
+        self.samples_per_voxel = 1          # samples per occupied voxel segment (render options)
         self._ws: Optional[torch.Tensor] = None
 
     @classmethod
@@ -93,6 +95,7 @@ class Scene:
         s = cls(occ, fm, w, lo=(sc.lo,) * 3, voxel=sc.voxel, threshold=sc.threshold, hidden=sc.hidden,
                 center=sc.center, half_extent=sc.half_extent)
         s.near, s.far, s.max_samples = sc.near, sc.far, sc.max_samples
+        s.samples_per_voxel = getattr(sc, "samples_per_voxel", 1)
         torch.cuda.current_stream().synchronize()
         return s
 
@@ -156,7 +159,8 @@ class Equirect:
 
 def _opts(scene: Scene, near, far, max_samples, precision):
     return make_opts(scene.near if near is None else near, scene.far if far is None else far,
-                     scene.max_samples if max_samples is None else max_samples, precision)
+                     scene.max_samples if max_samples is None else max_samples, precision,
+                     getattr(scene, "samples_per_voxel", 1))
 
 
 def sample_rays(scene: Scene, o: torch.Tensor, d: torch.Tensor, *, near=None, far=None, max_samples=None,

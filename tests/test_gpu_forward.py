@@ -275,3 +275,44 @@ def test_render_deterministic(R, room):
     a = _np(R.render_equirect(scene, 512, 256, synth.IDENTITY_C2W, precision="bf16")[0])
     b = _np(R.render_equirect(scene, 512, 256, synth.IDENTITY_C2W, precision="bf16")[0])
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+# ---------------------------------------------------------------------------
+# Several samples per occupied voxel
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("spv", [2, 3, 5])
+def test_samples_per_voxel_bitexact(R, orc, spv):
+    sc = synth.tiny_scene(8, 23, p_occ=0.6, n_fields=5, max_samples=64)
+    sc.samples_per_voxel = spv
+    scene = R.Scene.from_synth(sc)
+    o, d = _random_rays(3001, 23, -6, 6)
+    ref = orc.sample_rays(sc, o, d)
+    _both_paths(R, scene, o, d, ref)
+    # the cap cuts part-way through a voxel's pieces
+    _both_paths(R, scene, o, d, orc.sample_rays(sc, o, d, max_samples=7), max_samples=7)
+    scene.close()
+
+
+def test_samples_per_voxel_render(R, orc):
+    """Three samples per occupied voxel on the small configuration: the
+    render (slot-layout path) against the oracle in FP32 and BF16, and the
+    headline view's sampling bit for bit."""
+    sc = synth.scene_small()
+    sc.samples_per_voxel = 3
+    sc.max_samples = 96
+    scene = R.Scene.from_synth(sc)
+    o, d = orc.equirect_rays(256, 128, synth.IDENTITY_C2W)
+    ref_rgb, ref_depth, ref_op = orc.render_rays(sc, o, d)
+    rgb, depth, op = R.render_rays(scene, _t(o), _t(d), precision="fp32")
+    _check_fp32(_np(rgb), ref_rgb)
+    _check_fp32(_np(depth), ref_depth)
+    rgb, _, _ = R.render_rays(scene, _t(o), _t(d), precision="bf16")
+    _check_x16(_np(rgb), ref_rgb)
+    scene.close()
+    room = synth.scene_room()
+    room.samples_per_voxel = 2
+    rscene = R.Scene.from_synth(room)
+    o, d = orc.equirect_rays(1024, 512, synth.IDENTITY_C2W)
+    _both_paths(R, rscene, o, d, orc.sample_rays(room, o, d))
+    rscene.close()
