@@ -86,6 +86,7 @@ def lib():
             "orc_equirect_lut": (None, [C.c_int, C.c_int, vp, vp, vp, vp]),
             "orc_equirect_rays": (None, [C.c_int, C.c_int, vp, vp, i64, vp, vp]),
             "orc_pinhole_rays": (None, [C.c_int, C.c_int, f32, f32, vp, i64, i64, vp, vp]),
+            "orc_ods_rays": (None, [C.c_int, C.c_int, vp, f32, vp, i64, vp, vp]),
             "orc_count_samples": (None, [vp, i64, vp, vp, vp, C.c_int]),
             "orc_sample_rays": (None, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_encode": (None, [vp, C.c_int, vp]),
@@ -184,6 +185,16 @@ def equirect_rays(W: int, H: int, c2w: np.ndarray, pix: Optional[np.ndarray] = N
         pp = _p(pix)
     o = np.empty((3, N), np.float32); d = np.empty((3, N), np.float32)
     lib().orc_equirect_rays(W, H, _p(c2w), pp, N, _p(o), _p(d))
+    return o, d
+
+
+def ods_rays(W: int, H: int, c2w: np.ndarray, eye: float, pix: Optional[np.ndarray] = None):
+    """Omni-directional stereo rays of one eye (eye = signed half inter-pupillary distance)."""
+    c2w = _c(c2w, np.float32)
+    N = W * H if pix is None else len(pix)
+    pix_a = None if pix is None else _c(pix, np.int64)
+    o = np.empty((3, N), np.float32); d = np.empty((3, N), np.float32)
+    lib().orc_ods_rays(W, H, _p(c2w), eye, None if pix_a is None else _p(pix_a), N, _p(o), _p(d))
     return o, d
 
 

@@ -565,6 +565,32 @@ void orc_equirect_rays(int W, int H, const float* c2w, const int64_t* pix, int64
     }
 }
 
+// Omni-directional stereo (the stereoscopic mode of Sec. 5 for panoramas):
+// the ray of pixel (u, v) keeps its equirect direction but starts on the
+// viewing circle of radius |eye| around the camera centre, at the point
+// perpendicular to its horizontal heading: in the camera frame the origin
+// offset is (eye cos(phi), 0, -eye sin(phi)) (eye > 0: the right eye, which
+// sits at +x when looking along +z), rotated to the world as
+//   o_i = t_i + fma(R_i2, oz, fma(R_i1, oy, R_i0 * ox)).
+// eye = 0 gives the equirect rays exactly.
+void orc_ods_rays(int W, int H, const float* c2w, float eye, const int64_t* pix, int64_t N, float* o, float* d) {
+    for (int64_t r = 0; r < N; ++r) {
+        int64_t p = pix ? pix[r] : r;
+        int u = (int)(p % W), v = (int)(p / W);
+        float sphi, cphi, sth, cth;
+        equirect_trig(W, H, u, v, &sphi, &cphi, &sth, &cth);
+        float dc[3] = {cth * sphi, -sth, cth * cphi};
+        float oc[3] = {ORC_PLANT == 24 ? eye * sphi : eye * cphi, 0.0f, ORC_PLANT == 24 ? eye * cphi : -(eye * sphi)};
+        float oo[3], dd[3];
+        to_world(c2w, dc, oo, dd);
+        for (int a = 0; a < 3; ++a) {
+            const float* R = c2w + 4 * a;
+            if (eye != 0.0f) oo[a] = R[3] + std::fma(R[2], oc[2], std::fma(R[1], oc[1], R[0] * oc[0]));
+            o[a * N + r] = oo[a]; d[a * N + r] = dd[a];
+        }
+    }
+}
+
 // Pinhole rays (perspective viewports): x = ((u + 1/2) - W/2) / fx,
 // y = ((v + 1/2) - H/2) / fy, z = 1, normalised with a correctly rounded
 // sqrt of fma(x, x, fma(y, y, 1)); then to the world frame.

@@ -34,6 +34,7 @@ PLANTS = {
     21: "distillation: each field's term averaged over all points instead of its own",
     22: "distillation: density term left out of the gradient",
     23: "samples per voxel: pieces sampled at their start instead of their middle",
+    24: "stereo rays: eye offset along the heading instead of across it",
 }
 
 

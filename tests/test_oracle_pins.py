@@ -996,3 +996,32 @@ def test_samples_per_voxel_lengths_and_cap(orc):
     sc.max_samples = 5
     capped = orc.sample_rays(sc, o, d)
     assert np.array_equal(capped["counts"], np.minimum(three["counts"], 5))
+
+
+# ---------------------------------------------------------------------------
+# Omni-directional stereo rays (stereoscopic mode, Sec. 5)
+# ---------------------------------------------------------------------------
+
+def test_ods_rays_geometry(orc):
+    W, H, eye = 65, 32, np.float32(0.032)
+    mono_o, mono_d = orc.equirect_rays(W, H, synth.IDENTITY_C2W)
+    o0, d0 = orc.ods_rays(W, H, synth.IDENTITY_C2W, 0.0)
+    assert np.array_equal(o0, mono_o) and np.array_equal(d0, mono_d)
+    oR, dR = orc.ods_rays(W, H, synth.IDENTITY_C2W, eye)
+    oL, dL = orc.ods_rays(W, H, synth.IDENTITY_C2W, -eye)
+    assert np.array_equal(dR, mono_d) and np.array_equal(dL, mono_d)
+    assert np.array_equal(oL, -oR)                              # the two eyes mirror through the centre
+    off = oR.astype(np.float64)
+    assert np.allclose(np.linalg.norm(off, axis=0), eye, rtol=1e-6)
+    assert np.all(off[1] == 0)                                  # on the horizontal viewing circle
+    # perpendicular to the ray's horizontal heading
+    assert np.abs(off[0] * mono_d[0] + off[2] * mono_d[2]).max() < 1e-7
+    # looking along +z (the centre column of an odd width) the right eye sits at +x
+    mid = (H // 2) * W + W // 2
+    assert abs(mono_d[0, mid]) < 1e-7 and mono_d[2, mid] > 0.99
+    assert abs(off[0, mid] - eye) < 1e-9 and abs(off[2, mid]) < 1e-9
+    # a camera moved and turned a quarter: the offsets turn with it
+    c2w = synth.c2w_yaw((1.0, 2.0, 3.0), 1)
+    o1, _ = orc.ods_rays(W, H, c2w, eye)
+    R = c2w.reshape(3, 4)[:, :3].astype(np.float64)
+    assert np.allclose(o1.astype(np.float64) - np.array([[1.0], [2.0], [3.0]]), R @ off, atol=1e-6)
