@@ -146,6 +146,16 @@ r360_status r360_equirect_tables(const r360_equirect* eq, float* sin_phi_host, f
 r360_status r360_equirect_rays(const r360_equirect* eq, const float c2w_host[12], const int64_t* pix, int64_t N,
                                float* o, float* d, void* stream);
 
+/* Omni-directional stereo (the stereoscopic mode of Sec. 5, for panoramas):
+ * the rays of one eye. Directions as r360_equirect_rays; the origin of pixel
+ * (u, v) lies on the viewing circle of radius |eye_offset| around the camera
+ * centre, across the ray's horizontal heading: camera-frame offset
+ * (eye_offset cos(phi), 0, -eye_offset sin(phi)), world o_i = t_i +
+ * fma(R_i2, oz, fma(R_i1, oy, R_i0 ox)). eye_offset = +ipd/2 for the right
+ * eye, -ipd/2 for the left; 0 gives r360_equirect_rays exactly. */
+r360_status r360_ods_rays(const r360_equirect* eq, const float c2w_host[12], float eye_offset, const int64_t* pix,
+                          int64_t N, float* o, float* d, void* stream);
+
 /* Workspace bytes for r360_render_* / r360_sample_rays / r360_backward over
  * N rays with the given max_samples (the capacity is N * max_samples). */
 size_t r360_workspace_bytes(const r360_scene* scene, int64_t n_rays, int32_t max_samples);
@@ -178,6 +188,12 @@ r360_status r360_render_rays(const r360_scene* scene, const float* o, const floa
 r360_status r360_render_equirect(const r360_scene* scene, const r360_equirect* eq, const float c2w_host[12],
                                  const r360_render_opts* opts, float* rgb, float* depth, float* opacity,
                                  void* ws, size_t ws_bytes, void* stream);
+
+/* Render one eye of an omni-directional stereo pair (rays as r360_ods_rays);
+ * otherwise as r360_render_equirect. */
+r360_status r360_render_ods(const r360_scene* scene, const r360_equirect* eq, const float c2w_host[12],
+                            float eye_offset, const r360_render_opts* opts, float* rgb, float* depth,
+                            float* opacity, void* ws, size_t ws_bytes, void* stream);
 
 /* Render a pinhole viewport: d_cam = (x, y, 1)/|.| with x = ((u + 1/2) - W/2)/fx,
  * y = ((v + 1/2) - H/2)/fy (correctly rounded sqrt of fma(x,x,fma(y,y,1))). */

@@ -65,6 +65,8 @@ SIGNATURES = {
     "r360_equirect_destroy": (None, [vp]),
     "r360_equirect_tables": (i32, [vp, vp, vp, vp, vp]),
     "r360_equirect_rays": (i32, [vp, F12, vp, i64, vp, vp, vp]),
+    "r360_ods_rays": (i32, [vp, F12, f32, vp, i64, vp, vp, vp]),
+    "r360_render_ods": (i32, [vp, vp, F12, f32, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),
     "r360_workspace_bytes": (sz, [vp, i64, i32]),
     "r360_sample_rays": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), C.POINTER(i64), vp, vp, vp, vp, vp, vp, vp, sz, vp]),
     "r360_render_rays": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),

@@ -367,6 +367,25 @@ r360_status r360_equirect_rays(const r360_equirect* eq, const float c2w_host[12]
     return R360_OK;
 }
 
+r360_status r360_ods_rays(const r360_equirect* eq, const float c2w_host[12], float eye_offset, const int64_t* pix,
+                          int64_t N, float* o, float* d, void* stream) {
+    if (!eq || !o || !d) return inval("NULL pointer");
+    if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
+    if (!std::isfinite(eye_offset)) return inval("eye_offset not finite");
+    if (N <= 0) return inval("N must be positive");
+    if (!pix && N != (int64_t)eq->W * eq->H) return inval("without a pixel list N must be W*H");
+    RaySource src{};
+    src.mode = RAYS_EQUIRECT;
+    src.tables = eq->tables;
+    src.W = eq->W;
+    src.H = eq->H;
+    std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    src.pix = pix;
+    src.eye = eye_offset;
+    R360_TRY("ods_rays", launch_rays(src, N, o, d, S(stream)));
+    return R360_OK;
+}
+
 size_t r360_workspace_bytes(const r360_scene* s, int64_t n_rays, int32_t max_samples) {
     if (!s || n_rays <= 0 || max_samples < 1) return 0;
     return carve(nullptr, n_rays, max_samples, s->mlp.n_fields, s->P).bytes;
@@ -428,6 +447,26 @@ r360_status r360_render_equirect(const r360_scene* s, const r360_equirect* eq, c
     src.W = eq->W;
     src.H = eq->H;
     std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    return render_common(s, src, N, opts, rgb, depth, opacity, w, S(stream));
+}
+
+r360_status r360_render_ods(const r360_scene* s, const r360_equirect* eq, const float c2w_host[12], float eye_offset,
+                            const r360_render_opts* opts, float* rgb, float* depth, float* opacity, void* ws,
+                            size_t ws_bytes, void* stream) {
+    if (!eq || !rgb || !depth || !opacity) return inval("NULL pointer");
+    if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
+    if (!std::isfinite(eye_offset)) return inval("eye_offset not finite");
+    const int64_t N = (int64_t)eq->W * eq->H;
+    Workspace w;
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    if (st != R360_OK) return st;
+    RaySource src{};
+    src.mode = RAYS_EQUIRECT;
+    src.tables = eq->tables;
+    src.W = eq->W;
+    src.H = eq->H;
+    std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    src.eye = eye_offset;
     return render_common(s, src, N, opts, rgb, depth, opacity, w, S(stream));
 }
 

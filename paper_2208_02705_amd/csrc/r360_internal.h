@@ -441,6 +441,7 @@ struct RaySource {
     float fx, fy;         // RAYS_PINHOLE
     float c2w[12];
     const int64_t* pix;   // optional pixel list (equirect)
+    float eye;            // equirect: signed half eye distance (stereo), 0 for one centre
 };
 struct DdaParams {
     const int16_t* labels;

@@ -35,6 +35,8 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
         return;
     } else {
         float dc[3];
+        float oc0 = 0.0f, oc2 = 0.0f;   // stereo eye offset in the camera frame (equirect only)
+        bool eye = false;
         if constexpr (MODE == RAYS_EQUIRECT) {
             const int64_t p = s.pix ? s.pix[r] : r;
             if (p < 0 || p >= (int64_t)s.W * s.H) {   // out-of-range pixel: a NaN ray that samples nothing
@@ -45,6 +47,11 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
             const float sphi = s.tables[u], cphi = s.tables[s.W + u];
             const float sth = s.tables[2 * s.W + v], cth = s.tables[2 * s.W + s.H + v];
             dc[0] = cth * sphi; dc[1] = -sth; dc[2] = cth * cphi;
+            if (s.eye != 0.0f) {      // omni-directional stereo: origin on the viewing circle, across the heading
+                eye = true;
+                oc0 = s.eye * cphi;
+                oc2 = -(s.eye * sphi);
+            }
         } else {
             const int u = (int)(r % s.W), v = (int)(r / s.W);
             const float x = ((float)u + 0.5f - 0.5f * (float)s.W) / s.fx;
@@ -56,7 +63,7 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
         for (int i = 0; i < 3; ++i) {
             const float* R = s.c2w + 4 * i;
             d[i] = __builtin_fmaf(R[2], dc[2], __builtin_fmaf(R[1], dc[1], R[0] * dc[0]));
-            o[i] = R[3];
+            o[i] = eye ? R[3] + __builtin_fmaf(R[2], oc2, __builtin_fmaf(R[1], 0.0f, R[0] * oc0)) : R[3];
         }
     }
 }

@@ -136,13 +136,18 @@ class Equirect:
         check(lib().r360_equirect_tables(self._h, sp.ctypes.data, cp.ctypes.data, st.ctypes.data, ct.ctypes.data))
         return sp, cp, st, ct
 
-    def rays(self, c2w, pix: Optional[torch.Tensor] = None, device="cuda"):
+    def rays(self, c2w, pix: Optional[torch.Tensor] = None, device="cuda", eye: float = 0.0):
+        """Rays [3, N] of the given pixels (all in raster order without a list);
+        eye != 0: one eye of an omni-directional stereo pair (signed half eye distance)."""
         N = self.W * self.H if pix is None else pix.numel()
         if pix is not None:
             pix = _dev(pix, torch.int64, "pix")
         o = torch.empty(3, N, dtype=torch.float32, device=device)
         d = torch.empty(3, N, dtype=torch.float32, device=device)
-        check(lib().r360_equirect_rays(self._h, _lib.c2w_arg(c2w), _ptr(pix), N, _ptr(o), _ptr(d), _stream()))
+        if eye:
+            check(lib().r360_ods_rays(self._h, _lib.c2w_arg(c2w), eye, _ptr(pix), N, _ptr(o), _ptr(d), _stream()))
+        else:
+            check(lib().r360_equirect_rays(self._h, _lib.c2w_arg(c2w), _ptr(pix), N, _ptr(o), _ptr(d), _stream()))
         return o, d
 
     def close(self):
@@ -216,10 +221,16 @@ class EquirectRenderer:
         self.depth = torch.empty(H, W, dtype=torch.float32, device=dev)
         self.opacity = torch.empty(H, W, dtype=torch.float32, device=dev)
 
-    def __call__(self, c2w):
-        check(lib().r360_render_equirect(self.scene._h, self.eq._h, _lib.c2w_arg(c2w), C.byref(self.opts),
-                                         _ptr(self.rgb), _ptr(self.depth), _ptr(self.opacity), _ptr(self.ws),
-                                         self.ws.numel(), _stream()))
+    def __call__(self, c2w, eye: float = 0.0):
+        """One view; eye != 0 renders that eye of an omni-directional stereo pair."""
+        if eye:
+            check(lib().r360_render_ods(self.scene._h, self.eq._h, _lib.c2w_arg(c2w), eye, C.byref(self.opts),
+                                        _ptr(self.rgb), _ptr(self.depth), _ptr(self.opacity), _ptr(self.ws),
+                                        self.ws.numel(), _stream()))
+        else:
+            check(lib().r360_render_equirect(self.scene._h, self.eq._h, _lib.c2w_arg(c2w), C.byref(self.opts),
+                                             _ptr(self.rgb), _ptr(self.depth), _ptr(self.opacity), _ptr(self.ws),
+                                             self.ws.numel(), _stream()))
         return self.rgb, self.depth, self.opacity
 
 
@@ -227,6 +238,17 @@ def render_equirect(scene: Scene, W: int, H: int, c2w, **kw):
     r = EquirectRenderer(scene, W, H, **kw)
     rgb, depth, opac = r(c2w)
     return rgb.clone(), depth.clone(), opac.clone()
+
+
+def render_stereo(scene: Scene, W: int, H: int, c2w, ipd: float = 0.064, **kw):
+    """Omni-directional stereo pair ((rgb, depth, opacity) of the left eye,
+    then of the right) with the eyes ipd apart (Sec. 5's stereoscopic mode)."""
+    r = EquirectRenderer(scene, W, H, **kw)
+    out = []
+    for eye in (-0.5 * ipd, 0.5 * ipd):
+        rgb, depth, opac = r(c2w, eye=eye)
+        out.append((rgb.clone(), depth.clone(), opac.clone()))
+    return tuple(out)
 
 
 class PinholeRenderer:

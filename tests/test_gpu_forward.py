@@ -316,3 +316,33 @@ def test_samples_per_voxel_render(R, orc):
     o, d = orc.equirect_rays(1024, 512, synth.IDENTITY_C2W)
     _both_paths(R, rscene, o, d, orc.sample_rays(room, o, d))
     rscene.close()
+
+
+# ---------------------------------------------------------------------------
+# Omni-directional stereo (stereoscopic mode)
+# ---------------------------------------------------------------------------
+
+def test_ods_rays_bitwise(R, orc):
+    eq = R.Equirect(2048, 1024)
+    for eye, c2w in ((0.032, synth.IDENTITY_C2W), (-0.032, synth.c2w_yaw((0.5, -0.25, 1.0), 3)), (0.0, synth.IDENTITY_C2W)):
+        o, d = eq.rays(c2w, eye=eye)
+        ro, rd = orc.ods_rays(2048, 1024, c2w, eye)
+        assert np.array_equal(_np(o).view(np.uint32), ro.view(np.uint32))
+        assert np.array_equal(_np(d).view(np.uint32), rd.view(np.uint32))
+    pix = np.array([0, 5, 2048 * 1024 - 1, 777777], np.int64)
+    o, d = eq.rays(synth.IDENTITY_C2W, pix=_t(pix), eye=0.05)
+    ro, rd = orc.ods_rays(2048, 1024, synth.IDENTITY_C2W, 0.05, pix)
+    assert np.array_equal(_np(o), ro) and np.array_equal(_np(d), rd)
+
+
+def test_stereo_render_matches_oracle(R, orc, room):
+    """Both eyes of a 256 x 128 pair from the room scene's centre (FP32),
+    against the oracle's render of the oracle's stereo rays."""
+    sc, scene = room
+    left, right = R.render_stereo(scene, 256, 128, synth.IDENTITY_C2W, ipd=0.064, precision="fp32")
+    for (rgb, depth, _), eye in ((left, -0.032), (right, 0.032)):
+        o, d = orc.ods_rays(256, 128, synth.IDENTITY_C2W, eye)
+        ref_rgb, ref_depth, _ = orc.render_rays(sc, o, d, threads=None)
+        _check_fp32(_np(rgb).reshape(3, -1), ref_rgb)
+        _check_fp32(_np(depth).reshape(-1), ref_depth)
+    assert not np.array_equal(_np(left[0]), _np(right[0]))
