@@ -55,7 +55,7 @@ class OrcScene(C.Structure):
                 ("occ", C.c_void_p), ("field", C.c_void_p), ("n_fields", C.c_int32), ("hidden", C.c_int32),
                 ("L_xyz", C.c_int32), ("L_dir", C.c_int32), ("center", C.c_float * 3), ("half_extent", C.c_float),
                 ("weights", C.c_void_p), ("near_", C.c_float), ("far_", C.c_float), ("max_samples", C.c_int32),
-                ("samples_per_voxel", C.c_int32)]
+                ("samples_per_voxel", C.c_int32), ("frames", C.c_void_p)]
 
 
 class OrcGlobal(C.Structure):
@@ -87,6 +87,7 @@ def lib():
             "orc_equirect_rays": (None, [C.c_int, C.c_int, vp, vp, i64, vp, vp]),
             "orc_pinhole_rays": (None, [C.c_int, C.c_int, f32, f32, vp, i64, i64, vp, vp]),
             "orc_ods_rays": (None, [C.c_int, C.c_int, vp, f32, vp, i64, vp, vp]),
+            "orc_field_frames": (None, [vp, vp, f32, vp, i32, vp]),
             "orc_count_samples": (None, [vp, i64, vp, vp, vp, C.c_int]),
             "orc_sample_rays": (None, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_encode": (None, [vp, C.c_int, vp]),
@@ -155,6 +156,9 @@ class SceneHandle:
         s.far_ = scene.far if far is None else far
         s.max_samples = scene.max_samples if max_samples is None else max_samples
         s.samples_per_voxel = getattr(scene, "samples_per_voxel", 1)
+        fr = getattr(scene, "frames", None)
+        self.frames = None if fr is None else _c(fr, np.float32)
+        s.frames = None if self.frames is None else self.frames.ctypes.data
         self.s = s
 
     @property
@@ -461,3 +465,14 @@ def global_points(weights, x, d, width=256, color_width=128, L_xyz=10, L_dir=4, 
     sig = np.empty(M); rgb = np.empty((3, M))
     lib().orc_global_points(C.byref(g), M, _p(x), _p(d), _p(sig), _p(rgb), threads or default_threads())
     return sig, rgb
+
+
+# ---- per-field encoding frames -----------------------------------------------
+def field_frames(field_map: np.ndarray, lo, voxel: float, n_fields: int) -> np.ndarray:
+    """[n_fields, 4] FP32: the box centre (3) and half extent of each field's voxels."""
+    fm = _c(field_map, np.int32)
+    n = (C.c_int32 * 3)(fm.shape[2], fm.shape[1], fm.shape[0])
+    lo3 = (C.c_float * 3)(*([lo] * 3 if np.ndim(lo) == 0 else list(lo)))
+    out = np.empty((n_fields, 4), np.float32)
+    lib().orc_field_frames(n, lo3, voxel, _p(fm), n_fields, _p(out))
+    return out

@@ -60,6 +60,7 @@ struct OrcScene {
     float near_, far_;
     int32_t max_samples;
     int32_t samples_per_voxel; // k >= 1 samples per occupied segment (0 reads as 1)
+    const float* frames;       // optional [n_fields][4]: per-field encoding centre (3) and half extent
 };
 
 const double PI = 3.14159265358979323846;
@@ -204,11 +205,15 @@ int sample_ray(const OrcScene& s, const float o[3], const float d[3], Seg* out) 
 
 // Encoding input: p = fma(t_mid, d, o), xhat = (p - center) * (1 / half_extent)
 // in FP32, then widened exactly.
-void sample_position(const OrcScene& s, const float o[3], const float d[3], float t_mid, double xh[3]) {
-    const float inv_h = 1.0f / s.half_extent;
+// With per-field frames, field f uses its own centre c_f and half extent h_f:
+// xhat = (p - c_f) * (1 / h_f).
+void sample_position(const OrcScene& s, const float o[3], const float d[3], float t_mid, int field, double xh[3]) {
+    const bool own = s.frames && ORC_PLANT != 25;
+    const float* c = own ? s.frames + 4 * field : s.center;
+    const float inv_h = 1.0f / (own ? s.frames[4 * field + 3] : s.half_extent);
     for (int a = 0; a < 3; ++a) {
         float p = std::fma(t_mid, d[a], o[a]);
-        xh[a] = (double)((p - s.center[a]) * inv_h);
+        xh[a] = (double)((p - c[a]) * inv_h);
     }
 }
 
@@ -637,6 +642,43 @@ void orc_sample_rays(const OrcScene* s, int64_t N, const float* o, const float* 
     });
 }
 
+// ---- per-field encoding frames ----------------------------------------------
+// Axis-aligned box of the voxels labelled f in field_map: per axis the
+// smallest and largest voxel index, box_lo = fma(imin, voxel, lo), box_hi =
+// fma(imax + 1, voxel, lo); centre (box_lo + box_hi) * 0.5, half extent the
+// largest of (box_hi - box_lo) * 0.5 over the axes (FP32). A field with no
+// voxel gets centre 0 and half extent 1. frames [F][4].
+void orc_field_frames(const int32_t* n, const float* lo, float voxel, const int32_t* field_map, int32_t F,
+                      float* frames) {
+    std::vector<int> mn(3 * (size_t)F, std::numeric_limits<int>::max()), mx(3 * (size_t)F, -1);
+    for (int z = 0; z < n[2]; ++z)
+        for (int y = 0; y < n[1]; ++y)
+            for (int x = 0; x < n[0]; ++x) {
+                const int f = field_map[x + (int64_t)n[0] * (y + (int64_t)n[1] * z)];
+                if (f < 0 || f >= F) continue;
+                const int idx[3] = {x, y, z};
+                for (int a = 0; a < 3; ++a) {
+                    mn[3 * f + a] = std::min(mn[3 * f + a], idx[a]);
+                    mx[3 * f + a] = std::max(mx[3 * f + a], idx[a]);
+                }
+            }
+    for (int f = 0; f < F; ++f) {
+        if (mx[3 * f] < 0) {
+            frames[4 * f] = frames[4 * f + 1] = frames[4 * f + 2] = 0.0f;
+            frames[4 * f + 3] = 1.0f;
+            continue;
+        }
+        float h = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            const float blo = std::fma((float)mn[3 * f + a], voxel, lo[a]);
+            const float bhi = std::fma((float)(mx[3 * f + a] + 1), voxel, lo[a]);
+            frames[4 * f + a] = (blo + bhi) * 0.5f;
+            h = std::max(h, (bhi - blo) * 0.5f);
+        }
+        frames[4 * f + 3] = h;
+    }
+}
+
 // ---- encoding / MLP / compositing building blocks (for pins) ---------------
 void orc_encode(const double* x, int L, double* out) { encode(x, L, out); }
 
@@ -679,7 +721,7 @@ void orc_render_rays(const OrcScene* s, int64_t N, const float* o, const float* 
             double dir[3] = {dv[0], dv[1], dv[2]};
             for (int k = 0; k < n; ++k) {
                 double xh[3];
-                sample_position(*s, oo, dv, segs[k].t_mid, xh);
+                sample_position(*s, oo, dv, segs[k].t_mid, segs[k].field, xh);
                 LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
                 local_forward(net, xh, dir, s->L_xyz, s->L_dir, a);
                 sig[k] = a.sigma;
@@ -709,7 +751,7 @@ void orc_sample_outputs(const OrcScene* s, int64_t N, const float* o, const floa
             double dir[3] = {dv[0], dv[1], dv[2]};
             for (int k = 0; k < n; ++k) {
                 double xh[3];
-                sample_position(*s, oo, dv, segs[k].t_mid, xh);
+                sample_position(*s, oo, dv, segs[k].t_mid, segs[k].field, xh);
                 LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
                 local_forward(net, xh, dir, s->L_xyz, s->L_dir, a);
                 int64_t j = offsets[r] + k;
@@ -743,7 +785,7 @@ double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float*
             double dir[3] = {dv[0], dv[1], dv[2]};
             for (int k = 0; k < n; ++k) {
                 double xh[3];
-                sample_position(*s, oo, dv, segs[k].t_mid, xh);
+                sample_position(*s, oo, dv, segs[k].t_mid, segs[k].field, xh);
                 LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
                 local_forward(net, xh, dir, s->L_xyz, s->L_dir, acts[k]);
                 sig[k] = acts[k].sigma;
@@ -805,7 +847,7 @@ double orc_distill(const OrcScene* s, int64_t M, const float* x, const float* di
             if (k < 0 || k >= s->n_fields) continue;
             float oo[3] = {x[i], x[M + i], x[2 * M + i]}, dv[3] = {dir[i], dir[M + i], dir[2 * M + i]};
             double xh[3], dd3[3] = {dv[0], dv[1], dv[2]};
-            sample_position(*s, oo, dv, 0.0f, xh);
+            sample_position(*s, oo, dv, 0.0f, k, xh);
             LocalNet net = local_view(wd.data() + P * k, s->hidden, dx, dd);
             local_forward(net, xh, dd3, s->L_xyz, s->L_dir, a);
             const double inv = ORC_PLANT == 21 ? 1.0 / (double)M : 1.0 / (double)I[k];

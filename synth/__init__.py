@@ -178,6 +178,7 @@ class Scene:
     far: float = float("inf")
     max_samples: int = 32
     samples_per_voxel: int = 1  # samples per occupied voxel segment
+    frames: Optional[np.ndarray] = None   # per-field encoding frames [n_fields, 4] (centre, half extent)
     name: str = ""
     meta: dict = dc_field(default_factory=dict)
 

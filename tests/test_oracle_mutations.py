@@ -35,6 +35,7 @@ PLANTS = {
     22: "distillation: density term left out of the gradient",
     23: "samples per voxel: pieces sampled at their start instead of their middle",
     24: "stereo rays: eye offset along the heading instead of across it",
+    25: "per-field frames ignored: every field encoded in the scene frame",
 }
 
 

@@ -1025,3 +1025,56 @@ def test_ods_rays_geometry(orc):
     o1, _ = orc.ods_rays(W, H, c2w, eye)
     R = c2w.reshape(3, 4)[:, :3].astype(np.float64)
     assert np.allclose(o1.astype(np.float64) - np.array([[1.0], [2.0], [3.0]]), R @ off, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Per-field encoding frames (a renderer variant: each field encodes its box)
+# ---------------------------------------------------------------------------
+
+def test_field_frames_boxes(orc):
+    fm = np.full((8, 8, 8), -1, np.int32)
+    fm[0:4, 1, 2:6] = 0                      # z 0..3, y 1, x 2..5
+    fm[7, 7, 7] = 2                          # a single voxel; field 1 is empty
+    fr = orc.field_frames(fm, -4.0, 1.0, 3)
+    assert np.array_equal(fr[0], np.float32([0.0, -2.5, -2.0, 2.0]))
+    assert np.array_equal(fr[1], np.float32([0.0, 0.0, 0.0, 1.0]))
+    assert np.array_equal(fr[2], np.float32([3.5, 3.5, 3.5, 0.5]))
+    # random maps against the index extremes found by numpy
+    rng = np.random.default_rng(3)
+    fm = rng.integers(-1, 5, size=(6, 7, 9)).astype(np.int32)
+    fr = orc.field_frames(fm, (-1.0, -2.0, -0.5), 0.25, 5)
+    for f in range(5):
+        z, y, x = np.nonzero(fm == f)
+        lo = np.array([-1.0, -2.0, -0.5]) + 0.25 * np.array([x.min(), y.min(), z.min()])
+        hi = np.array([-1.0, -2.0, -0.5]) + 0.25 * (np.array([x.max(), y.max(), z.max()]) + 1)
+        assert np.allclose(fr[f, :3], (lo + hi) / 2, atol=1e-7) and abs(fr[f, 3] - ((hi - lo) / 2).max()) < 1e-7
+
+
+def test_field_frames_reach_the_encoding(orc):
+    """A field wired to output softplus(relu(xhat_x)) shows which frame
+    encodes its points."""
+    sc = synth.tiny_scene(4, 9, p_occ=1.0, n_fields=2, hidden=8)
+    lay = synth.local_mlp_layout(8)
+    w = np.zeros((2, synth.n_params(lay)), np.float32)
+    for k in range(2):
+        t = synth.unpack(lay, w[k])
+        t["W1"][0, 0] = 1.0; t["W2"][0, 0] = 1.0; t["ws"][0, 0] = 1.0
+    x = np.array([[1.5, 3.0, -2.0], [0.25, 0.5, 0.75], [0.0, 1.0, 2.0]], np.float32)
+    d = np.tile(np.float32([[0.0], [0.0], [1.0]]), (1, 3))
+    field = np.array([0, 1, 1], np.int32)
+    ts = np.zeros(3, np.float32); tr = np.zeros((3, 3), np.float32)
+    _, _, sig, _ = orc.distill(sc, x, d, field, ts, tr, weights=w)
+    want = [sp(max(0.0, float(v) / 4.0)) for v in x[0]]        # the scene frame: centre 0, half extent 4
+    assert np.allclose(sig, want, atol=1e-12)
+    sc.frames = np.array([[1.0, 0.0, 0.0, 0.25], [2.0, 0.0, 0.0, 2.0]], np.float32)
+    _, _, sig, _ = orc.distill(sc, x, d, field, ts, tr, weights=w)
+    want = [sp(max(0.0, (1.5 - 1.0) * 4.0)), sp(max(0.0, (3.0 - 2.0) * 0.5)), sp(0.0)]
+    assert np.allclose(sig, want, atol=1e-12)
+    # frames equal to the scene's reproduce the scene-wide encoding exactly
+    sc.frames = np.array([[0.0, 0.0, 0.0, 4.0]] * 2, np.float32)
+    w2 = sc.weights
+    o, dd = orc.equirect_rays(32, 16, synth.IDENTITY_C2W)
+    a = orc.render_rays(sc, o, dd)
+    sc.frames = None
+    b = orc.render_rays(sc, o, dd)
+    assert all(np.array_equal(p, q) for p, q in zip(a, b)) and w2 is sc.weights
