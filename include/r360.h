@@ -359,6 +359,23 @@ r360_status r360_distill_step(const r360_scene* scene, const float* x, const flo
                               const r360_render_opts* opts, float* loss, float* grad_weights, void* ws,
                               size_t ws_bytes, void* stream);
 
+/* Per-field encoding frames (a renderer variant: each local field encodes
+ * its own region). r360_field_frames computes, for each field f of
+ * field_map [n2][n1][n0] (device int32, grid as `grid`), the box of its
+ * voxels: per axis box_lo = fma(imin, voxel, lo), box_hi = fma(imax + 1,
+ * voxel, lo); centers [F][3] = (box_lo + box_hi) * 0.5 and half_extents [F]
+ * the largest (box_hi - box_lo) * 0.5 over the axes (FP32); a field without
+ * voxels gets centre 0 and half extent 1. Workspace:
+ * r360_field_frames_workspace_bytes(F). r360_scene_set_frames makes every
+ * later render, training, distillation and gradient-check call encode a
+ * sample of field f as xhat = (p - c_f) * (1 / h_f) (centers [F][3],
+ * half_extents [F] > 0, device); NULL centers restores the scene-wide frame
+ * of r360_mlp_desc. The scene keeps its own copy. */
+size_t r360_field_frames_workspace_bytes(int32_t n_fields);
+r360_status r360_field_frames(const r360_grid_desc* grid, const int32_t* field_map, int32_t n_fields, float* centers,
+                              float* half_extents, void* ws, size_t ws_bytes, void* stream);
+r360_status r360_scene_set_frames(r360_scene* scene, const float* centers, const float* half_extents, void* stream);
+
 /* Stage II of Alg.1 (Sec. 4.2): adaptive field assignment. Occupied voxels
  * are those with occ > threshold (FP32 compare), S of them; field k (0 <= k <
  * n_fields) receives floor(S / n_fields) + (k < S mod n_fields) voxels. For k

@@ -61,6 +61,9 @@ SIGNATURES = {
     "r360_scene_set_weights": (i32, [vp, vp, vp]),
     "r360_scene_set_grid": (i32, [vp, vp, vp, vp]),
     "r360_scene_destroy": (None, [vp]),
+    "r360_field_frames_workspace_bytes": (sz, [i32]),
+    "r360_field_frames": (i32, [C.POINTER(GridDesc), vp, i32, vp, vp, vp, sz, vp]),
+    "r360_scene_set_frames": (i32, [vp, vp, vp, vp]),
     "r360_equirect_create": (i32, [i32, i32, C.POINTER(vp)]),
     "r360_equirect_destroy": (None, [vp]),
     "r360_equirect_tables": (i32, [vp, vp, vp, vp, vp]),

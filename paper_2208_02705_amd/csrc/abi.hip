@@ -279,8 +279,48 @@ r360_status r360_scene_set_grid(r360_scene* s, const float* occ_prob, const int3
     return R360_OK;
 }
 
+size_t r360_field_frames_workspace_bytes(int32_t n_fields) {
+    if (n_fields < 1) return 0;
+    return ((size_t)6 * n_fields * sizeof(int32_t) + 255) & ~size_t(255);
+}
+
+r360_status r360_field_frames(const r360_grid_desc* grid, const int32_t* field_map, int32_t n_fields, float* centers,
+                              float* half_extents, void* ws, size_t ws_bytes, void* stream) {
+    if (!grid || !field_map || !centers || !half_extents || !ws) return inval("NULL pointer");
+    if (n_fields < 1) return inval("n_fields must be >= 1");
+    for (int a = 0; a < 3; ++a) {
+        if (grid->n[a] < 1 || grid->n[a] > 4096) return inval("grid size outside [1, 4096]");
+        if (!std::isfinite(grid->lo[a])) return inval("grid corner not finite");
+    }
+    if ((int64_t)grid->n[0] * grid->n[1] * grid->n[2] >= (int64_t(1) << 31)) return inval("grid has 2^31 voxels or more");
+    if (!pow2(grid->voxel)) return inval("voxel edge must be a positive power of two");
+    if (ws_bytes < r360_field_frames_workspace_bytes(n_fields)) return R360_EWORKSPACE;
+    R360_TRY("field frames", launch_field_frames(grid, field_map, n_fields, centers, half_extents, ws, S(stream)));
+    return R360_OK;
+}
+
+r360_status r360_scene_set_frames(r360_scene* s, const float* centers, const float* half_extents, void* stream) {
+    if (!s) return inval("scene is NULL");
+    if (!centers) {
+        s->use_frames = false;
+        return R360_OK;
+    }
+    if (!half_extents) return inval("NULL pointer");
+    const int F = s->mlp.n_fields;
+    if (!s->frames) {
+        if (hipMalloc(reinterpret_cast<void**>(&s->frames), (size_t)F * 4 * sizeof(float)) != hipSuccess) {
+            s->frames = nullptr;
+            return R360_ENOMEM;
+        }
+    }
+    R360_TRY("set frames", launch_pack_frames(centers, half_extents, F, s->frames, S(stream)));
+    s->use_frames = true;
+    return R360_OK;
+}
+
 void r360_scene_destroy(r360_scene* s) {
     if (!s) return;
+    (void)hipFree(s->frames);
     (void)hipFree(s->labels);
     (void)hipFree(s->pack16_bf);
     (void)hipFree(s->pack16_h);

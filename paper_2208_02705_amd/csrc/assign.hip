@@ -310,6 +310,63 @@ __global__ __launch_bounds__(256) void k_uni_label(UniArgs a) {
         a.fmap[v] = a.occ[v] > a.thr ? a.flag[block_of(a, v)] : -1;
 }
 
+// ---- per-field encoding frames ----------------------------------------------
+// Box of the voxels labelled f: per axis the extreme voxel indices (atomic
+// min / max, order-independent), box_lo = fma(imin, voxel, lo), box_hi =
+// fma(imax + 1, voxel, lo), centre (box_lo + box_hi) * 0.5, half extent the
+// largest (box_hi - box_lo) * 0.5 over the axes; a field without voxels gets
+// centre 0 and half extent 1.
+__global__ __launch_bounds__(256) void k_ff_init(int32_t* __restrict__ mm, int F) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 6 * F) mm[i] = i < 3 * F ? 0x7fffffff : -1;
+}
+
+__global__ __launch_bounds__(256) void k_ff_scan(const int32_t* __restrict__ fmap, int n0, int n1, int64_t nvox, int F,
+                                                 int32_t* __restrict__ mm) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * blockDim.x) {
+        const int f = fmap[v];
+        if (f < 0 || f >= F) continue;
+        const int idx[3] = {(int)(v % n0), (int)((v / n0) % n1), (int)(v / ((int64_t)n0 * n1))};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            atomicMin(mm + 3 * f + a, idx[a]);
+            atomicMax(mm + 3 * F + 3 * f + a, idx[a]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ff_final(const int32_t* __restrict__ mm, int F, float lo0, float lo1, float lo2,
+                                                  float voxel, float* __restrict__ centers, float* __restrict__ halves) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    if (mm[3 * F + 3 * f] < 0) {
+        centers[3 * f] = centers[3 * f + 1] = centers[3 * f + 2] = 0.0f;
+        halves[f] = 1.0f;
+        return;
+    }
+    const float lo[3] = {lo0, lo1, lo2};
+    float h = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float blo = __builtin_fmaf((float)mm[3 * f + a], voxel, lo[a]);
+        const float bhi = __builtin_fmaf((float)(mm[3 * F + 3 * f + a] + 1), voxel, lo[a]);
+        centers[3 * f + a] = (blo + bhi) * 0.5f;
+        const float ha = (bhi - blo) * 0.5f;
+        h = h < ha ? ha : h;
+    }
+    halves[f] = h;
+}
+
+__global__ __launch_bounds__(256) void k_pack_frames(const float* __restrict__ centers, const float* __restrict__ halves,
+                                                     int F, float* __restrict__ frames) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    frames[4 * f] = centers[3 * f];
+    frames[4 * f + 1] = centers[3 * f + 1];
+    frames[4 * f + 2] = centers[3 * f + 2];
+    frames[4 * f + 3] = 1.0f / halves[f];
+}
+
 unsigned grid_for(int64_t n, int64_t cap = 2048) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap));
 }
@@ -360,6 +417,22 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_field_frames(const r360_grid_desc* g, const int32_t* fmap, int F, float* centers, float* halves,
+                               void* ws, hipStream_t st) {
+    int32_t* mm = static_cast<int32_t*>(ws);
+    const int64_t nvox = (int64_t)g->n[0] * g->n[1] * g->n[2];
+    hipLaunchKernelGGL(k_ff_init, dim3((6 * F + 255) / 256), dim3(256), 0, st, mm, F);
+    hipLaunchKernelGGL(k_ff_scan, dim3(grid_for(nvox)), dim3(256), 0, st, fmap, g->n[0], g->n[1], nvox, F, mm);
+    hipLaunchKernelGGL(k_ff_final, dim3((F + 255) / 256), dim3(256), 0, st, mm, F, g->lo[0], g->lo[1], g->lo[2], g->voxel,
+                       centers, halves);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_frames(const float* centers, const float* halves, int F, float* frames, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_frames, dim3((F + 255) / 256), dim3(256), 0, st, centers, halves, F, frames);
+    return hipGetLastError();
 }
 
 hipError_t launch_assign_uniform(const int32_t n[3], const float* occ, float thr, const int32_t b[3], int32_t* fmap,

@@ -138,6 +138,7 @@ struct BwdArgs {
     int F;
     int P;
     float c0, c1, c2, inv_h;
+    const float* frames;         // [F][4] per-field (centre, 1 / half extent), or null: the scene's frame
     const void* pack;           // forward fragments in the K = 32 layout, element type T
     const void* packT;          // transposed fragments
     const float* bias;
@@ -244,8 +245,6 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     const int last = find_field(a.field_start, a.F, end - 1);
     const F8* pk = reinterpret_cast<const F8*>(a.pack);
     const F8* pt = reinterpret_cast<const F8*>(a.packT);
-    const float cc[3] = {a.c0, a.c1, a.c2};
-
     f32x4 w1[N1], w2[N2], wh[NH], w3[N3], w4[N4];
     auto zero = [](f32x4* v, int n) { for (int q = 0; q < n; ++q) v[q] = f32x4{0.f, 0.f, 0.f, 0.f}; };
     zero(w1, N1); zero(w2, N2); zero(wh, NH); zero(w3, N3); zero(w4, N4);
@@ -253,6 +252,10 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     for (int pos = beg; pos < end;) {
         const int f = find_field(a.field_start, a.F, pos);
         const int fend = min(end, a.field_start[f + 1]);
+        // the encoding frame of this field
+        const float cc[3] = {a.frames ? a.frames[4 * f] : a.c0, a.frames ? a.frames[4 * f + 1] : a.c1,
+                             a.frames ? a.frames[4 * f + 2] : a.c2};
+        const float inv_h = a.frames ? a.frames[4 * f + 3] : a.inv_h;
         const F8* P = pk + (int64_t)f * G::FRAGS16 * WAVE + lane;
         const F8* PT = pt + (int64_t)f * G::FRAGS_T * WAVE + lane;
         if constexpr (WL) {
@@ -278,7 +281,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 dv[k] = ld32(a.d[k], r);
-                xh[k] = (__builtin_fmaf(t, dv[k], ld32(a.o[k], r)) - cc[k]) * a.inv_h;
+                xh[k] = (__builtin_fmaf(t, dv[k], ld32(a.o[k], r)) - cc[k]) * inv_h;
                 grgb[k] = ld32(a.drgb[k], u);
             }
             gsig = ld32(a.dsigma, u);
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             for (int k = 0; k < 3; ++k) {
                 dv[k] = d_n[k];
                 grgb[k] = grgb_n[k];
-                xh[k] = (__builtin_fmaf(t_n, d_n[k], o_n[k]) - cc[k]) * a.inv_h;
+                xh[k] = (__builtin_fmaf(t_n, d_n[k], o_n[k]) - cc[k]) * inv_h;
             }
         }
         // flush this field's tiles
@@ -600,6 +603,7 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     a.P = (int)s->P;
     a.c0 = s->mlp.center[0]; a.c1 = s->mlp.center[1]; a.c2 = s->mlp.center[2];
     a.inv_h = 1.0f / s->mlp.half_extent;
+    a.frames = s->use_frames ? s->frames : nullptr;
     a.pack = pack; a.packT = packT;
     a.bias = s->bias;
     a.grad = grad;
@@ -654,6 +658,7 @@ struct GcArgs {
     const float* d;
     int64_t N;
     float c0, c1, c2, inv_h;
+    const float* frames;         // [F][4] per-field (centre, 1 / half extent), or null: the scene's frame
     const double* w;
     int P;
     const double* grad_rgb;    // [3][N] (backward)
@@ -726,11 +731,14 @@ __device__ double sigmoid_d(double z) { return 1.0 / (1.0 + exp(-z)); }
 template <int H>
 __device__ void gc_inputs(const GcArgs& a, int64_t r, int j, double xh[3], double dd[3]) {
     const float t = a.t_mid[j];
-    const float cc[3] = {a.c0, a.c1, a.c2};
+    const int f = a.field[j];
+    const float cc[3] = {a.frames ? a.frames[4 * f] : a.c0, a.frames ? a.frames[4 * f + 1] : a.c1,
+                         a.frames ? a.frames[4 * f + 2] : a.c2};
+    const float inv_h = a.frames ? a.frames[4 * f + 3] : a.inv_h;
     for (int k = 0; k < 3; ++k) {
         const float dk = a.d[k * a.N + r];
         const float p = __builtin_fmaf(t, dk, a.o[k * a.N + r]);
-        xh[k] = (double)((p - cc[k]) * a.inv_h);
+        xh[k] = (double)((p - cc[k]) * inv_h);
         dd[k] = (double)dk;
     }
 }
@@ -890,6 +898,7 @@ GcArgs gc_args(const r360_scene* s, const Workspace& w, const double* w64) {
     a.N = w.N;
     a.c0 = s->mlp.center[0]; a.c1 = s->mlp.center[1]; a.c2 = s->mlp.center[2];
     a.inv_h = 1.0f / s->mlp.half_extent;
+    a.frames = s->use_frames ? s->frames : nullptr;
     a.w = w64;
     a.P = (int)s->P;
     a.grad_rgb = nullptr;

@@ -96,6 +96,7 @@ struct FwdArgs {
     int64_t N, cap;
     int F;
     float c0, c1, c2, inv_h;
+    const float* frames;         // [F][4] per-field (centre, 1 / half extent), or null: the scene's frame
     const void* pack;            // [F][FRAGS16][64] fragments of the chosen element type
     const float* bias;
     float* sigma;
@@ -135,10 +136,13 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
     const int per = (((S + nb - 1) / nb) + BCHK - 1) / BCHK * BCHK;
     const int beg = min(S, b * per), end = min(S, beg + per);
     const F8* pk = reinterpret_cast<const F8*>(a.pack);
-    const float cc[3] = {a.c0, a.c1, a.c2};
     for (int pos = beg; pos < end;) {
         const int f = find_field(a.field_start, a.F, pos);
         const int fend = min(end, a.field_start[f + 1]);
+        // the encoding frame of this field
+        const float cc[3] = {a.frames ? a.frames[4 * f] : a.c0, a.frames ? a.frames[4 * f + 1] : a.c1,
+                             a.frames ? a.frames[4 * f + 2] : a.c2};
+        const float inv_h = a.frames ? a.frames[4 * f + 3] : a.inv_h;
         __syncthreads();                               // the previous field's fragments are no longer read
         const F8* src = pk + (int64_t)f * FR * WAVE;
         for (int i = threadIdx.x; i < FR * WAVE; i += 64 * FWD_WAVES) lw[i] = src[i];
@@ -171,7 +175,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 dv[n][k] = ld32(a.d[k], r);
-                xh[n][k] = (__builtin_fmaf(t, dv[n][k], ld32(a.o[k], r)) - cc[k]) * a.inv_h;
+                xh[n][k] = (__builtin_fmaf(t, dv[n][k], ld32(a.o[k], r)) - cc[k]) * inv_h;
             }
         }
         for (; c < fend; c += BCHK) {   // no iterations when this wave has no chunk here
@@ -332,7 +336,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     dv[n][k] = d_n[n][k];
-                    xh[n][k] = (__builtin_fmaf(t_n[n], d_n[n][k], o_n[n][k]) - cc[k]) * a.inv_h;
+                    xh[n][k] = (__builtin_fmaf(t_n[n], d_n[n][k], o_n[n][k]) - cc[k]) * inv_h;
                 }
             }
         }
@@ -375,6 +379,7 @@ hipError_t fwd_h(const r360_scene* s, const Workspace& w, int precision, hipStre
     a.F = s->mlp.n_fields;
     a.c0 = s->mlp.center[0]; a.c1 = s->mlp.center[1]; a.c2 = s->mlp.center[2];
     a.inv_h = 1.0f / s->mlp.half_extent;
+    a.frames = s->use_frames ? s->frames : nullptr;
     a.bias = s->bias;
     a.sigma = w.sigma; a.rgb0 = w.rgb; a.rgb1 = w.rgb + w.cap; a.rgb2 = w.rgb + 2 * w.cap;
     if (precision == R360_BF16) { a.pack = s->pack16_bf; return fwd_launch<H, __bf16>(a, st); }

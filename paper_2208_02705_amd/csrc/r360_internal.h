@@ -350,6 +350,8 @@ struct r360_scene {
     void* packT_bf;          // [F][FRAGS_T][64][8] bf16 transposed fragments (backward)
     void* packT_h;           // [F][FRAGS_T][64][8] f16
     float* packT_f;          // [F][FRAGS_T][64][8] f32
+    float* frames;           // [F][4] per-field encoding frame (centre, 1 / half extent), or null
+    bool use_frames;         // encode each field in its own frame
     int device;
 };
 
@@ -511,6 +513,11 @@ hipError_t launch_distill_loss(const Workspace& w, int64_t M, const float* tsig,
 // Stage II field assignment (synchronises the stream once to read the
 // number of occupied voxels) and the uniform block decomposition.
 size_t assign_workspace_bytes(int64_t nvox);
+// Per-field encoding frames: the box of each field's voxels, and the packed
+// (centre, 1 / half extent) table the field kernels read.
+hipError_t launch_field_frames(const r360_grid_desc* g, const int32_t* fmap, int F, float* centers, float* halves,
+                               void* ws, hipStream_t st);
+hipError_t launch_pack_frames(const float* centers, const float* halves, int F, float* frames, hipStream_t st);
 size_t uniform_workspace_bytes(int64_t nblocks);
 hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr, int32_t n_fields, int32_t* fmap,
                                 int64_t* S_out, void* ws, hipStream_t st);

@@ -10,6 +10,7 @@ import ctypes as C
 import math
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -96,8 +97,22 @@ class Scene:
                 center=sc.center, half_extent=sc.half_extent)
         s.near, s.far, s.max_samples = sc.near, sc.far, sc.max_samples
         s.samples_per_voxel = getattr(sc, "samples_per_voxel", 1)
+        fr = getattr(sc, "frames", None)
+        if fr is not None:
+            fr = torch.from_numpy(np.ascontiguousarray(fr, dtype=np.float32)).to(device)
+            s.set_frames(fr[:, :3].contiguous(), fr[:, 3].contiguous())
         torch.cuda.current_stream().synchronize()
         return s
+
+    def set_frames(self, centers: Optional[torch.Tensor], half_extents: Optional[torch.Tensor] = None):
+        """Per-field encoding frames (centers [F, 3], half_extents [F]); None
+        restores the scene-wide frame."""
+        if centers is None:
+            check(lib().r360_scene_set_frames(self._h, None, None, _stream()))
+            return
+        centers = _dev(centers, torch.float32, "centers")
+        half_extents = _dev(half_extents, torch.float32, "half_extents")
+        check(lib().r360_scene_set_frames(self._h, _ptr(centers), _ptr(half_extents), _stream()))
 
     def set_weights(self, weights: torch.Tensor):
         check(lib().r360_scene_set_weights(self._h, _ptr(_dev(weights, torch.float32, "weights")), _stream()))
@@ -160,6 +175,22 @@ class Equirect:
             self.close()
         except Exception:
             pass
+
+
+def field_frames(field_map: torch.Tensor, n_fields: int, *, lo=(-4.0, -4.0, -4.0), voxel: float = 0.25):
+    """(centers [F, 3], half_extents [F]): the box of each field's voxels."""
+    field_map = _dev(field_map, torch.int32, "field_map")
+    g = _lib.GridDesc()
+    g.n[:] = [field_map.shape[2], field_map.shape[1], field_map.shape[0]]
+    g.lo[:] = list(lo) if isinstance(lo, Sequence) else [lo] * 3
+    g.voxel, g.threshold = voxel, 0.5
+    ws = torch.empty(int(lib().r360_field_frames_workspace_bytes(n_fields)), dtype=torch.uint8,
+                     device=field_map.device)
+    centers = torch.empty(n_fields, 3, dtype=torch.float32, device=field_map.device)
+    halves = torch.empty(n_fields, dtype=torch.float32, device=field_map.device)
+    check(lib().r360_field_frames(C.byref(g), _ptr(field_map), n_fields, _ptr(centers), _ptr(halves), _ptr(ws),
+                                  ws.numel(), _stream()))
+    return centers, halves
 
 
 def _opts(scene: Scene, near, far, max_samples, precision):

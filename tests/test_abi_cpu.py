@@ -121,3 +121,12 @@ def test_assignment_arguments_rejected(L):
     assert L.r360_assign_uniform_workspace_bytes((C.c_int32 * 3)(0, 1, 1)) == 0
     nf = C.c_int32(0)
     assert L.r360_assign_uniform(n, None, 0.5, b, None, C.byref(nf), None, 0, None) == _lib.R360_EINVAL
+
+
+def test_frames_arguments_rejected(L):
+    from paper_2208_02705_amd import _lib
+    assert L.r360_field_frames_workspace_bytes(0) == 0
+    assert L.r360_field_frames_workspace_bytes(5) == 256
+    g = _lib.GridDesc()
+    assert L.r360_field_frames(C.byref(g), None, 4, None, None, None, 0, None) == _lib.R360_EINVAL
+    assert L.r360_scene_set_frames(None, None, None, None) == _lib.R360_EINVAL

@@ -176,3 +176,36 @@ def test_adam_matches_oracle(R, orc):
         R.adam_step(tw, tg, tm, tv, step, 1e-3)
         orc.adam(w, g, m, v, step, 1e-3)
     assert np.allclose(_np(tw), w, rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_train_step_with_field_frames(R, orc, prec):
+    """Training gradients with every field encoding its own box."""
+    sc = synth.tiny_scene(8, 47, p_occ=0.5, n_fields=5, hidden=32, max_samples=24)
+    sc.frames = orc.field_frames(sc.field_map, sc.lo, sc.voxel, sc.n_fields)
+    w = _perturbed(sc, 2)
+    scene = R.Scene.from_synth(sc, weights=_t(w))
+    o, d, tgt = _rays(3000, 48)
+    loss, grad = R.train_step(scene, _t(o), _t(d), _t(tgt), precision=prec)
+    l_ref, g_ref, _ = orc.train_grad(sc, o, d, tgt, weights=w)
+    assert abs(float(_np(loss)[0]) - l_ref) <= (1e-5 if prec == "fp32" else 1e-2) * l_ref
+    assert _rel_err(_np(grad), g_ref) <= (FP32_GRAD if prec == "fp32" else X16_GRAD)
+    scene.close()
+
+
+def test_fp64_gradcheck_with_field_frames(R, orc):
+    import torch
+    sc = synth.tiny_scene(4, 49, p_occ=0.6, n_fields=2, hidden=32, max_samples=8)
+    sc.frames = orc.field_frames(sc.field_map, sc.lo, sc.voxel, sc.n_fields)
+    scene = R.Scene.from_synth(sc)
+    o, d, _ = _rays(16, 49, lim=1.0)
+    w64 = torch.from_numpy(sc.weights.astype(np.float64) + np.random.default_rng(49).normal(
+        size=sc.weights.shape) * 0.05).cuda().requires_grad_(True)
+    rgb = R.GradcheckFunction.apply(w64, scene, _t(o), _t(d))
+    g = torch.rand(3, 16, dtype=torch.float64, device="cuda")
+    (rgb * g).sum().backward()
+    C = _np(rgb.detach())
+    target = (C - _np(g) * (3 * 16) / 2).astype(np.float32)
+    _, g_ref, _ = orc.train_grad(sc, o, d, target, weights=w64.detach().cpu().numpy().astype(np.float32))
+    assert _rel_err(_np(w64.grad), g_ref) <= 1e-4
+    scene.close()

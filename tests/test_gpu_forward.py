@@ -346,3 +346,35 @@ def test_stereo_render_matches_oracle(R, orc, room):
         _check_fp32(_np(rgb).reshape(3, -1), ref_rgb)
         _check_fp32(_np(depth).reshape(-1), ref_depth)
     assert not np.array_equal(_np(left[0]), _np(right[0]))
+
+
+# ---------------------------------------------------------------------------
+# Per-field encoding frames
+# ---------------------------------------------------------------------------
+
+def test_field_frames_bitwise(R, orc, room):
+    sc, _ = room
+    c, h = R.field_frames(_t(sc.field_map), sc.n_fields, lo=sc.lo, voxel=sc.voxel)
+    ref = orc.field_frames(sc.field_map, sc.lo, sc.voxel, sc.n_fields)
+    assert np.array_equal(_np(c), ref[:, :3]) and np.array_equal(_np(h), ref[:, 3])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_render_with_field_frames(R, orc, prec):
+    sc = synth.scene_small()
+    sc.frames = orc.field_frames(sc.field_map, sc.lo, sc.voxel, sc.n_fields)
+    scene = R.Scene.from_synth(sc)
+    o, d = orc.equirect_rays(256, 128, synth.IDENTITY_C2W)
+    ref_rgb, ref_depth, _ = orc.render_rays(sc, o, d)
+    rgb, depth, _ = R.render_rays(scene, _t(o), _t(d), precision=prec)
+    if prec == "fp32":
+        _check_fp32(_np(rgb), ref_rgb)
+        _check_fp32(_np(depth), ref_depth)
+    else:
+        _check_x16(_np(rgb), ref_rgb)
+    # back to the scene-wide frame
+    scene.set_frames(None)
+    sc.frames = None
+    rgb, _, _ = R.render_rays(scene, _t(o), _t(d), precision="fp32")
+    _check_fp32(_np(rgb), orc.render_rays(sc, o, d)[0])
+    scene.close()
