@@ -73,7 +73,9 @@ def parse():
     p.add_argument("--no-occupancy", action="store_true")
     p.add_argument("--no-assign", action="store_true")
     p.add_argument("--no-distill", action="store_true")
-    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill"],
+    p.add_argument("--no-variants", action="store_true")
+    p.add_argument("--only", choices=["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill",
+                                      "variants"],
                    default=None,
                    help="time only one leg (for profiler runs)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -139,8 +141,8 @@ def main():
         del r
         return sec, prof
 
-    legs = (["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill"] if args.only is None
-            else [args.only])
+    legs = (["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill", "variants"]
+            if args.only is None else [args.only])
     res = {}
     if "bf16" in legs:
         res["bf16"] = leg("bf16", args.steps, args.warmup)
@@ -168,6 +170,9 @@ def main():
     dst = None
     if "distill" in legs and not args.no_distill:
         dst = distill_leg(R, sc, scene, args)
+    var = None
+    if "variants" in legs and not args.no_variants:
+        var = variants_leg(R, sc, args)
 
     main_prec = "bf16" if "bf16" in res else next(iter(res), None)
     line = {"metric": METRIC, "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -221,6 +226,8 @@ def main():
         line["field_assignment"] = asg
     if dst is not None:
         line["distillation"] = dst
+    if var is not None:
+        line["renderer_variants"] = var
     line["context"] = ("paper: 360Roam renders a 1520x760 panorama in 0.03 s on one RTX2080 Ti (about 38.5 Mrays/s, "
                        "precision not stated) and runs in real time on a GTX1080; different hardware and scenes")
     if not args.no_cpu_baseline and args.only is None:
@@ -446,6 +453,44 @@ def distill_leg(R, sc, scene, args):
             "ms_step": sec * 1e3, "mpoints_per_s": M / sec / 1e6,
             "step_tflops": M * FLOP_PER_SAMPLE_TRAIN / sec / 1e12,
             "stages_ms": {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}}
+
+
+def variants_leg(R, sc, args):
+    """Renderer variants on the headline view (BF16): an omni-directional
+    stereo pair (two eyes 64 mm apart), two samples per occupied voxel, and
+    per-field encoding frames."""
+    import synth
+    out = {}
+    steps = max(5, args.steps // 5)
+    scene = R.Scene.from_synth(sc)
+    r = R.EquirectRenderer(scene, W, H, precision="bf16")
+
+    def pair():
+        r(synth.IDENTITY_C2W, eye=-0.032)
+        r(synth.IDENTITY_C2W, eye=0.032)
+    sec = timed(pair, steps, 2)
+    out["stereo_pair"] = {"ms_per_pair": sec * 1e3, "mrays_per_s": 2 * W * H / sec / 1e6}
+    del r
+    scene.samples_per_voxel = 2
+    r = R.EquirectRenderer(scene, W, H, precision="bf16", max_samples=2 * sc.max_samples)
+    sec = timed(lambda: r(synth.IDENTITY_C2W), steps, 2)
+    out["two_samples_per_voxel"] = {"ms_per_frame": sec * 1e3, "mrays_per_s": W * H / sec / 1e6,
+                                    "max_samples": 2 * sc.max_samples}
+    del r
+    scene.samples_per_voxel = 1
+    c, h = R.field_frames(scene_field_map(sc), sc.n_fields, lo=sc.lo, voxel=sc.voxel)
+    scene.set_frames(c, h)
+    r = R.EquirectRenderer(scene, W, H, precision="bf16")
+    sec = timed(lambda: r(synth.IDENTITY_C2W), steps, 2)
+    out["field_frames"] = {"ms_per_frame": sec * 1e3, "mrays_per_s": W * H / sec / 1e6}
+    del r
+    scene.close()
+    return out
+
+
+def scene_field_map(sc):
+    import torch
+    return torch.from_numpy(sc.field_map).cuda()
 
 
 def cpu_baseline(sc):
