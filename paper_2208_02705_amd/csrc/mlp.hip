@@ -116,13 +116,19 @@ __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) 
 
 __device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 
-constexpr int NTILE = 4;               // 16-sample column tiles per wave chunk
-constexpr int FCH = 16 * NTILE;        // samples per wave chunk
+// 16-sample column tiles per wave chunk and blocks per CU: 16-bit fragments
+// take three tiles (146 VGPRs at hidden 64) so that three blocks, three waves
+// per SIMD, are resident; FP32 fragments fill LDS with two blocks and keep
+// four tiles.
+template <typename T> constexpr int fwd_tiles() { return sizeof(T) == 2 ? 3 : 4; }
+template <typename T> constexpr int fwd_blocks() { return sizeof(T) == 2 ? 3 : 2; }
 constexpr int FWD_WAVES = 4;
 
 template <int H, typename T>
-__global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
+__global__ __launch_bounds__(64 * FWD_WAVES, fwd_blocks<T>()) void k_fwd(FwdArgs a) {
     using G = PackGeom<H>;
+    constexpr int NTILE = fwd_tiles<T>();
+    constexpr int FCH = 16 * NTILE;        // samples per wave chunk
     using F8 = typename FragT<T>::type;
     constexpr int NT = G::NT, KH = G::KH16, FR = G::FRAGS16;
     extern __shared__ __attribute__((aligned(32))) char smem[];
@@ -310,9 +316,9 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
             }
             __builtin_amdgcn_s_setprio(0);
             // Outputs: the sigma and rgb rows are replicated in every lane
-            // group, so lane group g finishes tile g (NTILE == 4 groups).
+            // group, so lane group g finishes tile g (groups past NTILE idle).
             {
-                static_assert(NTILE == 4, "one output tile per lane group");
+                static_assert(NTILE <= 4, "one output tile per lane group");
                 float z = zs[0], q0 = acc[0][0][0], q1 = acc[0][0][1], q2 = acc[0][0][2];
                 int og = orig[0];
 #pragma unroll
@@ -321,7 +327,7 @@ __global__ __launch_bounds__(64 * FWD_WAVES, 2) void k_fwd(FwdArgs a) {
                         z = zs[n]; q0 = acc[n][0][0]; q1 = acc[n][0][1]; q2 = acc[n][0][2]; og = orig[n];
                     }
                 }
-                if (c + 16 * g + j < fend) {
+                if (g < NTILE && c + 16 * g + j < fend) {
                     const unsigned u = (unsigned)og;
                     st32(a.sigma, u, softplusf(z));
                     st32(a.rgb0, u, sigmoidf(q0));
