@@ -11,7 +11,6 @@
 namespace r360 {
 size_t pack_bytes16(int H);
 size_t bias_floats(int H);
-int route_waves(int F);
 inline size_t packT_bytes16(int H) {
     return (size_t)(H == 32 ? PackGeom<32>::FRAGS_T : PackGeom<64>::FRAGS_T) * WAVE * 16;
 }
@@ -171,13 +170,14 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
     w.ro = src.mode == RAYS_GIVEN ? src.o : w.o;
     w.rd = src.mode == RAYS_GIVEN ? src.d : w.d;
     const DdaParams p = dda_params(s, opts);
+    bool counted = false;
     {
         R360_STAGE(0, st);
-        R360_TRY("sample", launch_trace(src, p, N, w, st));
+        R360_TRY("sample", launch_trace(src, p, N, w, s->mlp.n_fields, &counted, st));
     }
     {
         R360_STAGE(1, st);
-        R360_TRY("route", launch_route(w, s->mlp.n_fields, st));
+        R360_TRY("route", launch_route(w, s->mlp.n_fields, counted, st));
     }
     {
         R360_STAGE(2, st);
@@ -790,7 +790,7 @@ r360_status r360_distill_step(const r360_scene* s, const float* x, const float* 
     }
     {
         R360_STAGE(1, S(stream));
-        R360_TRY("route", launch_route(w, s->mlp.n_fields, S(stream)));
+        R360_TRY("route", launch_route(w, s->mlp.n_fields, false, S(stream)));
     }
     {
         R360_STAGE(2, S(stream));

@@ -460,11 +460,18 @@ hipError_t launch_rays(const RaySource& src, int64_t N, float* o, float* d, hipS
 // Compact layout into w.t_mid/delta/ray/field (+ voxel ids), offsets in w.ray_off.
 hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w,
                          int32_t* voxel_out, hipStream_t st);
-// Slot layout into w.t_mid/delta/field, per-ray counts in w.ray_off.
-hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, hipStream_t st);
+// Slot layout into w.t_mid/delta/field, per-ray counts in w.ray_off. For
+// 1 <= F <= TRACE_COUNT_MAX_FIELDS the walk also fills the routing counts
+// w.hist (*counted = true), so launch_route skips its counting pass.
+constexpr int TRACE_COUNT_MAX_FIELDS = 1024;
+hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, int F,
+                        bool* counted, hipStream_t st);
 hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64_t nvox, int n_fields,
                          int16_t* labels, hipStream_t st);
-hipError_t launch_route(const Workspace& w, int F, hipStream_t st);
+// Routing counts per routing wave (route_waves(F) of them) in w.hist:
+// computed here unless `counted` (gathered by launch_trace).
+int route_waves(int F);
+hipError_t launch_route(const Workspace& w, int F, bool counted, hipStream_t st);
 hipError_t launch_repack(r360_scene* s, const float* weights, hipStream_t st);
 hipError_t launch_repack_bwd(r360_scene* s, const float* weights, hipStream_t st);
 hipError_t launch_mlp_forward(const r360_scene* s, const Workspace& w, int precision, hipStream_t st);

@@ -3,7 +3,9 @@
 // Alg.1 Stage II). A stable counting sort by field id over the samples in
 // slot layout (sample k of ray r at slot (r - r % 64) S + 64 k + r % 64):
 //   1. every wave takes a contiguous run of 64-ray blocks and counts the
-//      field ids of their samples (block by block, k by k, lane = ray);
+//      field ids of their samples (block by block, k by k, lane = ray); the
+//      render path gathers the same counts during the traversal instead
+//      (sample.hip), and this pass is then skipped;
 //   2. per field, an exclusive scan over the waves' counts; then a scan over
 //      the fields gives each field's first sorted position (start[F] = total);
 //   3. every wave walks its blocks again in the same order and places each
@@ -200,13 +202,15 @@ int route_waves(int F) {
     return rw;
 }
 
-hipError_t launch_route(const Workspace& w, int F, hipStream_t st) {
+hipError_t launch_route(const Workspace& w, int F, bool counted, hipStream_t st) {
     const int rw = route_waves(F);
     int nbits = 1;
     while ((1 << nbits) < F) ++nbits;
     const int64_t N = w.N;
     const int smax = w.slots.smax;
-    if (F <= 4096) {
+    if (counted) {
+        // step 1 was done during the traversal
+    } else if (F <= 4096) {
         const size_t lds = 4 * F * sizeof(int32_t);
         hipLaunchKernelGGL(k_hist<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw, w.hist);
     } else {

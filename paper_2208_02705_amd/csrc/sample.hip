@@ -6,12 +6,13 @@
 // occupied voxel segment of positive length (Sec. 4.2 dense sampling of the
 // occupied voxels; Sec. 5 ray casting over the labelled occupancy map).
 //
-// One traversal per ray writes sample k of ray r to slot k*N + r of
-// staging arrays (neighbouring lanes write neighbouring addresses, so every
-// store is coalesced) and its count; after an exclusive scan of the counts a
-// compaction pass moves each ray's samples to one contiguous run in t order
-// at its offset, so compositing reads one run per ray and the whole result
-// is deterministic.
+// One traversal per ray writes sample k of ray r to slot
+// (r - r % 64) * max_samples + 64 k + r % 64 of the staging arrays (lanes at
+// the same k write neighbouring addresses) and its count. The render path
+// consumes that slot layout directly; the compact form (launch_sample) adds
+// an exclusive scan of the counts and a pass that moves each ray's samples to
+// one contiguous run in t order at its offset. The render path also gathers
+// the routing pass's per-field counts during the walk (RouteCounts).
 //
 // Bit-exact contract: this file is compiled without floating-point
 // contraction; every operation below is a correctly rounded FP32 add, mul,
@@ -81,14 +82,19 @@ struct CountSink {
 // block of 64 * max_samples slots, and lanes at the same k write
 // neighbouring addresses (k < max_samples, so slots stay below the
 // workspace's sample capacity < 2^31).
+// With `count` set, every emitted sample also adds one to its field's entry
+// of the wave's LDS histogram h.
 struct SlotSink {
     int base;
     float *t, *dl;
     int32_t *fld, *vox;
+    int32_t* h;
+    bool count;
     __device__ void emit(int k, float tm, float d, int lab, int lin) {
         const int j = base + 64 * k;
         t[j] = tm; dl[j] = d; fld[j] = lab;
         if (vox) vox[j] = (int32_t)lin;
+        if (count) atomicAdd(h + lab, 1);
     }
 };
 
@@ -241,19 +247,54 @@ struct Staging {
     float* t; float* dl; int32_t* fld; int32_t* vox;
 };
 
+// Routing counts gathered during the walk: the number of samples of each
+// field in the 64-ray blocks of every routing wave (route.hip), added into
+// hist[f][w] (zeroed beforehand). Routing wave w owns the blocks
+// [w per, (w + 1) per). hist == nullptr: not gathered here.
+struct RouteCounts {
+    int32_t* hist;
+    int F, rw, per;
+};
+
 template <int MODE, bool MULTI>
 __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64_t N, int32_t* __restrict__ cnt,
-                                               float* __restrict__ o_ws, float* __restrict__ d_ws, Staging sg) {
+                                               float* __restrict__ o_ws, float* __restrict__ d_ws, Staging sg,
+                                               RouteCounts rc) {
+    extern __shared__ int32_t l_hist[];   // [4][F] while counting
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    float o[3], d[3];
-    make_ray<MODE>(src, N, r, o, d);
-    if constexpr (MODE != RAYS_GIVEN) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
+    const int lane = threadIdx.x & 63;
+    const bool counting = rc.hist != nullptr;
+    int32_t* h = l_hist + (threadIdx.x >> 6) * rc.F;
+    if (counting) {
+        for (int f = lane; f < rc.F; f += 64) h[f] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    SlotSink sink{(int)(r & ~int64_t(63)) * P.max_samples + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox};
-    cnt[r] = traverse<SlotSink, MULTI>(P, o, d, sink);
+    if (r < N) {
+        float o[3], d[3];
+        make_ray<MODE>(src, N, r, o, d);
+        if constexpr (MODE != RAYS_GIVEN) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
+        }
+        SlotSink sink{(int)(r & ~int64_t(63)) * P.max_samples + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox,
+                      h, counting};
+        cnt[r] = traverse<SlotSink, MULTI>(P, o, d, sink);
+    }
+    if (counting) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int64_t r0 = r - lane;             // the wave's first ray
+        if (r0 < N) {
+            const int w = (int)((r0 >> 6) / rc.per);
+            for (int f = lane; f < rc.F; f += 64) {
+                const int v = h[f];
+                if (v) atomicAdd(rc.hist + (int64_t)f * rc.rw + w, v);
+            }
+        }
+    }
 }
 
 // Pass 2 (after the scan): compaction. The 64 rays of a wave own one
@@ -431,22 +472,28 @@ hipError_t launch_rays(const RaySource& src, int64_t N, float* o, float* d, hipS
 }
 
 // The traversal kernel for the ray source and the samples-per-voxel form.
+__global__ __launch_bounds__(256) void k_fill_zero(int32_t* __restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
 static hipError_t trace_any(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, const Staging& sg,
-                     unsigned nb, hipStream_t st) {
+                     unsigned nb, hipStream_t st, const RouteCounts& rc = RouteCounts{nullptr, 0, 1, 1}) {
+    const size_t lds = rc.hist ? (size_t)4 * rc.F * sizeof(int32_t) : 0;
     if (p.spv > 1) {
         if (src.mode == RAYS_EQUIRECT)
-            hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, true>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+            hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, true>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
         else if (src.mode == RAYS_PINHOLE)
-            hipLaunchKernelGGL((k_trace<RAYS_PINHOLE, true>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+            hipLaunchKernelGGL((k_trace<RAYS_PINHOLE, true>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
         else
-            hipLaunchKernelGGL((k_trace<RAYS_GIVEN, true>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+            hipLaunchKernelGGL((k_trace<RAYS_GIVEN, true>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
     } else {
         if (src.mode == RAYS_EQUIRECT)
-            hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, false>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+            hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, false>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
         else if (src.mode == RAYS_PINHOLE)
-            hipLaunchKernelGGL((k_trace<RAYS_PINHOLE, false>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+            hipLaunchKernelGGL((k_trace<RAYS_PINHOLE, false>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
         else
-            hipLaunchKernelGGL((k_trace<RAYS_GIVEN, false>), dim3(nb), dim3(256), 0, st, src, p, N, w.ray_off, w.o, w.d, sg);
+            hipLaunchKernelGGL((k_trace<RAYS_GIVEN, false>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
     }
     return hipGetLastError();
 }
@@ -470,10 +517,22 @@ hipError_t launch_sample(const RaySource& src, const DdaParams& p, int64_t N, co
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, hipStream_t st) {
+hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, int F,
+                        bool* counted, hipStream_t st) {
     const unsigned nb = blocks_for(N, 256);
     const Staging sg{w.t_mid, w.delta, w.field, nullptr};
-    return trace_any(src, p, N, w, sg, nb, st);
+    *counted = false;
+    if (F < 1 || F > TRACE_COUNT_MAX_FIELDS) return trace_any(src, p, N, w, sg, nb, st);
+    const int rw = route_waves(F);
+    const int64_t nblk = (N + 63) / 64;
+    const RouteCounts rc{w.hist, F, rw, (int)((nblk + rw - 1) / rw)};
+    const int64_t n = (int64_t)F * rw;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, w.hist, n);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = trace_any(src, p, N, w, sg, nb, st, rc);
+    *counted = e == hipSuccess;
+    return e;
 }
 
 hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64_t nvox, int n_fields,
