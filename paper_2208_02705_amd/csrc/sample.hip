@@ -70,18 +70,16 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 }
 
 // Voxel traversal. Emits (t_mid, delta, voxel, field) for the first
-// max_samples occupied segments; returns the count. With a CountSink only
-// counts. Per step only the crossed axis's next-plane distance changes; the
-// others are reused (their plane index did not change, so the recomputation
-// would give the same bits).
-struct CountSink {
-    __device__ void emit(int, float, float, int, int) {}
-};
+// max_samples occupied segments; returns the count. Per step only the
+// crossed axis's next-plane distance changes; the others are reused (their
+// plane index did not change, so the recomputation would give the same bits).
+//
 // Sample k of ray r goes to slot base + 64 k, base = (r - r % 64) *
 // max_samples + r % 64: each wave of 64 rays stages into one contiguous
 // block of 64 * max_samples slots, and lanes at the same k write
 // neighbouring addresses (k < max_samples, so slots stay below the
 // workspace's sample capacity < 2^31).
+//
 // With `count` set, every emitted sample also adds one to its field's entry
 // of the wave's LDS histogram h.
 struct SlotSink {
@@ -91,9 +89,9 @@ struct SlotSink {
     int32_t* h;
     bool count;
     __device__ void emit(int k, float tm, float d, int lab, int lin) {
-        const int j = base + 64 * k;
-        t[j] = tm; dl[j] = d; fld[j] = lab;
-        if (vox) vox[j] = (int32_t)lin;
+        const unsigned j = (unsigned)(base + 64 * k);
+        st32(t, j, tm); st32(dl, j, d); st32(fld, j, (int32_t)lab);
+        if (vox) st32(vox, j, (int32_t)lin);
         if (count) atomicAdd(h + lab, 1);
     }
 };
@@ -187,7 +185,7 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         const float ia = c2 ? iv2 : (c1 ? iv1 : iv0);                                \
         const int lin_next = lin + (c2 ? ds2 : (c1 ? ds1 : ds0));                    \
         const bool more = tna < t1 && (unsigned)lin_next < nvox;                     \
-        nxt = labels[more ? lin_next : lin];                                         \
+        nxt = ld32(labels, (unsigned)(more ? lin_next : lin));                       \
         __builtin_amdgcn_sched_barrier(0);                                           \
         if (t_out > t_in && cur < 0x8000) {                                          \
             if constexpr (!MULTI) {                                                  \
@@ -222,7 +220,7 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
     // distance is that axis's box exit (the plane position is computed with
     // one rounding either way), which is >= t1: the walk ends on tna >= t1
     // first. The index test in `more` only guards the load.
-    uint16_t la = labels[lin], lb = 0;
+    uint16_t la = ld32(labels, (unsigned)lin), lb = 0;
     for (;;) {
         R360_DDA_STEP(la, lb)
         R360_DDA_STEP(lb, la)

@@ -257,6 +257,23 @@ def test_render_edge_cases(R, orc):
     assert not _np(rgb).any() and not _np(op).any()
 
 
+@pytest.mark.parametrize("n_fields", [1024, 1500])
+def test_render_many_fields_both_routing_count_paths(R, orc, n_fields):
+    """Up to 1024 fields the traversal gathers the routing counts itself;
+    beyond that the routing pass counts them. Both must route every sample
+    to its field: FP32 render against the oracle with one or two voxels per
+    field."""
+    sc = synth.tiny_scene(16, 34, p_occ=0.6, n_fields=n_fields, max_samples=48)
+    assert int((sc.field_map >= 0).sum()) > n_fields
+    scene = R.Scene.from_synth(sc)
+    o, d = _random_rays(3001, 34, lo=-3.5, hi=3.5)
+    ref_rgb, ref_depth, ref_op = orc.render_rays(sc, o, d)
+    rgb, depth, op = R.render_rays(scene, _t(o), _t(d), precision="fp32")
+    _check_fp32(_np(rgb), ref_rgb)
+    _check_fp32(_np(op), ref_op)
+    _check_fp32(_np(depth), ref_depth)
+
+
 def test_render_empty_grid_and_single_field(R, orc):
     sc = synth.tiny_scene(8, 32, p_occ=0.0, n_fields=1)
     scene = R.Scene.from_synth(sc)
