@@ -10,7 +10,8 @@
 //      the fields gives each field's first sorted position (start[F] = total);
 //   3. every wave walks its blocks again in the same order and places each
 //      sample at field_start + (earlier waves' count) + (rank among equal ids
-//      so far), the rank within 64 lanes coming from ballots over the id bits.
+//      so far), the rank within 64 lanes coming from one ballot per distinct
+//      field id among the lanes.
 // perm[sorted position] = slot; the order inside each field is the fixed
 // walk order, so the sort is deterministic.
 #include "r360_internal.h"
@@ -145,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_fields(int32_t* __restrict__ start, in
 
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict__ field, const int32_t* __restrict__ cnt,
-                                                      int64_t N, int smax, int F, int nbits, int rw,
+                                                      int64_t N, int smax, int F, int rw,
                                                       const int32_t* __restrict__ hist, const int32_t* __restrict__ start,
                                                       int32_t* __restrict__ perm) {
     extern __shared__ int32_t lds[];
@@ -172,12 +173,16 @@ __global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict_
             for (int u = 0; u < RB; ++u) {
                 if (k0 + u >= kmax) break;                  // wave-uniform
                 const bool valid = fv[u] >= 0;
-                const int f = valid ? fv[u] : 0;
-                uint64_t peers = __ballot(valid);
-                for (int bt = 0; bt < nbits; ++bt) {
-                    const bool bit = (f >> bt) & 1;
-                    const uint64_t m = __ballot(bit);
-                    peers &= bit ? m : ~m;
+                const int f = fv[u];   // -1 when not valid
+                // the lanes sharing this lane's field: peel one field per
+                // round (the first lane not yet grouped names it); the 64
+                // rays of a block are neighbours, so a level holds few fields
+                uint64_t rest = __ballot(valid), peers = 0;
+                while (rest) {
+                    const int fl = __builtin_amdgcn_readlane(f, (int)__builtin_ctzll(rest));
+                    const uint64_t m = __ballot(f == fl);
+                    peers = f == fl ? m : peers;
+                    rest &= ~m;
                 }
                 if (valid) {
                     const int rank = __popcll(peers & lt);
@@ -204,8 +209,6 @@ int route_waves(int F) {
 
 hipError_t launch_route(const Workspace& w, int F, bool counted, hipStream_t st) {
     const int rw = route_waves(F);
-    int nbits = 1;
-    while ((1 << nbits) < F) ++nbits;
     const int64_t N = w.N;
     const int smax = w.slots.smax;
     if (counted) {
@@ -221,11 +224,11 @@ hipError_t launch_route(const Workspace& w, int F, bool counted, hipStream_t st)
     hipLaunchKernelGGL(k_fields, dim3(1), dim3(1024), 0, st, w.field_start, F);
     if (F <= 4096) {
         const size_t lds = 4 * F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, nbits, rw,
+        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw,
                            w.hist, w.field_start, w.perm);
     } else {
         const size_t lds = F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, nbits, rw,
+        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, rw,
                            w.hist, w.field_start, w.perm);
     }
     return hipGetLastError();
