@@ -187,15 +187,18 @@ __global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restri
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
     const int c = cnt[r];
-    const int64_t base = (r & ~int64_t(63)) * smax + (r & 63);
+    // slot indices stay below 2^30: 32-bit offsets from each array's base
+    const unsigned base = (unsigned)((r & ~int64_t(63)) * smax + (r & 63));
+    const float* rgb1 = rgb + cap;
+    const float* rgb2 = rgb + 2 * cap;
     float S = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f, A = 0.0f;
     for (int k = 0; k < c; k += CB) {
         float sg[CB], dl[CB], tm[CB], q0[CB], q1[CB], q2[CB];
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
-            const int64_t i = base + 64 * (int64_t)min(k + u, c - 1);
-            sg[u] = sigma[i]; dl[u] = delta[i]; tm[u] = t_mid[i];
-            q0[u] = rgb[i]; q1[u] = rgb[cap + i]; q2[u] = rgb[2 * cap + i];
+            const unsigned i = base + 64u * (unsigned)min(k + u, c - 1);
+            sg[u] = ld32(sigma, i); dl[u] = ld32(delta, i); tm[u] = ld32(t_mid, i);
+            q0[u] = ld32(rgb, i); q1[u] = ld32(rgb1, i); q2[u] = ld32(rgb2, i);
         }
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
@@ -227,7 +230,11 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
     const int c = cnt[r];
-    const int64_t base = (r & ~int64_t(63)) * smax + (r & 63);
+    const unsigned base = (unsigned)((r & ~int64_t(63)) * smax + (r & 63));
+    const float* rgb1 = rgb + cap;
+    const float* rgb2 = rgb + 2 * cap;
+    float* drgb1 = drgb + cap;
+    float* drgb2 = drgb + 2 * cap;
     const float g0 = grad[r], g1 = grad[N + r], g2 = grad[2 * N + r];
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     for (int pass = 0; pass < 2; ++pass) {
@@ -236,9 +243,9 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
             float sg[CB], dl[CB], q0[CB], q1[CB], q2[CB];
 #pragma unroll
             for (int u = 0; u < CB; ++u) {
-                const int64_t i = base + 64 * (int64_t)min(k + u, c - 1);
-                sg[u] = sigma[i]; dl[u] = delta[i];
-                q0[u] = rgb[i]; q1[u] = rgb[cap + i]; q2[u] = rgb[2 * cap + i];
+                const unsigned i = base + 64u * (unsigned)min(k + u, c - 1);
+                sg[u] = ld32(sigma, i); dl[u] = ld32(delta, i);
+                q0[u] = ld32(rgb, i); q1[u] = ld32(rgb1, i); q2[u] = ld32(rgb2, i);
             }
 #pragma unroll
             for (int u = 0; u < CB; ++u) {
@@ -248,11 +255,11 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
                     P0 += w * q0[u]; P1 += w * q1[u]; P2 += w * q2[u];
                     S += tau;
                     if (pass == 1) {
-                        const int64_t i = base + 64 * (int64_t)(k + u);
+                        const unsigned i = base + 64u * (unsigned)(k + u);
                         const float cg = q0[u] * g0 + q1[u] * g1 + q2[u] * g2;
                         const float rg = (C0 - P0) * g0 + (C1 - P1) * g1 + (C2 - P2) * g2;
-                        dsigma[i] = dl[u] * (expf(-S) * cg - rg);
-                        drgb[i] = w * g0; drgb[cap + i] = w * g1; drgb[2 * cap + i] = w * g2;
+                        st32(dsigma, i, dl[u] * (expf(-S) * cg - rg));
+                        st32(drgb, i, w * g0); st32(drgb1, i, w * g1); st32(drgb2, i, w * g2);
                     }
                 }
             }
