@@ -178,11 +178,6 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         const bool c2 = tn2 < m01;                                                   \
         const float tna = c2 ? tn2 : m01;                                            \
         const float t_out = mn(tna, t1);                                             \
-        const float pka = c2 ? pk2 : (c1 ? pk1 : pk0);                               \
-        const float sfa = c2 ? sf2 : (c1 ? sf1 : sf0);                               \
-        const float loa = c2 ? lo2 : (c1 ? lo1 : lo0);                               \
-        const float oa = c2 ? o2 : (c1 ? o1 : o0);                                   \
-        const float ia = c2 ? iv2 : (c1 ? iv1 : iv0);                                \
         const int lin_next = lin + (c2 ? ds2 : (c1 ? ds1 : ds0));                    \
         const bool more = tna < t1 && (unsigned)lin_next < nvox;                     \
         nxt = ld32(labels, (unsigned)(more ? lin_next : lin));                       \
@@ -208,12 +203,15 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         }                                                                            \
         if (!more) break;                                                            \
         t_in = mx(t_in, tna);                                                        \
-        const float pkn = pka + sfa;                                                 \
-        const float tnn = (__builtin_fmaf(pkn, P.voxel, loa) - oa) * ia;             \
+        /* every axis's next plane, kept only for the crossed axis */                \
+        const float pn0 = pk0 + sf0, pn1 = pk1 + sf1, pn2 = pk2 + sf2;               \
+        const float tm0 = (__builtin_fmaf(pn0, P.voxel, lo0) - o0) * iv0;            \
+        const float tm1 = (__builtin_fmaf(pn1, P.voxel, lo1) - o1) * iv1;            \
+        const float tm2 = (__builtin_fmaf(pn2, P.voxel, lo2) - o2) * iv2;            \
         const bool x0 = !c1 && !c2, x1 = c1 && !c2;                                  \
-        pk0 = x0 ? pkn : pk0; tn0 = x0 ? tnn : tn0;                                  \
-        pk1 = x1 ? pkn : pk1; tn1 = x1 ? tnn : tn1;                                  \
-        pk2 = c2 ? pkn : pk2; tn2 = c2 ? tnn : tn2;                                  \
+        pk0 = x0 ? pn0 : pk0; tn0 = x0 ? tm0 : tn0;                                  \
+        pk1 = x1 ? pn1 : pk1; tn1 = x1 ? tm1 : tn1;                                  \
+        pk2 = c2 ? pn2 : pk2; tn2 = c2 ? tm2 : tn2;                                  \
         lin = lin_next;                                                              \
     }
     // Leaving the grid means crossing one of its boundary planes, whose
