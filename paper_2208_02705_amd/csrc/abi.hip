@@ -117,6 +117,7 @@ Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P) {
     w.hist = (int32_t*)take((size_t)F * route_waves(F) * 4);
     w.field_start = (int32_t*)take((F + 1) * 4);
     w.dw_part = (float*)take((size_t)DW_SLOTS * P * 4);
+    w.blk_fields = (int32_t*)take(DW_SLOTS * 4);
     w.misc = (int32_t*)take(256 * 4);
     w.loss_part = (float*)take(((N + 255) / 256) * 4);
     w.ray_rgb = (float*)take(3 * N * 4);

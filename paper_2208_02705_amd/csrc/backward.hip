@@ -144,6 +144,7 @@ struct BwdArgs {
     const float* bias;
     float* grad;                // [F][P]
     float* part;                // [2 * gridDim][P]
+    int32_t* blk_fields;        // [2 * gridDim] first and last field of each block's slice
 };
 
 template <int H>
@@ -243,6 +244,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     if (beg >= end) return;
     const int first = find_field(a.field_start, a.F, beg);
     const int last = find_field(a.field_start, a.F, end - 1);
+    if (threadIdx.x == 0) { a.blk_fields[2 * b] = first; a.blk_fields[2 * b + 1] = last; }
     const F8* pk = reinterpret_cast<const F8*>(a.pack);
     const F8* pt = reinterpret_cast<const F8*>(a.packT);
     f32x4 w1[N1], w2[N2], wh[NH], w3[N3], w4[N4];
@@ -547,9 +549,10 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 }
 
 // Adds the partial slots of fields shared by several blocks, in block order.
+// bf: the first and last field of every block's slice (written by k_bwd).
 __global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, float* __restrict__ grad,
                                                    const int32_t* __restrict__ start, const int32_t* __restrict__ total,
-                                                   int F, int P, int nb) {
+                                                   const int32_t* __restrict__ bf, int P, int nb) {
     const int f = blockIdx.y;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
@@ -558,13 +561,10 @@ __global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ par
     const int fs = start[f], fe = start[f + 1];
     if (fe <= fs) { grad[(int64_t)f * P + p] = 0.0f; return; }
     const int b0 = fs / per, b1 = (fe - 1) / per;
-    if (b0 == b1) {
-        const int beg = b0 * per, end = min(S, beg + per);
-        if (f != find_field(start, F, beg) && f != find_field(start, F, end - 1)) return;   // written directly
-    }
+    if (b0 == b1 && f != bf[2 * b0] && f != bf[2 * b0 + 1]) return;   // written directly
     float acc = 0.0f;
     for (int b = b0; b <= b1; ++b) {
-        const int slot = (f == find_field(start, F, b * per)) ? 2 * b : 2 * b + 1;
+        const int slot = (f == bf[2 * b]) ? 2 * b : 2 * b + 1;
         acc += part[(int64_t)slot * P + p];
     }
     grad[(int64_t)f * P + p] = acc;
@@ -608,6 +608,7 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     a.bias = s->bias;
     a.grad = grad;
     a.part = w.dw_part;
+    a.blk_fields = w.blk_fields;
     using G = PackGeom<H>;
     const size_t lds = (size_t)(sizeof(T) == 2 ? 2 : 1) * BG::ROWS * BG::PSTRIDE * sizeof(T) +
                        (sizeof(T) == 2 ? (size_t)(G::FRAGS16 + G::FRAGS_T) * WAVE * 16 : 0);
@@ -623,7 +624,7 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dw_reduce, dim3((a.P + 255) / 256, a.F), dim3(256), 0, st, w.dw_part, grad, w.field_start,
-                       a.total, a.F, a.P, nb);
+                       a.total, w.blk_fields, a.P, nb);
     return hipGetLastError();
 }
 

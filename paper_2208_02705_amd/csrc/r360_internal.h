@@ -410,6 +410,7 @@ struct Workspace {
     int32_t* hist;      // [F][ROUTE_WAVES]
     int32_t* field_start;  // [F+1]
     float* dw_part;     // [DW_SLOTS][P] per-slot gradient partials
+    int32_t* blk_fields;  // [DW_SLOTS] first and last field of each backward block's slice
     int32_t* misc;      // small counters
     float* loss_part;   // per-block loss partial sums
     float* ray_rgb;     // [3][N] per-ray colour (train step)
