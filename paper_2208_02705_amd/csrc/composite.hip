@@ -178,6 +178,7 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
 // are issued four samples at a time. The sums run in sample order, as in the
 // definition.
 constexpr int CB = 4;
+constexpr int CBB = 8;   // backward: training batches leave about one wave per SIMD, so more loads per batch
 
 __global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restrict__ cnt, int64_t N, int64_t cap,
                                                          int smax, const float* __restrict__ sigma,
@@ -239,16 +240,16 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     for (int pass = 0; pass < 2; ++pass) {
         float S = 0.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
-        for (int k = 0; k < c; k += CB) {
-            float sg[CB], dl[CB], q0[CB], q1[CB], q2[CB];
+        for (int k = 0; k < c; k += CBB) {
+            float sg[CBB], dl[CBB], q0[CBB], q1[CBB], q2[CBB];
 #pragma unroll
-            for (int u = 0; u < CB; ++u) {
+            for (int u = 0; u < CBB; ++u) {
                 const unsigned i = base + 64u * (unsigned)min(k + u, c - 1);
                 sg[u] = ld32(sigma, i); dl[u] = ld32(delta, i);
                 q0[u] = ld32(rgb, i); q1[u] = ld32(rgb1, i); q2[u] = ld32(rgb2, i);
             }
 #pragma unroll
-            for (int u = 0; u < CB; ++u) {
+            for (int u = 0; u < CBB; ++u) {
                 if (k + u < c) {
                     const float tau = sg[u] * dl[u];
                     const float w = expf(-S) * -expm1f(-tau);
