@@ -91,13 +91,25 @@ typedef struct {
  * b_j = fma(j, (t_out - t_in) / k, t_in), 0 < j < k (b_0 = t_in, b_k =
  * t_out), and every piece gives a sample t_mid = (b_j + b_j+1) / 2, delta =
  * b_j+1 - b_j (FP32, as written); k = 1 is the single midpoint sample. The
- * pieces count against max_samples. */
+ * pieces count against max_samples.
+ *
+ * Early ray termination (renders only; the tolerance-bounded form of the
+ * stopping rule for volume rendering that the related work of Sec. 2 names):
+ * term_eps > 0 stops a ray after its first term_after samples when its
+ * transmittance exp(-sum sigma delta) there is below term_eps; rays above it
+ * continue with their remaining samples, and their result is the same as
+ * without termination. A stopped ray differs from the full result by less
+ * than term_eps in each colour channel and in opacity (the weights it drops
+ * sum to less than its transmittance). term_eps = 0 disables it; otherwise
+ * term_eps <= 1 and 1 <= term_after < max_samples. */
 typedef struct {
     float near_;
     float far_;
     int32_t max_samples;
     int32_t precision;
     int32_t samples_per_voxel;
+    float term_eps;
+    int32_t term_after;
 } r360_render_opts;
 
 typedef struct r360_scene r360_scene;

@@ -301,6 +301,23 @@ def render_rays(scene, o, d, threads: Optional[int] = None, **kw):
     return rgb, depth, opac
 
 
+def render_rays_terminated(scene, o, d, term_eps: float, term_after: int, threads: Optional[int] = None, **kw):
+    """Early ray termination as a stopping rule of volume rendering: a ray
+    stops after its first term_after samples when its transmittance there,
+    exp(-sum tau) = 1 - (opacity of those samples), is below term_eps, and
+    keeps all its samples otherwise. Returns (rgb, depth, opacity, stopped)
+    in FP64; stopped marks the rays that stopped with samples left."""
+    full = render_rays(scene, o, d, threads, **kw)
+    first = render_rays(scene, o, d, threads, **dict(kw, max_samples=term_after))
+    counts = np.diff(sample_rays(scene, o, d, **kw)["offsets"])
+    T = 1.0 - first[2]
+    stopped = (counts > term_after) & (T < term_eps)
+    rgb = np.where(stopped[None, :], first[0], full[0])
+    depth = np.where(stopped, first[1], full[1])
+    opac = np.where(stopped, first[2], full[2])
+    return rgb, depth, opac, stopped
+
+
 def sample_outputs(scene, o, d, offsets, threads: Optional[int] = None, **kw):
     """Per-sample sigma [S] and rgb [3, S] in ray-major order."""
     h = SceneHandle(scene, **kw)

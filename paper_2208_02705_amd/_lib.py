@@ -31,7 +31,7 @@ class MlpDesc(C.Structure):
 
 class RenderOpts(C.Structure):
     _fields_ = [("near_", C.c_float), ("far_", C.c_float), ("max_samples", C.c_int32), ("precision", C.c_int32),
-                ("samples_per_voxel", C.c_int32)]
+                ("samples_per_voxel", C.c_int32), ("term_eps", C.c_float), ("term_after", C.c_int32)]
 
 
 class GlobalDesc(C.Structure):

@@ -77,6 +77,9 @@ r360_status check_opts(const r360_render_opts* o, bool allow_fp64) {
     if (o->max_samples < 1 || o->max_samples > 256) return inval("max_samples outside [1, 256]");
     if (o->samples_per_voxel < 0 || o->samples_per_voxel > 64) return inval("samples_per_voxel outside [0, 64]");
     if (std::isnan(o->near_) || std::isnan(o->far_)) return inval("near/far is NaN");
+    if (!(o->term_eps >= 0.0f && o->term_eps <= 1.0f)) return inval("term_eps outside [0, 1]");
+    if (o->term_eps > 0.0f && (o->term_after < 1 || o->term_after >= o->max_samples))
+        return inval("term_after outside [1, max_samples) with term_eps > 0");
     if (o->precision < R360_FP32 || o->precision > R360_FP64_GRADCHECK) return inval("unknown precision");
     if (o->precision == R360_FP64_GRADCHECK && !allow_fp64) {
         std::snprintf(g_err, sizeof(g_err), "FP64 is only accepted by the gradient-check entry points");
@@ -140,6 +143,7 @@ DdaParams dda_params(const r360_scene* s, const r360_render_opts* o) {
     p.far_ = o->far_;
     p.max_samples = o->max_samples;
     p.spv = o->samples_per_voxel > 1 ? o->samples_per_voxel : 1;
+    p.skip = 0;
     return p;
 }
 
@@ -149,10 +153,14 @@ namespace {
 
 // Validates the common render arguments and carves the workspace.
 r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts, void* ws, size_t ws_bytes,
-                    bool allow_fp64, Workspace* w) {
+                    bool allow_fp64, Workspace* w, bool allow_term = false) {
     if (!s) return inval("scene is NULL");
     r360_status st = check_opts(opts, allow_fp64);
     if (st != R360_OK) return st;
+    if (opts->term_eps > 0.0f && !allow_term) {
+        std::snprintf(g_err, sizeof(g_err), "early ray termination applies to the render entry points only");
+        return R360_EUNSUPPORTED;
+    }
     if (N <= 0 || N > (int64_t(1) << 30)) return inval("N must be in [1, 2^30]");
     if (sample_cap(N, opts->max_samples) >= (int64_t(1) << 30))
         return inval("N * max_samples must stay below 2^30; split the rays");
@@ -166,10 +174,14 @@ r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts
     return R360_OK;
 }
 
+r360_status render_terminated(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
+                              float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st);
+
 r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
                           float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st) {
     w.ro = src.mode == RAYS_GIVEN ? src.o : w.o;
     w.rd = src.mode == RAYS_GIVEN ? src.d : w.d;
+    if (opts->term_eps > 0.0f) return render_terminated(s, src, N, opts, rgb, depth, opacity, w, st);
     const DdaParams p = dda_params(s, opts);
     bool counted = false;
     {
@@ -188,6 +200,72 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
         R360_STAGE(3, st);
         R360_TRY("composite", launch_composite_slots(w, N, rgb, depth, opacity, st));
     }
+    return R360_OK;
+}
+
+// Early ray termination in two rounds. Round 1 renders the first K =
+// term_after samples of every ray and keeps the compositing sums; the rays
+// that emitted all K and whose transmittance expf(-S) is still at least
+// term_eps are listed, and round 2 walks them again, emits samples K onwards
+// (the same FP32 walk, so the same samples) and continues the sums. A
+// continued ray's result is therefore the one-pass result; a stopped ray's is
+// that of its first K samples. Scratch (free during a render): the sums in
+// drgb ([6][N] <= 3 cap floats, as max_samples >= 2), the list in `ray`, the
+// continued rays in ray_rgb / ray_grad, the count in misc. Stage timers cover
+// round 1.
+r360_status render_terminated(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
+                              float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st) {
+    const int F = s->mlp.n_fields, K = opts->term_after;
+    float* state = w.drgb;
+    int32_t* list = w.ray;
+    int32_t* n2dev = w.misc;
+    {
+        DdaParams p = dda_params(s, opts);
+        p.max_samples = K;
+        Workspace w1 = w;
+        w1.slots = slot_map(K);
+        bool counted = false;
+        {
+            R360_STAGE(0, st);
+            R360_TRY("sample", launch_trace(src, p, N, w1, F, &counted, st));
+        }
+        {
+            R360_STAGE(1, st);
+            R360_TRY("route", launch_route(w1, F, counted, st));
+        }
+        {
+            R360_STAGE(2, st);
+            R360_TRY("mlp forward", launch_mlp_forward(s, w1, opts->precision, st));
+        }
+        {
+            R360_STAGE(3, st);
+            R360_TRY("composite", launch_composite_slots(w1, N, rgb, depth, opacity, st, state));
+        }
+        R360_TRY("termination", launch_term_select(w1, N, K, state + 5 * N, opts->term_eps, list, n2dev, st));
+    }
+    int32_t n2 = 0;
+    R360_TRY("termination", hipMemcpyAsync(&n2, n2dev, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    R360_TRY("termination", hipStreamSynchronize(st));
+    if (n2 == 0) return R360_OK;
+    float* o2 = w.ray_rgb;
+    float* d2 = w.ray_grad;
+    R360_TRY("termination", launch_term_gather(n2, list, w.ro, w.rd, N, o2, d2, st));
+    DdaParams p = dda_params(s, opts);
+    p.skip = K;
+    RaySource src2{};
+    src2.mode = RAYS_GIVEN;
+    src2.o = o2;
+    src2.d = d2;
+    Workspace w2 = w;
+    w2.N = n2;
+    w2.slots = slot_map(opts->max_samples - K);
+    w2.ro = o2;
+    w2.rd = d2;
+    bool counted = false;
+    R360_TRY("sample", launch_trace(src2, p, n2, w2, F, &counted, st));
+    R360_TRY("route", launch_route(w2, F, counted, st));
+    R360_TRY("mlp forward", launch_mlp_forward(s, w2, opts->precision, st));
+    R360_TRY("composite", launch_composite_continue(w2, list, N, state, rgb, depth, opacity, st));
     return R360_OK;
 }
 
@@ -464,7 +542,7 @@ r360_status r360_render_rays(const r360_scene* s, const float* o, const float* d
                              size_t ws_bytes, void* stream) {
     if (!o || !d || !rgb || !depth || !opacity) return inval("NULL pointer");
     Workspace w;
-    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w, true);
     if (st != R360_OK) return st;
     RaySource src{};
     src.mode = RAYS_GIVEN;
@@ -480,7 +558,7 @@ r360_status r360_render_equirect(const r360_scene* s, const r360_equirect* eq, c
     if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
     const int64_t N = (int64_t)eq->W * eq->H;
     Workspace w;
-    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w, true);
     if (st != R360_OK) return st;
     RaySource src{};
     src.mode = RAYS_EQUIRECT;
@@ -499,7 +577,7 @@ r360_status r360_render_ods(const r360_scene* s, const r360_equirect* eq, const 
     if (!std::isfinite(eye_offset)) return inval("eye_offset not finite");
     const int64_t N = (int64_t)eq->W * eq->H;
     Workspace w;
-    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w, true);
     if (st != R360_OK) return st;
     RaySource src{};
     src.mode = RAYS_EQUIRECT;
@@ -520,7 +598,7 @@ r360_status r360_render_pinhole(const r360_scene* s, int32_t W, int32_t H, float
     if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
     const int64_t N = (int64_t)W * H;
     Workspace w;
-    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w);
+    r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w, true);
     if (st != R360_OK) return st;
     RaySource src{};
     src.mode = RAYS_PINHOLE;
@@ -778,6 +856,7 @@ r360_status r360_distill_step(const r360_scene* s, const float* x, const float* 
     if (!x || !dir || !field || !tsig || !trgb || !loss || !grad_weights || !opts) return inval("NULL pointer");
     r360_render_opts one = *opts;
     one.max_samples = 1;
+    one.term_eps = 0.0f;        // one sample per point: nothing to stop
     one.near_ = 0.0f;
     one.far_ = 1.0f;
     Workspace w;

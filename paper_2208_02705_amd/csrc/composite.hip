@@ -180,26 +180,40 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
 constexpr int CB = 4;
 constexpr int CBB = 8;   // backward: training batches leave about one wave per SIMD, so more loads per batch
 
-__global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restrict__ cnt, int64_t N, int64_t cap,
+// One lane per ray over the slot layout. CONT: the second round of early
+// termination: lane i composites the slots of continued ray i and adds them
+// to the saved sums of the original ray list[i] (the same operations in the
+// same order as one pass over all its samples). Otherwise lane i is ray i,
+// starting from zero; with `state` set the final sums are also saved
+// ([6][N]: C0, C1, C2, depth, opacity, S). Outputs go to the original ray.
+template <bool CONT>
+__global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restrict__ cnt, int64_t n, int64_t cap,
                                                          int smax, const float* __restrict__ sigma,
                                                          const float* __restrict__ rgb, const float* __restrict__ t_mid,
-                                                         const float* __restrict__ delta, float* __restrict__ out_rgb,
+                                                         const float* __restrict__ delta,
+                                                         const int32_t* __restrict__ list, int64_t N,
+                                                         float* __restrict__ state, float* __restrict__ out_rgb,
                                                          float* __restrict__ depth, float* __restrict__ opacity) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    const int c = cnt[r];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t r = CONT ? (int64_t)list[i] : i;
+    const int c = cnt[i];
     // slot indices stay below 2^30: 32-bit offsets from each array's base
-    const unsigned base = (unsigned)((r & ~int64_t(63)) * smax + (r & 63));
+    const unsigned base = (unsigned)((i & ~int64_t(63)) * smax + (i & 63));
     const float* rgb1 = rgb + cap;
     const float* rgb2 = rgb + 2 * cap;
     float S = 0.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f, A = 0.0f;
+    if constexpr (CONT) {
+        c0 = state[r]; c1 = state[N + r]; c2 = state[2 * N + r];
+        D = state[3 * N + r]; A = state[4 * N + r]; S = state[5 * N + r];
+    }
     for (int k = 0; k < c; k += CB) {
         float sg[CB], dl[CB], tm[CB], q0[CB], q1[CB], q2[CB];
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
-            const unsigned i = base + 64u * (unsigned)min(k + u, c - 1);
-            sg[u] = ld32(sigma, i); dl[u] = ld32(delta, i); tm[u] = ld32(t_mid, i);
-            q0[u] = ld32(rgb, i); q1[u] = ld32(rgb1, i); q2[u] = ld32(rgb2, i);
+            const unsigned j = base + 64u * (unsigned)min(k + u, c - 1);
+            sg[u] = ld32(sigma, j); dl[u] = ld32(delta, j); tm[u] = ld32(t_mid, j);
+            q0[u] = ld32(rgb, j); q1[u] = ld32(rgb1, j); q2[u] = ld32(rgb2, j);
         }
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
@@ -216,6 +230,38 @@ __global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restri
     if (out_rgb) { out_rgb[r] = c0; out_rgb[N + r] = c1; out_rgb[2 * N + r] = c2; }
     if (depth) depth[r] = D;
     if (opacity) opacity[r] = A;
+    if (!CONT && state) {
+        state[r] = c0; state[N + r] = c1; state[2 * N + r] = c2;
+        state[3 * N + r] = D; state[4 * N + r] = A; state[5 * N + r] = S;
+    }
+}
+
+// Early termination: the rays that continue after their first K samples are
+// those that emitted all K and whose transmittance expf(-S) is still at least
+// eps. The list order (atomic) affects no result: every ray is composited on
+// its own and every sample's field MLP output is independent of its batch.
+__global__ __launch_bounds__(256) void k_term_select(int64_t N, const int32_t* __restrict__ cnt, int K,
+                                                     const float* __restrict__ S, float eps,
+                                                     int32_t* __restrict__ list, int32_t* __restrict__ n2) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    if (cnt[r] == K && expf(-S[r]) >= eps) list[atomicAdd(n2, 1)] = (int32_t)r;
+}
+
+__global__ void k_term_zero(int32_t* __restrict__ n2) { *n2 = 0; }
+
+// The continued rays' origins and directions, [3][n2] each.
+__global__ __launch_bounds__(256) void k_term_gather(int64_t n2, const int32_t* __restrict__ list,
+                                                     const float* __restrict__ ro, const float* __restrict__ rd,
+                                                     int64_t N, float* __restrict__ o2, float* __restrict__ d2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    const int64_t r = list[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        o2[a * n2 + i] = ro[a * N + r];
+        d2[a * n2 + i] = rd[a * N + r];
+    }
 }
 
 // Backward over the slot layout, one lane per ray: pass 1 recomputes C,
@@ -408,9 +454,30 @@ hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* de
 }
 
 hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL(k_composite_slots, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.slots.smax, w.sigma,
-                       w.rgb, w.t_mid, w.delta, rgb, depth, opacity);
+                                  hipStream_t st, float* state) {
+    hipLaunchKernelGGL(k_composite_slots<false>, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.slots.smax,
+                       w.sigma, w.rgb, w.t_mid, w.delta, nullptr, N, state, rgb, depth, opacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_composite_continue(const Workspace& w2, const int32_t* list, int64_t N, const float* state,
+                                     float* rgb, float* depth, float* opacity, hipStream_t st) {
+    hipLaunchKernelGGL(k_composite_slots<true>, dim3(nblk(w2.N)), dim3(256), 0, st, w2.ray_off, w2.N, w2.cap,
+                       w2.slots.smax, w2.sigma, w2.rgb, w2.t_mid, w2.delta, list, N, const_cast<float*>(state), rgb,
+                       depth, opacity);
+    return hipGetLastError();
+}
+
+hipError_t launch_term_select(const Workspace& w, int64_t N, int K, const float* S, float eps, int32_t* list,
+                              int32_t* n2, hipStream_t st) {
+    hipLaunchKernelGGL(k_term_zero, dim3(1), dim3(1), 0, st, n2);
+    hipLaunchKernelGGL(k_term_select, dim3(nblk(N)), dim3(256), 0, st, N, w.ray_off, K, S, eps, list, n2);
+    return hipGetLastError();
+}
+
+hipError_t launch_term_gather(int64_t n2, const int32_t* list, const float* ro, const float* rd, int64_t N, float* o2,
+                              float* d2, hipStream_t st) {
+    hipLaunchKernelGGL(k_term_gather, dim3(nblk(n2)), dim3(256), 0, st, n2, list, ro, rd, N, o2, d2);
     return hipGetLastError();
 }
 

@@ -454,6 +454,7 @@ struct DdaParams {
     float near_, far_;
     int max_samples;
     int spv;              // samples per occupied segment (>= 1)
+    int skip;             // samples 0 .. skip-1 are walked but not emitted (early termination's second round)
 };
 DdaParams dda_params(const r360_scene* s, const r360_render_opts* opts);
 
@@ -481,7 +482,16 @@ hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* de
                             hipStream_t st);
 // ... and over the slot layout (w.ray_off counts).
 hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
-                                  hipStream_t st);
+                                  hipStream_t st, float* state = nullptr);
+// Early termination: the second round's compositing from the saved sums
+// (state [6][N]), the selection of the rays that continue (list, count n2 on
+// the device) and the gather of their rays ([3][n2] each).
+hipError_t launch_composite_continue(const Workspace& w2, const int32_t* list, int64_t N, const float* state,
+                                     float* rgb, float* depth, float* opacity, hipStream_t st);
+hipError_t launch_term_select(const Workspace& w, int64_t N, int K, const float* S, float eps, int32_t* list,
+                              int32_t* n2, hipStream_t st);
+hipError_t launch_term_gather(int64_t n2, const int32_t* list, const float* ro, const float* rd, int64_t N, float* o2,
+                              float* d2, hipStream_t st);
 hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);
 hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, const float* target, float* loss,
                             float* grad_rgb, hipStream_t st);

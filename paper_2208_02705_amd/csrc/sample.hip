@@ -70,15 +70,17 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 }
 
 // Voxel traversal. Emits (t_mid, delta, voxel, field) for the first
-// max_samples occupied segments; returns the count. Per step only the
+// max_samples occupied segments, except the first P.skip of them (which are
+// walked but not emitted; the rest are numbered from 0); returns the number
+// emitted. Per step only the
 // crossed axis's next-plane distance changes; the others are reused (their
 // plane index did not change, so the recomputation would give the same bits).
 //
-// Sample k of ray r goes to slot base + 64 k, base = (r - r % 64) *
-// max_samples + r % 64: each wave of 64 rays stages into one contiguous
-// block of 64 * max_samples slots, and lanes at the same k write
-// neighbouring addresses (k < max_samples, so slots stay below the
-// workspace's sample capacity < 2^31).
+// Sample k of ray r goes to slot base + 64 k, base = (r - r % 64) * S +
+// r % 64 with S = max_samples - skip slots per ray: each wave of 64 rays
+// stages into one contiguous block of 64 S slots, and lanes at the same k
+// write neighbouring addresses (k < S, so slots stay below the workspace's
+// sample capacity < 2^31).
 //
 // With `count` set, every emitted sample also adds one to its field's entry
 // of the wave's LDS histogram h.
@@ -184,7 +186,8 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         __builtin_amdgcn_sched_barrier(0);                                           \
         if (t_out > t_in && cur < 0x8000) {                                          \
             if constexpr (!MULTI) {                                                  \
-                sink.emit(count, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin);\
+                if (count >= P.skip)                                                 \
+                    sink.emit(count - P.skip, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin); \
                 if (++count == P.max_samples) break;                                 \
             } else {                                                                 \
                 /* P.spv pieces cut at fma(j, length / k, t_in) */                   \
@@ -194,7 +197,8 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
                 for (int q = 0; q < P.spv; ++q) {                                    \
                     const float b1 = q + 1 == P.spv ? t_out                          \
                                                     : __builtin_fmaf((float)(q + 1), piece, t_in); \
-                    sink.emit(count, (b0 + b1) * 0.5f, b1 - b0, (int)cur, lin);      \
+                    if (count >= P.skip)                                             \
+                        sink.emit(count - P.skip, (b0 + b1) * 0.5f, b1 - b0, (int)cur, lin); \
                     b0 = b1;                                                         \
                     if (++count == P.max_samples) { full = true; break; }            \
                 }                                                                    \
@@ -224,7 +228,7 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         R360_DDA_STEP(lb, la)
     }
 #undef R360_DDA_STEP
-    return count;
+    return count > P.skip ? count - P.skip : 0;
 }
 
 template <int MODE>
@@ -274,7 +278,7 @@ __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64
 #pragma unroll
             for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
         }
-        SlotSink sink{(int)(r & ~int64_t(63)) * P.max_samples + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox,
+        SlotSink sink{(int)(r & ~int64_t(63)) * (P.max_samples - P.skip) + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox,
                       h, counting};
         cnt[r] = traverse<SlotSink, MULTI>(P, o, d, sink);
     }

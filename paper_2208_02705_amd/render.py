@@ -226,11 +226,14 @@ def sample_rays(scene: Scene, o: torch.Tensor, d: torch.Tensor, *, near=None, fa
 
 
 def render_rays(scene: Scene, o: torch.Tensor, d: torch.Tensor, *, precision="fp32", near=None, far=None,
-                max_samples=None, ws: Optional[torch.Tensor] = None):
-    """(rgb [3, N], depth [N], opacity [N]) for caller rays o, d [3, N]."""
+                max_samples=None, ws: Optional[torch.Tensor] = None, term_eps: float = 0.0, term_after: int = 0):
+    """(rgb [3, N], depth [N], opacity [N]) for caller rays o, d [3, N].
+    term_eps > 0: early ray termination after term_after samples (rays whose
+    transmittance there is below term_eps stop)."""
     o = _dev(o, torch.float32, "o"); d = _dev(d, torch.float32, "d")
     N = o.shape[1]
     opts = _opts(scene, near, far, max_samples, precision)
+    opts.term_eps, opts.term_after = term_eps, term_after
     ws = scene.workspace(N, opts.max_samples) if ws is None else ws
     rgb = torch.empty(3, N, dtype=torch.float32, device=o.device)
     depth = torch.empty(N, dtype=torch.float32, device=o.device)
@@ -243,9 +246,11 @@ def render_rays(scene: Scene, o: torch.Tensor, d: torch.Tensor, *, precision="fp
 class EquirectRenderer:
     """Renders W x H equirect views; owns the tables and output buffers."""
 
-    def __init__(self, scene: Scene, W: int, H: int, *, precision="bf16", near=None, far=None, max_samples=None):
+    def __init__(self, scene: Scene, W: int, H: int, *, precision="bf16", near=None, far=None, max_samples=None,
+                 term_eps: float = 0.0, term_after: int = 0):
         self.scene, self.eq = scene, Equirect(W, H)
         self.opts = _opts(scene, near, far, max_samples, precision)
+        self.opts.term_eps, self.opts.term_after = term_eps, term_after
         self.ws = scene.workspace(W * H, self.opts.max_samples)
         dev = scene.device
         self.rgb = torch.empty(3, H, W, dtype=torch.float32, device=dev)

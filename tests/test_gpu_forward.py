@@ -395,3 +395,71 @@ def test_render_with_field_frames(R, orc, prec):
     rgb, _, _ = R.render_rays(scene, _t(o), _t(d), precision="fp32")
     _check_fp32(_np(rgb), orc.render_rays(sc, o, d)[0])
     scene.close()
+
+
+# ---------------------------------------------------------------------------
+# Early ray termination (two rounds)
+# ---------------------------------------------------------------------------
+
+def _median_stop_eps(orc, sc, o, d, K):
+    first = orc.render_rays(sc, o, d, max_samples=K)
+    T_K = 1.0 - first[2]
+    counts = np.diff(orc.sample_rays(sc, o, d)["offsets"])
+    long_ = counts > K
+    return float(np.median(T_K[long_])), T_K, long_
+
+
+def test_early_termination_bitwise_against_both_renders(R, orc, room):
+    """Every ray's result is, bit for bit, either the full render (it
+    continued) or the render of its first K samples (it stopped), and the
+    rays that stop are those whose transmittance after K samples is below
+    eps (up to rays at the threshold, where FP32 and FP64 may differ)."""
+    sc, scene = room
+    o, d = orc.equirect_rays(256, 128, synth.IDENTITY_C2W)
+    K = 8
+    eps, T_K, long_ = _median_stop_eps(orc, sc, o, d, K)
+    full = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32")]
+    first = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", max_samples=K)]
+    term = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", term_eps=eps, term_after=K)]
+    eq_full = (term[0] == full[0]).all(0) & (term[1] == full[1]) & (term[2] == full[2])
+    eq_first = (term[0] == first[0]).all(0) & (term[1] == first[1]) & (term[2] == first[2])
+    assert (eq_full | eq_first).all()
+    near = np.abs(T_K - eps) < 1e-4
+    took_first = eq_first & ~eq_full
+    assert took_first.sum() > 100
+    assert not (took_first & ~(T_K < eps) & ~near).any()
+    assert not (long_ & (T_K < eps) & ~near & ~eq_first).any()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_early_termination_matches_oracle(R, orc, small, prec):
+    sc, scene = small
+    o, d = orc.equirect_rays(256, 128, synth.IDENTITY_C2W)
+    K = 4
+    eps, T_K, long_ = _median_stop_eps(orc, sc, o, d, K)
+    ref_rgb, _, ref_op, stopped = orc.render_rays_terminated(sc, o, d, eps, K)
+    assert stopped.sum() > 100 and (long_ & ~stopped).sum() > 100
+    rgb, depth, op = R.render_rays(scene, _t(o), _t(d), precision=prec, term_eps=eps, term_after=K)
+    rgb, op = _np(rgb), _np(op)
+    near = np.abs(T_K - eps) < (1e-4 if prec == "fp32" else 3e-2)
+    far = ~near
+    if prec == "fp32":
+        _check_fp32(rgb[:, far], ref_rgb[:, far])
+        _check_fp32(op[far], ref_op[far])
+    else:
+        _check_x16(rgb[:, far], ref_rgb[:, far])
+        _check_x16(op[far], ref_op[far])
+    # at the threshold either branch is right; the two differ by less than eps
+    alt = np.where(stopped, orc.render_rays(sc, o, d)[0], orc.render_rays(sc, o, d, max_samples=K)[0])
+    tol = 1e-3 if prec == "fp32" else 2e-2
+    err = np.minimum(np.abs(rgb - ref_rgb), np.abs(rgb - alt))[:, near]
+    assert err.size == 0 or float(err.max()) <= tol
+
+
+def test_early_termination_rejects_bad_arguments(R, small):
+    sc, scene = small
+    o, d = _random_rays(100, 7)
+    for kw in (dict(term_eps=1.5, term_after=2), dict(term_eps=-0.1, term_after=2),
+               dict(term_eps=0.1, term_after=0), dict(term_eps=0.1, term_after=sc.max_samples)):
+        with pytest.raises(Exception):
+            R.render_rays(scene, _t(o), _t(d), precision="fp32", **kw)

@@ -1078,3 +1078,42 @@ def test_field_frames_reach_the_encoding(orc):
     sc.frames = None
     b = orc.render_rays(sc, o, dd)
     assert all(np.array_equal(p, q) for p, q in zip(a, b)) and w2 is sc.weights
+
+
+# ---------------------------------------------------------------------------
+# Early ray termination (a stopping rule of Eq.5's compositing)
+# ---------------------------------------------------------------------------
+
+def test_termination_drops_less_than_the_transmittance(orc):
+    """Compositing telescopes: the weights after the first K samples sum to
+    T_K - T_final <= T_K = 1 - (opacity of the first K samples), and colours
+    lie in [0, 1], so the K-sample render differs from the full one by at
+    most T_K in every channel, in opacity by T_K - T_final exactly."""
+    sc = synth.scene_small()
+    o, d = orc.equirect_rays(64, 32, synth.IDENTITY_C2W)
+    K = 3
+    full = orc.render_rays(sc, o, d)
+    first = orc.render_rays(sc, o, d, max_samples=K)
+    T_K = 1.0 - first[2]
+    assert (np.abs(full[0] - first[0]) <= T_K[None, :] + 1e-12).all()
+    assert (full[2] - first[2] <= T_K + 1e-12).all() and (full[2] >= first[2] - 1e-12).all()
+    assert (T_K < 0.999).any() and (np.abs(full[0] - first[0]).max() > 1e-6)   # the test is not vacuous
+
+
+def test_termination_rule_selects_per_ray(orc):
+    sc = synth.scene_small()
+    o, d = orc.equirect_rays(64, 32, synth.IDENTITY_C2W)
+    K = 3
+    full = orc.render_rays(sc, o, d)
+    first = orc.render_rays(sc, o, d, max_samples=K)
+    counts = np.diff(orc.sample_rays(sc, o, d)["offsets"])
+    T_K = 1.0 - first[2]
+    eps = float(np.median(T_K[counts > K]))          # about half of the long rays stop
+    rgb, depth, opac, stopped = orc.render_rays_terminated(sc, o, d, eps, K)
+    assert stopped.any() and (~stopped & (counts > K)).any()
+    assert np.array_equal(stopped, (counts > K) & (T_K < eps))
+    assert np.array_equal(rgb[:, stopped], first[0][:, stopped]) and np.array_equal(rgb[:, ~stopped], full[0][:, ~stopped])
+    assert np.array_equal(opac[stopped], first[2][stopped]) and np.array_equal(depth[~stopped], full[1][~stopped])
+    # eps = 0 keeps every sample
+    rgb0, _, _, st0 = orc.render_rays_terminated(sc, o, d, 0.0, K)
+    assert not st0.any() and np.array_equal(rgb0, full[0])
