@@ -457,8 +457,9 @@ def distill_leg(R, sc, scene, args):
 
 def variants_leg(R, sc, args):
     """Renderer variants on the headline view (BF16): an omni-directional
-    stereo pair (two eyes 64 mm apart), two samples per occupied voxel, and
-    per-field encoding frames."""
+    stereo pair (two eyes 64 mm apart), two samples per occupied voxel,
+    early ray termination (after 16 samples, where the transmittance is
+    below 1 %), and per-field encoding frames."""
     import synth
     out = {}
     steps = max(5, args.steps // 5)
@@ -478,6 +479,16 @@ def variants_leg(R, sc, args):
                                     "max_samples": 2 * sc.max_samples}
     del r
     scene.samples_per_voxel = 1
+    r = R.EquirectRenderer(scene, W, H, precision="bf16")
+    r(synth.IDENTITY_C2W)
+    ref = r.rgb.clone()
+    del r
+    r = R.EquirectRenderer(scene, W, H, precision="bf16", term_eps=0.01, term_after=16)
+    sec = timed(lambda: r(synth.IDENTITY_C2W), steps, 2)
+    changed = int((r.rgb != ref).any(0).sum())
+    out["early_termination"] = {"term_eps": 0.01, "term_after": 16, "ms_per_frame": sec * 1e3,
+                                "mrays_per_s": W * H / sec / 1e6, "rays_changed_by_stopping": changed}
+    del r, ref
     c, h = R.field_frames(scene_field_map(sc), sc.n_fields, lo=sc.lo, voxel=sc.voxel)
     scene.set_frames(c, h)
     r = R.EquirectRenderer(scene, W, H, precision="bf16")
