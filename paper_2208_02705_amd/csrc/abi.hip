@@ -203,16 +203,16 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
     return R360_OK;
 }
 
-// Early ray termination in two rounds. Round 1 renders the first K =
+// Early ray termination in two passes. Pass 1 renders the first K =
 // term_after samples of every ray and keeps the compositing sums; the rays
 // that emitted all K and whose transmittance expf(-S) is still at least
-// term_eps are listed, and round 2 walks them again, emits samples K onwards
+// term_eps are listed, and pass 2 walks them again, emits samples K onwards
 // (the same FP32 walk, so the same samples) and continues the sums. A
 // continued ray's result is therefore the one-pass result; a stopped ray's is
 // that of its first K samples. Scratch (free during a render): the sums in
 // drgb ([6][N] <= 3 cap floats, as max_samples >= 2), the list in `ray`, the
 // continued rays in ray_rgb / ray_grad, the count in misc. Stage timers cover
-// round 1.
+// pass 1.
 r360_status render_terminated(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
                               float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st) {
     const int F = s->mlp.n_fields, K = opts->term_after;

@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
 constexpr int CB = 4;
 constexpr int CBB = 8;   // backward: training batches leave about one wave per SIMD, so more loads per batch
 
-// One lane per ray over the slot layout. CONT: the second round of early
+// One lane per ray over the slot layout. CONT: the second pass of early
 // termination: lane i composites the slots of continued ray i and adds them
 // to the saved sums of the original ray list[i] (the same operations in the
 // same order as one pass over all its samples). Otherwise lane i is ray i,

@@ -454,7 +454,7 @@ struct DdaParams {
     float near_, far_;
     int max_samples;
     int spv;              // samples per occupied segment (>= 1)
-    int skip;             // samples 0 .. skip-1 are walked but not emitted (early termination's second round)
+    int skip;             // samples 0 .. skip-1 are walked but not emitted (early termination's second pass)
 };
 DdaParams dda_params(const r360_scene* s, const r360_render_opts* opts);
 
@@ -483,7 +483,7 @@ hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* de
 // ... and over the slot layout (w.ray_off counts).
 hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
                                   hipStream_t st, float* state = nullptr);
-// Early termination: the second round's compositing from the saved sums
+// Early termination: the second pass's compositing from the saved sums
 // (state [6][N]), the selection of the rays that continue (list, count n2 on
 // the device) and the gather of their rays ([3][n2] each).
 hipError_t launch_composite_continue(const Workspace& w2, const int32_t* list, int64_t N, const float* state,

@@ -398,7 +398,7 @@ def test_render_with_field_frames(R, orc, prec):
 
 
 # ---------------------------------------------------------------------------
-# Early ray termination (two rounds)
+# Early ray termination (two passes)
 # ---------------------------------------------------------------------------
 
 def _median_stop_eps(orc, sc, o, d, K):
