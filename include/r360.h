@@ -101,7 +101,10 @@ typedef struct {
  * without termination. A stopped ray differs from the full result by less
  * than term_eps in each colour channel and in opacity (the weights it drops
  * sum to less than its transmittance). term_eps = 0 disables it; otherwise
- * term_eps <= 1 and 1 <= term_after < max_samples. */
+ * term_eps <= 1 and 1 <= term_after < max_samples. With termination the
+ * render runs in two passes and synchronises the stream once between them
+ * (to read how many rays continue), so such a render cannot be captured
+ * into a HIP graph; training, sampling and the gradient checks reject it. */
 typedef struct {
     float near_;
     float far_;
