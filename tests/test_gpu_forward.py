@@ -463,3 +463,26 @@ def test_early_termination_rejects_bad_arguments(R, small):
                dict(term_eps=0.1, term_after=0), dict(term_eps=0.1, term_after=sc.max_samples)):
         with pytest.raises(Exception):
             R.render_rays(scene, _t(o), _t(d), precision="fp32", **kw)
+
+
+def test_early_termination_rejected_outside_renders(R, small):
+    """Training needs every sample's gradient: the training step refuses a
+    termination tolerance (argument check, before any launch)."""
+    import ctypes as C
+    import torch
+    from paper_2208_02705_amd import _lib, render as RR
+    sc, scene = small
+    N = 64
+    o, d = _random_rays(N, 8)
+    to, td = _t(o), _t(d)
+    target = torch.zeros(3, N, dtype=torch.float32, device="cuda")
+    opts = RR._opts(scene, None, None, None, "fp32")
+    opts.term_eps, opts.term_after = 0.1, 2
+    ws = scene.workspace(N, opts.max_samples)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    grad = torch.empty(scene.n_fields, scene.P, dtype=torch.float32, device="cuda")
+    status = _lib.lib().r360_train_step(scene._h, RR._ptr(to), RR._ptr(td), N, RR._ptr(target), C.byref(opts),
+                                        RR._ptr(loss), RR._ptr(grad), RR._ptr(None), RR._ptr(ws), ws.numel(),
+                                        RR._stream())
+    assert status != 0
+    assert "render entry points" in _lib.lib().r360_last_error().decode()
