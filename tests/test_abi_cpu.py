@@ -130,3 +130,36 @@ def test_frames_arguments_rejected(L):
     g = _lib.GridDesc()
     assert L.r360_field_frames(C.byref(g), None, 4, None, None, None, 0, None) == _lib.R360_EINVAL
     assert L.r360_scene_set_frames(None, None, None, None) == _lib.R360_EINVAL
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of the header's descriptor structs have
+    the same size and field offsets as the C compiler gives them (a field
+    added on one side only would be read as garbage by the other)."""
+    import shutil
+    import subprocess
+    from paper_2208_02705_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = {"r360_grid_desc": _lib.GridDesc, "r360_mlp_desc": _lib.MlpDesc, "r360_render_opts": _lib.RenderOpts,
+             "r360_global_desc": _lib.GlobalDesc, "r360_occ_desc": _lib.OccDesc}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "r360.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-std=c11", "-I", include, str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
