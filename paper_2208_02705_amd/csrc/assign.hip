@@ -154,20 +154,21 @@ __global__ void k_sel_init(SelState* st) {
     st->first = 0;
 }
 
-// Anchor of the next field, and the selection reset.
-__global__ void k_sel_begin(SelState* st, const int32_t* __restrict__ list, int64_t sk) {
-    st->anchor = list[st->first];
-    st->prefix = 0;
-    st->need = sk;
-    st->found = 0;
-    st->threshold = 0;
-}
-
-// key = (d^2 << 31) | lin for unassigned entries, NOKEY for assigned ones.
-__global__ __launch_bounds__(256) void k_sel_keys(const SelState* st, const int32_t* __restrict__ list,
+// key = (d^2 << 31) | lin for unassigned entries, NOKEY for assigned ones;
+// the anchor is the first unassigned entry. Block 0 also resets the
+// selection for this field (read only by the kernels launched after this
+// one).
+__global__ __launch_bounds__(256) void k_sel_keys(SelState* st, const int32_t* __restrict__ list,
                                                   const uint8_t* __restrict__ done, uint64_t* __restrict__ key,
-                                                  int64_t S, int n0, int n1) {
-    const int first = st->first, a = st->anchor;
+                                                  int64_t S, int n0, int n1, int64_t sk) {
+    const int first = st->first, a = list[first];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->anchor = a;
+        st->prefix = 0;
+        st->need = sk;
+        st->found = 0;
+        st->threshold = 0;
+    }
     const int ax = a % n0, ay = (a / n0) % n1, az = a / (n0 * n1);
     for (int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -403,8 +404,8 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
         const unsigned g = grid_for(left);
         const int take_all = sk >= left ? 1 : 0;
         if (!take_all) {
-            hipLaunchKernelGGL(k_sel_begin, dim3(1), dim3(1), 0, st, w.st, w.list, sk);
-            hipLaunchKernelGGL(k_sel_keys, dim3(g), dim3(256), 0, st, w.st, w.list, w.done, w.key, S, n[0], n[1]);
+            hipLaunchKernelGGL(k_sel_keys, dim3(g), dim3(256), 0, st, w.st, w.list, w.done, w.key, S, n[0], n[1],
+                               sk);
             for (int lv = 0; lv < LEVELS; ++lv) {
                 hipLaunchKernelGGL(k_sel_hist, dim3(std::min(g, 512u)), dim3(256), 0, st, w.st, w.key, S, lv,
                                    w.hist);
