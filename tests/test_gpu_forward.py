@@ -486,3 +486,19 @@ def test_early_termination_rejected_outside_renders(R, small):
                                         RR._stream())
     assert status != 0
     assert "render entry points" in _lib.lib().r360_last_error().decode()
+
+
+def test_early_termination_on_generated_rays(R, orc, room):
+    """The equirect entry point (rays generated into the workspace, then
+    gathered for the second pass) gives the same result bit for bit as
+    caller rays with the same directions."""
+    sc, scene = room
+    W, H, K = 256, 128, 8
+    o, d = orc.equirect_rays(W, H, synth.IDENTITY_C2W)
+    eps, _, _ = _median_stop_eps(orc, sc, o, d, K)
+    view = R.EquirectRenderer(scene, W, H, precision="fp32", term_eps=eps, term_after=K)
+    rgb_v, depth_v, op_v = [_np(x).reshape(x.shape[0], -1) if x.dim() == 3 else _np(x).reshape(-1)
+                            for x in view(synth.IDENTITY_C2W)]
+    rgb_r, depth_r, op_r = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", term_eps=eps,
+                                                         term_after=K)]
+    assert np.array_equal(rgb_v, rgb_r) and np.array_equal(depth_v, depth_r) and np.array_equal(op_v, op_r)
