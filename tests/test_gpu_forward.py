@@ -502,3 +502,24 @@ def test_early_termination_on_generated_rays(R, orc, room):
     rgb_r, depth_r, op_r = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", term_eps=eps,
                                                          term_after=K)]
     assert np.array_equal(rgb_v, rgb_r) and np.array_equal(depth_v, depth_r) and np.array_equal(op_v, op_r)
+
+
+def test_early_termination_with_pieces_per_voxel(R, orc):
+    """With two samples per occupied voxel the first pass may end halfway
+    through a voxel (K = 5 pieces); the second pass continues with the next
+    piece, so every ray still equals the full render or its first-K render
+    bit for bit."""
+    sc = synth.tiny_scene(16, 71, p_occ=0.6, n_fields=4, max_samples=32)
+    scene = R.Scene.from_synth(sc)
+    scene.samples_per_voxel = 2
+    o, d = _random_rays(3000, 71, lo=-3.5, hi=3.5)
+    K = 5
+    full = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32")]
+    first = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", max_samples=K)]
+    T_K = 1.0 - first[2]
+    eps = float(np.median(T_K[(first[2] > 0) & (full[2] > first[2])]))
+    term = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", term_eps=eps, term_after=K)]
+    eq_full = (term[0] == full[0]).all(0) & (term[1] == full[1]) & (term[2] == full[2])
+    eq_first = (term[0] == first[0]).all(0) & (term[1] == first[1]) & (term[2] == first[2])
+    assert (eq_full | eq_first).all()
+    assert (eq_first & ~eq_full).sum() > 50 and (eq_full & ~eq_first).sum() > 50
