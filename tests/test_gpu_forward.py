@@ -525,3 +525,23 @@ def test_early_termination_with_pieces_per_voxel(R, orc):
     eq_first = (term[0] == first[0]).all(0) & (term[1] == first[1]) & (term[2] == first[2])
     assert (eq_full | eq_first).all()
     assert (eq_first & ~eq_full).sum() > 50 and (eq_full & ~eq_first).sum() > 50
+
+
+@pytest.mark.parametrize("K", [1, 23])
+def test_early_termination_extreme_split(R, orc, K):
+    """term_after = 1 (one slot per ray in the first pass) and
+    max_samples - 1 (one slot per ray in the second): still the full or
+    the first-K render, bit for bit, for every ray; eps = 1 stops every ray
+    with samples left."""
+    sc = synth.tiny_scene(16, 72, p_occ=0.7, n_fields=5, max_samples=24)
+    scene = R.Scene.from_synth(sc)
+    o, d = _random_rays(2000, 72, lo=-3.5, hi=3.5)
+    full = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32")]
+    first = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", max_samples=K)]
+    for eps in (0.5, 1.0):
+        term = [_np(x) for x in R.render_rays(scene, _t(o), _t(d), precision="fp32", term_eps=eps, term_after=K)]
+        eq_full = (term[0] == full[0]).all(0) & (term[2] == full[2])
+        eq_first = (term[0] == first[0]).all(0) & (term[2] == first[2])
+        assert (eq_full | eq_first).all()
+        if eps == 1.0:   # transmittance below 1 after any opaque sample: only rays without opacity continue
+            assert eq_first[first[2] > 0].all()
