@@ -291,6 +291,7 @@ void local_forward(const LocalNet& n, const double xh[3], const double dir[3], i
     dense(n.ws, n.bs, 1, h, a.h2.data(), &a.zs);
     a.sigma = ORC_PLANT == 7 ? relu(a.zs) : softplus(a.zs);
     dense(n.Wf, n.bf, h, h, a.h2.data(), a.f.data());
+    if (ORC_PLANT == 26) for (int i = 0; i < h; ++i) a.f[i] = relu(a.f[i]);
     for (int i = 0; i < h; ++i) a.in3[i] = a.f[i];
     for (int i = 0; i < n.dd; ++i) a.in3[h + i] = a.gd[i];
     dense(n.W3, n.b3, h, h + n.dd, a.in3.data(), a.z3.data());
@@ -326,6 +327,7 @@ void local_backward(const LocalNet& n, const LocalAct& a, double dsigma, const d
     for (int i = 0; i < h; ++i) dz3[i] = a.z3[i] > 0.0 ? dh3[i] : 0.0;
     dense_backward(n.W3, h, h + n.dd, a.in3.data(), dz3.data(), (double*)gn.W3, (double*)gn.b3, din3.data());
     // f = Wf h2 + bf (linear): df = din3[0:h]
+    if (ORC_PLANT == 26) for (int i = 0; i < h; ++i) if (!(a.f[i] > 0.0)) din3[i] = 0.0;
     dense_backward(n.Wf, h, h, a.h2.data(), din3.data(), (double*)gn.Wf, (double*)gn.bf, tmp.data());
     for (int i = 0; i < h; ++i) dh2[i] += tmp[i];
     double dzs = dsigma * sigmoid(a.zs);   // softplus' = sigmoid
@@ -505,11 +507,12 @@ void global_forward(const GlobalNet& n, const double xh[3], const double dir[3],
     a.sigma = relu(a.zs);
     a.zf.assign(n.w, 0.0); a.f.assign(n.w, 0.0);
     dense(n.Wf, n.bf, n.w, n.w, a.h[7].data(), a.zf.data());
-    for (int i = 0; i < n.w; ++i) a.f[i] = relu(a.zf[i]);
+    for (int i = 0; i < n.w; ++i) a.f[i] = ORC_PLANT == 27 ? a.zf[i] : relu(a.zf[i]);
     a.in10 = a.f; a.in10.insert(a.in10.end(), a.gd.begin(), a.gd.end());
+    if (ORC_PLANT == 29) for (int i = n.w; i < n.w + n.dd; ++i) a.in10[i] = 0.0;
     a.z10.assign(n.c, 0.0); a.h10.assign(n.c, 0.0);
     dense(n.W10, n.b10, n.c, n.w + n.dd, a.in10.data(), a.z10.data());
-    for (int i = 0; i < n.c; ++i) a.h10[i] = relu(a.z10[i]);
+    for (int i = 0; i < n.c; ++i) a.h10[i] = ORC_PLANT == 28 ? a.z10[i] : relu(a.z10[i]);
     dense(n.W11, n.b11, 3, n.c, a.h10.data(), a.z11);
     for (int k = 0; k < 3; ++k) a.rgb[k] = sigmoid(a.z11[k]);
 }
@@ -518,9 +521,9 @@ void global_backward(const GlobalNet& n, const GlobalAct& a, double dsigma, cons
     for (int k = 0; k < 3; ++k) dz11[k] = drgb[k] * a.rgb[k] * (1.0 - a.rgb[k]);
     std::vector<double> dh10(n.c), dz10(n.c), din10(n.w + n.dd), dh8(n.w, 0.0), dzf(n.w), tmp(n.w + n.dx);
     dense_backward(n.W11, 3, n.c, a.h10.data(), dz11, (double*)g.W11, (double*)g.b11, dh10.data());
-    for (int i = 0; i < n.c; ++i) dz10[i] = a.z10[i] > 0.0 ? dh10[i] : 0.0;
+    for (int i = 0; i < n.c; ++i) dz10[i] = (ORC_PLANT == 28 || a.z10[i] > 0.0) ? dh10[i] : 0.0;
     dense_backward(n.W10, n.c, n.w + n.dd, a.in10.data(), dz10.data(), (double*)g.W10, (double*)g.b10, din10.data());
-    for (int i = 0; i < n.w; ++i) dzf[i] = a.zf[i] > 0.0 ? din10[i] : 0.0;
+    for (int i = 0; i < n.w; ++i) dzf[i] = (ORC_PLANT == 27 || a.zf[i] > 0.0) ? din10[i] : 0.0;
     dense_backward(n.Wf, n.w, n.w, a.h[7].data(), dzf.data(), (double*)g.Wf, (double*)g.bf, tmp.data());
     for (int i = 0; i < n.w; ++i) dh8[i] += tmp[i];
     double dzs = a.zs > 0.0 ? dsigma : 0.0;

@@ -36,6 +36,10 @@ PLANTS = {
     23: "samples per voxel: pieces sampled at their start instead of their middle",
     24: "stereo rays: eye offset along the heading instead of across it",
     25: "per-field frames ignored: every field encoded in the scene frame",
+    26: "local field: ReLU on the linear feature layer (forward and backward)",
+    27: "global field: feature layer without its ReLU (forward and backward)",
+    28: "global field: colour layer 10 without its ReLU (forward and backward)",
+    29: "global field: direction encoding left out of layer 10's input",
 }
 
 

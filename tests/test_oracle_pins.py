@@ -315,6 +315,26 @@ def test_local_mlp_routed_signal(orc):
     assert abs(rgb[2] - sg(0.5 - h33)) < 1e-14
 
 
+def test_local_mlp_feature_is_linear(orc):
+    """The tiny network's feature layer has no activation (App. C, tiny-network
+    table): a negative feature must reach the colour layer with its sign, and a
+    feature that is negative only through its bias must still add its value."""
+    h = 32
+    lay, w, t = _zeros_local(h)
+    x = 0.3
+    t["W1"][5, 0] = 1.0                        # raw x -> h1[5] = x
+    t["W2"][7, 5] = 1.0                        # -> h2[7] = x
+    t["Wf"][20, 7] = -1.0; t["bf"][20] = -0.25  # f[20] = -x - 0.25 < 0
+    t["W3"][6, 20] = -1.0                      # h3[6] = relu(x + 0.25)
+    t["W4"][0, 6] = 1.0
+    t["Wf"][21, 7] = 1.0; t["bf"][21] = -0.75  # f[21] = x - 0.75 = -0.45
+    t["W3"][8, 21] = 1.0; t["b3"][8] = 1.0     # h3[8] = relu(1 + f[21]) = 0.55
+    t["W4"][1, 8] = 2.0; t["b4"][1] = -1.0
+    sigma, rgb = orc.local_mlp(w, h, [x, 0.1, 0.05], [0.6, 0.0, 0.8])
+    assert abs(rgb[0] - sg(x + 0.25)) < 1e-14
+    assert abs(rgb[1] - sg(2 * (1.0 + x - 0.75) - 1.0)) < 1e-14
+
+
 def test_local_mlp_single_layer_against_matmul(orc):
     """With identity-like downstream layers the red output is sigmoid of one
     ReLU dense layer of the encoding, checked against numpy's matmul."""
@@ -510,6 +530,45 @@ def test_global_mlp_zero_weights_and_skip(orc):
     t["ws"][0, 3] = -2.0
     s, _ = orc.global_mlp(w, [0.1, 0.2, 0.3], [0, 0, 1], width=16, color_width=8)
     assert abs(s - 1.4) < 1e-15
+
+
+def test_global_mlp_colour_branch_routed(orc):
+    """The 360NeRF table's colour branch: f = ReLU(Wf h8 + bf), then layer 10
+    on [f ; gamma(d)] with a ReLU, then sigmoid. A raw coordinate is carried
+    through the trunk to h8 and then split into signals that only the right
+    activations and the right input order reproduce in closed form."""
+    width, cw, dd = 16, 8, 27
+    lay = synth.global_mlp_layout(width, color_width=cw)
+    w = np.zeros(synth.n_params(lay), np.float32)
+    t = synth.unpack(lay, w)
+    x = 0.3
+    d = np.array([0.48, 0.6, 0.64])              # unit length
+    t["W1"][3, 0] = 1.0                          # raw x -> h1[3] = x
+    for k in (2, 3, 4, 5, 6, 7, 8):
+        t[f"W{k}"][3, 3] = 1.0                   # the h part of layer 5's [h4 ; gx] input comes first
+    # feature ReLU: f5 = relu(-x) = 0, f6 = relu(x) = x; layer 10 row 2 adds both
+    t["Wf"][5, 3] = -1.0; t["Wf"][6, 3] = 1.0
+    t["W10"][2, 5] = 1.0; t["W10"][2, 6] = 1.0
+    t["W11"][0, 2] = 1.0
+    # layer 10 ReLU: row 4 = relu(-f6) = 0 feeds green beside a bias
+    t["W10"][4, 6] = -1.0
+    t["W11"][1, 4] = 1.0; t["b11"][1] = 0.25
+    # gamma(d) follows f in layer 10's input: sin(2 pi d_y) (l = 1, y) and raw d_z
+    t["W10"][7, width + 3 + 6 * 1 + 1] = 1.0
+    t["W10"][7, width + 2] = -0.5
+    t["b10"][7] = 1.0
+    t["W11"][2, 7] = 1.0
+    s, rgb = orc.global_mlp(w, [x, 0.2, 0.1], d, width=width, color_width=cw)
+    assert s == 0.0
+    assert abs(rgb[0] - sg(x)) < 1e-14
+    assert abs(rgb[1] - sg(0.25)) < 1e-14
+    h107 = 1.0 + math.sin(2 * math.pi * 0.6) - 0.5 * 0.64
+    assert h107 > 0
+    assert abs(rgb[2] - sg(h107)) < 1e-14
+    # a negative layer-10 pre-activation is clipped, a positive one is not
+    t["b10"][7] = -1.0
+    s, rgb = orc.global_mlp(w, [x, 0.2, 0.1], d, width=width, color_width=cw)
+    assert abs(rgb[2] - 0.5) < 1e-15
 
 
 def test_global_step_finite_difference_and_occupancy(orc):
