@@ -106,6 +106,27 @@ def timed(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def timed_profiled(R, fn, steps, warmup):
+    """(seconds per call with the library's stage events off, per-stage
+    profile from a separate pass of the same calls with the events on,
+    seconds per call of that pass). Only the first figure is a throughput;
+    the profile gives the per-kernel launch durations for the rooflines."""
+    sec = timed(fn, steps, warmup)
+    R.profile_read()
+    R.profile_enable(True)
+    try:
+        sec_ev = timed(fn, steps, 0)
+        prof = R.profile_read()
+    finally:
+        R.profile_enable(False)
+    return sec, prof, sec_ev
+
+
+def avg_ms(prof, stage):
+    ms, n = prof.get(stage, (0.0, 0))
+    return ms / n if n else None
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -133,13 +154,9 @@ def main():
 
     def leg(prec, steps, warmup):
         r = R.EquirectRenderer(scene, W, H, precision=prec)
-        R.profile_read()
-        R.profile_enable(True)
-        sec = timed(lambda: r(c2w), steps, warmup)
-        prof = R.profile_read()
-        R.profile_enable(False)
+        sec, prof, sec_ev = timed_profiled(R, lambda: r(c2w), steps, warmup)
         del r
-        return sec, prof
+        return sec, prof, sec_ev
 
     legs = (["bf16", "fp32", "train", "large", "global", "occupancy", "assign", "distill", "variants"]
             if args.only is None else [args.only])
@@ -182,13 +199,13 @@ def main():
                        "samples_per_frame": S, "n_fields": sc.n_fields, "hidden": sc.hidden,
                        "max_samples": sc.max_samples, "near": sc.near, "far": sc.far}}
     if main_prec is not None:
-        sec, prof = res[main_prec]
+        sec, prof, sec_ev = res[main_prec]
         line["value"] = W * H / sec / 1e6
         line["ms_per_step"] = sec * 1e3
+        line["ms_per_step_with_stage_events"] = sec_ev * 1e3
         line["dtype"] = main_prec
         line["msamples_per_s"] = S / sec / 1e6
-        mlp_ms, mlp_n = prof["mlp_forward"]
-        avg = mlp_ms / max(mlp_n, 1)
+        avg = avg_ms(prof, "mlp_forward")
         achieved = S * FLOP_PER_SAMPLE_FWD / (avg * 1e-3) / 1e12
         line["roofline"] = {"bound": "mfma", "kernel": f"field MLP forward ({main_prec})", "achieved": achieved,
                             "peak": PEAK[main_prec], "unit": "TFLOP/s", "frac": achieved / PEAK[main_prec],
@@ -209,11 +226,13 @@ def main():
         for v in hb.values():
             v["frac"] = v["GB/s"] / HBM_PEAK_GBS
         line["hbm_stages"] = hb
-    for prec, (sec, prof) in res.items():
+    for prec, (sec, prof, _) in res.items():
         line[f"{prec}_mrays_per_s"] = W * H / sec / 1e6
+        line[f"{prec}_msamples_per_s"] = S / sec / 1e6
         line[f"{prec}_ms_per_frame"] = sec * 1e3
-        m = prof["mlp_forward"]
-        line[f"{prec}_mlp_tflops"] = S * FLOP_PER_SAMPLE_FWD / (m[0] / max(m[1], 1) * 1e-3) / 1e12
+        tf = S * FLOP_PER_SAMPLE_FWD / (avg_ms(prof, "mlp_forward") * 1e-3) / 1e12
+        line[f"{prec}_mlp_tflops"] = tf
+        line[f"{prec}_mlp_frac_of_peak"] = tf / PEAK[prec]
     if train is not None:
         line["train_step"] = train
     if large is not None:
@@ -275,17 +294,28 @@ def train_leg(R, sc, scene, args):
         R.adam_step(w, grad, m, vv, step[0], R.lr_at(step[0], 1000))
         scene.set_weights(w)
 
-    R.profile_read()
-    R.profile_enable(True)
-    sec = timed(fwd_bwd, max(5, args.steps // 2), 2)
-    prof = R.profile_read()
-    R.profile_enable(False)
-    sec_full = timed(full, max(5, args.steps // 2), 2)
+    steps = max(5, args.steps // 2)
+    sec, prof, sec_ev = timed_profiled(R, fwd_bwd, steps, 2)
+    sec_full = timed(full, steps, 2)
     smp = R.sample_rays(scene, o, d, with_voxel=False)
     S = int(smp["t_mid"].numel())
     st = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1]}
-    return {"rays": N, "samples": S, "ms_fwd_bwd": sec * 1e3, "ms_with_adam": sec_full * 1e3,
-            "stages_ms": st, "tflops_fwd_bwd": S * FLOP_PER_SAMPLE_TRAIN / sec / 1e12, "loss": float(loss.item())}
+    tf = S * FLOP_PER_SAMPLE_TRAIN / sec / 1e12
+    out = {"rays": N, "samples": S, "ms_fwd_bwd": sec * 1e3, "ms_with_adam": sec_full * 1e3,
+           "ms_fwd_bwd_with_stage_events": sec_ev * 1e3, "msamples_per_s": S / sec / 1e6,
+           "mrays_per_s": N / sec / 1e6, "stages_ms": st,
+           "tflops_fwd_bwd": tf, "frac_bf16_peak": tf / PEAK["bf16"], "loss": float(loss.item())}
+    # per-kernel fractions from the stage events: the forward MLP at 36,608 FLOP
+    # per sample; the backward MLP (it recomputes the forward, then dW and dX)
+    # at 98,304 FLOP per sample
+    if st.get("mlp_forward"):
+        f = S * FLOP_PER_SAMPLE_FWD / (st["mlp_forward"] * 1e-3) / 1e12
+        out["mlp_forward"] = {"tflops": f, "frac_bf16_peak": f / PEAK["bf16"]}
+    if st.get("mlp_backward"):
+        b = S * FLOP_PER_SAMPLE_TRAIN / (st["mlp_backward"] * 1e-3) / 1e12
+        out["mlp_backward"] = {"tflops": b, "frac_bf16_peak": b / PEAK["bf16"],
+                               "flop_per_sample": FLOP_PER_SAMPLE_TRAIN}
+    return out
 
 
 def large_leg(R, args):
@@ -299,28 +329,38 @@ def large_leg(R, args):
     EW, EH, PW, PH = 4096, 2048, 1920, 1080
     rays = EW * EH + 4 * PW * PH
     out = {"rays_per_sequence": rays, "n_fields": sc.n_fields, "max_samples": sc.max_samples}
+    yaws = [synth.c2w_yaw((0.0, 0.0, 0.0), q) for q in range(4)]
+    # samples per sequence: the equirect view and the four viewports
+    views = [R.Equirect(EW, EH).rays(synth.IDENTITY_C2W)] + [R.pinhole_rays(PW, PH, PW / 2, PW / 2, c) for c in yaws]
+    counts = []
+    for vo, vd in views:
+        smp = R.sample_rays(scene, vo, vd, with_voxel=False)
+        counts.append(int(smp["t_mid"].numel()))
+        del smp
+    del views
+    torch.cuda.empty_cache()
+    S = sum(counts)
+    out["samples_per_sequence"] = S
+    out["equirect_samples"] = counts[0]
+    out["viewport_samples"] = counts[1:]
     steps = max(3, args.steps // 10)
     for prec in ("bf16", "fp16", "fp32"):
         eqr = R.EquirectRenderer(scene, EW, EH, precision=prec)
         phs = [R.PinholeRenderer(scene, PW, PH, PW / 2, PW / 2, precision=prec) for _ in range(4)]
-        yaws = [synth.c2w_yaw((0.0, 0.0, 0.0), q) for q in range(4)]
 
         def seq():
             eqr(synth.IDENTITY_C2W)
             for r, c in zip(phs, yaws):
                 r(c)
-        R.profile_read()
-        R.profile_enable(True)
-        sec = timed(seq, steps, 1)
-        prof = R.profile_read()
-        R.profile_enable(False)
-        # five launches per sequence; the profile also holds the warm-up sequence
-        out[prec] = {"mrays_per_s": rays / sec / 1e6, "ms_per_sequence": sec * 1e3,
-                     "stages_ms_per_sequence": {k: v[0] / (v[1] / 5) for k, v in prof.items() if v[1]}}
+        sec, prof, _ = timed_profiled(R, seq, steps, 1)
+        # five launches per sequence
+        st = {k: v[0] / (v[1] / 5) for k, v in prof.items() if v[1]}
+        tf = S * FLOP_PER_SAMPLE_FWD / (st["mlp_forward"] * 1e-3) / 1e12
+        out[prec] = {"mrays_per_s": rays / sec / 1e6, "msamples_per_s": S / sec / 1e6,
+                     "ms_per_sequence": sec * 1e3, "stages_ms_per_sequence": st,
+                     "mlp_tflops": tf, "mlp_frac_of_peak": tf / PEAK[prec], "peak_tflops": PEAK[prec]}
         del eqr, phs
-    smp = R.sample_rays(scene, *R.Equirect(EW, EH).rays(synth.IDENTITY_C2W), with_voxel=False)
-    out["equirect_samples"] = int(smp["t_mid"].numel())
-    del smp, scene
+    del scene
     torch.cuda.empty_cache()
     return out
 
@@ -355,12 +395,8 @@ def global_leg(R, args):
 
     def step():
         gf.step(w, o, d, target=tgt, occ=occ, grad=grad)
-    R.profile_read()
-    R.profile_enable(True)
     steps = max(5, args.steps // 5)
-    sec = timed(step, steps, 2)
-    prof = R.profile_read()
-    R.profile_enable(False)
+    sec, prof, _ = timed_profiled(R, step, steps, 2)
     S = N * gf.desc.n_samples
     tf = S * FLOP_PER_SAMPLE_GLOBAL / sec / 1e12
     return {"rays": N, "samples": S, "params": gf.P, "ms_per_step": sec * 1e3,
@@ -392,12 +428,8 @@ def occupancy_leg(R, scene, args):
 
     def pose():
         om.update(o, d, depth, uncert, opac)
-    R.profile_read()
-    R.profile_enable(True)
     steps = max(10, args.steps // 2)
-    sec = timed(pose, steps, 3)
-    prof = R.profile_read()
-    R.profile_enable(False)
+    sec, prof, _ = timed_profiled(R, pose, steps, 3)
     nvox = 128 ** 3
     ms = prof["occupancy"][0] / max(prof["occupancy"][1], 1)
     return {"rays": W * H, "grid": [128, 128, 128], "ms_per_pose": sec * 1e3, "mrays_per_s": W * H / sec / 1e6,
@@ -443,11 +475,8 @@ def distill_leg(R, sc, scene, args):
     sec_t = timed(targets, steps, 2)
     ts, tr = box["t"]
     grad = torch.empty(scene.n_fields, scene.P, device="cuda")
-    R.profile_read()
-    R.profile_enable(True)
-    sec = timed(lambda: R.distill_step(scene, x, d, field, ts, tr, precision="bf16", grad=grad), steps, 2)
-    prof = R.profile_read()
-    R.profile_enable(False)
+    sec, prof, _ = timed_profiled(R, lambda: R.distill_step(scene, x, d, field, ts, tr, precision="bf16", grad=grad),
+                                  steps, 2)
     return {"points": M, "fields": scene.n_fields, "ms_targets": sec_t * 1e3,
             "targets_tflops": M * FLOP_PER_SAMPLE_GLOBAL_FWD / sec_t / 1e12,
             "ms_step": sec * 1e3, "mpoints_per_s": M / sec / 1e6,

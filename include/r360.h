@@ -27,8 +27,9 @@
  *    launch; a failed check launches nothing. Launch failures return
  *    R360_EHIP and r360_last_error() gives the runtime's text. Nothing aborts
  *    across this boundary.
- *  - Sizes: N * max_samples must stay below 2^31 per call (split larger ray
- *    sets into chunks); max_samples is in [1, 256]; n_fields in [1, 16384].
+ *  - Sizes: N <= 2^30 and ceil(N / 64) * 64 * max_samples (the sample slots
+ *    of the call) below 2^30 per call (split larger ray sets into chunks);
+ *    max_samples is in [1, 256]; n_fields in [1, 16384].
  *  - Calls that share a workspace or a scene must not overlap on different
  *    streams.
  */
@@ -171,6 +172,14 @@ r360_status r360_equirect_rays(const r360_equirect* eq, const float c2w_host[12]
 r360_status r360_ods_rays(const r360_equirect* eq, const float c2w_host[12], float eye_offset, const int64_t* pix,
                           int64_t N, float* o, float* d, void* stream);
 
+/* Pinhole viewport rays (the perspective views of r360_render_pinhole):
+ * pixel (u, v) in raster order, x = ((u + 1/2) - W/2) / fx, y = ((v + 1/2) -
+ * H/2) / fy, d_cam = (x, y, 1) / n with n the correctly rounded sqrt of
+ * fma(x, x, fma(y, y, 1)), rotated by c2w_host as for r360_equirect_rays;
+ * o = c2w translation. Outputs o, d: [3][W*H] (device, written). */
+r360_status r360_pinhole_rays(int32_t W, int32_t H, float fx, float fy, const float c2w_host[12], float* o,
+                              float* d, void* stream);
+
 /* Workspace bytes for r360_render_* / r360_sample_rays / r360_backward over
  * N rays with the given max_samples (the capacity is N * max_samples). */
 size_t r360_workspace_bytes(const r360_scene* scene, int64_t n_rays, int32_t max_samples);
@@ -234,6 +243,12 @@ r360_status r360_train_step(const r360_scene* scene, const float* o, const float
                             const float* target_rgb, const r360_render_opts* opts, float* loss,
                             float* grad_weights, float* rgb_out, void* ws, size_t ws_bytes, void* stream);
 
+/* Learning-rate schedule of the fine-tuning (Sec. 6.3: exponential decay
+ * from lr0 to lr1): lr0 (lr1 / lr0)^(min(step, total) / max(total, 1)),
+ * evaluated in FP64 on the host; lr0, lr1 > 0, step >= 0. Returns the rate to
+ * pass to r360_adam_step (NaN for invalid arguments). */
+double r360_lr_schedule(int64_t step, int64_t total, double lr0, double lr1);
+
 /* Adam (Sec. 6.3: beta1 0.9, beta2 0.99): m = b1 m + (1-b1) g;
  * v = b2 v + (1-b2) g^2; w -= lr (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps).
  * FP32 master weights, in place. step >= 1. */
@@ -283,11 +298,13 @@ size_t r360_global_workspace_bytes(const r360_global_desc* desc, int64_t n_rays)
 
 /* Forward (BF16 MFMA GEMMs, FP32 accumulation) over N rays [3][N]; writes
  * rgb_out [3][N] and depth_out [N] if not NULL; folds max(sigma) into
- * occ_grid [n2][n1][n0] (FP32, caller-initialised; NULL skips). With
+ * occ_grid [n2][n1][n0] (FP32, caller-initialised; NULL skips): each cell
+ * becomes max(cell, sigma) over the samples whose position lies in it
+ * (sigma >= 0 always; a cell may start at any non-NaN value, e.g. 0 or a
+ * negative sentinel, and is replaced by the first sample's density). With
  * target_rgb [3][N] also the loss (loss[0], L = 1/(3N) sum (C - C*)^2) and
  * its gradient w.r.t. all weights, grad [P] FP32 (overwritten). Sizes: width
- * and color_width multiples of 32; N * n_samples a multiple of 2048 when a
- * target is given. */
+ * and color_width multiples of 32; 1 <= N * n_samples < 2^31. */
 r360_status r360_global_field_step(const r360_global_desc* desc, const float* weights, const float* o,
                                    const float* d, int64_t N, const float* target_rgb, float* loss, float* grad,
                                    float* rgb_out, float* depth_out, float* occ_grid, void* ws, size_t ws_bytes,
@@ -320,6 +337,15 @@ typedef struct {
     float l_min, l_max;     /* clamp, l_min < l_max (-2 and 3.5 in the paper) */
     float min_opacity;      /* rays below this opacity measure nothing */
 } r360_occ_desc;
+
+/* Fill an update description from sensor probabilities: l_hit =
+ * logit(p_hit), l_miss = logit(p_miss) (logit(p) = log(p / (1 - p)), FP64
+ * rounded to FP32), clamp [l_min, l_max] and the other fields as given
+ * (n and lo the same on every axis). The customary OctoMap sensor model is
+ * p_hit = 0.7, p_miss = 0.4 with the paper's clamp -2, 3.5. Returns
+ * R360_EINVAL unless 1/2 < p_hit < 1 and 0 < p_miss < 1/2. */
+r360_status r360_occ_desc_init(r360_occ_desc* desc, int32_t n, float lo, float voxel, float near_, float far_,
+                               double p_hit, double p_miss, float l_min, float l_max, float min_opacity);
 
 /* Per-ray depth, uncertainty and opacity ([N] each, device, written) from
  * dense samples t, delta, sigma ([N][S] ray-major, device, read). N >= 1,

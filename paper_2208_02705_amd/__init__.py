@@ -12,6 +12,7 @@ is loaded on first use and its absence is an error.
 from ._lib import R360Error, FP32, BF16, FP16, FP64_GRADCHECK, LIB_PATH  # noqa: F401
 from .render import (Scene, Equirect, EquirectRenderer, PinholeRenderer, RenderFunction, GradcheckFunction,  # noqa: F401
                      sample_rays, render_rays, render_equirect, render_pinhole, render_stereo, backward, train_step, adam_step,
+                     pinhole_rays,
                      field_params, field_frames, lr_at, profile_enable, profile_read, GlobalField)
 from .occupancy import OccupancyMap, depth_uncertainty, global_measure  # noqa: F401
 from .assign import assign_fields, assign_uniform  # noqa: F401

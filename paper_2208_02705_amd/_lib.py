@@ -70,6 +70,10 @@ SIGNATURES = {
     "r360_equirect_rays": (i32, [vp, F12, vp, i64, vp, vp, vp]),
     "r360_ods_rays": (i32, [vp, F12, f32, vp, i64, vp, vp, vp]),
     "r360_render_ods": (i32, [vp, vp, F12, f32, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),
+    "r360_pinhole_rays": (i32, [i32, i32, f32, f32, F12, vp, vp, vp]),
+    "r360_lr_schedule": (C.c_double, [i64, i64, C.c_double, C.c_double]),
+    "r360_occ_desc_init": (i32, [C.POINTER(OccDesc), i32, f32, f32, f32, f32, C.c_double, C.c_double, f32, f32,
+                                 f32]),
     "r360_workspace_bytes": (sz, [vp, i64, i32]),
     "r360_sample_rays": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), C.POINTER(i64), vp, vp, vp, vp, vp, vp, vp, sz, vp]),
     "r360_render_rays": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),

@@ -262,10 +262,22 @@ r360_status render_terminated(const r360_scene* s, const RaySource& src, int64_t
     w2.ro = o2;
     w2.rd = d2;
     bool counted = false;
-    R360_TRY("sample", launch_trace(src2, p, n2, w2, F, &counted, st));
-    R360_TRY("route", launch_route(w2, F, counted, st));
-    R360_TRY("mlp forward", launch_mlp_forward(s, w2, opts->precision, st));
-    R360_TRY("composite", launch_composite_continue(w2, list, N, state, rgb, depth, opacity, st));
+    {
+        R360_STAGE(0, st);
+        R360_TRY("sample", launch_trace(src2, p, n2, w2, F, &counted, st));
+    }
+    {
+        R360_STAGE(1, st);
+        R360_TRY("route", launch_route(w2, F, counted, st));
+    }
+    {
+        R360_STAGE(2, st);
+        R360_TRY("mlp forward", launch_mlp_forward(s, w2, opts->precision, st));
+    }
+    {
+        R360_STAGE(3, st);
+        R360_TRY("composite", launch_composite_continue(w2, list, N, state, rgb, depth, opacity, st));
+    }
     return R360_OK;
 }
 
@@ -505,6 +517,29 @@ r360_status r360_ods_rays(const r360_equirect* eq, const float c2w_host[12], flo
     return R360_OK;
 }
 
+r360_status r360_pinhole_rays(int32_t W, int32_t H, float fx, float fy, const float c2w_host[12], float* o,
+                              float* d, void* stream) {
+    if (!o || !d) return inval("NULL pointer");
+    if (W < 1 || H < 1) return inval("W, H must be positive");
+    if (!(fx > 0.0f) || !(fy > 0.0f) || !std::isfinite(fx) || !std::isfinite(fy)) return inval("focal length");
+    if (!valid_c2w(c2w_host)) return inval("c2w is NULL or not finite");
+    RaySource src{};
+    src.mode = RAYS_PINHOLE;
+    src.W = W;
+    src.H = H;
+    src.fx = fx;
+    src.fy = fy;
+    std::memcpy(src.c2w, c2w_host, sizeof(src.c2w));
+    R360_TRY("pinhole_rays", launch_rays(src, (int64_t)W * H, o, d, S(stream)));
+    return R360_OK;
+}
+
+double r360_lr_schedule(int64_t step, int64_t total, double lr0, double lr1) {
+    if (!(lr0 > 0.0) || !(lr1 > 0.0) || step < 0) return std::nan("");
+    const double frac = (double)std::min(step, total) / (double)std::max<int64_t>(total, 1);
+    return lr0 * std::pow(lr1 / lr0, frac);
+}
+
 size_t r360_workspace_bytes(const r360_scene* s, int64_t n_rays, int32_t max_samples) {
     if (!s || n_rays <= 0 || max_samples < 1) return 0;
     return carve(nullptr, n_rays, max_samples, s->mlp.n_fields, s->P).bytes;
@@ -737,7 +772,6 @@ r360_status r360_global_field_step(const r360_global_desc* g, const float* weigh
     if (!weights || !o || !d || !ws) return inval("NULL pointer");
     if (N <= 0 || N * (int64_t)g->n_samples >= (int64_t(1) << 31)) return inval("N * n_samples outside [1, 2^31)");
     if (target && (!loss || !grad)) return inval("a target needs loss and grad outputs");
-    if (target && (N * (int64_t)g->n_samples) % 2048) return inval("with a target, N * n_samples must be a multiple of 2048");
     if (reinterpret_cast<uintptr_t>(ws) & 255) return inval("workspace must be 256-byte aligned");
     const size_t need = global_workspace_bytes(g->width, g->color_width, N, g->n_samples);
     if (ws_bytes < need) {
@@ -774,6 +808,26 @@ r360_status r360_depth_uncertainty(const float* t, const float* delta, const flo
     R360_TRY("depth statistics",
              launch_depth_stats(t, delta, sigma, N, per_ray, depth, uncert, opacity, S(stream)));
     return R360_OK;
+}
+
+r360_status r360_occ_desc_init(r360_occ_desc* g, int32_t n, float lo, float voxel, float near_, float far_,
+                               double p_hit, double p_miss, float l_min, float l_max, float min_opacity) {
+    if (!g) return inval("desc is NULL");
+    if (!(p_hit > 0.5 && p_hit < 1.0) || !(p_miss > 0.0 && p_miss < 0.5))
+        return inval("need 1/2 < p_hit < 1 and 0 < p_miss < 1/2");
+    for (int a = 0; a < 3; ++a) {
+        g->n[a] = n;
+        g->lo[a] = lo;
+    }
+    g->voxel = voxel;
+    g->near_ = near_;
+    g->far_ = far_;
+    g->l_hit = (float)std::log(p_hit / (1.0 - p_hit));
+    g->l_miss = (float)std::log(p_miss / (1.0 - p_miss));
+    g->l_min = l_min;
+    g->l_max = l_max;
+    g->min_opacity = min_opacity;
+    return check_occ(g);
 }
 
 size_t r360_occupancy_workspace_bytes(const r360_occ_desc* g) {

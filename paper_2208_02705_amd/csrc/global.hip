@@ -740,16 +740,18 @@ __global__ void k_gout_grads(int64_t M, const float* __restrict__ rgb, const flo
     for (int c = w + 1; c < ldh; ++c) dzh[m * ldh + c] = (bf16)0.0f;
 }
 
-// Per-sample density max into the occupancy grid (float bits as unsigned:
-// order-preserving for non-negative values; -0 is stored as +0).
+// Per-sample density max into the occupancy grid. The density is >= 0 (its
+// bits as a signed integer are >= 0 and ordered like the floats), and every
+// negative float (-0 included) has a negative signed pattern, so a signed
+// integer max gives max(cell, sigma) whatever non-NaN value the cell held.
 __global__ void k_gocc(int64_t M, const float* __restrict__ sig, const int32_t* __restrict__ voxel,
-                       unsigned* __restrict__ grid) {
+                       int* __restrict__ grid) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     const int v = voxel[m];
     if (v < 0) return;
     const float s = sig[m] > 0.0f ? sig[m] : 0.0f;
-    atomicMax(grid + v, __float_as_uint(s));
+    atomicMax(grid + v, __float_as_int(s));
 }
 
 GNetDev dev_net(const GNet& n) {
@@ -925,7 +927,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
         return hipMemcpyAsync(meas->point_rgb, g.rgb, 3 * M * sizeof(float), hipMemcpyDeviceToDevice, st);
     }
     if (occ) hipLaunchKernelGGL(k_gocc, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, st, M, g.sig, g.voxel,
-                                reinterpret_cast<unsigned*>(occ));
+                                reinterpret_cast<int*>(occ));
     // compositing, loss and its backward reuse the local path's kernels
     Workspace lw{};
     lw.ray_off = g.ray_off; lw.ray = g.ray; lw.sigma = g.sig; lw.rgb = g.rgb; lw.t_mid = g.t; lw.delta = g.delta;

@@ -10,7 +10,6 @@ r360_occupancy_update); this module only marshals arguments.
 from __future__ import annotations
 
 import ctypes as C
-import math
 from typing import Optional
 
 import torch
@@ -21,10 +20,6 @@ from .render import GlobalField, _dev, _ptr, _stream
 
 P_OCCUPIED = 0.97          # Sec. 4.1: occupied above this probability
 LOGIT_RANGE = (-2.0, 3.5)  # Sec. 4.1: probability 0.12 to 0.97
-
-
-def logit(p: float) -> float:
-    return math.log(p / (1.0 - p))
 
 
 def depth_uncertainty(t: torch.Tensor, delta: torch.Tensor, sigma: torch.Tensor):
@@ -64,11 +59,14 @@ class OccupancyMap:
                  p_hit: float = 0.7, p_miss: float = 0.4, l_min: float = LOGIT_RANGE[0],
                  l_max: float = LOGIT_RANGE[1], min_opacity: float = 0.5, device="cuda"):
         g = _lib.OccDesc()
-        g.n[:] = list(n) if isinstance(n, (tuple, list)) else [n] * 3
-        g.lo[:] = list(lo) if isinstance(lo, (tuple, list)) else [lo] * 3
-        g.voxel, g.near_, g.far_ = voxel, near, far
-        g.l_hit, g.l_miss, g.l_min, g.l_max = logit(p_hit), logit(p_miss), l_min, l_max
-        g.min_opacity = min_opacity
+        n0 = n[0] if isinstance(n, (tuple, list)) else n
+        lo0 = lo[0] if isinstance(lo, (tuple, list)) else lo
+        check(lib().r360_occ_desc_init(C.byref(g), n0, lo0, voxel, near, far, p_hit, p_miss, l_min, l_max,
+                                       min_opacity))
+        if isinstance(n, (tuple, list)):
+            g.n[:] = list(n)
+        if isinstance(lo, (tuple, list)):
+            g.lo[:] = list(lo)
         need = int(lib().r360_occupancy_workspace_bytes(C.byref(g)))
         if need == 0:
             raise ValueError(f"invalid occupancy description: {lib().r360_last_error().decode()}")

@@ -308,6 +308,14 @@ class PinholeRenderer:
         return self.rgb, self.depth, self.opacity
 
 
+def pinhole_rays(W: int, H: int, fx: float, fy: float, c2w, device="cuda"):
+    """(o, d) [3, W*H] rays of a pinhole viewport, pixels in raster order."""
+    o = torch.empty(3, W * H, dtype=torch.float32, device=device)
+    d = torch.empty(3, W * H, dtype=torch.float32, device=device)
+    check(lib().r360_pinhole_rays(W, H, fx, fy, _lib.c2w_arg(c2w), _ptr(o), _ptr(d), _stream()))
+    return o, d
+
+
 def render_pinhole(scene: Scene, W: int, H: int, fx: float, fy: float, c2w, **kw):
     r = PinholeRenderer(scene, W, H, fx, fy, **kw)
     return r(c2w)
@@ -420,7 +428,10 @@ def profile_read() -> dict:
 
 def lr_at(step: int, total: int, lr0: float = 1e-3, lr1: float = 5e-5) -> float:
     """Exponential decay from lr0 to lr1 over `total` steps (Sec. 6.3)."""
-    return lr0 * (lr1 / lr0) ** (min(step, total) / max(total, 1))
+    lr = lib().r360_lr_schedule(step, total, lr0, lr1)
+    if lr != lr:
+        raise ValueError("lr0, lr1 must be positive and step >= 0")
+    return lr
 
 
 class RenderFunction(torch.autograd.Function):

@@ -163,3 +163,28 @@ def test_ctypes_structs_match_the_header(tmp_path):
         assert got[(cname, "size")] == C.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_host_helpers(L):
+    """The learning-rate schedule (Sec. 6.3: 1e-3 decaying to 5e-5) and the
+    update description's sensor logits are computed by the library."""
+    import math
+    from paper_2208_02705_amd import _lib
+    assert L.r360_lr_schedule(0, 1000, 1e-3, 5e-5) == 1e-3
+    assert abs(L.r360_lr_schedule(1000, 1000, 1e-3, 5e-5) - 5e-5) < 1e-18
+    assert abs(L.r360_lr_schedule(5000, 1000, 1e-3, 5e-5) - 5e-5) < 1e-18
+    assert abs(L.r360_lr_schedule(500, 1000, 1e-3, 5e-5) - math.sqrt(1e-3 * 5e-5)) < 1e-15
+    assert math.isnan(L.r360_lr_schedule(-1, 1000, 1e-3, 5e-5))
+    g = _lib.OccDesc()
+    assert L.r360_occ_desc_init(C.byref(g), 128, -4.0, 0.0625, 0.0, float("inf"), 0.7, 0.4, -2.0, 3.5, 0.5) == 0
+    assert list(g.n) == [128] * 3 and list(g.lo) == [-4.0] * 3
+    assert g.l_hit == C.c_float(math.log(0.7 / 0.3)).value
+    assert g.l_miss == C.c_float(math.log(0.4 / 0.6)).value
+    assert (g.l_min, g.l_max, g.min_opacity) == (-2.0, 3.5, 0.5)
+    assert L.r360_occ_desc_init(C.byref(g), 128, -4.0, 0.0625, 0.0, 1.0, 0.4, 0.4, -2.0, 3.5, 0.5) == _lib.R360_EINVAL
+    assert L.r360_occ_desc_init(C.byref(g), 128, -4.0, 0.0625, 0.0, 1.0, 0.7, 0.5, -2.0, 3.5, 0.5) == _lib.R360_EINVAL
+    o = C.c_void_p(1)
+    c2w = (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    assert L.r360_pinhole_rays(0, 4, 2.0, 2.0, c2w, o, o, None) == _lib.R360_EINVAL
+    assert L.r360_pinhole_rays(4, 4, 0.0, 2.0, c2w, o, o, None) == _lib.R360_EINVAL
+    assert L.r360_pinhole_rays(4, 4, 2.0, 2.0, c2w, None, o, None) == _lib.R360_EINVAL

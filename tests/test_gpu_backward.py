@@ -11,11 +11,17 @@ import numpy as np
 import pytest
 
 import synth
+from tests._grad import block_errors, describe
 
 pytestmark = pytest.mark.gpu
 
 FP32_GRAD = 2e-4
 X16_GRAD = 3e-2
+# per (field, tensor) block, against the block's own largest entry (blocks
+# below BLOCK_FLOOR of the batch's largest entry against that floor)
+BLOCK_FLOOR = 1e-3
+FP32_BLOCK = 1e-3
+X16_BLOCK = 1e-1
 
 
 @pytest.fixture(scope="module")
@@ -66,8 +72,10 @@ def test_train_step_matches_oracle_gradient(R, orc, hidden, prec):
     tol = FP32_GRAD if prec == "fp32" else X16_GRAD
     assert abs(float(_np(loss)[0]) - l_ref) <= (1e-5 if prec == "fp32" else 1e-2) * l_ref
     err = _rel_err(_np(grad), g_ref)
-    print(f"{prec} h{hidden}: max|dg|/max|g| = {err:.3g}")
+    blk = block_errors(_np(grad), g_ref, synth.local_mlp_layout(hidden), BLOCK_FLOOR)
+    print(f"{prec} h{hidden}: max|dg|/max|g| = {err:.3g}, per block {describe(blk)}")
     assert err <= tol, err
+    assert blk[0][0] <= (FP32_BLOCK if prec == "fp32" else X16_BLOCK), describe(blk)
 
 
 def test_train_step_headline_batch(R, orc):
@@ -87,12 +95,19 @@ def test_train_step_headline_batch(R, orc):
     tgt = np.random.default_rng(5).uniform(0, 1, (3, N)).astype(np.float32)
     loss, grad = R.train_step(scene, _t(o), _t(d), _t(tgt), precision="bf16")
     l_ref, g_ref, _ = orc.train_grad(sc, o, d, tgt)
+    lay = synth.local_mlp_layout(sc.hidden)
     err = _rel_err(_np(grad), g_ref)
-    print(f"headline batch bf16: loss {float(_np(loss)[0]):.6g} vs {l_ref:.6g}, grad rel err {err:.3g}")
+    blk = block_errors(_np(grad), g_ref, lay, BLOCK_FLOOR)
+    print(f"headline batch bf16: loss {float(_np(loss)[0]):.6g} vs {l_ref:.6g}, grad rel err {err:.3g}, "
+          f"per block {describe(blk)}")
     assert abs(float(_np(loss)[0]) - l_ref) <= 1e-2 * l_ref
     assert err <= X16_GRAD, err
+    assert blk[0][0] <= X16_BLOCK, describe(blk)
     loss32, grad32 = R.train_step(scene, _t(o), _t(d), _t(tgt), precision="fp32")
+    blk32 = block_errors(_np(grad32), g_ref, lay, BLOCK_FLOOR)
+    print(f"headline batch fp32: grad rel err {_rel_err(_np(grad32), g_ref):.3g}, per block {describe(blk32)}")
     assert _rel_err(_np(grad32), g_ref) <= FP32_GRAD
+    assert blk32[0][0] <= FP32_BLOCK, describe(blk32)
 
 
 def test_chunk_aligned_rays_forward_and_backward(R, orc):

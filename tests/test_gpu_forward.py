@@ -243,6 +243,17 @@ def test_render_pinhole_viewport(R, orc, room):
     _check_fp32(_np(rgb).reshape(3, -1), ref_rgb)
 
 
+def test_pinhole_rays_bit_exact(R, orc):
+    """The four 1920x1080 quarter-turn viewports' rays equal the oracle's bit
+    for bit (same FP32 formula on both sides)."""
+    for q in range(4):
+        c2w = synth.c2w_yaw((0.5, -0.25, 1.0), q)
+        o, d = R.pinhole_rays(1920, 1080, 960.0, 960.0, c2w)
+        ro, rd = orc.pinhole_rays(1920, 1080, 960.0, 960.0, c2w)
+        assert np.array_equal(_np(o).view(np.uint32), ro.view(np.uint32))
+        assert np.array_equal(_np(d).view(np.uint32), rd.view(np.uint32))
+
+
 def test_render_edge_cases(R, orc):
     sc = synth.tiny_scene(8, 31, p_occ=0.5, n_fields=4, hidden=64, max_samples=16)
     scene = R.Scene.from_synth(sc)

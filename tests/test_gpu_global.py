@@ -107,3 +107,71 @@ def test_global_step_deterministic(R, orc):
     g1 = _np(gf.step(_t(w), _t(o), _t(d), target=_t(tgt))["grad"])
     g2 = _np(gf.step(_t(w), _t(o), _t(d), target=_t(tgt))["grad"])
     assert np.array_equal(g1.view(np.uint32), g2.view(np.uint32))
+
+
+def _compare_step(R, orc, N, S, seed, tol_layer):
+    """One global step on N rays of S samples against the oracle: colour,
+    depth, loss, the gradient per parameter tensor (each against its own
+    scale, tensors below 1e-3 of the largest entry against that floor) and
+    the density max grid cell by cell."""
+    import torch
+    from tests._grad import block_errors, describe
+    o, d = _batch(orc, N, seed)
+    w = _weights(seed)
+    tgt = np.random.default_rng(seed).uniform(0, 1, (3, N)).astype(np.float32)
+    gf = R.GlobalField(n_samples=S)
+    occ = torch.zeros(128, 128, 128, device="cuda")
+    res = gf.step(_t(w), _t(o), _t(d), target=_t(tgt), occ=occ)
+    ref = orc.global_step(w, o, d, tgt, n_samples=S)
+    rgb, depth = _np(res["rgb"]), _np(res["depth"])
+    loss = float(_np(res["loss"])[0])
+    g = _np(res["grad"])
+    errs = block_errors(g, ref["grad"], synth.global_mlp_layout(), 1e-3)
+    occ_g, occ_ref = _np(occ), ref["occ_max"]
+    err_occ = float(np.abs(occ_g - occ_ref).max() / max(occ_ref.max(), 1e-6))
+    err_all = float(np.abs(g - ref["grad"]).max() / np.abs(ref["grad"]).max())
+    print(f"global {N}x{S}: rgb {np.abs(rgb - ref['rgb']).max():.3g}, depth {np.abs(depth - ref['depth']).max():.3g}, "
+          f"loss {loss:.6g} vs {ref['loss']:.6g}, grad {err_all:.3g} of the largest, per tensor {describe(errs)}, "
+          f"occ {err_occ:.3g}")
+    assert np.abs(rgb - ref["rgb"]).max() <= 2e-2
+    assert np.allclose(depth, ref["depth"], rtol=3e-2, atol=3e-2)
+    assert abs(loss - ref["loss"]) <= 2e-2 * ref["loss"]
+    assert err_all <= 3e-2
+    assert errs[0][0] <= tol_layer, describe(errs)
+    assert err_occ <= 2e-2
+    # cells touched by a sample (positive density) are the same up to cells
+    # whose density is within the BF16 budget of zero
+    diff = (occ_g > 0) ^ (occ_ref > 0)
+    assert np.all(occ_ref[diff] <= 2e-2 * occ_ref.max())
+
+
+def test_global_step_1024_rays(R, orc):
+    """1,024 rays x 128 samples: each weight-gradient slice runs eight
+    64-sample steps of its loop (with the next step's loads in flight)."""
+    _compare_step(R, orc, 1024, 128, 6, 1e-1)
+
+
+def test_global_step_ragged_batch(R, orc):
+    """37 rays x 100 samples = 3,700 samples: no multiple of any tile or
+    slice length, so every GEMM ends on a partial tile and the weight-gradient
+    slices end part-way through a step."""
+    _compare_step(R, orc, 37, 100, 7, 1e-1)
+
+
+def test_density_max_into_negative_cells(R, orc):
+    """Cells may start below zero (a sentinel): each ends at max(cell, sigma)
+    over its samples, so touched cells equal the zero-initialised result and
+    untouched ones keep the sentinel."""
+    import torch
+    N = 32
+    o, d = _batch(orc, N, 8)
+    w = _weights(8)
+    gf = R.GlobalField()
+    zer = torch.zeros(128, 128, 128, device="cuda")
+    neg = torch.full((128, 128, 128), -1.0, device="cuda")
+    gf.step(_t(w), _t(o), _t(d), occ=zer)
+    gf.step(_t(w), _t(o), _t(d), occ=neg)
+    zer, neg = _np(zer), _np(neg)
+    assert np.all((neg >= 0) | (neg == -1.0))
+    assert np.array_equal(np.where(neg >= 0, neg, 0.0), zer)
+    assert (neg >= 0).sum() >= (zer > 0).sum() > 0
