@@ -96,7 +96,7 @@ def lib():
             "orc_composite_backward": (None, [C.c_int, vp, vp, vp, vp, vp, vp]),
             "orc_render_rays": (None, [vp, i64, vp, vp, vp, vp, vp, C.c_int]),
             "orc_sample_outputs": (None, [vp, i64, vp, vp, vp, vp, vp, i64, C.c_int]),
-            "orc_train_grad": (f64, [vp, i64, vp, vp, vp, vp, vp, C.c_int]),
+            "orc_train_grad": (f64, [vp, i64, vp, vp, vp, vp, vp, C.c_int, vp, f64, vp]),
             "orc_invdepth_t": (None, [C.c_int, f32, f32, vp, vp]),
             "orc_global_step": (f64, [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int]),
             "orc_global_mlp": (None, [vp, C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp]),
@@ -330,14 +330,30 @@ def sample_outputs(scene, o, d, offsets, threads: Optional[int] = None, **kw):
     return sigma, rgb
 
 
-def train_grad(scene, o, d, target, weights: Optional[np.ndarray] = None, threads: Optional[int] = None, **kw):
-    """(loss, grad [n_fields, P] FP64, rgb [3, N]) for L = mean over rays and channels of (C - C*)^2."""
+def train_grad(scene, o, d, target, weights: Optional[np.ndarray] = None, threads: Optional[int] = None,
+               magnitude: bool = False, kink: Optional[float] = None, **kw):
+    """(loss, grad [n_fields, P] FP64, rgb [3, N]) for L = mean over rays and
+    channels of (C - C*)^2. With magnitude=True a fourth item: the magnitude
+    of every gradient entry (the same computation with the absolute value of
+    each operand; |grad| <= magnitude), the scale a rounding error of another
+    implementation is measured against. With kink = tau as well, a fifth: the
+    magnitude of the terms that pass through a ReLU unit whose pre-activation
+    lies within tau of zero (a computation with pre-activation errors up to
+    tau may take the other branch there and add or drop such a term whole)."""
     h = SceneHandle(scene, weights=weights, **kw)
     o = _c(o, np.float32); d = _c(d, np.float32); target = _c(target, np.float32)
     N = o.shape[1]
     grad = np.empty(h.weights.shape, np.float64)
+    mag = np.empty(h.weights.shape, np.float64) if magnitude else None
+    kin = np.empty(h.weights.shape, np.float64) if magnitude and kink is not None else None
     rgb = np.empty((3, N))
-    loss = lib().orc_train_grad(h.ptr, N, _p(o), _p(d), _p(target), _p(grad), _p(rgb), threads or default_threads())
+    loss = lib().orc_train_grad(h.ptr, N, _p(o), _p(d), _p(target), _p(grad), _p(rgb), threads or default_threads(),
+                                _p(mag) if magnitude else None, float(kink or 0.0),
+                                _p(kin) if kin is not None else None)
+    if kin is not None:
+        return float(loss), grad, rgb, mag, kin
+    if magnitude:
+        return float(loss), grad, rgb, mag
     return float(loss), grad, rgb
 
 

@@ -339,6 +339,94 @@ void local_backward(const LocalNet& n, const LocalAct& a, double dsigma, const d
     dense_backward(n.W1, h, n.dx, a.gx.data(), dz1.data(), (double*)gn.W1, (double*)gn.b1, nullptr);
 }
 
+// Magnitudes for error bounds (running error analysis): each quantity of the
+// local-field forward and backward re-evaluated with the absolute value of
+// every operand, so that |q| <= q_mag by the triangle inequality and a
+// rounding of relative size u in any term moves q by at most u q_mag. ReLU
+// masks and the slopes of softplus and sigmoid are those of the actual
+// evaluation `a`. dsig_mag >= 0 and drgb_mag[3] >= 0 are the magnitudes of
+// dL/dsigma and dL/drgb; magnitudes of the weight gradients accumulate into gm.
+// Kinks: a ReLU unit whose pre-activation lies within tau of zero may take
+// the other branch in a computation whose pre-activations carry errors up to
+// tau; the flip adds or drops the unit's whole term (its row and bias, and
+// the path below it) for that sample. gk (optional) accumulates, for every
+// such unit, the magnitude of that term: the backward of the magnitudes
+// seeded with the unit's incoming gradient magnitude alone.
+void dense_abs(const double* W, const double* b, int n_out, int n_in, const double* x, double* y) {
+    for (int o = 0; o < n_out; ++o) {
+        double acc = std::fabs(b[o]);
+        for (int i = 0; i < n_in; ++i) acc += std::fabs(W[(size_t)o * n_in + i]) * x[i];
+        y[o] = acc;
+    }
+}
+void dense_backward_abs(const double* W, int n_out, int n_in, const double* x, const double* g,
+                        double* dW, double* db, double* dx) {
+    for (int o = 0; o < n_out; ++o) {
+        for (int i = 0; i < n_in; ++i) dW[(size_t)o * n_in + i] += g[o] * x[i];
+        db[o] += g[o];
+    }
+    if (dx) {
+        for (int i = 0; i < n_in; ++i) {
+            double acc = 0.0;
+            for (int o = 0; o < n_out; ++o) acc += std::fabs(W[(size_t)o * n_in + i]) * g[o];
+            dx[i] = acc;
+        }
+    }
+}
+void local_magnitude(const LocalNet& n, const LocalAct& a, double dsig_mag, const double drgb_mag[3],
+                     const LocalNet& gm, double tau, const LocalNet* gk) {
+    const int h = n.h;
+    std::vector<double> gx(n.dx), z1(h), h1(h), z2(h), h2(h), f(h), in3(h + n.dd), z3(h), h3(h);
+    std::vector<char> m1(h), m2(h), m3(h);
+    for (int i = 0; i < n.dx; ++i) gx[i] = std::fabs(a.gx[i]);
+    dense_abs(n.W1, n.b1, h, n.dx, gx.data(), z1.data());
+    for (int i = 0; i < h; ++i) { m1[i] = a.z1[i] > 0.0; h1[i] = m1[i] ? z1[i] : 0.0; }
+    dense_abs(n.W2, n.b2, h, h, h1.data(), z2.data());
+    for (int i = 0; i < h; ++i) { m2[i] = a.z2[i] > 0.0; h2[i] = m2[i] ? z2[i] : 0.0; }
+    dense_abs(n.Wf, n.bf, h, h, h2.data(), f.data());
+    for (int i = 0; i < h; ++i) in3[i] = f[i];
+    for (int i = 0; i < n.dd; ++i) in3[h + i] = std::fabs(a.gd[i]);
+    dense_abs(n.W3, n.b3, h, h + n.dd, in3.data(), z3.data());
+    for (int i = 0; i < h; ++i) { m3[i] = a.z3[i] > 0.0; h3[i] = m3[i] ? z3[i] : 0.0; }
+
+    double dz4[3];
+    for (int c = 0; c < 3; ++c) dz4[c] = drgb_mag[c] * a.rgb[c] * (1.0 - a.rgb[c]);
+    std::vector<double> dh3(h), dz3(h), din3(h + n.dd), dh2(h, 0.0), dz2(h), dh1(h), dz1(h), tmp(h);
+    dense_backward_abs(n.W4, 3, h, h3.data(), dz4, (double*)gm.W4, (double*)gm.b4, dh3.data());
+    for (int i = 0; i < h; ++i) dz3[i] = m3[i] ? dh3[i] : 0.0;
+    dense_backward_abs(n.W3, h, h + n.dd, in3.data(), dz3.data(), (double*)gm.W3, (double*)gm.b3, din3.data());
+    dense_backward_abs(n.Wf, h, h, h2.data(), din3.data(), (double*)gm.Wf, (double*)gm.bf, tmp.data());
+    for (int i = 0; i < h; ++i) dh2[i] += tmp[i];
+    double dzs = dsig_mag * sigmoid(a.zs);
+    dense_backward_abs(n.ws, 1, h, h2.data(), &dzs, (double*)gm.ws, (double*)gm.bs, tmp.data());
+    for (int i = 0; i < h; ++i) dh2[i] += tmp[i];
+    for (int i = 0; i < h; ++i) dz2[i] = m2[i] ? dh2[i] : 0.0;
+    dense_backward_abs(n.W2, h, h, h1.data(), dz2.data(), (double*)gm.W2, (double*)gm.b2, dh1.data());
+    for (int i = 0; i < h; ++i) dz1[i] = m1[i] ? dh1[i] : 0.0;
+    dense_backward_abs(n.W1, h, n.dx, gx.data(), dz1.data(), (double*)gm.W1, (double*)gm.b1, nullptr);
+    if (!gk) return;
+
+    // terms through units within tau of their kink: seeds at layer 3, then the
+    // path below it joined by the seeds of layers 2 and 1 (all linear in the seeds)
+    std::vector<double> k3(h, 0.0), kin3(h + n.dd), kh2(h), kz2(h), kh1(h), kz1(h);
+    bool any = false;
+    for (int i = 0; i < h; ++i)
+        if (std::fabs(a.z3[i]) <= tau) { k3[i] = dh3[i]; any = true; }
+    dense_backward_abs(n.W3, h, h + n.dd, in3.data(), k3.data(), (double*)gk->W3, (double*)gk->b3, kin3.data());
+    dense_backward_abs(n.Wf, h, h, h2.data(), kin3.data(), (double*)gk->Wf, (double*)gk->bf, kh2.data());
+    for (int i = 0; i < h; ++i) {
+        kz2[i] = m2[i] ? kh2[i] : 0.0;
+        if (std::fabs(a.z2[i]) <= tau) { kz2[i] += dh2[i]; any = true; }
+    }
+    dense_backward_abs(n.W2, h, h, h1.data(), kz2.data(), (double*)gk->W2, (double*)gk->b2, kh1.data());
+    for (int i = 0; i < h; ++i) {
+        kz1[i] = m1[i] ? kh1[i] : 0.0;
+        if (std::fabs(a.z1[i]) <= tau) { kz1[i] += dh1[i]; any = true; }
+    }
+    dense_backward_abs(n.W1, h, n.dx, gx.data(), kz1.data(), (double*)gk->W1, (double*)gk->b1, nullptr);
+    (void)any;
+}
+
 // ---------------------------------------------------------------------------
 // Compositing (Sec. 3.2, Eq.4 and Eq.5): with tau_k = sigma_k delta_k,
 //   w_i = exp(-sum_{k<i} tau_k) (1 - exp(-tau_i)),
@@ -389,6 +477,37 @@ void composite_backward(int n, const double* sigma, const double* rgb, const dou
             drgb[3 * i + c] = w[i] * g[c];
         }
         dsigma[i] = delta[i] * (T_next * cg + (ORC_PLANT == 10 ? rg : -rg));
+    }
+}
+
+// Magnitudes of the compositing gradients (see local_magnitude): with
+// colours, weights and transmittances non-negative and gm[c] >= |dL/dC_c|,
+//   drgb_mag_i = w_i gm,
+//   dsig_mag_i = delta_i [T_{i+1} (c_i . gm) + ((C + C_{<=i}) . gm)],
+// the tail C - C_{<=i} taken at the magnitude of its two sums.
+void composite_magnitude(int n, const double* sigma, const double* rgb, const double* delta, const double gm[3],
+                         double* dsig_mag, double* drgb_mag) {
+    std::vector<double> w(n);
+    double C[3] = {0, 0, 0};
+    double S = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double tau = sigma[i] * delta[i];
+        w[i] = std::exp(-S) * (-std::expm1(-tau));
+        for (int c = 0; c < 3; ++c) C[c] += w[i] * rgb[3 * i + c];
+        S += tau;
+    }
+    double Cle[3] = {0, 0, 0};
+    S = 0.0;
+    for (int i = 0; i < n; ++i) {
+        S += sigma[i] * delta[i];
+        double cg = 0.0, rg = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            Cle[c] += w[i] * rgb[3 * i + c];
+            cg += rgb[3 * i + c] * gm[c];
+            rg += (C[c] + Cle[c]) * gm[c];
+            drgb_mag[3 * i + c] = w[i] * gm[c];
+        }
+        dsig_mag[i] = delta[i] * (std::exp(-S) * cg + rg);
     }
 }
 
@@ -768,20 +887,31 @@ void orc_sample_outputs(const OrcScene* s, int64_t N, const float* o, const floa
 // ---- training: L = 1/(3B) sum_rays sum_ch (C - C*)^2, gradient w.r.t. all
 // local-field weights (Sec. 4.2 fine-tuning with an L2 photometric loss).
 // grad is [n_fields][P] FP64 (overwritten). Returns the loss.
+// grad_mag (optional, [n_fields][P]) receives the magnitude of each gradient
+// entry (local_magnitude, composite_magnitude; dL/dC at the magnitude
+// 2 (|C| + |C*|) / (3B) of its difference), for error bounds of other
+// implementations: a rounding of relative size u in every term of an entry
+// moves it by at most u times its magnitude. grad_kink (optional, with
+// grad_mag) receives the magnitude of the terms through ReLU units whose
+// pre-activation lies within tau of zero (see local_magnitude).
 double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float* d, const float* target /*[3][N]*/,
-                      double* grad, double* rgb_out /*[3][N] or null*/, int nthreads) {
+                      double* grad, double* rgb_out /*[3][N] or null*/, int nthreads, double* grad_mag,
+                      double tau, double* grad_kink) {
     const int dx = 3 + 6 * s->L_xyz, dd = 3 + 6 * s->L_dir;
     const size_t P = local_params(s->hidden, dx, dd);
     const size_t GP = P * s->n_fields;
     std::vector<double> wd = widen(s->weights, GP);
     int nt = std::max(1, nthreads);
     std::vector<std::vector<double>> gth(nt, std::vector<double>(GP, 0.0));
+    std::vector<std::vector<double>> mth(grad_mag ? nt : 0, std::vector<double>(GP, 0.0));
+    std::vector<std::vector<double>> kth(grad_mag && grad_kink ? nt : 0, std::vector<double>(GP, 0.0));
     std::vector<double> lth(nt, 0.0);
     parallel_for(N, nt, [&](int64_t b, int64_t e, int t) {
         std::vector<Seg> segs(s->max_samples);
         std::vector<LocalAct> acts(s->max_samples);
         std::vector<double> sig(s->max_samples), col(3 * s->max_samples), tm(s->max_samples), de(s->max_samples);
         std::vector<double> dsig(s->max_samples), dcol(3 * s->max_samples);
+        std::vector<double> msig(s->max_samples), mcol(3 * s->max_samples);
         for (int64_t r = b; r < e; ++r) {
             float oo[3] = {o[r], o[N + r], o[2 * N + r]}, dv[3] = {d[r], d[N + r], d[2 * N + r]};
             int n = sample_ray(*s, oo, dv, segs.data());
@@ -810,6 +940,19 @@ double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float*
                 LocalNet gn = local_view(gth[t].data() + P * segs[k].field, s->hidden, dx, dd);
                 local_backward(net, acts[k], dsig[k], &dcol[3 * k], gn);
             }
+            if (grad_mag) {
+                double gm[3];
+                for (int c = 0; c < 3; ++c)
+                    gm[c] = 2.0 * (std::fabs(C[c]) + std::fabs((double)target[c * N + r])) / (3.0 * N);
+                composite_magnitude(n, sig.data(), col.data(), de.data(), gm, msig.data(), mcol.data());
+                for (int k = 0; k < n; ++k) {
+                    LocalNet net = local_view(wd.data() + P * segs[k].field, s->hidden, dx, dd);
+                    LocalNet gmv = local_view(mth[t].data() + P * segs[k].field, s->hidden, dx, dd);
+                    LocalNet gkv;
+                    if (grad_kink) gkv = local_view(kth[t].data() + P * segs[k].field, s->hidden, dx, dd);
+                    local_magnitude(net, acts[k], msig[k], &mcol[3 * k], gmv, tau, grad_kink ? &gkv : nullptr);
+                }
+            }
         }
     });
     double loss = 0.0;
@@ -817,6 +960,16 @@ double orc_train_grad(const OrcScene* s, int64_t N, const float* o, const float*
     for (int t = 0; t < nt; ++t) {
         loss += lth[t];
         for (size_t i = 0; i < GP; ++i) grad[i] += gth[t][i];
+    }
+    if (grad_mag) {
+        for (size_t i = 0; i < GP; ++i) grad_mag[i] = 0.0;
+        for (int t = 0; t < nt; ++t)
+            for (size_t i = 0; i < GP; ++i) grad_mag[i] += mth[t][i];
+    }
+    if (grad_mag && grad_kink) {
+        for (size_t i = 0; i < GP; ++i) grad_kink[i] = 0.0;
+        for (int t = 0; t < nt; ++t)
+            for (size_t i = 0; i < GP; ++i) grad_kink[i] += kth[t][i];
     }
     return loss;
 }

@@ -34,6 +34,41 @@ def block_errors(g, ref, layout, floor_frac):
     return out
 
 
+def magnitude_errors(g, ref, mag, layout, eps, kink=None):
+    """Errors of a gradient against its reference, entry by entry, in units
+    of the bound eps * mag + kink: mag is the oracle's magnitude of each entry
+    (the same sums with every operand taken by absolute value, so |ref| <=
+    mag; a rounding of relative size u in every term moves an entry by at
+    most u times it per rounding on its longest chain), kink the oracle's
+    magnitude of the terms through ReLU units whose pre-activation lies
+    within the compared computation's pre-activation error of zero (such a
+    unit may take the other branch and add or drop its term whole). One
+    (max over the block of |g - ref| / bound, field, tensor name,
+    max|ref| / max mag) per (field, tensor) block, worst first; the bound
+    holds where every value is at most 1."""
+    g = np.atleast_2d(np.asarray(g, np.float64))
+    ref = np.atleast_2d(np.asarray(ref, np.float64))
+    mag = np.atleast_2d(np.asarray(mag, np.float64))
+    kin = np.zeros_like(mag) if kink is None else np.atleast_2d(np.asarray(kink, np.float64))
+    out = []
+    off = 0
+    for name, shape in layout:
+        size = int(np.prod(shape))
+        sl = slice(off, off + size)
+        for f in range(ref.shape[0]):
+            m = mag[f, sl]
+            bound = eps * m + kin[f, sl]
+            d = np.abs(g[f, sl] - ref[f, sl])
+            if not m.any():
+                assert not d.any(), (f, name)      # untouched blocks are exactly zero
+                continue
+            err = float(np.max(np.where(bound > 0, d / np.where(bound > 0, bound, 1.0), np.where(d > 0, np.inf, 0.0))))
+            out.append((err, f, name, float(np.abs(ref[f, sl]).max() / m.max())))
+        off += size
+    out.sort(key=lambda e: -e[0])
+    return out
+
+
 def describe(errs, k=3):
     return ", ".join(f"{e:.3g} (field {f} {n}, scale {s:.3g})" for e, f, n, s in errs[:k])
 

@@ -498,6 +498,66 @@ def test_train_grad_finite_difference(orc):
     assert np.count_nonzero(grad) > 0.3 * grad.size
 
 
+def test_train_grad_magnitude_bounds_the_gradient(orc):
+    """The magnitude of each gradient entry (every operand of the forward and
+    backward taken by absolute value) bounds the entry by the triangle
+    inequality, is not changed by asking for it, and equals the entry where
+    all its terms are non-negative: with zero weight matrices, positive
+    biases and zero targets, dL/dC = 2C/(3B) >= 0, the colour layer sees
+    h3 = relu(b3) >= 0, so the W4 and b4 gradients are sums of non-negative
+    terms and their magnitudes are the gradients themselves."""
+    sc = synth.tiny_scene(6, 31, p_occ=0.5, n_fields=3, hidden=16, max_samples=20)
+    rng = np.random.default_rng(31)
+    N = 200
+    o = rng.uniform(-2, 2, size=(3, N)).astype(np.float32)
+    d = rng.normal(size=(3, N)); d /= np.linalg.norm(d, axis=0); d = d.astype(np.float32)
+    w0 = (sc.weights + rng.normal(size=sc.weights.shape).astype(np.float32) * 0.05).astype(np.float32)
+    target = rng.uniform(0, 1, (3, N)).astype(np.float32)
+    loss, grad, rgb = orc.train_grad(sc, o, d, target, weights=w0)
+    loss_m, grad_m, rgb_m, mag = orc.train_grad(sc, o, d, target, weights=w0, magnitude=True)
+    assert loss_m == loss and np.array_equal(grad_m, grad) and np.array_equal(rgb_m, rgb)
+    assert np.all(mag >= np.abs(grad) * (1 - 1e-12))
+    assert np.all(mag[grad != 0] > 0)
+    # cancellation is visible: some entries are far below their magnitude
+    ratio = np.abs(grad[mag > 0]) / mag[mag > 0]
+    assert ratio.min() < 1e-2 and np.median(ratio) > 1e-4
+
+    lay = synth.local_mlp_layout(16)
+    wz = np.zeros_like(w0)
+    off = {}
+    o_ = 0
+    for name, shape in lay:
+        size = int(np.prod(shape))
+        off[name] = (o_, o_ + size)
+        if len(shape) == 1:   # biases
+            wz[:, o_:o_ + size] = rng.uniform(0.1, 0.5, (sc.n_fields, size))
+        o_ += size
+    _, gz, _, mz = orc.train_grad(sc, o, d, np.zeros((3, N), np.float32), weights=wz, magnitude=True)
+    for name in ("W4", "b4"):
+        a, b = off[name]
+        assert np.any(gz[:, a:b] > 0)
+        assert np.array_equal(mz[:, a:b], gz[:, a:b]), name
+    a, b = off["bs"]
+    assert np.all(mz[:, a:b] >= np.abs(gz[:, a:b]))
+    # kink terms: none at tau = 0 (no pre-activation is exactly zero here),
+    # more with a wider band, and at most the magnitude itself
+    _, _, _, m0, k0 = orc.train_grad(sc, o, d, target, weights=w0, magnitude=True, kink=0.0)
+    _, _, _, m1, k1 = orc.train_grad(sc, o, d, target, weights=w0, magnitude=True, kink=1e-2)
+    _, _, _, m2, k2 = orc.train_grad(sc, o, d, target, weights=w0, magnitude=True, kink=1e9)
+    assert np.array_equal(m0, mag) and np.array_equal(m1, mag)
+    assert not k0.any() and np.all(k1 >= 0) and np.any(k1 > 0) and np.all(k2 >= k1)
+    # with every unit in the band, the kink terms contain every term that
+    # passes a ReLU unit (W1..W3, Wf and their biases reach the loss through
+    # one; inactive units and paths through several units add more), and
+    # none of the heads that pass none (W4, b4 and the density head)
+    for name in ("W1", "b1", "W2", "b2", "Wf", "bf", "W3", "b3"):
+        a, b = off[name]
+        assert np.all(k2[:, a:b] >= mag[:, a:b] * (1 - 1e-12)) and np.any(k2[:, a:b] > mag[:, a:b]), name
+    for name in ("W4", "b4", "ws", "bs"):
+        a, b = off[name]
+        assert not k2[:, a:b].any(), name
+
+
 # ---------------------------------------------------------------------------
 # Global omnidirectional field
 # ---------------------------------------------------------------------------
