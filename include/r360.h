@@ -207,6 +207,31 @@ r360_status r360_render_rays(const r360_scene* scene, const float* o, const floa
                              const r360_render_opts* opts, float* rgb, float* depth, float* opacity,
                              void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): r360_render_rays with its
+ * workspace in a library-owned device array of R360_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) per GPU instead of a caller workspace. It calls no hipMalloc,
+ * hipFree or allocating library routine; the array is set aside when the
+ * library's code is loaded on a device and stays there until the process
+ * ends. Each call carves it as a render-only workspace:
+ * 36 B per sample slot (ceil(N / 64) * 64 * max_samples slots), 28 B per ray,
+ * 4 * n_fields * W B of per-wave field counts (W = 8192 for up to 512
+ * fields, halved while W * n_fields exceeds 4 Mi and W > 256) and a few KB;
+ * a call that needs more returns R360_EWORKSPACE with the bytes it needs
+ * (split the rays into smaller calls; the room scene's 141 fields leave
+ * room for about 3.4 M slots, e.g. 53,000 rays at max_samples 64). Early ray
+ * termination (term_eps > 0) is not offered here: it waits on the stream
+ * between its passes (R360_EUNSUPPORTED). Arguments, outputs and errors
+ * otherwise as r360_render_rays; the stream must belong to the current
+ * device. Every call on one GPU uses that GPU's one array and overwrites
+ * what the last call left there: calls that overlap on one GPU (different
+ * streams, or host threads without ordering) race and give wrong results;
+ * calls in order on one stream do not. */
+#define R360_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+r360_status r360_render_rays_noalloc(const r360_scene* scene, const float* o, const float* d, int64_t N,
+                                     const r360_render_opts* opts, float* rgb, float* depth, float* opacity,
+                                     void* stream);
+
 /* Render a whole equirect view (W*H rays from the table's resolution) from
  * camera c2w_host. Outputs [3][H][W], [H][W], [H][W]. */
 r360_status r360_render_equirect(const r360_scene* scene, const r360_equirect* eq, const float c2w_host[12],

@@ -77,6 +77,7 @@ SIGNATURES = {
     "r360_workspace_bytes": (sz, [vp, i64, i32]),
     "r360_sample_rays": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), C.POINTER(i64), vp, vp, vp, vp, vp, vp, vp, sz, vp]),
     "r360_render_rays": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),
+    "r360_render_rays_noalloc": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, vp]),
     "r360_render_equirect": (i32, [vp, vp, F12, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),
     "r360_render_pinhole": (i32, [vp, i32, i32, f32, f32, F12, C.POINTER(RenderOpts), vp, vp, vp, vp, sz, vp]),
     "r360_backward": (i32, [vp, vp, vp, i64, C.POINTER(RenderOpts), vp, vp, vp, sz, vp]),

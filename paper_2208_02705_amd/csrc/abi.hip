@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "r360_internal.h"
@@ -94,16 +95,18 @@ namespace r360 {
 
 int64_t sample_cap(int64_t N, int max_samples) { return (N + 63) / 64 * 64 * (int64_t)max_samples; }
 
-Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P) {
+Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P, bool train) {
     Workspace w{};
     const int64_t cap = sample_cap(N, max_samples);
     char* p = static_cast<char*>(base);
     size_t off = 0;
-    auto take = [&](size_t bytes) -> char* {
+    auto take_always = [&](size_t bytes) -> char* {
         char* q = p ? p + off : nullptr;
         off += al(bytes);
         return q;
     };
+    auto take = [&](size_t bytes) -> char* { return take_always(bytes); };
+    auto take_train = [&](size_t bytes) -> char* { return train ? take_always(bytes) : nullptr; };
     w.ray_off = (int32_t*)take((N + 1) * 4);
     w.o = (float*)take(3 * N * 4);
     w.d = (float*)take(3 * N * 4);
@@ -114,17 +117,17 @@ Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P) {
     w.perm = (int32_t*)take(cap * 4);
     w.sigma = (float*)take(cap * 4);
     w.rgb = (float*)take(3 * cap * 4);
-    w.dsigma = (float*)take(cap * 4);
-    w.drgb = (float*)take(3 * cap * 4);
+    w.dsigma = (float*)take_train(cap * 4);
+    w.drgb = (float*)take_train(3 * cap * 4);
     w.scan = (int32_t*)take(((N + SCAN_TILE - 1) / SCAN_TILE + 1) * 4);
     w.hist = (int32_t*)take((size_t)F * route_waves(F) * 4);
     w.field_start = (int32_t*)take((F + 1) * 4);
-    w.dw_part = (float*)take((size_t)DW_SLOTS * P * 4);
-    w.blk_fields = (int32_t*)take(DW_SLOTS * 4);
+    w.dw_part = (float*)take_train((size_t)DW_SLOTS * P * 4);
+    w.blk_fields = (int32_t*)take_train(DW_SLOTS * 4);
     w.misc = (int32_t*)take(256 * 4);
-    w.loss_part = (float*)take(((N + 255) / 256) * 4);
-    w.ray_rgb = (float*)take(3 * N * 4);
-    w.ray_grad = (float*)take(3 * N * 4);
+    w.loss_part = (float*)take_train(((N + 255) / 256) * 4);
+    w.ray_rgb = (float*)take_train(3 * N * 4);
+    w.ray_grad = (float*)take_train(3 * N * 4);
     w.N = N;
     w.cap = cap;
     w.slots = slot_map(max_samples);
@@ -288,6 +291,35 @@ bool valid_c2w(const float* c) {
     return true;
 }
 
+}  // namespace
+
+// ---- allocation-free render: the workspace is a file-scope device array ----
+// In host code `scratch` names a host-side stand-in, not device memory: the
+// device address (one copy per GPU) comes from hipGetSymbolAddress with that
+// GPU current, taken once per device and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[R360_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kScratchDevices] = {};
+
+r360_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail("hipGetDevice", e);
+    if (dev < 0 || dev >= kScratchDevices) return inval("device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail("hipGetSymbolAddress(scratch)", e);
+        if (!p || (reinterpret_cast<uintptr_t>(p) & 255)) return inval("scratch array not 256-byte aligned");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return R360_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -579,6 +611,37 @@ r360_status r360_render_rays(const r360_scene* s, const float* o, const float* d
     Workspace w;
     r360_status st = prepare(s, N, opts, ws, ws_bytes, false, &w, true);
     if (st != R360_OK) return st;
+    RaySource src{};
+    src.mode = RAYS_GIVEN;
+    src.o = o;
+    src.d = d;
+    return render_common(s, src, N, opts, rgb, depth, opacity, w, S(stream));
+}
+
+r360_status r360_render_rays_noalloc(const r360_scene* s, const float* o, const float* d, int64_t N,
+                                     const r360_render_opts* opts, float* rgb, float* depth, float* opacity,
+                                     void* stream) {
+    if (!o || !d || !rgb || !depth || !opacity) return inval("NULL pointer");
+    if (!s) return inval("scene is NULL");
+    r360_status st = check_opts(opts, false);
+    if (st != R360_OK) return st;
+    if (opts->term_eps > 0.0f) {
+        std::snprintf(g_err, sizeof(g_err), "early ray termination waits on the stream; use r360_render_rays");
+        return R360_EUNSUPPORTED;
+    }
+    if (N <= 0 || N > (int64_t(1) << 30)) return inval("N must be in [1, 2^30]");
+    if (sample_cap(N, opts->max_samples) >= (int64_t(1) << 30))
+        return inval("N * max_samples must stay below 2^30; split the rays");
+    const size_t need = carve(nullptr, N, opts->max_samples, s->mlp.n_fields, s->P, false).bytes;
+    if (need > R360_NOALLOC_SCRATCH_BYTES) {
+        std::snprintf(g_err, sizeof(g_err), "needs %zu bytes of scratch, the library's array holds %zu; split the rays",
+                      need, (size_t)R360_NOALLOC_SCRATCH_BYTES);
+        return R360_EWORKSPACE;
+    }
+    void* base = nullptr;
+    st = scratch_of_current_device(&base);
+    if (st != R360_OK) return st;
+    Workspace w = carve(base, N, opts->max_samples, s->mlp.n_fields, s->P, false);
     RaySource src{};
     src.mode = RAYS_GIVEN;
     src.o = o;

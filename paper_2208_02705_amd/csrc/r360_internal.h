@@ -431,7 +431,9 @@ constexpr int DW_SLOTS = 1024;            // two gradient partial slots per back
 // max_samples (the traversal stages sample k of ray r at slot
 // (r - r % 64) * max_samples + 64 k + r % 64).
 int64_t sample_cap(int64_t N, int max_samples);
-Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P);
+// train = false leaves out what only training and early termination use
+// (the gradient, partial and per-ray training arrays; those pointers are null).
+Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P, bool train = true);
 
 // launchers (return hipError_t of the launch)
 enum RayMode { RAYS_GIVEN = 0, RAYS_EQUIRECT = 1, RAYS_PINHOLE = 2 };

@@ -243,6 +243,22 @@ def render_rays(scene: Scene, o: torch.Tensor, d: torch.Tensor, *, precision="fp
     return rgb, depth, opac
 
 
+def render_rays_noalloc(scene: Scene, o: torch.Tensor, d: torch.Tensor, rgb: torch.Tensor, depth: torch.Tensor,
+                        opacity: torch.Tensor, *, precision="fp32", near=None, far=None, max_samples=None):
+    """render_rays into caller-owned outputs (rgb [3, N], depth [N], opacity
+    [N], FP32 on the rays' device) with the library's own device scratch in
+    place of a workspace: no device memory is allocated by this call."""
+    o = _dev(o, torch.float32, "o"); d = _dev(d, torch.float32, "d")
+    N = o.shape[1]
+    for name, t, shape in (("rgb", rgb, (3, N)), ("depth", depth, (N,)), ("opacity", opacity, (N,))):
+        if tuple(t.shape) != shape or t.dtype != torch.float32 or t.device != o.device or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shape} on {o.device}")
+    opts = _opts(scene, near, far, max_samples, precision)
+    check(lib().r360_render_rays_noalloc(scene._h, _ptr(o), _ptr(d), N, C.byref(opts), _ptr(rgb), _ptr(depth),
+                                         _ptr(opacity), _stream()))
+    return rgb, depth, opacity
+
+
 class EquirectRenderer:
     """Renders W x H equirect views; owns the tables and output buffers."""
 

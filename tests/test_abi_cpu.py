@@ -54,6 +54,7 @@ def test_null_arguments_rejected_before_launch(L):
     assert L.r360_workspace_bytes(None, 10, 4) == 0
     opts = _lib.RenderOpts(0.0, 1.0, 4, 0)
     assert L.r360_render_rays(None, None, None, 4, C.byref(opts), None, None, None, None, 0, None) == _lib.R360_EINVAL
+    assert L.r360_render_rays_noalloc(None, None, None, 4, C.byref(opts), None, None, None, None) == _lib.R360_EINVAL
     assert L.r360_adam_step(None, None, None, None, 4, 1, 1e-3, 0.9, 0.99, 1e-8, None) == _lib.R360_EINVAL
     assert L.r360_train_step(None, None, None, 4, None, C.byref(opts), None, None, None, None, 0, None) == _lib.R360_EINVAL
 
