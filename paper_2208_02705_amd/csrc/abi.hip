@@ -122,6 +122,7 @@ Workspace carve(void* base, int64_t N, int max_samples, int F, int64_t P, bool t
     w.scan = (int32_t*)take(((N + SCAN_TILE - 1) / SCAN_TILE + 1) * 4);
     w.hist = (int32_t*)take((size_t)F * route_waves(F) * 4);
     w.field_start = (int32_t*)take((F + 1) * 4);
+    w.chunk_start = (int32_t*)take_train((F + 1) * 4);
     w.dw_part = (float*)take_train((size_t)DW_SLOTS * P * 4);
     w.blk_fields = (int32_t*)take_train(DW_SLOTS * 4);
     w.misc = (int32_t*)take(256 * 4);

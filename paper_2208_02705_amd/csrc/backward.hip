@@ -17,8 +17,16 @@
 //     samples run along k, and every wave accumulates its share of the
 //     16x16 tiles of dW = dz x^T (the bias gradient rides along as a row of
 //     ones in x).
+// The work is cut into chunks that never straddle a field (a field of n
+// samples has ceil(n / 128) of them) and shared out by cost: a chunk counts
+// two units and each field a block enters one more (loading its weight
+// fragments and writing its gradient cost about half a chunk), and block b
+// of nb takes the chunks whose first unit lies in [b U / nb, (b + 1) U / nb)
+// of the U in field order. Blocks then differ by about one chunk whatever
+// the field sizes (an equal share of samples would give a block one extra,
+// mostly empty chunk and a field switch per field it touches).
 // The weight-gradient tiles stay in registers while the block stays on one
-// field. A field that lies entirely inside one block's slice is written to
+// field. A field that lies entirely inside one block's range is written to
 // the gradient directly; the pieces of fields shared by neighbouring blocks
 // go to two per-block partial slots and a reduction kernel adds them in block
 // order, so the result does not depend on scheduling.
@@ -46,7 +54,48 @@ __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) 
 __device__ __forceinline__ int xcd_block(int b, int nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
 constexpr int BW = 8;                           // waves per backward block
 constexpr int BCH = 16 * BW;                    // samples per backward chunk
-__device__ __forceinline__ int slice_len(int S, int nb) { return (((S + nb - 1) / nb) + BCH - 1) / BCH * BCH; }
+// Work units: field f (n_f samples, c_f = ceil(n_f / BCH) chunks) spans
+// units [u_f, u_f + 2 c_f + 1) (none if n_f = 0); its chunk j starts at
+// unit u_f + 2 j. Block b of nb owns units [b U / nb, (b + 1) U / nb), and
+// with them the chunks that start there; unit u belongs to block
+// ceil((u + 1) nb / U) - 1.
+constexpr int UNITS_PER_CHUNK = 2;
+__device__ __forceinline__ int unit_lo(int b, int U, int nb) { return (int)((int64_t)b * U / nb); }
+__device__ __forceinline__ int block_of_unit(int u, int U, int nb) {
+    return (int)(((int64_t)(u + 1) * nb + U - 1) / U) - 1;
+}
+// The chunks [*j0, *j1) of the field whose units start at uf (c chunks) that
+// start inside [lo, hi).
+__device__ __forceinline__ void chunks_in(int uf, int c, int lo, int hi, int* j0, int* j1) {
+    const int a = max(lo, uf) - uf, e = min(hi, uf + UNITS_PER_CHUNK * c) - uf;
+    *j0 = (a + UNITS_PER_CHUNK - 1) / UNITS_PER_CHUNK;
+    *j1 = e > 0 ? (e + UNITS_PER_CHUNK - 1) / UNITS_PER_CHUNK : 0;
+}
+
+// unit_start[f] = sum over g < f of (n_g > 0 ? 2 ceil(n_g / BCH) + 1 : 0),
+// unit_start[F] = U (n_g = start[g + 1] - start[g]); one block of 1024 threads.
+__global__ __launch_bounds__(1024) void k_chunk_starts(const int32_t* __restrict__ start, int F,
+                                                       int32_t* __restrict__ chunk_start) {
+    __shared__ int32_t sc[1024];
+    int carry = 0;
+    for (int base = 0; base < F; base += 1024) {
+        const int i = base + (int)threadIdx.x;
+        const int n = i < F ? start[i + 1] - start[i] : 0;
+        const int v = n > 0 ? UNITS_PER_CHUNK * ((n + BCH - 1) / BCH) + 1 : 0;
+        sc[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {          // inclusive scan in LDS
+            const int t = threadIdx.x >= (unsigned)off ? sc[threadIdx.x - off] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < F) chunk_start[i] = carry + sc[threadIdx.x] - v;
+        carry += sc[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) chunk_start[F] = carry;
+}
 
 // ---------------------------------------------------------------------------
 // Transposed fragments for the input-gradient chain. Fragment (ot, ks) of a
@@ -125,8 +174,8 @@ __device__ __forceinline__ int dw_index(int ly, int out, int in) {
 }
 
 struct BwdArgs {
-    const int32_t* total;       // field_start + F: number of samples
     const int32_t* field_start;
+    const int32_t* chunk_start; // [F+1] prefix of the fields' work units
     const int32_t* perm;        // sorted position -> slot
     const float* t_mid;         // slot layout
     SlotMap slots;
@@ -238,12 +287,23 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     const int col = 16 * wv + j;                     // this lane's sample column in the panel
     const int nb = gridDim.x;
     const int b = xcd_block(blockIdx.x, nb);
-    const int S = *a.total;
-    const int per = slice_len(S, nb);
-    const int beg = min(S, b * per), end = min(S, beg + per);
-    if (beg >= end) return;
-    const int first = find_field(a.field_start, a.F, beg);
-    const int last = find_field(a.field_start, a.F, end - 1);
+    const int U = a.chunk_start[a.F];
+    const int u_lo = unit_lo(b, U, nb), u_hi = unit_lo(b + 1, U, nb);
+    // the first and last fields with a chunk that starts in this block's units
+    // (a unit maps to its field like a sample index: the last field whose
+    // first unit is not after it, which has units)
+    auto chunks_of = [&](int f, int* j0, int* j1) {
+        chunks_in(a.chunk_start[f], (a.field_start[f + 1] - a.field_start[f] + BCH - 1) / BCH, u_lo, u_hi, j0, j1);
+    };
+    int first = -1, last = -1;
+    for (int u = u_lo; u < u_hi;) {
+        const int f = find_field(a.chunk_start, a.F, u);
+        int j0, j1;
+        chunks_of(f, &j0, &j1);
+        if (j1 > j0) { if (first < 0) first = f; last = f; }
+        u = a.chunk_start[f + 1];
+    }
+    if (first < 0) return;
     if (threadIdx.x == 0) { a.blk_fields[2 * b] = first; a.blk_fields[2 * b + 1] = last; }
     const F8* pk = reinterpret_cast<const F8*>(a.pack);
     const F8* pt = reinterpret_cast<const F8*>(a.packT);
@@ -251,9 +311,13 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
     auto zero = [](f32x4* v, int n) { for (int q = 0; q < n; ++q) v[q] = f32x4{0.f, 0.f, 0.f, 0.f}; };
     zero(w1, N1); zero(w2, N2); zero(wh, NH); zero(w3, N3); zero(w4, N4);
 
-    for (int pos = beg; pos < end;) {
-        const int f = find_field(a.field_start, a.F, pos);
-        const int fend = min(end, a.field_start[f + 1]);
+    for (int f = first; f <= last; ++f) {
+        int j0, j1;
+        chunks_of(f, &j0, &j1);
+        if (j1 <= j0) continue;                                   // an empty field between first and last
+        const int fs0 = a.field_start[f];
+        const int pos = fs0 + j0 * BCH;                             // this block's samples of field f
+        const int fend = min(a.field_start[f + 1], fs0 + j1 * BCH);
         // the encoding frame of this field
         const float cc[3] = {a.frames ? a.frames[4 * f] : a.c0, a.frames ? a.frames[4 * f + 1] : a.c1,
                              a.frames ? a.frames[4 * f + 2] : a.c2};
@@ -261,11 +325,24 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
         const F8* P = pk + (int64_t)f * G::FRAGS16 * WAVE + lane;
         const F8* PT = pt + (int64_t)f * G::FRAGS_T * WAVE + lane;
         if constexpr (WL) {
-            __syncthreads();                      // every wave is done with the previous field's fragments
+            // all of a thread's fragment loads are issued before its first LDS
+            // store, so the copy waits for memory once rather than per fragment
+            constexpr int NFP = G::FRAGS16 * WAVE, NFR = (G::FRAGS16 + G::FRAGS_T) * WAVE;
+            constexpr int NIT = (NFR + 64 * BW - 1) / (64 * BW);
             const F8* srcP = pk + (int64_t)f * G::FRAGS16 * WAVE;
             const F8* srcT = pt + (int64_t)f * G::FRAGS_T * WAVE;
-            for (int i = threadIdx.x; i < G::FRAGS16 * WAVE; i += 64 * BW) wlds[i] = srcP[i];
-            for (int i = threadIdx.x; i < G::FRAGS_T * WAVE; i += 64 * BW) wlds[G::FRAGS16 * WAVE + i] = srcT[i];
+            F8 stage[NIT];
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int i = (int)threadIdx.x + 64 * BW * it;
+                if (i < NFR) stage[it] = i < NFP ? srcP[i] : srcT[i - NFP];
+            }
+            __syncthreads();                      // every wave is done with the previous field's fragments
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int i = (int)threadIdx.x + 64 * BW * it;
+                if (i < NFR) wlds[i] = stage[it];
+            }
             __syncthreads();
         }
         const f32x4* bias = reinterpret_cast<const f32x4*>(a.bias + (int64_t)f * G::BIAS_FLOATS) + g;
@@ -534,36 +611,58 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 xh[k] = (__builtin_fmaf(t_n, d_n[k], o_n[k]) - cc[k]) * inv_h;
             }
         }
-        // flush this field's tiles
+        // flush this field's tiles: every wave scatters its tiles into the
+        // panel area (free now) in canonical parameter order, then the block
+        // writes the field's P floats out in whole pieces
         float* dst;
         if (f == first) dst = a.part + (int64_t)(2 * b) * a.P;
         else if (f == last) dst = a.part + (int64_t)(2 * b + 1) * a.P;
         else dst = a.grad + (int64_t)f * a.P;
-        dw_flush<H, N1>(LY_L1, NT, 4, wv, lane, w1, dst);
-        dw_flush<H, N2>(LY_L2, NT, NT + 1, wv, lane, w2, dst);
-        dw_flush<H, NH>(LY_HD, NT + 1, NT + 1, wv, lane, wh, dst);
-        dw_flush<H, N3>(LY_L3, NT, NT + 2, wv, lane, w3, dst);
-        dw_flush<H, N4>(LY_L4, 1, NT + 1, wv, lane, w4, dst);
-        pos = fend;
+        constexpr int PF = FieldLayout{H}.P();
+        static_assert(PF % 4 == 0, "field parameters in whole 16-byte pieces");
+        static_assert(PF * sizeof(float) <= (DB ? 2 : 1) * BG::ROWS * BG::PSTRIDE * sizeof(T), "gradient fits the panels");
+        float* gst = reinterpret_cast<float*>(smem_raw);
+        __syncthreads();                                  // the last stage is done with the panels
+        for (int i = threadIdx.x; i < PF / 4; i += 64 * BW) reinterpret_cast<f32x4*>(gst)[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        __syncthreads();
+        dw_flush<H, N1>(LY_L1, NT, 4, wv, lane, w1, gst);
+        dw_flush<H, N2>(LY_L2, NT, NT + 1, wv, lane, w2, gst);
+        dw_flush<H, NH>(LY_HD, NT + 1, NT + 1, wv, lane, wh, gst);
+        dw_flush<H, N3>(LY_L3, NT, NT + 2, wv, lane, w3, gst);
+        dw_flush<H, N4>(LY_L4, 1, NT + 1, wv, lane, w4, gst);
+        __syncthreads();
+        if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+            for (int i = threadIdx.x; i < PF / 4; i += 64 * BW)
+                reinterpret_cast<f32x4*>(dst)[i] = reinterpret_cast<const f32x4*>(gst)[i];
+        } else {
+            for (int i = threadIdx.x; i < PF; i += 64 * BW) dst[i] = gst[i];
+        }
+        __syncthreads();                                  // before the panels are written again
     }
 }
 
 // Adds the partial slots of fields shared by several blocks, in block order.
 // bf: the first and last field of every block's slice (written by k_bwd).
 __global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, float* __restrict__ grad,
-                                                   const int32_t* __restrict__ start, const int32_t* __restrict__ total,
-                                                   const int32_t* __restrict__ bf, int P, int nb) {
+                                                   const int32_t* __restrict__ start,
+                                                   const int32_t* __restrict__ chunk_start,
+                                                   const int32_t* __restrict__ bf, int F, int P, int nb) {
     const int f = blockIdx.y;
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= P) return;
-    const int S = *total;
-    const int per = slice_len(S, nb);
-    const int fs = start[f], fe = start[f + 1];
-    if (fe <= fs) { grad[(int64_t)f * P + p] = 0.0f; return; }
-    const int b0 = fs / per, b1 = (fe - 1) / per;
+    const int U = chunk_start[F];
+    const int uf = chunk_start[f];
+    const int c = (start[f + 1] - start[f] + BCH - 1) / BCH;
+    if (c == 0) { grad[(int64_t)f * P + p] = 0.0f; return; }
+    const int b0 = block_of_unit(uf, U, nb), b1 = block_of_unit(uf + UNITS_PER_CHUNK * (c - 1), U, nb);
     if (b0 == b1 && f != bf[2 * b0] && f != bf[2 * b0 + 1]) return;   // written directly
     float acc = 0.0f;
     for (int b = b0; b <= b1; ++b) {
+        // blocks where no chunk of this field starts (with fewer units than
+        // blocks, empty ones lie in between) wrote nothing for it
+        int j0, j1;
+        chunks_in(uf, c, unit_lo(b, U, nb), unit_lo(b + 1, U, nb), &j0, &j1);
+        if (j1 <= j0) continue;
         const int slot = (f == bf[2 * b]) ? 2 * b : 2 * b + 1;
         acc += part[(int64_t)slot * P + p];
     }
@@ -589,8 +688,8 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
                       hipStream_t st) {
     using BG = BwdGeom<H>;
     BwdArgs a;
-    a.total = w.field_start + s->mlp.n_fields;
     a.field_start = w.field_start;
+    a.chunk_start = w.chunk_start;
     a.perm = w.perm;
     a.t_mid = w.t_mid;
     a.slots = w.slots;
@@ -620,11 +719,12 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
         if (e != hipSuccess) return e;
         nb = resident(k_bwd<H, T>, lds);
     }
+    hipLaunchKernelGGL(k_chunk_starts, dim3(1), dim3(1024), 0, st, w.field_start, a.F, w.chunk_start);
     hipLaunchKernelGGL((k_bwd<H, T>), dim3(nb), dim3(64 * BW), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dw_reduce, dim3((a.P + 255) / 256, a.F), dim3(256), 0, st, w.dw_part, grad, w.field_start,
-                       a.total, w.blk_fields, a.P, nb);
+                       w.chunk_start, w.blk_fields, a.F, a.P, nb);
     return hipGetLastError();
 }
 

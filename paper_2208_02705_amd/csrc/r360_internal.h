@@ -409,6 +409,7 @@ struct Workspace {
     int32_t* scan;      // scan block sums
     int32_t* hist;      // [F][ROUTE_WAVES]
     int32_t* field_start;  // [F+1]
+    int32_t* chunk_start;  // [F+1]   backward: prefix of the fields' work units (128-sample chunks and field switches)
     float* dw_part;     // [DW_SLOTS][P] per-slot gradient partials
     int32_t* blk_fields;  // [DW_SLOTS] first and last field of each backward block's slice
     int32_t* misc;      // small counters

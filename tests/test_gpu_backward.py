@@ -255,3 +255,27 @@ def test_fp64_gradcheck_with_field_frames(R, orc):
     _, g_ref, _ = orc.train_grad(sc, o, d, target, weights=w64.detach().cpu().numpy().astype(np.float32))
     assert _rel_err(_np(w64.grad), g_ref) <= 1e-4
     scene.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_train_step_reads_nothing_it_did_not_write(R, orc, prec):
+    """A training step whose workspace and gradient buffer start as NaN bytes
+    gives the oracle's gradient: no stage reads scratch memory that the call
+    itself has not written. The batch has fewer 128-sample chunks than the
+    backward has blocks, so blocks without work lie between the blocks that
+    share a field (their partial slots are never written and must not be
+    read)."""
+    import torch
+    sc = synth.tiny_scene(8, 45, p_occ=0.5, n_fields=3, hidden=32, max_samples=16)
+    scene = R.Scene.from_synth(sc)
+    o, d, tgt = _rays(700, 45)
+    ws = scene.workspace(o.shape[1], sc.max_samples)
+    ws.fill_(255)
+    grad = torch.full((scene.n_fields, scene.P), float("nan"), device="cuda")
+    loss, grad = R.train_step(scene, _t(o), _t(d), _t(tgt), precision=prec, grad=grad)
+    l_ref, g_ref, _ = orc.train_grad(sc, o, d, tgt)
+    g = _np(grad)
+    assert not np.isnan(g).any()
+    assert abs(float(_np(loss)[0]) - l_ref) <= (1e-5 if prec == "fp32" else 1e-2) * l_ref
+    assert _rel_err(g, g_ref) <= (FP32_GRAD if prec == "fp32" else X16_GRAD)
+    scene.close()
