@@ -209,19 +209,27 @@ struct BwdGeom {
     static constexpr int PSTRIDE = BCH + 8;        // samples per panel row, padded
 };
 
+// Tiles of one layer's OT x IT weight-gradient grid (row-major) held by wave
+// wv: the contiguous range [wv T / BW, (wv + 1) T / BW) (wv is wave-uniform).
+__device__ __forceinline__ int tile_lo(int wv, int T) { return wv * T / BW; }
+
 // One layer's weight-gradient stage: the panel holds x rows [0, XR) and dz
-// rows [XR, XR + 16 OT) for the chunk's samples; wave wv accumulates tiles
-// k = wv, wv + BW, ... of the OT x IT tile grid.
+// rows [XR, XR + 16 OT) for the chunk's samples; wave wv accumulates its
+// tiles one after the other. (Keeping a tile's dz fragments for the next
+// tile that shares them, or running the k-steps outermost, cuts the LDS
+// reads by about a third but was measured no faster: the stage waits on
+// latency, not on LDS bandwidth.)
 template <typename T, int NACC>
 __device__ __forceinline__ void dw_stage(const T* panel, int pstride, int XR, int OT, int IT, int wv, int lane,
                                          f32x4* acc) {
     using F8 = typename FragT<T>::type;
     const int g = lane >> 4, l16 = lane & 15;
+    const int t0 = tile_lo(wv, OT * IT), t1 = tile_lo(wv + 1, OT * IT);
 #pragma unroll
     for (int q = 0; q < NACC; ++q) {
-        const int k = wv + BW * q;
+        const int k = t0 + q;
         __builtin_amdgcn_sched_barrier(0);
-        if (k < OT * IT) {
+        if (k < t1) {
             const int ot = k / IT, it = k % IT;
 #pragma unroll
             for (int ks = 0; ks < BCH / 32; ++ks) {
@@ -233,17 +241,35 @@ __device__ __forceinline__ void dw_stage(const T* panel, int pstride, int XR, in
     }
 }
 
+// dz *= [h > 0] on hand-off fragments, h a ReLU output as stored (zero or
+// positive; in 16 bits, h > 0 exactly when its bits are not zero).
+template <typename T>
+__device__ __forceinline__ typename FragT<T>::type relu_mask(typename FragT<T>::type dz,
+                                                            typename FragT<T>::type h) {
+    if constexpr (__is_same(T, float)) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dz[e] = h[e] > 0.0f ? dz[e] : 0.0f;
+        return dz;
+    } else {
+        typedef __attribute__((ext_vector_type(8))) unsigned short u16x8;
+        const u16x8 one = __builtin_elementwise_min(__builtin_bit_cast(u16x8, h), (u16x8)1);
+        const u16x8 m = (u16x8)0 - one;                      // 0xffff where h > 0
+        return __builtin_bit_cast(typename FragT<T>::type, __builtin_bit_cast(u16x8, dz) & m);
+    }
+}
+
 template <int H, int NACC>
 __device__ __forceinline__ void dw_flush(int ly, int OT, int IT, int wv, int lane, f32x4* acc, float* dst) {
     // opaque copies: the flush indices are recomputed here, once per field,
     // instead of being hoisted out of the field loop into live registers
     asm volatile("" : "+v"(lane));
-    asm volatile("" : "+v"(wv));
+    asm volatile("" : "+s"(wv));
     const int g = lane >> 4, l16 = lane & 15;
+    const int t0 = tile_lo(wv, OT * IT), t1 = tile_lo(wv + 1, OT * IT);
 #pragma unroll
     for (int q = 0; q < NACC; ++q) {
-        const int k = wv + BW * q;
-        if (k < OT * IT) {
+        const int k = t0 + q;
+        if (k < t1) {
             const int ot = k / IT, it = k % IT;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -283,7 +309,8 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
         if constexpr (DB) panel = (panel == panels) ? panels + BG::ROWS * BG::PSTRIDE : panels;
         else __syncthreads();
     };
-    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int col = 16 * wv + j;                     // this lane's sample column in the panel
     const int nb = gridDim.x;
     const int b = xcd_block(blockIdx.x, nb);
@@ -495,12 +522,18 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
                     for (int rr = 0; rr < 4; ++rr) panel[(row0 + 16 * tt + 4 * g + rr) * PS + col] = (T)tl[tt][rr];
             };
-            auto mask = [&](f32x4* dz, const F8* hb) {   // dz *= [h > 0]
+            // tiles [0, ntl) of hand-off fragments (tile 2ks + e/4, row 4g + e%4)
+            auto put_frags = [&](int row0, const F8* fb_, int ntl) {
 #pragma unroll
-                for (int tt = 0; tt < NT; ++tt)
+                for (int ks = 0; ks < (ntl + 1) / 2; ++ks)
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr)
-                        if (!((float)hb[tt >> 1][4 * (tt & 1) + rr] > 0.0f)) dz[tt][rr] = 0.0f;
+                    for (int e = 0; e < 8; ++e)
+                        if (2 * ks + (e >> 2) < ntl) panel[(row0 + hidden_col16(ks, g, e)) * PS + col] = fb_[ks][e];
+            };
+            // dz in fragment form, masked by the layer input's ReLU
+            auto masked = [&](F8* bz, const f32x4* dz, const F8* hb) {
+#pragma unroll
+                for (int ks = 0; ks < KH; ++ks) bz[ks] = relu_mask<T>(hand<T, false>(dz[2 * ks], dz[2 * ks + 1]), hb[ks]);
             };
 
             __builtin_amdgcn_sched_barrier(0);
@@ -517,21 +550,20 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
                 for (int ot = 0; ot < NT; ++ot) dz[ot] = mma<T>(PTc[ot * WAVE], bz, f32x4{0.f, 0.f, 0.f, 0.f});
             }
-            mask(dz, h3);
+            F8 bz3[KH];
+            masked(bz3, dz, h3);
             __builtin_amdgcn_sched_barrier(0);
             // ---- L3: dW3 over [f ; g(d)] and df = W3_f^T dz3 ----
             put_hidden(0, fb);
 #pragma unroll
             for (int e = 0; e < 8; ++e) panel[(H + 8 * g + e) * PS + col] = xd[e];
-            put_tiles(H + 32, dz, NT);
+            put_frags(H + 32, bz3, NT);
             __syncthreads();
             dw_stage<T, N3>(panel, PS, H + 32, NT, NT + 2, wv, lane, w3);
             flip();
             f32x4 df[NT + 1];
             {
-                F8 bz[KH];
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) bz[ks] = hand<T, false>(dz[2 * ks], dz[2 * ks + 1]);
+                const F8* bz = bz3;
                 const F8* q3 = PTc + G::T_L4 * WAVE;
 #pragma unroll
                 for (int ot = 0; ot < NT; ++ot) {
@@ -543,41 +575,40 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             df[NT] = f32x4{dzs, 0.f, 0.f, 0.f};           // the sigma row H sits in tile NT, row 0
             __builtin_amdgcn_sched_barrier(0);
             // ---- HEAD: d[Wf ; ws] and dh2 = [Wf ; ws]^T [df ; dzs] ----
+            F8 bzh[KHD];
+#pragma unroll
+            for (int ks = 0; ks < KHD; ++ks) {
+                const f32x4 t0 = df[2 * ks];
+                const f32x4 t1 = (2 * ks + 1 <= NT) ? df[(2 * ks + 1 <= NT) ? 2 * ks + 1 : 0] : f32x4{0.f, 0.f, 0.f, 0.f};
+                bzh[ks] = hand<T, false>(t0, t1);
+            }
             put_hidden(0, h2);
             put_ones(H);
-            put_tiles(H + 16, df, NT + 1);
+            put_frags(H + 16, bzh, NT + 1);
             __syncthreads();
             dw_stage<T, NH>(panel, PS, H + 16, NT + 1, NT + 1, wv, lane, wh);
             flip();
             {
-                F8 bz[KHD];
-#pragma unroll
-                for (int ks = 0; ks < KHD; ++ks) {
-                    const f32x4 t0 = df[2 * ks];
-                    const f32x4 t1 = (2 * ks + 1 <= NT) ? df[(2 * ks + 1 <= NT) ? 2 * ks + 1 : 0] : f32x4{0.f, 0.f, 0.f, 0.f};
-                    bz[ks] = hand<T, false>(t0, t1);
-                }
                 const F8* qh = PTc + (G::T_L4 + G::T_L3) * WAVE;
 #pragma unroll
                 for (int ot = 0; ot < NT; ++ot) {
                     dz[ot] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int ks = 0; ks < KHD; ++ks) dz[ot] = mma<T>(qh[(ot * KHD + ks) * WAVE], bz[ks], dz[ot]);
+                    for (int ks = 0; ks < KHD; ++ks) dz[ot] = mma<T>(qh[(ot * KHD + ks) * WAVE], bzh[ks], dz[ot]);
                 }
             }
-            mask(dz, h2);
+            F8 bz2[KH];
+            masked(bz2, dz, h2);
             __builtin_amdgcn_sched_barrier(0);
             // ---- L2: dW2 and dh1 = W2^T dz2 ----
             put_hidden(0, h1);
             put_ones(H);
-            put_tiles(H + 16, dz, NT);
+            put_frags(H + 16, bz2, NT);
             __syncthreads();
             dw_stage<T, N2>(panel, PS, H + 16, NT, NT + 1, wv, lane, w2);
             flip();
             {
-                F8 bz[KH];
-#pragma unroll
-                for (int ks = 0; ks < KH; ++ks) bz[ks] = hand<T, false>(dz[2 * ks], dz[2 * ks + 1]);
+                const F8* bz = bz2;
                 const F8* q2 = PTc + (G::T_L4 + G::T_L3 + G::T_HD) * WAVE;
                 f32x4 t1[NT];
 #pragma unroll
@@ -589,7 +620,8 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
                 for (int ot = 0; ot < NT; ++ot) dz[ot] = t1[ot];
             }
-            mask(dz, h1);
+            F8 bz1[KH];
+            masked(bz1, dz, h1);
             __builtin_amdgcn_sched_barrier(0);
             // ---- L1: dW1 over the encoding slots ----
 #pragma unroll
@@ -597,7 +629,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 panel[(16 * g + s2) * PS + col] = x0[s2];
                 panel[(16 * g + 8 + s2) * PS + col] = x1[s2];
             }
-            put_tiles(64, dz, NT);
+            put_frags(64, bz1, NT);
             __syncthreads();
             dw_stage<T, N1>(panel, PS, 64, NT, 4, wv, lane, w1);
             flip();
