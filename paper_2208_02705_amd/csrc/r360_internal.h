@@ -101,10 +101,19 @@ __device__ __forceinline__ void sincospi(float x, float& s, float& c) {
     c = ((q + 1) & 2) ? -cv : cv;
 }
 
-// Angle doubling: (sin 2a, cos 2a) from (sin a, cos a).
+// Angle doubling: (sin 2a, cos 2a) from (sin a, cos a). EXACT: 2 s c and
+// (c - s)(c + s); otherwise (inputs to 8- or 11-bit rounding) t = 2 s,
+// t c and 1 - t s, three instructions.
+template <bool EXACT = true>
 __device__ __forceinline__ void dbl(float s, float c, float& s2, float& c2) {
-    s2 = 2.0f * s * c;
-    c2 = (c - s) * (c + s);
+    if constexpr (EXACT) {
+        s2 = 2.0f * s * c;
+        c2 = (c - s) * (c + s);
+    } else {
+        const float t = s + s;
+        s2 = t * c;
+        c2 = __builtin_fmaf(-t, s, 1.0f);
+    }
 }
 
 // (sin pi a, cos pi a) for a = 2^l x. EXACT: the reduced polynomial above.
@@ -139,37 +148,38 @@ __device__ __forceinline__ void pe_position(int g, const float xh[3], float v[16
     float s, c;
     sincos_oct<EXACT>(sel3(g3 ? 0 : g, xh), g3 ? 8 : 0, s, c);
     v[0] = s; v[1] = c;
-    dbl(s, c, v[2], v[3]);
-    dbl(v[2], v[3], v[4], v[5]);
+    dbl<EXACT>(s, c, v[2], v[3]);
+    dbl<EXACT>(v[2], v[3], v[4], v[5]);
     sincos_oct<EXACT>(sel3(g3 ? 1 : g, xh), g3 ? 8 : 3, s, c);
     v[6] = s; v[7] = c;
-    dbl(s, c, v[8], v[9]);
-    dbl(v[8], v[9], v[10], v[11]);
+    dbl<EXACT>(s, c, v[8], v[9]);
+    dbl<EXACT>(v[8], v[9], v[10], v[11]);
     sincos_oct<EXACT>(sel3(g3 ? 2 : g, xh), g3 ? 8 : 6, s, c);
     v[12] = s; v[13] = c;
-    dbl(s, c, v[14], v[15]);
+    dbl<EXACT>(s, c, v[14], v[15]);
     v[4] = g3 ? xh[0] : v[4];
     v[5] = g3 ? xh[1] : v[5];
     v[10] = g3 ? xh[2] : v[10];
     v[11] = g3 ? 1.0f : v[11];
 }
 
-// Direction encoding values of lane group g in slot order (8 values).
+// Direction encoding values of lane group g in slot order (8 values; lane
+// group 3: the raw components, the bias 1 and four padding slots).
 template <bool EXACT = true>
 __device__ __forceinline__ void pe_direction(int g, const float d[3], float v[8]) {
     const bool g3 = (g == 3);
     float s, c;
     sincos_oct<EXACT>(sel3(g3 ? 0 : g, d), 0, s, c);
     v[0] = s; v[1] = c;
-    dbl(v[0], v[1], v[2], v[3]);
-    dbl(v[2], v[3], v[4], v[5]);
-    dbl(v[4], v[5], v[6], v[7]);
+    dbl<EXACT>(v[0], v[1], v[2], v[3]);
+    dbl<EXACT>(v[2], v[3], v[4], v[5]);
+    dbl<EXACT>(v[4], v[5], v[6], v[7]);
     v[0] = g3 ? d[0] : v[0];
     v[1] = g3 ? d[1] : v[1];
     v[2] = g3 ? d[2] : v[2];
     v[3] = g3 ? 1.0f : v[3];
-#pragma unroll
-    for (int e = 4; e < 8; ++e) v[e] = g3 ? 0.0f : v[e];
+    // lane group 3's slots 4..7 are padding: their weight columns are zero
+    // and their values (sines and cosines, finite) contribute exactly 0
 }
 
 // ---------------------------------------------------------------------------
