@@ -423,7 +423,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             F8 x0, x1;
             {
                 float pe[16];
-                pe_position(g, xh, pe);
+                pe_position<__is_same(T, float)>(g, xh, pe);      // as the forward pass evaluates it
                 x0 = pack8<T>(pe);
                 x1 = pack8<T>(pe + 8);
             }
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             F8 xd;
             {
                 float dpe[8];
-                pe_direction(g, dv, dpe);
+                pe_direction<__is_same(T, float)>(g, dv, dpe);
                 xd = pack8<T>(dpe);
             }
 #pragma unroll
