@@ -7,11 +7,23 @@
 // anchor is the unassigned occupied voxel of smallest linear index (the
 // minimum coordinate, z then y then x) and the field takes the s_k
 // unassigned voxels nearest to it (squared distance between voxel indices,
-// ties to the smaller linear index). Each voxel's rank is the unique 57-bit
-// key (d^2 << 31) | lin, so field k is exactly the keys up to the s_k-th
-// smallest; that key is found by a five-level radix select (12-bit digits
-// from the top, a block-privatised histogram per level, one pick block that
-// narrows the prefix and stops as soon as a whole bin is taken).
+// ties to the smaller linear index). Each voxel's rank is the unique key
+// (d^2 << LB) | lin (LB the bit width of the linear index; at most 57 bits
+// for grids of up to 4096^3 voxels), so field k is exactly the keys up to
+// the s_k-th smallest; that key is found by a radix select over 12-bit
+// digits from the top (LV levels, 4 for the 128^3 and 256^3 grids), one
+// histogram per level, stopping as soon as a whole bin is taken. (Wider
+// digits save a level but every block clears, flushes and scans its whole
+// histogram: at 14 bits those fixed costs took most of each launch.)
+//
+// Launches per field: one kernel that assigns the previous field, finds
+// this field's anchor, writes its keys and counts their top digits, then
+// one histogram kernel per further level. A level's digit is picked from
+// the previous level's histogram by every block of the kernel that needs it
+// (the same deterministic scan in each; block 0 stores the result for the
+// kernels after it), so no launch is spent on picks. Fields alternate
+// between two histogram sets: the one a field reads is cleared by the next
+// field's first histogram kernel.
 //
 // Layout: the occupied voxels in increasing linear index (a stable
 // compaction), a done byte and a key per list entry; the walk over the list
@@ -25,20 +37,30 @@ namespace r360 {
 namespace {
 
 constexpr int CB = 4096;            // voxels per compaction block (256 threads x 16)
-constexpr int HB = 4096;            // histogram bins (12-bit digits)
-constexpr int LEVELS = 5;        // digits of the 57-bit key: bits 45-56, 33-44, 21-32, 9-20, 0-8
-__device__ __forceinline__ int level_shift(int lv) { return lv < 4 ? 45 - 12 * lv : 0; }
-__device__ __forceinline__ int level_width(int lv) { return lv < 4 ? 12 : 9; }
+constexpr int DIG = 12;             // digit width of the radix select
+constexpr int NBIN = 1 << DIG;      // histogram bins per level
+constexpr int LVMAX = 5;            // 57-bit keys
 constexpr uint64_t NOKEY = ~uint64_t(0);
+// Blocks of the selection kernels (each holds a 16 KB histogram and pays its
+// fixed costs): one per 1024 occupied voxels, between 64 and 256 (256 for
+// the large grid, 128 for the room scene, the measured best of 64/128/256).
+inline unsigned sel_grid(int64_t S) { return (unsigned)std::min<int64_t>(256, std::max<int64_t>(64, S / 1024)); }
 
-struct SelState {
-    uint64_t prefix;      // top digits of the s_k-th key found so far
-    uint64_t threshold;   // keys <= threshold join the field
-    int64_t need;         // rank still to find inside the current prefix
+// Radix-select state after some levels: keys <= threshold join the field
+// once found; otherwise the s_k-th key lies among the keys whose top digits
+// equal prefix, at rank `need` there.
+struct Pick {
+    uint64_t prefix;
+    uint64_t threshold;
+    int64_t need;
     int32_t found;
-    int32_t first;        // first unassigned list entry
-    int32_t anchor;       // its linear index
     int32_t pad;
+};
+struct FieldSel {
+    int32_t first;        // first list entry not assigned before this field
+    int32_t anchor;       // its linear index
+    int32_t pad[2];
+    Pick lv[LVMAX + 1];   // lv[0]: before any level; lv[l + 1]: after picking level l
 };
 
 struct AssignWs {
@@ -46,8 +68,8 @@ struct AssignWs {
     uint8_t* done;        // [nvox]
     uint64_t* key;        // [nvox]
     int32_t* bcount;      // [blocks] occupied voxels per compaction block, then their offsets
-    uint32_t* hist;       // [HB]
-    SelState* st;
+    uint32_t* hist;       // [2][LVMAX][NBIN] two histogram sets
+    FieldSel* sel;        // [2]
     int32_t* total;       // S
 };
 
@@ -63,16 +85,16 @@ AssignWs carve_assign(void* base, int64_t nvox) {
     w.done = reinterpret_cast<uint8_t*>(take(nvox));
     w.key = reinterpret_cast<uint64_t*>(take(nvox * 8));
     w.bcount = reinterpret_cast<int32_t*>(take(nb * 4));
-    w.hist = reinterpret_cast<uint32_t*>(take(HB * 4));
-    w.st = reinterpret_cast<SelState*>(take(sizeof(SelState)));
+    w.hist = reinterpret_cast<uint32_t*>(take((size_t)2 * LVMAX * NBIN * 4));
+    w.sel = reinterpret_cast<FieldSel*>(take(2 * sizeof(FieldSel)));
     w.total = reinterpret_cast<int32_t*>(take(4));
     return w;
 }
 
 size_t assign_bytes(int64_t nvox) {
     const int64_t nb = (nvox + CB - 1) / CB;
-    return up256(nvox * 4) + up256(nvox) + up256(nvox * 8) + up256(nb * 4) + up256(HB * 4) +
-           up256(sizeof(SelState)) + up256(4);
+    return up256(nvox * 4) + up256(nvox) + up256(nvox * 8) + up256(nb * 4) + up256((size_t)2 * LVMAX * NBIN * 4) +
+           up256(2 * sizeof(FieldSel)) + up256(4);
 }
 
 // Exclusive prefix over a block of 256 threads; returns the block total.
@@ -150,124 +172,196 @@ __global__ __launch_bounds__(256) void k_occ_scatter(const float* __restrict__ o
         }
 }
 
-__global__ void k_sel_init(SelState* st) {
-    st->first = 0;
-}
+// Key geometry: LB bits of linear index under the squared distance; LV
+// levels of DIG bits cover the key from the top (level l: bits
+// [DIG (LV - 1 - l), DIG (LV - l))).
+struct KeyGeom {
+    int LB, LV;
+};
+__device__ __forceinline__ int lv_shift(const KeyGeom& kg, int l) { return DIG * (kg.LV - 1 - l); }
 
-// key = (d^2 << 31) | lin for unassigned entries, NOKEY for assigned ones;
-// the anchor is the first unassigned entry. Block 0 also resets the
-// selection for this field (read only by the kernels launched after this
-// one).
-__global__ __launch_bounds__(256) void k_sel_keys(SelState* st, const int32_t* __restrict__ list,
-                                                  const uint8_t* __restrict__ done, uint64_t* __restrict__ key,
-                                                  int64_t S, int n0, int n1, int64_t sk) {
-    const int first = st->first, a = list[first];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->anchor = a;
-        st->prefix = 0;
-        st->need = sk;
-        st->found = 0;
-        st->threshold = 0;
+// Picks level l's digit from its histogram (every thread of the block
+// returns the same state). The digit is the bin holding the need-th key;
+// a bin taken whole ends the search.
+__device__ Pick block_pick(Pick s, const uint32_t* __restrict__ hist, int shift) {
+    __shared__ Pick res;
+    if (s.found) return s;                               // uniform
+    constexpr int PER = NBIN / 256;                      // bins per thread, in order, held in registers
+    typedef __attribute__((ext_vector_type(4))) unsigned u32x4_;
+    uint32_t hb[PER];
+    const u32x4_* src = reinterpret_cast<const u32x4_*>(hist + threadIdx.x * PER);
+#pragma unroll
+    for (int q = 0; q < PER / 4; ++q) {
+        const u32x4_ v = src[q];
+        hb[4 * q] = v[0]; hb[4 * q + 1] = v[1]; hb[4 * q + 2] = v[2]; hb[4 * q + 3] = v[3];
     }
-    const int ax = a % n0, ay = (a / n0) % n1, az = a / (n0 * n1);
-    for (int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (done[i]) { key[i] = NOKEY; continue; }
-        const int l = list[i];
-        const int64_t dx = l % n0 - ax, dy = (l / n0) % n1 - ay, dz = l / (n0 * n1) - az;
-        key[i] = ((uint64_t)(dx * dx + dy * dy + dz * dz) << 31) | (uint64_t)l;
-    }
-}
-
-// Histogram of the level's digit over the keys inside the current prefix.
-__global__ __launch_bounds__(256) void k_sel_hist(const SelState* st, const uint64_t* __restrict__ key, int64_t S,
-                                                  int level, uint32_t* __restrict__ hist) {
-    if (st->found) return;
-    __shared__ uint32_t h[HB];
-    for (int b = threadIdx.x; b < HB; b += 256) h[b] = 0;
-    __syncthreads();
-    const int sh = level_shift(level), wd = level_width(level);
-    const uint64_t pre = st->prefix;
-    const uint64_t mask = (uint64_t(1) << wd) - 1;
-    for (int64_t i = st->first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = key[i];
-        if ((k >> (sh + wd)) == pre) atomicAdd(&h[(k >> sh) & mask], 1u);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < HB; b += 256)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
-}
-
-// One block of 256 threads: the digit whose bin holds the need-th key; the
-// prefix grows by it; a bin taken whole ends the search. Clears the
-// histogram for the next level.
-__global__ __launch_bounds__(256) void k_sel_pick(SelState* st, uint32_t* __restrict__ hist, int level) {
-    if (st->found) return;                               // uniform: every thread reads the same word
-    const int t = threadIdx.x;
-    constexpr int PER = HB / 256;                        // 16 bins per thread, in order
-    uint32_t c[PER];
     int sum = 0;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        c[j] = hist[t * PER + j];
-        sum += (int)c[j];
-    }
+    for (int q = 0; q < PER; ++q) sum += (int)hb[q];
     int excl;
     block_scan256(sum, excl);
-    const int64_t need = st->need;
-    __syncthreads();                                     // every thread has read `need` before it changes
-    if (excl < need && need <= excl + sum) {             // exactly one thread holds the need-th key
+    if (excl < s.need && s.need <= excl + sum) {         // exactly one thread holds the need-th key
         int64_t below = excl;
-        int j = 0;
-        while (below + c[j] < need) below += c[j++];
-        const int sh = level_shift(level), wd = level_width(level);
-        const uint64_t pre = (st->prefix << wd) | (uint64_t)(t * PER + j);
-        const int64_t left = need - below;
-        st->prefix = pre;
-        st->need = left;
-        if ((int64_t)c[j] == left) {                    // the whole bin joins: done
-            st->found = 1;
-            st->threshold = (pre << sh) | ((uint64_t(1) << sh) - 1);
-        }
-    }
+        int q = 0;
 #pragma unroll
-    for (int j = 0; j < PER; ++j) hist[t * PER + j] = 0;
-}
-
-__global__ __launch_bounds__(256) void k_sel_assign(const SelState* st, const int32_t* __restrict__ list,
-                                                    uint8_t* __restrict__ done, const uint64_t* __restrict__ key,
-                                                    int64_t S, int take_all, int32_t field, int32_t* __restrict__ fmap) {
-    const uint64_t th = st->threshold;
-    for (int64_t i = st->first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (done[i]) continue;
-        if (take_all || key[i] <= th) {
-            done[i] = 1;
-            fmap[list[i]] = field;
-        }
+        for (int t = 0; t < PER; ++t)                    // the first bin where the count reaches need
+            if (t == q && below + hb[t] < s.need) { below += hb[t]; ++q; }
+        Pick r;
+        r.prefix = (s.prefix << DIG) | (uint64_t)(threadIdx.x * PER + q);
+        r.need = s.need - below;
+        uint32_t cq = 0;
+#pragma unroll
+        for (int t = 0; t < PER; ++t) cq = t == q ? hb[t] : cq;
+        r.found = (int64_t)cq == r.need ? 1 : 0;
+        r.threshold = r.found ? ((r.prefix << shift) | ((uint64_t(1) << shift) - 1)) : 0;
+        r.pad = 0;
+        res = r;
     }
-}
-
-// Moves `first` to the next unassigned entry (one block, 256 entries a round).
-__global__ __launch_bounds__(256) void k_sel_advance(SelState* st, const uint8_t* __restrict__ done, int64_t S) {
-    __shared__ int hit;
-    int64_t f = st->first;
     __syncthreads();
-    for (;;) {
-        if (threadIdx.x == 0) hit = 256;
-        __syncthreads();
-        const int64_t i = f + threadIdx.x;
-        if (i < S && !done[i]) atomicMin(&hit, (int)threadIdx.x);
-        __syncthreads();
-        const int h = hit;
-        if (h < 256 || f + 256 >= S) {
-            if (threadIdx.x == 0) st->first = (int32_t)(h < 256 ? f + h : S);
-            return;
-        }
-        f += 256;
-        __syncthreads();
+    const Pick r = res;
+    __syncthreads();                                     // before res is written again
+    return r;
+}
+
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4h;
+// Zeroes a block's LDS histogram (16 bytes per store).
+__device__ __forceinline__ void clear_hist(uint32_t* h) {
+#pragma unroll
+    for (int q = 0; q < NBIN / 1024; ++q) reinterpret_cast<u32x4h*>(h)[threadIdx.x + 256 * q] = u32x4h{0u, 0u, 0u, 0u};
+}
+// Adds a block's LDS histogram into a global one (16-byte LDS reads, one
+// atomic per non-empty bin).
+__device__ __forceinline__ void flush_hist(const uint32_t* h, uint32_t* __restrict__ dst) {
+#pragma unroll
+    for (int q = 0; q < NBIN / 1024; ++q) {
+        const int b = 4 * (threadIdx.x + 256 * q);
+        const u32x4h v = reinterpret_cast<const u32x4h*>(h)[threadIdx.x + 256 * q];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (v[e]) atomicAdd(&dst[b + e], v[e]);
     }
+}
+
+struct StepArgs {
+    const int32_t* list;
+    uint8_t* done;
+    uint64_t* key;
+    int64_t S;
+    int n0, n1;
+    KeyGeom kg;
+    const FieldSel* cur;        // field k (its keys and histograms are complete)
+    const uint32_t* hcur;       // its histogram set
+    FieldSel* nxt;              // field k + 1
+    uint32_t* hnxt;
+    int32_t field;              // k, or -1 before the first field
+    int32_t take_all;           // field k takes every entry left
+    int32_t has_next;
+    int64_t s_next;             // size of field k + 1
+    int32_t* fmap;
+};
+
+// Assigns field k (keys <= its threshold, or all that are left), finds the
+// anchor of field k + 1 (the first entry neither assigned before nor taken
+// by field k), writes field k + 1's keys and counts their top digit.
+__global__ __launch_bounds__(256) void k_sel_step(StepArgs a) {
+    __shared__ __attribute__((aligned(16))) uint32_t h[NBIN];
+    __shared__ int hit;
+    const int64_t first = a.field >= 0 ? a.cur->first : 0;
+    uint64_t th = 0;
+    if (a.field >= 0 && !a.take_all)
+        th = block_pick(a.cur->lv[a.kg.LV - 1], a.hcur + (size_t)(a.kg.LV - 1) * NBIN, lv_shift(a.kg, a.kg.LV - 1))
+                 .threshold;
+    auto key_of = [&](int l, int ax, int ay, int az) {
+        const int64_t dx = l % a.n0 - ax, dy = (l / a.n0) % a.n1 - ay, dz = l / (a.n0 * a.n1) - az;
+        return ((uint64_t)(dx * dx + dy * dy + dz * dz) << a.kg.LB) | (uint64_t)l;
+    };
+    // field k's own entry (its key was written by the step before this one;
+    // only this thread touches it here)
+    auto taken = [&](int64_t i) { return a.field >= 0 && (a.take_all || a.key[i] <= th); };
+    int64_t nfirst = a.S;
+    if (a.has_next) {
+        // The anchor search reads entries other blocks are assigning and
+        // re-keying meanwhile: it recomputes field k's keys from its anchor
+        // instead of reading them, and a done byte seen either before or
+        // after another block sets it gives the same answer.
+        int kx = 0, ky = 0, kz = 0;
+        if (a.field >= 0) {
+            const int ka = a.cur->anchor;
+            kx = ka % a.n0; ky = (ka / a.n0) % a.n1; kz = ka / (a.n0 * a.n1);
+        }
+        auto taken_k = [&](int64_t i) {
+            return a.field >= 0 && (a.take_all || key_of(a.list[i], kx, ky, kz) <= th);
+        };
+        for (int64_t i0 = first;; i0 += 256) {
+            if (threadIdx.x == 0) hit = 256;
+            __syncthreads();
+            const int64_t i = i0 + threadIdx.x;
+            if (i < a.S && !a.done[i] && !taken_k(i)) atomicMin(&hit, (int)threadIdx.x);
+            __syncthreads();
+            const int hh = hit;
+            __syncthreads();
+            if (hh < 256) { nfirst = i0 + hh; break; }
+            if (i0 + 256 >= a.S) break;
+        }
+    }
+    const bool next = a.has_next && nfirst < a.S;
+    int ax = 0, ay = 0, az = 0;
+    if (next) {
+        const int an = a.list[nfirst];
+        ax = an % a.n0; ay = (an / a.n0) % a.n1; az = an / (a.n0 * a.n1);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            a.nxt->first = (int32_t)nfirst;
+            a.nxt->anchor = an;
+            Pick p0;
+            p0.prefix = 0; p0.threshold = 0; p0.need = a.s_next; p0.found = 0; p0.pad = 0;
+            a.nxt->lv[0] = p0;
+        }
+    }
+    clear_hist(h);
+    __syncthreads();
+    const int sh0 = lv_shift(a.kg, 0);
+    for (int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.S;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (a.done[i]) continue;
+        if (taken(i)) {
+            a.done[i] = 1;
+            a.key[i] = NOKEY;
+            a.fmap[a.list[i]] = a.field;
+            continue;
+        }
+        if (!next) continue;
+        const uint64_t k = key_of(a.list[i], ax, ay, az);
+        a.key[i] = k;
+        atomicAdd(&h[k >> sh0], 1u);
+    }
+    __syncthreads();
+    if (next) flush_hist(h, a.hnxt);
+}
+
+// Level l >= 1 of field k's select: picks level l - 1 (block 0 stores it),
+// then counts the digit of the keys inside the picked prefix. Level 1 also
+// clears the other histogram set for field k + 1.
+__global__ __launch_bounds__(256) void k_sel_level(FieldSel* sel, uint32_t* __restrict__ hset,
+                                                   uint32_t* __restrict__ hother, const uint64_t* __restrict__ key,
+                                                   int64_t S, KeyGeom kg, int level) {
+    __shared__ __attribute__((aligned(16))) uint32_t h[NBIN];
+    if (level == 1)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)LVMAX * NBIN;
+             i += (int64_t)gridDim.x * blockDim.x)
+            hother[i] = 0;
+    const Pick s = block_pick(sel->lv[level - 1], hset + (size_t)(level - 1) * NBIN, lv_shift(kg, level - 1));
+    if (blockIdx.x == 0 && threadIdx.x == 0) sel->lv[level] = s;
+    if (s.found) return;                                 // uniform
+    clear_hist(h);
+    __syncthreads();
+    const int sh = lv_shift(kg, level);
+    for (int64_t i = sel->first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = key[i];
+        if (k != NOKEY && (k >> (sh + DIG)) == s.prefix) atomicAdd(&h[(k >> sh) & (NBIN - 1)], 1u);
+    }
+    __syncthreads();
+    flush_hist(h, hset + (size_t)level * NBIN);
 }
 
 // ---- uniform blocks ----------------------------------------------------------
@@ -386,8 +480,8 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     hipLaunchKernelGGL(k_occ_count, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount);
     hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(256), 0, st, w.bcount, nb, w.total);
     hipLaunchKernelGGL(k_occ_scatter, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount, w.list, w.done);
-    hipLaunchKernelGGL(k_fill, dim3(16), dim3(256), 0, st, reinterpret_cast<int32_t*>(w.hist), (int64_t)HB, 0);
-    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1), 0, st, w.st);
+    hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<int32_t*>(w.hist),
+                       (int64_t)2 * LVMAX * NBIN, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int32_t S32 = 0;
@@ -396,26 +490,48 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     const int64_t S = S32;
     if (S_out) *S_out = S;
     if (S == 0) return hipSuccess;
+    // key geometry: bit widths of the largest linear index and squared distance
+    auto bits = [](uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; };
+    const uint64_t d2max = (uint64_t)(n[0] - 1) * (n[0] - 1) + (uint64_t)(n[1] - 1) * (n[1] - 1) +
+                           (uint64_t)(n[2] - 1) * (n[2] - 1);
+    KeyGeom kg;
+    kg.LB = std::max(1, bits((uint64_t)(nvox - 1)));
+    kg.LV = std::max(2, (bits(d2max) + kg.LB + DIG - 1) / DIG);
+    if (kg.LV > LVMAX) return hipErrorInvalidValue;
     const int64_t base = S / n_fields, rem = S % n_fields;
+    auto size_of = [&](int32_t k) { return base + (k < rem ? 1 : 0); };
+    StepArgs sa{};
+    sa.list = w.list; sa.done = w.done; sa.key = w.key; sa.S = S; sa.n0 = n[0]; sa.n1 = n[1]; sa.kg = kg;
+    sa.fmap = fmap;
+    // the step before field 0 only finds its anchor and keys
+    int32_t k = 0;
+    while (k < n_fields && size_of(k) == 0) ++k;
+    sa.field = -1; sa.take_all = 0; sa.has_next = 1; sa.s_next = size_of(k);
+    sa.cur = w.sel + 1; sa.hcur = w.hist + (size_t)LVMAX * NBIN;
+    sa.nxt = w.sel; sa.hnxt = w.hist;
+    hipLaunchKernelGGL(k_sel_step, dim3(sel_grid(S)), dim3(256), 0, st, sa);
     int64_t left = S;
-    for (int32_t k = 0; k < n_fields && left > 0; ++k) {
-        const int64_t sk = base + (k < rem ? 1 : 0);
-        if (sk == 0) continue;
-        const unsigned g = grid_for(left);
+    while (k < n_fields && left > 0) {
+        const int set = k & 1;
+        FieldSel* sel = w.sel + set;
+        uint32_t* hset = w.hist + (size_t)set * LVMAX * NBIN;
+        uint32_t* hother = w.hist + (size_t)(set ^ 1) * LVMAX * NBIN;
+        const int64_t sk = size_of(k);
         const int take_all = sk >= left ? 1 : 0;
-        if (!take_all) {
-            hipLaunchKernelGGL(k_sel_keys, dim3(g), dim3(256), 0, st, w.st, w.list, w.done, w.key, S, n[0], n[1],
-                               sk);
-            for (int lv = 0; lv < LEVELS; ++lv) {
-                hipLaunchKernelGGL(k_sel_hist, dim3(std::min(g, 512u)), dim3(256), 0, st, w.st, w.key, S, lv,
-                                   w.hist);
-                hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, st, w.st, w.hist, lv);
-            }
-        }
-        hipLaunchKernelGGL(k_sel_assign, dim3(g), dim3(256), 0, st, w.st, w.list, w.done, w.key, S, take_all, k, fmap);
+        if (!take_all)
+            for (int lv = 1; lv < kg.LV; ++lv)
+                hipLaunchKernelGGL(k_sel_level, dim3(sel_grid(S)), dim3(256), 0, st, sel, hset, hother, w.key, S, kg, lv);
         left -= sk;
-        if (left > 0) hipLaunchKernelGGL(k_sel_advance, dim3(1), dim3(256), 0, st, w.st, w.done, S);
+        int32_t k2 = k + 1;
+        while (k2 < n_fields && size_of(k2) == 0) ++k2;
+        sa.field = k; sa.take_all = take_all;
+        sa.has_next = (left > 0 && k2 < n_fields) ? 1 : 0;
+        sa.s_next = sa.has_next ? size_of(k2) : 0;
+        sa.cur = sel; sa.hcur = hset;
+        sa.nxt = w.sel + (set ^ 1); sa.hnxt = hother;
+        hipLaunchKernelGGL(k_sel_step, dim3(sel_grid(S)), dim3(256), 0, st, sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        k = k2;
     }
     return hipSuccess;
 }
