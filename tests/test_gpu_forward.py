@@ -135,6 +135,41 @@ def test_sampling_bitexact_random_rays_and_edges(R, orc):
         _both_paths(R, scene, o, d, orc.sample_rays(sc, o, d, **kw), **kw)
 
 
+@pytest.mark.parametrize("n,p_occ", [(16, 0.05), (16, 0.15), (15, 0.05)])
+def test_sampling_bitexact_sparse_grids_lattice_starts(R, orc, n, p_occ):
+    """Sparse grids (long runs of free voxels between samples): random rays,
+    and rays started on voxel corners, edges and faces along diagonals and
+    axes of both signs (ties between crossing planes), with caps and near/far
+    limits; an odd grid size as well."""
+    sc = synth.tiny_scene(16, 300 + n, p_occ=p_occ, n_fields=4, max_samples=64)
+    if n != 16:      # the same voxel edge (a power of two) on an n^3 grid
+        sc.occ = np.ascontiguousarray(sc.occ[:n, :n, :n])
+        sc.field_map = np.ascontiguousarray(sc.field_map[:n, :n, :n])
+        sc.n = n
+    scene = R.Scene.from_synth(sc)
+    o, d = _random_rays(4000, 300 + n, -5, 5)
+    v = sc.voxel
+    corners = np.array([[-4 + 2 * v * i, -4 + 2 * v * j, -4 + 2 * v * k] for i, j, k in
+                        [(0, 0, 0), (1, 1, 1), (2, 1, 0), (3, 3, 3), (1, 2, 3)]], np.float32)
+    edges = corners + np.array([v, 0, 0], np.float32)          # on a cell edge (interior plane in x)
+    faces = corners + np.array([v, v, 0], np.float32)
+    dirs = []
+    for s in ((1, 1, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 1, 1), (1, 2, 2)):
+        for sg in ((1, 1, 1), (-1, 1, 1), (1, -1, -1), (-1, -1, -1)):
+            w = np.array(s, np.float64) * np.array(sg)
+            dirs.append(w / np.linalg.norm(w))
+    dirs = np.array(dirs, np.float32)
+    starts = np.concatenate([corners, edges, faces])
+    eo = np.repeat(starts, len(dirs), axis=0).T
+    ed = np.tile(dirs, (len(starts), 1)).T
+    o = np.concatenate([o, eo], 1); d = np.concatenate([d, ed], 1)
+    ref = orc.sample_rays(sc, o, d)
+    assert ref["t_mid"].size > 1000
+    _both_paths(R, scene, o, d, ref)
+    for kw in (dict(max_samples=2), dict(near=1.0, far=3.0)):
+        _both_paths(R, scene, o, d, orc.sample_rays(sc, o, d, **kw), **kw)
+
+
 # ---------------------------------------------------------------------------
 # Rendering
 # ---------------------------------------------------------------------------
