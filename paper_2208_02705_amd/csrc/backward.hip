@@ -40,7 +40,7 @@ namespace r360 {
 
 namespace {
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+__device__ __forceinline__ float sigmoidf_(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 __device__ __forceinline__ int find_field(const int32_t* start, int F, int pos) {
     int lo = 0, hi = F;
@@ -151,7 +151,8 @@ __device__ __forceinline__ int dw_index(int ly, int out, int in) {
     constexpr FieldLayout L{H};
     switch (ly) {
     case LY_L1: {
-        const int feat = pe_slot_feature(in >> 4, in & 15);
+        // panel row hidden_col16(s >> 3, g, s & 7) holds slot s of lane group g
+        const int feat = pe_slot_feature((in >> 2) & 3, 4 * (in >> 4) + (in & 3));
         return feat == SLOT_BIAS ? L.b1() + out : L.W1() + out * DXYZ + feat;
     }
     case LY_L2:
@@ -163,7 +164,7 @@ __device__ __forceinline__ int dw_index(int ly, int out, int in) {
     case LY_L3: {
         if (in < H) return L.W3() + out * (H + DDIR) + in;
         const int q = in - H;
-        const int feat = dir_slot_feature(q >> 3, q & 7);
+        const int feat = dir_slot_feature((q >> 2) & 3, 4 * (q >> 4) + (q & 3));
         if (feat == SLOT_ZERO) return -1;
         return feat == SLOT_BIAS ? L.b3() + out : L.W3() + out * (H + DDIR) + H + feat;
     }
@@ -556,7 +557,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             // ---- L3: dW3 over [f ; g(d)] and df = W3_f^T dz3 ----
             put_hidden(0, fb);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) panel[(H + 8 * g + e) * PS + col] = xd[e];
+            for (int e = 0; e < 8; ++e) panel[(H + hidden_col16(0, g, e)) * PS + col] = xd[e];
             put_frags(H + 32, bz3, NT);
             __syncthreads();
             dw_stage<T, N3>(panel, PS, H + 32, NT, NT + 2, wv, lane, w3);
@@ -626,8 +627,8 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             // ---- L1: dW1 over the encoding slots ----
 #pragma unroll
             for (int s2 = 0; s2 < 8; ++s2) {
-                panel[(16 * g + s2) * PS + col] = x0[s2];
-                panel[(16 * g + 8 + s2) * PS + col] = x1[s2];
+                panel[hidden_col16(0, g, s2) * PS + col] = x0[s2];
+                panel[hidden_col16(1, g, s2) * PS + col] = x1[s2];
             }
             put_frags(64, bz1, NT);
             __syncthreads();
