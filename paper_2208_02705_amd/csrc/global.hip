@@ -619,6 +619,10 @@ static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
 // samples: the MFMA fragments are then plain 16-byte LDS reads. The next
 // step's blocks are loaded while this step's MFMAs run. Bias gradients (row
 // sums of A over the samples) come from extra MFMAs against a ones fragment.
+// Within an LDS row the eight 8-sample chunks are permuted by an XOR with
+// 2 ((row >> 4) & 3): the 16-byte stores of a wave (16 or 32 column blocks,
+// rows 8 apart) then spread over all banks instead of half of them, while
+// the 16 rows a fragment read covers share one permutation.
 constexpr int DK = 64;
 constexpr int DPAD = DK + 8;    // 144-byte LDS rows
 
@@ -641,6 +645,7 @@ __device__ __forceinline__ void transpose8(const u4 in[8], u4 out[8]) {
 template <int TILE>
 __global__ __launch_bounds__(2 * TILE) void k_gemm_dw(GemmArgs g) {
     constexpr int WM = TILE / 64, NW = 2 * TILE / 64, WNC = NW / WM, WCW = TILE / WNC, TJ = WCW / 16;
+    static_assert(WCW % 64 == 0, "a wave's first operand row is a multiple of 64 (chunk permutation i & 3, j & 3)");
     extern __shared__ __attribute__((aligned(16))) char dw_smem[];
     bf16* la = reinterpret_cast<bf16*>(dw_smem);
     bf16* lb = la + TILE * DPAD;
@@ -657,7 +662,7 @@ __global__ __launch_bounds__(2 * TILE) void k_gemm_dw(GemmArgs g) {
     const int64_t sr = isA ? g.a_sr : g.b_sr;
     const int col = (isA ? r0 : c0) + 8 * cb;
     const bool col_ok = col < (isA ? g.a_lim : g.b_lim);
-    bf16* dst = (isA ? la : lb) + 8 * cb * DPAD + 8 * mb;
+    bf16* dst = (isA ? la : lb) + 8 * cb * DPAD + 8 * (mb ^ (2 * ((cb >> 1) & 3)));
     const bool do_bias = g.boff >= 0 && blockIdx.y == 0 && wn == 0;
     f32x4 acc[4][TJ], accb[4];
 #pragma unroll
@@ -689,10 +694,10 @@ __global__ __launch_bounds__(2 * TILE) void k_gemm_dw(GemmArgs g) {
             bf16x8 fa[4], fb[TJ];
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                fa[i] = *reinterpret_cast<const bf16x8*>(&la[(64 * wm + 16 * i + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
+                fa[i] = *reinterpret_cast<const bf16x8*>(&la[(64 * wm + 16 * i + (lane & 15)) * DPAD + 8 * ((4 * ks + (lane >> 4)) ^ (2 * (i & 3)))]);
 #pragma unroll
             for (int j = 0; j < TJ; ++j)
-                fb[j] = *reinterpret_cast<const bf16x8*>(&lb[(WCW * wn + 16 * j + (lane & 15)) * DPAD + 32 * ks + 8 * (lane >> 4)]);
+                fb[j] = *reinterpret_cast<const bf16x8*>(&lb[(WCW * wn + 16 * j + (lane & 15)) * DPAD + 8 * ((4 * ks + (lane >> 4)) ^ (2 * (j & 3)))]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
