@@ -452,18 +452,21 @@ constexpr int RW_WAVES = 16;
 // takes the next four from its partner group (lane + 16); a lane of an odd
 // group does the same for tile ta+1. Each lane then owns eight consecutive
 // columns (16 bytes) and a row receives 64 contiguous bytes per store.
+// The exchange is one v_permlane16_swap per element: it swaps the odd 16-lane
+// rows of its first operand with the even rows of its second, which leaves
+// the first operand holding (a of an even row, b of the even row below an
+// odd row) and the second (a of the odd row above an even row, b of an odd
+// row), exactly the lane's first and last four columns.
 template <int EPI>
 __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, int g4, f32x4 a, f32x4 b,
                                              int ncols) {
     const bool odd = g4 & 1;
-    f32x4 send = odd ? a : b, got;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) got[q] = __shfl_xor(send[q], 16, WAVE);
     float x[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        x[q] = odd ? got[q] : a[q];
-        x[4 + q] = odd ? b[q] : got[q];
+        const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[q]), __float_as_uint(b[q]), false, false);
+        x[q] = __uint_as_float(sw[0]);
+        x[4 + q] = __uint_as_float(sw[1]);
     }
     const int c0 = 16 * (ta + (odd ? 1 : 0)) + 4 * (g4 & 2);   // first of the lane's eight columns
     if (r >= g.R) return;
