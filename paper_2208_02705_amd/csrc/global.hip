@@ -457,10 +457,28 @@ constexpr int RW_WAVES = 16;
 // the first operand holding (a of an even row, b of the even row below an
 // odd row) and the second (a of the odd row above an even row, b of an odd
 // row), exactly the lane's first and last four columns.
+// First of the lane's eight columns in the epilogue of tiles ta, ta+1.
+__device__ __forceinline__ int rw_col0(int ta, int g4) { return 16 * (ta + (g4 & 1)) + 4 * (g4 & 2); }
+
+// The forward activations at those eight columns of row r (zero past ncols
+// or past the last row): the ReLU pattern of an input-gradient epilogue,
+// loaded before the tiles' products so that its latency overlaps them.
+__device__ __forceinline__ bf16x8 rw_mask(const GemmArgs& g, int r, int ta, int g4, int ncols) {
+    bf16x8 m;
+    const int c0 = rw_col0(ta, g4);
+    const bf16* mp = g.mask + (int64_t)r * g.ldm + c0;
+    if (r < g.R && c0 + 8 <= ncols) {
+        m = *reinterpret_cast<const bf16x8*>(mp);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m[q] = (r < g.R && c0 + q < ncols) ? mp[q] : (bf16)0.0f;
+    }
+    return m;
+}
+
 template <int EPI>
 __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, int g4, f32x4 a, f32x4 b,
-                                             int ncols) {
-    const bool odd = g4 & 1;
+                                             int ncols, bf16x8 m) {
     float x[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -468,7 +486,7 @@ __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, i
         x[q] = __uint_as_float(sw[0]);
         x[4 + q] = __uint_as_float(sw[1]);
     }
-    const int c0 = 16 * (ta + (odd ? 1 : 0)) + 4 * (g4 & 2);   // first of the lane's eight columns
+    const int c0 = rw_col0(ta, g4);
     if (r >= g.R) return;
     if constexpr (EPI == EPI_FWD) {
 #pragma unroll
@@ -488,14 +506,6 @@ __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, i
     if constexpr (EPI == EPI_DX) {
         if (g.mask) {
             // keep the gradient where the forward activation is > 0 (ReLU)
-            const bf16* mp = g.mask + (int64_t)r * g.ldm + c0;
-            bf16x8 m;
-            if (whole) {
-                m = *reinterpret_cast<const bf16x8*>(mp);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) m[q] = c0 + q < ncols ? mp[q] : (bf16)0.0f;
-            }
 #pragma unroll
             for (int q = 0; q < 8; ++q)
                 if (!((float)m[q] > 0.0f)) o[q] = (bf16)0.0f;
@@ -547,6 +557,13 @@ __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) 
     auto tile_mm = [&](const bf16x8* x, int tile) {
         const int r = tile * 16 + l16;
         for (int ot0 = 0; ot0 < CT; ot0 += 4) {
+            bf16x8 m0{}, m1{};
+            if constexpr (EPI == EPI_DX) {
+                if (g.mask) {
+                    m0 = rw_mask(g, r, ot0, g4, ncols);
+                    if (ot0 + 2 < CT) m1 = rw_mask(g, r, ot0 + 2, g4, ncols);
+                }
+            }
             f32x4 acc[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -564,8 +581,8 @@ __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) 
                 }
             // tiles past CT were computed from a repeated fragment: their
             // columns lie beyond C and are neither stored nor read
-            rw_epilogue2<EPI>(g, r, ot0, g4, acc[0], acc[1], ncols);
-            if (ot0 + 2 < CT) rw_epilogue2<EPI>(g, r, ot0 + 2, g4, acc[2], acc[3], ncols);
+            rw_epilogue2<EPI>(g, r, ot0, g4, acc[0], acc[1], ncols, m0);
+            if (ot0 + 2 < CT) rw_epilogue2<EPI>(g, r, ot0 + 2, g4, acc[2], acc[3], ncols, m1);
         }
     };
     int t = blockIdx.x * RW_WAVES + wv;
