@@ -217,31 +217,49 @@ __global__ __launch_bounds__(256) void k_gsamples(GSampleArgs a) {
         cell[q] = inside ? (int)__builtin_floorf(u) : 0;
     }
     a.voxel[m] = inside ? cell[0] + gn[0] * (cell[1] + gn[1] * cell[2]) : -1;
-    bf16* x = a.x5 + m * (a.w + 64) + a.w;
-    x[0] = (bf16)xh[0]; x[1] = (bf16)xh[1]; x[2] = (bf16)xh[2];
+    // the encodings are assembled in registers and stored 16 bytes at a time
+    // (row strides and the first encoding column are multiples of 32 elements)
+    static_assert(GDX + 1 == 64 && GDD + 1 <= 32, "encoding widths");
+    bf16x8 xv[8];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) xv[0][q] = (bf16)xh[q];
+#pragma unroll
     for (int l = 0; l < LXYZ; ++l) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             float s, cth;
             sincospi(__builtin_ldexpf(xh[q], l), s, cth);
-            x[3 + 6 * l + q] = (bf16)s;
-            x[6 + 6 * l + q] = (bf16)cth;
+            const int is = 3 + 6 * l + q, ic = 6 + 6 * l + q;
+            xv[is >> 3][is & 7] = (bf16)s;
+            xv[ic >> 3][ic & 7] = (bf16)cth;
         }
     }
-    x[GDX] = (bf16)1.0f;
-    bf16* y = a.x10 + m * a.k10 + a.w;
-    y[0] = (bf16)d[0]; y[1] = (bf16)d[1]; y[2] = (bf16)d[2];
+    xv[GDX >> 3][GDX & 7] = (bf16)1.0f;
+    bf16x8* x = reinterpret_cast<bf16x8*>(a.x5 + m * (a.w + 64) + a.w);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = xv[j];
+    bf16x8 yv[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) yv[j][e] = (bf16)0.0f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) yv[0][q] = (bf16)d[q];
+#pragma unroll
     for (int l = 0; l < LDIR; ++l) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             float s, cth;
             sincospi(__builtin_ldexpf(d[q], l), s, cth);
-            y[3 + 6 * l + q] = (bf16)s;
-            y[6 + 6 * l + q] = (bf16)cth;
+            const int is = 3 + 6 * l + q, ic = 6 + 6 * l + q;
+            yv[is >> 3][is & 7] = (bf16)s;
+            yv[ic >> 3][ic & 7] = (bf16)cth;
         }
     }
-    y[GDD] = (bf16)1.0f;
-    for (int q = GDD + 1; q < a.k10 - a.w; ++q) y[q] = (bf16)0.0f;
+    yv[GDD >> 3][GDD & 7] = (bf16)1.0f;
+    bf16x8* y = reinterpret_cast<bf16x8*>(a.x10 + m * a.k10 + a.w);    // k10 - w = 32 columns
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[j] = yv[j];
 }
 
 // ---------------------------------------------------------------------------
@@ -753,30 +771,54 @@ __global__ void k_gout_grads(int64_t M, const float* __restrict__ rgb, const flo
                              bf16* __restrict__ dzh, int ldh, int w) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
-    for (int c = 0; c < 32; ++c) {
-        float v = 0.0f;
-        if (c < 3) {
-            const float s = rgb[c * M + m];
-            v = drgb[c * M + m] * s * (1.0f - s);
-        }
-        dz11[m * 32 + c] = (bf16)v;
+    // both rows are written as whole 16-byte pieces: dz11 is 32 columns wide,
+    // and dzh's columns w .. ldh - 1 are the 32 after the w feature rows
+    // (w and ldh = w + 32 are multiples of 32)
+    bf16x8 z[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) z[j][e] = (bf16)0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float s = rgb[c * M + m];
+        z[0][c] = (bf16)(drgb[c * M + m] * s * (1.0f - s));
     }
-    dzh[m * ldh + w] = (bf16)(sig[m] > 0.0f ? dsig[m] : 0.0f);
-    for (int c = w + 1; c < ldh; ++c) dzh[m * ldh + c] = (bf16)0.0f;
+    bf16x8* d11 = reinterpret_cast<bf16x8*>(dz11 + m * 32);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) d11[j] = z[j];
+    z[0][0] = (bf16)(sig[m] > 0.0f ? dsig[m] : 0.0f);
+    z[0][1] = (bf16)0.0f; z[0][2] = (bf16)0.0f;
+    bf16x8* dh = reinterpret_cast<bf16x8*>(dzh + m * ldh + w);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dh[j] = z[j];
 }
 
 // Per-sample density max into the occupancy grid. The density is >= 0 (its
 // bits as a signed integer are >= 0 and ordered like the floats), and every
 // negative float (-0 included) has a negative signed pattern, so a signed
 // integer max gives max(cell, sigma) whatever non-NaN value the cell held.
-__global__ void k_gocc(int64_t M, const float* __restrict__ sig, const int32_t* __restrict__ voxel,
-                       int* __restrict__ grid) {
+// Consecutive samples of a ray that lie in one cell are neighbouring lanes:
+// each run's first lane takes the maximum over the run (a doubling over the
+// following lanes with the same cell; lanes of the same cell further on may
+// join it, which changes nothing) and alone issues the atomic.
+__global__ __launch_bounds__(256) void k_gocc(int64_t M, const float* __restrict__ sig,
+                                              const int32_t* __restrict__ voxel, int* __restrict__ grid) {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    const int v = voxel[m];
-    if (v < 0) return;
-    const float s = sig[m] > 0.0f ? sig[m] : 0.0f;
-    atomicMax(grid + v, __float_as_int(s));
+    const int lane = threadIdx.x & 63;
+    int v = -1, best = 0;
+    if (m < M) {
+        v = voxel[m];
+        best = __float_as_int(sig[m] > 0.0f ? sig[m] : 0.0f);
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int vo = __shfl_down(v, d, 64);
+        const int bo = __shfl_down(best, d, 64);
+        if (lane + d < 64 && vo == v) best = max(best, bo);
+    }
+    const int prev = __shfl_up(v, 1, 64);
+    if (v >= 0 && (lane == 0 || prev != v)) atomicMax(grid + v, best);
 }
 
 GNetDev dev_net(const GNet& n) {
