@@ -159,7 +159,11 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         ds0 = ds[0]; ds1 = ds[1]; ds2 = ds[2];
     }
     const float o0 = o[0], o1 = o[1], o2 = o[2];
-    const float lo0 = lo[0], lo1 = lo[1], lo2 = lo[2];
+    // the grid corner in vector registers: the per-step fma(plane, voxel,
+    // corner) then reads one scalar operand (the voxel edge), the most a
+    // vector instruction may, instead of copying the corner in every step
+    float lo0 = lo[0], lo1 = lo[1], lo2 = lo[2];
+    asm volatile("" : "+v"(lo0), "+v"(lo1), "+v"(lo2));
     const float iv0 = inv[0], iv1 = inv[1], iv2 = inv[2];
     const unsigned nvox = (unsigned)P.n0 * (unsigned)P.n1 * (unsigned)P.n2;
     // labels read as unsigned 16-bit words: free labels (-1) become 0xFFFF,
@@ -169,7 +173,8 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
     float t_in = t0;
     // One traversal step (R360_DDA_STEP): handles the current voxel (label
     // `cur`) and requests the label of the next one into `nxt`; leaves the
-    // loop when the walk ends. The loop alternates the two label registers,
+    // loop when the walk ends or the cap is reached (one exit test per step,
+    // outside the emitting branch). The loop alternates the two label registers,
     // so the value just requested is not copied (which would wait for the
     // load) within the step. (A macro, not a lambda: captured references
     // would turn the per-axis selects into loads through selected pointers.)
@@ -184,28 +189,25 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
         const bool more = tna < t1 && (unsigned)lin_next < nvox;                     \
         nxt = ld32(labels, (unsigned)(more ? lin_next : lin));                       \
         __builtin_amdgcn_sched_barrier(0);                                           \
-        if (t_out > t_in && cur < 0x8000) {                                          \
-            if constexpr (!MULTI) {                                                  \
+        const bool hit = t_out > t_in && cur < 0x8000;                               \
+        if constexpr (!MULTI) {                                                      \
+            if (hit && count >= P.skip)                                              \
+                sink.emit(count - P.skip, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin); \
+            count += hit ? 1 : 0;                                                    \
+        } else if (hit) {                                                            \
+            /* P.spv pieces cut at fma(j, length / k, t_in) */                       \
+            const float piece = (t_out - t_in) / (float)P.spv;                       \
+            float b0 = t_in;                                                         \
+            for (int q = 0; q < P.spv; ++q) {                                        \
+                const float b1 = q + 1 == P.spv ? t_out                              \
+                                                : __builtin_fmaf((float)(q + 1), piece, t_in); \
                 if (count >= P.skip)                                                 \
-                    sink.emit(count - P.skip, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin); \
+                    sink.emit(count - P.skip, (b0 + b1) * 0.5f, b1 - b0, (int)cur, lin); \
+                b0 = b1;                                                             \
                 if (++count == P.max_samples) break;                                 \
-            } else {                                                                 \
-                /* P.spv pieces cut at fma(j, length / k, t_in) */                   \
-                const float piece = (t_out - t_in) / (float)P.spv;                   \
-                float b0 = t_in;                                                     \
-                bool full = false;                                                   \
-                for (int q = 0; q < P.spv; ++q) {                                    \
-                    const float b1 = q + 1 == P.spv ? t_out                          \
-                                                    : __builtin_fmaf((float)(q + 1), piece, t_in); \
-                    if (count >= P.skip)                                             \
-                        sink.emit(count - P.skip, (b0 + b1) * 0.5f, b1 - b0, (int)cur, lin); \
-                    b0 = b1;                                                         \
-                    if (++count == P.max_samples) { full = true; break; }            \
-                }                                                                    \
-                if (full) break;                                                     \
             }                                                                        \
         }                                                                            \
-        if (!more) break;                                                            \
+        if (!more || count == P.max_samples) break;                                  \
         t_in = mx(t_in, tna);                                                        \
         /* every axis's next plane, kept only for the crossed axis */                \
         const float pn0 = pk0 + sf0, pn1 = pk1 + sf1, pn2 = pk2 + sf2;               \
