@@ -208,7 +208,16 @@ struct BwdGeom {
     static constexpr int PER_WAVE(int ly) { return (TILES(ly) + BW - 1) / BW; }
     static constexpr int ROWS = 2 * H + 32;        // largest x + dz panel (L3 / HEAD)
     static constexpr int PSTRIDE = BCH + 8;        // samples per panel row, padded
+    static_assert(ROWS % 32 == 0, "panel rows in whole 32-row blocks (prow)");
 };
+
+// Panel row of logical row base16 + low (base16 a multiple of 16, low < 16):
+// the two 16-row tiles of each 32-row block are interleaved (physical row
+// 2 low + tile parity). A 16-byte LDS read is served 32 lanes at a time over
+// 32 slots of 16 bytes; with 272-byte rows (17 slots) a fragment read's 16
+// consecutive rows would put two lanes in one slot, while every other row
+// (an even slot step) puts the 16 rows and two pieces in distinct slots.
+__device__ __forceinline__ int prow(int base16, int low) { return (base16 & ~31) | (low << 1) | ((base16 >> 4) & 1); }
 
 // Tiles of one layer's OT x IT weight-gradient grid (row-major) held by wave
 // wv: the contiguous range [wv T / BW, (wv + 1) T / BW) (wv is wave-uniform).
@@ -234,8 +243,8 @@ __device__ __forceinline__ void dw_stage(const T* panel, int pstride, int XR, in
             const int ot = k / IT, it = k % IT;
 #pragma unroll
             for (int ks = 0; ks < BCH / 32; ++ks) {
-                const F8 A = *reinterpret_cast<const F8*>(panel + (XR + 16 * ot + l16) * pstride + 32 * ks + 8 * g);
-                const F8 B = *reinterpret_cast<const F8*>(panel + (16 * it + l16) * pstride + 32 * ks + 8 * g);
+                const F8 A = *reinterpret_cast<const F8*>(panel + prow(XR + 16 * ot, l16) * pstride + 32 * ks + 8 * g);
+                const F8 B = *reinterpret_cast<const F8*>(panel + prow(16 * it, l16) * pstride + 32 * ks + 8 * g);
                 acc[q] = mma<T>(A, B, acc[q]);
             }
         }
@@ -512,16 +521,16 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 #pragma unroll
                 for (int ks = 0; ks < KH; ++ks)
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) panel[(row0 + hidden_col16(ks, g, e)) * PS + col] = hb[ks][e];
+                    for (int e = 0; e < 8; ++e) panel[prow(row0 + 16 * (2 * ks + (e >> 2)), 4 * g + (e & 3)) * PS + col] = hb[ks][e];
             };
             auto put_ones = [&](int row0) {
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) panel[(row0 + 4 * g + rr) * PS + col] = (T)((4 * g + rr) == 0 ? 1.0f : 0.0f);
+                for (int rr = 0; rr < 4; ++rr) panel[prow(row0, 4 * g + rr) * PS + col] = (T)((4 * g + rr) == 0 ? 1.0f : 0.0f);
             };
             auto put_tiles = [&](int row0, const f32x4* tl, int ntl) {
                 for (int tt = 0; tt < ntl; ++tt)
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) panel[(row0 + 16 * tt + 4 * g + rr) * PS + col] = (T)tl[tt][rr];
+                    for (int rr = 0; rr < 4; ++rr) panel[prow(row0 + 16 * tt, 4 * g + rr) * PS + col] = (T)tl[tt][rr];
             };
             // tiles [0, ntl) of hand-off fragments (tile 2ks + e/4, row 4g + e%4)
             auto put_frags = [&](int row0, const F8* fb_, int ntl) {
@@ -529,7 +538,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
                 for (int ks = 0; ks < (ntl + 1) / 2; ++ks)
 #pragma unroll
                     for (int e = 0; e < 8; ++e)
-                        if (2 * ks + (e >> 2) < ntl) panel[(row0 + hidden_col16(ks, g, e)) * PS + col] = fb_[ks][e];
+                        if (2 * ks + (e >> 2) < ntl) panel[prow(row0 + 16 * (2 * ks + (e >> 2)), 4 * g + (e & 3)) * PS + col] = fb_[ks][e];
             };
             // dz in fragment form, masked by the layer input's ReLU
             auto masked = [&](F8* bz, const f32x4* dz, const F8* hb) {
@@ -557,7 +566,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             // ---- L3: dW3 over [f ; g(d)] and df = W3_f^T dz3 ----
             put_hidden(0, fb);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) panel[(H + hidden_col16(0, g, e)) * PS + col] = xd[e];
+            for (int e = 0; e < 8; ++e) panel[prow(H + 16 * (e >> 2), 4 * g + (e & 3)) * PS + col] = xd[e];
             put_frags(H + 32, bz3, NT);
             __syncthreads();
             dw_stage<T, N3>(panel, PS, H + 32, NT, NT + 2, wv, lane, w3);
@@ -627,8 +636,8 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             // ---- L1: dW1 over the encoding slots ----
 #pragma unroll
             for (int s2 = 0; s2 < 8; ++s2) {
-                panel[hidden_col16(0, g, s2) * PS + col] = x0[s2];
-                panel[hidden_col16(1, g, s2) * PS + col] = x1[s2];
+                panel[prow(16 * (s2 >> 2), 4 * g + (s2 & 3)) * PS + col] = x0[s2];
+                panel[prow(16 * (2 + (s2 >> 2)), 4 * g + (s2 & 3)) * PS + col] = x1[s2];
             }
             put_frags(64, bz1, NT);
             __syncthreads();

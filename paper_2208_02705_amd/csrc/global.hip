@@ -454,8 +454,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
 // Weight-resident row GEMM for the forward and input-gradient layers whose
 // B (C <= 272 rows of Kc) fits in LDS: out[r][c] = sum_k A[r][k] B[c][k].
 // One block per CU stages B in LDS once (rows padded to whole 16-row tiles
-// with zeros, row stride Kc + 8 elements so that the 16 rows a fragment read
-// touches fall in distinct banks); each wave then walks 16-row tiles of A on
+// with zeros, row stride Kc + 16 elements: a 16-byte LDS read is served 32
+// lanes at a time over 32 slots of 16 bytes, and the lanes (row l, piece q)
+// of a fragment read then fall in distinct slots, which a row stride of
+// Kc + 8 (an odd number of slots) does not give); each wave then walks 16-row tiles of A on
 // its own, with no block barrier: the tile's operand fragments come straight
 // from memory (lane group q reads the 16-byte piece 8q of each 32-wide k
 // step of its row) and the next tile's are loaded while the current one is
@@ -543,7 +545,7 @@ template <int EPI, int KS>
 __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) {
     extern __shared__ __attribute__((aligned(16))) char rw_raw[];
     bf16* const wsm = reinterpret_cast<bf16*>(rw_raw);
-    constexpr int KP = 32 * KS + 8;                        // LDS row stride (elements)
+    constexpr int KP = 32 * KS + 16;                       // LDS row stride (elements)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     {
         constexpr int PQ = 4 * KS;                         // 16-byte pieces per row
@@ -638,8 +640,8 @@ template <int EPI>
 static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
     if (a.Kc % 32 || a.C > 272 || a.R < 1) return false;
     const int KS = a.Kc / 32, CT = (a.C + 15) / 16;
-    const size_t lds = (size_t)16 * CT * (a.Kc + 8) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
-    if (lds > (size_t)150 * 1024) return false;
+    const size_t lds = (size_t)16 * CT * (a.Kc + 16) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
+    if (lds > (size_t)160 * 1024) return false;
     switch (KS) {
     case 1: *err = rowmm_launch<EPI, 1>(a, CT, lds, st); return true;
     case 2: *err = rowmm_launch<EPI, 2>(a, CT, lds, st); return true;
@@ -657,12 +659,15 @@ static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
 // samples: the MFMA fragments are then plain 16-byte LDS reads. The next
 // step's blocks are loaded while this step's MFMAs run. Bias gradients (row
 // sums of A over the samples) come from extra MFMAs against a ones fragment.
-// Within an LDS row the eight 8-sample chunks are permuted by an XOR with
-// 2 ((row >> 4) & 3): the 16-byte stores of a wave (16 or 32 column blocks,
-// rows 8 apart) then spread over all banks instead of half of them, while
-// the 16 rows a fragment read covers share one permutation.
+// LDS rows are 160 bytes (ten 16-byte slots, an even number not divisible
+// by four): a 16-byte read is served 32 lanes at a time over 32 slots, and
+// the fragment reads (16 rows, two pieces per 32 lanes) then fall in
+// distinct slots. Within a row the eight 8-sample chunks are permuted by an
+// XOR with 2 ((row >> 4) & 3), which spreads the transposed 16-byte stores
+// of a wave (16 or 32 column blocks, rows 8 apart) while the 16 rows a
+// fragment read covers share one permutation.
 constexpr int DK = 64;
-constexpr int DPAD = DK + 8;    // 144-byte LDS rows
+constexpr int DPAD = DK + 16;   // 160-byte LDS rows
 
 __device__ __forceinline__ void transpose8(const u4 in[8], u4 out[8]) {
     // in[q] = 8 columns of sample row q (two 16-bit columns per dword);
