@@ -517,28 +517,80 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             }
 
             // Panel writers: hidden features from hand-off fragments, C-layout tiles.
+            // 16-bit paths: neighbouring lanes (samples 2m, 2m + 1) swap halves of
+            // each packed pair of rows (one DPP move and one byte permute), so
+            // that each lane stores two samples of one row with a 4-byte store:
+            // the even lane the pair's first row, the odd lane its second.
+            constexpr bool SM = sizeof(T) == 2;
+            const int odd = j & 1;
+            const unsigned psel = odd ? 0x03020706u : 0x05040100u;
+            // dword w holds rows (low, low + 1) of tile base16 for this lane's sample
+            auto st2 = [&](int base16, int low, unsigned w) {
+                const unsigned theirs = (unsigned)__builtin_amdgcn_mov_dpp((int)w, 0xB1, 0xF, 0xF, false);
+                const unsigned out = __builtin_amdgcn_perm(theirs, w, psel);
+                *reinterpret_cast<unsigned*>(panel + prow(base16, low + odd) * PS + col - odd) = out;
+            };
+            auto st_frag = [&](int base16_lo, int base16_hi, F8 v) {
+                if constexpr (SM) {
+                    const u32x4 w = __builtin_bit_cast(u32x4, v);
+                    st2(base16_lo, 4 * g, w[0]);
+                    st2(base16_lo, 4 * g + 2, w[1]);
+                    st2(base16_hi, 4 * g, w[2]);
+                    st2(base16_hi, 4 * g + 2, w[3]);
+                }
+            };
             auto put_hidden = [&](int row0, const F8* hb) {
 #pragma unroll
-                for (int ks = 0; ks < KH; ++ks)
+                for (int ks = 0; ks < KH; ++ks) {
+                    if constexpr (SM) {
+                        st_frag(row0 + 32 * ks, row0 + 32 * ks + 16, hb[ks]);
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) panel[prow(row0 + 16 * (2 * ks + (e >> 2)), 4 * g + (e & 3)) * PS + col] = hb[ks][e];
+                        for (int e = 0; e < 8; ++e) panel[prow(row0 + 16 * (2 * ks + (e >> 2)), 4 * g + (e & 3)) * PS + col] = hb[ks][e];
+                    }
+                }
             };
             auto put_ones = [&](int row0) {
+                if constexpr (SM) {
+                    // row 0 of the tile is 1 for every sample, rows 1..15 are 0
+                    const unsigned one = __builtin_bit_cast(unsigned short, (T)1.0f);
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) panel[prow(row0, 4 * g + rr) * PS + col] = (T)((4 * g + rr) == 0 ? 1.0f : 0.0f);
+                    for (int rr = 0; rr < 4; rr += 2) {
+                        const unsigned v = (4 * g + rr + odd == 0) ? (one | (one << 16)) : 0u;
+                        *reinterpret_cast<unsigned*>(panel + prow(row0, 4 * g + rr + odd) * PS + col - odd) = v;
+                    }
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) panel[prow(row0, 4 * g + rr) * PS + col] = (T)((4 * g + rr) == 0 ? 1.0f : 0.0f);
+                }
             };
             auto put_tiles = [&](int row0, const f32x4* tl, int ntl) {
-                for (int tt = 0; tt < ntl; ++tt)
+                for (int tt = 0; tt < ntl; ++tt) {
+                    if constexpr (SM) {
+                        const F8 v = hand<T, false>(tl[tt], f32x4{0.f, 0.f, 0.f, 0.f});
+                        const u32x4 w = __builtin_bit_cast(u32x4, v);
+                        st2(row0 + 16 * tt, 4 * g, w[0]);
+                        st2(row0 + 16 * tt, 4 * g + 2, w[1]);
+                    } else {
 #pragma unroll
-                    for (int rr = 0; rr < 4; ++rr) panel[prow(row0 + 16 * tt, 4 * g + rr) * PS + col] = (T)tl[tt][rr];
+                        for (int rr = 0; rr < 4; ++rr) panel[prow(row0 + 16 * tt, 4 * g + rr) * PS + col] = (T)tl[tt][rr];
+                    }
+                }
             };
             // tiles [0, ntl) of hand-off fragments (tile 2ks + e/4, row 4g + e%4)
             auto put_frags = [&](int row0, const F8* fb_, int ntl) {
 #pragma unroll
-                for (int ks = 0; ks < (ntl + 1) / 2; ++ks)
+                for (int ks = 0; ks < (ntl + 1) / 2; ++ks) {
+                    if constexpr (SM) {
+                        const u32x4 w = __builtin_bit_cast(u32x4, fb_[ks]);
+                        if (2 * ks < ntl) { st2(row0 + 32 * ks, 4 * g, w[0]); st2(row0 + 32 * ks, 4 * g + 2, w[1]); }
+                        if (2 * ks + 1 < ntl) { st2(row0 + 32 * ks + 16, 4 * g, w[2]); st2(row0 + 32 * ks + 16, 4 * g + 2, w[3]); }
+                    } else {
 #pragma unroll
-                    for (int e = 0; e < 8; ++e)
-                        if (2 * ks + (e >> 2) < ntl) panel[prow(row0 + 16 * (2 * ks + (e >> 2)), 4 * g + (e & 3)) * PS + col] = fb_[ks][e];
+                        for (int e = 0; e < 8; ++e)
+                            if (2 * ks + (e >> 2) < ntl) panel[prow(row0 + 16 * (2 * ks + (e >> 2)), 4 * g + (e & 3)) * PS + col] = fb_[ks][e];
+                    }
+                }
             };
             // dz in fragment form, masked by the layer input's ReLU
             auto masked = [&](F8* bz, const f32x4* dz, const F8* hb) {
@@ -565,8 +617,12 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             __builtin_amdgcn_sched_barrier(0);
             // ---- L3: dW3 over [f ; g(d)] and df = W3_f^T dz3 ----
             put_hidden(0, fb);
+            if constexpr (SM) {
+                st_frag(H, H + 16, xd);
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) panel[prow(H + 16 * (e >> 2), 4 * g + (e & 3)) * PS + col] = xd[e];
+                for (int e = 0; e < 8; ++e) panel[prow(H + 16 * (e >> 2), 4 * g + (e & 3)) * PS + col] = xd[e];
+            }
             put_frags(H + 32, bz3, NT);
             __syncthreads();
             dw_stage<T, N3>(panel, PS, H + 32, NT, NT + 2, wv, lane, w3);
@@ -634,10 +690,15 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
             masked(bz1, dz, h1);
             __builtin_amdgcn_sched_barrier(0);
             // ---- L1: dW1 over the encoding slots ----
+            if constexpr (SM) {
+                st_frag(0, 16, x0);
+                st_frag(32, 48, x1);
+            } else {
 #pragma unroll
-            for (int s2 = 0; s2 < 8; ++s2) {
-                panel[prow(16 * (s2 >> 2), 4 * g + (s2 & 3)) * PS + col] = x0[s2];
-                panel[prow(16 * (2 + (s2 >> 2)), 4 * g + (s2 & 3)) * PS + col] = x1[s2];
+                for (int s2 = 0; s2 < 8; ++s2) {
+                    panel[prow(16 * (s2 >> 2), 4 * g + (s2 & 3)) * PS + col] = x0[s2];
+                    panel[prow(16 * (2 + (s2 >> 2)), 4 * g + (s2 & 3)) * PS + col] = x1[s2];
+                }
             }
             put_frags(64, bz1, NT);
             __syncthreads();
