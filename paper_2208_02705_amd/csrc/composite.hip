@@ -13,6 +13,27 @@ namespace r360 {
 
 namespace {
 
+// exp(-x) from the hardware exponential (relative error about x 2^-24 from
+// the scaling by log2 e plus an ulp, far inside the FP32 render tolerance).
+__device__ __forceinline__ float exp_neg(float x) { return __expf(-x); }
+
+// alpha = 1 - exp(-x) for x >= 0: below 1/4 its Taylor series to x^7 in
+// nested form (the first omitted term, x^8 / 8!, is below 4e-10, about 2e-9
+// of the result), above from the hardware exponential (no cancellation:
+// the result is at least 0.22).
+constexpr double fct(int k) { return k <= 1 ? 1.0 : k * fct(k - 1); }
+constexpr float kA2 = (float)(-1.0 / fct(2)), kA3 = (float)(1.0 / fct(3)), kA4 = (float)(-1.0 / fct(4)),
+                kA5 = (float)(1.0 / fct(5)), kA6 = (float)(-1.0 / fct(6)), kA7 = (float)(1.0 / fct(7));
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
+    float p = __builtin_fmaf(x, kA7, kA6);
+    p = __builtin_fmaf(x, p, kA5);
+    p = __builtin_fmaf(x, p, kA4);
+    p = __builtin_fmaf(x, p, kA3);
+    p = __builtin_fmaf(x, p, kA2);
+    p = __builtin_fmaf(x, p, 1.0f) * x;
+    return x < 0.25f ? p : 1.0f - __expf(-x);
+}
+
 // Sample-parallel compositing. Each wave owns `rpw` consecutive rays, whose
 // samples form one contiguous range, and walks that range 64 samples at a
 // time with one sample per lane (coalesced loads of every per-sample array,
@@ -153,7 +174,7 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
             float S = dppf<DPP_WAVE_SHR1>(0.0f, incl);
             if (lane == cs.seg) S = 0.0f;
             if (cs.cont) S += cS;
-            const float w = cs.valid ? expf(-S) * -expm1f(-tau) : 0.0f;
+            const float w = cs.valid ? exp_neg(S) * one_minus_exp_neg(tau) : 0.0f;
             float a0 = seg_scan(w * in[u].q0, lane, cs.seg), a1 = seg_scan(w * in[u].q1, lane, cs.seg);
             float a2 = seg_scan(w * in[u].q2, lane, cs.seg), aD = seg_scan(w * in[u].tm, lane, cs.seg);
             float aA = seg_scan(w, lane, cs.seg);
@@ -219,7 +240,7 @@ __global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restri
         for (int u = 0; u < CB; ++u) {
             if (k + u < c) {
                 const float tau = sg[u] * dl[u];
-                const float w = expf(-S) * -expm1f(-tau);
+                const float w = exp_neg(S) * one_minus_exp_neg(tau);
                 c0 += w * q0[u]; c1 += w * q1[u]; c2 += w * q2[u];
                 D += w * tm[u];
                 A += w;
@@ -237,7 +258,7 @@ __global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restri
 }
 
 // Early termination: the rays that continue after their first K samples are
-// those that emitted all K and whose transmittance expf(-S) is still at least
+// those that emitted all K and whose transmittance exp(-S) is still at least
 // eps. The list order (atomic) affects no result: every ray is composited on
 // its own and every sample's field MLP output is independent of its batch.
 __global__ __launch_bounds__(256) void k_term_select(int64_t N, const int32_t* __restrict__ cnt, int K,
@@ -245,7 +266,7 @@ __global__ __launch_bounds__(256) void k_term_select(int64_t N, const int32_t* _
                                                      int32_t* __restrict__ list, int32_t* __restrict__ n2) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
-    if (cnt[r] == K && expf(-S[r]) >= eps) list[atomicAdd(n2, 1)] = (int32_t)r;
+    if (cnt[r] == K && exp_neg(S[r]) >= eps) list[atomicAdd(n2, 1)] = (int32_t)r;
 }
 
 __global__ void k_term_zero(int32_t* __restrict__ n2) { *n2 = 0; }
@@ -298,14 +319,14 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
             for (int u = 0; u < CBB; ++u) {
                 if (k + u < c) {
                     const float tau = sg[u] * dl[u];
-                    const float w = expf(-S) * -expm1f(-tau);
+                    const float w = exp_neg(S) * one_minus_exp_neg(tau);
                     P0 += w * q0[u]; P1 += w * q1[u]; P2 += w * q2[u];
                     S += tau;
                     if (pass == 1) {
                         const unsigned i = base + 64u * (unsigned)(k + u);
                         const float cg = q0[u] * g0 + q1[u] * g1 + q2[u] * g2;
                         const float rg = (C0 - P0) * g0 + (C1 - P1) * g1 + (C2 - P2) * g2;
-                        st32(dsigma, i, dl[u] * (expf(-S) * cg - rg));
+                        st32(dsigma, i, dl[u] * (exp_neg(S) * cg - rg));
                         st32(drgb, i, w * g0); st32(drgb1, i, w * g1); st32(drgb2, i, w * g2);
                     }
                 }
@@ -393,7 +414,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const int32_t* __restrict
                 float S = dppf<DPP_WAVE_SHR1>(0.0f, incl);
                 if (lane == cs.seg) S = 0.0f;
                 if (cs.cont) S += cS;
-                const float w = cs.valid ? expf(-S) * -expm1f(-tau) : 0.0f;
+                const float w = cs.valid ? exp_neg(S) * one_minus_exp_neg(tau) : 0.0f;
                 const float cg = q0 * g0 + q1 * g1 + q2 * g2;
                 float U = seg_scan(w * cg, lane, cs.seg);
                 if (cs.cont) U += cU;
@@ -402,7 +423,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(const int32_t* __restrict
                     if (cs.ends) u_tot[wv][cs.ray - rb] = U;
                 } else if (cs.valid) {
                     const float tail = u_tot[wv][cs.ray - rb] - U;
-                    const float Tn = expf(-(S + tau));
+                    const float Tn = exp_neg(S + tau);
                     dsigma[s] = dl * (Tn * cg - tail);
                     drgb[s] = w * g0;
                     drgb[cap + s] = w * g1;
