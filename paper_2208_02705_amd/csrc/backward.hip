@@ -746,30 +746,49 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 
 // Adds the partial slots of fields shared by several blocks, in block order.
 // bf: the first and last field of every block's slice (written by k_bwd).
+// Blocks (x, f): field f, the x-th of gridDim.x interleaved parts of its P
+// parameters; the field's contributing slots are listed once per block.
+// P is a multiple of 4 and every row starts on 16 bytes (16-byte loads).
+constexpr int DWR_PARTS = 4;
 __global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, float* __restrict__ grad,
                                                    const int32_t* __restrict__ start,
                                                    const int32_t* __restrict__ chunk_start,
                                                    const int32_t* __restrict__ bf, int F, int P, int nb) {
+    __shared__ int slots[DW_SLOTS / 2];      // at most one per backward block (nb <= DW_SLOTS / 2)
+    __shared__ int nslot;
     const int f = blockIdx.y;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= P) return;
     const int U = chunk_start[F];
     const int uf = chunk_start[f];
     const int c = (start[f + 1] - start[f] + BCH - 1) / BCH;
-    if (c == 0) { grad[(int64_t)f * P + p] = 0.0f; return; }
+    const int P4 = P / 4;
+    f32x4* g4 = reinterpret_cast<f32x4*>(grad + (int64_t)f * P);
+    if (c == 0) {
+        for (int i = blockIdx.x * 256 + threadIdx.x; i < P4; i += gridDim.x * 256) g4[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        return;
+    }
     const int b0 = block_of_unit(uf, U, nb), b1 = block_of_unit(uf + UNITS_PER_CHUNK * (c - 1), U, nb);
     if (b0 == b1 && f != bf[2 * b0] && f != bf[2 * b0 + 1]) return;   // written directly
-    float acc = 0.0f;
-    for (int b = b0; b <= b1; ++b) {
+    if (threadIdx.x == 0) {
         // blocks where no chunk of this field starts (with fewer units than
         // blocks, empty ones lie in between) wrote nothing for it
-        int j0, j1;
-        chunks_in(uf, c, unit_lo(b, U, nb), unit_lo(b + 1, U, nb), &j0, &j1);
-        if (j1 <= j0) continue;
-        const int slot = (f == bf[2 * b]) ? 2 * b : 2 * b + 1;
-        acc += part[(int64_t)slot * P + p];
+        int n = 0;
+        for (int b = b0; b <= b1; ++b) {
+            int j0, j1;
+            chunks_in(uf, c, unit_lo(b, U, nb), unit_lo(b + 1, U, nb), &j0, &j1);
+            if (j1 > j0) slots[n++] = (f == bf[2 * b]) ? 2 * b : 2 * b + 1;
+        }
+        nslot = n;
     }
-    grad[(int64_t)f * P + p] = acc;
+    __syncthreads();
+    const int n = nslot;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < P4; i += gridDim.x * 256) {
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k = 0; k < n; ++k) {
+            const f32x4 v = reinterpret_cast<const f32x4*>(part + (int64_t)slots[k] * P)[i];
+            acc[0] += v[0]; acc[1] += v[1]; acc[2] += v[2]; acc[3] += v[3];
+        }
+        g4[i] = acc;
+    }
 }
 
 template <typename K>
@@ -826,7 +845,7 @@ hipError_t bwd_launch(const r360_scene* s, const Workspace& w, const void* pack,
     hipLaunchKernelGGL((k_bwd<H, T>), dim3(nb), dim3(64 * BW), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dw_reduce, dim3((a.P + 255) / 256, a.F), dim3(256), 0, st, w.dw_part, grad, w.field_start,
+    hipLaunchKernelGGL(k_dw_reduce, dim3(DWR_PARTS, a.F), dim3(256), 0, st, w.dw_part, grad, w.field_start,
                        w.chunk_start, w.blk_fields, a.F, a.P, nb);
     return hipGetLastError();
 }
