@@ -6,30 +6,40 @@
 // receives s_k = floor(S/n) + (k < S mod n) of them. For k = 0, 1, ...: the
 // anchor is the unassigned occupied voxel of smallest linear index (the
 // minimum coordinate, z then y then x) and the field takes the s_k
-// unassigned voxels nearest to it (squared distance between voxel indices,
-// ties to the smaller linear index). Each voxel's rank is the unique key
-// (d^2 << LB) | lin (LB the bit width of the linear index; at most 57 bits
-// for grids of up to 4096^3 voxels), so field k is exactly the keys up to
-// the s_k-th smallest; that key is found by a radix select over 12-bit
-// digits from the top (LV levels, 4 for the 128^3 and 256^3 grids), one
-// histogram per level, stopping as soon as a whole bin is taken. (Wider
-// digits save a level but every block clears, flushes and scans its whole
-// histogram: at 14 bits those fixed costs took most of each launch.)
+// unassigned voxels nearest to it (squared distance d^2 between voxel
+// indices, ties to the smaller linear index).
 //
-// Launches per field: one kernel that assigns the previous field, finds
-// this field's anchor, writes its keys and counts their top digits, then
-// one histogram kernel per further level. A level's digit is picked from
-// the previous level's histogram by every block of the kernel that needs it
-// (the same deterministic scan in each; block 0 stores the result for the
-// kernels after it), so no launch is spent on picks. Fields alternate
-// between two histogram sets: the one a field reads is cleared by the next
-// field's first histogram kernel.
+// Selection. The occupied voxels are listed in increasing linear index, so
+// among voxels at one distance the list order is the tie order. Field k is
+// therefore every unassigned entry with d^2 < D, plus the first r entries
+// in list order with d^2 = D, where D is the d^2 of its s_k-th nearest
+// voxel. D is found by a radix select over the digits of d^2 alone (d^2 <
+// 2^26 for grids up to 4096^3): one or two histogram levels of up to 12
+// bits from the top (one for grids up to 256^3), then a final digit of up
+// to 6 bits whose counts are kept per block, each block counting one
+// contiguous chunk of the list. With those counts the block holding the
+// r-th tie and the rank inside its chunk follow from a prefix over the
+// blocks, and one scan of that chunk gives the list position of the last
+// entry taken. A level whose picked bin is taken whole ends the search.
 //
-// Layout: the occupied voxels in increasing linear index (a stable
-// compaction), a done byte and a key per list entry; the walk over the list
-// starts at the first unassigned entry, which only moves forward.
-// Every step is a deterministic function of the keys (the histogram atomics
-// only count), so the field map is reproducible bit for bit.
+// Launches per field: one step kernel that settles the previous field's
+// threshold (final pick and tie position), assigns it, finds this field's
+// anchor, writes this field's d^2 and counts its top digit; then one kernel
+// per further digit (the last one keeps per-block counts). A level's digit
+// is picked from the previous level's histogram by every block of the
+// kernel that needs it (the same deterministic scan in each; block 0 stores
+// the result for the kernels after it). Fields alternate between two sets
+// of histograms and d^2 arrays: the step kernel settles field k from one
+// while it writes field k + 1's into the other, and the first digit kernel
+// of field k + 1 clears field k's histograms.
+//
+// Layout: the list of occupied voxels and two d^2 arrays per entry (SENT
+// marks an entry assigned before the field), padded to whole groups of 16
+// entries; the passes take units of 4 consecutive entries per thread
+// (16-byte loads and stores), the chunk scan whole groups. The walk over
+// the list starts at the first unassigned entry, which only moves forward.
+// Every step is a deterministic function of the occupancy (the histogram
+// atomics only count), so the field map is reproducible bit for bit.
 #include "r360_internal.h"
 
 namespace r360 {
@@ -37,21 +47,43 @@ namespace r360 {
 namespace {
 
 constexpr int CB = 4096;            // voxels per compaction block (256 threads x 16)
-constexpr int DIG = 12;             // digit width of the radix select
+constexpr int DIG = 12;             // widest histogram digit
 constexpr int NBIN = 1 << DIG;      // histogram bins per level
-constexpr int LVMAX = 5;            // 57-bit keys
-constexpr uint64_t NOKEY = ~uint64_t(0);
-// Blocks of the selection kernels (each holds a 16 KB histogram and pays its
-// fixed costs): one per 1024 occupied voxels, between 64 and 256 (256 for
-// the large grid, 128 for the room scene, the measured best of 64/128/256).
-inline unsigned sel_grid(int64_t S) { return (unsigned)std::min<int64_t>(256, std::max<int64_t>(64, S / 1024)); }
+constexpr int HLMAX = 2;            // histogram levels (d^2 < 2^26: at most 20 bits above the final digit)
+constexpr int FW = 6;               // widest final digit
+constexpr int NFIN = 1 << FW;       // its values
+constexpr int ST = 1024;            // threads per block of the selection kernels
+constexpr int GMAX = 64;            // their blocks, at most
+constexpr uint32_t SENT = 0xFFFFFFFFu;   // d^2 of an entry outside the field's candidates
+// One histogram set: level 0 in NCOPY copies (block b adds into copy b mod
+// NCOPY, so that the blocks' flushes do not all meet at one address), the
+// further levels, then the final digit's totals.
+constexpr int NCOPY = 1;
+constexpr int HSET = (NCOPY + HLMAX - 1) * NBIN + NFIN;
+constexpr int HTOT = (NCOPY + HLMAX - 1) * NBIN;
+__host__ __device__ constexpr int lv_off(int l) { return l == 0 ? 0 : (NCOPY + l - 1) * NBIN; }
+__host__ __device__ constexpr int lv_copies(int l) { return l == 0 ? NCOPY : 1; }
+// Blocks of the selection kernels: one per 2 K occupied voxels, at most
+// 64. Few, wide blocks: each block adds its histogram into the global one
+// with one atomic per non-empty bin, so the block count sets how many
+// atomics meet at each bin.
+inline unsigned sel_grid(int64_t S) {
+    return (unsigned)std::min<int64_t>(GMAX, std::max<int64_t>(1, (S + 2047) / 2048));
+}
 
-// Radix-select state after some levels: keys <= threshold join the field
-// once found; otherwise the s_k-th key lies among the keys whose top digits
-// equal prefix, at rank `need` there.
+// Digits of d^2 from the top: nh histogram levels (level l: w[l] bits at
+// shift sh[l]), then the final digit of wf bits at shift 0.
+struct Geom {
+    int nh, wf;
+    int w[HLMAX], sh[HLMAX];
+};
+
+// Radix-select state after some levels: if found, the field is the entries
+// with d^2 <= dlim; otherwise its s_k-th entry has d^2 >> (shift after the
+// level) = prefix, at rank `need` among those.
 struct Pick {
-    uint64_t prefix;
-    uint64_t threshold;
+    uint32_t prefix;
+    uint32_t dlim;
     int64_t need;
     int32_t found;
     int32_t pad;
@@ -60,15 +92,15 @@ struct FieldSel {
     int32_t first;        // first list entry not assigned before this field
     int32_t anchor;       // its linear index
     int32_t pad[2];
-    Pick lv[LVMAX + 1];   // lv[0]: before any level; lv[l + 1]: after picking level l
+    Pick lv[HLMAX + 1];   // lv[0]: before any level; lv[l + 1]: after picking level l
 };
 
 struct AssignWs {
-    int32_t* list;        // [nvox] occupied voxels, increasing linear index
-    uint8_t* done;        // [nvox]
-    uint64_t* key;        // [nvox]
+    int32_t* list;        // [nvox16] occupied voxels, increasing linear index
+    uint32_t* d2[2];      // [nvox16] d^2 to the anchor of the fields using each set, SENT for entries assigned before
     int32_t* bcount;      // [blocks] occupied voxels per compaction block, then their offsets
-    uint32_t* hist;       // [2][LVMAX][NBIN] two histogram sets
+    uint32_t* hist;       // [2][HSET] two histogram sets
+    uint32_t* cnt;        // [NFIN][GMAX] final-digit counts per block
     FieldSel* sel;        // [2]
     int32_t* total;       // S
 };
@@ -80,26 +112,28 @@ AssignWs carve_assign(void* base, int64_t nvox) {
     char* p = static_cast<char*>(base);
     size_t off = 0;
     auto take = [&](size_t bytes) { char* q = p + off; off += up256(bytes); return q; };
-    const int64_t nb = (nvox + CB - 1) / CB;
-    w.list = reinterpret_cast<int32_t*>(take(nvox * 4));
-    w.done = reinterpret_cast<uint8_t*>(take(nvox));
-    w.key = reinterpret_cast<uint64_t*>(take(nvox * 8));
+    const int64_t nb = (nvox + CB - 1) / CB, n16 = (nvox + 15) & ~int64_t(15);
+    w.list = reinterpret_cast<int32_t*>(take(n16 * 4));
+    w.d2[0] = reinterpret_cast<uint32_t*>(take(n16 * 4));
+    w.d2[1] = reinterpret_cast<uint32_t*>(take(n16 * 4));
     w.bcount = reinterpret_cast<int32_t*>(take(nb * 4));
-    w.hist = reinterpret_cast<uint32_t*>(take((size_t)2 * LVMAX * NBIN * 4));
+    w.hist = reinterpret_cast<uint32_t*>(take((size_t)2 * HSET * 4));
+    w.cnt = reinterpret_cast<uint32_t*>(take((size_t)NFIN * GMAX * 4));
     w.sel = reinterpret_cast<FieldSel*>(take(2 * sizeof(FieldSel)));
     w.total = reinterpret_cast<int32_t*>(take(4));
     return w;
 }
 
 size_t assign_bytes(int64_t nvox) {
-    const int64_t nb = (nvox + CB - 1) / CB;
-    return up256(nvox * 4) + up256(nvox) + up256(nvox * 8) + up256(nb * 4) + up256((size_t)2 * LVMAX * NBIN * 4) +
-           up256(2 * sizeof(FieldSel)) + up256(4);
+    const int64_t nb = (nvox + CB - 1) / CB, n16 = (nvox + 15) & ~int64_t(15);
+    return up256(n16 * 4) + 2 * up256(n16 * 4) + up256(nb * 4) + up256((size_t)2 * HSET * 4) +
+           up256((size_t)NFIN * GMAX * 4) + up256(2 * sizeof(FieldSel)) + up256(4);
 }
 
-// Exclusive prefix over a block of 256 threads; returns the block total.
-__device__ int block_scan256(int v, int& excl) {
-    __shared__ int wsum[4];
+// Exclusive prefix over a block of NT threads; returns the block total.
+template <int NT>
+__device__ int block_scan(int v, int& excl) {
+    __shared__ int wsum[NT / 64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int inc = v;
 #pragma unroll
@@ -111,7 +145,7 @@ __device__ int block_scan256(int v, int& excl) {
     __syncthreads();
     int before = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NT / 64; ++q) {
         before += q < wv ? wsum[q] : 0;
         tot += wsum[q];
     }
@@ -119,6 +153,7 @@ __device__ int block_scan256(int v, int& excl) {
     __syncthreads();
     return tot;
 }
+__device__ __forceinline__ int block_scan256(int v, int& excl) { return block_scan<256>(v, excl); }
 
 __global__ __launch_bounds__(256) void k_fill(int32_t* __restrict__ p, int64_t n, int32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -154,8 +189,7 @@ __global__ __launch_bounds__(256) void k_block_offsets(int32_t* __restrict__ bco
 }
 
 __global__ __launch_bounds__(256) void k_occ_scatter(const float* __restrict__ occ, float thr, int64_t nvox,
-                                                     const int32_t* __restrict__ boff, int32_t* __restrict__ list,
-                                                     uint8_t* __restrict__ done) {
+                                                     const int32_t* __restrict__ boff, int32_t* __restrict__ list) {
     const int64_t v0 = (int64_t)blockIdx.x * CB + threadIdx.x * 16;
     uint32_t bits = 0;
 #pragma unroll
@@ -165,55 +199,93 @@ __global__ __launch_bounds__(256) void k_occ_scatter(const float* __restrict__ o
     int pos = boff[blockIdx.x] + excl;
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-        if (bits & (1u << j)) {
-            list[pos] = (int32_t)(v0 + j);
-            done[pos] = 0;
-            ++pos;
-        }
+        if (bits & (1u << j)) list[pos++] = (int32_t)(v0 + j);
 }
 
-// Key geometry: LB bits of linear index under the squared distance; LV
-// levels of DIG bits cover the key from the top (level l: bits
-// [DIG (LV - 1 - l), DIG (LV - l))).
-struct KeyGeom {
-    int LB, LV;
-};
-__device__ __forceinline__ int lv_shift(const KeyGeom& kg, int l) { return DIG * (kg.LV - 1 - l); }
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4h;
+typedef __attribute__((ext_vector_type(4))) int i32x4h;
 
-// Picks level l's digit from its histogram (every thread of the block
-// returns the same state). The digit is the bin holding the need-th key;
-// a bin taken whole ends the search.
-__device__ Pick block_pick(Pick s, const uint32_t* __restrict__ hist, int shift) {
+typedef __attribute__((ext_vector_type(4))) int i32x4h;
+__device__ __forceinline__ void load_d2(const uint32_t* __restrict__ d2, int64_t g, uint32_t (&d)[16]) {
+    const u32x4h* p = reinterpret_cast<const u32x4h*>(d2 + 16 * g);
+    u32x4h v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = p[q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[4 * q + e] = v[q][e];
+}
+
+// Exact unsigned division of n < 2^31 by 2 <= d <= 4096 as one high
+// multiply: with l = ceil(log2 d) and m = ceil(2^(31+l) / d) < 2^32,
+// floor(n / d) = floor(n m / 2^(31+l)) (the excess m d - 2^(31+l) is below
+// d <= 2^l, so n times it stays below 2^(31+l)). For d = 1 the multiplier
+// is 0 and the numerator passes through a mask, so there is no branch.
+struct Divisor {
+    uint32_t m, d, one;   // one: all ones for d = 1, else 0
+    int sh;               // l - 1 (0 for d = 1)
+};
+inline Divisor make_divisor(uint32_t d) {
+    int l = 0;
+    while ((1u << l) < d) ++l;
+    if (d == 1) return Divisor{0u, 1u, ~0u, 0};
+    return Divisor{(uint32_t)(((uint64_t(1) << (31 + l)) + d - 1) / d), d, 0u, l - 1};
+}
+__device__ __forceinline__ uint32_t div_by(uint32_t n, const Divisor& v) {
+    return (__umulhi(n, v.m) >> v.sh) + (n & v.one);
+}
+
+// Voxel coordinates of a linear index and squared distances between them.
+struct Vox {
+    int x, y, z;
+};
+__device__ __forceinline__ Vox vox_of(uint32_t lin, const Divisor& n0, const Divisor& n1) {
+    const uint32_t q = div_by(lin, n0), z = div_by(q, n1);
+    return Vox{(int)(lin - q * n0.d), (int)(q - z * n1.d), (int)z};
+}
+__device__ __forceinline__ uint32_t dist2(const Vox& a, const Vox& b) {
+    const int dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;    // |d| < 2^12: 24-bit products are exact
+    return (uint32_t)(__mul24(dx, dx) + __mul24(dy, dy) + __mul24(dz, dz));
+}
+
+// Picks level l's digit (w bits, at shift sh) from its histogram; every
+// thread of the block returns the same state. The digit is the bin holding
+// the need-th entry; a bin taken whole ends the search.
+__device__ Pick block_pick(Pick s, const uint32_t* __restrict__ hist, int ncopy, int w, int sh) {
     __shared__ Pick res;
     if (s.found) return s;                               // uniform
-    constexpr int PER = NBIN / 256;                      // bins per thread, in order, held in registers
-    typedef __attribute__((ext_vector_type(4))) unsigned u32x4_;
+    constexpr int PER = NBIN / ST;                       // bins per thread, in order, held in registers
     uint32_t hb[PER];
-    const u32x4_* src = reinterpret_cast<const u32x4_*>(hist + threadIdx.x * PER);
 #pragma unroll
-    for (int q = 0; q < PER / 4; ++q) {
-        const u32x4_ v = src[q];
-        hb[4 * q] = v[0]; hb[4 * q + 1] = v[1]; hb[4 * q + 2] = v[2]; hb[4 * q + 3] = v[3];
+    for (int q = 0; q < PER; ++q) hb[q] = 0;
+    for (int c = 0; c < ncopy; ++c) {                    // the copies' sums
+        const u32x4h* src = reinterpret_cast<const u32x4h*>(hist + (size_t)c * NBIN + threadIdx.x * PER);
+#pragma unroll
+        for (int q = 0; q < PER / 4; ++q) {
+            const u32x4h v = src[q];
+            hb[4 * q] += v[0]; hb[4 * q + 1] += v[1]; hb[4 * q + 2] += v[2]; hb[4 * q + 3] += v[3];
+        }
     }
     int sum = 0;
 #pragma unroll
     for (int q = 0; q < PER; ++q) sum += (int)hb[q];
     int excl;
-    block_scan256(sum, excl);
-    if (excl < s.need && s.need <= excl + sum) {         // exactly one thread holds the need-th key
+    block_scan<ST>(sum, excl);
+    if (excl < s.need && s.need <= excl + sum) {         // exactly one thread holds the need-th entry
         int64_t below = excl;
         int q = 0;
 #pragma unroll
         for (int t = 0; t < PER; ++t)                    // the first bin where the count reaches need
             if (t == q && below + hb[t] < s.need) { below += hb[t]; ++q; }
         Pick r;
-        r.prefix = (s.prefix << DIG) | (uint64_t)(threadIdx.x * PER + q);
+        r.prefix = (s.prefix << w) | (uint32_t)(threadIdx.x * PER + q);
         r.need = s.need - below;
         uint32_t cq = 0;
 #pragma unroll
         for (int t = 0; t < PER; ++t) cq = t == q ? hb[t] : cq;
         r.found = (int64_t)cq == r.need ? 1 : 0;
-        r.threshold = r.found ? ((r.prefix << shift) | ((uint64_t(1) << shift) - 1)) : 0;
+        r.dlim = r.found ? (((r.prefix + 1u) << sh) - 1u) : 0u;
         r.pad = 0;
         res = r;
     }
@@ -223,145 +295,365 @@ __device__ Pick block_pick(Pick s, const uint32_t* __restrict__ hist, int shift)
     return r;
 }
 
-typedef __attribute__((ext_vector_type(4))) unsigned u32x4h;
 // Zeroes a block's LDS histogram (16 bytes per store).
 __device__ __forceinline__ void clear_hist(uint32_t* h) {
 #pragma unroll
-    for (int q = 0; q < NBIN / 1024; ++q) reinterpret_cast<u32x4h*>(h)[threadIdx.x + 256 * q] = u32x4h{0u, 0u, 0u, 0u};
+    for (int q = 0; q < NBIN / (4 * ST); ++q) reinterpret_cast<u32x4h*>(h)[threadIdx.x + ST * q] = u32x4h{0u, 0u, 0u, 0u};
 }
-// Adds a block's LDS histogram into a global one (16-byte LDS reads, one
-// atomic per non-empty bin).
-__device__ __forceinline__ void flush_hist(const uint32_t* h, uint32_t* __restrict__ dst) {
-#pragma unroll
-    for (int q = 0; q < NBIN / 1024; ++q) {
-        const int b = 4 * (threadIdx.x + 256 * q);
-        const u32x4h v = reinterpret_cast<const u32x4h*>(h)[threadIdx.x + 256 * q];
+// Adds the first nbin bins of a block's LDS histogram into a global one
+// (16-byte LDS reads, one atomic per non-empty bin).
+__device__ __forceinline__ void flush_hist(const uint32_t* h, uint32_t* __restrict__ dst, int nbin) {
+    for (int c = threadIdx.x; 4 * c < nbin; c += ST) {
+        const u32x4h v = reinterpret_cast<const u32x4h*>(h)[c];
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            if (v[e]) atomicAdd(&dst[b + e], v[e]);
+            if (v[e]) atomicAdd(&dst[4 * c + e], v[e]);
     }
+}
+
+// The contiguous chunk of groups that block b counts in the final digit:
+// groups [first / 16, ceil(S / 16)) cut into G equal chunks.
+__device__ __forceinline__ void chunk_of(int64_t first, int64_t S, int G, int b, int64_t& cb, int64_t& ce) {
+    const int64_t g0 = first >> 4, gend = (S + 15) >> 4, cg = (gend - g0 + G - 1) / G;
+    cb = g0 + (int64_t)b * cg;
+    cb = cb < gend ? cb : gend;
+    ce = cb + cg < gend ? cb + cg : gend;
 }
 
 struct StepArgs {
     const int32_t* list;
-    uint8_t* done;
-    uint64_t* key;
+    const uint32_t* d2cur;      // field k's d^2
+    uint32_t* d2nxt;            // field k + 1's, written here
     int64_t S;
-    int n0, n1;
-    KeyGeom kg;
-    const FieldSel* cur;        // field k (its keys and histograms are complete)
+    Divisor n0, n1;
+    Geom g;
+    const FieldSel* cur;        // field k (its digit kernels are complete)
     const uint32_t* hcur;       // its histogram set
+    const uint32_t* cnt;        // its final-digit counts per block
     FieldSel* nxt;              // field k + 1
     uint32_t* hnxt;
     int32_t field;              // k, or -1 before the first field
     int32_t take_all;           // field k takes every entry left
     int32_t has_next;
+    int32_t G;                  // blocks of the selection kernels (this grid)
     int64_t s_next;             // size of field k + 1
     int32_t* fmap;
 };
 
-// Assigns field k (keys <= its threshold, or all that are left), finds the
-// anchor of field k + 1 (the first entry neither assigned before nor taken
-// by field k), writes field k + 1's keys and counts their top digit.
-__global__ __launch_bounds__(256) void k_sel_step(StepArgs a) {
+// Inclusive prefix over a wave.
+__device__ __forceinline__ int wave_scan(int x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    return x;
+}
+
+// Settles field k's threshold: entries with d^2 < dlim, or d^2 = dlim at
+// list positions up to pos, belong to it. The totals of the final digit
+// and the whole matrix of per-block counts are loaded at once; the first
+// wave then finds the value of d^2 and the rank r among its ties, and the
+// block whose chunk holds the r-th tie with the rank there; one scan of
+// that chunk gives its position.
+// Its inputs (the state after the histogram levels, this thread's 16 bytes
+// of the per-block counts, and for the first wave one total each) are
+// loaded by the caller before anything else.
+struct SettleIn {
+    Pick s;
+    u32x4h cv;
+    int tv;
+};
+__device__ __forceinline__ SettleIn settle_load(const StepArgs& a) {
+    static_assert(NFIN * GMAX == 4 * ST, "one 16-byte load of counts per thread");
+    SettleIn in;
+    in.s = a.cur->lv[a.g.nh];
+    in.cv = reinterpret_cast<const u32x4h*>(a.cnt)[threadIdx.x];
+    in.tv = threadIdx.x < (1u << a.g.wf) ? (int)a.hcur[HTOT + threadIdx.x] : 0;
+    return in;
+}
+__device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uint32_t& dlim, int64_t& pos) {
+    __shared__ __attribute__((aligned(16))) uint32_t s_cnt[NFIN * GMAX];
+    __shared__ int s_v, s_whole, s_b;
+    __shared__ int64_t s_need, s_pos;
+    const Pick s = in.s;
+    const int tv = in.tv;
+    if (s.found) { dlim = s.dlim; pos = INT64_MAX; return; }     // uniform
+    const u32x4h cv = in.cv;
+    reinterpret_cast<u32x4h*>(s_cnt)[threadIdx.x] = cv;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int t = threadIdx.x;
+        const int inc = wave_scan(tv);
+        const int64_t ex = inc - tv;
+        const uint64_t m = __ballot(ex < s.need && s.need <= inc);
+        const int v = m ? __ffsll((unsigned long long)m) - 1 : 0;
+        const int64_t need = s.need - __shfl((int)ex, v, 64);
+        const int whole = need == __shfl(tv, v, 64) ? 1 : 0;
+        int b = 0;
+        int64_t r = need;
+        if (!whole) {
+            const int c = t < a.G ? (int)s_cnt[v * GMAX + t] : 0;
+            const int inc2 = wave_scan(c);
+            const int64_t ex2 = inc2 - c;
+            const uint64_t m2 = __ballot(c > 0 && ex2 < need && need <= inc2);
+            b = m2 ? __ffsll((unsigned long long)m2) - 1 : 0;
+            r = need - __shfl((int)ex2, b, 64);
+        }
+        if (t == 0) { s_v = v; s_whole = whole; s_b = b; s_need = r; s_pos = first; }
+    }
+    __syncthreads();
+    dlim = (s.prefix << a.g.wf) | (uint32_t)s_v;
+    if (s_whole) { pos = INT64_MAX; return; }                  // uniform
+    int64_t r = s_need;
+    int64_t cb, ce;
+    chunk_of(first, a.S, a.G, s_b, cb, ce);
+    for (int64_t g0 = cb; g0 < ce; g0 += ST) {
+        const int64_t g = g0 + threadIdx.x;
+        uint32_t d[16];
+        int m = 0;
+        if (g < ce) {
+            load_d2(a.d2cur, g, d);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t i = 16 * g + e;
+                m += (i >= first && i < a.S && d[e] == dlim) ? 1 : 0;
+            }
+        }
+        int ex;
+        const int total = block_scan<ST>(m, ex);
+        if (m > 0 && ex < r && r <= ex + m) {
+            int64_t left = r - ex;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t i = 16 * g + e;
+                if (i >= first && i < a.S && d[e] == dlim && --left == 0) s_pos = i;
+            }
+        }
+        __syncthreads();
+        if (r <= total) break;                                  // uniform
+        r -= total;
+    }
+    pos = s_pos;
+}
+
+// Assigns field k (entries under its threshold, or all that are left),
+// finds the anchor of field k + 1 (the first entry neither assigned before
+// nor taken by field k), writes field k + 1's d^2 and counts its top digit.
+// Field k's own d^2 tells both: SENT marks an entry assigned before, and
+// field k takes d^2 < dlim, or d^2 = dlim up to list position pos. Work goes
+// in units of 4 entries per thread (one 16-byte load of d^2, one of linear
+// indices), loaded in batches of four units so that their loads are in
+// flight together; the first batch of the main pass and of the anchor
+// search are issued before the threshold is settled.
+__global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
+    constexpr int PB = 4;                          // units per batch
     __shared__ __attribute__((aligned(16))) uint32_t h[NBIN];
     __shared__ int hit;
-    const int64_t first = a.field >= 0 ? a.cur->first : 0;
-    uint64_t th = 0;
-    if (a.field >= 0 && !a.take_all)
-        th = block_pick(a.cur->lv[a.kg.LV - 1], a.hcur + (size_t)(a.kg.LV - 1) * NBIN, lv_shift(a.kg, a.kg.LV - 1))
-                 .threshold;
-    auto key_of = [&](int l, int ax, int ay, int az) {
-        const int64_t dx = l % a.n0 - ax, dy = (l / a.n0) % a.n1 - ay, dz = l / (a.n0 * a.n1) - az;
-        return ((uint64_t)(dx * dx + dy * dy + dz * dz) << a.kg.LB) | (uint64_t)l;
+    const bool prev = a.field >= 0;
+    const int64_t first = prev ? a.cur->first : 0;
+    const int64_t ubeg = (first >> 4) << 2, uend = (a.S + 3) >> 2;
+    const int64_t um = ubeg + (int64_t)blockIdx.x * ST + threadIdx.x, ustride = (int64_t)gridDim.x * ST;
+    auto ld_d2 = [&](int64_t u) {
+        return prev ? *reinterpret_cast<const u32x4h*>(a.d2cur + 4 * u) : u32x4h{0u, 0u, 0u, 0u};
     };
-    // field k's own entry (its key was written by the step before this one;
-    // only this thread touches it here)
-    auto taken = [&](int64_t i) { return a.field >= 0 && (a.take_all || a.key[i] <= th); };
+    auto ld_lin = [&](int64_t u) { return *reinterpret_cast<const i32x4h*>(a.list + 4 * u); };
+    // loads in the order they are needed (the wait counter completes in
+    // issue order): the threshold's inputs, the first anchor round, the
+    // first batch of the main pass
+    const bool need_settle = prev && !a.take_all;
+    SettleIn sin;
+    if (need_settle) sin = settle_load(a);
+    u32x4h md[PB], ad[PB];
+    i32x4h ml[PB];
+    if (a.has_next) {
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int64_t u = ubeg + PB * threadIdx.x + p;
+            if (u < uend) ad[p] = ld_d2(u);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int64_t u = um + p * ustride;
+        if (u < uend) { md[p] = ld_d2(u); ml[p] = ld_lin(u); }
+    }
+    uint32_t dlim = 0;
+    int64_t pos = -1;
+    if (prev) {
+        if (a.take_all) { dlim = SENT; pos = INT64_MAX; }
+        else settle(a, sin, first, dlim, pos);
+    }
+    // an entry is a candidate of field k + 1 when it is one of field k's
+    // candidates (or any entry before the first field) that field k leaves
+    auto left_for_next = [&](uint32_t dk, int64_t i) {
+        if (i < first || i >= a.S) return false;
+        if (!prev) return true;
+        return dk != SENT && !(dk < dlim || (dk == dlim && i <= pos));
+    };
+    // The anchor search: rounds of 4 ST units (16 consecutive entries per
+    // thread); field k's d^2 is read-only here.
     int64_t nfirst = a.S;
     if (a.has_next) {
-        // The anchor search reads entries other blocks are assigning and
-        // re-keying meanwhile: it recomputes field k's keys from its anchor
-        // instead of reading them, and a done byte seen either before or
-        // after another block sets it gives the same answer.
-        int kx = 0, ky = 0, kz = 0;
-        if (a.field >= 0) {
-            const int ka = a.cur->anchor;
-            kx = ka % a.n0; ky = (ka / a.n0) % a.n1; kz = ka / (a.n0 * a.n1);
-        }
-        auto taken_k = [&](int64_t i) {
-            return a.field >= 0 && (a.take_all || key_of(a.list[i], kx, ky, kz) <= th);
-        };
-        for (int64_t i0 = first;; i0 += 256) {
-            if (threadIdx.x == 0) hit = 256;
+        for (int r = 0; ubeg + (int64_t)PB * ST * r < uend; ++r) {
+            const int64_t u0 = ubeg + (int64_t)PB * ST * r + PB * threadIdx.x;
+            if (r > 0) {
+#pragma unroll
+                for (int p = 0; p < PB; ++p)
+                    if (u0 + p < uend) ad[p] = ld_d2(u0 + p);
+            }
+            if (threadIdx.x == 0) hit = 0x7fffffff;
             __syncthreads();
-            const int64_t i = i0 + threadIdx.x;
-            if (i < a.S && !a.done[i] && !taken_k(i)) atomicMin(&hit, (int)threadIdx.x);
+            uint32_t live = 0;
+#pragma unroll
+            for (int p = 0; p < PB; ++p)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    live |= (uint32_t)(u0 + p < uend && left_for_next(ad[p][e], 4 * (u0 + p) + e)) << (4 * p + e);
+            // one atomic per wave: its first lane with a live entry holds the
+            // wave's smallest one
+            const uint64_t bm = __ballot(live != 0);
+            if (bm && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)bm) - 1)
+                atomicMin(&hit, 16 * (int)threadIdx.x + __builtin_ctz(live));
             __syncthreads();
             const int hh = hit;
             __syncthreads();
-            if (hh < 256) { nfirst = i0 + hh; break; }
-            if (i0 + 256 >= a.S) break;
+            if (hh != 0x7fffffff) { nfirst = 4 * (ubeg + (int64_t)PB * ST * r) + hh; break; }
         }
     }
     const bool next = a.has_next && nfirst < a.S;
-    int ax = 0, ay = 0, az = 0;
+    Vox na{0, 0, 0};
     if (next) {
-        const int an = a.list[nfirst];
-        ax = an % a.n0; ay = (an / a.n0) % a.n1; az = an / (a.n0 * a.n1);
+        const uint32_t an = (uint32_t)a.list[nfirst];
+        na = vox_of(an, a.n0, a.n1);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.nxt->first = (int32_t)nfirst;
-            a.nxt->anchor = an;
+            a.nxt->anchor = (int32_t)an;
             Pick p0;
-            p0.prefix = 0; p0.threshold = 0; p0.need = a.s_next; p0.found = 0; p0.pad = 0;
+            p0.prefix = 0; p0.dlim = 0; p0.need = a.s_next; p0.found = 0; p0.pad = 0;
             a.nxt->lv[0] = p0;
         }
     }
     clear_hist(h);
     __syncthreads();
-    const int sh0 = lv_shift(a.kg, 0);
-    for (int64_t i = first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.S;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (a.done[i]) continue;
-        if (taken(i)) {
-            a.done[i] = 1;
-            a.key[i] = NOKEY;
-            a.fmap[a.list[i]] = a.field;
-            continue;
+    const int sh0 = a.g.sh[0];
+    for (int64_t ub = um; ub < uend; ub += PB * ustride) {
+        if (ub != um) {
+#pragma unroll
+            for (int p = 0; p < PB; ++p) {
+                const int64_t u = ub + p * ustride;
+                if (u < uend) { md[p] = ld_d2(u); ml[p] = ld_lin(u); }
+            }
         }
-        if (!next) continue;
-        const uint64_t k = key_of(a.list[i], ax, ay, az);
-        a.key[i] = k;
-        atomicAdd(&h[k >> sh0], 1u);
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int64_t u = ub + p * ustride;
+            if (u >= uend) break;
+            // straight-line over the unit, then the stores and counts
+            uint32_t d[4];
+            uint32_t lv = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = 4 * u + e;
+                const uint32_t dk = md[p][e];
+                const bool in = i >= first && i < a.S && (!prev || dk != SENT);
+                const bool l = left_for_next(dk, i) && next;
+                lv |= (uint32_t)l << e;
+                d[e] = l ? dist2(vox_of((uint32_t)ml[p][e], a.n0, a.n1), na) : SENT;
+                if (in && prev && !left_for_next(dk, i)) a.fmap[ml[p][e]] = a.field;
+            }
+            // neighbouring entries often share a bin: one LDS add per run
+            uint32_t rb = 0, rn = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (!((lv >> e) & 1u)) continue;
+                const uint32_t bn = d[e] >> sh0;
+                if (rn && bn != rb) { atomicAdd(&h[rb], rn); rn = 0; }
+                rb = bn;
+                ++rn;
+            }
+            if (rn) atomicAdd(&h[rb], rn);
+            if (next) *reinterpret_cast<u32x4h*>(a.d2nxt + 4 * u) = u32x4h{d[0], d[1], d[2], d[3]};
+        }
     }
     __syncthreads();
-    if (next) flush_hist(h, a.hnxt);
+    if (next) flush_hist(h, a.hnxt + (size_t)(blockIdx.x % NCOPY) * NBIN, 1 << a.g.w[0]);
 }
 
-// Level l >= 1 of field k's select: picks level l - 1 (block 0 stores it),
-// then counts the digit of the keys inside the picked prefix. Level 1 also
-// clears the other histogram set for field k + 1.
-__global__ __launch_bounds__(256) void k_sel_level(FieldSel* sel, uint32_t* __restrict__ hset,
-                                                   uint32_t* __restrict__ hother, const uint64_t* __restrict__ key,
-                                                   int64_t S, KeyGeom kg, int level) {
+// Histogram level l >= 1 of field k's select: picks level l - 1 (block 0
+// stores it), then counts level l's digit of the entries inside the picked
+// prefix. The first digit kernel of a field also clears the other set for
+// field k + 1.
+__global__ __launch_bounds__(ST) void k_sel_level(FieldSel* sel, uint32_t* __restrict__ hset,
+                                                   uint32_t* __restrict__ hother, const uint32_t* __restrict__ d2,
+                                                   int64_t S, Geom g, int level) {
     __shared__ __attribute__((aligned(16))) uint32_t h[NBIN];
     if (level == 1)
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)LVMAX * NBIN;
-             i += (int64_t)gridDim.x * blockDim.x)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < HSET; i += (int64_t)gridDim.x * blockDim.x)
             hother[i] = 0;
-    const Pick s = block_pick(sel->lv[level - 1], hset + (size_t)(level - 1) * NBIN, lv_shift(kg, level - 1));
+    const Pick s = block_pick(sel->lv[level - 1], hset + lv_off(level - 1), lv_copies(level - 1), g.w[level - 1],
+                              g.sh[level - 1]);
     if (blockIdx.x == 0 && threadIdx.x == 0) sel->lv[level] = s;
     if (s.found) return;                                 // uniform
     clear_hist(h);
     __syncthreads();
-    const int sh = lv_shift(kg, level);
-    for (int64_t i = sel->first + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < S;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const uint64_t k = key[i];
-        if (k != NOKEY && (k >> (sh + DIG)) == s.prefix) atomicAdd(&h[(k >> sh) & (NBIN - 1)], 1u);
+    const int sh = g.sh[level], top = sh + g.w[level];
+    const uint32_t mask = (1u << g.w[level]) - 1u;
+    const int64_t first = sel->first;
+    for (int64_t q = (first >> 4) + (int64_t)blockIdx.x * ST + threadIdx.x; 16 * q < S; q += (int64_t)gridDim.x * ST) {
+        uint32_t d[16];
+        load_d2(d2, q, d);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t i = 16 * q + e;
+            if (i >= first && i < S && d[e] != SENT && (d[e] >> top) == s.prefix) atomicAdd(&h[(d[e] >> sh) & mask], 1u);
+        }
     }
     __syncthreads();
-    flush_hist(h, hset + (size_t)level * NBIN);
+    flush_hist(h, hset + lv_off(level), 1 << g.w[level]);
+}
+
+// The final digit of field k's select: picks the last histogram level
+// (block 0 stores it), then each block counts the final digit of the
+// entries inside the picked prefix over its own chunk of the list, storing
+// the counts per block and adding them into the totals. Clears the other
+// set when it is the field's first digit kernel.
+__global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __restrict__ hset,
+                                                   uint32_t* __restrict__ hother, const uint32_t* __restrict__ d2,
+                                                   uint32_t* __restrict__ cnt, int64_t S, Geom g) {
+    __shared__ uint32_t c[NFIN];
+    const int64_t first = sel->first;
+    int64_t cb, ce;
+    chunk_of(first, S, gridDim.x, blockIdx.x, cb, ce);
+    const int64_t ub = 4 * cb, ue = 4 * ce;              // units of 4 entries
+    u32x4h d = u32x4h{SENT, SENT, SENT, SENT};           // this thread's first unit, loaded before the pick
+    if (ub + threadIdx.x < ue) d = *reinterpret_cast<const u32x4h*>(d2 + 4 * (ub + threadIdx.x));
+    if (g.nh == 1)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < HSET; i += (int64_t)gridDim.x * blockDim.x)
+            hother[i] = 0;
+    const int L = g.nh - 1;
+    const Pick s = block_pick(sel->lv[L], hset + lv_off(L), lv_copies(L), g.w[L], g.sh[L]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sel->lv[g.nh] = s;
+    if (s.found) return;                                 // uniform
+    if (threadIdx.x < NFIN) c[threadIdx.x] = 0;
+    __syncthreads();
+    const int wf = g.wf;
+    const uint32_t mask = (1u << wf) - 1u;
+    for (int64_t u = ub + threadIdx.x; u < ue; u += ST) {
+        if (u != ub + threadIdx.x) d = *reinterpret_cast<const u32x4h*>(d2 + 4 * u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t i = 4 * u + e;
+            if (i >= first && i < S && d[e] != SENT && (d[e] >> wf) == s.prefix) atomicAdd(&c[d[e] & mask], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < (1 << wf)) {
+        const uint32_t v = c[threadIdx.x];
+        cnt[threadIdx.x * GMAX + blockIdx.x] = v;
+        if (v) atomicAdd(&hset[HTOT + threadIdx.x], v);
+    }
 }
 
 // ---- uniform blocks ----------------------------------------------------------
@@ -479,9 +771,8 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     hipLaunchKernelGGL(k_fill, dim3(grid_for(nvox)), dim3(256), 0, st, fmap, nvox, -1);
     hipLaunchKernelGGL(k_occ_count, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount);
     hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(256), 0, st, w.bcount, nb, w.total);
-    hipLaunchKernelGGL(k_occ_scatter, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount, w.list, w.done);
-    hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<int32_t*>(w.hist),
-                       (int64_t)2 * LVMAX * NBIN, 0);
+    hipLaunchKernelGGL(k_occ_scatter, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount, w.list);
+    hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<int32_t*>(w.hist), (int64_t)2 * HSET, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int32_t S32 = 0;
@@ -490,48 +781,57 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     const int64_t S = S32;
     if (S_out) *S_out = S;
     if (S == 0) return hipSuccess;
-    // key geometry: bit widths of the largest linear index and squared distance
+    // digits of d^2: bit width of the largest squared distance in the grid
     auto bits = [](uint64_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; };
     const uint64_t d2max = (uint64_t)(n[0] - 1) * (n[0] - 1) + (uint64_t)(n[1] - 1) * (n[1] - 1) +
                            (uint64_t)(n[2] - 1) * (n[2] - 1);
-    KeyGeom kg;
-    kg.LB = std::max(1, bits((uint64_t)(nvox - 1)));
-    kg.LV = std::max(2, (bits(d2max) + kg.LB + DIG - 1) / DIG);
-    if (kg.LV > LVMAX) return hipErrorInvalidValue;
+    const int dbits = std::max(1, bits(d2max));
+    Geom g{};
+    g.wf = std::min(FW, dbits - 1);
+    const int rest = dbits - g.wf;
+    g.nh = (rest + DIG - 1) / DIG;
+    if (g.nh > HLMAX || dbits > 31) return hipErrorInvalidValue;
+    for (int l = 0; l < g.nh; ++l) g.w[l] = l == 0 ? rest - DIG * (g.nh - 1) : DIG;
+    for (int l = 0, top = dbits; l < g.nh; ++l) { top -= g.w[l]; g.sh[l] = top; }
+    const int G = (int)sel_grid(S);
     const int64_t base = S / n_fields, rem = S % n_fields;
     auto size_of = [&](int32_t k) { return base + (k < rem ? 1 : 0); };
     StepArgs sa{};
-    sa.list = w.list; sa.done = w.done; sa.key = w.key; sa.S = S; sa.n0 = n[0]; sa.n1 = n[1]; sa.kg = kg;
-    sa.fmap = fmap;
-    // the step before field 0 only finds its anchor and keys
+    sa.list = w.list; sa.S = S; sa.g = g;
+    sa.n0 = make_divisor((uint32_t)n[0]); sa.n1 = make_divisor((uint32_t)n[1]);
+    sa.cnt = w.cnt; sa.G = G; sa.fmap = fmap;
+    // the step before field 0 only finds its anchor and d^2 (set 0)
     int32_t k = 0;
     while (k < n_fields && size_of(k) == 0) ++k;
     sa.field = -1; sa.take_all = 0; sa.has_next = 1; sa.s_next = size_of(k);
-    sa.cur = w.sel + 1; sa.hcur = w.hist + (size_t)LVMAX * NBIN;
-    sa.nxt = w.sel; sa.hnxt = w.hist;
-    hipLaunchKernelGGL(k_sel_step, dim3(sel_grid(S)), dim3(256), 0, st, sa);
+    sa.cur = w.sel + 1; sa.hcur = w.hist + HSET; sa.d2cur = w.d2[1];
+    sa.nxt = w.sel; sa.hnxt = w.hist; sa.d2nxt = w.d2[0];
+    hipLaunchKernelGGL(k_sel_step, dim3(G), dim3(ST), 0, st, sa);
     int64_t left = S;
+    int set = 0;
     while (k < n_fields && left > 0) {
-        const int set = k & 1;
         FieldSel* sel = w.sel + set;
-        uint32_t* hset = w.hist + (size_t)set * LVMAX * NBIN;
-        uint32_t* hother = w.hist + (size_t)(set ^ 1) * LVMAX * NBIN;
+        uint32_t* hset = w.hist + (size_t)set * HSET;
+        uint32_t* hother = w.hist + (size_t)(set ^ 1) * HSET;
         const int64_t sk = size_of(k);
         const int take_all = sk >= left ? 1 : 0;
-        if (!take_all)
-            for (int lv = 1; lv < kg.LV; ++lv)
-                hipLaunchKernelGGL(k_sel_level, dim3(sel_grid(S)), dim3(256), 0, st, sel, hset, hother, w.key, S, kg, lv);
+        if (!take_all) {
+            for (int lv = 1; lv < g.nh; ++lv)
+                hipLaunchKernelGGL(k_sel_level, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], S, g, lv);
+            hipLaunchKernelGGL(k_sel_final, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], w.cnt, S, g);
+        }
         left -= sk;
         int32_t k2 = k + 1;
         while (k2 < n_fields && size_of(k2) == 0) ++k2;
         sa.field = k; sa.take_all = take_all;
         sa.has_next = (left > 0 && k2 < n_fields) ? 1 : 0;
         sa.s_next = sa.has_next ? size_of(k2) : 0;
-        sa.cur = sel; sa.hcur = hset;
-        sa.nxt = w.sel + (set ^ 1); sa.hnxt = hother;
-        hipLaunchKernelGGL(k_sel_step, dim3(sel_grid(S)), dim3(256), 0, st, sa);
+        sa.cur = sel; sa.hcur = hset; sa.d2cur = w.d2[set];
+        sa.nxt = w.sel + (set ^ 1); sa.hnxt = hother; sa.d2nxt = w.d2[set ^ 1];
+        hipLaunchKernelGGL(k_sel_step, dim3(G), dim3(ST), 0, st, sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k = k2;
+        set ^= 1;
     }
     return hipSuccess;
 }
