@@ -96,7 +96,7 @@ struct FieldSel {
 };
 
 struct AssignWs {
-    int32_t* list;        // [nvox16] occupied voxels, increasing linear index
+    int32_t* list;        // [nvox16] occupied voxels, increasing linear index (packed coordinates where they fit)
     uint32_t* d2[2];      // [nvox16] d^2 to the anchor of the fields using each set, SENT for entries assigned before
     int32_t* bcount;      // [blocks] occupied voxels per compaction block, then their offsets
     uint32_t* hist;       // [2][HSET] two histogram sets
@@ -188,8 +188,14 @@ __global__ __launch_bounds__(256) void k_block_offsets(int32_t* __restrict__ bco
     if (threadIdx.x == 0) *total = carry;
 }
 
+// List entries: the voxel's coordinates packed as x | y << 11 | z << 22
+// when the grid is at most 2048 x 2048 x 1024 (the same order as the
+// linear index, and unpacked with three bit-field extracts), else its
+// linear index.
+template <bool PACKED>
 __global__ __launch_bounds__(256) void k_occ_scatter(const float* __restrict__ occ, float thr, int64_t nvox,
-                                                     const int32_t* __restrict__ boff, int32_t* __restrict__ list) {
+                                                     int n0, int n1, const int32_t* __restrict__ boff,
+                                                     int32_t* __restrict__ list) {
     const int64_t v0 = (int64_t)blockIdx.x * CB + threadIdx.x * 16;
     uint32_t bits = 0;
 #pragma unroll
@@ -199,7 +205,15 @@ __global__ __launch_bounds__(256) void k_occ_scatter(const float* __restrict__ o
     int pos = boff[blockIdx.x] + excl;
 #pragma unroll
     for (int j = 0; j < 16; ++j)
-        if (bits & (1u << j)) list[pos++] = (int32_t)(v0 + j);
+        if (bits & (1u << j)) {
+            const int64_t v = v0 + j;
+            if constexpr (PACKED) {
+                const int64_t q = v / n0;
+                list[pos++] = (int32_t)((uint32_t)(v - q * n0) | (uint32_t)(q % n1) << 11 | (uint32_t)(q / n1) << 22);
+            } else {
+                list[pos++] = (int32_t)v;
+            }
+        }
 }
 
 typedef __attribute__((ext_vector_type(4))) unsigned u32x4h;
@@ -243,6 +257,17 @@ struct Vox {
 __device__ __forceinline__ Vox vox_of(uint32_t lin, const Divisor& n0, const Divisor& n1) {
     const uint32_t q = div_by(lin, n0), z = div_by(q, n1);
     return Vox{(int)(lin - q * n0.d), (int)(q - z * n1.d), (int)z};
+}
+// A list entry's coordinates and linear index.
+template <bool PACKED>
+__device__ __forceinline__ Vox entry_vox(uint32_t w, const Divisor& n0, const Divisor& n1) {
+    if constexpr (PACKED) return Vox{(int)(w & 2047u), (int)((w >> 11) & 2047u), (int)(w >> 22)};
+    else return vox_of(w, n0, n1);
+}
+template <bool PACKED>
+__device__ __forceinline__ uint32_t entry_lin(uint32_t w, const Divisor& n0, const Divisor& n1) {
+    if constexpr (PACKED) return (w & 2047u) + n0.d * (((w >> 11) & 2047u) + n1.d * (w >> 22));
+    else return w;
 }
 __device__ __forceinline__ uint32_t dist2(const Vox& a, const Vox& b) {
     const int dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;    // |d| < 2^12: 24-bit products are exact
@@ -447,6 +472,7 @@ __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uin
 // indices), loaded in batches of four units so that their loads are in
 // flight together; the first batch of the main pass and of the anchor
 // search are issued before the threshold is settled.
+template <bool PACKED>
 __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
     constexpr int PB = 4;                          // units per batch
     __shared__ __attribute__((aligned(16))) uint32_t h[NBIN];
@@ -526,10 +552,10 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
     Vox na{0, 0, 0};
     if (next) {
         const uint32_t an = (uint32_t)a.list[nfirst];
-        na = vox_of(an, a.n0, a.n1);
+        na = entry_vox<PACKED>(an, a.n0, a.n1);
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             a.nxt->first = (int32_t)nfirst;
-            a.nxt->anchor = (int32_t)an;
+            a.nxt->anchor = (int32_t)entry_lin<PACKED>(an, a.n0, a.n1);
             Pick p0;
             p0.prefix = 0; p0.dlim = 0; p0.need = a.s_next; p0.found = 0; p0.pad = 0;
             a.nxt->lv[0] = p0;
@@ -560,8 +586,8 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
                 const bool in = i >= first && i < a.S && (!prev || dk != SENT);
                 const bool l = left_for_next(dk, i) && next;
                 lv |= (uint32_t)l << e;
-                d[e] = l ? dist2(vox_of((uint32_t)ml[p][e], a.n0, a.n1), na) : SENT;
-                if (in && prev && !left_for_next(dk, i)) a.fmap[ml[p][e]] = a.field;
+                d[e] = l ? dist2(entry_vox<PACKED>((uint32_t)ml[p][e], a.n0, a.n1), na) : SENT;
+                if (in && prev && !left_for_next(dk, i)) a.fmap[entry_lin<PACKED>((uint32_t)ml[p][e], a.n0, a.n1)] = a.field;
             }
             // neighbouring entries often share a bin: one LDS add per run
             uint32_t rb = 0, rn = 0;
@@ -771,7 +797,11 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     hipLaunchKernelGGL(k_fill, dim3(grid_for(nvox)), dim3(256), 0, st, fmap, nvox, -1);
     hipLaunchKernelGGL(k_occ_count, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount);
     hipLaunchKernelGGL(k_block_offsets, dim3(1), dim3(256), 0, st, w.bcount, nb, w.total);
-    hipLaunchKernelGGL(k_occ_scatter, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, w.bcount, w.list);
+    const bool packed = n[0] <= 2048 && n[1] <= 2048 && n[2] <= 1024;
+    if (packed)
+        hipLaunchKernelGGL(k_occ_scatter<true>, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, n[0], n[1], w.bcount, w.list);
+    else
+        hipLaunchKernelGGL(k_occ_scatter<false>, dim3((unsigned)nb), dim3(256), 0, st, occ, thr, nvox, n[0], n[1], w.bcount, w.list);
     hipLaunchKernelGGL(k_fill, dim3(64), dim3(256), 0, st, reinterpret_cast<int32_t*>(w.hist), (int64_t)2 * HSET, 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -794,6 +824,10 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     for (int l = 0; l < g.nh; ++l) g.w[l] = l == 0 ? rest - DIG * (g.nh - 1) : DIG;
     for (int l = 0, top = dbits; l < g.nh; ++l) { top -= g.w[l]; g.sh[l] = top; }
     const int G = (int)sel_grid(S);
+    auto launch_step = [&](const StepArgs& sa) {
+        if (packed) hipLaunchKernelGGL(k_sel_step<true>, dim3(G), dim3(ST), 0, st, sa);
+        else hipLaunchKernelGGL(k_sel_step<false>, dim3(G), dim3(ST), 0, st, sa);
+    };
     const int64_t base = S / n_fields, rem = S % n_fields;
     auto size_of = [&](int32_t k) { return base + (k < rem ? 1 : 0); };
     StepArgs sa{};
@@ -806,7 +840,7 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     sa.field = -1; sa.take_all = 0; sa.has_next = 1; sa.s_next = size_of(k);
     sa.cur = w.sel + 1; sa.hcur = w.hist + HSET; sa.d2cur = w.d2[1];
     sa.nxt = w.sel; sa.hnxt = w.hist; sa.d2nxt = w.d2[0];
-    hipLaunchKernelGGL(k_sel_step, dim3(G), dim3(ST), 0, st, sa);
+    launch_step(sa);
     int64_t left = S;
     int set = 0;
     while (k < n_fields && left > 0) {
@@ -828,7 +862,7 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
         sa.s_next = sa.has_next ? size_of(k2) : 0;
         sa.cur = sel; sa.hcur = hset; sa.d2cur = w.d2[set];
         sa.nxt = w.sel + (set ^ 1); sa.hnxt = hother; sa.d2nxt = w.d2[set ^ 1];
-        hipLaunchKernelGGL(k_sel_step, dim3(G), dim3(ST), 0, st, sa);
+        launch_step(sa);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k = k2;
         set ^= 1;

@@ -31,7 +31,8 @@ def _np(t):
 @pytest.mark.parametrize("shape,p,n", [((1, 1, 10), 1.0, 3), ((3, 4, 5), 0.5, 4), ((6, 6, 6), 0.3, 7),
                                        ((5, 2, 7), 0.8, 30), ((7, 9, 11), 0.4, 1), ((4, 4, 4), 0.05, 9),
                                        ((8, 8, 8), 0.0, 5), ((33, 17, 29), 0.35, 57), ((1, 1, 1), 1.0, 1),
-                                       ((1, 1, 2), 1.0, 2), ((1, 1, 600), 0.6, 7), ((2, 3, 520), 0.5, 13)])
+                                       ((1, 1, 2), 1.0, 2), ((1, 1, 600), 0.6, 7), ((2, 3, 520), 0.5, 13),
+                                       ((1, 1, 2100), 0.5, 9), ((1100, 2, 1), 0.7, 6)])
 def test_assign_small_grids_match_oracle(A, orc, shape, p, n):
     u = synth.uniform(len(shape) + n, synth.STREAM_SCENE, np.arange(int(np.prod(shape)), dtype=np.uint64))
     occ = u.astype(np.float32).reshape(shape)
