@@ -486,6 +486,17 @@ hipError_t launch_labels(const float* occ, const int32_t* fmap, float thr, int64
 // Routing counts per routing wave (route_waves(F) of them) in w.hist:
 // computed here unless `counted` (gathered by launch_trace).
 int route_waves(int F);
+// The routing walk's units, one per routing wave. With at least as many
+// 64-ray blocks as waves, unit w is the run of blocks [w per, (w + 1) per)
+// over all their sample levels (lr = 1). With fewer blocks, every block's
+// sample levels are cut into lr ranges of ls levels and unit w is range
+// w % lr of block w / lr, so that small batches still spread over many
+// waves. Either way the units in order visit (block, level, lane) in the
+// same order, so the routing result does not depend on the cut.
+struct RouteMap {
+    int per, lr, ls;
+};
+RouteMap route_map(int64_t N, int smax, int F);
 hipError_t launch_route(const Workspace& w, int F, bool counted, hipStream_t st);
 hipError_t launch_repack(r360_scene* s, const float* weights, hipStream_t st);
 hipError_t launch_repack_bwd(r360_scene* s, const float* weights, hipStream_t st);

@@ -20,12 +20,21 @@ namespace r360 {
 
 namespace {
 
-// The 64-ray blocks [beg, end) of route wave w.
-__device__ __forceinline__ void blocks_of(int64_t N, int rw, int w, int& beg, int& end) {
+// The 64-ray blocks [beg, end) and sample levels [klo, khi) of route wave
+// w (RouteMap).
+__device__ __forceinline__ void unit_of(int64_t N, RouteMap m, int w, int& beg, int& end, int& klo, int& khi) {
     const int nblk = (int)((N + 63) / 64);
-    const int per = (nblk + rw - 1) / rw;
-    beg = min(nblk, w * per);
-    end = min(nblk, beg + per);
+    if (m.lr == 1) {
+        beg = min(nblk, w * m.per);
+        end = min(nblk, beg + m.per);
+        klo = 0;
+        khi = m.ls;
+    } else {
+        beg = min(nblk, w / m.lr);
+        end = min(nblk, beg + 1);
+        klo = (w % m.lr) * m.ls;
+        khi = klo + m.ls;
+    }
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -48,24 +57,26 @@ __device__ __forceinline__ void load_levels(const int32_t* __restrict__ field, i
 
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_hist(const int32_t* __restrict__ field, const int32_t* __restrict__ cnt,
-                                                   int64_t N, int smax, int F, int rw, int32_t* __restrict__ hist) {
+                                                   int64_t N, int smax, int F, int rw, RouteMap m,
+                                                   int32_t* __restrict__ hist) {
     extern __shared__ int32_t lds[];
     const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t* h = lds + wl * F;
     for (int f = lane; f < F; f += 64) h[f] = 0;
     const int w = blockIdx.x * WPB + wl;
-    int beg, end;
-    blocks_of(N, rw, w, beg, end);
+    int beg, end, klo, khi;
+    unit_of(N, m, w, beg, end, klo, khi);
     int c_next = 0;
     if (beg < end) { const int64_t r = (int64_t)beg * 64 + lane; c_next = r < N ? cnt[r] : 0; }
     for (int blk = beg; blk < end; ++blk) {
         const int c = c_next;
         if (blk + 1 < end) { const int64_t r = (int64_t)(blk + 1) * 64 + lane; c_next = r < N ? cnt[r] : 0; }
-        const int kmax = wave_max(c);
+        const int kmax = min(wave_max(c), khi);
+        const int cu = min(c, khi);
         const int slot0 = blk * 64 * smax + lane;
-        for (int k0 = 0; k0 < kmax; k0 += RB) {
+        for (int k0 = klo; k0 < kmax; k0 += RB) {
             int fv[RB];
-            load_levels(field, slot0, k0, c, fv);
+            load_levels(field, slot0, k0, cu, fv);
 #pragma unroll
             for (int u = 0; u < RB; ++u)
                 if (fv[u] >= 0) atomicAdd(&h[fv[u]], 1);
@@ -146,15 +157,15 @@ __global__ __launch_bounds__(1024) void k_fields(int32_t* __restrict__ start, in
 
 template <int WPB>
 __global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict__ field, const int32_t* __restrict__ cnt,
-                                                      int64_t N, int smax, int F, int rw,
+                                                      int64_t N, int smax, int F, int rw, RouteMap m,
                                                       const int32_t* __restrict__ hist, const int32_t* __restrict__ start,
                                                       int32_t* __restrict__ perm) {
     extern __shared__ int32_t lds[];
     const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int32_t* run = lds + wl * F;
     const int w = blockIdx.x * WPB + wl;
-    int beg, end;
-    blocks_of(N, rw, w, beg, end);
+    int beg, end, klo, khi;
+    unit_of(N, m, w, beg, end, klo, khi);
     if (beg < end)
         for (int f = lane; f < F; f += 64) run[f] = start[f] + hist[(int64_t)f * rw + w];
     __syncthreads();
@@ -164,11 +175,12 @@ __global__ __launch_bounds__(WPB * 64) void k_scatter(const int32_t* __restrict_
     for (int blk = beg; blk < end; ++blk) {
         const int c = c_next;
         if (blk + 1 < end) { const int64_t r = (int64_t)(blk + 1) * 64 + lane; c_next = r < N ? cnt[r] : 0; }
-        const int kmax = wave_max(c);
+        const int kmax = min(wave_max(c), khi);
+        const int cu = min(c, khi);
         const int slot0 = blk * 64 * smax + lane;
-        for (int k0 = 0; k0 < kmax; k0 += RB) {
+        for (int k0 = klo; k0 < kmax; k0 += RB) {
             int fv[RB];
-            load_levels(field, slot0, k0, c, fv);
+            load_levels(field, slot0, k0, cu, fv);
 #pragma unroll
             for (int u = 0; u < RB; ++u) {
                 if (k0 + u >= kmax) break;                  // wave-uniform
@@ -207,28 +219,44 @@ int route_waves(int F) {
     return rw;
 }
 
+// Level ranges only when blocks are fewer than waves, at most eight per
+// block, each of at least RB levels, and at most 1024 counters per wave for
+// the walk-time counting (4 lr F ints of LDS per traversal block).
+RouteMap route_map(int64_t N, int smax, int F) {
+    const int rw = route_waves(F);
+    const int64_t nblk = (N + 63) / 64;
+    if (nblk >= rw || smax <= RB) return RouteMap{(int)std::max<int64_t>(1, (nblk + rw - 1) / rw), 1, smax};
+    int64_t lr = std::min<int64_t>(rw / std::max<int64_t>(nblk, 1), (smax + RB - 1) / RB);
+    lr = std::min<int64_t>(lr, 8);
+    lr = std::min<int64_t>(lr, std::max(1, 1024 / std::max(F, 1)));
+    if (lr <= 1) return RouteMap{1, 1, smax};
+    const int ls = (int)((smax + lr - 1) / lr);
+    return RouteMap{1, (int)((smax + ls - 1) / ls), ls};
+}
+
 hipError_t launch_route(const Workspace& w, int F, bool counted, hipStream_t st) {
     const int rw = route_waves(F);
     const int64_t N = w.N;
     const int smax = w.slots.smax;
+    const RouteMap m = route_map(N, smax, F);
     if (counted) {
         // step 1 was done during the traversal
     } else if (F <= 4096) {
         const size_t lds = 4 * F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_hist<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw, w.hist);
+        hipLaunchKernelGGL(k_hist<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw, m, w.hist);
     } else {
         const size_t lds = F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_hist<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, rw, w.hist);
+        hipLaunchKernelGGL(k_hist<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, rw, m, w.hist);
     }
     hipLaunchKernelGGL(k_rows, dim3(F), dim3(1024), 0, st, w.hist, rw, w.field_start);
     hipLaunchKernelGGL(k_fields, dim3(1), dim3(1024), 0, st, w.field_start, F);
     if (F <= 4096) {
         const size_t lds = 4 * F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw,
+        hipLaunchKernelGGL(k_scatter<4>, dim3(rw / 4), dim3(256), lds, st, w.field, w.ray_off, N, smax, F, rw, m,
                            w.hist, w.field_start, w.perm);
     } else {
         const size_t lds = F * sizeof(int32_t);
-        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, rw,
+        hipLaunchKernelGGL(k_scatter<1>, dim3(rw), dim3(64), lds, st, w.field, w.ray_off, N, smax, F, rw, m,
                            w.hist, w.field_start, w.perm);
     }
     return hipGetLastError();

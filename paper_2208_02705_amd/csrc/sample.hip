@@ -84,17 +84,23 @@ __device__ __forceinline__ void make_ray(const RaySource& s, int64_t N, int64_t 
 //
 // With `count` set, every emitted sample also adds one to its field's entry
 // of the wave's LDS histogram h.
+// With the routing's level ranges (RouteMap lr > 1) the counts go to the
+// histogram of the range holding k: h advances by F at every ls-th sample.
 struct SlotSink {
     int base;
     float *t, *dl;
     int32_t *fld, *vox;
     int32_t* h;
     bool count;
+    int F, ls, bound;
     __device__ void emit(int k, float tm, float d, int lab, int lin) {
         const unsigned j = (unsigned)(base + 64 * k);
         st32(t, j, tm); st32(dl, j, d); st32(fld, j, (int32_t)lab);
         if (vox) st32(vox, j, (int32_t)lin);
-        if (count) atomicAdd(h + lab, 1);
+        if (count) {
+            if (k == bound) { h += F; bound += ls; }
+            atomicAdd(h + lab, 1);
+        }
     }
 };
 
@@ -250,25 +256,26 @@ struct Staging {
 };
 
 // Routing counts gathered during the walk: the number of samples of each
-// field in the 64-ray blocks of every routing wave (route.hip), added into
-// hist[f][w] (zeroed beforehand). Routing wave w owns the blocks
-// [w per, (w + 1) per). hist == nullptr: not gathered here.
+// field in every routing wave's unit (RouteMap in r360_internal.h), added
+// into hist[f][w] (zeroed beforehand). hist == nullptr: not gathered here.
 struct RouteCounts {
     int32_t* hist;
-    int F, rw, per;
+    int F, rw;
+    RouteMap m;
 };
 
 template <int MODE, bool MULTI>
 __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64_t N, int32_t* __restrict__ cnt,
                                                float* __restrict__ o_ws, float* __restrict__ d_ws, Staging sg,
                                                RouteCounts rc) {
-    extern __shared__ int32_t l_hist[];   // [4][F] while counting
+    extern __shared__ int32_t l_hist[];   // [4][lr][F] while counting
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool counting = rc.hist != nullptr;
-    int32_t* h = l_hist + (threadIdx.x >> 6) * rc.F;
+    const int nh = rc.m.lr * rc.F;
+    int32_t* h = l_hist + (threadIdx.x >> 6) * nh;
     if (counting) {
-        for (int f = lane; f < rc.F; f += 64) h[f] = 0;
+        for (int f = lane; f < nh; f += 64) h[f] = 0;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -281,7 +288,7 @@ __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64
             for (int a = 0; a < 3; ++a) { o_ws[a * N + r] = o[a]; d_ws[a * N + r] = d[a]; }
         }
         SlotSink sink{(int)(r & ~int64_t(63)) * (P.max_samples - P.skip) + (int)(r & 63), sg.t, sg.dl, sg.fld, sg.vox,
-                      h, counting};
+                      h, counting, rc.F, rc.m.ls, rc.m.ls};
         cnt[r] = traverse<SlotSink, MULTI>(P, o, d, sink);
     }
     if (counting) {
@@ -290,10 +297,13 @@ __global__ __launch_bounds__(256) void k_trace(RaySource src, DdaParams P, int64
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int64_t r0 = r - lane;             // the wave's first ray
         if (r0 < N) {
-            const int w = (int)((r0 >> 6) / rc.per);
-            for (int f = lane; f < rc.F; f += 64) {
-                const int v = h[f];
-                if (v) atomicAdd(rc.hist + (int64_t)f * rc.rw + w, v);
+            const int64_t blk = r0 >> 6;
+            for (int q = 0; q < rc.m.lr; ++q) {
+                const int w = rc.m.lr == 1 ? (int)(blk / rc.m.per) : (int)(blk * rc.m.lr + q);
+                for (int f = lane; f < rc.F; f += 64) {
+                    const int v = h[q * rc.F + f];
+                    if (v) atomicAdd(rc.hist + (int64_t)f * rc.rw + w, v);
+                }
             }
         }
     }
@@ -480,8 +490,8 @@ __global__ __launch_bounds__(256) void k_fill_zero(int32_t* __restrict__ p, int6
 }
 
 static hipError_t trace_any(const RaySource& src, const DdaParams& p, int64_t N, const Workspace& w, const Staging& sg,
-                     unsigned nb, hipStream_t st, const RouteCounts& rc = RouteCounts{nullptr, 0, 1, 1}) {
-    const size_t lds = rc.hist ? (size_t)4 * rc.F * sizeof(int32_t) : 0;
+                     unsigned nb, hipStream_t st, const RouteCounts& rc = RouteCounts{nullptr, 0, 1, RouteMap{1, 1, 1}}) {
+    const size_t lds = rc.hist ? (size_t)4 * rc.m.lr * rc.F * sizeof(int32_t) : 0;
     if (p.spv > 1) {
         if (src.mode == RAYS_EQUIRECT)
             hipLaunchKernelGGL((k_trace<RAYS_EQUIRECT, true>), dim3(nb), dim3(256), lds, st, src, p, N, w.ray_off, w.o, w.d, sg, rc);
@@ -526,8 +536,7 @@ hipError_t launch_trace(const RaySource& src, const DdaParams& p, int64_t N, con
     *counted = false;
     if (F < 1 || F > TRACE_COUNT_MAX_FIELDS) return trace_any(src, p, N, w, sg, nb, st);
     const int rw = route_waves(F);
-    const int64_t nblk = (N + 63) / 64;
-    const RouteCounts rc{w.hist, F, rw, (int)((nblk + rw - 1) / rw)};
+    const RouteCounts rc{w.hist, F, rw, route_map(N, w.slots.smax, F)};
     const int64_t n = (int64_t)F * rw;
     hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, w.hist, n);
     hipError_t e = hipGetLastError();
