@@ -177,28 +177,53 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
     const uint16_t* labels = reinterpret_cast<const uint16_t*>(P.labels);
     int count = 0;
     float t_in = t0;
-    // One traversal step (R360_DDA_STEP): handles the current voxel (label
-    // `cur`) and requests the label of the next one into `nxt`; leaves the
-    // loop when the walk ends or the cap is reached (one exit test per step,
-    // outside the emitting branch). The loop alternates the two label registers,
-    // so the value just requested is not copied (which would wait for the
-    // load) within the step. (A macro, not a lambda: captured references
-    // would turn the per-axis selects into loads through selected pointers.)
-#define R360_DDA_STEP(cur, nxt)                                                      \
+    // The walk in two halves per step. The crossing out of a voxel (nearest
+    // plane, ties to the lowest axis; its distance, the next voxel, whether
+    // the walk goes on) depends only on the ray, so it is computed one voxel
+    // ahead of the voxel being handled, and each label is requested two
+    // voxels ahead: a load has two steps of arithmetic to arrive in. The
+    // voxel being handled uses exactly the values the one-voxel-at-a-time
+    // walk computes, in the same order.
+    // R360_DDA_CROSS(S): the crossing out of the walk-ahead voxel `lin` into
+    // set S (tna, tout, next, more), then the walk-ahead state moves on (the
+    // crossed axis's next plane; unused once the walk has ended).
+#define R360_DDA_CROSS(S)                                                            \
     {                                                                                \
-        const bool c1 = tn1 < tn0; /* nearest plane, ties to the lowest axis */      \
+        const bool c1 = tn1 < tn0;                                                   \
         const float m01 = c1 ? tn1 : tn0;                                            \
         const bool c2 = tn2 < m01;                                                   \
-        const float tna = c2 ? tn2 : m01;                                            \
-        const float t_out = mn(tna, t1);                                             \
-        const int lin_next = lin + (c2 ? ds2 : (c1 ? ds1 : ds0));                    \
-        const bool more = tna < t1 && (unsigned)lin_next < nvox;                     \
-        nxt = ld32(labels, (unsigned)(more ? lin_next : lin));                       \
+        S##tna = c2 ? tn2 : m01;                                                     \
+        S##tout = mn(S##tna, t1);                                                    \
+        S##next = lin + (c2 ? ds2 : (c1 ? ds1 : ds0));                               \
+        S##more = S##tna < t1 && (unsigned)S##next < nvox;                           \
+        const float pn0 = pk0 + sf0, pn1 = pk1 + sf1, pn2 = pk2 + sf2;               \
+        const float tm0 = (__builtin_fmaf(pn0, P.voxel, lo0) - o0) * iv0;            \
+        const float tm1 = (__builtin_fmaf(pn1, P.voxel, lo1) - o1) * iv1;            \
+        const float tm2 = (__builtin_fmaf(pn2, P.voxel, lo2) - o2) * iv2;            \
+        const bool x0 = !c1 && !c2, x1 = c1 && !c2;                                  \
+        pk0 = x0 ? pn0 : pk0; tn0 = x0 ? tm0 : tn0;                                  \
+        pk1 = x1 ? pn1 : pk1; tn1 = x1 ? tm1 : tn1;                                  \
+        pk2 = c2 ? pn2 : pk2; tn2 = c2 ? tm2 : tn2;                                  \
+        lin = S##next;                                                               \
+    }
+    // One step: voxel `cl` (label `cur`, crossing set C) is handled while the
+    // crossing of the next voxel goes into set N and the label of the voxel
+    // after it is requested into `nx2` (that voxel exists when both
+    // crossings go on; otherwise a voxel known to exist is read instead).
+    // Leaves the loop when the walk ends or the cap is reached. Unrolled six
+    // times so that three label registers and two crossing sets rotate
+    // without copies. (A macro, not a lambda: captured references would turn
+    // the per-axis selects into loads through selected pointers.)
+#define R360_DDA_STEP(cur, nx2, C, N)                                                \
+    {                                                                                \
+        R360_DDA_CROSS(N)                                                            \
+        nx2 = ld32(labels, (unsigned)(C##more && N##more ? N##next : cl));           \
         __builtin_amdgcn_sched_barrier(0);                                           \
+        const float t_out = C##tout;                                                 \
         const bool hit = t_out > t_in && cur < 0x8000;                               \
         if constexpr (!MULTI) {                                                      \
             if (hit && count >= P.skip)                                              \
-                sink.emit(count - P.skip, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, lin); \
+                sink.emit(count - P.skip, (t_in + t_out) * 0.5f, t_out - t_in, (int)cur, cl); \
             count += hit ? 1 : 0;                                                    \
         } else if (hit) {                                                            \
             /* P.spv pieces cut at fma(j, length / k, t_in) */                       \
@@ -208,34 +233,36 @@ __device__ int traverse(const DdaParams& P, const float o[3], const float d[3], 
                 const float b1 = q + 1 == P.spv ? t_out                              \
                                                 : __builtin_fmaf((float)(q + 1), piece, t_in); \
                 if (count >= P.skip)                                                 \
-                    sink.emit(count - P.skip, (b0 + b1) * 0.5f, b1 - b0, (int)cur, lin); \
+                    sink.emit(count - P.skip, (b0 + b1) * 0.5f, b1 - b0, (int)cur, cl); \
                 b0 = b1;                                                             \
                 if (++count == P.max_samples) break;                                 \
             }                                                                        \
         }                                                                            \
-        if (!more || count == P.max_samples) break;                                  \
-        t_in = mx(t_in, tna);                                                        \
-        /* every axis's next plane, kept only for the crossed axis */                \
-        const float pn0 = pk0 + sf0, pn1 = pk1 + sf1, pn2 = pk2 + sf2;               \
-        const float tm0 = (__builtin_fmaf(pn0, P.voxel, lo0) - o0) * iv0;            \
-        const float tm1 = (__builtin_fmaf(pn1, P.voxel, lo1) - o1) * iv1;            \
-        const float tm2 = (__builtin_fmaf(pn2, P.voxel, lo2) - o2) * iv2;            \
-        const bool x0 = !c1 && !c2, x1 = c1 && !c2;                                  \
-        pk0 = x0 ? pn0 : pk0; tn0 = x0 ? tm0 : tn0;                                  \
-        pk1 = x1 ? pn1 : pk1; tn1 = x1 ? tm1 : tn1;                                  \
-        pk2 = c2 ? pn2 : pk2; tn2 = c2 ? tm2 : tn2;                                  \
-        lin = lin_next;                                                              \
+        if (!C##more || count == P.max_samples) break;                               \
+        t_in = mx(t_in, C##tna);                                                     \
+        cl = C##next;                                                                \
     }
     // Leaving the grid means crossing one of its boundary planes, whose
     // distance is that axis's box exit (the plane position is computed with
     // one rounding either way), which is >= t1: the walk ends on tna >= t1
-    // first. The index test in `more` only guards the load.
-    uint16_t la = ld32(labels, (unsigned)lin), lb = 0;
+    // first. The index test in `more` only guards the loads.
+    int cl = lin;                                        // the voxel being handled
+    float Atna, Atout, Btna, Btout;
+    int Anext, Bnext;
+    bool Amore, Bmore;
+    uint16_t la = ld32(labels, (unsigned)lin), lb, lc = 0;
+    R360_DDA_CROSS(A)                                    // the first voxel's crossing
+    lb = ld32(labels, (unsigned)(Amore ? Anext : cl));
     for (;;) {
-        R360_DDA_STEP(la, lb)
-        R360_DDA_STEP(lb, la)
+        R360_DDA_STEP(la, lc, A, B)
+        R360_DDA_STEP(lb, la, B, A)
+        R360_DDA_STEP(lc, lb, A, B)
+        R360_DDA_STEP(la, lc, B, A)
+        R360_DDA_STEP(lb, la, A, B)
+        R360_DDA_STEP(lc, lb, B, A)
     }
 #undef R360_DDA_STEP
+#undef R360_DDA_CROSS
     return count > P.skip ? count - P.skip : 0;
 }
 
