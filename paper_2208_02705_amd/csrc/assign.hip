@@ -54,6 +54,7 @@ constexpr int FW = 6;               // widest final digit
 constexpr int NFIN = 1 << FW;       // its values
 constexpr int ST = 1024;            // threads per block of the selection kernels
 constexpr int GMAX = 64;            // their blocks, at most
+constexpr int TP = 1;               // first ties per block and value whose list positions are kept
 constexpr uint32_t SENT = 0xFFFFFFFFu;   // d^2 of an entry outside the field's candidates
 // One histogram set: level 0 in NCOPY copies (block b adds into copy b mod
 // NCOPY, so that the blocks' flushes do not all meet at one address), the
@@ -101,6 +102,7 @@ struct AssignWs {
     int32_t* bcount;      // [blocks] occupied voxels per compaction block, then their offsets
     uint32_t* hist;       // [2][HSET] two histogram sets
     uint32_t* cnt;        // [NFIN][GMAX] final-digit counts per block
+    int32_t* tpos;        // [NFIN][GMAX] list position of each block's first tie per value (-1 none)
     FieldSel* sel;        // [2]
     int32_t* total;       // S
 };
@@ -119,6 +121,7 @@ AssignWs carve_assign(void* base, int64_t nvox) {
     w.bcount = reinterpret_cast<int32_t*>(take(nb * 4));
     w.hist = reinterpret_cast<uint32_t*>(take((size_t)2 * HSET * 4));
     w.cnt = reinterpret_cast<uint32_t*>(take((size_t)NFIN * GMAX * 4));
+    w.tpos = reinterpret_cast<int32_t*>(take((size_t)NFIN * GMAX * TP * 4));
     w.sel = reinterpret_cast<FieldSel*>(take(2 * sizeof(FieldSel)));
     w.total = reinterpret_cast<int32_t*>(take(4));
     return w;
@@ -127,7 +130,7 @@ AssignWs carve_assign(void* base, int64_t nvox) {
 size_t assign_bytes(int64_t nvox) {
     const int64_t nb = (nvox + CB - 1) / CB, n16 = (nvox + 15) & ~int64_t(15);
     return up256(n16 * 4) + 2 * up256(n16 * 4) + up256(nb * 4) + up256((size_t)2 * HSET * 4) +
-           up256((size_t)NFIN * GMAX * 4) + up256(2 * sizeof(FieldSel)) + up256(4);
+           up256((size_t)NFIN * GMAX * 4) + up256((size_t)NFIN * GMAX * TP * 4) + up256(2 * sizeof(FieldSel)) + up256(4);
 }
 
 // Exclusive prefix over a block of NT threads; returns the block total.
@@ -355,6 +358,7 @@ struct StepArgs {
     const FieldSel* cur;        // field k (its digit kernels are complete)
     const uint32_t* hcur;       // its histogram set
     const uint32_t* cnt;        // its final-digit counts per block
+    const int32_t* tpos;        // and the positions of each block's first ties
     FieldSel* nxt;              // field k + 1
     uint32_t* hnxt;
     int32_t field;              // k, or -1 before the first field
@@ -389,6 +393,7 @@ struct SettleIn {
     Pick s;
     u32x4h cv;
     int tv;
+    i32x4h tp;
 };
 __device__ __forceinline__ SettleIn settle_load(const StepArgs& a) {
     static_assert(NFIN * GMAX == 4 * ST, "one 16-byte load of counts per thread");
@@ -396,17 +401,21 @@ __device__ __forceinline__ SettleIn settle_load(const StepArgs& a) {
     in.s = a.cur->lv[a.g.nh];
     in.cv = reinterpret_cast<const u32x4h*>(a.cnt)[threadIdx.x];
     in.tv = threadIdx.x < (1u << a.g.wf) ? (int)a.hcur[HTOT + threadIdx.x] : 0;
+    static_assert(NFIN * GMAX * TP == 4 * ST, "one 16-byte load of tie positions per thread");
+    in.tp = reinterpret_cast<const i32x4h*>(a.tpos)[threadIdx.x];
     return in;
 }
 __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uint32_t& dlim, int64_t& pos) {
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[NFIN * GMAX];
-    __shared__ int s_v, s_whole, s_b;
+    __shared__ __attribute__((aligned(16))) int32_t s_tp[NFIN * GMAX * TP];
+    __shared__ int s_v, s_whole, s_b, s_direct;
     __shared__ int64_t s_need, s_pos;
     const Pick s = in.s;
     const int tv = in.tv;
     if (s.found) { dlim = s.dlim; pos = INT64_MAX; return; }     // uniform
     const u32x4h cv = in.cv;
     reinterpret_cast<u32x4h*>(s_cnt)[threadIdx.x] = cv;
+    reinterpret_cast<i32x4h*>(s_tp)[threadIdx.x] = in.tp;
     __syncthreads();
     if (threadIdx.x < 64) {
         const int t = threadIdx.x;
@@ -418,6 +427,8 @@ __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uin
         const int whole = need == __shfl(tv, v, 64) ? 1 : 0;
         int b = 0;
         int64_t r = need;
+        int direct = 0;
+        int64_t p = first;
         if (!whole) {
             const int c = t < a.G ? (int)s_cnt[v * GMAX + t] : 0;
             const int inc2 = wave_scan(c);
@@ -425,12 +436,18 @@ __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uin
             const uint64_t m2 = __ballot(c > 0 && ex2 < need && need <= inc2);
             b = m2 ? __ffsll((unsigned long long)m2) - 1 : 0;
             r = need - __shfl((int)ex2, b, 64);
+            // the chunk's first tie: its position was kept
+            if (r >= 1 && r <= TP) {
+                const int32_t q = s_tp[(v * GMAX + b) * TP + (int)r - 1];
+                if (q >= 0) { direct = 1; p = q; }
+            }
         }
-        if (t == 0) { s_v = v; s_whole = whole; s_b = b; s_need = r; s_pos = first; }
+        if (t == 0) { s_v = v; s_whole = whole; s_b = b; s_need = r; s_pos = p; s_direct = direct; }
     }
     __syncthreads();
     dlim = (s.prefix << a.g.wf) | (uint32_t)s_v;
     if (s_whole) { pos = INT64_MAX; return; }                  // uniform
+    if (s_direct) { pos = s_pos; return; }                     // uniform
     int64_t r = s_need;
     int64_t cb, ce;
     chunk_of(first, a.S, a.G, s_b, cb, ce);
@@ -647,8 +664,10 @@ __global__ __launch_bounds__(ST) void k_sel_level(FieldSel* sel, uint32_t* __res
 // set when it is the field's first digit kernel.
 __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __restrict__ hset,
                                                    uint32_t* __restrict__ hother, const uint32_t* __restrict__ d2,
-                                                   uint32_t* __restrict__ cnt, int64_t S, Geom g) {
+                                                   uint32_t* __restrict__ cnt, int32_t* __restrict__ tpos, int64_t S,
+                                                   Geom g) {
     __shared__ uint32_t c[NFIN];
+    __shared__ int32_t tf[NFIN];
     const int64_t first = sel->first;
     int64_t cb, ce;
     chunk_of(first, S, gridDim.x, blockIdx.x, cb, ce);
@@ -662,7 +681,7 @@ __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __res
     const Pick s = block_pick(sel->lv[L], hset + lv_off(L), lv_copies(L), g.w[L], g.sh[L]);
     if (blockIdx.x == 0 && threadIdx.x == 0) sel->lv[g.nh] = s;
     if (s.found) return;                                 // uniform
-    if (threadIdx.x < NFIN) c[threadIdx.x] = 0;
+    if (threadIdx.x < NFIN) { c[threadIdx.x] = 0; tf[threadIdx.x] = 0x7fffffff; }
     __syncthreads();
     const int wf = g.wf;
     const uint32_t mask = (1u << wf) - 1u;
@@ -671,7 +690,10 @@ __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __res
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int64_t i = 4 * u + e;
-            if (i >= first && i < S && d[e] != SENT && (d[e] >> wf) == s.prefix) atomicAdd(&c[d[e] & mask], 1u);
+            if (i >= first && i < S && d[e] != SENT && (d[e] >> wf) == s.prefix) {
+                atomicAdd(&c[d[e] & mask], 1u);
+                atomicMin(&tf[d[e] & mask], (int32_t)i);    // the chunk's first tie of this value
+            }
         }
     }
     __syncthreads();
@@ -679,6 +701,7 @@ __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __res
         const uint32_t v = c[threadIdx.x];
         cnt[threadIdx.x * GMAX + blockIdx.x] = v;
         if (v) atomicAdd(&hset[HTOT + threadIdx.x], v);
+        tpos[threadIdx.x * GMAX + blockIdx.x] = v ? tf[threadIdx.x] : -1;
     }
 }
 
@@ -833,7 +856,7 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     StepArgs sa{};
     sa.list = w.list; sa.S = S; sa.g = g;
     sa.n0 = make_divisor((uint32_t)n[0]); sa.n1 = make_divisor((uint32_t)n[1]);
-    sa.cnt = w.cnt; sa.G = G; sa.fmap = fmap;
+    sa.cnt = w.cnt; sa.tpos = w.tpos; sa.G = G; sa.fmap = fmap;
     // the step before field 0 only finds its anchor and d^2 (set 0)
     int32_t k = 0;
     while (k < n_fields && size_of(k) == 0) ++k;
@@ -852,7 +875,7 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
         if (!take_all) {
             for (int lv = 1; lv < g.nh; ++lv)
                 hipLaunchKernelGGL(k_sel_level, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], S, g, lv);
-            hipLaunchKernelGGL(k_sel_final, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], w.cnt, S, g);
+            hipLaunchKernelGGL(k_sel_final, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], w.cnt, w.tpos, S, g);
         }
         left -= sk;
         int32_t k2 = k + 1;
