@@ -720,7 +720,7 @@ r360_status r360_backward(const r360_scene* s, const float* o, const float* d, i
     w.rd = d;
     {
         R360_STAGE(5, S(stream));
-        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, S(stream)));
+        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, nullptr, S(stream)));
     }
     {
         R360_STAGE(6, S(stream));
@@ -750,7 +750,7 @@ r360_status r360_train_step(const r360_scene* s, const float* o, const float* d,
     }
     {
         R360_STAGE(5, S(stream));
-        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, S(stream)));
+        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, rgb, S(stream)));
     }
     {
         R360_STAGE(6, S(stream));

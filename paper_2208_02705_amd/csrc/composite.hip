@@ -285,15 +285,19 @@ __global__ __launch_bounds__(256) void k_term_gather(int64_t n2, const int32_t* 
     }
 }
 
-// Backward over the slot layout, one lane per ray: pass 1 recomputes C,
-// pass 2 repeats the same accumulation so that C - C_{<=i} is a difference of
-// identically computed partial sums (exactly 0 after the last sample):
-//   dL/dc_i = w_i g,  dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - ((C - C_{<=i}) . g)].
+// Backward over the slot layout, one lane per ray:
+//   dL/dc_i = w_i g,  dL/dsigma_i = delta_i [T_{i+1} (c_i . g) - ((C - C_{<=i}) . g)],
+// with C - C_{<=i} a difference of identically computed partial sums
+// (exactly 0 after the last sample). HAVE_C: C is the forward pass's colour
+// (crgb [3][N]), whose accumulation is the same operations in the same
+// order; otherwise a first pass recomputes it.
+template <bool HAVE_C>
 __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __restrict__ cnt, int64_t N, int64_t cap,
                                                              int smax, const float* __restrict__ sigma,
                                                              const float* __restrict__ rgb,
                                                              const float* __restrict__ delta,
-                                                             const float* __restrict__ grad, float* __restrict__ dsigma,
+                                                             const float* __restrict__ grad,
+                                                             const float* __restrict__ crgb, float* __restrict__ dsigma,
                                                              float* __restrict__ drgb) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
@@ -305,7 +309,8 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
     float* drgb2 = drgb + 2 * cap;
     const float g0 = grad[r], g1 = grad[N + r], g2 = grad[2 * N + r];
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    for (int pass = 0; pass < 2; ++pass) {
+    if constexpr (HAVE_C) { C0 = crgb[r]; C1 = crgb[N + r]; C2 = crgb[2 * N + r]; }
+    for (int pass = HAVE_C ? 1 : 0; pass < 2; ++pass) {
         float S = 0.0f, P0 = 0.0f, P1 = 0.0f, P2 = 0.0f;
         for (int k = 0; k < c; k += CBB) {
             float sg[CBB], dl[CBB], q0[CBB], q1[CBB], q2[CBB];
@@ -502,9 +507,14 @@ hipError_t launch_term_gather(int64_t n2, const int32_t* list, const float* ro, 
     return hipGetLastError();
 }
 
-hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st) {
-    hipLaunchKernelGGL(k_composite_bwd_slots, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.slots.smax,
-                       w.sigma, w.rgb, w.delta, grad_rgb, w.dsigma, w.drgb);
+hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, const float* crgb,
+                                           hipStream_t st) {
+    if (crgb)
+        hipLaunchKernelGGL(k_composite_bwd_slots<true>, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap,
+                           w.slots.smax, w.sigma, w.rgb, w.delta, grad_rgb, crgb, w.dsigma, w.drgb);
+    else
+        hipLaunchKernelGGL(k_composite_bwd_slots<false>, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap,
+                           w.slots.smax, w.sigma, w.rgb, w.delta, grad_rgb, crgb, w.dsigma, w.drgb);
     return hipGetLastError();
 }
 

@@ -516,7 +516,9 @@ hipError_t launch_term_select(const Workspace& w, int64_t N, int K, const float*
                               int32_t* n2, hipStream_t st);
 hipError_t launch_term_gather(int64_t n2, const int32_t* list, const float* ro, const float* rd, int64_t N, float* o2,
                               float* d2, hipStream_t st);
-hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);
+// crgb: the forward pass's per-ray colour [3][N], or null to recompute it.
+hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, const float* crgb,
+                                           hipStream_t st);
 hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, const float* target, float* loss,
                             float* grad_rgb, hipStream_t st);
 hipError_t launch_composite_backward(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);
