@@ -19,8 +19,10 @@
 // to 6 bits whose counts are kept per block, each block counting one
 // contiguous chunk of the list. With those counts the block holding the
 // r-th tie and the rank inside its chunk follow from a prefix over the
-// blocks, and one scan of that chunk gives the list position of the last
-// entry taken. A level whose picked bin is taken whole ends the search.
+// blocks; each block also keeps the list position of its first tie per
+// value, so only a tie that is not the first of its chunk needs a scan of
+// that chunk for the position of the last entry taken. A level whose picked
+// bin is taken whole ends the search.
 //
 // Launches per field: one step kernel that settles the previous field's
 // threshold (final pick and tie position), assigns it, finds this field's
@@ -57,8 +59,9 @@ constexpr int GMAX = 64;            // their blocks, at most
 constexpr int TP = 1;               // first ties per block and value whose list positions are kept
 constexpr uint32_t SENT = 0xFFFFFFFFu;   // d^2 of an entry outside the field's candidates
 // One histogram set: level 0 in NCOPY copies (block b adds into copy b mod
-// NCOPY, so that the blocks' flushes do not all meet at one address), the
-// further levels, then the final digit's totals.
+// NCOPY, so that the blocks' flushes meet at fewer addresses; one copy since
+// the blocks are few and wide), the further levels, then the final digit's
+// totals.
 constexpr int NCOPY = 1;
 constexpr int HSET = (NCOPY + HLMAX - 1) * NBIN + NFIN;
 constexpr int HTOT = (NCOPY + HLMAX - 1) * NBIN;
