@@ -471,7 +471,8 @@ r360_status r360_assign_uniform(const int32_t n[3], const float* occ, float thre
 /* Optional per-stage timing for benchmarking: when enabled, every entry
  * point records a HIP event pair around each stage of its launch sequence on
  * the call's own stream. Stages: 0 sampling (traversal + scan + compaction), 1 routing,
- * 2 field-MLP forward, 3 compositing, 4 loss, 5 compositing backward,
+ * 2 field-MLP forward, 3 compositing, 4 loss (as a launch of its own; the
+ * local training step folds it into stages 3 and 5), 5 compositing backward,
  * 6 field-MLP backward (with the per-field gradient reduction), 7 the whole
  * global-field step, 8 the occupancy update (and depth statistics). */
 #define R360_NSTAGES 9

@@ -181,8 +181,11 @@ r360_status prepare(const r360_scene* s, int64_t N, const r360_render_opts* opts
 r360_status render_terminated(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
                               float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st);
 
+// target / grad_rgb (training): the compositing also writes the loss gradient
+// and the loss partials.
 r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, const r360_render_opts* opts,
-                          float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st) {
+                          float* rgb, float* depth, float* opacity, Workspace& w, hipStream_t st,
+                          const float* target = nullptr, float* grad_rgb = nullptr) {
     w.ro = src.mode == RAYS_GIVEN ? src.o : w.o;
     w.rd = src.mode == RAYS_GIVEN ? src.d : w.d;
     if (opts->term_eps > 0.0f) return render_terminated(s, src, N, opts, rgb, depth, opacity, w, st);
@@ -202,7 +205,7 @@ r360_status render_common(const r360_scene* s, const RaySource& src, int64_t N, 
     }
     {
         R360_STAGE(3, st);
-        R360_TRY("composite", launch_composite_slots(w, N, rgb, depth, opacity, st));
+        R360_TRY("composite", launch_composite_slots(w, N, rgb, depth, opacity, st, nullptr, target, grad_rgb));
     }
     return R360_OK;
 }
@@ -720,7 +723,7 @@ r360_status r360_backward(const r360_scene* s, const float* o, const float* d, i
     w.rd = d;
     {
         R360_STAGE(5, S(stream));
-        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, nullptr, S(stream)));
+        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, nullptr, nullptr, S(stream)));
     }
     {
         R360_STAGE(6, S(stream));
@@ -742,15 +745,13 @@ r360_status r360_train_step(const r360_scene* s, const float* o, const float* d,
     src.mode = RAYS_GIVEN;
     src.o = o;
     src.d = d;
-    st = render_common(s, src, N, opts, rgb, nullptr, nullptr, w, S(stream));
+    // the loss is folded into the compositing passes: its gradient and partial
+    // sums in the forward one, the final sum in the backward one
+    st = render_common(s, src, N, opts, rgb, nullptr, nullptr, w, S(stream), target, grad_rgb);
     if (st != R360_OK) return st;
     {
-        R360_STAGE(4, S(stream));
-        R360_TRY("loss", launch_loss_grad(w, N, rgb, target, loss, grad_rgb, S(stream)));
-    }
-    {
         R360_STAGE(5, S(stream));
-        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, rgb, S(stream)));
+        R360_TRY("composite backward", launch_composite_backward_slots(w, N, grad_rgb, rgb, loss, S(stream)));
     }
     {
         R360_STAGE(6, S(stream));

@@ -201,22 +201,44 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
 constexpr int CB = 4;
 constexpr int CBB = 8;   // backward: training batches leave about one wave per SIMD, so more loads per batch
 
+// The training loss L = 1/(3N) sum (C - C*)^2, split over the kernels that
+// already touch the rays: the forward compositing writes dL/dC = 2 (C - C*)
+// / (3N) per ray and channel and one partial sum per block of 256 rays (a
+// fixed tree order), and block 0 of the compositing backward adds the
+// partials (a fixed order again).
+struct LossOut {
+    const float* target;   // [3][N]
+    float* grad;           // [3][N]
+    float* part;           // [blocks of the forward compositing]
+};
+__device__ __forceinline__ float block_sum256(float v) {
+    __shared__ float red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    const float r = red[0];
+    __syncthreads();
+    return r;
+}
+
 // One lane per ray over the slot layout. CONT: the second pass of early
 // termination: lane i composites the slots of continued ray i and adds them
 // to the saved sums of the original ray list[i] (the same operations in the
 // same order as one pass over all its samples). Otherwise lane i is ray i,
 // starting from zero; with `state` set the final sums are also saved
 // ([6][N]: C0, C1, C2, depth, opacity, S). Outputs go to the original ray.
+// The compositing of one ray (lane i); returns its squared colour error
+// when lo is set (and writes the loss gradient), else 0.
 template <bool CONT>
-__global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restrict__ cnt, int64_t n, int64_t cap,
-                                                         int smax, const float* __restrict__ sigma,
-                                                         const float* __restrict__ rgb, const float* __restrict__ t_mid,
-                                                         const float* __restrict__ delta,
-                                                         const int32_t* __restrict__ list, int64_t N,
-                                                         float* __restrict__ state, float* __restrict__ out_rgb,
-                                                         float* __restrict__ depth, float* __restrict__ opacity) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ float composite_one(int64_t i, const int32_t* __restrict__ cnt, int64_t cap, int smax,
+                                               const float* __restrict__ sigma, const float* __restrict__ rgb,
+                                               const float* __restrict__ t_mid, const float* __restrict__ delta,
+                                               const int32_t* __restrict__ list, int64_t N, float* __restrict__ state,
+                                               float* __restrict__ out_rgb, float* __restrict__ depth,
+                                               float* __restrict__ opacity, const LossOut* lo) {
     const int64_t r = CONT ? (int64_t)list[i] : i;
     const int c = cnt[i];
     // slot indices stay below 2^30: 32-bit offsets from each array's base
@@ -255,6 +277,42 @@ __global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restri
         state[r] = c0; state[N + r] = c1; state[2 * N + r] = c2;
         state[3 * N + r] = D; state[4 * N + r] = A; state[5 * N + r] = S;
     }
+    float l = 0.0f;
+    if (lo) {
+        const float inv = 1.0f / (3.0f * (float)N);
+        const float cc[3] = {c0, c1, c2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float diff = cc[k] - lo->target[k * N + r];
+            l += diff * diff;
+            lo->grad[k * N + r] = 2.0f * diff * inv;
+        }
+    }
+    return l;
+}
+
+// LOSS (training, not with CONT): also the loss gradient and the block's
+// loss partial (LossOut); every thread of the block then reaches the sum.
+template <bool CONT, bool LOSS = false>
+__global__ __launch_bounds__(256) void k_composite_slots(const int32_t* __restrict__ cnt, int64_t n, int64_t cap,
+                                                         int smax, const float* __restrict__ sigma,
+                                                         const float* __restrict__ rgb, const float* __restrict__ t_mid,
+                                                         const float* __restrict__ delta,
+                                                         const int32_t* __restrict__ list, int64_t N,
+                                                         float* __restrict__ state, float* __restrict__ out_rgb,
+                                                         float* __restrict__ depth, float* __restrict__ opacity,
+                                                         LossOut lo = LossOut{}) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (LOSS) {
+        float l = 0.0f;
+        if (i < n) l = composite_one<CONT>(i, cnt, cap, smax, sigma, rgb, t_mid, delta, list, N, state, out_rgb, depth,
+                                           opacity, &lo);
+        const float sum = block_sum256(l);
+        if (threadIdx.x == 0) lo.part[blockIdx.x] = sum;
+        return;
+    }
+    if (i >= n) return;
+    composite_one<CONT>(i, cnt, cap, smax, sigma, rgb, t_mid, delta, list, N, state, out_rgb, depth, opacity, nullptr);
 }
 
 // Early termination: the rays that continue after their first K samples are
@@ -291,6 +349,8 @@ __global__ __launch_bounds__(256) void k_term_gather(int64_t n2, const int32_t* 
 // (exactly 0 after the last sample). HAVE_C: C is the forward pass's colour
 // (crgb [3][N]), whose accumulation is the same operations in the same
 // order; otherwise a first pass recomputes it.
+// With loss set, block 0 first adds the forward compositing's nb loss
+// partials (the loss's last step).
 template <bool HAVE_C>
 __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __restrict__ cnt, int64_t N, int64_t cap,
                                                              int smax, const float* __restrict__ sigma,
@@ -298,7 +358,14 @@ __global__ __launch_bounds__(256) void k_composite_bwd_slots(const int32_t* __re
                                                              const float* __restrict__ delta,
                                                              const float* __restrict__ grad,
                                                              const float* __restrict__ crgb, float* __restrict__ dsigma,
-                                                             float* __restrict__ drgb) {
+                                                             float* __restrict__ drgb, const float* __restrict__ lpart,
+                                                             int nb, float* __restrict__ loss) {
+    if (loss && blockIdx.x == 0) {
+        float sp = 0.0f;
+        for (int k = threadIdx.x; k < nb; k += 256) sp += lpart[k];
+        const float tot = block_sum256(sp);
+        if (threadIdx.x == 0) *loss = tot / (3.0f * (float)N);
+    }
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
     const int c = cnt[r];
@@ -480,17 +547,23 @@ hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* de
 }
 
 hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
-                                  hipStream_t st, float* state) {
-    hipLaunchKernelGGL(k_composite_slots<false>, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap, w.slots.smax,
-                       w.sigma, w.rgb, w.t_mid, w.delta, nullptr, N, state, rgb, depth, opacity);
+                                  hipStream_t st, float* state, const float* target, float* grad_rgb) {
+    if (target)
+        hipLaunchKernelGGL((k_composite_slots<false, true>), dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap,
+                           w.slots.smax, w.sigma, w.rgb, w.t_mid, w.delta, nullptr, N, state, rgb, depth, opacity,
+                           LossOut{target, grad_rgb, w.loss_part});
+    else
+        hipLaunchKernelGGL((k_composite_slots<false, false>), dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap,
+                           w.slots.smax, w.sigma, w.rgb, w.t_mid, w.delta, nullptr, N, state, rgb, depth, opacity,
+                           LossOut{});
     return hipGetLastError();
 }
 
 hipError_t launch_composite_continue(const Workspace& w2, const int32_t* list, int64_t N, const float* state,
                                      float* rgb, float* depth, float* opacity, hipStream_t st) {
-    hipLaunchKernelGGL(k_composite_slots<true>, dim3(nblk(w2.N)), dim3(256), 0, st, w2.ray_off, w2.N, w2.cap,
-                       w2.slots.smax, w2.sigma, w2.rgb, w2.t_mid, w2.delta, list, N, const_cast<float*>(state), rgb,
-                       depth, opacity);
+    hipLaunchKernelGGL((k_composite_slots<true, false>), dim3(nblk(w2.N)), dim3(256), 0, st, w2.ray_off, w2.N,
+                       w2.cap, w2.slots.smax, w2.sigma, w2.rgb, w2.t_mid, w2.delta, list, N, const_cast<float*>(state),
+                       rgb, depth, opacity, LossOut{});
     return hipGetLastError();
 }
 
@@ -508,13 +581,16 @@ hipError_t launch_term_gather(int64_t n2, const int32_t* list, const float* ro, 
 }
 
 hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, const float* crgb,
-                                           hipStream_t st) {
+                                           float* loss, hipStream_t st) {
+    const int nb = (int)nblk(N);
     if (crgb)
-        hipLaunchKernelGGL(k_composite_bwd_slots<true>, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap,
-                           w.slots.smax, w.sigma, w.rgb, w.delta, grad_rgb, crgb, w.dsigma, w.drgb);
+        hipLaunchKernelGGL(k_composite_bwd_slots<true>, dim3(nb), dim3(256), 0, st, w.ray_off, N, w.cap,
+                           w.slots.smax, w.sigma, w.rgb, w.delta, grad_rgb, crgb, w.dsigma, w.drgb, w.loss_part, nb,
+                           loss);
     else
-        hipLaunchKernelGGL(k_composite_bwd_slots<false>, dim3(nblk(N)), dim3(256), 0, st, w.ray_off, N, w.cap,
-                           w.slots.smax, w.sigma, w.rgb, w.delta, grad_rgb, crgb, w.dsigma, w.drgb);
+        hipLaunchKernelGGL(k_composite_bwd_slots<false>, dim3(nb), dim3(256), 0, st, w.ray_off, N, w.cap,
+                           w.slots.smax, w.sigma, w.rgb, w.delta, grad_rgb, crgb, w.dsigma, w.drgb, w.loss_part, nb,
+                           loss);
     return hipGetLastError();
 }
 

@@ -504,9 +504,12 @@ hipError_t launch_mlp_forward(const r360_scene* s, const Workspace& w, int preci
 // Compositing over the compact layout with ray ids (w.ray_off offsets, w.ray) ...
 hipError_t launch_composite(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
                             hipStream_t st);
-// ... and over the slot layout (w.ray_off counts).
+// ... and over the slot layout (w.ray_off counts); with target [3][N] also
+// the training loss's gradient grad_rgb [3][N] and its per-block partials
+// (w.loss_part), summed by launch_composite_backward_slots.
 hipError_t launch_composite_slots(const Workspace& w, int64_t N, float* rgb, float* depth, float* opacity,
-                                  hipStream_t st, float* state = nullptr);
+                                  hipStream_t st, float* state = nullptr, const float* target = nullptr,
+                                  float* grad_rgb = nullptr);
 // Early termination: the second pass's compositing from the saved sums
 // (state [6][N]), the selection of the rays that continue (list, count n2 on
 // the device) and the gather of their rays ([3][n2] each).
@@ -516,9 +519,11 @@ hipError_t launch_term_select(const Workspace& w, int64_t N, int K, const float*
                               int32_t* n2, hipStream_t st);
 hipError_t launch_term_gather(int64_t n2, const int32_t* list, const float* ro, const float* rd, int64_t N, float* o2,
                               float* d2, hipStream_t st);
-// crgb: the forward pass's per-ray colour [3][N], or null to recompute it.
+// crgb: the forward pass's per-ray colour [3][N], or null to recompute it;
+// loss: where to finish the loss from the forward compositing's partials,
+// or null.
 hipError_t launch_composite_backward_slots(const Workspace& w, int64_t N, const float* grad_rgb, const float* crgb,
-                                           hipStream_t st);
+                                           float* loss, hipStream_t st);
 hipError_t launch_loss_grad(const Workspace& w, int64_t N, const float* rgb, const float* target, float* loss,
                             float* grad_rgb, hipStream_t st);
 hipError_t launch_composite_backward(const Workspace& w, int64_t N, const float* grad_rgb, hipStream_t st);
