@@ -148,17 +148,25 @@ __global__ void k_gnet_pack(GNetDev n, const float* __restrict__ wc, bf16* __res
 }
 
 // Weight gradient: canonical parameter <- sum over slices of its partial.
+// Four neighbouring lanes per parameter, lane j adding the slices k = j mod
+// 4 in order; the four sums are then added as (s0 + s1) + (s2 + s3) (a
+// fixed order), so four times as many loads are in flight.
 __global__ void k_gnet_grad(GNetDev n, const float* __restrict__ part, int64_t part_stride, int slices,
                             float* __restrict__ grad) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n.P) return;
-    int ly, row, col;
-    canon_to_layer(n.w, n.c, p, ly, row, col);
-    const GLayerGeom& g = n.L[ly];
-    const int64_t off = col < 0 ? g.gb_off + row : g.g_off + (int64_t)row * g.K + col;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p = t >> 2;
+    const int j = (int)(t & 3);
     float s = 0.0f;
-    for (int k = 0; k < slices; ++k) s += part[(int64_t)k * part_stride + off];
-    grad[p] = s;
+    if (p < n.P) {
+        int ly, row, col;
+        canon_to_layer(n.w, n.c, p, ly, row, col);
+        const GLayerGeom& g = n.L[ly];
+        const int64_t off = col < 0 ? g.gb_off + row : g.g_off + (int64_t)row * g.K + col;
+        for (int k = j; k < slices; k += 4) s += part[(int64_t)k * part_stride + off];
+    }
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    if (p < n.P && j == 0) grad[p] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,7 +1076,8 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
         std::swap(cur, nxt);
     }
     if ((e = dw(G1, cur, w, g.x5 + w, ld5)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_gnet_grad, dim3(nbP), dim3(256), 0, st, nd, g.part, n.g_elems, G_SLICES, grad);
+    hipLaunchKernelGGL(k_gnet_grad, dim3((unsigned)((4 * n.P + 255) / 256)), dim3(256), 0, st, nd, g.part, n.g_elems,
+                       G_SLICES, grad);
     return hipGetLastError();
 }
 
