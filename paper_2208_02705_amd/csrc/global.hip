@@ -295,6 +295,11 @@ struct GemmArgs {
     float* rgb;
     // EPI_DX: out[r * ldo + c] = acc * [mask[r * ldm + c] > 0] (mask may be null)
     const bf16* mask; int64_t ldm;
+    // The ReLU pattern as sign bits, bit c % 8 of byte mbits[r * ldb + c / 8]
+    // set where the stored output is > 0: written by EPI_FWD when mbits is set
+    // (weight-resident kernel only), read by EPI_DX from mbits_in in place of
+    // mask (a sixteenth of the bytes).
+    uint8_t* mbits; const uint8_t* mbits_in; int64_t ldb;
     // EPI_DW: total samples M; readable columns of A and B (multiples of 8);
     // part[slice * pstride + r * ldp + c] = acc; row sums at part[slice * pstride + boff + r]
     int64_t Mtot; int a_lim, b_lim;
@@ -488,25 +493,36 @@ constexpr int RW_WAVES = 16;
 // First of the lane's eight columns in the epilogue of tiles ta, ta+1.
 __device__ __forceinline__ int rw_col0(int ta, int g4) { return 16 * (ta + (g4 & 1)) + 4 * (g4 & 2); }
 
-// The forward activations at those eight columns of row r (zero past ncols
-// or past the last row): the ReLU pattern of an input-gradient epilogue,
-// loaded before the tiles' products so that its latency overlaps them.
-__device__ __forceinline__ bf16x8 rw_mask(const GemmArgs& g, int r, int ta, int g4, int ncols) {
+// The ReLU pattern of an input-gradient epilogue at those eight columns of
+// row r (zero past ncols or past the last row): the forward activations, or
+// their sign bits (one byte; c0 is a multiple of 8), loaded before the
+// tiles' products so that the latency overlaps them.
+struct MaskIn {
     bf16x8 m;
+    uint32_t bits;
+};
+__device__ __forceinline__ MaskIn rw_mask(const GemmArgs& g, int r, int ta, int g4, int ncols) {
+    MaskIn mi{};
     const int c0 = rw_col0(ta, g4);
+    if (g.mbits_in) {
+        mi.bits = (r < g.R && c0 < ncols) ? (uint32_t)g.mbits_in[(int64_t)r * g.ldb + (c0 >> 3)] : 0u;
+        return mi;
+    }
     const bf16* mp = g.mask + (int64_t)r * g.ldm + c0;
     if (r < g.R && c0 + 8 <= ncols) {
-        m = *reinterpret_cast<const bf16x8*>(mp);
+        mi.m = *reinterpret_cast<const bf16x8*>(mp);
     } else {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) m[q] = (r < g.R && c0 + q < ncols) ? mp[q] : (bf16)0.0f;
+        for (int q = 0; q < 8; ++q) mi.m[q] = (r < g.R && c0 + q < ncols) ? mp[q] : (bf16)0.0f;
     }
-    return m;
+    return mi;
 }
 
+// Returns, for the forward epilogue with sign bits wanted, the lane's eight
+// sign bits (0 past the last row or column); the caller packs them.
 template <int EPI>
-__device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, int g4, f32x4 a, f32x4 b,
-                                             int ncols, bf16x8 m) {
+__device__ __forceinline__ uint32_t rw_epilogue2(const GemmArgs& g, int r, int ta, int g4, f32x4 a, f32x4 b,
+                                                 int ncols, const MaskIn& m) {
     float x[8];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -515,7 +531,7 @@ __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, i
         x[4 + q] = __uint_as_float(sw[1]);
     }
     const int c0 = rw_col0(ta, g4);
-    if (r >= g.R) return;
+    if (r >= g.R) return 0u;
     if constexpr (EPI == EPI_FWD) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -526,17 +542,28 @@ __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, i
             x[q] = y;
         }
     }
-    if (c0 >= ncols) return;
+    if (c0 >= ncols) return 0u;
     bf16x8 o;
 #pragma unroll
     for (int q = 0; q < 8; ++q) o[q] = (bf16)x[q];
     const bool whole = c0 + 8 <= ncols;
     if constexpr (EPI == EPI_DX) {
-        if (g.mask) {
-            // keep the gradient where the forward activation is > 0 (ReLU)
+        // keep the gradient where the forward activation is > 0 (ReLU)
+        if (g.mbits_in) {
 #pragma unroll
             for (int q = 0; q < 8; ++q)
-                if (!((float)m[q] > 0.0f)) o[q] = (bf16)0.0f;
+                if (!((m.bits >> q) & 1u)) o[q] = (bf16)0.0f;
+        } else if (g.mask) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (!((float)m.m[q] > 0.0f)) o[q] = (bf16)0.0f;
+        }
+    }
+    uint32_t bits = 0;
+    if constexpr (EPI == EPI_FWD) {
+        if (g.mbits) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bits |= (c0 + q < ncols && (float)o[q] > 0.0f) ? (1u << q) : 0u;
         }
     }
     bf16* dst = g.out + (int64_t)r * g.ldo + c0;
@@ -547,6 +574,15 @@ __device__ __forceinline__ void rw_epilogue2(const GemmArgs& g, int r, int ta, i
         for (int q = 0; q < 8; ++q)
             if (c0 + q < ncols) dst[q] = o[q];
     }
+    return bits;
+}
+
+// The sign bits of output tiles ta, ta+1 of row r as one word, in lane group
+// 0: lane groups 0, 2, 1, 3 hold columns 16 ta + 0, 8, 16, 24 of the row.
+__device__ __forceinline__ uint32_t rw_bits_word(uint32_t b, int lane) {
+    const uint32_t b2 = __shfl(b, (lane + 32) & 63, 64), b1 = __shfl(b, (lane + 16) & 63, 64),
+                   b3 = __shfl(b, (lane + 48) & 63, 64);
+    return b | (b2 << 8) | (b1 << 16) | (b3 << 24);
 }
 
 template <int EPI, int KS>
@@ -585,9 +621,9 @@ __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) 
     auto tile_mm = [&](const bf16x8* x, int tile) {
         const int r = tile * 16 + l16;
         for (int ot0 = 0; ot0 < CT; ot0 += 4) {
-            bf16x8 m0{}, m1{};
+            MaskIn m0{}, m1{};
             if constexpr (EPI == EPI_DX) {
-                if (g.mask) {
+                if (g.mask || g.mbits_in) {
                     m0 = rw_mask(g, r, ot0, g4, ncols);
                     if (ot0 + 2 < CT) m1 = rw_mask(g, r, ot0 + 2, g4, ncols);
                 }
@@ -609,8 +645,20 @@ __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) 
                 }
             // tiles past CT were computed from a repeated fragment: their
             // columns lie beyond C and are neither stored nor read
-            rw_epilogue2<EPI>(g, r, ot0, g4, acc[0], acc[1], ncols, m0);
-            if (ot0 + 2 < CT) rw_epilogue2<EPI>(g, r, ot0 + 2, g4, acc[2], acc[3], ncols, m1);
+            const uint32_t s0 = rw_epilogue2<EPI>(g, r, ot0, g4, acc[0], acc[1], ncols, m0);
+            const uint32_t s1 = ot0 + 2 < CT ? rw_epilogue2<EPI>(g, r, ot0 + 2, g4, acc[2], acc[3], ncols, m1) : 0u;
+            if constexpr (EPI == EPI_FWD) {
+                if (g.mbits) {
+                    // 64 columns of sign bits per row: one 8-byte store (4 if
+                    // only the first 32 columns exist) by lane group 0
+                    const uint32_t w0 = rw_bits_word(s0, lane), w1 = rw_bits_word(s1, lane);
+                    if (g4 == 0 && r < g.R && 16 * ot0 < ncols) {
+                        uint8_t* bp = g.mbits + (int64_t)r * g.ldb + 2 * ot0;
+                        if (16 * ot0 + 32 < ncols) *reinterpret_cast<uint2*>(bp) = uint2{w0, w1};
+                        else *reinterpret_cast<uint32_t*>(bp) = w0;
+                    }
+                }
+            }
         }
     };
     int t = blockIdx.x * RW_WAVES + wv;
@@ -644,12 +692,18 @@ static hipError_t rowmm_launch(const GemmArgs& a, int CT, size_t lds, hipStream_
 }
 
 // The weight-resident kernel when B fits: returns false if it does not apply.
-template <int EPI>
-static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
+static bool rowmm_applies(const GemmArgs& a) {
     if (a.Kc % 32 || a.C > 272 || a.R < 1) return false;
     const int KS = a.Kc / 32, CT = (a.C + 15) / 16;
     const size_t lds = (size_t)16 * CT * (a.Kc + 16) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
-    if (lds > (size_t)160 * 1024) return false;
+    return lds <= (size_t)160 * 1024 && (KS == 1 || KS == 2 || KS == 4 || KS == 8 || KS == 9);
+}
+
+template <int EPI>
+static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
+    if (!rowmm_applies(a)) return false;
+    const int KS = a.Kc / 32, CT = (a.C + 15) / 16;
+    const size_t lds = (size_t)16 * CT * (a.Kc + 16) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
     switch (KS) {
     case 1: *err = rowmm_launch<EPI, 1>(a, CT, lds, st); return true;
     case 2: *err = rowmm_launch<EPI, 2>(a, CT, lds, st); return true;
@@ -844,8 +898,12 @@ GNetDev dev_net(const GNet& n) {
 }  // namespace
 
 // Workspace of the global stage.
+// Sign bits of the ReLU outputs that later mask an input gradient: h1..h7,
+// the feature f (x10's first columns) and h10.
+enum { MB_F = 8, MB_H10 = 9, MB_N = 10 };
 struct GlobalWs {
     bf16 *arena, *x5, *h[9], *x10, *h10, *dza, *dzb, *dz11;   // h[1..3], h[5..8]
+    uint8_t* mb[MB_N];                                        // mb[1..7], mb[MB_F], mb[MB_H10]
     float *bias, *sig, *rgb, *t, *delta, *dsig, *drgb, *part, *ray_rgb, *ray_grad, *loss_part;
     int32_t *voxel, *ray, *ray_off;
     size_t bytes;
@@ -886,6 +944,9 @@ static GlobalWs gcarve(void* base, const GNet& n, int64_t Nr, int S) {
     g.ray_rgb = (float*)take(3 * Nr * 4);
     g.ray_grad = (float*)take(3 * Nr * 4);
     g.loss_part = (float*)take(((Nr + 255) / 256) * 4);
+    for (int k = 1; k <= 7; ++k) g.mb[k] = (uint8_t*)take(M * (w / 8));
+    g.mb[MB_F] = (uint8_t*)take(M * (w / 8));
+    g.mb[MB_H10] = (uint8_t*)take(M * (n.c / 8));
     g.bytes = off;
     return g;
 }
@@ -967,32 +1028,44 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     auto Wt = [&](int ly) { return W + n.L[ly].t_off; };
     auto Bv = [&](int ly) { return n.L[ly].b_off >= 0 ? g.bias + n.L[ly].b_off : nullptr; };
     const int64_t ld5 = w + 64, ld10 = n.L[G10].K;
+    // ReLU sign bits written by the forward layers that run in the
+    // weight-resident kernel (null where another kernel ran), with their row
+    // strides in bytes
+    const uint8_t* bits[MB_N] = {};
+    int64_t bits_ld[MB_N] = {};
+    auto want_bits = [&](GemmArgs& a, int k) {
+        if (k < 0 || !rowmm_applies(a)) return;
+        a.mbits = g.mb[k]; a.ldb = a.n_out / 8;
+        bits[k] = a.mbits; bits_ld[k] = a.ldb;
+    };
     // forward: layer(A input [M x K] with row stride lda) -> out
-    auto fwd = [&](int ly, const bf16* A, int64_t lda, bf16* out, int64_t ldo, bool relu) {
+    auto fwd = [&](int ly, const bf16* A, int64_t lda, bf16* out, int64_t ldo, bool relu, int mbk) {
         GemmArgs a{};
         a.A = A; a.a_sr = lda; 
         a.B = Wm(ly); a.b_sr = n.L[ly].K;
         a.R = (int)M; a.C = n.L[ly].N; a.Kc = n.L[ly].K;
         a.bias = Bv(ly); a.relu = relu; a.out = out; a.ldo = ldo; a.n_out = n.L[ly].N; a.sig_col = -1;
+        want_bits(a, mbk);
         return gemm(EPI_FWD, a, 1, st);
     };
-    if ((e = fwd(G1, g.x5 + w, ld5, g.h[1], w, true)) != hipSuccess) return e;
-    if ((e = fwd(G2, g.h[1], w, g.h[2], w, true)) != hipSuccess) return e;
-    if ((e = fwd(G3, g.h[2], w, g.h[3], w, true)) != hipSuccess) return e;
-    if ((e = fwd(G4, g.h[3], w, g.x5, ld5, true)) != hipSuccess) return e;
-    if ((e = fwd(G5, g.x5, ld5, g.h[5], w, true)) != hipSuccess) return e;
-    if ((e = fwd(G6, g.h[5], w, g.h[6], w, true)) != hipSuccess) return e;
-    if ((e = fwd(G7, g.h[6], w, g.h[7], w, true)) != hipSuccess) return e;
-    if ((e = fwd(G8, g.h[7], w, g.h[8], w, false)) != hipSuccess) return e;
+    if ((e = fwd(G1, g.x5 + w, ld5, g.h[1], w, true, 1)) != hipSuccess) return e;
+    if ((e = fwd(G2, g.h[1], w, g.h[2], w, true, 2)) != hipSuccess) return e;
+    if ((e = fwd(G3, g.h[2], w, g.h[3], w, true, 3)) != hipSuccess) return e;
+    if ((e = fwd(G4, g.h[3], w, g.x5, ld5, true, 4)) != hipSuccess) return e;
+    if ((e = fwd(G5, g.x5, ld5, g.h[5], w, true, 5)) != hipSuccess) return e;
+    if ((e = fwd(G6, g.h[5], w, g.h[6], w, true, 6)) != hipSuccess) return e;
+    if ((e = fwd(G7, g.h[6], w, g.h[7], w, true, 7)) != hipSuccess) return e;
+    if ((e = fwd(G8, g.h[7], w, g.h[8], w, false, -1)) != hipSuccess) return e;
     {   // head: relu(Wf h8 + bf) -> x10[:, :w]; relu(ws h8 + bs) -> sigma
         GemmArgs a{};
         a.A = g.h[8]; a.a_sr = w; 
         a.B = Wm(GH); a.b_sr = w;
         a.R = (int)M; a.C = w + 1; a.Kc = w;
         a.bias = Bv(GH); a.relu = true; a.out = g.x10; a.ldo = ld10; a.n_out = w; a.sig_col = w; a.sig = g.sig;
+        want_bits(a, MB_F);
         if ((e = gemm(EPI_FWD, a, 1, st)) != hipSuccess) return e;
     }
-    if ((e = fwd(G10, g.x10, ld10, g.h10, c, true)) != hipSuccess) return e;
+    if ((e = fwd(G10, g.x10, ld10, g.h10, c, true, MB_H10)) != hipSuccess) return e;
     {
         GemmArgs a{};
         a.A = g.h10; a.a_sr = c; 
@@ -1026,13 +1099,16 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     // samples per slice: a multiple of the GEMM's step; the last slice is clipped to M
     const int64_t kslice = ((M + G_SLICES - 1) / G_SLICES + DK - 1) / DK * DK;
     // input gradient: dX[M x K'] = dZ [M x NC] . W^T -> masked by act (if any)
+    // (mbk: the sign bits of act, used in its place when the forward wrote
+    // them and this product runs in the weight-resident kernel)
     auto dx = [&](int ly, const bf16* dz, int64_t ldz, bf16* out, int64_t ldo, int ncols, const bf16* act,
-                  int64_t ldact) {
+                  int64_t ldact, int mbk) {
         GemmArgs a{};
         a.A = dz; a.a_sr = ldz; 
         a.B = Wt(ly); a.b_sr = n.L[ly].NC;
         a.R = (int)M; a.C = ncols; a.Kc = n.L[ly].NC;
         a.out = out; a.ldo = ldo; a.mask = act; a.ldm = ldact;
+        if (mbk >= 0 && bits[mbk] && rowmm_applies(a)) { a.mbits_in = bits[mbk]; a.ldb = bits_ld[mbk]; }
         return gemm(EPI_DX, a, 1, st);
     };
     // weight gradient partials: dW[N x K] = dZ^T [N x M] . X [M x K], sliced over M
@@ -1048,31 +1124,31 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     const int ldh = up32(w + 1);
     // L11
     if ((e = dw(G11, g.dz11, 32, g.h10, c)) != hipSuccess) return e;
-    if ((e = dx(G11, g.dz11, 32, g.dza, c, c, g.h10, c)) != hipSuccess) return e;              // dz10
+    if ((e = dx(G11, g.dz11, 32, g.dza, c, c, g.h10, c, MB_H10)) != hipSuccess) return e;      // dz10
     // L10 (feature part of the input only) -> dZf into dzb[:, :w]
     if ((e = dw(G10, g.dza, c, g.x10, ld10)) != hipSuccess) return e;
-    if ((e = dx(G10, g.dza, c, g.dzb, ldh, w, g.x10, ld10)) != hipSuccess) return e;
+    if ((e = dx(G10, g.dza, c, g.dzb, ldh, w, g.x10, ld10, MB_F)) != hipSuccess) return e;
     // head -> dz8 (layer 8 is linear)
     if ((e = dw(GH, g.dzb, ldh, g.h[8], w)) != hipSuccess) return e;
-    if ((e = dx(GH, g.dzb, ldh, g.dza, w, w, nullptr, 0)) != hipSuccess) return e;
+    if ((e = dx(GH, g.dzb, ldh, g.dza, w, w, nullptr, 0, -1)) != hipSuccess) return e;
     // layers 8..6
     bf16* cur = g.dza; bf16* nxt = g.dzb;
     const int back[3] = {G8, G7, G6};
     const bf16* inputs[3] = {g.h[7], g.h[6], g.h[5]};
     for (int q = 0; q < 3; ++q) {
         if ((e = dw(back[q], cur, w, inputs[q], w)) != hipSuccess) return e;
-        if ((e = dx(back[q], cur, w, nxt, w, w, inputs[q], w)) != hipSuccess) return e;
+        if ((e = dx(back[q], cur, w, nxt, w, w, inputs[q], w, 7 - q)) != hipSuccess) return e;
         std::swap(cur, nxt);
     }
     // layer 5: input [h4 | gx | 1]; only the h4 part propagates
     if ((e = dw(G5, cur, w, g.x5, ld5)) != hipSuccess) return e;
-    if ((e = dx(G5, cur, w, nxt, w, w, g.x5, ld5)) != hipSuccess) return e;
+    if ((e = dx(G5, cur, w, nxt, w, w, g.x5, ld5, 4)) != hipSuccess) return e;
     std::swap(cur, nxt);
     const int back2[3] = {G4, G3, G2};
     const bf16* inputs2[3] = {g.h[3], g.h[2], g.h[1]};
     for (int q = 0; q < 3; ++q) {
         if ((e = dw(back2[q], cur, w, inputs2[q], w)) != hipSuccess) return e;
-        if ((e = dx(back2[q], cur, w, nxt, w, w, inputs2[q], w)) != hipSuccess) return e;
+        if ((e = dx(back2[q], cur, w, nxt, w, w, inputs2[q], w, 3 - q)) != hipSuccess) return e;
         std::swap(cur, nxt);
     }
     if ((e = dw(G1, cur, w, g.x5 + w, ld5)) != hipSuccess) return e;
