@@ -1034,7 +1034,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     const uint8_t* bits[MB_N] = {};
     int64_t bits_ld[MB_N] = {};
     auto want_bits = [&](GemmArgs& a, int k) {
-        if (k < 0 || !rowmm_applies(a)) return;
+        if (k < 0 || !(stage_mask & 2) || !rowmm_applies(a)) return;     // only when a backward follows
         a.mbits = g.mb[k]; a.ldb = a.n_out / 8;
         bits[k] = a.mbits; bits_ld[k] = a.ldb;
     };
