@@ -106,6 +106,7 @@ struct AssignWs {
     uint32_t* hist;       // [2][HSET] two histogram sets
     uint32_t* cnt;        // [NFIN][GMAX] final-digit counts per block
     int32_t* tpos;        // [NFIN][GMAX] list position of each block's first tie per value (-1 none)
+    int32_t* agt;         // [GMAX] each block's first entry whose d^2 lies above the picked prefix (INT_MAX none)
     FieldSel* sel;        // [2]
     int32_t* total;       // S
 };
@@ -125,6 +126,7 @@ AssignWs carve_assign(void* base, int64_t nvox) {
     w.hist = reinterpret_cast<uint32_t*>(take((size_t)2 * HSET * 4));
     w.cnt = reinterpret_cast<uint32_t*>(take((size_t)NFIN * GMAX * 4));
     w.tpos = reinterpret_cast<int32_t*>(take((size_t)NFIN * GMAX * TP * 4));
+    w.agt = reinterpret_cast<int32_t*>(take((size_t)GMAX * 4));
     w.sel = reinterpret_cast<FieldSel*>(take(2 * sizeof(FieldSel)));
     w.total = reinterpret_cast<int32_t*>(take(4));
     return w;
@@ -133,7 +135,8 @@ AssignWs carve_assign(void* base, int64_t nvox) {
 size_t assign_bytes(int64_t nvox) {
     const int64_t nb = (nvox + CB - 1) / CB, n16 = (nvox + 15) & ~int64_t(15);
     return up256(n16 * 4) + 2 * up256(n16 * 4) + up256(nb * 4) + up256((size_t)2 * HSET * 4) +
-           up256((size_t)NFIN * GMAX * 4) + up256((size_t)NFIN * GMAX * TP * 4) + up256(2 * sizeof(FieldSel)) + up256(4);
+           up256((size_t)NFIN * GMAX * 4) + up256((size_t)NFIN * GMAX * TP * 4) + up256((size_t)GMAX * 4) +
+           up256(2 * sizeof(FieldSel)) + up256(4);
 }
 
 // Exclusive prefix over a block of NT threads; returns the block total.
@@ -362,6 +365,7 @@ struct StepArgs {
     const uint32_t* hcur;       // its histogram set
     const uint32_t* cnt;        // its final-digit counts per block
     const int32_t* tpos;        // and the positions of each block's first ties
+    const int32_t* agt;         // and each block's first entry above the picked prefix
     FieldSel* nxt;              // field k + 1
     uint32_t* hnxt;
     int32_t field;              // k, or -1 before the first field
@@ -397,6 +401,7 @@ struct SettleIn {
     u32x4h cv;
     int tv;
     i32x4h tp;
+    int32_t ag;
 };
 __device__ __forceinline__ SettleIn settle_load(const StepArgs& a) {
     static_assert(NFIN * GMAX == 4 * ST, "one 16-byte load of counts per thread");
@@ -406,15 +411,25 @@ __device__ __forceinline__ SettleIn settle_load(const StepArgs& a) {
     in.tv = threadIdx.x < (1u << a.g.wf) ? (int)a.hcur[HTOT + threadIdx.x] : 0;
     static_assert(NFIN * GMAX * TP == 4 * ST, "one 16-byte load of tie positions per thread");
     in.tp = reinterpret_cast<const i32x4h*>(a.tpos)[threadIdx.x];
+    in.ag = threadIdx.x < (unsigned)a.G ? a.agt[threadIdx.x] : 0x7fffffff;
     return in;
 }
-__device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uint32_t& dlim, int64_t& pos) {
+// Also the anchor of field k + 1 when it follows from the same counts
+// (anchor = -1 otherwise): the first entry that field k leaves is the first
+// one above the picked prefix, or the first with a larger final digit, or
+// the first tie after the cut. When the cut took every tie of its chunk, the
+// last is the first tie of a later chunk; otherwise it is unknown, but lies
+// after the cut, so the smallest of the others stands when it lies before.
+__device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uint32_t& dlim, int64_t& pos,
+                       int64_t& anchor) {
     __shared__ __attribute__((aligned(16))) uint32_t s_cnt[NFIN * GMAX];
     __shared__ __attribute__((aligned(16))) int32_t s_tp[NFIN * GMAX * TP];
     __shared__ int s_v, s_whole, s_b, s_direct;
-    __shared__ int64_t s_need, s_pos;
+    __shared__ int64_t s_need, s_pos, s_anchor;
+    __shared__ int s_known;
     const Pick s = in.s;
     const int tv = in.tv;
+    anchor = -1;
     if (s.found) { dlim = s.dlim; pos = INT64_MAX; return; }     // uniform
     const u32x4h cv = in.cv;
     reinterpret_cast<u32x4h*>(s_cnt)[threadIdx.x] = cv;
@@ -445,12 +460,46 @@ __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uin
                 if (q >= 0) { direct = 1; p = q; }
             }
         }
-        if (t == 0) { s_v = v; s_whole = whole; s_b = b; s_need = r; s_pos = p; s_direct = direct; }
+        // the next field's anchor (lane t: block t)
+        auto wave_min = [](int32_t x) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, 64));
+            return x;
+        };
+        int32_t cand = in.ag;                                   // above the prefix
+        if (t < a.G) {
+            for (int u = v + 1; u < (1 << a.g.wf); ++u) {      // larger final digit
+                const int32_t q = s_tp[u * GMAX + t];
+                if (q >= 0) cand = min(cand, q);
+            }
+        }
+        bool known = true;
+        if (!whole) {
+            const int cb = __shfl(t < a.G ? (int)s_cnt[v * GMAX + t] : 0, b, 64);
+            if (r < cb) known = false;                          // another tie of the chunk follows the cut
+            else if (t > b && t < a.G) {                        // ties in later chunks
+                const int32_t q = s_tp[v * GMAX + t];
+                if (q >= 0) cand = min(cand, q);
+            }
+        }
+        cand = wave_min(cand);
+        if (t == 0) {
+            s_v = v; s_whole = whole; s_b = b; s_need = r; s_pos = p; s_direct = direct;
+            s_anchor = cand == 0x7fffffff ? (int64_t)a.S : (int64_t)cand;
+            s_known = known ? 1 : 0;
+        }
     }
     __syncthreads();
     dlim = (s.prefix << a.g.wf) | (uint32_t)s_v;
+    const int64_t other = s_anchor;
+    const bool known = s_known;
+    anchor = known ? other : -1;
     if (s_whole) { pos = INT64_MAX; return; }                  // uniform
-    if (s_direct) { pos = s_pos; return; }                     // uniform
+    if (s_direct) {                                            // uniform
+        pos = s_pos;
+        if (!known && other < pos) anchor = other;
+        return;
+    }
     int64_t r = s_need;
     int64_t cb, ce;
     chunk_of(first, a.S, a.G, s_b, cb, ce);
@@ -481,6 +530,7 @@ __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uin
         r -= total;
     }
     pos = s_pos;
+    if (!known && other < pos) anchor = other;
 }
 
 // Assigns field k (entries under its threshold, or all that are left),
@@ -526,10 +576,10 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
         if (u < uend) { md[p] = ld_d2(u); ml[p] = ld_lin(u); }
     }
     uint32_t dlim = 0;
-    int64_t pos = -1;
+    int64_t pos = -1, known_anchor = -1;
     if (prev) {
         if (a.take_all) { dlim = SENT; pos = INT64_MAX; }
-        else settle(a, sin, first, dlim, pos);
+        else settle(a, sin, first, dlim, pos, known_anchor);
     }
     // an entry is a candidate of field k + 1 when it is one of field k's
     // candidates (or any entry before the first field) that field k leaves
@@ -541,7 +591,8 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
     // The anchor search: rounds of 4 ST units (16 consecutive entries per
     // thread); field k's d^2 is read-only here.
     int64_t nfirst = a.S;
-    if (a.has_next) {
+    if (a.has_next && known_anchor >= 0) nfirst = known_anchor;  // uniform
+    else if (a.has_next) {
         for (int r = 0; ubeg + (int64_t)PB * ST * r < uend; ++r) {
             const int64_t u0 = ubeg + (int64_t)PB * ST * r + PB * threadIdx.x;
             if (r > 0) {
@@ -667,10 +718,11 @@ __global__ __launch_bounds__(ST) void k_sel_level(FieldSel* sel, uint32_t* __res
 // set when it is the field's first digit kernel.
 __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __restrict__ hset,
                                                    uint32_t* __restrict__ hother, const uint32_t* __restrict__ d2,
-                                                   uint32_t* __restrict__ cnt, int32_t* __restrict__ tpos, int64_t S,
-                                                   Geom g) {
+                                                   uint32_t* __restrict__ cnt, int32_t* __restrict__ tpos,
+                                                   int32_t* __restrict__ agt, int64_t S, Geom g) {
     __shared__ uint32_t c[NFIN];
     __shared__ int32_t tf[NFIN];
+    __shared__ int32_t above;
     const int64_t first = sel->first;
     int64_t cb, ce;
     chunk_of(first, S, gridDim.x, blockIdx.x, cb, ce);
@@ -685,7 +737,9 @@ __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __res
     if (blockIdx.x == 0 && threadIdx.x == 0) sel->lv[g.nh] = s;
     if (s.found) return;                                 // uniform
     if (threadIdx.x < NFIN) { c[threadIdx.x] = 0; tf[threadIdx.x] = 0x7fffffff; }
+    if (threadIdx.x == 0) above = 0x7fffffff;
     __syncthreads();
+    int32_t ab = 0x7fffffff;                                // this thread's first entry above the prefix
     const int wf = g.wf;
     const uint32_t mask = (1u << wf) - 1u;
     for (int64_t u = ub + threadIdx.x; u < ue; u += ST) {
@@ -697,9 +751,14 @@ __global__ __launch_bounds__(ST) void k_sel_final(FieldSel* sel, uint32_t* __res
                 atomicAdd(&c[d[e] & mask], 1u);
                 atomicMin(&tf[d[e] & mask], (int32_t)i);    // the chunk's first tie of this value
             }
+            if (i >= first && i < S && d[e] != SENT && (d[e] >> wf) > s.prefix) ab = min(ab, (int32_t)i);
         }
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ab = min(ab, __shfl_xor(ab, off, 64));
+    if ((threadIdx.x & 63) == 0 && ab != 0x7fffffff) atomicMin(&above, ab);
     __syncthreads();
+    if (threadIdx.x == 0) agt[blockIdx.x] = above;
     if (threadIdx.x < (1 << wf)) {
         const uint32_t v = c[threadIdx.x];
         cnt[threadIdx.x * GMAX + blockIdx.x] = v;
@@ -859,7 +918,7 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
     StepArgs sa{};
     sa.list = w.list; sa.S = S; sa.g = g;
     sa.n0 = make_divisor((uint32_t)n[0]); sa.n1 = make_divisor((uint32_t)n[1]);
-    sa.cnt = w.cnt; sa.tpos = w.tpos; sa.G = G; sa.fmap = fmap;
+    sa.cnt = w.cnt; sa.tpos = w.tpos; sa.agt = w.agt; sa.G = G; sa.fmap = fmap;
     // the step before field 0 only finds its anchor and d^2 (set 0)
     int32_t k = 0;
     while (k < n_fields && size_of(k) == 0) ++k;
@@ -878,7 +937,8 @@ hipError_t launch_assign_fields(const int32_t n[3], const float* occ, float thr,
         if (!take_all) {
             for (int lv = 1; lv < g.nh; ++lv)
                 hipLaunchKernelGGL(k_sel_level, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], S, g, lv);
-            hipLaunchKernelGGL(k_sel_final, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], w.cnt, w.tpos, S, g);
+            hipLaunchKernelGGL(k_sel_final, dim3(G), dim3(ST), 0, st, sel, hset, hother, w.d2[set], w.cnt, w.tpos, w.agt, S,
+                               g);
         }
         left -= sk;
         int32_t k2 = k + 1;
