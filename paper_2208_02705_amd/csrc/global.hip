@@ -956,9 +956,11 @@ int64_t global_params(int w, int c) { return make_net(w, c).P; }
 
 static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
     if (epi == EPI_DW) {
-        // 256 x 256 tiles for layers that fill them exactly (each operand row read once per slice)
+        // 256 x 256 tiles when both sides reach 256 (each operand row read once per slice for a 256 x 256
+        // layer; a 257 x 256 or 256 x 320 layer reads one operand twice, where 128 x 128 tiles read
+        // both two or three times); 128 x 128 otherwise
         const size_t lds256 = (size_t)2 * 256 * DPAD * sizeof(bf16), lds128 = (size_t)2 * 128 * DPAD * sizeof(bf16);
-        if (a.R % 256 == 0 && a.C % 256 == 0) {
+        if (a.R >= 256 && a.C >= 256) {
             static bool attr = false;       // more than 64 KB of dynamic LDS must be allowed explicitly
             if (!attr) {
                 const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_gemm_dw<256>),
@@ -966,7 +968,8 @@ static hipError_t gemm(int epi, GemmArgs a, int slices, hipStream_t st) {
                 if (e != hipSuccess) return e;
                 attr = true;
             }
-            hipLaunchKernelGGL(k_gemm_dw<256>, dim3(a.R / 256, a.C / 256, slices), dim3(512), lds256, st, a);
+            hipLaunchKernelGGL(k_gemm_dw<256>, dim3((a.R + 255) / 256, (a.C + 255) / 256, slices), dim3(512), lds256, st,
+                               a);
         }
         else
             hipLaunchKernelGGL(k_gemm_dw<128>, dim3((a.R + GT - 1) / GT, (a.C + GT - 1) / GT, slices), dim3(256), lds128,
