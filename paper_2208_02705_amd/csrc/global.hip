@@ -478,7 +478,21 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
 // with four consecutive output columns of one row; pairs of lane groups
 // swap halves so that each stores eight (16 bytes). Four output tiles are
 // accumulated at a time, so consecutive MFMAs are independent.
-constexpr int RW_WAVES = 16;
+// A 320-wide contraction (the skip layer: 256 features, 63 encoded inputs
+// and the ones column that carries its bias) fills the LDS exactly with
+// unpadded rows of 40 pieces (8 slots apart, mod 32): there the pieces of
+// rows l .. l + 12 step 4 would share slots, so row l stores piece p at
+// p ^ (2 ((l >> 2) & 3)), which gives the 32 lanes of a read distinct slots
+// again and keeps every piece inside its row; it has no epilogue bias.
+constexpr int RW_KS_SWZ = 10;
+// waves per block: 16, or 8 for the 320-wide case, whose two 10-piece
+// fragment buffers do not fit 128 registers (16 waves spill 10 and run no
+// faster)
+template <int KS>
+constexpr int rw_waves() { return KS == RW_KS_SWZ ? 8 : 16; }
+
+template <int KS>
+constexpr int rw_kp() { return KS == RW_KS_SWZ ? 32 * KS : 32 * KS + 16; }   // LDS row stride (elements)
 
 // Epilogue of two output tiles (a, b: the accumulators of tiles ta and ta+1
 // for row r). A lane of an even group keeps its four columns of tile ta and
@@ -586,30 +600,39 @@ __device__ __forceinline__ uint32_t rw_bits_word(uint32_t b, int lane) {
 }
 
 template <int EPI, int KS>
-__global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) {
+__global__ __launch_bounds__(64 * rw_waves<KS>(), 1) void k_rowmm(GemmArgs g, int CT) {
+    constexpr int RW_WAVES = rw_waves<KS>();
     extern __shared__ __attribute__((aligned(16))) char rw_raw[];
     bf16* const wsm = reinterpret_cast<bf16*>(rw_raw);
-    constexpr int KP = 32 * KS + 16;                       // LDS row stride (elements)
+    constexpr bool SWZ = KS == RW_KS_SWZ;
+    constexpr int KP = rw_kp<KS>();
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     {
         constexpr int PQ = 4 * KS;                         // 16-byte pieces per row
         for (int i = tid; i < 16 * CT * PQ; i += 64 * RW_WAVES) {
             const int c = i / PQ, pq = i % PQ;
+            const int sq = SWZ ? pq ^ (2 * ((c >> 2) & 3)) : pq;
             const u4 v = c < g.C ? *reinterpret_cast<const u4*>(g.B + (int64_t)c * g.b_sr + 8 * pq) : u4{0u, 0u, 0u, 0u};
-            *reinterpret_cast<u4*>(wsm + c * KP + 8 * pq) = v;
+            *reinterpret_cast<u4*>(wsm + c * KP + 8 * sq) = v;
         }
     }
     // the forward bias (zero past C) after the weights: each accumulator
     // starts from its four rows' biases
     float* const bsm = reinterpret_cast<float*>(wsm + 16 * CT * KP);
-    if constexpr (EPI == EPI_FWD)
+    if constexpr (EPI == EPI_FWD && !SWZ)
         for (int c = tid; c < 16 * CT; c += 64 * RW_WAVES) bsm[c] = (g.bias && c < g.C) ? g.bias[c] : 0.0f;
     __syncthreads();
     const int l16 = lane & 15, g4 = lane >> 4;
     const int ntile = (g.R + 15) / 16;
     const int stride = gridDim.x * RW_WAVES;
     const int ncols = EPI == EPI_FWD ? min(g.C, g.n_out) : g.C;
-    const bf16* wl = wsm + l16 * KP + 8 * g4;              // this lane's fragment origin
+    // this lane's fragment origin; with the swizzle, piece 4 ks + g4 of row
+    // l16 sits at 4 (ks ^ jh) + (g4 ^ 2 jl) for j = (l16 >> 2) & 3, so even
+    // and odd k-steps take origins one k-step ahead and behind
+    const int jsw = SWZ ? (l16 >> 2) & 3 : 0;
+    const bf16* wl = wsm + l16 * KP + 8 * (g4 ^ (2 * (jsw & 1)));
+    const bf16* wl_even = wl + ((jsw >> 1) ? 32 : 0);
+    const bf16* wl_odd = wl - ((jsw >> 1) ? 32 : 0);
     bf16x8 xa[KS], xb[KS];
     auto load = [&](bf16x8* x, int tile) {
         const int row = tile * 16 + l16;
@@ -632,7 +655,7 @@ __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) 
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int ot = ot0 + j < CT ? ot0 + j : CT - 1;
-                if constexpr (EPI == EPI_FWD) acc[j] = *reinterpret_cast<const f32x4*>(bsm + 16 * ot + 4 * g4);
+                if constexpr (EPI == EPI_FWD && !SWZ) acc[j] = *reinterpret_cast<const f32x4*>(bsm + 16 * ot + 4 * g4);
                 else acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
@@ -640,7 +663,8 @@ __global__ __launch_bounds__(64 * RW_WAVES, 1) void k_rowmm(GemmArgs g, int CT) 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int ot = ot0 + j < CT ? ot0 + j : CT - 1;   // past the last tile: recompute it, unused
-                    const bf16x8 w = *reinterpret_cast<const bf16x8*>(wl + 16 * ot * KP + 32 * ks);
+                    const bf16* wk = SWZ ? ((ks & 1) ? wl_odd : wl_even) : wl;
+                    const bf16x8 w = *reinterpret_cast<const bf16x8*>(wk + 16 * ot * KP + 32 * ks);
                     acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, x[ks], acc[j], 0, 0, 0);
                 }
             // tiles past CT were computed from a repeated fragment: their
@@ -686,30 +710,44 @@ static hipError_t rowmm_launch(const GemmArgs& a, int CT, size_t lds, hipStream_
         attr = true;
     }
     const int ntile = (a.R + 15) / 16;
+    constexpr int RW_WAVES = rw_waves<KS>();
     const int blocks = std::max(1, std::min(256, (ntile + RW_WAVES - 1) / RW_WAVES));
     hipLaunchKernelGGL((k_rowmm<EPI, KS>), dim3(blocks), dim3(64 * RW_WAVES), lds, st, a, CT);
     return hipGetLastError();
 }
 
-// The weight-resident kernel when B fits: returns false if it does not apply.
-static bool rowmm_applies(const GemmArgs& a) {
-    if (a.Kc % 32 || a.C > 272 || a.R < 1) return false;
+// LDS bytes of the weight-resident kernel: the weights, then (except for
+// the swizzled 320-wide case, which has no epilogue bias) the bias.
+static size_t rowmm_lds(const GemmArgs& a) {
     const int KS = a.Kc / 32, CT = (a.C + 15) / 16;
-    const size_t lds = (size_t)16 * CT * (a.Kc + 16) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
-    return lds <= (size_t)160 * 1024 && (KS == 1 || KS == 2 || KS == 4 || KS == 8 || KS == 9);
+    if (KS == RW_KS_SWZ) return (size_t)16 * CT * a.Kc * sizeof(bf16);
+    return (size_t)16 * CT * (a.Kc + 16) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
+}
+
+// The weight-resident kernel when B fits: returns false if it does not apply
+// (the 320-wide case only for a forward layer without an epilogue bias).
+static bool rowmm_applies(const GemmArgs& a, int epi) {
+    if (a.Kc % 32 || a.C > 272 || a.R < 1) return false;
+    const int KS = a.Kc / 32;
+    if (KS == RW_KS_SWZ && (epi != EPI_FWD || a.bias)) return false;
+    return rowmm_lds(a) <= (size_t)160 * 1024 &&
+           (KS == 1 || KS == 2 || KS == 4 || KS == 8 || KS == 9 || KS == RW_KS_SWZ);
 }
 
 template <int EPI>
 static bool rowmm(const GemmArgs& a, hipStream_t st, hipError_t* err) {
-    if (!rowmm_applies(a)) return false;
+    if (!rowmm_applies(a, EPI)) return false;
     const int KS = a.Kc / 32, CT = (a.C + 15) / 16;
-    const size_t lds = (size_t)16 * CT * (a.Kc + 16) * sizeof(bf16) + (size_t)16 * CT * sizeof(float);
+    const size_t lds = rowmm_lds(a);
     switch (KS) {
     case 1: *err = rowmm_launch<EPI, 1>(a, CT, lds, st); return true;
     case 2: *err = rowmm_launch<EPI, 2>(a, CT, lds, st); return true;
     case 4: *err = rowmm_launch<EPI, 4>(a, CT, lds, st); return true;
     case 8: *err = rowmm_launch<EPI, 8>(a, CT, lds, st); return true;
     case 9: *err = rowmm_launch<EPI, 9>(a, CT, lds, st); return true;
+    case RW_KS_SWZ:
+        if constexpr (EPI == EPI_FWD) { *err = rowmm_launch<EPI, RW_KS_SWZ>(a, CT, lds, st); return true; }
+        return false;
     default: return false;
     }
 }
@@ -1037,7 +1075,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
     const uint8_t* bits[MB_N] = {};
     int64_t bits_ld[MB_N] = {};
     auto want_bits = [&](GemmArgs& a, int k) {
-        if (k < 0 || !(stage_mask & 2) || !rowmm_applies(a)) return;     // only when a backward follows
+        if (k < 0 || !(stage_mask & 2) || !rowmm_applies(a, EPI_FWD)) return;     // only when a backward follows
         a.mbits = g.mb[k]; a.ldb = a.n_out / 8;
         bits[k] = a.mbits; bits_ld[k] = a.ldb;
     };
@@ -1111,7 +1149,7 @@ hipError_t launch_global_step(const r360_global_desc* desc, const float* weights
         a.B = Wt(ly); a.b_sr = n.L[ly].NC;
         a.R = (int)M; a.C = ncols; a.Kc = n.L[ly].NC;
         a.out = out; a.ldo = ldo; a.mask = act; a.ldm = ldact;
-        if (mbk >= 0 && bits[mbk] && rowmm_applies(a)) { a.mbits_in = bits[mbk]; a.ldb = bits_ld[mbk]; }
+        if (mbk >= 0 && bits[mbk] && rowmm_applies(a, EPI_DX)) { a.mbits_in = bits[mbk]; a.ldb = bits_ld[mbk]; }
         return gemm(EPI_DX, a, 1, st);
     };
     // weight gradient partials: dW[N x K] = dZ^T [N x M] . X [M x K], sliced over M
