@@ -148,25 +148,35 @@ __global__ void k_gnet_pack(GNetDev n, const float* __restrict__ wc, bf16* __res
 }
 
 // Weight gradient: canonical parameter <- sum over slices of its partial.
-// Four neighbouring lanes per parameter, lane j adding the slices k = j mod
-// 4 in order; the four sums are then added as (s0 + s1) + (s2 + s3) (a
-// fixed order), so four times as many loads are in flight.
-__global__ void k_gnet_grad(GNetDev n, const float* __restrict__ part, int64_t part_stride, int slices,
-                            float* __restrict__ grad) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t p = t >> 2;
-    const int j = (int)(t & 3);
+// A block of four waves takes 64 consecutive parameters, one per lane; wave
+// j adds the slices k = j mod 4 in order, so each load of a wave reads 64
+// consecutive partials of one slice (whole cache lines), and the four sums
+// are then added as (s0 + s1) + (s2 + s3) (a fixed order).
+__global__ __launch_bounds__(256) void k_gnet_grad(GNetDev n, const float* __restrict__ part, int64_t part_stride,
+                                                   int slices, float* __restrict__ grad) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, j = threadIdx.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
     float s = 0.0f;
     if (p < n.P) {
         int ly, row, col;
         canon_to_layer(n.w, n.c, p, ly, row, col);
         const GLayerGeom& g = n.L[ly];
         const int64_t off = col < 0 ? g.gb_off + row : g.g_off + (int64_t)row * g.K + col;
-        for (int k = j; k < slices; k += 4) s += part[(int64_t)k * part_stride + off];
+        const float* src = part + off;
+        int k = j;
+        for (; k + 28 < slices; k += 32) {            // eight loads in flight
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v[q] = src[(int64_t)(k + 4 * q) * part_stride];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) s += v[q];
+        }
+        for (; k < slices; k += 4) s += src[(int64_t)k * part_stride];
     }
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    if (p < n.P && j == 0) grad[p] = s;
+    red[j][lane] = s;
+    __syncthreads();
+    if (j == 0 && p < n.P) grad[p] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // ---------------------------------------------------------------------------
