@@ -213,6 +213,83 @@ def test_fp64_gradcheck_against_finite_differences(R, orc):
     assert _rel_err(_np(w64.grad), g_ref) <= 1e-4
 
 
+def test_fp64_central_differences_room_hidden64(R, orc):
+    """FP64 central differences against the FP64 analytic gradient on 16 rays
+    of the room training batch (the 65,536-ray recipe from 20 camera
+    centres), hidden 64, every tensor of the three fields those rays use most
+    (Sec. 4.2 fine-tuning). The scalar is L = sum(g * C) for a fixed seeded
+    g; each checked weight w_i gives (L(w + h e_i) - L(w - h e_i)) / 2h.
+
+    Tolerance basis: the walk is FP32 and does not depend on the weights, and
+    every other step is smooth in FP64 except the ReLUs, so the difference
+    quotient differs from the derivative by the truncation term (h^2 / 6
+    times the third derivative along e_i, below 1e-12 here) plus
+    cancellation of about u |L| / h with u = 2^-53 and |L| <= 48 (5e-8 at
+    h = 1e-7), unless a ReLU input lies within about h of zero for some
+    sample. The bound 1e-6 of the checked set's largest entry plus 1e-5 of
+    the entry covers the first two with a wide margin; a dropped term, a
+    wrong sign or a transposed index moves an entry by about its own size.
+    Per tensor, the entry with the largest analytic magnitude and a seeded
+    draw (which may be zero: an analytic gradient where the forward has no
+    dependence fails too) are checked."""
+    import torch
+    sc = synth.scene_room()
+    scene = R.Scene.from_synth(sc)
+    W, H, N = 2048, 1024, 65536
+    cams = synth.camera_centres(sc, 20)
+    cam, u, v = synth.ray_draws(N, 20, W, H)
+    n = 16
+    o = np.empty((3, n), np.float32); d = np.empty((3, n), np.float32)
+    for k in np.unique(cam[:n]):
+        sel = np.nonzero(cam[:n] == k)[0]
+        ok, dk = orc.equirect_rays(W, H, synth.c2w_at(cams[k]), v[sel].astype(np.int64) * W + u[sel])
+        o[:, sel] = ok; d[:, sel] = dk
+    to, td = _t(o), _t(d)
+    rng = np.random.default_rng(47)
+    w0 = sc.weights.astype(np.float64) + rng.normal(size=sc.weights.shape) * 0.05
+    g = torch.from_numpy(rng.uniform(-1, 1, (3, n))).cuda()
+
+    def L(w):
+        with torch.no_grad():
+            return float((R.GradcheckFunction.apply(w, scene, to, td) * g).sum().item())
+
+    w = torch.from_numpy(w0).cuda().requires_grad_(True)
+    (R.GradcheckFunction.apply(w, scene, to, td) * g).sum().backward()
+    an = _np(w.grad)
+    fields = np.argsort(-np.abs(an).sum(axis=1))[:3]
+    assert np.abs(an[fields[-1]]).max() > 0, "fewer than three fields reached by the rays"
+    lay = synth.local_mlp_layout(sc.hidden)
+    idx = []
+    off = 0
+    for name, shape in lay:
+        size = int(np.prod(shape))
+        for f in fields:
+            blk = np.abs(an[f, off:off + size])
+            idx.append((int(f), off + int(np.argmax(blk)), name))
+            idx.append((int(f), off + int(rng.integers(size)), name))
+        off += size
+    assert off == an.shape[1]
+    h = 1e-7
+    wb = torch.from_numpy(w0).cuda()
+    fd = np.empty(len(idx)); ref = np.empty(len(idx))
+    for q, (f, i, _) in enumerate(idx):
+        wp = wb.clone(); wp[f, i] += h
+        wm = wb.clone(); wm[f, i] -= h
+        fd[q] = (L(wp) - L(wm)) / (2 * h)
+        ref[q] = an[f, i]
+    scale = np.abs(ref).max()
+    err = np.abs(fd - ref)
+    bound = 1e-6 * scale + 1e-5 * np.abs(ref)
+    worst = int(np.argmax(err / bound))
+    print(f"room hidden 64, 16 rays, fields {list(fields)}: {len(idx)} entries, largest {scale:.3g}, "
+          f"worst {idx[worst]} fd {fd[worst]:.9g} analytic {ref[worst]:.9g} ({err[worst] / bound[worst]:.3g} of the bound)")
+    assert np.all(err <= bound), [(idx[q], fd[q], ref[q]) for q in np.nonzero(err > bound)[0]]
+    # every tensor of every chosen field has a non-zero entry checked
+    for name, _ in lay:
+        for f in fields:
+            assert any(abs(ref[q]) > 0 for q, (ff, _, nm) in enumerate(idx) if ff == f and nm == name), (f, name)
+
+
 def test_adam_matches_oracle(R, orc):
     rng = np.random.default_rng(7)
     n = 10000
