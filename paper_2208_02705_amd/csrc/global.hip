@@ -603,9 +603,15 @@ __device__ __forceinline__ uint32_t rw_epilogue2(const GemmArgs& g, int r, int t
 
 // The sign bits of output tiles ta, ta+1 of row r as one word, in lane group
 // 0: lane groups 0, 2, 1, 3 hold columns 16 ta + 0, 8, 16, 24 of the row.
+// The values of lanes + 16, + 32 and + 48 come from the half-swaps (the
+// second result of a swap holds, in the lower row or half, the upper one of
+// the first operand), with no LDS traffic; other lane groups get other
+// values, which they do not use.
 __device__ __forceinline__ uint32_t rw_bits_word(uint32_t b, int lane) {
-    const uint32_t b2 = __shfl(b, (lane + 32) & 63, 64), b1 = __shfl(b, (lane + 16) & 63, 64),
-                   b3 = __shfl(b, (lane + 48) & 63, 64);
+    (void)lane;
+    const uint32_t b2 = __builtin_amdgcn_permlane32_swap(b, b, false, false)[1];    // lanes 0..31: b[lane + 32]
+    const uint32_t b1 = __builtin_amdgcn_permlane16_swap(b, b, false, false)[1];    // even rows: b[lane + 16]
+    const uint32_t b3 = __builtin_amdgcn_permlane16_swap(b2, b2, false, false)[1];  // row 0: b[lane + 48]
     return b | (b2 << 8) | (b1 << 16) | (b3 << 24);
 }
 
