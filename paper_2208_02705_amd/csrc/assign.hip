@@ -59,10 +59,11 @@ constexpr int GMAX = 64;            // their blocks, at most
 constexpr int TP = 1;               // first ties per block and value whose list positions are kept
 constexpr uint32_t SENT = 0xFFFFFFFFu;   // d^2 of an entry outside the field's candidates
 // One histogram set: level 0 in NCOPY copies (block b adds into copy b mod
-// NCOPY, so that the blocks' flushes meet at fewer addresses; one copy since
-// the blocks are few and wide), the further levels, then the final digit's
-// totals.
-constexpr int NCOPY = 1;
+// NCOPY, so that the blocks' flushes meet at fewer addresses; the pick adds
+// the copies), the further levels, then the final digit's totals. Two
+// copies halve the contention of the flush atomics for one more 16 KB read
+// per pick; three, four or eight cost more than they save.
+constexpr int NCOPY = 2;
 constexpr int HSET = (NCOPY + HLMAX - 1) * NBIN + NFIN;
 constexpr int HTOT = (NCOPY + HLMAX - 1) * NBIN;
 __host__ __device__ constexpr int lv_off(int l) { return l == 0 ? 0 : (NCOPY + l - 1) * NBIN; }
