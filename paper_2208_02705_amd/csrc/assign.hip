@@ -540,12 +540,13 @@ __device__ void settle(const StepArgs& a, const SettleIn& in, int64_t first, uin
 // Field k's own d^2 tells both: SENT marks an entry assigned before, and
 // field k takes d^2 < dlim, or d^2 = dlim up to list position pos. Work goes
 // in units of 4 entries per thread (one 16-byte load of d^2, one of linear
-// indices), loaded in batches of four units so that their loads are in
-// flight together; the first batch of the main pass and of the anchor
-// search are issued before the threshold is settled.
+// indices), PB units per batch; the main pass's first batch is issued
+// before the threshold is settled. One unit per batch is fastest (2, 3 and
+// 4 hold more registers and were slower), and the anchor search, which
+// most fields skip, loads its rounds itself.
 template <bool PACKED>
 __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
-    constexpr int PB = 4;                          // units per batch
+    constexpr int PB = 1;                          // units per batch
     __shared__ __attribute__((aligned(16))) uint32_t h[NBIN];
     __shared__ int hit;
     const bool prev = a.field >= 0;
@@ -557,20 +558,13 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
     };
     auto ld_lin = [&](int64_t u) { return *reinterpret_cast<const i32x4h*>(a.list + 4 * u); };
     // loads in the order they are needed (the wait counter completes in
-    // issue order): the threshold's inputs, the first anchor round, the
-    // first batch of the main pass
+    // issue order): the threshold's inputs, then the first batch of the
+    // main pass
     const bool need_settle = prev && !a.take_all;
     SettleIn sin;
     if (need_settle) sin = settle_load(a);
     u32x4h md[PB], ad[PB];
     i32x4h ml[PB];
-    if (a.has_next) {
-#pragma unroll
-        for (int p = 0; p < PB; ++p) {
-            const int64_t u = ubeg + PB * threadIdx.x + p;
-            if (u < uend) ad[p] = ld_d2(u);
-        }
-    }
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
         const int64_t u = um + p * ustride;
@@ -589,18 +583,17 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
         if (!prev) return true;
         return dk != SENT && !(dk < dlim || (dk == dlim && i <= pos));
     };
-    // The anchor search: rounds of 4 ST units (16 consecutive entries per
+    // The anchor search: rounds of PB ST units (4 PB consecutive entries per
     // thread); field k's d^2 is read-only here.
+    static_assert(4 * PB <= 32, "one live bit per entry of a thread's round");
     int64_t nfirst = a.S;
     if (a.has_next && known_anchor >= 0) nfirst = known_anchor;  // uniform
     else if (a.has_next) {
         for (int r = 0; ubeg + (int64_t)PB * ST * r < uend; ++r) {
             const int64_t u0 = ubeg + (int64_t)PB * ST * r + PB * threadIdx.x;
-            if (r > 0) {
 #pragma unroll
-                for (int p = 0; p < PB; ++p)
-                    if (u0 + p < uend) ad[p] = ld_d2(u0 + p);
-            }
+            for (int p = 0; p < PB; ++p)
+                if (u0 + p < uend) ad[p] = ld_d2(u0 + p);
             if (threadIdx.x == 0) hit = 0x7fffffff;
             __syncthreads();
             uint32_t live = 0;
@@ -613,7 +606,7 @@ __global__ __launch_bounds__(ST) void k_sel_step(StepArgs a) {
             // wave's smallest one
             const uint64_t bm = __ballot(live != 0);
             if (bm && (int)(threadIdx.x & 63) == __ffsll((unsigned long long)bm) - 1)
-                atomicMin(&hit, 16 * (int)threadIdx.x + __builtin_ctz(live));
+                atomicMin(&hit, 4 * PB * (int)threadIdx.x + __builtin_ctz(live));
             __syncthreads();
             const int hh = hit;
             __syncthreads();
