@@ -749,7 +749,7 @@ __global__ __launch_bounds__(64 * BW, 1) void k_bwd(BwdArgs a) {
 // Blocks (x, f): field f, the x-th of gridDim.x interleaved parts of its P
 // parameters; the field's contributing slots are listed once per block.
 // P is a multiple of 4 and every row starts on 16 bytes (16-byte loads).
-constexpr int DWR_PARTS = 4;
+constexpr int DWR_PARTS = 16;
 __global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, float* __restrict__ grad,
                                                    const int32_t* __restrict__ start,
                                                    const int32_t* __restrict__ chunk_start,
