@@ -45,7 +45,7 @@ __device__ __forceinline__ int wave_max(int v) {
 
 // Field ids of sample levels k0 .. k0+RB-1 of this lane's ray in block blk
 // (-1 past the ray's count); the loads are issued together.
-constexpr int RB = 8;
+constexpr int RB = 16;
 __device__ __forceinline__ void load_levels(const int32_t* __restrict__ field, int slot0, int k0, int c, int fv[RB]) {
 #pragma unroll
     for (int u = 0; u < RB; ++u) {
