@@ -196,7 +196,8 @@ __global__ __launch_bounds__(256) void k_composite(const int32_t* __restrict__ o
 // Compositing over the slot layout: one lane per ray (64 rays per wave),
 // walking its samples in t order; the lanes of a wave read sample k of their
 // rays from one contiguous 256-byte run, so every load is coalesced. Loads
-// are issued four samples at a time. The sums run in sample order, as in the
+// are issued four samples at a time, only for the lanes whose ray still has
+// those samples. The sums run in sample order, as in the
 // definition.
 constexpr int CB = 4;
 constexpr int CBB = 8;   // backward: training batches leave about one wave per SIMD, so more loads per batch
@@ -254,9 +255,13 @@ __device__ __forceinline__ float composite_one(int64_t i, const int32_t* __restr
         float sg[CB], dl[CB], tm[CB], q0[CB], q1[CB], q2[CB];
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
-            const unsigned j = base + 64u * (unsigned)min(k + u, c - 1);
-            sg[u] = ld32(sigma, j); dl[u] = ld32(delta, j); tm[u] = ld32(t_mid, j);
-            q0[u] = ld32(rgb, j); q1[u] = ld32(rgb1, j); q2[u] = ld32(rgb2, j);
+            if (k + u < c) {
+                const unsigned j = base + 64u * (unsigned)(k + u);
+                sg[u] = ld32(sigma, j); dl[u] = ld32(delta, j); tm[u] = ld32(t_mid, j);
+                q0[u] = ld32(rgb, j); q1[u] = ld32(rgb1, j); q2[u] = ld32(rgb2, j);
+            } else {
+                sg[u] = 0.f; dl[u] = 0.f; tm[u] = 0.f; q0[u] = 0.f; q1[u] = 0.f; q2[u] = 0.f;
+            }
         }
 #pragma unroll
         for (int u = 0; u < CB; ++u) {
